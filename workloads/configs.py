@@ -1,0 +1,366 @@
+"""Workload definitions and seeded generators (inputs only, no wave-equation arithmetic).
+
+Every generator is deterministic for a given seed (numpy ``default_rng`` and
+``scipy.ndimage.gaussian_filter``), so the oracle side and the GPU side rebuild
+bit-identical float32 inputs on any machine with the same numpy/scipy.
+
+Readings of the paper fixed here (the paper gives no discretisation, see the
+section "Wave-equation-based inversion"):
+  * layered model: 8 equal-thickness flat layers over the physical depth with
+    v_l = vmin + (vmax - vmin) * l / 7;
+  * perturbation: a unit-variance Gaussian-smoothed N(0,1) field, kernel std =
+    (correlation length / 2) in cells, ``mode='reflect'``; v = v_layer (1 + 0.05 p);
+  * time grid: dt = CFL h / vmax with vmax the maximum of the true model,
+    nt = ceil(T / dt) + 1, t_n = n dt;
+  * Ricker wavelet with delay t0 = 1.5 / f0 and unit amplitude;
+  * sources and receivers at depth 2h, receivers on every physical column.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+from scipy.ndimage import gaussian_filter
+
+__all__ = ["Shot", "Workload", "ricker", "layered_velocity", "two_layer_velocity",
+           "smooth_perturbation", "smooth_background", "extend_edge", "cfl_time_grid",
+           "make_config", "config_names", "small_2d", "small_3d", "synthetic_residual",
+           "random_field"]
+
+
+# --------------------------------------------------------------------------------------
+# basic generators
+# --------------------------------------------------------------------------------------
+def ricker(nt: int, dt: float, f0: float, t0: Optional[float] = None) -> np.ndarray:
+    """Ricker wavelet r(t) = (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2) at t_n = n dt.
+
+    f0 in kHz, dt in ms; default delay t0 = 1.5 / f0.  Returned as float32 (the
+    precision both the oracle and the GPU path read).
+    """
+    if t0 is None:
+        t0 = 1.5 / f0
+    t = np.arange(nt, dtype=np.float64) * dt
+    a = (math.pi * f0 * (t - t0)) ** 2
+    return ((1.0 - 2.0 * a) * np.exp(-a)).astype(np.float32)
+
+
+def two_layer_velocity(nz: int, nx: int, h: float, z_interface: float,
+                       v_top: float, v_bottom: float) -> np.ndarray:
+    """Two flat layers: v_top for depth z = k h < z_interface, v_bottom below."""
+    z = np.arange(nz, dtype=np.float64) * h
+    col = np.where(z < z_interface, v_top, v_bottom)
+    return np.repeat(col[:, None], nx, axis=1)
+
+
+def layered_velocity(shape, nlayers: int = 8, vmin: float = 1.5, vmax: float = 4.5) -> np.ndarray:
+    """Flat layers of equal thickness over the depth axis (axis 0), velocity rising linearly."""
+    nz = shape[0]
+    k = np.arange(nz)
+    layer = (k * nlayers) // nz
+    col = vmin + (vmax - vmin) * layer / (nlayers - 1)
+    out = np.empty(shape, dtype=np.float64)
+    out[...] = col.reshape((nz,) + (1,) * (len(shape) - 1))
+    return out
+
+
+def smooth_perturbation(shape, h: float, corr_length: float, seed: int) -> np.ndarray:
+    """Unit-variance Gaussian-smoothed white noise (kernel std corr_length / 2 in metres)."""
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal(shape)
+    p = gaussian_filter(white, sigma=0.5 * corr_length / h, mode="reflect")
+    p -= p.mean()
+    return p / p.std()
+
+
+def smooth_background(v: np.ndarray, h: float, length: float = 100.0) -> np.ndarray:
+    """Smoothed starting model v0 = gaussian_filter(v, length / h cells, mode='nearest')."""
+    return gaussian_filter(v, sigma=length / h, mode="nearest")
+
+
+def extend_edge(a: np.ndarray, nbl: int) -> np.ndarray:
+    """Replicate the edge values of a physical-grid array nbl cells outward on every axis."""
+    return np.pad(a, nbl, mode="edge")
+
+
+def cfl_time_grid(T: float, h: float, vmax: float, cfl: float = 0.4):
+    """dt = cfl h / vmax (ms) and nt = ceil(T / dt) + 1 samples (last sample at or past T)."""
+    dt = cfl * h / vmax
+    nt = int(math.ceil(T / dt - 1e-9)) + 1
+    return dt, nt
+
+
+def random_field(shape, seed: int, smooth_cells: float = 0.0, dtype=np.float32) -> np.ndarray:
+    """Seeded N(0,1) field, optionally Gaussian-smoothed (std in cells) and renormalised."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(shape)
+    if smooth_cells > 0:
+        a = gaussian_filter(a, sigma=smooth_cells, mode="reflect")
+        a /= a.std()
+    return a.astype(dtype)
+
+
+def synthetic_residual(nt: int, nrec: int, dt: float, f0: float, seed: int) -> np.ndarray:
+    """Band-limited random traces [nt][nrec]: white noise convolved in time with a Ricker.
+
+    Used as a data residual when only the linear adjoint / gradient operators are
+    being compared (any residual exercises them; this one has the data's band).
+    """
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal((nt, nrec))
+    half = int(math.ceil(1.5 / f0 / dt))
+    t = (np.arange(-half, half + 1) * dt)
+    a = (math.pi * f0 * t) ** 2
+    w = (1.0 - 2.0 * a) * np.exp(-a)
+    out = np.empty_like(white)
+    for r in range(nrec):
+        out[:, r] = np.convolve(white[:, r], w, mode="same")
+    out /= np.abs(out).max()
+    return out.astype(np.float32)
+
+
+# --------------------------------------------------------------------------------------
+# workload container
+# --------------------------------------------------------------------------------------
+@dataclass
+class Shot:
+    """One shot: which model window it runs on, its length and its acquisition.
+
+    Positions are (x, y, z) in metres in the physical coordinates of the shot's
+    window (x = i h for physical column i; y = 0 in 2D).
+    """
+    window: int
+    nt: int
+    src: np.ndarray
+    rec: np.ndarray
+
+
+@dataclass
+class Workload:
+    name: str
+    ndim: int
+    h: float
+    nbl: int
+    dt: float
+    f0: float
+    vmax: float
+    cfl: float
+    v: List[np.ndarray]                # physical velocity per window (float64)
+    shots: List[Shot]
+    description: str = ""
+    v0: Optional[List[np.ndarray]] = None   # smooth starting model (gradient configs)
+    extra: dict = field(default_factory=dict)
+
+    # ---- sizes -------------------------------------------------------------------
+    @property
+    def nshot(self) -> int:
+        return len(self.shots)
+
+    @property
+    def nwindow(self) -> int:
+        return len(self.v)
+
+    def comp_shape(self, w: int):
+        """Computational-grid shape (nz, [ny,] nx) of window w: physical + 2 nbl per axis."""
+        return tuple(n + 2 * self.nbl for n in self.v[w].shape)
+
+    def point_updates(self) -> int:
+        """Sum over shots of N_s (nt_s - 1): the work unit of the Gpts/s metric."""
+        return int(sum(int(np.prod(self.comp_shape(s.window))) * (s.nt - 1) for s in self.shots))
+
+    # ---- arrays ------------------------------------------------------------------
+    def m(self, w: int, background: bool = False) -> np.ndarray:
+        """Squared slowness on the computational grid of window w (float32, edge-extended)."""
+        vv = (self.v0 if background else self.v)[w]
+        m_phys = (1.0 / vv.astype(np.float64) ** 2).astype(np.float32)
+        return extend_edge(m_phys, self.nbl)
+
+    def q(self, s: int) -> np.ndarray:
+        """Source wavelet samples of shot s (float32, length nt_s)."""
+        return ricker(self.shots[s].nt, self.dt, self.f0)
+
+    def with_shots(self, idx) -> "Workload":
+        """A copy restricted to the given shot indices (window list unchanged)."""
+        return replace(self, shots=[self.shots[i] for i in idx])
+
+
+# --------------------------------------------------------------------------------------
+# configurations
+# --------------------------------------------------------------------------------------
+def _surface_receivers(nx: int, h: float, depth: float) -> np.ndarray:
+    rec = np.zeros((nx, 3))
+    rec[:, 0] = np.arange(nx) * h
+    rec[:, 2] = depth
+    return rec
+
+
+def _c1() -> Workload:
+    nx, nz, h = 201, 101, 10.0
+    v = two_layer_velocity(nz, nx, h, 500.0, 1.5, 2.5)
+    vmax = float(v.max())
+    dt, nt = cfl_time_grid(1000.0, h, vmax)
+    rec = np.zeros((101, 3))
+    rec[:, 0] = np.arange(101) * 20.0
+    rec[:, 2] = 20.0
+    shots = [Shot(0, nt, np.array([1000.0, 0.0, 20.0]), rec)]
+    return Workload("c1_fwd", 2, h, 40, dt, 0.015, vmax, 0.4, [v], shots,
+                    "2D forward, 201x101 @ 10 m, two layers 1.5/2.5 km/s, 1 shot, 101 receivers")
+
+
+def _layered_perturbed(shape, h, seed):
+    return layered_velocity(shape) * (1.0 + 0.05 * smooth_perturbation(shape, h, 200.0, seed))
+
+
+def _surface_survey(name, nx, nz, h, T, nshot, seed, desc):
+    v = _layered_perturbed((nz, nx), h, seed)
+    vmax = float(v.max())
+    dt, nt = cfl_time_grid(T, h, vmax)
+    rec = _surface_receivers(nx, h, 2 * h)
+    shots = []
+    for s in range(nshot):
+        xs = (s + 0.5) * (nx - 1) * h / nshot
+        shots.append(Shot(0, nt, np.array([xs, 0.0, 2 * h]), rec))
+    v0 = [smooth_background(v, h)]
+    return Workload(name, 2, h, 40, dt, 0.015, vmax, 0.4, [v], shots, desc, v0=v0)
+
+
+def _c2() -> Workload:
+    return _surface_survey("c2_grad", 650, 341, 6.25, 1800.0, 16, 0,
+                           "2D forward + gradient, 650x341 @ 6.25 m, layered 1.5-4.5 + 5% "
+                           "perturbation, 16 shots, 650 receivers, full FP32 wavefield storage")
+
+
+def _c3() -> Workload:
+    return _surface_survey("c3_autograd", 1024, 512, 6.25, 2500.0, 32, 0,
+                           "2D autograd gradient, 1024x512 @ 6.25 m, 32 shots, 1024 receivers, "
+                           "16 FP32 checkpoint slots per shot")
+
+
+def _c4() -> Workload:
+    h, nz, nx_big = 6.25, 341, 4096
+    vbig = _layered_perturbed((nz, nx_big), h, 1)
+    vmax = float(vbig.max())
+    rng = np.random.default_rng(101)
+    widths = rng.integers(256, 1025, size=64)
+    Ts = rng.uniform(1000.0, 2500.0, size=64)
+    starts = [int(rng.integers(0, nx_big - w + 1)) for w in widths]
+    dt = 0.4 * h / vmax
+    windows, shots = [], []
+    for i, (w, T, x0) in enumerate(zip(widths, Ts, starts)):
+        windows.append(np.ascontiguousarray(vbig[:, x0:x0 + int(w)]))
+        nt = int(math.ceil(T / dt - 1e-9)) + 1
+        src = np.array([0.5 * (int(w) - 1) * h, 0.0, 2 * h])
+        shots.append(Shot(i, nt, src, _surface_receivers(int(w), h, 2 * h)))
+    v0 = [smooth_background(v, h) for v in windows]
+    return Workload("c4_uneven", 2, h, 40, dt, 0.015, vmax, 0.4, windows, shots,
+                    "2D uneven batching: 64 windows, widths U{256..1024} x 341 @ 6.25 m, "
+                    "T ~ U[1.0, 2.5] s", v0=v0)
+
+
+def _volume_survey(name, n, h, T, src, rec_step_cells, rec_n, seed, desc, crop=None):
+    shape = (n, n, n)
+    v = _layered_perturbed(shape, h, seed)
+    vmax = float(v.max())
+    dt, nt = cfl_time_grid(T, h, vmax)
+    if crop is not None:
+        (z0, z1), (y0, y1), (x0, x1) = crop
+        v = np.ascontiguousarray(v[z0:z1, y0:y1, x0:x1])
+        src = src - np.array([x0 * h, y0 * h, z0 * h])
+    g = np.arange(rec_n) * rec_step_cells * h
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    rec = np.zeros((rec_n * rec_n, 3))
+    rec[:, 0] = X.ravel()
+    rec[:, 1] = Y.ravel()
+    rec[:, 2] = 2 * h
+    shots = [Shot(0, nt, src, rec)]
+    v0 = [smooth_background(v, h)]
+    return Workload(name, 3, h, 40, dt, 0.015, vmax, 0.4, [v], shots, desc, v0=v0)
+
+
+def _c5() -> Workload:
+    return _volume_survey("c5_3d", 256, 12.5, 2000.0, np.array([1600.0, 1600.0, 25.0]), 2, 128, 0,
+                          "3D forward + gradient, 256^3 @ 12.5 m, 1 shot, 128x128 receivers")
+
+
+def _c5_crop() -> Workload:
+    return _volume_survey("c5_crop", 256, 12.5, 2000.0, np.array([1600.0, 1600.0, 25.0]), 2, 32, 0,
+                          "64^3 crop (x, y in [96,160), z in [0,64)) of the 3D model, 32x32 receivers",
+                          crop=((0, 64), (96, 160), (96, 160)))
+
+
+_CONFIGS = {"c1_fwd": _c1, "c2_grad": _c2, "c3_autograd": _c3, "c4_uneven": _c4,
+            "c5_3d": _c5, "c5_crop": _c5_crop}
+
+
+def config_names():
+    return list(_CONFIGS)
+
+
+def make_config(name: str) -> Workload:
+    """Build one of the named workloads (c1_fwd, c2_grad, c3_autograd, c4_uneven, c5_3d, c5_crop)."""
+    return _CONFIGS[name]()
+
+
+# --------------------------------------------------------------------------------------
+# small workloads for tests (sizes the oracle finishes in seconds)
+# --------------------------------------------------------------------------------------
+def small_2d(nx: int = 90, nz: int = 60, h: float = 10.0, nbl: int = 12, T: float = 400.0,
+             nshot: int = 3, seed: int = 5, nrec: Optional[int] = None, windows: Optional[list] = None,
+             T_per_shot: Optional[list] = None, perturb: float = 0.05) -> Workload:
+    """A small layered/perturbed 2D survey: off-grid sources, receivers near the top.
+
+    ``windows`` (list of widths) gives one model window per shot (uneven batching);
+    ``T_per_shot`` gives each shot its own duration.
+    """
+    if windows is None:
+        widths = [nx]
+    else:
+        widths = list(windows)
+    vbig = layered_velocity((nz, max(widths)), vmin=1.5, vmax=3.0) * \
+        (1.0 + perturb * smooth_perturbation((nz, max(widths)), h, 80.0, seed))
+    vmax = float(vbig.max())
+    dt = 0.4 * h / vmax
+    vs = [np.ascontiguousarray(vbig[:, :w]) for w in widths]
+    shots = []
+    n = nshot if windows is None else len(widths)
+    for s in range(n):
+        wi = 0 if windows is None else s
+        w = widths[wi]
+        T_s = T if T_per_shot is None else T_per_shot[s]
+        nt = int(math.ceil(T_s / dt - 1e-9)) + 1
+        xs = (s + 0.5) * (w - 1) * h / n if windows is None else 0.37 * (w - 1) * h
+        src = np.array([xs + 0.3 * h, 0.0, 2.4 * h])
+        k = w if nrec is None else nrec
+        rec = np.zeros((k, 3))
+        rec[:, 0] = np.linspace(0.5 * h, (w - 1.6) * h, k)
+        rec[:, 2] = 3.3 * h
+        shots.append(Shot(wi, nt, src, rec))
+    v0 = [smooth_background(v, h, 3 * h) for v in vs]
+    return Workload("small_2d", 2, h, nbl, dt, 0.015, vmax, 0.4, vs, shots,
+                    "small 2D test survey", v0=v0)
+
+
+def small_3d(n=(24, 20, 22), h: float = 12.5, nbl: int = 8, T: float = 300.0, seed: int = 7,
+             nrec_side: int = 5, nshot: int = 1) -> Workload:
+    """A small layered/perturbed 3D survey with off-grid source and a receiver patch."""
+    nz, ny, nx = n
+    v = layered_velocity((nz, ny, nx), vmin=1.5, vmax=3.0) * \
+        (1.0 + 0.05 * smooth_perturbation((nz, ny, nx), h, 80.0, seed))
+    vmax = float(v.max())
+    dt, nt = cfl_time_grid(T, h, vmax)
+    gx = np.linspace(0.7 * h, (nx - 1.8) * h, nrec_side)
+    gy = np.linspace(0.4 * h, (ny - 1.3) * h, nrec_side)
+    X, Y = np.meshgrid(gx, gy, indexing="xy")
+    rec = np.zeros((nrec_side * nrec_side, 3))
+    rec[:, 0] = X.ravel()
+    rec[:, 1] = Y.ravel()
+    rec[:, 2] = 2.6 * h
+    shots = []
+    for s in range(nshot):
+        src = np.array([(0.45 + 0.1 * s) * (nx - 1) * h + 0.21 * h,
+                        0.52 * (ny - 1) * h - 0.33 * h, 2.2 * h])
+        shots.append(Shot(0, nt, src, rec))
+    v0 = [smooth_background(v, h, 3 * h)]
+    return Workload("small_3d", 3, h, nbl, dt, 0.015, vmax, 0.4, [v], shots,
+                    "small 3D test survey", v0=v0)
