@@ -1,0 +1,206 @@
+/*
+ * awe.h - acoustic wave-equation forward operator, its adjoint and the adjoint-state
+ * gradient on AMD Instinct MI355X (gfx950).  C ABI; no C++ or framework types.
+ *
+ * Operations (paper: section "Wave-equation-based inversion", equation eq-fwi and the
+ * two Julia listings that follow it - the JUDI gradient-descent loop and the rrule
+ * whose pullback returns (J^T dy, F^T dy)):
+ *
+ *   forward   d  = F(m) q,      F(m) = P_r A(m)^{-1} P_s^T   (m = squared slowness)
+ *   adjoint   v  = F(m)^T dd                                 (gradient w.r.t. the source)
+ *   gradient  g  = J(m, q)^T dd                              (gradient w.r.t. m; with
+ *                  dd = F(m) q - d_obs it is the gradient of 1/2 ||F(m) q - d_obs||^2)
+ *   born      dd = J(m, q) dm                                (linearised data)
+ *
+ * Discretisation (the paper gives none; these are the library's definitions):
+ *   - computational grid = physical grid + nbl cells on both ends of every axis;
+ *     arrays are row-major [nz][nx] (2D) or [nz][ny][nx] (3D), x fastest; fields are
+ *     zero outside the computational grid;
+ *   - L_h = 8th-order central Laplacian (weights -205/72, 8/5, -1/5, 8/315, -1/560 per
+ *     axis, divided by h^2);
+ *   - damping eta = sum over axes of 3 ln(1/R) / (2 nbl h vref) (d/nbl)^2 with d the
+ *     number of cells past the inner edge of the border (0 inside);
+ *   - row k = 1..nt-1 of A u = s, with u^0 = u^{-1} = 0:
+ *       (m/dt^2 + eta/(2dt)) u^k - (2m/dt^2 + L_h) u^{k-1} + (m/dt^2 - eta/(2dt)) u^{k-2}
+ *         = s^{k-1};
+ *   - P_s^T q: s^n = R(x_s)^T q^n / h^ndim; P_r u: d^n = R(x_r) u^n for n = 0..nt-1,
+ *     R = bilinear (2D) / trilinear (3D) interpolation weights;
+ *   - adjoint: A^T w = P_r^T dd solved backward from w^nt = w^{nt+1} = 0;
+ *     v^n = R(x_s) w^{n+1} / h^ndim for n = 0..nt-2 and v^{nt-1} = 0;
+ *   - gradient: g = -(1/dt^2) sum_j u^j (w^j - 2 w^{j+1} + w^{j+2}) summed over the shots
+ *     of each model window in ascending shot order (FP64 accumulation).
+ *
+ * Units: h in m, time in ms, m in ms^2/m^2 (= s^2/km^2), velocities in km/s, positions
+ * in m in the physical coordinates of the shot's model window (x = i h for physical
+ * column i).
+ *
+ * Ownership and streams: every array argument except the problem description is a
+ * device pointer owned by the caller.  The library allocates device memory only in
+ * awe_plan_create (its geometry tables, freed by awe_plan_destroy); calls on the
+ * compute path never allocate.  All compute calls enqueue on the given hipStream_t
+ * (NULL = default stream) and return without synchronising; inputs must stay valid
+ * until the stream reaches the work.  Calls on one workspace must not overlap.
+ *
+ * Errors: every function returns an awe_status; nothing throws across the ABI.  On
+ * error no work has been enqueued and awe_last_error() returns a thread-local message.
+ */
+#ifndef AWE_H
+#define AWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AWE_VERSION 1
+
+typedef enum {
+  AWE_OK = 0,
+  AWE_ERR_INVALID_ARG = 1,  /* null pointer, bad size, bad enum value */
+  AWE_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+  AWE_ERR_CFL = 3,          /* vmax dt / h above the leapfrog stability limit */
+  AWE_ERR_GEOMETRY = 4,     /* source or receiver outside the computational grid */
+  AWE_ERR_WORKSPACE = 5,    /* workspace null or smaller than awe_plan_workspace_size */
+  AWE_ERR_STATE = 6,        /* awe_backward without a preceding awe_forward(keep=1) */
+  AWE_ERR_HIP = 7           /* a HIP runtime call failed */
+} awe_status;
+
+/* One shot: a model window, its time axis and its acquisition. */
+typedef struct {
+  int32_t nx, ny, nz;   /* computational grid of the window (physical + 2 nbl); ny = 1 in 2D */
+  int32_t nt;           /* time samples t_n = n dt, n = 0..nt-1 (nt >= 2) */
+  int64_t m_offset;     /* element offset of the window in m, dm and g */
+  int64_t q_offset;     /* element offset of the shot's nt samples in q and v */
+  int64_t d_offset;     /* element offset of the shot's traces [nt][nrec] in d and dd */
+  int64_t rec_offset;   /* row of the shot's first receiver in awe_problem.rec_pos */
+  int32_t nrec;         /* receivers of this shot (>= 0) */
+  int32_t reserved0;
+  double src[3];        /* source position (x, y, z) in m; y ignored in 2D */
+} awe_shot;
+
+typedef struct {
+  int32_t ndim;          /* 2 or 3 */
+  int32_t nbl;           /* damping border width in cells (>= 0) */
+  double h;              /* grid spacing, m */
+  double dt;             /* time step, ms */
+  double vmax;           /* bound on the velocity 1/sqrt(m) of every model passed (km/s) */
+  double damp_vref;      /* reference velocity of the damping profile (km/s) */
+  double damp_R;         /* target reflection coefficient, 0 < R <= 1 (1 = no damping) */
+  int32_t nshot;
+  int32_t reserved0;
+  const awe_shot* shots; /* host array [nshot]; copied by awe_plan_create */
+  const double* rec_pos; /* host array [rows][3] of (x, y, z); copied by awe_plan_create */
+} awe_problem;
+
+typedef enum {
+  AWE_STORE_NONE = 0,       /* forward only: no wavefield kept (forward, adjoint, born) */
+  AWE_STORE_FULL = 1,       /* every u^n kept in the workspace */
+  AWE_STORE_CHECKPOINT = 2  /* nslots restart pairs (u^n, u^{n-1}) per shot, binomial
+                               recomputation schedule */
+} awe_store_mode;
+
+typedef enum {
+  AWE_PREC_FP32 = 0,
+  AWE_PREC_BF16 = 1,  /* stored value = RNE(u / s), s = max |u| of that field (FP32) */
+  AWE_PREC_FP16 = 2   /* as BF16, in IEEE half precision (subnormals kept) */
+} awe_store_prec;
+
+typedef struct {
+  int32_t mode;    /* awe_store_mode */
+  int32_t nslots;  /* CHECKPOINT: restart slots per shot (>= 1); ignored otherwise */
+  int32_t prec;    /* awe_store_prec of the stored wavefield */
+  int32_t reserved0;
+} awe_storage;
+
+typedef struct awe_plan awe_plan;
+
+/* Validate the problem, build geometry tables (device copies allocated here), choose
+ * tile shapes and lay out the workspace.  Uses the current HIP device.
+ * Shots may have different nt: their time axes are aligned at the last sample.
+ * Errors: INVALID_ARG, CFL, GEOMETRY, UNSUPPORTED (FULL storage in BF16/FP16), HIP. */
+awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, awe_plan** plan);
+
+/* Bytes of device workspace every compute call on this plan needs (256-byte aligned
+ * pointer required). */
+awe_status awe_plan_workspace_size(const awe_plan* plan, size_t* bytes);
+
+/* Free the plan and its device tables.  NULL is ignored. */
+void awe_plan_destroy(awe_plan* plan);
+
+/* d = F(m) q for every shot.  m: float [sum of windows] squared slowness; q: float
+ * wavelets at q_offset; d: float traces [nt][nrec] at d_offset (written).
+ * keep = 1 also stores the wavefield in the workspace (per the plan's storage mode)
+ * for a following awe_backward on the same workspace, m and q. */
+awe_status awe_forward(awe_plan* plan, const float* m, const float* q, float* d, int keep,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Reverse sweep after awe_forward(keep = 1) on the same workspace, m and q: g = J^T dd
+ * (FP64, written on every window a shot uses, other elements untouched; may be NULL) and
+ * v = F^T dd (float at q_offset; may be NULL).  dd: float [nt][nrec] per shot at
+ * d_offset.  q is read again when CHECKPOINT storage recomputes forward states.  FULL
+ * storage keeps the forward, so backward may be repeated; CHECKPOINT consumes it.
+ * Error STATE if the workspace does not hold a kept forward of this plan. */
+awe_status awe_backward(awe_plan* plan, const float* m, const float* q, const float* dd, double* g,
+                        float* v, void* ws, size_t ws_bytes, void* stream);
+
+/* awe_forward(keep = 1) followed by awe_backward.  d may be NULL (traces not returned). */
+awe_status awe_gradient(awe_plan* plan, const float* m, const float* q, const float* dd,
+                        double* g, float* v, float* d, void* ws, size_t ws_bytes, void* stream);
+
+/* v = F(m)^T dd: float [nt] per shot at q_offset. */
+awe_status awe_adjoint(awe_plan* plan, const float* m, const float* dd, float* v, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* dd = J(m, q) dm (Born modelling): dm float, same layout as m; dd float traces. */
+awe_status awe_born(awe_plan* plan, const float* m, const float* q, const float* dm, float* dd,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace awe_residual / awe_dot_f64 need for n elements. */
+size_t awe_reduce_workspace_size(int64_t n);
+
+/* r = d_pred - d_obs (float, may alias d_pred) and *loss = 1/2 sum r^2 accumulated in
+ * FP64 (device pointer, may be NULL).  Deterministic: fixed partition and order. */
+awe_status awe_residual(const float* d_pred, const float* d_obs, float* r, int64_t n,
+                        double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* *out = sum a_i b_i in FP64 (device pointer), deterministic. */
+awe_status awe_dot_f64(const float* a, const float* b, int64_t n, double* out, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* *out = sum a_i b_i for FP64 inputs (device pointers), deterministic. */
+awe_status awe_dot_f64d(const double* a, const double* b, int64_t n, double* out, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Binomial checkpoint schedule (host only, no device work) for a reverse sweep over
+ * states S_1..S_{nsteps} with nslots restart slots.  Writes up to cap actions
+ * (op, a, b) into actions[3*i..3*i+2] and the count into *count:
+ *   op 0 ADVANCE  a -> b : run forward steps from state a to state b (b > a)
+ *   op 1 STORE    slot a <- current state b
+ *   op 2 RESTORE  current state <- slot a (which holds state b)
+ *   op 3 REVERSE  adjoint step of state a (needs the current state to be a)
+ * The first ADVANCE starts from the zero state S_0.  Returns INVALID_ARG if cap is too
+ * small (*count then holds the needed size). */
+awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions,
+                                   int64_t cap, int64_t* count);
+
+/* Kernel timing (measurement aid).  After awe_profile_enable, every time-step launch of
+ * the compute calls on this plan is bracketed by a pair of HIP events recorded on the
+ * call's stream, for up to max_launches launches; further launches are not timed.
+ * Classes: 0 forward step, 1 adjoint step (with imaging and, in 3D, receiver injection),
+ * 2 Born step.  awe_profile_read waits for the recorded events, returns per class the
+ * number of timed launches and the summed event time in ms, and restarts the count.
+ * Enabling creates HIP events (host resources, no device memory). */
+awe_status awe_profile_enable(awe_plan* plan, int64_t max_launches);
+awe_status awe_profile_read(awe_plan* plan, int64_t counts[3], double ms[3]);
+awe_status awe_profile_disable(awe_plan* plan);
+
+const char* awe_status_string(awe_status s);
+const char* awe_last_error(void);
+int awe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AWE_H */

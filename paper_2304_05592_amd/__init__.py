@@ -1,0 +1,20 @@
+"""Acoustic wave-equation forward operator and adjoint-state gradient on AMD MI355X (gfx950).
+
+The computation lives in libawe.so (hand-written HIP kernels behind a C ABI, include/awe.h);
+this package is its Python binding and a torch.autograd rule.  Nothing here computes the
+operators itself, and nothing falls back to the CPU.
+"""
+from .binding import (EXPORTS, LIB_PATH, PREC_BF16, PREC_FP16, PREC_FP32, STORE_CHECKPOINT,
+                      STORE_FULL, STORE_NONE, AweError, Plan, ShotGeometry, Storage,
+                      checkpoint_schedule, dot, lib, residual)
+
+__all__ = ["EXPORTS", "LIB_PATH", "PREC_BF16", "PREC_FP16", "PREC_FP32", "STORE_CHECKPOINT",
+           "STORE_FULL", "STORE_NONE", "AweError", "Plan", "ShotGeometry", "Storage",
+           "checkpoint_schedule", "dot", "lib", "residual", "WaveOp", "wave_forward", "extend_edge"]
+
+
+def __getattr__(name):
+    if name in ("WaveOp", "wave_forward", "extend_edge"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)

@@ -1,0 +1,62 @@
+"""Differentiation rule of the wave-equation operator for torch.autograd.
+
+Mirrors the paper's rrule for F*q (section "Wave-equation-based inversion"): the forward
+returns y = F(m) q and the pullback of dy is (J^T dy, F^T dy) - the gradient with respect
+to the squared slowness m and with respect to the source q.  The forward keeps the
+wavefield in a workspace held by the autograd context (every step when the plan stores
+everything, restart slots when it checkpoints), so the pullback runs one reverse sweep
+that yields both J^T dy and F^T dy.
+"""
+from __future__ import annotations
+
+import torch
+import torch.nn.functional as F
+
+from .binding import STORE_NONE, Plan
+
+
+class WaveOp(torch.autograd.Function):
+    """d = F(m) q on a Plan; m and q are packed float32 CUDA tensors (see Plan)."""
+
+    @staticmethod
+    def forward(ctx, m: torch.Tensor, q: torch.Tensor, plan: Plan):
+        mf = m.detach().to(torch.float32).contiguous()
+        qf = q.detach().to(torch.float32).contiguous()
+        keep = bool(ctx.needs_input_grad[0]) and plan.storage.mode != STORE_NONE
+        ws = plan.workspace(mf.device)
+        d = plan.forward(mf, qf, keep=keep, ws=ws)
+        ctx.plan, ctx.ws, ctx.kept = plan, ws, keep
+        ctx.m_dtype = m.dtype
+        ctx.save_for_backward(mf, qf)
+        return d
+
+    @staticmethod
+    def backward(ctx, dy: torch.Tensor):
+        mf, qf = ctx.saved_tensors
+        plan = ctx.plan
+        dyf = dy.detach().to(torch.float32).contiguous()
+        gm = gq = None
+        if ctx.needs_input_grad[0]:
+            if not ctx.kept:
+                raise RuntimeError("the plan keeps no wavefield (storage mode NONE): gradient "
+                                   "with respect to m needs FULL or CHECKPOINT storage")
+            g, v = plan.backward(mf, qf, dyf, g=True, v=bool(ctx.needs_input_grad[1]), ws=ctx.ws)
+            gm = g.to(ctx.m_dtype)
+            gq = v
+        elif ctx.needs_input_grad[1]:
+            gq = plan.adjoint(mf, dyf, ws=ctx.ws)
+        ctx.ws = None
+        return gm, gq, None
+
+
+def wave_forward(m: torch.Tensor, q: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable d = F(m) q."""
+    return WaveOp.apply(m, q, plan)
+
+
+def extend_edge(m_phys: torch.Tensor, nbl: int) -> torch.Tensor:
+    """Replicate a physical-grid model nbl cells outward on every axis (differentiable; its
+    backward folds the border gradient onto the edge cells)."""
+    x = m_phys.unsqueeze(0).unsqueeze(0)
+    pad = [nbl] * (2 * m_phys.dim())
+    return F.pad(x, pad, mode="replicate")[0, 0]

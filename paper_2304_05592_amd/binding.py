@@ -1,0 +1,392 @@
+"""ctypes binding of libawe.so (declarations in include/awe.h).
+
+Argument marshalling only: every computation runs in the library's HIP kernels.  PyTorch
+supplies device memory (tensors) and the current HIP stream.  If the library is missing or
+fails to load, every entry point raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libawe.so")
+
+AWE_OK = 0
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "CFL", 4: "GEOMETRY", 5: "WORKSPACE",
+          6: "STATE", 7: "HIP"}
+STORE_NONE, STORE_FULL, STORE_CHECKPOINT = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+
+EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "awe_forward",
+           "awe_backward", "awe_gradient", "awe_adjoint", "awe_born", "awe_reduce_workspace_size",
+           "awe_residual", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
+           "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
+           "awe_status_string", "awe_last_error", "awe_version"]
+
+
+class AweError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"awe status {STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class AweShot(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("nt", ctypes.c_int32), ("m_offset", ctypes.c_int64), ("q_offset", ctypes.c_int64),
+                ("d_offset", ctypes.c_int64), ("rec_offset", ctypes.c_int64),
+                ("nrec", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("src", ctypes.c_double * 3)]
+
+
+class AweProblem(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("nbl", ctypes.c_int32), ("h", ctypes.c_double),
+                ("dt", ctypes.c_double), ("vmax", ctypes.c_double), ("damp_vref", ctypes.c_double),
+                ("damp_R", ctypes.c_double), ("nshot", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("shots", ctypes.POINTER(AweShot)), ("rec_pos", ctypes.POINTER(ctypes.c_double))]
+
+
+class AweStorage(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("nslots", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libawe.so once (raises OSError if it is missing: build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing; build it with `python -m paper_2304_05592_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int
+    L.awe_plan_create.argtypes = [ctypes.POINTER(AweProblem), ctypes.POINTER(AweStorage), ctypes.POINTER(vp)]
+    L.awe_plan_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    L.awe_plan_destroy.argtypes = [vp]
+    L.awe_plan_destroy.restype = None
+    L.awe_forward.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
+    L.awe_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.awe_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.awe_adjoint.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.awe_born.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.awe_reduce_workspace_size.argtypes = [i64]
+    L.awe_reduce_workspace_size.restype = sz
+    L.awe_residual.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+    L.awe_dot_f64.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+    L.awe_dot_f64d.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+    L.awe_checkpoint_schedule.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          i64, ctypes.POINTER(i64)]
+    L.awe_profile_enable.argtypes = [vp, i64]
+    L.awe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+    L.awe_profile_disable.argtypes = [vp]
+    L.awe_status_string.argtypes = [i32]
+    L.awe_status_string.restype = ctypes.c_char_p
+    L.awe_last_error.restype = ctypes.c_char_p
+    L.awe_version.restype = ctypes.c_int
+    for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
+                 "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_dot_f64",
+                 "awe_dot_f64d", "awe_checkpoint_schedule", "awe_profile_enable",
+                 "awe_profile_read", "awe_profile_disable"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != AWE_OK:
+        raise AweError(status, lib().awe_last_error().decode())
+
+
+def checkpoint_schedule(nsteps: int, nslots: int) -> np.ndarray:
+    """Action list (op, a, b) of the binomial reverse schedule (host only)."""
+    L = lib()
+    cnt = ctypes.c_int64(0)
+    L.awe_checkpoint_schedule(nsteps, nslots, None, 0, ctypes.byref(cnt))
+    buf = (ctypes.c_int32 * (3 * max(cnt.value, 1)))()
+    check(L.awe_checkpoint_schedule(nsteps, nslots, buf, cnt.value, ctypes.byref(cnt)))
+    return np.frombuffer(buf, dtype=np.int32, count=3 * cnt.value).reshape(-1, 3).copy()
+
+
+# --------------------------------------------------------------------------------------
+# survey description -> plan
+# --------------------------------------------------------------------------------------
+@dataclass
+class ShotGeometry:
+    """One shot: its model window index, samples and acquisition (metres, window coordinates)."""
+    window: int
+    nt: int
+    src: Sequence[float]
+    rec: np.ndarray
+
+
+@dataclass
+class Storage:
+    mode: int = STORE_NONE
+    nslots: int = 0
+    prec: int = PREC_FP32
+
+
+@dataclass
+class Layout:
+    """Element offsets of every window / shot in the packed m, q and d arrays."""
+    windows: List[tuple]
+    m_offset: List[int] = field(default_factory=list)
+    q_offset: List[int] = field(default_factory=list)
+    d_offset: List[int] = field(default_factory=list)
+    m_size: int = 0
+    q_size: int = 0
+    d_size: int = 0
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A survey on one GPU: windows (computational-grid shapes) and shots.
+
+    Arrays are packed flat: m / dm / g hold the windows back to back (C order), q / v the
+    shots' wavelets, d / dd the shots' traces [nt][nrec].
+    """
+
+    def __init__(self, ndim: int, h: float, dt: float, nbl: int, vmax: float, windows,
+                 shots: List[ShotGeometry], storage: Optional[Storage] = None,
+                 damp_vref: Optional[float] = None, damp_R: float = 1e-3):
+        L = lib()
+        self.ndim, self.h, self.dt, self.nbl = ndim, float(h), float(dt), int(nbl)
+        self.storage = storage or Storage()
+        self.windows = [tuple(int(n) for n in w) for w in windows]
+        self.shots = shots
+        lay = Layout(self.windows)
+        off = 0
+        for w in self.windows:
+            lay.m_offset.append(off)
+            off += int(np.prod(w))
+        lay.m_size = off
+        qo = do = 0
+        recs = []
+        cs = (AweShot * len(shots))()
+        roff = 0
+        for i, s in enumerate(shots):
+            shape = self.windows[s.window]
+            if ndim == 2:
+                nz, nx = shape
+                ny = 1
+            else:
+                nz, ny, nx = shape
+            rec = np.asarray(s.rec, dtype=np.float64).reshape(-1, 3)
+            cs[i].nx, cs[i].ny, cs[i].nz, cs[i].nt = nx, ny, nz, int(s.nt)
+            cs[i].m_offset = lay.m_offset[s.window]
+            cs[i].q_offset = qo
+            cs[i].d_offset = do
+            cs[i].rec_offset = roff
+            cs[i].nrec = rec.shape[0]
+            for a in range(3):
+                cs[i].src[a] = float(s.src[a])
+            lay.q_offset.append(qo)
+            lay.d_offset.append(do)
+            qo += int(s.nt)
+            do += int(s.nt) * rec.shape[0]
+            roff += rec.shape[0]
+            recs.append(rec)
+        lay.q_size, lay.d_size = qo, do
+        self.layout = lay
+        self._rec = np.ascontiguousarray(np.concatenate(recs, axis=0) if recs else np.zeros((1, 3)))
+        self._cshots = cs
+        prob = AweProblem()
+        prob.ndim, prob.nbl, prob.h, prob.dt = ndim, self.nbl, self.h, self.dt
+        prob.vmax = float(vmax)
+        prob.damp_vref = float(vmax if damp_vref is None else damp_vref)
+        prob.damp_R = float(damp_R)
+        prob.nshot = len(shots)
+        prob.shots = ctypes.cast(cs, ctypes.POINTER(AweShot))
+        prob.rec_pos = self._rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st = AweStorage(self.storage.mode, self.storage.nslots, self.storage.prec, 0)
+        handle = ctypes.c_void_p()
+        check(L.awe_plan_create(ctypes.byref(prob), ctypes.byref(st), ctypes.byref(handle)))
+        self._h = handle
+        sz = ctypes.c_size_t(0)
+        check(L.awe_plan_workspace_size(self._h, ctypes.byref(sz)))
+        self.ws_bytes = sz.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().awe_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ---------------------------------------------------------------- memory helpers
+    def workspace(self, device=None):
+        """A fresh device workspace (uint8 tensor, 256-byte aligned view)."""
+        import torch
+        dev = torch.device("cuda") if device is None else device
+        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        shift = (-raw.data_ptr()) % 256
+        return raw[shift:shift + self.ws_bytes]
+
+    def pack(self, arrays, kind: str, device=None, dtype=None):
+        """Pack per-window (kind 'm') / per-shot (kind 'q' or 'd') arrays into one device tensor."""
+        import torch
+        dtype = torch.float32 if dtype is None else dtype
+        flat = np.concatenate([np.asarray(a, dtype=np.float64 if dtype == torch.float64 else np.float32).ravel()
+                               for a in arrays])
+        return torch.from_numpy(flat).to(torch.device("cuda") if device is None else device)
+
+    def unpack(self, t, kind: str):
+        """Split a packed tensor into per-window ('m') or per-shot ('q', 'd') numpy arrays."""
+        a = t.detach().cpu().numpy()
+        lay = self.layout
+        out = []
+        if kind == "m":
+            for w, o in zip(self.windows, lay.m_offset):
+                out.append(a[o:o + int(np.prod(w))].reshape(w))
+        elif kind == "q":
+            for s, o in zip(self.shots, lay.q_offset):
+                out.append(a[o:o + s.nt])
+        else:
+            for s, o in zip(self.shots, lay.d_offset):
+                nrec = np.asarray(s.rec).reshape(-1, 3).shape[0]
+                out.append(a[o:o + s.nt * nrec].reshape(s.nt, nrec))
+        return out
+
+    # ---------------------------------------------------------------- kernel timing
+    def profile_enable(self, max_launches: int):
+        check(lib().awe_profile_enable(self._h, int(max_launches)))
+
+    def profile_read(self):
+        """{class: (launches, total ms)} for classes 'forward', 'adjoint', 'born'."""
+        counts = (ctypes.c_int64 * 3)()
+        ms = (ctypes.c_double * 3)()
+        check(lib().awe_profile_read(self._h, counts, ms))
+        return {name: (counts[i], ms[i]) for i, name in enumerate(("forward", "adjoint", "born"))}
+
+    def profile_disable(self):
+        check(lib().awe_profile_disable(self._h))
+
+    def _check(self, t, n, dtype, name):
+        import torch
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor with >= {n} elements "
+                             f"(got {t.dtype}, {tuple(t.shape)}, cuda={t.is_cuda})")
+        return t
+
+    # ---------------------------------------------------------------- operators
+    def forward(self, m, q, d=None, keep=False, ws=None, stream=None):
+        """d = F(m) q (packed traces).  keep=True stores the wavefield in ws for backward."""
+        import torch
+        lay = self.layout
+        self._check(m, lay.m_size, torch.float32, "m")
+        self._check(q, lay.q_size, torch.float32, "q")
+        if d is None:
+            d = torch.empty(lay.d_size, dtype=torch.float32, device=m.device)
+        ws = self.workspace(m.device) if ws is None else ws
+        check(lib().awe_forward(self._h, _ptr(m), _ptr(q), _ptr(d), int(bool(keep)), _ptr(ws),
+                                self.ws_bytes, _stream_ptr(stream)))
+        return d
+
+    def backward(self, m, q, dd, g=True, v=False, ws=None, stream=None):
+        """Reverse sweep after forward(keep=True): returns (g FP64 or None, v or None)."""
+        import torch
+        lay = self.layout
+        self._check(dd, lay.d_size, torch.float32, "dd")
+        gt = torch.empty(lay.m_size, dtype=torch.float64, device=dd.device) if g is True else \
+            (None if g is None or g is False else g)
+        vt = torch.empty(lay.q_size, dtype=torch.float32, device=dd.device) if v is True else \
+            (None if v is None or v is False else v)
+        if gt is not None:
+            self._check(gt, lay.m_size, torch.float64, "g")
+        if vt is not None:
+            self._check(vt, lay.q_size, torch.float32, "v")
+        check(lib().awe_backward(self._h, _ptr(m), _ptr(q), _ptr(dd), _ptr(gt), _ptr(vt), _ptr(ws),
+                                 self.ws_bytes, _stream_ptr(stream)))
+        return gt, vt
+
+    def gradient(self, m, q, dd, v=False, d=False, ws=None, stream=None):
+        """(g, v, d): g = J^T dd (FP64), v = F^T dd, d = F(m) q, in one forward + reverse sweep."""
+        import torch
+        lay = self.layout
+        self._check(m, lay.m_size, torch.float32, "m")
+        self._check(q, lay.q_size, torch.float32, "q")
+        self._check(dd, lay.d_size, torch.float32, "dd")
+        gt = torch.empty(lay.m_size, dtype=torch.float64, device=m.device)
+        vt = torch.empty(lay.q_size, dtype=torch.float32, device=m.device) if v else None
+        dt_ = torch.empty(lay.d_size, dtype=torch.float32, device=m.device) if d else None
+        ws = self.workspace(m.device) if ws is None else ws
+        check(lib().awe_gradient(self._h, _ptr(m), _ptr(q), _ptr(dd), _ptr(gt), _ptr(vt), _ptr(dt_),
+                                 _ptr(ws), self.ws_bytes, _stream_ptr(stream)))
+        return gt, vt, dt_
+
+    def adjoint(self, m, dd, v=None, ws=None, stream=None):
+        """v = F(m)^T dd (packed per shot)."""
+        import torch
+        lay = self.layout
+        self._check(m, lay.m_size, torch.float32, "m")
+        self._check(dd, lay.d_size, torch.float32, "dd")
+        if v is None:
+            v = torch.empty(lay.q_size, dtype=torch.float32, device=m.device)
+        ws = self.workspace(m.device) if ws is None else ws
+        check(lib().awe_adjoint(self._h, _ptr(m), _ptr(dd), _ptr(v), _ptr(ws), self.ws_bytes,
+                                _stream_ptr(stream)))
+        return v
+
+    def born(self, m, q, dm, dd=None, ws=None, stream=None):
+        """dd = J(m, q) dm (packed traces)."""
+        import torch
+        lay = self.layout
+        self._check(m, lay.m_size, torch.float32, "m")
+        self._check(q, lay.q_size, torch.float32, "q")
+        self._check(dm, lay.m_size, torch.float32, "dm")
+        if dd is None:
+            dd = torch.empty(lay.d_size, dtype=torch.float32, device=m.device)
+        ws = self.workspace(m.device) if ws is None else ws
+        check(lib().awe_born(self._h, _ptr(m), _ptr(q), _ptr(dm), _ptr(dd), _ptr(ws), self.ws_bytes,
+                             _stream_ptr(stream)))
+        return dd
+
+
+def _reduce_ws(n, device):
+    import torch
+    nb = lib().awe_reduce_workspace_size(n)
+    return torch.empty((nb + 7) // 8, dtype=torch.float64, device=device)
+
+
+def residual(d_pred, d_obs, r=None, stream=None):
+    """(r, loss): r = d_pred - d_obs and loss = 1/2 sum r^2 (FP64 device scalar)."""
+    import torch
+    n = d_pred.numel()
+    if r is None:
+        r = torch.empty_like(d_pred)
+    loss = torch.empty(1, dtype=torch.float64, device=d_pred.device)
+    ws = _reduce_ws(n, d_pred.device)
+    check(lib().awe_residual(_ptr(d_pred), _ptr(d_obs), _ptr(r), n, _ptr(loss), _ptr(ws),
+                             ws.numel() * 8, _stream_ptr(stream)))
+    return r, loss
+
+
+def dot(a, b, stream=None):
+    """sum a_i b_i accumulated in FP64 on the device (float32 or float64 inputs)."""
+    import torch
+    n = a.numel()
+    out = torch.empty(1, dtype=torch.float64, device=a.device)
+    ws = _reduce_ws(n, a.device)
+    fn = lib().awe_dot_f64d if a.dtype == torch.float64 else lib().awe_dot_f64
+    check(fn(_ptr(a), _ptr(b), n, _ptr(out), _ptr(ws), ws.numel() * 8, _stream_ptr(stream)))
+    return out

@@ -1,0 +1,828 @@
+// Host side of the awe C ABI: validation, geometry tables, tiling, workspace layout and the
+// time loops (forward, reverse sweep with stored or recomputed wavefield, Born).
+//
+// Time axes of shots with different nt are aligned at their ends: shot s's local state n
+// is the global state n + off_s with off_s = max_nt - nt_s.  A launch for global step n
+// covers the tiles of the shots with off_s < n, which are a prefix of the tile list
+// because shots are ordered by off_s.  Every shot then runs its own nt - 1 steps, and one
+// checkpoint schedule over max_nt - 1 global steps serves all shots.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "awe.h"
+#include "awe_internal.h"
+#include "schedule.h"
+
+using awe::InjEntry;
+using awe::InjPoint;
+using awe::RecDev;
+using awe::ShotDev;
+using awe::TileDev;
+using awe::WinDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+awe_status fail(awe_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+awe_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return AWE_ERR_HIP;
+}
+
+#define AWE_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+constexpr double kStencil[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+long long align256(long long x) { return (x + 255) & ~255LL; }
+
+}  // namespace
+
+struct awe_plan {
+  int ndim = 2, nbl = 0;
+  double h = 0, dt = 0, vmax = 0, vref = 0, R = 1e-3;
+  awe_storage store{};
+  int nshot = 0, max_nt = 0, nsteps = 0;
+  int tz = 32;            // 2D tile rows
+  int ty = 8, bz = 0;     // 3D tile rows in y and z-block length
+  std::vector<awe_shot> shots;
+  std::vector<ShotDev> sd;
+  std::vector<TileDev> tiles;
+  std::vector<int> active;        // active[n]: tiles of the shots with off < n
+  std::vector<RecDev> recs;
+  std::vector<InjPoint> inj_pts;
+  std::vector<InjEntry> inj_ent;
+  std::vector<WinDev> wins;
+  std::vector<int> win_shots;
+  std::vector<long long> win_coef;
+  std::vector<int> win_dims;
+  long long max_win_npts = 0;
+  int total_recs = 0;
+  size_t ws_bytes = 0;
+  long long fields_off = 0, fields_bytes = 0, acc_off = 0, acc_bytes = 0;
+  void* dev = nullptr;
+  awe::Tables tab{};
+  std::vector<int32_t> sched;
+  size_t sched_first_reverse = 0;
+  const void* kept_ws = nullptr;
+  float c[5] = {0, 0, 0, 0, 0};
+  float eta_dt = 0.f;
+  double amp = 0.0;
+  // kernel timing
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_cls;
+  size_t prof_next = 0;
+};
+
+namespace {
+
+struct Interp {
+  int base[3];     // x, y, z base node
+  double w[8];     // corner = bx + 2 by + 4 bz
+};
+
+// Bilinear / trilinear weights of a physical position on a window's computational grid.
+bool interp(const awe_plan* P, const awe_shot& s, const double* pos, Interp* out) {
+  const int n[3] = {s.nx, s.ny, s.nz};
+  double f[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a) {
+    if (a == 1 && P->ndim == 2) {
+      out->base[a] = 0;
+      continue;
+    }
+    const double g = pos[a] / P->h + P->nbl;
+    const double fl = std::floor(g);
+    if (!(fl >= 0.0) || fl > n[a] - 2) return false;
+    out->base[a] = (int)fl;
+    f[a] = g - fl;
+  }
+  const int nc = P->ndim == 2 ? 4 : 8;
+  for (int c = 0; c < 8; ++c) out->w[c] = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const int bx = c & 1;
+    const int by = P->ndim == 2 ? 0 : (c >> 1) & 1;
+    const int bz = P->ndim == 2 ? (c >> 1) & 1 : (c >> 2) & 1;
+    const double w = (bx ? f[0] : 1 - f[0]) * (P->ndim == 3 ? (by ? f[1] : 1 - f[1]) : 1.0) *
+                     (bz ? f[2] : 1 - f[2]);
+    out->w[c] = w;
+  }
+  return true;
+}
+
+// Corner offsets (dx, dy, dz) of corner c.
+void corner(int ndim, int c, int* dx, int* dy, int* dz) {
+  *dx = c & 1;
+  if (ndim == 2) {
+    *dy = 0;
+    *dz = (c >> 1) & 1;
+  } else {
+    *dy = (c >> 1) & 1;
+    *dz = (c >> 2) & 1;
+  }
+}
+
+awe_status build_tables(awe_plan* P, const double* rec_pos) {
+  const int nd = P->ndim;
+  // shots sorted by time offset (longest first), stable
+  std::vector<int> order(P->nshot);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return P->sd[a].off < P->sd[b].off; });
+  P->tiles.clear();
+  std::vector<int> first_tile(P->nshot), ntx(P->nshot), nty(P->nshot), ntz(P->nshot);
+  const int TY = nd == 2 ? 1 : P->ty;
+  for (int s : order) {
+    const awe_shot& sh = P->shots[s];
+    const int TZ = nd == 2 ? P->tz : (P->bz > 0 ? P->bz : sh.nz);
+    ntx[s] = (sh.nx + awe::kTX - 1) / awe::kTX;
+    nty[s] = nd == 2 ? 1 : (sh.ny + TY - 1) / TY;
+    ntz[s] = (sh.nz + TZ - 1) / TZ;
+    first_tile[s] = (int)P->tiles.size();
+    for (int kz = 0; kz < ntz[s]; ++kz)
+      for (int ky = 0; ky < nty[s]; ++ky)
+        for (int kx = 0; kx < ntx[s]; ++kx) {
+          TileDev t{};
+          t.shot = s;
+          t.x0 = kx * awe::kTX;
+          t.y0 = ky * TY;
+          t.z0 = kz * TZ;
+          P->tiles.push_back(t);
+        }
+  }
+  if (P->tiles.size() > (size_t)0x7fffffff) return fail(AWE_ERR_UNSUPPORTED, "too many tiles");
+  auto tile_of = [&](int s, int i, int j, int k) {
+    const awe_shot& sh = P->shots[s];
+    const int TZ = nd == 2 ? P->tz : (P->bz > 0 ? P->bz : sh.nz);
+    return first_tile[s] + ((k / TZ) * nty[s] + (j / TY)) * ntx[s] + i / awe::kTX;
+  };
+  // active tile prefix per global step
+  P->active.assign(P->nsteps + 2, 0);
+  for (int n = 0; n <= P->nsteps + 1; ++n) {
+    int cnt = 0;
+    for (int s : order)
+      if (P->sd[s].off < n) cnt += ntx[s] * nty[s] * ntz[s];
+    P->active[n] = cnt;
+  }
+  // sources
+  const double hd = std::pow(P->h, nd);
+  for (int s = 0; s < P->nshot; ++s) {
+    Interp I;
+    if (!interp(P, P->shots[s], P->shots[s].src, &I))
+      return fail(AWE_ERR_GEOMETRY, "source of shot " + std::to_string(s) +
+                                        " lies outside its computational grid");
+    ShotDev& d = P->sd[s];
+    d.src_i = I.base[0];
+    d.src_j = I.base[1];
+    d.src_k = I.base[2];
+    for (int c = 0; c < 8; ++c) d.src_w[c] = (float)(I.w[c] / hd);
+    d.src_tile = tile_of(s, I.base[0], I.base[1], I.base[2]);
+  }
+  // receivers: gather list grouped by owning tile; injection CSR by touched point
+  struct RecTmp { int tile; RecDev r; };
+  std::vector<RecTmp> rt;
+  struct Touch { int tile; long long p; int shot, lx, ly, lz, r; float w; };
+  std::vector<Touch> touches;
+  P->total_recs = 0;
+  for (int s = 0; s < P->nshot; ++s) {
+    const awe_shot& sh = P->shots[s];
+    for (int r = 0; r < sh.nrec; ++r) {
+      const double* pos = rec_pos + 3 * (sh.rec_offset + r);
+      Interp I;
+      if (!interp(P, sh, pos, &I))
+        return fail(AWE_ERR_GEOMETRY, "receiver " + std::to_string(r) + " of shot " +
+                                          std::to_string(s) + " lies outside its grid");
+      RecDev R{};
+      R.shot = s;
+      R.r = r;
+      R.i = I.base[0];
+      R.j = I.base[1];
+      R.k = I.base[2];
+      for (int c = 0; c < 8; ++c) R.w[c] = (float)I.w[c];
+      rt.push_back({tile_of(s, R.i, R.j, R.k), R});
+      const int nc = nd == 2 ? 4 : 8;
+      for (int c = 0; c < nc; ++c) {
+        if (I.w[c] == 0.0) continue;
+        int dx, dy, dz;
+        corner(nd, c, &dx, &dy, &dz);
+        const int i = R.i + dx, j = R.j + dy, k = R.k + dz;
+        const int t = tile_of(s, i, j, k);
+        const TileDev& T = P->tiles[t];
+        const long long p = ((long long)k * sh.ny + j) * sh.nx + i;
+        touches.push_back({t, p, s, i - T.x0, j - T.y0, k - T.z0, r, (float)I.w[c]});
+      }
+    }
+    P->total_recs += sh.nrec;
+  }
+  std::stable_sort(rt.begin(), rt.end(), [](const RecTmp& a, const RecTmp& b) { return a.tile < b.tile; });
+  P->recs.clear();
+  for (size_t i = 0; i < rt.size(); ++i) {
+    TileDev& T = P->tiles[rt[i].tile];
+    if (T.gat_count == 0) T.gat_begin = (int)i;
+    T.gat_count++;
+    P->recs.push_back(rt[i].r);
+  }
+  std::stable_sort(touches.begin(), touches.end(), [](const Touch& a, const Touch& b) {
+    if (a.tile != b.tile) return a.tile < b.tile;
+    if (a.p != b.p) return a.p < b.p;
+    return a.r < b.r;
+  });
+  P->inj_pts.clear();
+  P->inj_ent.clear();
+  for (size_t i = 0; i < touches.size();) {
+    size_t j = i;
+    InjPoint ip{};
+    ip.shot = touches[i].shot;
+    ip.lx = touches[i].lx;
+    ip.ly = touches[i].ly;
+    ip.lz = touches[i].lz;
+    ip.p = touches[i].p;
+    ip.e_begin = (int)P->inj_ent.size();
+    while (j < touches.size() && touches[j].tile == touches[i].tile && touches[j].p == touches[i].p) {
+      P->inj_ent.push_back({touches[j].r, touches[j].w});
+      ++j;
+    }
+    ip.e_count = (int)(j - i);
+    TileDev& T = P->tiles[touches[i].tile];
+    if (T.inj_count == 0) T.inj_begin = (int)P->inj_pts.size();
+    T.inj_count++;
+    P->inj_pts.push_back(ip);
+    i = j;
+  }
+  return AWE_OK;
+}
+
+awe_status upload_tables(awe_plan* P) {
+  auto bytes = [](size_t n, size_t e) { return (long long)align256((long long)(n * e)); };
+  const long long o_sd = 0;
+  const long long o_t = o_sd + bytes(P->sd.size(), sizeof(ShotDev));
+  const long long o_r = o_t + bytes(P->tiles.size(), sizeof(TileDev));
+  const long long o_ip = o_r + bytes(P->recs.size(), sizeof(RecDev));
+  const long long o_ie = o_ip + bytes(P->inj_pts.size(), sizeof(InjPoint));
+  const long long o_w = o_ie + bytes(P->inj_ent.size(), sizeof(InjEntry));
+  const long long o_ws = o_w + bytes(P->wins.size(), sizeof(WinDev));
+  const long long total = o_ws + bytes(P->win_shots.size(), sizeof(int)) + 256;
+  std::vector<unsigned char> host(total, 0);
+  auto put = [&](long long off, const void* src, size_t n) { if (n) std::memcpy(host.data() + off, src, n); };
+  put(o_sd, P->sd.data(), P->sd.size() * sizeof(ShotDev));
+  put(o_t, P->tiles.data(), P->tiles.size() * sizeof(TileDev));
+  put(o_r, P->recs.data(), P->recs.size() * sizeof(RecDev));
+  put(o_ip, P->inj_pts.data(), P->inj_pts.size() * sizeof(InjPoint));
+  put(o_ie, P->inj_ent.data(), P->inj_ent.size() * sizeof(InjEntry));
+  put(o_w, P->wins.data(), P->wins.size() * sizeof(WinDev));
+  put(o_ws, P->win_shots.data(), P->win_shots.size() * sizeof(int));
+  if (P->dev) {
+    (void)hipFree(P->dev);
+    P->dev = nullptr;
+  }
+  AWE_HIP(hipMalloc(&P->dev, total));
+  AWE_HIP(hipMemcpy(P->dev, host.data(), total, hipMemcpyHostToDevice));
+  unsigned char* b = static_cast<unsigned char*>(P->dev);
+  P->tab.shots = reinterpret_cast<const ShotDev*>(b + o_sd);
+  P->tab.tiles = reinterpret_cast<const TileDev*>(b + o_t);
+  P->tab.recs = reinterpret_cast<const RecDev*>(b + o_r);
+  P->tab.inj_pts = reinterpret_cast<const InjPoint*>(b + o_ip);
+  P->tab.inj_ent = reinterpret_cast<const InjEntry*>(b + o_ie);
+  P->tab.wins = reinterpret_cast<const WinDev*>(b + o_w);
+  P->tab.win_shots = reinterpret_cast<const int*>(b + o_ws);
+  return AWE_OK;
+}
+
+awe::StepArgs base_args(const awe_plan* P, void* ws) {
+  awe::StepArgs a{};
+  a.t = P->tab;
+  a.ws = static_cast<unsigned char*>(ws);
+  a.ndim = P->ndim;
+  a.nbl = P->nbl;
+  a.store_prec = P->store.prec;
+  for (int i = 0; i < 5; ++i) a.c[i] = P->c[i];
+  a.eta_dt = P->eta_dt;
+  a.inv_dt2 = (float)(1.0 / (P->dt * P->dt));
+  return a;
+}
+
+awe_status check_ws(const awe_plan* P, void* ws, size_t ws_bytes) {
+  if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  if (!ws) return fail(AWE_ERR_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < P->ws_bytes)
+    return fail(AWE_ERR_WORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                       std::to_string(P->ws_bytes));
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(AWE_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  return AWE_OK;
+}
+
+awe_status prepare(awe_plan* P, const float* m, void* ws, bool zero_fwd, bool zero_adj, hipStream_t s) {
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  for (size_t i = 0; i < P->wins.size(); ++i) {
+    AWE_HIP(awe::launch_coef(m, w, P->win_coef[i], P->wins[i].m, P->win_dims[3 * i],
+                             P->win_dims[3 * i + 1], P->win_dims[3 * i + 2], P->nbl, P->h, P->dt,
+                             P->amp, s));
+  }
+  for (int i = 0; i < P->nshot; ++i) {
+    const ShotDev& d = P->sd[i];
+    if (zero_fwd) AWE_HIP(awe::launch_fill(w, d.fld, 2 * d.npts * 4, s));
+    if (zero_adj) AWE_HIP(awe::launch_fill(w, d.fld + 2 * d.npts * 4, 2 * d.npts * 4, s));
+  }
+  return AWE_OK;
+}
+
+// Kernel timing: an event pair around one launch (class cls) when enabled and not full.
+struct ProfScope {
+  awe_plan* P;
+  hipStream_t s;
+  bool on;
+  ProfScope(awe_plan* P_, int cls, hipStream_t s_) : P(P_), s(s_) {
+    on = P->prof_next + 2 <= P->prof_ev.size();
+    if (on) {
+      (void)hipEventRecord(P->prof_ev[P->prof_next], s);
+      P->prof_cls.push_back(cls);
+    }
+  }
+  ~ProfScope() {
+    if (on) {
+      (void)hipEventRecord(P->prof_ev[P->prof_next + 1], s);
+      P->prof_next += 2;
+    }
+  }
+};
+
+awe_status step_fwd(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
+  a.step = n;
+  a.ntiles = P->active[n];
+  ProfScope ps(P, 0, s);
+  if (P->ndim == 2) AWE_HIP(awe::launch_fwd2d(a, P->tz, store, s));
+  else AWE_HIP(awe::launch_fwd3d(a, P->ty, P->bz, store, s));
+  return AWE_OK;
+}
+
+awe_status step_adj(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
+  a.step = n;
+  a.ntiles = P->active[n];
+  ProfScope ps(P, 1, s);
+  if (P->ndim == 2) {
+    AWE_HIP(awe::launch_adj2d(a, P->tz, s));
+  } else {
+    AWE_HIP(awe::launch_adj3d(a, P->ty, P->bz, s));
+    AWE_HIP(awe::launch_inj3d(a, (int)P->inj_pts.size(), s));
+  }
+  return AWE_OK;
+}
+
+awe_status run_slot(awe_plan* P, awe::StepArgs& a, int slot, int state, int dir, hipStream_t s) {
+  if (dir == 0 && P->store.prec != AWE_PREC_FP32) {
+    for (int i = 0; i < P->nshot; ++i)
+      AWE_HIP(awe::launch_fill(a.ws, P->sd[i].scale + 8LL * slot, 8, s));
+    AWE_HIP(awe::launch_absmax(a, P->nshot, slot, state, s));
+  }
+  AWE_HIP(awe::launch_slot(a, P->nshot, slot, state, dir, s));
+  return AWE_OK;
+}
+
+// Execute schedule actions [begin, end).  During the first sweep (gather != 0) traces are
+// sampled; REVERSE runs the adjoint step with imaging from the forward buffers.
+awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t begin, size_t end,
+                       hipStream_t s) {
+  for (size_t i = begin; i < end; ++i) {
+    const int op = P->sched[3 * i], x = P->sched[3 * i + 1], y = P->sched[3 * i + 2];
+    switch (op) {
+      case awe::kAdvance:
+        for (int n = x + 1; n <= y; ++n) {
+          awe_status st = step_fwd(P, fa, n, 0, s);
+          if (st != AWE_OK) return st;
+        }
+        break;
+      case awe::kStore: {
+        awe_status st = run_slot(P, fa, x, y, 0, s);
+        if (st != AWE_OK) return st;
+        break;
+      }
+      case awe::kRestore:
+        if (x < 0) {
+          for (int k = 0; k < P->nshot; ++k)
+            AWE_HIP(awe::launch_fill(fa.ws, P->sd[k].fld, 2 * P->sd[k].npts * 4, s));
+        } else {
+          awe_status st = run_slot(P, fa, x, y, 1, s);
+          if (st != AWE_OK) return st;
+        }
+        break;
+      case awe::kReverse: {
+        awe_status st = step_adj(P, aa, x, s);
+        if (st != AWE_OK) return st;
+        break;
+      }
+    }
+  }
+  return AWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int awe_version(void) { return AWE_VERSION; }
+
+const char* awe_last_error(void) { return g_err.c_str(); }
+
+const char* awe_status_string(awe_status s) {
+  switch (s) {
+    case AWE_OK: return "ok";
+    case AWE_ERR_INVALID_ARG: return "invalid argument";
+    case AWE_ERR_UNSUPPORTED: return "unsupported";
+    case AWE_ERR_CFL: return "CFL condition violated";
+    case AWE_ERR_GEOMETRY: return "source or receiver outside the grid";
+    case AWE_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case AWE_ERR_STATE: return "no kept forward wavefield";
+    case AWE_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, awe_plan** out) {
+  if (!out) return fail(AWE_ERR_INVALID_ARG, "plan output pointer is NULL");
+  *out = nullptr;
+  if (!prob || !store) return fail(AWE_ERR_INVALID_ARG, "problem or storage is NULL");
+  if (prob->ndim != 2 && prob->ndim != 3) return fail(AWE_ERR_INVALID_ARG, "ndim must be 2 or 3");
+  if (prob->nshot < 1 || !prob->shots) return fail(AWE_ERR_INVALID_ARG, "need at least one shot");
+  if (!(prob->h > 0) || !(prob->dt > 0) || !(prob->vmax > 0) || !(prob->damp_vref > 0))
+    return fail(AWE_ERR_INVALID_ARG, "h, dt, vmax and damp_vref must be positive");
+  if (!(prob->damp_R > 0) || prob->damp_R > 1) return fail(AWE_ERR_INVALID_ARG, "damp_R must be in (0, 1]");
+  if (prob->nbl < 0) return fail(AWE_ERR_INVALID_ARG, "nbl must be >= 0");
+  if (store->mode < AWE_STORE_NONE || store->mode > AWE_STORE_CHECKPOINT)
+    return fail(AWE_ERR_INVALID_ARG, "bad storage mode");
+  if (store->prec < AWE_PREC_FP32 || store->prec > AWE_PREC_FP16)
+    return fail(AWE_ERR_INVALID_ARG, "bad storage precision");
+  if (store->mode == AWE_STORE_CHECKPOINT && store->nslots < 1)
+    return fail(AWE_ERR_INVALID_ARG, "CHECKPOINT storage needs nslots >= 1");
+  if (store->mode == AWE_STORE_FULL && store->prec != AWE_PREC_FP32)
+    return fail(AWE_ERR_UNSUPPORTED, "FULL storage is FP32 only; use CHECKPOINT for BF16/FP16");
+  // stability of undamped leapfrog with the 8th-order stencil: v dt / h <= 2 / sqrt(ndim S)
+  double S = std::fabs(kStencil[0]);
+  for (int r = 1; r <= 4; ++r) S += 2 * std::fabs(kStencil[r]);
+  const double limit = 2.0 / std::sqrt(prob->ndim * S);
+  const double cfl = prob->vmax * prob->dt / prob->h;
+  if (cfl > limit) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "vmax dt / h = %.6f exceeds the stability limit %.6f", cfl, limit);
+    return fail(AWE_ERR_CFL, buf);
+  }
+
+  awe_plan* P = new awe_plan();
+  P->ndim = prob->ndim;
+  P->nbl = prob->nbl;
+  P->h = prob->h;
+  P->dt = prob->dt;
+  P->vmax = prob->vmax;
+  P->vref = prob->damp_vref;
+  P->R = prob->damp_R;
+  P->store = *store;
+  P->nshot = prob->nshot;
+  P->shots.assign(prob->shots, prob->shots + prob->nshot);
+  auto bad = [&](const std::string& m) { delete P; return fail(AWE_ERR_INVALID_ARG, m); };
+  long long rec_rows = 0;
+  for (int s = 0; s < P->nshot; ++s) {
+    const awe_shot& sh = P->shots[s];
+    const std::string id = "shot " + std::to_string(s) + ": ";
+    if (sh.nx < 2 || sh.nz < 2 || sh.ny < 1) return bad(id + "grid too small");
+    if (P->ndim == 2 && sh.ny != 1) return bad(id + "ny must be 1 in 2D");
+    if (P->ndim == 3 && sh.ny < 2) return bad(id + "ny must be >= 2 in 3D");
+    if (sh.nt < 2) return bad(id + "nt must be >= 2");
+    if (sh.m_offset < 0 || sh.q_offset < 0 || sh.d_offset < 0 || sh.rec_offset < 0 || sh.nrec < 0)
+      return bad(id + "negative offset or count");
+    if (sh.nrec > 0 && !prob->rec_pos) return bad("rec_pos is NULL");
+    rec_rows = std::max<long long>(rec_rows, (long long)(sh.rec_offset + sh.nrec));
+    P->max_nt = std::max(P->max_nt, sh.nt);
+  }
+  P->nsteps = P->max_nt - 1;
+  const int nd = P->ndim;
+  for (int r = 0; r < 5; ++r) P->c[r] = (float)(kStencil[r] / (P->h * P->h));
+  P->amp = P->nbl > 0 ? 3.0 * std::log(1.0 / P->R) / (2.0 * P->nbl * P->h * P->vref) : 0.0;
+  P->eta_dt = P->nbl > 0 ? (float)(P->amp / ((double)P->nbl * P->nbl) / P->dt) : 0.f;
+
+  // windows (unique m_offset, consistent dims)
+  std::map<long long, int> win_of;
+  std::vector<std::vector<int>> wshots;
+  for (int s = 0; s < P->nshot; ++s) {
+    const awe_shot& sh = P->shots[s];
+    auto it = win_of.find(sh.m_offset);
+    if (it == win_of.end()) {
+      win_of[sh.m_offset] = (int)P->wins.size();
+      WinDev w{};
+      w.m = sh.m_offset;
+      w.npts = (long long)sh.nx * sh.ny * sh.nz;
+      P->wins.push_back(w);
+      P->win_dims.insert(P->win_dims.end(), {sh.nx, sh.ny, sh.nz});
+      wshots.emplace_back();
+    }
+    const int wi = win_of[sh.m_offset];
+    if (P->win_dims[3 * wi] != sh.nx || P->win_dims[3 * wi + 1] != sh.ny || P->win_dims[3 * wi + 2] != sh.nz)
+      return bad("shots sharing m_offset " + std::to_string(sh.m_offset) + " have different grids");
+    wshots[wi].push_back(s);
+  }
+  for (size_t w = 0; w < P->wins.size(); ++w) {
+    P->wins[w].sbegin = (int)P->win_shots.size();
+    P->wins[w].scount = (int)wshots[w].size();
+    P->win_shots.insert(P->win_shots.end(), wshots[w].begin(), wshots[w].end());
+    P->max_win_npts = std::max(P->max_win_npts, P->wins[w].npts);
+  }
+
+  // workspace layout
+  long long off = align256((long long)awe::kReduceBlocks * 8);
+  P->win_coef.resize(P->wins.size());
+  for (size_t w = 0; w < P->wins.size(); ++w) {
+    P->win_coef[w] = off;
+    off = align256(off + P->wins[w].npts * 4);
+  }
+  const int esz = store->prec == AWE_PREC_FP32 ? 4 : 2;
+  P->sd.resize(P->nshot);
+  P->fields_off = off;
+  for (int s = 0; s < P->nshot; ++s) {
+    const awe_shot& sh = P->shots[s];
+    ShotDev& d = P->sd[s];
+    d.nx = sh.nx;
+    d.ny = sh.ny;
+    d.nz = sh.nz;
+    d.nt = sh.nt;
+    d.off = P->max_nt - sh.nt;
+    d.nrec = sh.nrec;
+    d.npts = (long long)sh.nx * sh.ny * sh.nz;
+    d.coef = P->win_coef[win_of[sh.m_offset]];
+    d.m = sh.m_offset;
+    d.q = sh.q_offset;
+    d.d = sh.d_offset;
+    d.fld = off;
+    off = align256(off + 4 * d.npts * 4);
+  }
+  P->fields_bytes = off - P->fields_off;
+  P->acc_off = off;
+  for (int s = 0; s < P->nshot; ++s) {
+    ShotDev& d = P->sd[s];
+    d.acc = -1;
+    d.store = -1;
+    d.scale = -1;
+    if (store->mode == AWE_STORE_NONE) continue;
+    d.acc = off;
+    off = align256(off + d.npts * 8);
+  }
+  P->acc_bytes = off - P->acc_off;
+  for (int s = 0; s < P->nshot; ++s) {
+    ShotDev& d = P->sd[s];
+    if (store->mode == AWE_STORE_FULL) {
+      d.store = off;
+      off = align256(off + (long long)d.nt * d.npts * esz);
+    } else if (store->mode == AWE_STORE_CHECKPOINT) {
+      d.store = off;
+      off = align256(off + (long long)store->nslots * 2 * d.npts * esz);
+      d.scale = off;
+      off = align256(off + (long long)store->nslots * 2 * 4);
+    }
+  }
+  P->ws_bytes = (size_t)off;
+
+  if (nd == 3) {
+    P->ty = 8;
+    P->bz = 0;
+  }
+  awe_status st = build_tables(P, prob->rec_pos);
+  if (st != AWE_OK) {
+    delete P;
+    return st;
+  }
+  (void)rec_rows;
+  if (store->mode == AWE_STORE_CHECKPOINT) {
+    awe::build_schedule(P->nsteps, store->nslots, P->sched);
+    const size_t na = P->sched.size() / 3;
+    P->sched_first_reverse = na;
+    for (size_t i = 0; i < na; ++i)
+      if (P->sched[3 * i] == awe::kReverse) {
+        P->sched_first_reverse = i;
+        break;
+      }
+  }
+  st = upload_tables(P);
+  if (st != AWE_OK) {
+    delete P;
+    return st;
+  }
+  *out = P;
+  return AWE_OK;
+}
+
+awe_status awe_plan_workspace_size(const awe_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(AWE_ERR_INVALID_ARG, "NULL argument");
+  *bytes = plan->ws_bytes;
+  return AWE_OK;
+}
+
+void awe_plan_destroy(awe_plan* plan) {
+  if (!plan) return;
+  for (hipEvent_t e : plan->prof_ev) (void)hipEventDestroy(e);
+  if (plan->dev) (void)hipFree(plan->dev);
+  delete plan;
+}
+
+awe_status awe_profile_enable(awe_plan* P, int64_t max_launches) {
+  if (!P || max_launches < 1) return fail(AWE_ERR_INVALID_ARG, "bad profiling arguments");
+  for (hipEvent_t e : P->prof_ev) (void)hipEventDestroy(e);
+  P->prof_ev.clear();
+  P->prof_cls.clear();
+  P->prof_next = 0;
+  P->prof_ev.resize(2 * (size_t)max_launches, nullptr);
+  for (auto& e : P->prof_ev) AWE_HIP(hipEventCreate(&e));
+  return AWE_OK;
+}
+
+awe_status awe_profile_read(awe_plan* P, int64_t counts[3], double ms[3]) {
+  if (!P || !counts || !ms) return fail(AWE_ERR_INVALID_ARG, "bad profiling arguments");
+  for (int c = 0; c < 3; ++c) {
+    counts[c] = 0;
+    ms[c] = 0.0;
+  }
+  if (P->prof_next > 0) AWE_HIP(hipEventSynchronize(P->prof_ev[P->prof_next - 1]));
+  for (size_t i = 0; 2 * i + 1 < P->prof_next; ++i) {
+    float t = 0.f;
+    AWE_HIP(hipEventElapsedTime(&t, P->prof_ev[2 * i], P->prof_ev[2 * i + 1]));
+    const int c = P->prof_cls[i];
+    counts[c] += 1;
+    ms[c] += t;
+  }
+  P->prof_next = 0;
+  P->prof_cls.clear();
+  return AWE_OK;
+}
+
+awe_status awe_profile_disable(awe_plan* P) {
+  if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  for (hipEvent_t e : P->prof_ev) (void)hipEventDestroy(e);
+  P->prof_ev.clear();
+  P->prof_cls.clear();
+  P->prof_next = 0;
+  return AWE_OK;
+}
+
+awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, int keep, void* ws,
+                       size_t ws_bytes, void* stream) {
+  awe_status st = check_ws(P, ws, ws_bytes);
+  if (st != AWE_OK) return st;
+  if (!m || !q) return fail(AWE_ERR_INVALID_ARG, "m and q must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool store = keep && P->store.mode != AWE_STORE_NONE;
+  P->kept_ws = nullptr;
+  if ((st = prepare(P, m, ws, true, false, s)) != AWE_OK) return st;
+  awe::StepArgs a = base_args(P, ws);
+  a.q = q;
+  a.d = d;
+  if (store && P->store.mode == AWE_STORE_CHECKPOINT) {
+    awe::StepArgs aa = a;
+    if ((st = run_actions(P, a, aa, 0, P->sched_first_reverse, s)) != AWE_OK) return st;
+  } else {
+    const int full = store && P->store.mode == AWE_STORE_FULL;
+    for (int n = 1; n <= P->nsteps; ++n)
+      if ((st = step_fwd(P, a, n, full, s)) != AWE_OK) return st;
+  }
+  if (d) AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 0, s));
+  if (store) P->kept_ws = ws;
+  return AWE_OK;
+}
+
+awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float* dd, double* g,
+                        float* v, void* ws, size_t ws_bytes, void* stream) {
+  awe_status st = check_ws(P, ws, ws_bytes);
+  if (st != AWE_OK) return st;
+  if (!dd || !q) return fail(AWE_ERR_INVALID_ARG, "q and dd must not be NULL");
+  if (P->store.mode == AWE_STORE_NONE || P->kept_ws != ws)
+    return fail(AWE_ERR_STATE, "the workspace holds no kept forward wavefield of this plan");
+  (void)m;  // the coefficients of the kept forward are reused
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  for (int i = 0; i < P->nshot; ++i) {
+    const ShotDev& d = P->sd[i];
+    AWE_HIP(awe::launch_fill(w, d.fld + 2 * d.npts * 4, 2 * d.npts * 4, s));
+  }
+  if (g) AWE_HIP(awe::launch_fill(w, P->acc_off, P->acc_bytes, s));
+  awe::StepArgs fa = base_args(P, ws);
+  fa.q = q;
+  awe::StepArgs aa = base_args(P, ws);
+  aa.dd = dd;
+  aa.v = v;
+  if (P->store.mode == AWE_STORE_FULL) {
+    aa.image_src = g ? 1 : 0;
+    for (int n = P->nsteps; n >= 1; --n)
+      if ((st = step_adj(P, aa, n, s)) != AWE_OK) return st;
+  } else {
+    aa.image_src = g ? 2 : 0;
+    if ((st = run_actions(P, fa, aa, P->sched_first_reverse, P->sched.size() / 3, s)) != AWE_OK) return st;
+    P->kept_ws = nullptr;  // the recomputation overwrote the kept forward state
+  }
+  if (v) AWE_HIP(awe::launch_src_last(aa, P->nshot, s));
+  if (g)
+    AWE_HIP(awe::launch_grad_reduce(P->tab, (int)P->wins.size(), P->max_win_npts, w, g,
+                                    -1.0 / (P->dt * P->dt), s));
+  return AWE_OK;
+}
+
+awe_status awe_gradient(awe_plan* P, const float* m, const float* q, const float* dd, double* g,
+                        float* v, float* d, void* ws, size_t ws_bytes, void* stream) {
+  if (P && P->store.mode == AWE_STORE_NONE)
+    return fail(AWE_ERR_UNSUPPORTED, "gradient needs FULL or CHECKPOINT storage");
+  awe_status st = awe_forward(P, m, q, d, 1, ws, ws_bytes, stream);
+  if (st != AWE_OK) return st;
+  return awe_backward(P, m, q, dd, g, v, ws, ws_bytes, stream);
+}
+
+awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, void* ws,
+                       size_t ws_bytes, void* stream) {
+  awe_status st = check_ws(P, ws, ws_bytes);
+  if (st != AWE_OK) return st;
+  if (!m || !dd || !v) return fail(AWE_ERR_INVALID_ARG, "m, dd and v must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  P->kept_ws = nullptr;
+  if ((st = prepare(P, m, ws, false, true, s)) != AWE_OK) return st;
+  awe::StepArgs a = base_args(P, ws);
+  a.dd = dd;
+  a.v = v;
+  a.image_src = 0;
+  for (int n = P->nsteps; n >= 1; --n)
+    if ((st = step_adj(P, a, n, s)) != AWE_OK) return st;
+  AWE_HIP(awe::launch_src_last(a, P->nshot, s));
+  return AWE_OK;
+}
+
+awe_status awe_born(awe_plan* P, const float* m, const float* q, const float* dm, float* dd,
+                    void* ws, size_t ws_bytes, void* stream) {
+  awe_status st = check_ws(P, ws, ws_bytes);
+  if (st != AWE_OK) return st;
+  if (!m || !q || !dm || !dd) return fail(AWE_ERR_INVALID_ARG, "m, q, dm and dd must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  P->kept_ws = nullptr;
+  if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
+  awe::StepArgs a = base_args(P, ws);
+  a.q = q;
+  a.dm = dm;
+  a.d = dd;
+  for (int n = 1; n <= P->nsteps; ++n) {
+    a.step = n;
+    a.ntiles = P->active[n];
+    ProfScope ps(P, 2, s);
+    if (P->ndim == 2) AWE_HIP(awe::launch_born2d(a, P->tz, s));
+    else AWE_HIP(awe::launch_born3d(a, P->ty, P->bz, s));
+  }
+  AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 2, s));
+  return AWE_OK;
+}
+
+size_t awe_reduce_workspace_size(int64_t n) {
+  (void)n;
+  return (size_t)awe::kReduceBlocks * 8;
+}
+
+awe_status awe_residual(const float* d_pred, const float* d_obs, float* r, int64_t n, double* loss,
+                        void* ws, size_t ws_bytes, void* stream) {
+  if (!d_pred || !d_obs || n < 0) return fail(AWE_ERR_INVALID_ARG, "bad residual arguments");
+  if (!ws || ws_bytes < awe_reduce_workspace_size(n)) return fail(AWE_ERR_WORKSPACE, "reduction workspace too small");
+  AWE_HIP(awe::launch_residual(d_pred, d_obs, r, n, loss, static_cast<unsigned char*>(ws),
+                               static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
+awe_status awe_dot_f64(const float* a, const float* b, int64_t n, double* out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!a || !b || !out || n < 0) return fail(AWE_ERR_INVALID_ARG, "bad dot arguments");
+  if (!ws || ws_bytes < awe_reduce_workspace_size(n)) return fail(AWE_ERR_WORKSPACE, "reduction workspace too small");
+  AWE_HIP(awe::launch_dot(a, b, n, out, static_cast<unsigned char*>(ws), static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
+awe_status awe_dot_f64d(const double* a, const double* b, int64_t n, double* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (!a || !b || !out || n < 0) return fail(AWE_ERR_INVALID_ARG, "bad dot arguments");
+  if (!ws || ws_bytes < awe_reduce_workspace_size(n)) return fail(AWE_ERR_WORKSPACE, "reduction workspace too small");
+  AWE_HIP(awe::launch_dotd(a, b, n, out, static_cast<unsigned char*>(ws), static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
+awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions, int64_t cap,
+                                   int64_t* count) {
+  if (nsteps < 0 || nslots < 0 || !count || (cap > 0 && !actions))
+    return fail(AWE_ERR_INVALID_ARG, "bad schedule arguments");
+  std::vector<int32_t> v;
+  awe::build_schedule(nsteps, nslots, v);
+  *count = (int64_t)(v.size() / 3);
+  if (*count > cap) return fail(AWE_ERR_INVALID_ARG, "action buffer too small");
+  if (!v.empty()) std::memcpy(actions, v.data(), v.size() * sizeof(int32_t));
+  return AWE_OK;
+}
+
+}  // extern "C"

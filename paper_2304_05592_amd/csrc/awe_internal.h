@@ -1,0 +1,139 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+//
+// Workspace layout, device tables and kernel argument blocks.  All offsets into the
+// caller's workspace are byte offsets; all offsets into caller arrays (m, q, d, ...)
+// are element offsets as given in awe_shot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace awe {
+
+constexpr int kThreads = 256;   // 4 wave64 per workgroup
+constexpr int kTX = 64;         // 2D tile width: one wavefront spans the tile row
+constexpr int kHalo = 4;        // stencil radius (8th order)
+
+// Storage precision of a kept wavefield.
+enum Prec : int { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+
+// Per-shot description as the kernels read it.
+struct ShotDev {
+  int nx, ny, nz;          // computational grid (ny = 1 in 2D)
+  int nt;                  // local samples
+  int off;                 // global state index of the shot's local state 0 (end-aligned)
+  int nrec;
+  long long npts;          // nx * ny * nz
+  long long coef;          // byte offset of the window's FP32 coefficient array
+  long long fld;           // byte offset of field buffer 0; buffer b at fld + b * npts * 4
+  long long acc;           // byte offset of the FP64 gradient accumulator (-1: none)
+  long long store;         // byte offset of the kept wavefield (FULL: [nt][npts]; CHECKPOINT: [nslots][2][npts])
+  long long scale;         // byte offset of FP32 per-field scales (BF16 / FP16 storage)
+  long long m;             // element offset of the window in m, dm, g
+  long long q;             // element offset in q and v
+  long long d;             // element offset in d and dd
+  int src_i, src_j, src_k; // base node of the source (x, y, z indices)
+  int src_tile;            // tile index owning the source base node
+  float src_w[8];          // interpolation weight / h^ndim; corner = bx + 2 by + 4 bz (2D: bx + 2 bz)
+};
+
+// A tile of one shot: 2D = [z0, z0 + TZ) x [x0, x0 + 64); 3D = z-block x xy-tile.
+struct TileDev {
+  int shot;
+  int x0, y0, z0;
+  int gat_begin, gat_count;  // receivers whose base node lies in this tile
+  int inj_begin, inj_count;  // points of this tile touched by receivers (adjoint injection)
+};
+
+// One receiver: column r of the shot's traces, base node and weights.
+struct RecDev {
+  int shot;
+  int r;
+  int i, j, k;
+  int pad;
+  float w[8];                // corner = bx + 2 by + 4 bz (2D: bx + 2 bz)
+};
+
+// A grid point touched by receivers: tile-local coordinates and its CSR entry range.
+struct InjPoint {
+  int shot;
+  int lx, ly, lz;
+  int e_begin, e_count;
+  long long p;               // flat point index in the shot grid
+};
+
+struct InjEntry {
+  int r;                     // receiver column within the shot
+  float w;                   // interpolation weight
+};
+
+// A model window and the shots that run on it (ascending shot order in win_shots).
+struct WinDev {
+  long long m;               // element offset in m, dm, g
+  long long npts;
+  int sbegin, scount;
+};
+
+// Device tables of a plan (one allocation, pointers into it).
+struct Tables {
+  const ShotDev* shots;
+  const TileDev* tiles;
+  const RecDev* recs;        // all receivers, grouped by gather tile
+  const InjPoint* inj_pts;
+  const InjEntry* inj_ent;
+  const WinDev* wins;
+  const int* win_shots;
+};
+
+// Arguments of one time-step launch.
+struct StepArgs {
+  Tables t;
+  unsigned char* ws;         // workspace base
+  const float* q;            // source wavelets (forward / born)
+  float* d;                  // traces out (forward: d; born: J dm); may be null
+  const float* dd;           // data residual in (adjoint)
+  float* v;                  // F^T dd out (adjoint); may be null
+  const float* dm;           // model perturbation (born)
+  int ndim;
+  int step;                  // global index of the state being produced
+  int ntiles;                // tiles in this launch (active prefix of the tile list)
+  int nbl;
+  int store_prec;            // Prec of the FULL store (forward write / adjoint read)
+  int image_src;             // adjoint imaging: 0 none, 1 FULL store, 2 forward buffers (recompute)
+  float c[5];                // stencil weights / h^2
+  float eta_dt;              // damping amplitude / (nbl^2 dt): eta/dt = eta_dt * (dx^2 + dy^2 + dz^2)
+  float inv_dt2;             // 1 / dt^2 (Born source)
+};
+
+// Launchers (defined in the .hip files).  All enqueue on `stream`.
+hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, long long m_off,
+                       int nx, int ny, int nz, int nbl, double h, double dt, double amp,
+                       hipStream_t stream);
+hipError_t launch_fill(unsigned char* ws, long long off, long long nbytes, hipStream_t stream);
+hipError_t launch_fwd2d(const StepArgs& a, int tz, int store, hipStream_t stream);
+hipError_t launch_adj2d(const StepArgs& a, int tz, hipStream_t stream);
+hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t stream);
+hipError_t launch_fwd3d(const StepArgs& a, int ty, int bz, int store, hipStream_t stream);
+hipError_t launch_adj3d(const StepArgs& a, int ty, int bz, hipStream_t stream);
+hipError_t launch_born3d(const StepArgs& a, int ty, int bz, hipStream_t stream);
+hipError_t launch_inj3d(const StepArgs& a, int ninj, hipStream_t stream);
+// Gather the last forward sample d^{nt-1} (field = forward buffers) of every shot.
+hipError_t launch_gather_last(const StepArgs& a, int nshot, int total_recs, int buf_base, hipStream_t stream);
+// v^0 = R(x_s) w^1 / h^ndim and v^{nt-1} = 0 for every shot.
+hipError_t launch_src_last(const StepArgs& a, int nshot, hipStream_t stream);
+// Checkpoint slot copies: dir 0 = store (fields -> slot), 1 = restore (slot -> fields).
+hipError_t launch_slot(const StepArgs& a, int nshot, int slot, int state, int dir, hipStream_t stream);
+hipError_t launch_absmax(const StepArgs& a, int nshot, int slot, int state, hipStream_t stream);
+// g[window] = scale * sum over the window's shots (ascending) of their FP64 accumulators.
+hipError_t launch_grad_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws,
+                              double* g, double scale, hipStream_t stream);
+hipError_t launch_residual(const float* a, const float* b, float* r, long long n, double* loss,
+                           unsigned char* ws, hipStream_t stream);
+hipError_t launch_dot(const float* a, const float* b, long long n, double* out, unsigned char* ws,
+                      hipStream_t stream);
+hipError_t launch_dotd(const double* a, const double* b, long long n, double* out,
+                       unsigned char* ws, hipStream_t stream);
+constexpr int kReduceBlocks = 1024;
+
+}  // namespace awe

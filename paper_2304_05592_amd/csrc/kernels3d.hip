@@ -1,0 +1,427 @@
+// 3D time-step kernels for gfx950: forward, adjoint with imaging, Born, and the adjoint's
+// receiver injection.
+//
+// A workgroup (4 x wave64) owns a 64 x TY column block of (x, y) and marches along z over
+// [z0, z0 + bz).  Each thread keeps a 9-deep register queue of its columns' values along z
+// (one new plane read per step, coalesced 256-byte rows), writes the current plane into a
+// double-buffered LDS tile and reads the x/y neighbours (4-cell halo) from there: one
+// barrier per plane.  Arithmetic is the increment form of the 2D kernels (see
+// kernels2d.hip).  Receivers whose base node lies in the block are sampled from the
+// previous level (read-only during the step); the adjoint's receiver injection is a
+// separate pass over the touched points (launch_inj3d), applied after the step.
+#include "awe_internal.h"
+
+namespace awe {
+
+namespace {
+
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+  const int q = n >> 3, r = n & 7, x = bid & 7;
+  return x * q + min(x, r) + (bid >> 3);
+}
+
+__device__ __forceinline__ int border_dist(int i, int n, int nbl) {
+  return max(max(nbl - i, i - (n - 1 - nbl)), 0);
+}
+
+__device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int b) {
+  return reinterpret_cast<float*>(ws + S.fld) + (long long)b * S.npts;
+}
+
+__device__ __forceinline__ float interp8(const float* f, const ShotDev& S, int i, int j, int k,
+                                         const float* w) {
+  const long long nx = S.nx, nxy = (long long)S.nx * S.ny;
+  const long long p = (long long)k * nxy + (long long)j * nx + i;
+  return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + nx] + w[3] * f[p + nx + 1] +
+         w[4] * f[p + nxy] + w[5] * f[p + nxy + 1] + w[6] * f[p + nxy + nx] +
+         w[7] * f[p + nxy + nx + 1];
+}
+
+template <int TY>
+struct T3 {
+  static constexpr int W = kTX + 2 * kHalo;  // 72
+  static constexpr int H = TY + 2 * kHalo;
+  static constexpr int NC = TY / 4;          // y-rows per thread
+};
+
+// Loads the halo ring of plane z (rows y0-4..y0+TY+3, columns x0-4..x0+67 minus the
+// centre) into P.
+template <int TY>
+__device__ __forceinline__ void load_halo(float (*P)[T3<TY>::W], const float* __restrict__ f,
+                                          int nx, int ny, int nz, int x0, int y0, int z) {
+  constexpr int W = T3<TY>::W;
+  const bool zin = (unsigned)z < (unsigned)nz;
+  const long long zb = (long long)z * ny;
+  // top and bottom bands: 4 + 4 rows of 72
+  for (int e = threadIdx.x; e < 8 * W; e += kThreads) {
+    const int band = e / W, c = e - band * W;
+    const int r = band < 4 ? band : TY + band;  // 0..3 and TY+4..TY+7
+    const int y = y0 - kHalo + r, x = x0 - kHalo + c;
+    float v = 0.f;
+    if (zin && (unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * nx + x];
+    P[r][c] = v;
+  }
+  // left and right bands: TY rows of 4 + 4 columns
+  for (int e = threadIdx.x; e < TY * 8; e += kThreads) {
+    const int r = e >> 3, cc = e & 7;
+    const int c = cc < 4 ? cc : kTX + cc;  // 0..3 and 68..71
+    const int y = y0 + r, x = x0 - kHalo + c;
+    float v = 0.f;
+    if (zin && y < ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * nx + x];
+    P[r + kHalo][c] = v;
+  }
+}
+
+template <int TY>
+__device__ __forceinline__ float lap3(const float (*P)[T3<TY>::W], const float* q, int ly, int lx,
+                                      const float* c) {
+  const int R = ly + kHalo, C = lx + kHalo;
+  const float u = q[4];
+  float s = 0.f;
+#pragma unroll
+  for (int r = kHalo; r >= 1; --r) {
+    s += c[r] * ((P[R][C - r] - u) + (P[R][C + r] - u));
+    s += c[r] * ((P[R - r][C] - u) + (P[R + r][C] - u));
+    s += c[r] * ((q[4 - r] - u) + (q[4 + r] - u));
+  }
+  return s;
+}
+
+// One field marched along z: register queue Q[col][0..8] = planes z-4..z+4.
+template <int TY>
+struct Column {
+  float Q[T3<TY>::NC][9];
+};
+
+template <int TY>
+__device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny, int nz, int x,
+                                     int y, int z) {
+  return (x < nx && y < ny && (unsigned)z < (unsigned)nz) ? f[((long long)z * ny + y) * nx + x] : 0.f;
+}
+
+// ------------------------------------------------------------------------------ forward
+template <int TY, bool STORE>
+__global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) {
+  constexpr int NC = T3<TY>::NC;
+  __shared__ float P[2][T3<TY>::H][T3<TY>::W];
+  const int tid = xcd_tile(blockIdx.x, a.ntiles);
+  const TileDev T = a.t.tiles[tid];
+  const ShotDev& S = a.t.shots[T.shot];
+  const int k = a.step - S.off;
+  if (k < 1 || k >= S.nt) return;
+  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const float* __restrict__ u1 = fbuf(a.ws, S, (k - 1) & 1);
+  float* __restrict__ u2 = fbuf(a.ws, S, k & 1);
+  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int x = T.x0 + lane;
+  const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
+
+  if (a.d != nullptr) {
+    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+      const RecDev R = a.t.recs[T.gat_begin + t];
+      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp8(u1, S, R.i, R.j, R.k, R.w);
+    }
+  }
+  const float qk = a.q[S.q + k - 1];
+  const int dx = border_dist(x, nx, a.nbl);
+
+  float Q[NC][9];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int y = T.y0 + g * NC + c;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+  }
+  for (int z = T.z0; z < zend; ++z) {
+    const int b = (z - T.z0) & 1;
+    float pu2[NC], pcf[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int y = T.y0 + g * NC + c;
+      Q[c][8] = ldc<TY>(u1, nx, ny, nz, x, y, z + kHalo);
+      const bool in = x < nx && y < ny;
+      const long long p = ((long long)z * ny + y) * nx + x;
+      pu2[c] = in ? u2[p] : 0.f;
+      pcf[c] = in ? cf[p] : 0.f;
+      P[b][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
+    }
+    load_halo<TY>(P[b], u1, nx, ny, nz, T.x0, T.y0, z);
+    __syncthreads();
+    const int dz = border_dist(z, nz, a.nbl);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int ly = g * NC + c;
+      const int y = T.y0 + ly;
+      if (x < nx && y < ny) {
+        float lap = lap3<TY>(P[b], Q[c], ly, lane, a.c);
+        const int bx = x - S.src_i, by = y - S.src_j, bzz = z - S.src_k;
+        if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
+          lap += S.src_w[bx + 2 * by + 4 * bzz] * qk;
+        const int dy = border_dist(y, ny, a.nbl);
+        const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
+        const float u = Q[c][4];
+        const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
+        const float un = (u + u - pu2[c]) + incr;
+        const long long p = ((long long)z * ny + y) * nx + x;
+        u2[p] = un;
+        if (STORE) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------ adjoint
+template <int TY, int IMG>
+__global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) {
+  constexpr int NC = T3<TY>::NC;
+  __shared__ float P[2][T3<TY>::H][T3<TY>::W];
+  const int tid = xcd_tile(blockIdx.x, a.ntiles);
+  const TileDev T = a.t.tiles[tid];
+  const ShotDev& S = a.t.shots[T.shot];
+  const int j = a.step - S.off;
+  if (j < 1 || j >= S.nt) return;
+  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const float* __restrict__ w1 = fbuf(a.ws, S, 2 + ((j + 1) & 1));
+  float* __restrict__ w2 = fbuf(a.ws, S, 2 + (j & 1));
+  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
+  const float* __restrict__ uj = nullptr;
+  if (IMG == 1) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
+  if (IMG == 2) uj = fbuf(a.ws, S, j & 1);
+  double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int x = T.x0 + lane;
+  const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
+
+  if (a.v != nullptr && tid == S.src_tile && threadIdx.x == 0)
+    a.v[S.q + j] = interp8(w1, S, S.src_i, S.src_j, S.src_k, S.src_w);
+  const int dx = border_dist(x, nx, a.nbl);
+
+  float Q[NC][9];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int y = T.y0 + g * NC + c;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+  }
+  for (int z = T.z0; z < zend; ++z) {
+    const int b = (z - T.z0) & 1;
+    float pw2[NC], pcf[NC], pu[NC];
+    double pacc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int y = T.y0 + g * NC + c;
+      Q[c][8] = ldc<TY>(w1, nx, ny, nz, x, y, z + kHalo);
+      const bool in = x < nx && y < ny;
+      const long long p = ((long long)z * ny + y) * nx + x;
+      pw2[c] = in ? w2[p] : 0.f;
+      pcf[c] = in ? cf[p] : 0.f;
+      if (IMG) {
+        pu[c] = in ? uj[p] : 0.f;
+        pacc[c] = in ? acc[p] : 0.0;
+      }
+      P[b][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
+    }
+    load_halo<TY>(P[b], w1, nx, ny, nz, T.x0, T.y0, z);
+    __syncthreads();
+    const int dz = border_dist(z, nz, a.nbl);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int ly = g * NC + c;
+      const int y = T.y0 + ly;
+      if (x < nx && y < ny) {
+        const float lap = lap3<TY>(P[b], Q[c], ly, lane, a.c);
+        const int dy = border_dist(y, ny, a.nbl);
+        const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
+        const float w = Q[c][4];
+        const float incr = pcf[c] * (lap - eta * (w - pw2[c]));
+        const long long p = ((long long)z * ny + y) * nx + x;
+        w2[p] = (w + w - pw2[c]) + incr;
+        if (IMG) acc[p] = pacc[c] + (double)pu[c] * (double)incr;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
+    }
+  }
+}
+
+// Receiver injection after the adjoint step: w^j += coef P_r^T dd^j at the touched points
+// (and the matching imaging term).  One thread per touched point, entries in fixed order.
+__global__ void inj3d_kernel(StepArgs a, int ninj) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ninj) return;
+  const InjPoint Pt = a.t.inj_pts[t];
+  const ShotDev& S = a.t.shots[Pt.shot];
+  const int j = a.step - S.off;
+  if (j < 1 || j >= S.nt) return;
+  const float* ddj = a.dd + S.d + (long long)j * S.nrec;
+  float s = 0.f;
+  for (int e = 0; e < Pt.e_count; ++e) {
+    const InjEntry E = a.t.inj_ent[Pt.e_begin + e];
+    s += E.w * ddj[E.r];
+  }
+  const float add = reinterpret_cast<const float*>(a.ws + S.coef)[Pt.p] * s;
+  float* w = fbuf(a.ws, S, 2 + (j & 1));
+  w[Pt.p] += add;
+  if (a.image_src) {
+    const float u = a.image_src == 1
+                        ? reinterpret_cast<const float*>(a.ws + S.store)[(long long)j * S.npts + Pt.p]
+                        : fbuf(a.ws, S, j & 1)[Pt.p];
+    double* acc = reinterpret_cast<double*>(a.ws + S.acc);
+    acc[Pt.p] += (double)u * (double)add;
+  }
+}
+
+// ------------------------------------------------------------------------------ Born
+template <int TY>
+__global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen) {
+  constexpr int NC = T3<TY>::NC;
+  __shared__ float PU[2][T3<TY>::H][T3<TY>::W];
+  __shared__ float PD[2][T3<TY>::H][T3<TY>::W];
+  const int tid = xcd_tile(blockIdx.x, a.ntiles);
+  const TileDev T = a.t.tiles[tid];
+  const ShotDev& S = a.t.shots[T.shot];
+  const int k = a.step - S.off;
+  if (k < 1 || k >= S.nt) return;
+  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const float* __restrict__ u1 = fbuf(a.ws, S, (k - 1) & 1);
+  float* __restrict__ u2 = fbuf(a.ws, S, k & 1);
+  const float* __restrict__ d1 = fbuf(a.ws, S, 2 + ((k - 1) & 1));
+  float* __restrict__ d2 = fbuf(a.ws, S, 2 + (k & 1));
+  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
+  const float* __restrict__ dm = a.dm + S.m;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int x = T.x0 + lane;
+  const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
+
+  if (a.d != nullptr) {
+    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+      const RecDev R = a.t.recs[T.gat_begin + t];
+      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp8(d1, S, R.i, R.j, R.k, R.w);
+    }
+  }
+  const float qk = a.q[S.q + k - 1];
+  const int dx = border_dist(x, nx, a.nbl);
+
+  float QU[NC][9], QD[NC][9];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int y = T.y0 + g * NC + c;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      QU[c][t] = ldc<TY>(u1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+      QD[c][t] = ldc<TY>(d1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+    }
+  }
+  for (int z = T.z0; z < zend; ++z) {
+    const int b = (z - T.z0) & 1;
+    float pu2[NC], pd2[NC], pcf[NC], pdm[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int y = T.y0 + g * NC + c;
+      QU[c][8] = ldc<TY>(u1, nx, ny, nz, x, y, z + kHalo);
+      QD[c][8] = ldc<TY>(d1, nx, ny, nz, x, y, z + kHalo);
+      const bool in = x < nx && y < ny;
+      const long long p = ((long long)z * ny + y) * nx + x;
+      pu2[c] = in ? u2[p] : 0.f;
+      pd2[c] = in ? d2[p] : 0.f;
+      pcf[c] = in ? cf[p] : 0.f;
+      pdm[c] = in ? dm[p] : 0.f;
+      PU[b][g * NC + c + kHalo][lane + kHalo] = QU[c][4];
+      PD[b][g * NC + c + kHalo][lane + kHalo] = QD[c][4];
+    }
+    load_halo<TY>(PU[b], u1, nx, ny, nz, T.x0, T.y0, z);
+    load_halo<TY>(PD[b], d1, nx, ny, nz, T.x0, T.y0, z);
+    __syncthreads();
+    const int dz = border_dist(z, nz, a.nbl);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int ly = g * NC + c;
+      const int y = T.y0 + ly;
+      if (x < nx && y < ny) {
+        const int dy = border_dist(y, ny, a.nbl);
+        const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
+        const long long p = ((long long)z * ny + y) * nx + x;
+        float lap = lap3<TY>(PU[b], QU[c], ly, lane, a.c);
+        const int bx = x - S.src_i, by = y - S.src_j, bzz = z - S.src_k;
+        if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
+          lap += S.src_w[bx + 2 * by + 4 * bzz] * qk;
+        const float u = QU[c][4];
+        const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
+        u2[p] = (u + u - pu2[c]) + incr;
+        const float du = QD[c][4];
+        const float lapd = lap3<TY>(PD[b], QD[c], ly, lane, a.c) - pdm[c] * incr * a.inv_dt2;
+        const float incd = pcf[c] * (lapd - eta * (du - pd2[c]));
+        d2[p] = (du + du - pd2[c]) + incd;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        QU[c][t] = QU[c][t + 1];
+        QD[c][t] = QD[c][t + 1];
+      }
+    }
+  }
+}
+
+template <int TY>
+hipError_t fwd3d_ty(const StepArgs& a, int bz, int store, hipStream_t s) {
+  if (store) fwd3d_kernel<TY, true><<<a.ntiles, kThreads, 0, s>>>(a, bz);
+  else fwd3d_kernel<TY, false><<<a.ntiles, kThreads, 0, s>>>(a, bz);
+  return hipGetLastError();
+}
+
+template <int TY>
+hipError_t adj3d_ty(const StepArgs& a, int bz, hipStream_t s) {
+  switch (a.image_src) {
+    case 0: adj3d_kernel<TY, 0><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case 1: adj3d_kernel<TY, 1><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    default: adj3d_kernel<TY, 2><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// bz <= 0 means one block spans the whole depth of every shot.
+static int zlen(int bz) { return bz > 0 ? bz : 0x7fffffff; }
+
+hipError_t launch_fwd3d(const StepArgs& a, int ty, int bz, int store, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  switch (ty) {
+    case 4: return fwd3d_ty<4>(a, zlen(bz), store, s);
+    case 8: return fwd3d_ty<8>(a, zlen(bz), store, s);
+    case 16: return fwd3d_ty<16>(a, zlen(bz), store, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj3d(const StepArgs& a, int ty, int bz, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  switch (ty) {
+    case 4: return adj3d_ty<4>(a, zlen(bz), s);
+    case 8: return adj3d_ty<8>(a, zlen(bz), s);
+    case 16: return adj3d_ty<16>(a, zlen(bz), s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_born3d(const StepArgs& a, int ty, int bz, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  switch (ty) {
+    case 4: born3d_kernel<4><<<a.ntiles, kThreads, 0, s>>>(a, zlen(bz)); break;
+    case 8: born3d_kernel<8><<<a.ntiles, kThreads, 0, s>>>(a, zlen(bz)); break;
+    case 16: born3d_kernel<16><<<a.ntiles, kThreads, 0, s>>>(a, zlen(bz)); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_inj3d(const StepArgs& a, int ninj, hipStream_t s) {
+  if (ninj <= 0 || a.dd == nullptr) return hipSuccess;
+  inj3d_kernel<<<(ninj + kThreads - 1) / kThreads, kThreads, 0, s>>>(a, ninj);
+  return hipGetLastError();
+}
+
+}  // namespace awe

@@ -1,0 +1,277 @@
+// Auxiliary gfx950 kernels: coefficients, fills, last-sample gathers, checkpoint slots
+// with per-field scaling, the gradient reduction over shots and deterministic FP64
+// reductions (residual / misfit, dot products).
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "awe_internal.h"
+
+namespace awe {
+
+namespace {
+
+__device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int b) {
+  return reinterpret_cast<float*>(ws + S.fld) + (long long)b * S.npts;
+}
+
+__device__ __forceinline__ float interp_global(const float* f, const ShotDev& S, int ndim, int i,
+                                               int j, int k, const float* w) {
+  const long long nx = S.nx, nxy = (long long)S.nx * S.ny;
+  const long long p = (long long)k * nxy + (long long)j * nx + i;
+  if (ndim == 2) {
+    return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + nx] + w[3] * f[p + nx + 1];
+  }
+  return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + nx] + w[3] * f[p + nx + 1] +
+         w[4] * f[p + nxy] + w[5] * f[p + nxy + 1] + w[6] * f[p + nxy + nx] +
+         w[7] * f[p + nxy + nx + 1];
+}
+
+// m -> coef = dt^2 / (m + eta dt / 2), computed in FP64 and rounded once.
+__global__ void coef_kernel(const float* __restrict__ m, float* __restrict__ coef, int nx, int ny,
+                            int nz, int nbl, double dt, double amp_nbl2) {
+  const long long n = (long long)nx * ny * nz;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p % nx);
+    const int j = (int)((p / nx) % ny);
+    const int k = (int)(p / ((long long)nx * ny));
+    const int dx = max(max(nbl - i, i - (nx - 1 - nbl)), 0);
+    const int dy = ny > 1 ? max(max(nbl - j, j - (ny - 1 - nbl)), 0) : 0;
+    const int dz = max(max(nbl - k, k - (nz - 1 - nbl)), 0);
+    const double eta = amp_nbl2 * (double)(dx * dx + dy * dy + dz * dz);
+    coef[p] = (float)(dt * dt / ((double)m[p] + 0.5 * eta * dt));
+  }
+}
+
+__global__ void fill_kernel(uint4* __restrict__ p, long long n16, unsigned char* tail, int ntail) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = z;
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ void gather_last_kernel(StepArgs a, int total, int buf_base) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const RecDev R = a.t.recs[t];
+  const ShotDev& S = a.t.shots[R.shot];
+  const int k = S.nt - 1;
+  const float* f = fbuf(a.ws, S, buf_base + (k & 1));
+  a.d[S.d + (long long)k * S.nrec + R.r] = interp_global(f, S, a.ndim, R.i, R.j, R.k, R.w);
+}
+
+__global__ void src_last_kernel(StepArgs a, int nshot) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nshot) return;
+  const ShotDev& S = a.t.shots[s];
+  const float* w1 = fbuf(a.ws, S, 2 + 1);
+  a.v[S.q] = interp_global(w1, S, a.ndim, S.src_i, S.src_j, S.src_k, S.src_w);
+  a.v[S.q + S.nt - 1] = 0.f;
+}
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  return __bfloat16_as_ushort(__float2bfloat16(x));  // round to nearest even
+}
+__device__ __forceinline__ float from_bf16(unsigned short b) {
+  return __uint_as_float(((unsigned)b) << 16);
+}
+__device__ __forceinline__ unsigned short to_f16(float x) {
+  return __half_as_ushort(__float2half_rn(x));
+}
+__device__ __forceinline__ float from_f16(unsigned short b) {
+  return __half2float(__ushort_as_half(b));
+}
+
+__device__ __forceinline__ int lpar(int x) { return x & 1; }  // parity, also for negative x
+
+// Max |u| of the two fields of a state into scale[slot][0..1] (atomic max on the float bits
+// of non-negative values, which is exact and order independent).
+__global__ void absmax_kernel(StepArgs a, int slot, int state) {
+  const ShotDev& S = a.t.shots[blockIdx.y];
+  const int ls = state - S.off;
+  const float* f = fbuf(a.ws, S, lpar(ls - (int)blockIdx.z));
+  float mx = 0.f;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < S.npts;
+       p += (long long)gridDim.x * blockDim.x)
+    mx = fmaxf(mx, fabsf(f[p]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  __shared__ float red[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) mx = fmaxf(mx, red[w]);
+    unsigned* sc = reinterpret_cast<unsigned*>(a.ws + S.scale) + 2 * slot + blockIdx.z;
+    atomicMax(sc, __float_as_uint(mx));
+  }
+}
+
+// dir 0: slot <- (u^state, u^{state-1}); dir 1: fields <- slot.  blockIdx.y = shot,
+// blockIdx.z = which of the two fields.
+__global__ void slot_kernel(StepArgs a, int slot, int state, int dir) {
+  const ShotDev& S = a.t.shots[blockIdx.y];
+  const int fz = blockIdx.z;
+  const int ls = state - S.off;
+  float* f = fbuf(a.ws, S, lpar(ls - fz));
+  const long long base = ((long long)slot * 2 + fz) * S.npts;
+  const int prec = a.store_prec;
+  float s = 1.f, inv = 1.f;
+  if (prec != kFP32) {
+    s = reinterpret_cast<const float*>(a.ws + S.scale)[2 * slot + fz];
+    if (!(s > 0.f)) s = 1.f;
+    inv = 1.f / s;
+  }
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < S.npts;
+       p += (long long)gridDim.x * blockDim.x) {
+    if (prec == kFP32) {
+      float* st = reinterpret_cast<float*>(a.ws + S.store) + base;
+      if (dir == 0) st[p] = f[p]; else f[p] = st[p];
+    } else {
+      unsigned short* st = reinterpret_cast<unsigned short*>(a.ws + S.store) + base;
+      if (dir == 0) {
+        const float y = f[p] * inv;
+        st[p] = prec == kBF16 ? to_bf16(y) : to_f16(y);
+      } else {
+        f[p] = (prec == kBF16 ? from_bf16(st[p]) : from_f16(st[p])) * s;
+      }
+    }
+  }
+}
+
+__global__ void grad_reduce_kernel(Tables t, unsigned char* ws, double* __restrict__ g,
+                                   double scale) {
+  const WinDev W = t.wins[blockIdx.y];
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < W.npts;
+       p += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < W.scount; ++i) {
+      const ShotDev& S = t.shots[t.win_shots[W.sbegin + i]];
+      s += reinterpret_cast<const double*>(ws + S.acc)[p];
+    }
+    g[W.m + p] = scale * s;
+  }
+}
+
+// Deterministic reduction: block b sums a fixed contiguous chunk in a fixed order, then one
+// block sums the kReduceBlocks partials.
+__device__ __forceinline__ double block_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __shared__ double red[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  return s;
+}
+
+template <int KIND>  // 0 residual (r = a - b, sum r^2 / 2), 1 dot float, 2 dot double
+__global__ void partial_kernel(const void* a_, const void* b_, float* r, long long n,
+                               double* part) {
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double s = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    if (KIND == 0) {
+      const float x = ((const float*)a_)[i] - ((const float*)b_)[i];
+      if (r) r[i] = x;
+      s += 0.5 * (double)x * (double)x;
+    } else if (KIND == 1) {
+      s += (double)((const float*)a_)[i] * (double)((const float*)b_)[i];
+    } else {
+      s += ((const double*)a_)[i] * ((const double*)b_)[i];
+    }
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void final_kernel(const double* part, int np, double* out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *out = s;
+}
+
+int grid_for(long long n) {
+  long long b = (n + kThreads - 1) / kThreads;
+  return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, long long m_off,
+                       int nx, int ny, int nz, int nbl, double h, double dt, double amp,
+                       hipStream_t s) {
+  (void)h;
+  const long long n = (long long)nx * ny * nz;
+  const double amp_nbl2 = nbl > 0 ? amp / ((double)nbl * nbl) : 0.0;
+  coef_kernel<<<grid_for(n), kThreads, 0, s>>>(m + m_off, reinterpret_cast<float*>(ws + coef_off),
+                                                nx, ny, nz, nbl, dt, amp_nbl2);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(unsigned char* ws, long long off, long long nbytes, hipStream_t s) {
+  if (nbytes <= 0) return hipSuccess;
+  // off is 16-byte aligned by construction of the workspace layout
+  const long long n16 = nbytes / 16;
+  const int ntail = (int)(nbytes - n16 * 16);
+  fill_kernel<<<grid_for(n16), kThreads, 0, s>>>(reinterpret_cast<uint4*>(ws + off), n16,
+                                                 ws + off + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_last(const StepArgs& a, int nshot, int total, int buf_base, hipStream_t s) {
+  (void)nshot;
+  if (total <= 0 || a.d == nullptr) return hipSuccess;
+  gather_last_kernel<<<(total + kThreads - 1) / kThreads, kThreads, 0, s>>>(a, total, buf_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_src_last(const StepArgs& a, int nshot, hipStream_t s) {
+  if (a.v == nullptr) return hipSuccess;
+  src_last_kernel<<<(nshot + 63) / 64, 64, 0, s>>>(a, nshot);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const StepArgs& a, int nshot, int slot, int state, hipStream_t s) {
+  absmax_kernel<<<dim3(256, nshot, 2), kThreads, 0, s>>>(a, slot, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot(const StepArgs& a, int nshot, int slot, int state, int dir, hipStream_t s) {
+  slot_kernel<<<dim3(512, nshot, 2), kThreads, 0, s>>>(a, slot, state, dir);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws,
+                              double* g, double scale, hipStream_t s) {
+  grad_reduce_kernel<<<dim3(grid_for(max_npts), nwin), kThreads, 0, s>>>(t, ws, g, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const float* a, const float* b, float* r, long long n, double* loss,
+                           unsigned char* ws, hipStream_t s) {
+  double* part = reinterpret_cast<double*>(ws);
+  partial_kernel<0><<<kReduceBlocks, kThreads, 0, s>>>(a, b, r, n, part);
+  if (loss) final_kernel<<<1, kThreads, 0, s>>>(part, kReduceBlocks, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, long long n, double* out, unsigned char* ws,
+                      hipStream_t s) {
+  double* part = reinterpret_cast<double*>(ws);
+  partial_kernel<1><<<kReduceBlocks, kThreads, 0, s>>>(a, b, nullptr, n, part);
+  final_kernel<<<1, kThreads, 0, s>>>(part, kReduceBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dotd(const double* a, const double* b, long long n, double* out,
+                       unsigned char* ws, hipStream_t s) {
+  double* part = reinterpret_cast<double*>(ws);
+  partial_kernel<2><<<kReduceBlocks, kThreads, 0, s>>>(a, b, nullptr, n, part);
+  final_kernel<<<1, kThreads, 0, s>>>(part, kReduceBlocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace awe

@@ -47,3 +47,23 @@ def rel_l2(a, b):
     b = np.concatenate([np.ravel(x) for x in b]) if isinstance(b, (list, tuple)) else np.ravel(b)
     return float(np.linalg.norm(a.astype(np.float64) - b.astype(np.float64)) /
                  np.linalg.norm(b.astype(np.float64)))
+
+
+# ------------------------------------------------------------------------------ GPU side
+def make_plan(wl, storage=None, shots=None, **kw):
+    """Plan for the workload's shots (all, or the given indices) on its windows."""
+    import paper_2304_05592_amd as A
+    shots = range(wl.nshot) if shots is None else list(shots)
+    geoms = [A.ShotGeometry(wl.shots[s].window, wl.shots[s].nt, wl.shots[s].src, wl.shots[s].rec)
+             for s in shots]
+    windows = [wl.comp_shape(w) for w in range(wl.nwindow)]
+    return A.Plan(wl.ndim, wl.h, wl.dt, wl.nbl, wl.vmax, windows, geoms, storage=storage,
+                  damp_vref=wl.vmax, **kw)
+
+
+def gpu_inputs(wl, plan, shots=None, background=False):
+    """Packed float32 device tensors m (all windows) and q (the plan's shots)."""
+    shots = range(wl.nshot) if shots is None else list(shots)
+    m = plan.pack([wl.m(w, background=background) for w in range(wl.nwindow)], "m")
+    q = plan.pack([wl.q(s) for s in shots], "q")
+    return m, q

@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI that need no GPU: exported symbols, argument validation,
+and the binomial checkpoint schedule."""
+import math
+import re
+from functools import lru_cache
+
+import numpy as np
+import pytest
+
+import paper_2304_05592_amd as A
+from paper_2304_05592_amd import binding as B
+
+
+def _declared_functions():
+    text = open(B.os.path.join(B._HERE, "..", "include", "awe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(awe_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = A.lib()
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(A.EXPORTS)
+    assert L.awe_version() == 1
+
+
+def _problem(**over):
+    shot = B.AweShot()
+    shot.nx, shot.ny, shot.nz, shot.nt = 50, 1, 40, 100
+    shot.nrec = 2
+    shot.src[0], shot.src[1], shot.src[2] = 100.0, 0.0, 50.0
+    rec = np.array([[10.0, 0, 20.0], [200.0, 0, 20.0]])
+    p = B.AweProblem()
+    p.ndim, p.nbl, p.h, p.dt, p.vmax, p.damp_vref, p.damp_R = 2, 5, 10.0, 1.0, 3.0, 3.0, 1e-3
+    p.nshot = 1
+    for k, v in over.items():
+        if hasattr(shot, k):
+            setattr(shot, k, v)
+        else:
+            setattr(p, k, v)
+    arr = (B.AweShot * 1)(shot)
+    p.shots = B.ctypes.cast(arr, B.ctypes.POINTER(B.AweShot))
+    p.rec_pos = rec.ctypes.data_as(B.ctypes.POINTER(B.ctypes.c_double))
+    return p, (arr, rec)
+
+
+def _create(p, mode=0, nslots=0, prec=0):
+    st = B.AweStorage(mode, nslots, prec, 0)
+    h = B.ctypes.c_void_p()
+    s = A.lib().awe_plan_create(B.ctypes.byref(p), B.ctypes.byref(st), B.ctypes.byref(h))
+    if s == 0:
+        A.lib().awe_plan_destroy(h)
+    return s, A.lib().awe_last_error().decode()
+
+
+def test_cfl_violation_is_rejected():
+    lim = 2 / math.sqrt(2 * (205 / 72 + 2 * (8 / 5 + 1 / 5 + 8 / 315 + 1 / 560)))
+    p, keep = _problem(dt=1.01 * lim * 10.0 / 3.0)
+    s, msg = _create(p)
+    assert s == 3 and "stability" in msg
+
+
+def test_geometry_outside_grid_is_rejected():
+    p, keep = _problem()
+    keep[1][1, 0] = 1e5
+    s, msg = _create(p)
+    assert s == 4 and "receiver 1" in msg
+    p, keep = _problem()
+    p.shots[0].src[2] = -80.0
+    assert _create(p)[0] == 4
+
+
+@pytest.mark.parametrize("over,code", [({"ndim": 4}, 1), ({"nt": 1}, 1), ({"h": -1.0}, 1),
+                                       ({"damp_R": 0.0}, 1), ({"ny": 2}, 1), ({"nshot": 0}, 1)])
+def test_invalid_arguments_are_rejected(over, code):
+    p, keep = _problem(**over)
+    assert _create(p)[0] == code
+
+
+def test_bad_storage_is_rejected():
+    p, keep = _problem()
+    assert _create(p, mode=2, nslots=0)[0] == 1
+    assert _create(p, mode=7)[0] == 1
+    assert _create(p, mode=1, prec=1)[0] == 2
+
+
+# ------------------------------------------------------------------------------ schedule
+@lru_cache(None)
+def _dp(l, s):
+    """Minimal forward steps to reverse l states from a stored start with s free slots."""
+    if l == 0:
+        return 0
+    if s == 0:
+        return l * (l + 1) // 2
+    best = l + _dp(l - 1, s)
+    for c in range(1, l):
+        best = min(best, c + _dp(l - c, s - 1) + _dp(c - 1, s))
+    return best
+
+
+def _simulate(n, slots, actions):
+    """Replay the action list on a counter; returns the number of forward steps."""
+    cur, stored, steps, reversed_ = 0, {}, 0, []
+    for op, a, b in actions:
+        if op == 0:
+            assert a == cur and b > a
+            steps += b - a
+            cur = b
+        elif op == 1:
+            assert b == cur and 0 <= a < slots
+            stored[a] = b
+        elif op == 2:
+            if a == -1:
+                assert b == 0
+            else:
+                assert stored.get(a) == b
+            cur = b
+        elif op == 3:
+            assert a == cur
+            reversed_.append(a)
+    assert reversed_ == list(range(n, 0, -1))
+    return steps
+
+
+@pytest.mark.parametrize("n,s", [(1, 1), (2, 1), (10, 2), (37, 3), (60, 1), (60, 5), (25, 30),
+                                 (80, 0)])
+def test_checkpoint_schedule_is_valid_and_optimal(n, s):
+    acts = A.checkpoint_schedule(n, s)
+    steps = _simulate(n, s, acts)
+    assert steps == _dp(n, s)
+    # the first sweep advances 0 -> n once, before any reversal
+    first_rev = next(i for i, a in enumerate(acts) if a[0] == 3)
+    adv = [a for a in acts[:first_rev] if a[0] == 0]
+    assert adv[0][1] == 0 and adv[-1][2] == n
+    assert all(adv[i][2] == adv[i + 1][1] for i in range(len(adv) - 1))
+
+
+def test_checkpoint_schedule_large_counts_binomial_cost():
+    # 16 slots and ~5000 steps: every state reversed, cost r*n - C(s+r+1, s+2)-style sum
+    acts = A.checkpoint_schedule(5000, 16)
+    steps = _simulate(5000, 16, acts)
+    assert 3 * 5000 < steps < 5 * 5000

@@ -1,0 +1,220 @@
+"""GPU parity of the 2D path against the oracle, through the C ABI.
+
+Tolerance: relative L2 <= 1e-5 for float32 traces, adjoint samples, Born data and gradients
+(the float32 rounding floor of these sizes is ~1e-6).  Sizes span several 64 x 32 tiles with
+ragged edges; the oracle finishes each case in about a second.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2304_05592_amd as A
+import workloads as W
+from helpers import (gpu_inputs, make_plan, oracle_adjoint, oracle_born, oracle_forward,
+                     oracle_gradient, rel_l2, shot_kwargs)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+def _report(name, err):
+    print(f"{name}: rel-L2 {err:.3e}", flush=True)
+
+
+def _residuals(wl, seed=3):
+    return [W.synthetic_residual(wl.shots[s].nt, len(wl.shots[s].rec), wl.dt, wl.f0, seed + s)
+            for s in range(wl.nshot)]
+
+
+def _oracle_residual(wl):
+    """dd = F(m0) q - F(m_true) q from the oracle (both models from the generator)."""
+    d_true = oracle_forward(wl)
+    d0 = oracle_forward(wl, ms=[wl.m(w, background=True) for w in range(wl.nwindow)])
+    return [(a - b).astype(np.float32) for a, b in zip(d0, d_true)]
+
+
+def test_forward_parity_small_survey():
+    wl = W.small_2d()
+    plan = make_plan(wl)
+    m, q = gpu_inputs(wl, plan)
+    d = plan.forward(m, q)
+    _sync()
+    err = rel_l2(plan.unpack(d, "d"), oracle_forward(wl))
+    _report("forward small_2d", err)
+    assert err <= TOL
+
+
+def test_forward_parity_two_layer_full_size_mirror_and_determinism():
+    wl = W.make_config("c1_fwd")
+    plan = make_plan(wl)
+    m, q = gpu_inputs(wl, plan)
+    d1 = plan.forward(m, q)
+    d2 = plan.forward(m, q)
+    _sync()
+    got = plan.unpack(d1, "d")[0]
+    err = rel_l2(got, oracle_forward(wl)[0])
+    _report("forward c1_fwd", err)
+    assert err <= TOL
+    assert torch.equal(d1, d2)
+    assert np.array_equal(got[:, :50], got[:, 100:50:-1])
+
+
+def test_adjoint_parity():
+    wl = W.small_2d()
+    plan = make_plan(wl)
+    m, _ = gpu_inputs(wl, plan)
+    dds = _residuals(wl)
+    v = plan.adjoint(m, plan.pack(dds, "d"))
+    _sync()
+    err = rel_l2(plan.unpack(v, "q"), oracle_adjoint(wl, dds))
+    _report("adjoint small_2d", err)
+    assert err <= TOL
+
+
+def test_born_parity():
+    wl = W.small_2d()
+    plan = make_plan(wl)
+    m, q = gpu_inputs(wl, plan, background=True)
+    dms = [W.random_field(wl.comp_shape(0), 4, smooth_cells=2.0) * np.float32(0.01)]
+    dd = plan.born(m, q, plan.pack(dms, "m"))
+    _sync()
+    ms = [wl.m(0, background=True)]
+    err = rel_l2(plan.unpack(dd, "d"), oracle_born(wl, dms, ms=ms))
+    _report("born small_2d", err)
+    assert err <= TOL
+
+
+def test_gradient_full_storage_parity():
+    wl = W.small_2d()
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, plan, background=True)
+    dds = _oracle_residual(wl)
+    g, v, d = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+    _sync()
+    ms = [wl.m(0, background=True)]
+    g_ref = oracle_gradient(wl, dds, ms=ms)
+    err = rel_l2(plan.unpack(g, "m"), g_ref)
+    _report("gradient FULL small_2d", err)
+    assert err <= TOL
+    err_v = rel_l2(plan.unpack(v, "q"), oracle_adjoint(wl, dds, ms=ms))
+    _report("gradient v small_2d", err_v)
+    assert err_v <= TOL
+    assert rel_l2(plan.unpack(d, "d"), oracle_forward(wl, ms=ms)) <= TOL
+
+
+def test_checkpointed_gradient_is_bitwise_the_full_storage_gradient():
+    wl = W.small_2d()
+    dds = _residuals(wl)
+    out = []
+    for st in (A.Storage(A.STORE_FULL), A.Storage(A.STORE_CHECKPOINT, 3), A.Storage(A.STORE_CHECKPOINT, 1)):
+        plan = make_plan(wl, storage=st)
+        m, q = gpu_inputs(wl, plan, background=True)
+        g, v, _ = plan.gradient(m, q, plan.pack(dds, "d"), v=True)
+        _sync()
+        out.append((g.cpu(), v.cpu()))
+    for g, v in out[1:]:
+        assert torch.equal(g, out[0][0])
+        assert torch.equal(v, out[0][1])
+
+
+@pytest.mark.parametrize("prec,bound", [(A.PREC_BF16, 2e-2), (A.PREC_FP16, 2e-3)])
+def test_low_precision_checkpoints_error_is_reported(prec, bound):
+    wl = W.small_2d()
+    dds = _residuals(wl)
+    ref_plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, ref_plan, background=True)
+    g_ref, _, _ = ref_plan.gradient(m, q, ref_plan.pack(dds, "d"))
+    plan = make_plan(wl, storage=A.Storage(A.STORE_CHECKPOINT, 4, prec))
+    g, _, _ = plan.gradient(m, q, plan.pack(dds, "d"))
+    _sync()
+    err = rel_l2(g.cpu().numpy(), g_ref.cpu().numpy())
+    _report(f"gradient CHECKPOINT prec={prec} vs FP32", err)
+    assert 0 < err <= bound
+
+
+def test_uneven_windows_and_lengths_parity():
+    wl = W.small_2d(windows=[90, 70, 113], T_per_shot=[400.0, 250.0, 330.0])
+    dds = _residuals(wl)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_CHECKPOINT, 5))
+    m, q = gpu_inputs(wl, plan)
+    g, v, d = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+    _sync()
+    e_d = rel_l2(plan.unpack(d, "d"), oracle_forward(wl))
+    e_g = rel_l2(plan.unpack(g, "m"), oracle_gradient(wl, dds))
+    e_v = rel_l2(plan.unpack(v, "q"), oracle_adjoint(wl, dds))
+    _report("uneven forward", e_d)
+    _report("uneven gradient", e_g)
+    _report("uneven adjoint", e_v)
+    assert max(e_d, e_g, e_v) <= TOL
+
+
+def test_batched_equals_single_shot_bitwise():
+    wl = W.small_2d(nshot=4)
+    dds = _residuals(wl)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, plan)
+    _, vb, db = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+    _sync()
+    vb, db = plan.unpack(vb, "q"), plan.unpack(db, "d")
+    for s in range(wl.nshot):
+        p1 = make_plan(wl, storage=A.Storage(A.STORE_FULL), shots=[s])
+        m1, q1 = gpu_inputs(wl, p1, shots=[s])
+        _, v1, d1 = p1.gradient(m1, q1, p1.pack([dds[s]], "d"), v=True, d=True)
+        _sync()
+        assert np.array_equal(p1.unpack(d1, "d")[0], db[s])
+        assert np.array_equal(p1.unpack(v1, "q")[0], vb[s])
+
+
+def _dot_errors(a, b, na, nb):
+    """|a - b| relative to |a| and to the Cauchy-Schwarz scale ||Fx|| ||y||."""
+    return abs(a - b) / max(abs(a), abs(b)), abs(a - b) / (na * nb)
+
+
+def test_dot_tests_on_gpu_with_fp64_inner_products():
+    """FP32 operators, FP64 inner products: |<Fx,y> - <x,F^T y>| / (||Fx|| ||y||) <= 1e-6
+    (a few float32 roundings per trace sample); the plain relative difference is reported."""
+    wl = W.small_2d(nshot=2)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, _ = gpu_inputs(wl, plan)
+    rng = np.random.default_rng(0)
+    x = plan.pack([rng.standard_normal(s.nt) for s in wl.shots], "q")
+    y = plan.pack([rng.standard_normal((s.nt, len(s.rec))) for s in wl.shots], "d")
+    fx = plan.forward(m, x)
+    a = A.dot(fx, y).item()
+    b = A.dot(x, plan.adjoint(m, y)).item()
+    rel, scaled = _dot_errors(a, b, torch.linalg.norm(fx.double()).item(), torch.linalg.norm(y.double()).item())
+    _report("GPU F dot test (relative)", rel)
+    _report("GPU F dot test (scaled)", scaled)
+    assert scaled <= 1e-6 and rel <= 1e-3
+    dm = plan.pack([W.random_field(wl.comp_shape(0), 1)], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    jdm = plan.born(m, q, dm)
+    a = A.dot(jdm, y).item()
+    g, _, _ = plan.gradient(m, q, y)
+    b = A.dot(dm.double(), g).item()
+    rel, scaled = _dot_errors(a, b, torch.linalg.norm(jdm.double()).item(), torch.linalg.norm(y.double()).item())
+    _report("GPU J dot test (relative)", rel)
+    _report("GPU J dot test (scaled)", scaled)
+    assert scaled <= 1e-6 and rel <= 1e-3
+
+
+def test_residual_and_dot_kernels():
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal(1_234_567).astype(np.float32)
+    b = rng.standard_normal(1_234_567).astype(np.float32)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    r, loss = A.residual(ta, tb)
+    dot = A.dot(ta, tb)
+    _sync()
+    assert np.array_equal(r.cpu().numpy(), a - b)
+    ref = 0.5 * np.sum((a - b).astype(np.float64) ** 2)
+    assert abs(loss.item() - ref) <= 1e-12 * ref
+    refd = np.dot(a.astype(np.float64), b.astype(np.float64))
+    assert abs(dot.item() - refd) <= 1e-10 * np.abs(a.astype(np.float64) * b).sum()
+    # deterministic
+    assert A.dot(ta, tb).item() == dot.item()

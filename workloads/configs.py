@@ -115,7 +115,7 @@ def synthetic_residual(nt: int, nrec: int, dt: float, f0: float, seed: int) -> n
     w = (1.0 - 2.0 * a) * np.exp(-a)
     out = np.empty_like(white)
     for r in range(nrec):
-        out[:, r] = np.convolve(white[:, r], w, mode="same")
+        out[:, r] = np.convolve(white[:, r], w, mode="full")[half:half + nt]
     out /= np.abs(out).max()
     return out.astype(np.float32)
 
