@@ -711,7 +711,8 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
     const ShotDev& d = P->sd[i];
     AWE_HIP(awe::launch_fill(w, d.fld + 2 * d.npts * 4, 2 * d.npts * 4, s));
   }
-  if (g) AWE_HIP(awe::launch_fill(w, P->acc_off, P->acc_bytes, s));
+  if (g)
+    for (int i = 0; i < P->nshot; ++i) AWE_HIP(awe::launch_fill(w, P->sd[i].acc, P->sd[i].npts * 8, s));
   awe::StepArgs fa = base_args(P, ws);
   fa.q = q;
   awe::StepArgs aa = base_args(P, ws);
