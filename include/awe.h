@@ -119,7 +119,7 @@ typedef struct awe_plan awe_plan;
 /* Validate the problem, build geometry tables (device copies allocated here), choose
  * tile shapes and lay out the workspace.  Uses the current HIP device.
  * Shots may have different nt: their time axes are aligned at the last sample.
- * Errors: INVALID_ARG, CFL, GEOMETRY, UNSUPPORTED (FULL storage in BF16/FP16), HIP. */
+ * Errors: INVALID_ARG, CFL, GEOMETRY, UNSUPPORTED (CHECKPOINT storage in 3D), HIP. */
 awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, awe_plan** plan);
 
 /* Bytes of device workspace every compute call on this plan needs (256-byte aligned

@@ -18,6 +18,14 @@ constexpr int kHalo = 4;        // stencil radius (8th order)
 // Storage precision of a kept wavefield.
 enum Prec : int { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
+// Where the adjoint's imaging condition reads u^j: nowhere, the FULL store (FP32 / BF16 /
+// FP16, the latter two scaled per level) or the recomputed forward buffers.
+enum ImageSrc : int { kImgNone = 0, kImgFull32 = 1, kImgBuffers = 2, kImgFullBF16 = 3, kImgFullFP16 = 4 };
+
+// Forward-step storage of each level: none, FP32 copy, or scaled BF16 / FP16 (the level is
+// quantised one step later, once its max |u| is complete).
+enum StoreKind : int { kStoreNone = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreFP16 = 3 };
+
 // Per-shot description as the kernels read it.
 struct ShotDev {
   int nx, ny, nz;          // computational grid (ny = 1 in 2D)
@@ -29,7 +37,7 @@ struct ShotDev {
   long long fld;           // byte offset of field buffer 0; buffer b at fld + b * npts * 4
   long long acc;           // byte offset of the FP64 gradient accumulator (-1: none)
   long long store;         // byte offset of the kept wavefield (FULL: [nt][npts]; CHECKPOINT: [nslots][2][npts])
-  long long scale;         // byte offset of FP32 per-field scales (BF16 / FP16 storage)
+  long long scale;         // byte offset of FP32 per-field scales (FULL: [nt]; CHECKPOINT: [nslots][2])
   long long m;             // element offset of the window in m, dm, g
   long long q;             // element offset in q and v
   long long d;             // element offset in d and dd
@@ -99,8 +107,8 @@ struct StepArgs {
   int step;                  // global index of the state being produced
   int ntiles;                // tiles in this launch (active prefix of the tile list)
   int nbl;
-  int store_prec;            // Prec of the FULL store (forward write / adjoint read)
-  int image_src;             // adjoint imaging: 0 none, 1 FULL store, 2 forward buffers (recompute)
+  int store_prec;            // Prec of the kept wavefield (FULL store / checkpoint slots)
+  int image_src;             // adjoint imaging source, see ImageSrc
   float c[5];                // stencil weights / h^2
   float eta_dt;              // damping amplitude / (nbl^2 dt): eta/dt = eta_dt * (dx^2 + dy^2 + dz^2)
   float inv_dt2;             // 1 / dt^2 (Born source)
@@ -112,6 +120,8 @@ hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, lo
                        hipStream_t stream);
 hipError_t launch_fill(unsigned char* ws, long long off, long long nbytes, hipStream_t stream);
 hipError_t launch_fwd2d(const StepArgs& a, int tz, int store, hipStream_t stream);
+// Quantise the last forward level u^{nt-1} of every shot into the scaled FULL store.
+hipError_t launch_store_last(const StepArgs& a, int nshot, long long max_npts, hipStream_t stream);
 hipError_t launch_adj2d(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_fwd3d(const StepArgs& a, int ty, int bz, int store, hipStream_t stream);

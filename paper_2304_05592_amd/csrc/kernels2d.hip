@@ -16,6 +16,7 @@
 // before rounding, which gives the imaging condition and the Born source without the
 // cancellation of a second time difference.
 #include "awe_internal.h"
+#include "codec.h"
 
 namespace awe {
 
@@ -80,7 +81,7 @@ __device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int 
 
 // ------------------------------------------------------------------------------ forward
 // Produces u^k (k = step - off) for every shot in the tile list; samples d^{k-1}.
-template <int TZ, bool STORE>
+template <int TZ, int SK>
 __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
   constexpr int RPT = T2<TZ>::RPT;
   __shared__ float L[T2<TZ>::H][T2<TZ>::W];
@@ -117,6 +118,12 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
 
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
+  // 16-bit store: u^{k-1} (the centre values read here) is quantised with its finished scale
+  float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
+  unsigned short* st16 = SK >= kStoreBF16
+      ? reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts : nullptr;
+  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(scl[k - 1]) : 0.f;
+  float lmax = 0.f;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int lr = wv * RPT + i;
@@ -132,7 +139,15 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
     const float un = (u + u - pu2[i]) + incr;
     const long long p = (long long)z * nx + x;
     u2[p] = un;
-    if (STORE) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
+    if (SK == kStoreF32) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
+    if (SK >= kStoreBF16) {
+      lmax = fmaxf(lmax, fabsf(un));
+      if (k >= 2) st16[p] = enc16(u * inv_prev, SK == kStoreBF16);
+    }
+  }
+  if (SK >= kStoreBF16) {
+    lmax = wave_max(lmax);
+    if (lane == 0) atomicMax(reinterpret_cast<unsigned*>(scl) + k, __float_as_uint(lmax));
   }
 }
 
@@ -155,8 +170,14 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
   float* __restrict__ w2 = fbuf(a.ws, S, 2 + (j & 1));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const float* __restrict__ uj = nullptr;
-  if (IMG == 1) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == 2) uj = fbuf(a.ws, S, j & 1);
+  const unsigned short* __restrict__ uj16 = nullptr;
+  float usc = 1.f;
+  if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
+  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, j & 1);
+  if (IMG >= kImgFullBF16) {
+    uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
+    usc = reinterpret_cast<const float*>(a.ws + S.scale)[j];
+  }
   double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = T.x0 + lane;
@@ -172,7 +193,8 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
     pw2[i] = in ? w2[p] : 0.f;
     pcf[i] = in ? cf[p] : 0.f;
     if (IMG) {
-      pu[i] = in ? uj[p] : 0.f;
+      if (IMG >= kImgFullBF16) pu[i] = in ? dec16(uj16[p], IMG == kImgFullBF16) * usc : 0.f;
+      else pu[i] = in ? uj[p] : 0.f;
       pacc[i] = in ? acc[p] : 0.0;
     }
     if (has_inj) INJ[wv * RPT + i][lane] = 0.f;
@@ -285,17 +307,25 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
 
 template <int TZ>
 hipError_t fwd2d_tz(const StepArgs& a, int store, hipStream_t s) {
-  if (store) fwd2d_kernel<TZ, true><<<a.ntiles, kThreads, 0, s>>>(a);
-  else fwd2d_kernel<TZ, false><<<a.ntiles, kThreads, 0, s>>>(a);
+  switch (store) {
+    case kStoreNone: fwd2d_kernel<TZ, kStoreNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kStoreF32: fwd2d_kernel<TZ, kStoreF32><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kStoreBF16: fwd2d_kernel<TZ, kStoreBF16><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kStoreFP16: fwd2d_kernel<TZ, kStoreFP16><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template <int TZ>
 hipError_t adj2d_tz(const StepArgs& a, hipStream_t s) {
   switch (a.image_src) {
-    case 0: adj2d_kernel<TZ, 0><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case 1: adj2d_kernel<TZ, 1><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    default: adj2d_kernel<TZ, 2><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgNone: adj2d_kernel<TZ, kImgNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgFull32: adj2d_kernel<TZ, kImgFull32><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgBuffers: adj2d_kernel<TZ, kImgBuffers><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgFullBF16: adj2d_kernel<TZ, kImgFullBF16><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgFullFP16: adj2d_kernel<TZ, kImgFullFP16><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -10,6 +10,7 @@
 // previous level (read-only during the step); the adjoint's receiver injection is a
 // separate pass over the touched points (launch_inj3d), applied after the step.
 #include "awe_internal.h"
+#include "codec.h"
 
 namespace awe {
 
@@ -100,7 +101,7 @@ __device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny
 }
 
 // ------------------------------------------------------------------------------ forward
-template <int TY, bool STORE>
+template <int TY, int SK>
 __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) {
   constexpr int NC = T3<TY>::NC;
   __shared__ float P[2][T3<TY>::H][T3<TY>::W];
@@ -125,6 +126,11 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
   }
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
+  float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
+  unsigned short* st16 = SK >= kStoreBF16
+      ? reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts : nullptr;
+  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(scl[k - 1]) : 0.f;
+  float lmax = 0.f;
 
   float Q[NC][9];
 #pragma unroll
@@ -165,11 +171,19 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
         const float un = (u + u - pu2[c]) + incr;
         const long long p = ((long long)z * ny + y) * nx + x;
         u2[p] = un;
-        if (STORE) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
+        if (SK == kStoreF32) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
+        if (SK >= kStoreBF16) {
+          lmax = fmaxf(lmax, fabsf(un));
+          if (k >= 2) st16[p] = enc16(u * inv_prev, SK == kStoreBF16);
+        }
       }
 #pragma unroll
       for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
     }
+  }
+  if (SK >= kStoreBF16) {
+    lmax = wave_max(lmax);
+    if (lane == 0) atomicMax(reinterpret_cast<unsigned*>(scl) + k, __float_as_uint(lmax));
   }
 }
 
@@ -188,8 +202,14 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
   float* __restrict__ w2 = fbuf(a.ws, S, 2 + (j & 1));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const float* __restrict__ uj = nullptr;
-  if (IMG == 1) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == 2) uj = fbuf(a.ws, S, j & 1);
+  const unsigned short* __restrict__ uj16 = nullptr;
+  float usc = 1.f;
+  if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
+  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, j & 1);
+  if (IMG >= kImgFullBF16) {
+    uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
+    usc = reinterpret_cast<const float*>(a.ws + S.scale)[j];
+  }
   double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int x = T.x0 + lane;
@@ -219,7 +239,8 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
       pw2[c] = in ? w2[p] : 0.f;
       pcf[c] = in ? cf[p] : 0.f;
       if (IMG) {
-        pu[c] = in ? uj[p] : 0.f;
+        if (IMG >= kImgFullBF16) pu[c] = in ? dec16(uj16[p], IMG == kImgFullBF16) * usc : 0.f;
+        else pu[c] = in ? uj[p] : 0.f;
         pacc[c] = in ? acc[p] : 0.0;
       }
       P[b][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
@@ -266,9 +287,15 @@ __global__ void inj3d_kernel(StepArgs a, int ninj) {
   float* w = fbuf(a.ws, S, 2 + (j & 1));
   w[Pt.p] += add;
   if (a.image_src) {
-    const float u = a.image_src == 1
-                        ? reinterpret_cast<const float*>(a.ws + S.store)[(long long)j * S.npts + Pt.p]
-                        : fbuf(a.ws, S, j & 1)[Pt.p];
+    float u;
+    if (a.image_src == kImgFull32)
+      u = reinterpret_cast<const float*>(a.ws + S.store)[(long long)j * S.npts + Pt.p];
+    else if (a.image_src == kImgBuffers)
+      u = fbuf(a.ws, S, j & 1)[Pt.p];
+    else
+      u = dec16(reinterpret_cast<const unsigned short*>(a.ws + S.store)[(long long)j * S.npts + Pt.p],
+                a.image_src == kImgFullBF16) *
+          reinterpret_cast<const float*>(a.ws + S.scale)[j];
     double* acc = reinterpret_cast<double*>(a.ws + S.acc);
     acc[Pt.p] += (double)u * (double)add;
   }
@@ -367,17 +394,25 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
 
 template <int TY>
 hipError_t fwd3d_ty(const StepArgs& a, int bz, int store, hipStream_t s) {
-  if (store) fwd3d_kernel<TY, true><<<a.ntiles, kThreads, 0, s>>>(a, bz);
-  else fwd3d_kernel<TY, false><<<a.ntiles, kThreads, 0, s>>>(a, bz);
+  switch (store) {
+    case kStoreNone: fwd3d_kernel<TY, kStoreNone><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kStoreF32: fwd3d_kernel<TY, kStoreF32><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kStoreBF16: fwd3d_kernel<TY, kStoreBF16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kStoreFP16: fwd3d_kernel<TY, kStoreFP16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template <int TY>
 hipError_t adj3d_ty(const StepArgs& a, int bz, hipStream_t s) {
   switch (a.image_src) {
-    case 0: adj3d_kernel<TY, 0><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case 1: adj3d_kernel<TY, 1><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    default: adj3d_kernel<TY, 2><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kImgNone: adj3d_kernel<TY, kImgNone><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kImgFull32: adj3d_kernel<TY, kImgFull32><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kImgBuffers: adj3d_kernel<TY, kImgBuffers><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kImgFullBF16: adj3d_kernel<TY, kImgFullBF16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kImgFullFP16: adj3d_kernel<TY, kImgFullFP16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

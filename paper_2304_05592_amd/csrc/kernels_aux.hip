@@ -1,10 +1,8 @@
 // Auxiliary gfx950 kernels: coefficients, fills, last-sample gathers, checkpoint slots
 // with per-field scaling, the gradient reduction over shots and deterministic FP64
 // reductions (residual / misfit, dot products).
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
-
 #include "awe_internal.h"
+#include "codec.h"
 
 namespace awe {
 
@@ -70,19 +68,6 @@ __global__ void src_last_kernel(StepArgs a, int nshot) {
   a.v[S.q + S.nt - 1] = 0.f;
 }
 
-__device__ __forceinline__ unsigned short to_bf16(float x) {
-  return __bfloat16_as_ushort(__float2bfloat16(x));  // round to nearest even
-}
-__device__ __forceinline__ float from_bf16(unsigned short b) {
-  return __uint_as_float(((unsigned)b) << 16);
-}
-__device__ __forceinline__ unsigned short to_f16(float x) {
-  return __half_as_ushort(__float2half_rn(x));
-}
-__device__ __forceinline__ float from_f16(unsigned short b) {
-  return __half2float(__ushort_as_half(b));
-}
-
 __device__ __forceinline__ int lpar(int x) { return x & 1; }  // parity, also for negative x
 
 // Max |u| of the two fields of a state into scale[slot][0..1] (atomic max on the float bits
@@ -130,12 +115,26 @@ __global__ void slot_kernel(StepArgs a, int slot, int state, int dir) {
       unsigned short* st = reinterpret_cast<unsigned short*>(a.ws + S.store) + base;
       if (dir == 0) {
         const float y = f[p] * inv;
-        st[p] = prec == kBF16 ? to_bf16(y) : to_f16(y);
+        st[p] = enc16(y, prec == kBF16);
       } else {
-        f[p] = (prec == kBF16 ? from_bf16(st[p]) : from_f16(st[p])) * s;
+        f[p] = dec16(st[p], prec == kBF16) * s;
       }
     }
   }
+}
+
+// u^{nt-1} -> FULL 16-bit store with its scale (the forward steps quantise u^1..u^{nt-2}).
+__global__ void store_last_kernel(StepArgs a) {
+  const ShotDev& S = a.t.shots[blockIdx.y];
+  const int k = S.nt - 1;
+  if (k < 1) return;
+  const float* f = fbuf(a.ws, S, k & 1);
+  const float inv = inv_scale(reinterpret_cast<const float*>(a.ws + S.scale)[k]);
+  unsigned short* st = reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)k * S.npts;
+  const int bf = a.store_prec == kBF16;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < S.npts;
+       p += (long long)gridDim.x * blockDim.x)
+    st[p] = enc16(f[p] * inv, bf);
 }
 
 __global__ void grad_reduce_kernel(Tables t, unsigned char* ws, double* __restrict__ g,
@@ -241,6 +240,11 @@ hipError_t launch_absmax(const StepArgs& a, int nshot, int slot, int state, hipS
 
 hipError_t launch_slot(const StepArgs& a, int nshot, int slot, int state, int dir, hipStream_t s) {
   slot_kernel<<<dim3(512, nshot, 2), kThreads, 0, s>>>(a, slot, state, dir);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_last(const StepArgs& a, int nshot, long long max_npts, hipStream_t s) {
+  store_last_kernel<<<dim3(grid_for(max_npts), nshot), kThreads, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -84,7 +84,8 @@ def test_bad_storage_is_rejected():
     p, keep = _problem()
     assert _create(p, mode=2, nslots=0)[0] == 1
     assert _create(p, mode=7)[0] == 1
-    assert _create(p, mode=1, prec=1)[0] == 2
+    p3, keep3 = _problem(ndim=3, ny=40)
+    assert _create(p3, mode=2, nslots=4)[0] == 2
 
 
 # ------------------------------------------------------------------------------ schedule

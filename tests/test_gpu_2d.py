@@ -218,3 +218,23 @@ def test_residual_and_dot_kernels():
     assert abs(dot.item() - refd) <= 1e-10 * np.abs(a.astype(np.float64) * b).sum()
     # deterministic
     assert A.dot(ta, tb).item() == dot.item()
+
+
+@pytest.mark.parametrize("prec,bound", [(A.PREC_BF16, 2e-2), (A.PREC_FP16, 2e-3)])
+def test_full_16bit_storage_gradient_error_is_reported(prec, bound):
+    wl = W.small_2d()
+    dds = _residuals(wl)
+    ref = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, ref, background=True)
+    g32, v32, d32 = ref.gradient(m, q, ref.pack(dds, "d"), v=True, d=True)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL, 0, prec))
+    g16, v16, d16 = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+    _sync()
+    err = rel_l2(g16.cpu().numpy(), g32.cpu().numpy())
+    _report(f"gradient FULL prec={prec} vs FP32", err)
+    assert 0 < err <= bound
+    # the stored precision does not touch the forward traces or F^T dd
+    assert torch.equal(d16, d32) and torch.equal(v16, v32)
+    e_or = rel_l2(plan.unpack(g16, "m"), oracle_gradient(wl, dds, ms=[wl.m(0, background=True)]))
+    _report(f"gradient FULL prec={prec} vs oracle", e_or)
+    assert e_or <= bound

@@ -73,3 +73,18 @@ def test_checkpointed_3d_gradient_matches_full_storage_bitwise():
         torch.cuda.synchronize()
         res.append(g.cpu())
     assert torch.equal(res[0], res[1])
+
+
+@pytest.mark.parametrize("prec,bound", [(A.PREC_BF16, 2e-2), (A.PREC_FP16, 2e-3)])
+def test_full_16bit_storage_gradient_3d(prec, bound):
+    wl = _small()
+    dds = _residuals(wl)
+    ref = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, ref, background=True)
+    g32, _, _ = ref.gradient(m, q, ref.pack(dds, "d"))
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL, 0, prec))
+    g16, _, _ = plan.gradient(m, q, plan.pack(dds, "d"))
+    torch.cuda.synchronize()
+    err = rel_l2(g16.cpu().numpy(), g32.cpu().numpy())
+    print(f"gradient 3D FULL prec={prec} vs FP32: rel-L2 {err:.3e}", flush=True)
+    assert 0 < err <= bound
