@@ -1,15 +1,19 @@
-"""Benchmark: batched 2D forward + adjoint-state gradient on one MI355X.
+"""Benchmark of the acoustic forward / adjoint-state gradient path on one MI355X.
 
-One step = the whole hot path over one batch of shots: forward solve with the wavefield
-kept in HBM (traces d = F(m0) q), residual r = d - d_obs with the misfit 1/2 ||r||^2 in
-FP64, and the reverse sweep g = J^T r (adjoint solve + imaging condition, FP64
-accumulation), all in the library's HIP kernels.  Inputs are resident in HBM before the
-timed region.  Default workload: 650 x 341 physical grid at 6.25 m (+40-cell damping
-border), layered 1.5-4.5 km/s with a 5 % smoothed random perturbation, 16 shots, 650
-receivers, T = 1.8 s, full FP32 wavefield storage.
+Default (the headline line): the batched 2D gradient workload c2_grad — 650 x 341 physical
+grid at 6.25 m (+40-cell damping border), layered 1.5-4.5 km/s with a 5 % smoothed random
+perturbation, 16 shots, 650 receivers, T = 1.8 s, full FP32 wavefield storage.  One step =
+the whole hot path over the 16 shots: forward solve keeping the wavefield in HBM, residual
+r = d - d_obs with the misfit 1/2 ||r||^2 in FP64, and the reverse sweep g = J^T r (adjoint
+solve + imaging condition, FP64 accumulation), all in the library's HIP kernels, captured
+once into a HIP graph and replayed.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.  Gpts/s = sum over shots of N_s (nt_s - 1) per step, divided by the
-step time (N_s = computational-grid points of the shot).
+Other workloads (--config): c3_autograd (torch.autograd through the wave operator with 16
+checkpoint slots per shot, 32 shots), c4_uneven (64 uneven windows, forward, batched vs 64
+sequential single-shot runs), c5_3d (256^3, FULL BF16 / FP16 storage gradient).
+
+Prints one JSON line.  Gpts/s = sum over shots of N_s (nt_s - 1) per step / step time
+(N_s = computational-grid points of the shot).
 """
 from __future__ import annotations
 
@@ -26,9 +30,17 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "Gpts/s (fwd+adjoint gradient) batched vs single-shot; % HBM roofline"
-# algorithmic bytes per grid point per launch of each step kernel (FP32 fields, FP64 accumulator)
-BYTES_FWD_FULL = 20   # read u^{k-1}, u^{k-2}, coef; write u^k and its stored copy
-BYTES_ADJ_FULL = 36   # read w^{j+1}, w^{j+2}, coef, stored u^j, acc (8); write w^j, acc (8)
+# Algorithmic HBM bytes per grid point per launch of each step kernel (FP32 fields, FP64
+# accumulator); see the kernel table of the design notes.
+BYTES = {
+    ("forward", "none"): 16,   # read u^{k-1}, u^{k-2}, coef; write u^k
+    ("forward", "fp32"): 20,   # + stored copy of u^k
+    ("forward", "16bit"): 18,  # + 16-bit stored copy
+    ("adjoint", "none"): 16,   # read w^{j+1}, w^{j+2}, coef; write w^j
+    ("adjoint", "fp32"): 36,   # + stored u^j (4) + accumulator read and write (16)
+    ("adjoint", "16bit"): 34,  # + 16-bit stored u^j (2) + accumulator (16)
+    ("adjoint", "buffers"): 36,  # u^j from the recomputed forward buffer (4) + accumulator
+}
 
 
 def parse():
@@ -36,11 +48,21 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2_grad")
+    ap.add_argument("--config", default="c2_grad",
+                    choices=["c2_grad", "c3_autograd", "c4_uneven", "c5_3d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=120, help="time steps of the oracle sample")
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "fp32"],
+                    help="stored-wavefield precision of the 3D workload")
     return ap.parse_args()
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
 
 
 def make_plan(wl, storage, shots):
@@ -52,15 +74,44 @@ def make_plan(wl, storage, shots):
                   damp_vref=wl.vmax)
 
 
-class Runner:
-    """Inputs resident on the GPU and one step of the hot path."""
+def points_of(wl, shots):
+    per_step = sum(int(np.prod(wl.comp_shape(wl.shots[s].window))) * (wl.shots[s].nt - 1) for s in shots)
+    per_launch = sum(int(np.prod(wl.comp_shape(wl.shots[s].window))) for s in shots)
+    return per_step, per_launch
 
-    def __init__(self, wl, shots):
+
+def kernel_table(prof, launch_points, kinds):
+    """Per kernel class: launches, average event time and achieved algorithmic GB/s."""
+    out = {}
+    for name, kind in kinds.items():
+        cnt, ms = prof[name]
+        if cnt == 0:
+            continue
+        avg_ms = ms / cnt
+        b = BYTES[(name, kind)] * launch_points
+        out[name] = {"launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 3), "bytes_per_point": BYTES[(name, kind)],
+                     "bytes_per_launch": b, "achieved_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1)}
+    return out
+
+
+def roofline_of(kernels, names):
+    # every forward launch is paired with one adjoint launch: the dominant kernel is the
+    # one with the longer average launch
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    ach = kernels[dom]["achieved_GBs"]
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": names[dom]}
+
+
+class GradientRunner:
+    """Forward (kept wavefield) + residual + reverse sweep on resident inputs."""
+
+    def __init__(self, wl, shots, storage, autotune=True):
         import torch
         import paper_2304_05592_amd as A
         self.A, self.torch = A, torch
         self.wl, self.shots = wl, list(shots)
-        self.plan = make_plan(wl, A.Storage(A.STORE_FULL), self.shots)
+        self.plan = make_plan(wl, storage, self.shots)
         p = self.plan
         self.m_true = p.pack([wl.m(w) for w in range(wl.nwindow)], "m")
         self.m0 = p.pack([wl.m(w, background=True) for w in range(wl.nwindow)], "m")
@@ -70,10 +121,12 @@ class Runner:
         self.d = torch.empty_like(self.d_obs)
         self.r = torch.empty_like(self.d_obs)
         self.g = torch.empty(p.layout.m_size, dtype=torch.float64, device="cuda")
-        self.points = sum(int(np.prod(wl.comp_shape(wl.shots[s].window))) * (wl.shots[s].nt - 1)
-                          for s in self.shots)
-        self.launch_points = sum(int(np.prod(wl.comp_shape(wl.shots[s].window))) for s in self.shots)
-        torch.cuda.synchronize()
+        self.points, self.launch_points = points_of(wl, self.shots)
+        self.tiles = None
+        if autotune:
+            self.tiles, _ = p.autotune(self.m0, self.q, self.d_obs, probe_steps=32, ws=self.ws)
+        self.graph = None
+        sync()
 
     def step(self):
         p = self.plan
@@ -81,31 +134,50 @@ class Runner:
         _, self.loss = self.A.residual(self.d, self.d_obs, r=self.r)
         p.backward(self.m0, self.q, self.r, g=self.g, v=None, ws=self.ws)
 
-    def timed(self, steps, warmup, profile=False):
+    def capture(self, profile_stride=0):
+        """Capture one step into a HIP graph (with kernel-timing events every stride-th launch)."""
         torch = self.torch
-        for _ in range(warmup):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
             self.step()
-        torch.cuda.synchronize()
-        if profile:
-            nt = max(self.wl.shots[s].nt for s in self.shots)
-            self.plan.profile_enable(2 * nt * steps + 16)
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().wait_stream(s)
+        sync()
+        if profile_stride:
+            nt = max(self.wl.shots[i].nt for i in self.shots)
+            self.plan.profile_enable(2 * nt // profile_stride + 64, profile_stride)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=s):
+            self.step()
+        sync()
+
+    def run(self, steps, warmup, use_graph, profile):
+        """Seconds per step (and the kernel-timing summary of the timed region)."""
+        for _ in range(warmup):
+            self.graph.replay() if use_graph else self.step()
+        sync()
+        if profile and not use_graph:
+            nt = max(self.wl.shots[i].nt for i in self.shots)
+            self.plan.profile_enable(2 * nt * steps + 64, 1)
+        sync()
         t0 = time.perf_counter()
         for _ in range(steps):
-            self.step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+            self.graph.replay() if use_graph else self.step()
+        sync()
+        sec = (time.perf_counter() - t0) / steps
         prof = self.plan.profile_read() if profile else None
         if profile:
             self.plan.profile_disable()
-        return (t1 - t0) / steps, prof
+        return sec, prof
 
     def release(self):
+        self.graph = None
         self.ws = None
         self.plan = None
         self.torch.cuda.empty_cache()
 
 
+# ------------------------------------------------------------------------------ CPU baseline
 def _oracle_worker(args):
     """Oracle gradient of one shot over its first n samples (runs in a worker process)."""
     name, s, n = args
@@ -116,14 +188,11 @@ def _oracle_worker(args):
     kw = dict(src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax)
     m_true, m0 = wl.m(sh.window), wl.m(sh.window, background=True)
     q = wl.q(s)[:n]
-    t0 = time.perf_counter()
     d_obs = O.forward(m_true, q, **kw)
     t1 = time.perf_counter()
     g = O.gradient(m0, q, O.forward(m0, q, **kw) - d_obs, **kw)
     t2 = time.perf_counter()
     npts = int(np.prod(wl.comp_shape(sh.window)))
-    # work of one step of the path for this sample: N (n - 1) point-updates; the oracle's
-    # gradient call repeats the forward, so time the forward-with-residual + gradient part
     return npts * (n - 1), (t2 - t1), float(np.abs(g).max())
 
 
@@ -143,9 +212,195 @@ def cpu_baseline(name, wl, n):
     return {"value": round(work / busy / 1e9, 6), "unit": "Gpts/s", "cores": workers,
             "kind": "oracle",
             "sample": f"{workers} shots of {name} in parallel processes (one NumPy thread each), "
-                      f"first {jobs[0][2]} of {wl.shots[0].nt} time samples, gradient "
-                      f"(forward with stored wavefield + adjoint + imaging) in FP64; "
-                      f"wall {wall:.1f} s including process start"}
+                      f"first {jobs[0][2]} of {wl.shots[0].nt} time samples; timed: forward at the "
+                      f"starting model + gradient call (forward with stored wavefield, adjoint, "
+                      f"imaging) in FP64; wall {wall:.1f} s including process start"}
+
+
+def base_line(args, wl, value, sec, extra):
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic"}
+    out.update(extra)
+    return out
+
+
+# ------------------------------------------------------------------------------ workloads
+def bench_c2(args):
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL), autotune=not args.no_autotune)
+    # timed region 1: eager launches with HIP events around every launch (kernel durations)
+    eager_sec, prof = run.run(max(1, min(args.steps, 3)), args.warmup, use_graph=False, profile=True)
+    timing = ("HIP events around every launch of an eager timed region of the same step, on the "
+              "launch stream (the graph's kernels are the same launches)")
+    # timed region 2: the step captured into a HIP graph and replayed (headline value)
+    use_graph = not args.no_graph
+    if use_graph:
+        run.capture(profile_stride=0)
+        sec, _ = run.run(args.steps, args.warmup, use_graph=True, profile=False)
+    else:
+        sec = eager_sec
+    value = run.points / sec / 1e9
+    kernels = kernel_table(prof, run.launch_points, {"forward": "fp32", "adjoint": "fp32"})
+    names = {"forward": "fwd2d step (forward + stored FP32 copy, 20 B/point)",
+             "adjoint": "adj2d step (adjoint + imaging from stored FP32, 36 B/point)"}
+    roof = roofline_of(kernels, names)
+    path_bytes = (BYTES[("forward", "fp32")] + BYTES[("adjoint", "fp32")]) * run.points
+    loss = float(run.loss.item())
+    tiles, points = run.tiles, run.points
+    run.release()
+    single = None
+    if not args.no_single:
+        r1 = GradientRunner(wl, [0], A.Storage(A.STORE_FULL), autotune=False)
+        s1, _ = r1.run(max(1, min(args.steps, 2)), 1, use_graph=False, profile=False)
+        single = {"value": round(r1.points / s1 / 1e9, 3), "ms_per_step": round(s1 * 1e3, 2), "shots": 1,
+                  "form": "one shot, one launch per time step, no graph"}
+        r1.release()
+    cpu = None if args.no_cpu_baseline else cpu_baseline("c2_grad", wl, args.cpu_steps)
+    return base_line(args, wl, value, sec, {
+        "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
+                   "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "FULL FP32",
+                   "batched": True, "graph": use_graph, "tiles": tiles},
+        "roofline": roof, "cpu_baseline": cpu, "kernels": kernels, "kernel_timing": timing,
+        "path_hbm_fraction": round(path_bytes / sec / 1e9 / PEAK_HBM_GBS, 4),
+        "eager": {"value": round(points / eager_sec / 1e9, 3), "ms_per_step": round(eager_sec * 1e3, 3)},
+        "single_shot": single, "loss": loss})
+
+
+def bench_c3(args):
+    """Autograd through WaveOp with 16 FP32 checkpoint slots per shot (32 shots)."""
+    import torch
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c3_autograd")
+    plan = make_plan(wl, A.Storage(A.STORE_CHECKPOINT, 16, A.PREC_FP32), range(wl.nshot))
+    m_true = plan.pack([wl.m(0)], "m")
+    m0 = plan.pack([wl.m(0, background=True)], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    d_obs = plan.forward(m_true, q)
+    tiles = None if args.no_autotune else plan.autotune(m0, q, d_obs, probe_steps=32)[0]
+    points, launch_points = points_of(wl, range(wl.nshot))
+
+    def step():
+        m = m0.clone().requires_grad_(True)
+        loss = A.misfit(A.wave_forward(m, q, plan), d_obs)
+        loss.backward()
+        return loss, m.grad
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    plan.profile_enable(wl.shots[0].nt * args.steps + 64, 8)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, g = step()
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    prof = plan.profile_read()
+    kernels = kernel_table(prof, launch_points, {"forward": "none", "adjoint": "buffers"})
+    names = {"forward": "fwd2d step (forward / recompute, 16 B/point)",
+             "adjoint": "adj2d step (adjoint + imaging from recomputed buffers, 36 B/point)"}
+    fwd_steps = prof["forward"][0] / args.steps
+    return base_line(args, wl, points / sec / 1e9, sec, {
+        "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
+                   "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "CHECKPOINT 16 FP32 slots",
+                   "batched": True, "graph": False, "tiles": tiles},
+        "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
+        "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item())})
+
+
+def bench_c4(args):
+    """64 uneven windows, forward: one batched graph-captured run vs 64 sequential runs."""
+    import torch
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c4_uneven")
+    plan = make_plan(wl, A.Storage(A.STORE_NONE), range(wl.nshot))
+    m = plan.pack([wl.m(w) for w in range(wl.nwindow)], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    ws = plan.workspace()
+    d = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
+    tiles = None if args.no_autotune else plan.autotune(m, q, None, probe_steps=32, ws=ws)[0]
+    points, launch_points = points_of(wl, range(wl.nshot))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.forward(m, q, d=d, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    sync()
+    nt_max = max(sh.nt for sh in wl.shots)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.forward(m, q, d=d, ws=ws)
+    sync()
+    for _ in range(args.warmup):
+        graph.replay()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    # kernel durations: one eager pass with HIP events around every launch
+    plan.profile_enable(nt_max + 64, 1)
+    plan.forward(m, q, d=d, ws=ws)
+    prof = plan.profile_read()
+    plan.profile_disable()
+    # sequential single-shot runs (plain form: one plan per shot, one launch per step)
+    seq = 0.0
+    for sidx in range(wl.nshot):
+        p1 = make_plan(wl, A.Storage(A.STORE_NONE), [sidx])
+        m1 = p1.pack([wl.m(w) for w in range(wl.nwindow)], "m")
+        q1 = p1.pack([wl.q(sidx)], "q")
+        ws1 = p1.workspace()
+        d1 = torch.empty(p1.layout.d_size, dtype=torch.float32, device="cuda")
+        p1.forward(m1, q1, d=d1, ws=ws1)
+        sync()
+        t0 = time.perf_counter()
+        p1.forward(m1, q1, d=d1, ws=ws1)
+        sync()
+        seq += time.perf_counter() - t0
+        del p1, m1, q1, ws1, d1
+    # launches cover different numbers of active shots: use the pass's summed kernel time
+    cnt, ms = prof["forward"]
+    est_kernel_s = ms * 1e-3
+    ach = BYTES[("forward", "none")] * points / est_kernel_s / 1e9 if cnt else None
+    return base_line(args, wl, points / sec / 1e9, sec, {
+        "metric": "Gpts/s forward, uneven batching (64 windows) batched vs sequential single-shot",
+        "config": {"workload": f"{wl.name}: {wl.description}", "shots": wl.nshot,
+                   "points_per_pass": points, "storage": "none (forward)", "batched": True,
+                   "graph": True, "tiles": tiles},
+        "roofline": {"bound": "hbm", "achieved": None if ach is None else round(ach, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": None if ach is None else round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "fwd2d step (16 B/point); summed event time of one eager pass"},
+        "sequential_single_shot": {"value": round(points / seq / 1e9, 3), "seconds": round(seq, 4)},
+        "cpu_baseline": None})
+
+
+def bench_c5(args):
+    """3D 256^3 single shot: forward + gradient with FULL 16-bit (or FP32) storage."""
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c5_3d")
+    prec = {"bf16": A.PREC_BF16, "fp16": A.PREC_FP16, "fp32": A.PREC_FP32}[args.prec]
+    run = GradientRunner(wl, [0], A.Storage(A.STORE_FULL, 0, prec), autotune=not args.no_autotune)
+    sec, prof = run.run(args.steps, args.warmup, use_graph=False, profile=True)
+    kind = "fp32" if prec == A.PREC_FP32 else "16bit"
+    kernels = kernel_table(prof, run.launch_points, {"forward": kind, "adjoint": kind})
+    names = {"forward": f"fwd3d step (forward + stored {args.prec} copy, {BYTES[('forward', kind)]} B/point)",
+             "adjoint": f"adj3d step (adjoint + imaging, {BYTES[('adjoint', kind)]} B/point)"}
+    out = base_line(args, wl, run.points / sec / 1e9, sec, {
+        "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
+                   "shots": 1, "nt": int(wl.shots[0].nt), "storage": f"FULL {args.prec}",
+                   "batched": False, "graph": False, "tiles": run.tiles},
+        "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
+        "loss": float(run.loss.item())})
+    run.release()
+    return out
 
 
 def main():
@@ -155,55 +410,8 @@ def main():
               "multi-GPU runs (shots sharded over GPUs, FP64 gradient all-reduce) are not part "
               "of this build", file=sys.stderr)
         sys.exit(2)
-    import torch
-    import workloads as W
-    wl = W.make_config(args.config)
-    run = Runner(wl, range(wl.nshot))
-    sec, prof = run.timed(args.steps, args.warmup, profile=True)
-    value = run.points / sec / 1e9
-    loss = float(run.loss.item())
-    kernels = {}
-    for name, bpp in (("forward", BYTES_FWD_FULL), ("adjoint", BYTES_ADJ_FULL)):
-        cnt, ms = prof[name]
-        avg_ms = ms / max(cnt, 1)
-        bytes_per_launch = bpp * run.launch_points
-        kernels[name] = {"launches": cnt, "avg_us": round(avg_ms * 1e3, 3),
-                         "bytes_per_launch": bytes_per_launch,
-                         "achieved_GBs": round(bytes_per_launch / (avg_ms * 1e-3) / 1e9, 1)}
-    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-    ach = kernels[dom]["achieved_GBs"]
-    roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": f"adj2d step (adjoint + imaging, {BYTES_ADJ_FULL} B/point)" if dom == "adjoint"
-                else f"fwd2d step (forward + stored copy, {BYTES_FWD_FULL} B/point)"}
-    path_bytes = (BYTES_FWD_FULL + BYTES_ADJ_FULL) * run.points
-    run.release()
-
-    single = None
-    if not args.no_single:
-        r1 = Runner(wl, [0])
-        sec1, _ = r1.timed(max(1, min(args.steps, 2)), 1)
-        single = {"value": round(r1.points / sec1 / 1e9, 3), "ms_per_step": round(sec1 * 1e3, 2),
-                  "shots": 1}
-        r1.release()
-
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.config, wl, args.cpu_steps)
-    out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
-                   "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "FULL FP32",
-                   "batched": True},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "kernels": kernels,
-        "path_hbm_fraction": round(path_bytes / sec / 1e9 / PEAK_HBM_GBS, 4),
-        "single_shot": single,
-        "loss": loss,
-    }
-    print(json.dumps(out), flush=True)
+    fn = {"c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4, "c5_3d": bench_c5}[args.config]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -185,14 +185,32 @@ awe_status awe_dot_f64d(const double* a, const double* b, int64_t n, double* out
 awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions,
                                    int64_t cap, int64_t* count);
 
-/* Kernel timing (measurement aid).  After awe_profile_enable, every time-step launch of
- * the compute calls on this plan is bracketed by a pair of HIP events recorded on the
- * call's stream, for up to max_launches launches; further launches are not timed.
- * Classes: 0 forward step, 1 adjoint step (with imaging and, in 3D, receiver injection),
- * 2 Born step.  awe_profile_read waits for the recorded events, returns per class the
- * number of timed launches and the summed event time in ms, and restarts the count.
- * Enabling creates HIP events (host resources, no device memory). */
-awe_status awe_profile_enable(awe_plan* plan, int64_t max_launches);
+/* Tile-shape autotuner (setup call, synchronous): for each candidate tile shape (2D: 8, 16,
+ * 32 or 64 rows of 64 columns; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth,
+ * 128 or 64 planes) times probe_steps forward steps and probe_steps adjoint steps (with
+ * imaging when the plan keeps a wavefield) on the given inputs, then keeps the fastest
+ * shape for all later calls.  dd may be NULL (the adjoint probe then injects nothing).
+ * Rebuilds the plan's device tables (the only allocation), overwrites the workspace and
+ * drops any kept forward.  chosen (may be NULL) receives {tz, ty, bz} of the winner and
+ * best_ms (may be NULL) its probe time. */
+awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, const float* dd,
+                             int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
+                             int32_t chosen[3], double* best_ms);
+
+/* Set the tile shape explicitly (tz: 8, 16, 32 or 64 rows in 2D; ty: 4, 8 or 16 rows and bz:
+ * z-block length, 0 = full depth, in 3D).  Results do not depend on the tile shape (every
+ * point's arithmetic and every sum's order are fixed).  Rebuilds the device tables. */
+awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz);
+
+/* Kernel timing (measurement aid).  After awe_profile_enable, every stride-th time-step
+ * launch of the compute calls on this plan is bracketed by a pair of HIP events recorded on
+ * the call's stream, for up to max_launches timed launches; further launches are not timed.
+ * The records are stream work, so they are also captured into a HIP graph and then time
+ * the graph's replays.  Classes: 0 forward step, 1 adjoint step (with imaging and, in 3D,
+ * receiver injection), 2 Born step.  awe_profile_read waits for the recorded events,
+ * returns per class the number of timed launches and the summed event time in ms, and
+ * restarts the count.  Enabling creates HIP events (host resources, no device memory). */
+awe_status awe_profile_enable(awe_plan* plan, int64_t max_launches, int32_t stride);
 awe_status awe_profile_read(awe_plan* plan, int64_t counts[3], double ms[3]);
 awe_status awe_profile_disable(awe_plan* plan);
 

@@ -10,11 +10,12 @@ from .binding import (EXPORTS, LIB_PATH, PREC_BF16, PREC_FP16, PREC_FP32, STORE_
 
 __all__ = ["EXPORTS", "LIB_PATH", "PREC_BF16", "PREC_FP16", "PREC_FP32", "STORE_CHECKPOINT",
            "STORE_FULL", "STORE_NONE", "AweError", "Plan", "ShotGeometry", "Storage",
-           "checkpoint_schedule", "dot", "lib", "residual", "WaveOp", "wave_forward", "extend_edge"]
+           "checkpoint_schedule", "dot", "lib", "residual", "WaveOp", "wave_forward", "extend_edge",
+           "misfit"]
 
 
 def __getattr__(name):
-    if name in ("WaveOp", "wave_forward", "extend_edge"):
+    if name in ("WaveOp", "wave_forward", "extend_edge", "misfit"):
         from . import autograd
         return getattr(autograd, name)
     raise AttributeError(name)

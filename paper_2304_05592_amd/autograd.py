@@ -49,6 +49,28 @@ class WaveOp(torch.autograd.Function):
         return gm, gq, None
 
 
+class Misfit(torch.autograd.Function):
+    """phi = 1/2 ||d - d_obs||^2 on the library's residual kernel (FP64 accumulation); the
+    pullback of phi is r = d - d_obs (the loss of the paper's AD listing)."""
+
+    @staticmethod
+    def forward(ctx, d: torch.Tensor, d_obs: torch.Tensor):
+        from .binding import residual
+        r, loss = residual(d.detach().contiguous(), d_obs.detach().contiguous())
+        ctx.save_for_backward(r)
+        return loss.squeeze(0)
+
+    @staticmethod
+    def backward(ctx, gphi: torch.Tensor):
+        (r,) = ctx.saved_tensors
+        return (r * gphi.to(r.dtype)), None
+
+
+def misfit(d: torch.Tensor, d_obs: torch.Tensor) -> torch.Tensor:
+    """Differentiable 1/2 ||d - d_obs||^2 (FP64 scalar)."""
+    return Misfit.apply(d, d_obs)
+
+
 def wave_forward(m: torch.Tensor, q: torch.Tensor, plan: Plan) -> torch.Tensor:
     """Differentiable d = F(m) q."""
     return WaveOp.apply(m, q, plan)

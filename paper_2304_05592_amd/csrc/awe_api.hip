@@ -60,6 +60,7 @@ struct awe_plan {
   int tz = 32;            // 2D tile rows
   int ty = 8, bz = 0;     // 3D tile rows in y and z-block length
   std::vector<awe_shot> shots;
+  std::vector<double> rec_pos;    // copy of the problem's receiver rows
   std::vector<ShotDev> sd;
   std::vector<TileDev> tiles;
   std::vector<int> active;        // active[n]: tiles of the shots with off < n
@@ -86,6 +87,8 @@ struct awe_plan {
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_cls;
   size_t prof_next = 0;
+  int prof_stride = 1;
+  long long prof_seen = 0;
 };
 
 namespace {
@@ -345,7 +348,7 @@ struct ProfScope {
   hipStream_t s;
   bool on;
   ProfScope(awe_plan* P_, int cls, hipStream_t s_) : P(P_), s(s_) {
-    on = P->prof_next + 2 <= P->prof_ev.size();
+    on = P->prof_next + 2 <= P->prof_ev.size() && (P->prof_seen++ % P->prof_stride) == 0;
     if (on) {
       (void)hipEventRecord(P->prof_ev[P->prof_next], s);
       P->prof_cls.push_back(cls);
@@ -599,12 +602,14 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     P->ty = 8;
     P->bz = 0;
   }
-  awe_status st = build_tables(P, prob->rec_pos);
+  P->rec_pos.assign(3 * (size_t)std::max<long long>(rec_rows, 1), 0.0);
+  if (prob->rec_pos && rec_rows > 0)
+    std::copy(prob->rec_pos, prob->rec_pos + 3 * rec_rows, P->rec_pos.begin());
+  awe_status st = build_tables(P, P->rec_pos.data());
   if (st != AWE_OK) {
     delete P;
     return st;
   }
-  (void)rec_rows;
   if (store->mode == AWE_STORE_CHECKPOINT) {
     awe::build_schedule(P->nsteps, store->nslots, P->sched);
     const size_t na = P->sched.size() / 3;
@@ -637,8 +642,100 @@ void awe_plan_destroy(awe_plan* plan) {
   delete plan;
 }
 
-awe_status awe_profile_enable(awe_plan* P, int64_t max_launches) {
-  if (!P || max_launches < 1) return fail(AWE_ERR_INVALID_ARG, "bad profiling arguments");
+awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const float* dd,
+                             int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
+                             int32_t chosen[3], double* best_ms) {
+  awe_status st = check_ws(P, ws, ws_bytes);
+  if (st != AWE_OK) return st;
+  if (!m || !q || probe_steps < 1) return fail(AWE_ERR_INVALID_ARG, "autotune needs m, q and probe_steps >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  P->kept_ws = nullptr;
+  struct Cand { int tz, ty, bz; };
+  std::vector<Cand> cands;
+  if (P->ndim == 2) {
+    for (int tz : {8, 16, 32, 64}) cands.push_back({tz, P->ty, P->bz});
+  } else {
+    for (int ty : {4, 8, 16})
+      for (int bz : {0, 128, 64}) cands.push_back({P->tz, ty, bz});
+  }
+  const int probe = std::min<int>(probe_steps, P->nsteps);
+  hipEvent_t e0, e1;
+  AWE_HIP(hipEventCreate(&e0));
+  AWE_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  Cand win = cands[0];
+  for (const Cand& c : cands) {
+    P->tz = c.tz;
+    P->ty = c.ty;
+    P->bz = c.bz;
+    if ((st = build_tables(P, P->rec_pos.data())) != AWE_OK) return st;
+    if ((st = upload_tables(P)) != AWE_OK) return st;
+    if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
+    for (int i = 0; i < P->nshot; ++i)
+      if (P->sd[i].acc >= 0)
+        AWE_HIP(awe::launch_fill(static_cast<unsigned char*>(ws), P->sd[i].acc, P->sd[i].npts * 8, s));
+    awe::StepArgs fa = base_args(P, ws);
+    fa.q = q;
+    awe::StepArgs aa = base_args(P, ws);
+    aa.dd = dd;
+    aa.image_src = P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
+    const size_t saved = P->prof_ev.size();  // keep the probe out of kernel timing
+    std::vector<hipEvent_t> keep_ev;
+    keep_ev.swap(P->prof_ev);
+    AWE_HIP(hipEventRecord(e0, s));
+    for (int n = 1; n <= probe; ++n)
+      if ((st = step_fwd(P, fa, n, awe::kStoreNone, s)) != AWE_OK) return st;
+    for (int n = P->nsteps; n > P->nsteps - probe; --n) {
+      aa.step = n;
+      aa.ntiles = P->active[n];
+      if (P->ndim == 2) AWE_HIP(awe::launch_adj2d(aa, P->tz, s));
+      else AWE_HIP(awe::launch_adj3d(aa, P->ty, P->bz, s));
+    }
+    AWE_HIP(hipEventRecord(e1, s));
+    AWE_HIP(hipEventSynchronize(e1));
+    keep_ev.swap(P->prof_ev);
+    (void)saved;
+    float ms = 0.f;
+    AWE_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      win = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->tz = win.tz;
+  P->ty = win.ty;
+  P->bz = win.bz;
+  if ((st = build_tables(P, P->rec_pos.data())) != AWE_OK) return st;
+  if ((st = upload_tables(P)) != AWE_OK) return st;
+  if (chosen) {
+    chosen[0] = P->tz;
+    chosen[1] = P->ty;
+    chosen[2] = P->bz;
+  }
+  if (best_ms) *best_ms = best;
+  return AWE_OK;
+}
+
+awe_status awe_plan_set_tiles(awe_plan* P, int32_t tz, int32_t ty, int32_t bz) {
+  if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  if (tz != 8 && tz != 16 && tz != 32 && tz != 64) return fail(AWE_ERR_INVALID_ARG, "tz must be 8, 16, 32 or 64");
+  if (ty != 4 && ty != 8 && ty != 16) return fail(AWE_ERR_INVALID_ARG, "ty must be 4, 8 or 16");
+  if (bz < 0) return fail(AWE_ERR_INVALID_ARG, "bz must be >= 0");
+  P->tz = tz;
+  P->ty = ty;
+  P->bz = bz;
+  P->kept_ws = nullptr;
+  awe_status st = build_tables(P, P->rec_pos.data());
+  if (st != AWE_OK) return st;
+  return upload_tables(P);
+}
+
+awe_status awe_profile_enable(awe_plan* P, int64_t max_launches, int32_t stride) {
+  if (!P || max_launches < 1 || stride < 1) return fail(AWE_ERR_INVALID_ARG, "bad profiling arguments");
+  P->prof_stride = stride;
+  P->prof_seen = 0;
   for (hipEvent_t e : P->prof_ev) (void)hipEventDestroy(e);
   P->prof_ev.clear();
   P->prof_cls.clear();
@@ -663,6 +760,7 @@ awe_status awe_profile_read(awe_plan* P, int64_t counts[3], double ms[3]) {
     ms[c] += t;
   }
   P->prof_next = 0;
+  P->prof_seen = 0;
   P->prof_cls.clear();
   return AWE_OK;
 }

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
   double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = T.x0 + lane;
-  const bool has_inj = T.inj_count > 0;
+  const bool has_inj = T.inj_count > 0 && a.dd != nullptr;  // no residual: nothing to inject
 
   float pw2[RPT], pcf[RPT], pu[RPT];
   double pacc[RPT];

@@ -238,3 +238,35 @@ def test_full_16bit_storage_gradient_error_is_reported(prec, bound):
     e_or = rel_l2(plan.unpack(g16, "m"), oracle_gradient(wl, dds, ms=[wl.m(0, background=True)]))
     _report(f"gradient FULL prec={prec} vs oracle", e_or)
     assert e_or <= bound
+
+
+def test_results_do_not_depend_on_the_tile_shape_and_autotune_keeps_them():
+    wl = W.small_2d(windows=[90, 70], T_per_shot=[300.0, 220.0])
+    dds = _residuals(wl)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, plan)
+    dd = plan.pack(dds, "d")
+    outs = []
+    for tz in (8, 16, 32, 64):
+        plan.set_tiles(tz=tz)
+        g, v, d = plan.gradient(m, q, dd, v=True, d=True)
+        outs.append((g.clone(), v.clone(), d.clone()))
+    choice, ms = plan.autotune(m, q, dd, probe_steps=16)
+    g, v, d = plan.gradient(m, q, dd, v=True, d=True)
+    _sync()
+    print(f"autotuned tile rows {choice['tz']} ({ms:.3f} ms probe)", flush=True)
+    for o in outs[1:] + [(g, v, d)]:
+        assert all(torch.equal(a, b) for a, b in zip(o, outs[0]))
+
+
+def test_autotune_without_a_residual_injects_nothing():
+    """Regression: the autotuner's adjoint probe runs with no residual (dd = NULL); tiles that
+    hold receivers must then skip the injection instead of reading through the null pointer."""
+    wl = W.small_2d(windows=[90, 70], T_per_shot=[200.0, 150.0])
+    plan = make_plan(wl)
+    m, q = gpu_inputs(wl, plan)
+    choice, ms = plan.autotune(m, q, None, probe_steps=8)
+    d = plan.forward(m, q)
+    _sync()
+    assert choice["tz"] in (8, 16, 32, 64) and ms > 0
+    assert rel_l2(plan.unpack(d, "d"), oracle_forward(wl)) <= TOL

@@ -88,3 +88,22 @@ def test_full_16bit_storage_gradient_3d(prec, bound):
     err = rel_l2(g16.cpu().numpy(), g32.cpu().numpy())
     print(f"gradient 3D FULL prec={prec} vs FP32: rel-L2 {err:.3e}", flush=True)
     assert 0 < err <= bound
+
+
+def test_3d_results_do_not_depend_on_the_tile_shape_and_autotune_keeps_them():
+    wl = _small()
+    dds = _residuals(wl)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, plan)
+    dd = plan.pack(dds, "d")
+    outs = []
+    for ty, bz in ((4, 0), (8, 16), (16, 11)):
+        plan.set_tiles(ty=ty, bz=bz)
+        g, v, d = plan.gradient(m, q, dd, v=True, d=True)
+        outs.append((g.clone(), v.clone(), d.clone()))
+    choice, ms = plan.autotune(m, q, dd, probe_steps=8)
+    g, v, d = plan.gradient(m, q, dd, v=True, d=True)
+    torch.cuda.synchronize()
+    print(f"autotuned 3D tiles {choice} ({ms:.3f} ms probe)", flush=True)
+    for o in outs[1:] + [(g, v, d)]:
+        assert all(torch.equal(a, b) for a, b in zip(o, outs[0]))
