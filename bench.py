@@ -303,12 +303,14 @@ def bench_c3(args):
     kernels = kernel_table(prof, launch_points, {"forward": "none", "adjoint": "buffers"})
     names = {"forward": "fwd2d step (forward / recompute, 16 B/point)",
              "adjoint": "adj2d step (adjoint + imaging from recomputed buffers, 36 B/point)"}
-    fwd_steps = prof["forward"][0] / args.steps
+    sched = A.checkpoint_schedule(wl.shots[0].nt - 1, 16)
+    fwd_steps = int(sum(b - a for op, a, b in sched if op == 0))   # forward steps per gradient
     return base_line(args, wl, points / sec / 1e9, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "CHECKPOINT 16 FP32 slots",
                    "batched": True, "graph": False, "tiles": tiles},
         "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
+        "forward_steps_per_gradient": fwd_steps,
         "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item())})
 
 

@@ -187,7 +187,7 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
 
 /* Tile-shape autotuner (setup call, synchronous): for each candidate tile shape (2D: 8, 16,
  * 32 or 64 rows of 64 columns; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth,
- * 128 or 64 planes) times probe_steps forward steps and probe_steps adjoint steps (with
+ * 128, 64 or 32 planes) times probe_steps forward steps and probe_steps adjoint steps (with
  * imaging when the plan keeps a wavefield) on the given inputs, then keeps the fastest
  * shape for all later calls.  dd may be NULL (the adjoint probe then injects nothing).
  * Rebuilds the plan's device tables (the only allocation), overwrites the workspace and

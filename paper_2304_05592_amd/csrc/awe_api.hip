@@ -17,6 +17,7 @@
 
 #include "awe.h"
 #include "awe_internal.h"
+#include "codec.h"
 #include "schedule.h"
 
 using awe::InjEntry;
@@ -588,7 +589,7 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
       d.store = off;
       off = align256(off + (long long)d.nt * d.npts * esz);
       d.scale = off;
-      off = align256(off + (long long)d.nt * 4);
+      off = align256(off + (long long)d.nt * awe::kScaleSlots * 4);
     } else if (store->mode == AWE_STORE_CHECKPOINT) {
       d.store = off;
       off = align256(off + (long long)store->nslots * 2 * d.npts * esz);
@@ -656,7 +657,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     for (int tz : {8, 16, 32, 64}) cands.push_back({tz, P->ty, P->bz});
   } else {
     for (int ty : {4, 8, 16})
-      for (int bz : {0, 128, 64}) cands.push_back({P->tz, ty, bz});
+      for (int bz : {0, 128, 64, 32}) cands.push_back({P->tz, ty, bz});
   }
   const int probe = std::min<int>(probe_steps, P->nsteps);
   hipEvent_t e0, e1;
@@ -796,7 +797,7 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
              : P->store.prec == AWE_PREC_BF16 ? awe::kStoreBF16 : awe::kStoreFP16;
       if (kind != awe::kStoreF32)
         for (int i = 0; i < P->nshot; ++i)
-          AWE_HIP(awe::launch_fill(a.ws, P->sd[i].scale, (long long)P->sd[i].nt * 4, s));
+          AWE_HIP(awe::launch_fill(a.ws, P->sd[i].scale, (long long)P->sd[i].nt * awe::kScaleSlots * 4, s));
     }
     for (int n = 1; n <= P->nsteps; ++n)
       if ((st = step_fwd(P, a, n, kind, s)) != AWE_OK) return st;

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
   float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
   unsigned short* st16 = SK >= kStoreBF16
       ? reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts : nullptr;
-  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(scl[k - 1]) : 0.f;
+  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
   float lmax = 0.f;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
@@ -145,10 +145,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
       if (k >= 2) st16[p] = enc16(u * inv_prev, SK == kStoreBF16);
     }
   }
-  if (SK >= kStoreBF16) {
-    lmax = wave_max(lmax);
-    if (lane == 0) atomicMax(reinterpret_cast<unsigned*>(scl) + k, __float_as_uint(lmax));
-  }
+  if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
 }
 
 // ------------------------------------------------------------------------------ adjoint
@@ -176,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
   if (IMG == kImgBuffers) uj = fbuf(a.ws, S, j & 1);
   if (IMG >= kImgFullBF16) {
     uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
-    usc = reinterpret_cast<const float*>(a.ws + S.scale)[j];
+    usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
   }
   double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

@@ -45,31 +45,60 @@ struct T3 {
   static constexpr int NC = TY / 4;          // y-rows per thread
 };
 
-// Loads the halo ring of plane z (rows y0-4..y0+TY+3, columns x0-4..x0+67 minus the
-// centre) into P.
+// Halo ring of one plane: rows y0-4..y0+TY+3 x columns x0-4..x0+67 minus the 64 x TY
+// centre; element e < COUNT maps to one ring position.  Each thread fetches PER elements
+// into registers (so the loads can be issued a plane ahead) and later stores them to LDS.
 template <int TY>
-__device__ __forceinline__ void load_halo(float (*P)[T3<TY>::W], const float* __restrict__ f,
-                                          int nx, int ny, int nz, int x0, int y0, int z) {
+struct Ring {
+  static constexpr int W = T3<TY>::W;
+  static constexpr int COUNT = 8 * W + TY * 8;
+  static constexpr int PER = (COUNT + kThreads - 1) / kThreads;
+};
+
+template <int TY>
+__device__ __forceinline__ void ring_pos(int e, int* r, int* c) {
   constexpr int W = T3<TY>::W;
+  if (e < 8 * W) {
+    const int band = e / W;
+    *c = e - band * W;
+    *r = band < 4 ? band : TY + band;          // rows 0..3 and TY+4..TY+7
+  } else {
+    const int e2 = e - 8 * W;
+    const int cc = e2 & 7;
+    *r = kHalo + (e2 >> 3);                    // rows 4..TY+3
+    *c = cc < 4 ? cc : kTX + cc;               // columns 0..3 and 68..71
+  }
+}
+
+template <int TY>
+__device__ __forceinline__ void ring_fetch(float (&h)[Ring<TY>::PER], const float* __restrict__ f,
+                                           int nx, int ny, int nz, int x0, int y0, int z) {
   const bool zin = (unsigned)z < (unsigned)nz;
   const long long zb = (long long)z * ny;
-  // top and bottom bands: 4 + 4 rows of 72
-  for (int e = threadIdx.x; e < 8 * W; e += kThreads) {
-    const int band = e / W, c = e - band * W;
-    const int r = band < 4 ? band : TY + band;  // 0..3 and TY+4..TY+7
-    const int y = y0 - kHalo + r, x = x0 - kHalo + c;
+#pragma unroll
+  for (int i = 0; i < Ring<TY>::PER; ++i) {
+    const int e = threadIdx.x + i * kThreads;
     float v = 0.f;
-    if (zin && (unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * nx + x];
-    P[r][c] = v;
+    if (e < Ring<TY>::COUNT && zin) {
+      int r, c;
+      ring_pos<TY>(e, &r, &c);
+      const int y = y0 - kHalo + r, x = x0 - kHalo + c;
+      if ((unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * nx + x];
+    }
+    h[i] = v;
   }
-  // left and right bands: TY rows of 4 + 4 columns
-  for (int e = threadIdx.x; e < TY * 8; e += kThreads) {
-    const int r = e >> 3, cc = e & 7;
-    const int c = cc < 4 ? cc : kTX + cc;  // 0..3 and 68..71
-    const int y = y0 + r, x = x0 - kHalo + c;
-    float v = 0.f;
-    if (zin && y < ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * nx + x];
-    P[r + kHalo][c] = v;
+}
+
+template <int TY>
+__device__ __forceinline__ void ring_store(float (*P)[T3<TY>::W], const float (&h)[Ring<TY>::PER]) {
+#pragma unroll
+  for (int i = 0; i < Ring<TY>::PER; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < Ring<TY>::COUNT) {
+      int r, c;
+      ring_pos<TY>(e, &r, &c);
+      P[r][c] = h[i];
+    }
   }
 }
 
@@ -88,12 +117,6 @@ __device__ __forceinline__ float lap3(const float (*P)[T3<TY>::W], const float* 
   return s;
 }
 
-// One field marched along z: register queue Q[col][0..8] = planes z-4..z+4.
-template <int TY>
-struct Column {
-  float Q[T3<TY>::NC][9];
-};
-
 template <int TY>
 __device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny, int nz, int x,
                                      int y, int z) {
@@ -101,9 +124,13 @@ __device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny
 }
 
 // ------------------------------------------------------------------------------ forward
+// Software-pipelined z-march: after the barrier of plane z each thread issues the global
+// loads of plane z+1 (halo ring, next queue value, u^{k-2}, coef), updates plane z from LDS
+// buffer b and its register queue, then writes plane z+1 into buffer 1-b (every wave has
+// passed the barrier, so nobody still reads the plane z-1 it held).
 template <int TY, int SK>
 __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) {
-  constexpr int NC = T3<TY>::NC;
+  constexpr int NC = T3<TY>::NC, HP = Ring<TY>::PER;
   __shared__ float P[2][T3<TY>::H][T3<TY>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
   const TileDev T = a.t.tiles[tid];
@@ -129,31 +156,40 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
   float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
   unsigned short* st16 = SK >= kStoreBF16
       ? reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts : nullptr;
-  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(scl[k - 1]) : 0.f;
+  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
   float lmax = 0.f;
 
-  float Q[NC][9];
+  float Q[NC][9], pu2[NC], pcf[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+    pu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, x, y, T.z0);
+  }
+  {
+    float h[HP];
+    ring_fetch<TY>(h, u1, nx, ny, nz, T.x0, T.y0, T.z0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
+    ring_store<TY>(P[0], h);
   }
   for (int z = T.z0; z < zend; ++z) {
     const int b = (z - T.z0) & 1;
-    float pu2[NC], pcf[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int y = T.y0 + g * NC + c;
-      Q[c][8] = ldc<TY>(u1, nx, ny, nz, x, y, z + kHalo);
-      const bool in = x < nx && y < ny;
-      const long long p = ((long long)z * ny + y) * nx + x;
-      pu2[c] = in ? u2[p] : 0.f;
-      pcf[c] = in ? cf[p] : 0.f;
-      P[b][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
-    }
-    load_halo<TY>(P[b], u1, nx, ny, nz, T.x0, T.y0, z);
     __syncthreads();
+    const bool more = z + 1 < zend;
+    float h[HP], qn[NC], nu2[NC], ncf[NC];
+    if (more) {
+      ring_fetch<TY>(h, u1, nx, ny, nz, T.x0, T.y0, z + 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int y = T.y0 + g * NC + c;
+        qn[c] = ldc<TY>(u1, nx, ny, nz, x, y, z + 1 + kHalo);
+        nu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, z + 1);
+        ncf[c] = ldc<TY>(cf, nx, ny, nz, x, y, z + 1);
+      }
+    }
     const int dz = border_dist(z, nz, a.nbl);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -177,20 +213,27 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
           if (k >= 2) st16[p] = enc16(u * inv_prev, SK == kStoreBF16);
         }
       }
+    }
+    if (more) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
+      for (int c = 0; c < NC; ++c) {
+        P[1 - b][g * NC + c + kHalo][lane + kHalo] = Q[c][5];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
+        Q[c][8] = qn[c];
+        pu2[c] = nu2[c];
+        pcf[c] = ncf[c];
+      }
+      ring_store<TY>(P[1 - b], h);
     }
   }
-  if (SK >= kStoreBF16) {
-    lmax = wave_max(lmax);
-    if (lane == 0) atomicMax(reinterpret_cast<unsigned*>(scl) + k, __float_as_uint(lmax));
-  }
+  if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
 }
 
 // ------------------------------------------------------------------------------ adjoint
 template <int TY, int IMG>
 __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) {
-  constexpr int NC = T3<TY>::NC;
+  constexpr int NC = T3<TY>::NC, HP = Ring<TY>::PER;
   __shared__ float P[2][T3<TY>::H][T3<TY>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
   const TileDev T = a.t.tiles[tid];
@@ -208,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
   if (IMG == kImgBuffers) uj = fbuf(a.ws, S, j & 1);
   if (IMG >= kImgFullBF16) {
     uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
-    usc = reinterpret_cast<const float*>(a.ws + S.scale)[j];
+    usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
   }
   double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -219,34 +262,54 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
     a.v[S.q + j] = interp8(w1, S, S.src_i, S.src_j, S.src_k, S.src_w);
   const int dx = border_dist(x, nx, a.nbl);
 
-  float Q[NC][9];
+  // imaging inputs of one point: u^j and the accumulator (0 outside the grid)
+  auto load_img = [&](int y, int z, float* u, double* ac) {
+    const bool in = x < nx && y < ny && z < nz;
+    const long long p = ((long long)z * ny + y) * nx + x;
+    if (IMG >= kImgFullBF16) *u = in ? dec16(uj16[p], IMG == kImgFullBF16) * usc : 0.f;
+    else if (IMG) *u = in ? uj[p] : 0.f;
+    if (IMG) *ac = in ? acc[p] : 0.0;
+  };
+
+  float Q[NC][9], pw2[NC], pcf[NC], pu[NC];
+  double pacc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+    pw2[c] = ldc<TY>(w2, nx, ny, nz, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, x, y, T.z0);
+    pu[c] = 0.f;
+    pacc[c] = 0.0;
+    load_img(y, T.z0, &pu[c], &pacc[c]);
+  }
+  {
+    float h[HP];
+    ring_fetch<TY>(h, w1, nx, ny, nz, T.x0, T.y0, T.z0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
+    ring_store<TY>(P[0], h);
   }
   for (int z = T.z0; z < zend; ++z) {
     const int b = (z - T.z0) & 1;
-    float pw2[NC], pcf[NC], pu[NC];
-    double pacc[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int y = T.y0 + g * NC + c;
-      Q[c][8] = ldc<TY>(w1, nx, ny, nz, x, y, z + kHalo);
-      const bool in = x < nx && y < ny;
-      const long long p = ((long long)z * ny + y) * nx + x;
-      pw2[c] = in ? w2[p] : 0.f;
-      pcf[c] = in ? cf[p] : 0.f;
-      if (IMG) {
-        if (IMG >= kImgFullBF16) pu[c] = in ? dec16(uj16[p], IMG == kImgFullBF16) * usc : 0.f;
-        else pu[c] = in ? uj[p] : 0.f;
-        pacc[c] = in ? acc[p] : 0.0;
-      }
-      P[b][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
-    }
-    load_halo<TY>(P[b], w1, nx, ny, nz, T.x0, T.y0, z);
     __syncthreads();
+    const bool more = z + 1 < zend;
+    float h[HP], qn[NC], nw2[NC], ncf[NC], nu[NC];
+    double nacc[NC];
+    if (more) {
+      ring_fetch<TY>(h, w1, nx, ny, nz, T.x0, T.y0, z + 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int y = T.y0 + g * NC + c;
+        qn[c] = ldc<TY>(w1, nx, ny, nz, x, y, z + 1 + kHalo);
+        nw2[c] = ldc<TY>(w2, nx, ny, nz, x, y, z + 1);
+        ncf[c] = ldc<TY>(cf, nx, ny, nz, x, y, z + 1);
+        nu[c] = 0.f;
+        nacc[c] = 0.0;
+        load_img(y, z + 1, &nu[c], &nacc[c]);
+      }
+    }
     const int dz = border_dist(z, nz, a.nbl);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -262,8 +325,20 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
         w2[p] = (w + w - pw2[c]) + incr;
         if (IMG) acc[p] = pacc[c] + (double)pu[c] * (double)incr;
       }
+    }
+    if (more) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
+      for (int c = 0; c < NC; ++c) {
+        P[1 - b][g * NC + c + kHalo][lane + kHalo] = Q[c][5];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
+        Q[c][8] = qn[c];
+        pw2[c] = nw2[c];
+        pcf[c] = ncf[c];
+        pu[c] = nu[c];
+        pacc[c] = nacc[c];
+      }
+      ring_store<TY>(P[1 - b], h);
     }
   }
 }
@@ -295,7 +370,7 @@ __global__ void inj3d_kernel(StepArgs a, int ninj) {
     else
       u = dec16(reinterpret_cast<const unsigned short*>(a.ws + S.store)[(long long)j * S.npts + Pt.p],
                 a.image_src == kImgFullBF16) *
-          reinterpret_cast<const float*>(a.ws + S.scale)[j];
+          level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
     double* acc = reinterpret_cast<double*>(a.ws + S.acc);
     acc[Pt.p] += (double)u * (double)add;
   }
@@ -304,7 +379,7 @@ __global__ void inj3d_kernel(StepArgs a, int ninj) {
 // ------------------------------------------------------------------------------ Born
 template <int TY>
 __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen) {
-  constexpr int NC = T3<TY>::NC;
+  constexpr int NC = T3<TY>::NC, HP = Ring<TY>::PER;
   __shared__ float PU[2][T3<TY>::H][T3<TY>::W];
   __shared__ float PD[2][T3<TY>::H][T3<TY>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
@@ -332,36 +407,51 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
 
-  float QU[NC][9], QD[NC][9];
+  float QU[NC][9], QD[NC][9], pu2[NC], pd2[NC], pcf[NC], pdm[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < 9; ++t) {
       QU[c][t] = ldc<TY>(u1, nx, ny, nz, x, y, T.z0 - kHalo + t);
       QD[c][t] = ldc<TY>(d1, nx, ny, nz, x, y, T.z0 - kHalo + t);
     }
+    pu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, T.z0);
+    pd2[c] = ldc<TY>(d2, nx, ny, nz, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, x, y, T.z0);
+    pdm[c] = ldc<TY>(dm, nx, ny, nz, x, y, T.z0);
+  }
+  {
+    float hu[HP], hd[HP];
+    ring_fetch<TY>(hu, u1, nx, ny, nz, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(hd, d1, nx, ny, nz, T.x0, T.y0, T.z0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      PU[0][g * NC + c + kHalo][lane + kHalo] = QU[c][4];
+      PD[0][g * NC + c + kHalo][lane + kHalo] = QD[c][4];
+    }
+    ring_store<TY>(PU[0], hu);
+    ring_store<TY>(PD[0], hd);
   }
   for (int z = T.z0; z < zend; ++z) {
     const int b = (z - T.z0) & 1;
-    float pu2[NC], pd2[NC], pcf[NC], pdm[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int y = T.y0 + g * NC + c;
-      QU[c][8] = ldc<TY>(u1, nx, ny, nz, x, y, z + kHalo);
-      QD[c][8] = ldc<TY>(d1, nx, ny, nz, x, y, z + kHalo);
-      const bool in = x < nx && y < ny;
-      const long long p = ((long long)z * ny + y) * nx + x;
-      pu2[c] = in ? u2[p] : 0.f;
-      pd2[c] = in ? d2[p] : 0.f;
-      pcf[c] = in ? cf[p] : 0.f;
-      pdm[c] = in ? dm[p] : 0.f;
-      PU[b][g * NC + c + kHalo][lane + kHalo] = QU[c][4];
-      PD[b][g * NC + c + kHalo][lane + kHalo] = QD[c][4];
-    }
-    load_halo<TY>(PU[b], u1, nx, ny, nz, T.x0, T.y0, z);
-    load_halo<TY>(PD[b], d1, nx, ny, nz, T.x0, T.y0, z);
     __syncthreads();
+    const bool more = z + 1 < zend;
+    float hu[HP], hd[HP], qun[NC], qdn[NC], nu2[NC], nd2[NC], ncf[NC], ndm[NC];
+    if (more) {
+      ring_fetch<TY>(hu, u1, nx, ny, nz, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(hd, d1, nx, ny, nz, T.x0, T.y0, z + 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int y = T.y0 + g * NC + c;
+        qun[c] = ldc<TY>(u1, nx, ny, nz, x, y, z + 1 + kHalo);
+        qdn[c] = ldc<TY>(d1, nx, ny, nz, x, y, z + 1 + kHalo);
+        nu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, z + 1);
+        nd2[c] = ldc<TY>(d2, nx, ny, nz, x, y, z + 1);
+        ncf[c] = ldc<TY>(cf, nx, ny, nz, x, y, z + 1);
+        ndm[c] = ldc<TY>(dm, nx, ny, nz, x, y, z + 1);
+      }
+    }
     const int dz = border_dist(z, nz, a.nbl);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -383,11 +473,26 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
         const float incd = pcf[c] * (lapd - eta * (du - pd2[c]));
         d2[p] = (du + du - pd2[c]) + incd;
       }
+    }
+    if (more) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        QU[c][t] = QU[c][t + 1];
-        QD[c][t] = QD[c][t + 1];
+      for (int c = 0; c < NC; ++c) {
+        PU[1 - b][g * NC + c + kHalo][lane + kHalo] = QU[c][5];
+        PD[1 - b][g * NC + c + kHalo][lane + kHalo] = QD[c][5];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          QU[c][t] = QU[c][t + 1];
+          QD[c][t] = QD[c][t + 1];
+        }
+        QU[c][8] = qun[c];
+        QD[c][8] = qdn[c];
+        pu2[c] = nu2[c];
+        pd2[c] = nd2[c];
+        pcf[c] = ncf[c];
+        pdm[c] = ndm[c];
       }
+      ring_store<TY>(PU[1 - b], hu);
+      ring_store<TY>(PD[1 - b], hd);
     }
   }
 }

@@ -129,7 +129,7 @@ __global__ void store_last_kernel(StepArgs a) {
   const int k = S.nt - 1;
   if (k < 1) return;
   const float* f = fbuf(a.ws, S, k & 1);
-  const float inv = inv_scale(reinterpret_cast<const float*>(a.ws + S.scale)[k]);
+  const float inv = inv_scale(level_scale(reinterpret_cast<const float*>(a.ws + S.scale), k));
   unsigned short* st = reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)k * S.npts;
   const int bf = a.store_prec == kBF16;
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < S.npts;
