@@ -40,6 +40,10 @@ BYTES = {
     ("adjoint", "fp32"): 36,   # + stored u^j (4) + accumulator read and write (16)
     ("adjoint", "16bit"): 34,  # + 16-bit stored u^j (2) + accumulator (16)
     ("adjoint", "buffers"): 36,  # u^j from the recomputed forward buffer (4) + accumulator
+    # two time levels per launch (2D): inputs read once, both new levels written
+    ("forward2", "none"): 20,   # read u^{k-1}, u^{k-2}, coef; write u^k, u^{k+1}
+    ("forward2", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
+    ("adjoint2", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
 }
 
 
@@ -54,10 +58,50 @@ def parse():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=120, help="time steps of the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=1000, help="time steps of the oracle sample")
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "fp32"],
                     help="stored-wavefield precision of the 3D workload")
-    return ap.parse_args()
+    ap.add_argument("--tiles", default=None,
+                    help="fixed launch shape instead of the autotuner, e.g. tz=32 or tz=16,levels_per_launch=2")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the plain device-to-device copy probe (PMC calibration)")
+    args = ap.parse_args()
+    if args.tiles:
+        args.tiles = {k: int(v) for k, v in (kv.split("=") for kv in args.tiles.split(","))}
+    return args
+
+
+def copy_probe(nbytes=1 << 30, reps=5):
+    """Bandwidth of a plain device-to-device copy (torch) of nbytes: read + write bytes / time."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    sync()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_copied": nbytes, "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+
+
+def traffic_record(kernel_file, kernel_name, launch_points):
+    """HBM bytes per launch measured by rocprofv3 PMC counters (profiles/traffic_*.json), or
+    None when the record is missing or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_c2_grad.json")
+    src = os.path.join(ROOT, "paper_2304_05592_amd", "csrc", kernel_file)
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    if rec.get("kernel") != kernel_name or rec.get("launch_points") != launch_points:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def sync():
@@ -80,16 +124,19 @@ def points_of(wl, shots):
     return per_step, per_launch
 
 
-def kernel_table(prof, launch_points, kinds):
-    """Per kernel class: launches, average event time and achieved algorithmic GB/s."""
+def kernel_table(prof, launch_points, kinds, fused=False):
+    """Per kernel class: launches, average event time and achieved algorithmic GB/s.  With
+    two levels per launch the bytes are those of a two-level launch."""
     out = {}
     for name, kind in kinds.items():
         cnt, ms = prof[name]
         if cnt == 0:
             continue
         avg_ms = ms / cnt
-        b = BYTES[(name, kind)] * launch_points
-        out[name] = {"launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 3), "bytes_per_point": BYTES[(name, kind)],
+        key = (name + "2", kind) if fused and (name + "2", kind) in BYTES else (name, kind)
+        b = BYTES[key] * launch_points
+        out[name] = {"launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 3), "bytes_per_point": BYTES[key],
+                     "levels_per_launch": 2 if key[0].endswith("2") else 1,
                      "bytes_per_launch": b, "achieved_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1)}
     return out
 
@@ -106,7 +153,7 @@ def roofline_of(kernels, names):
 class GradientRunner:
     """Forward (kept wavefield) + residual + reverse sweep on resident inputs."""
 
-    def __init__(self, wl, shots, storage, autotune=True):
+    def __init__(self, wl, shots, storage, autotune=True, tiles=None):
         import torch
         import paper_2304_05592_amd as A
         self.A, self.torch = A, torch
@@ -123,7 +170,11 @@ class GradientRunner:
         self.g = torch.empty(p.layout.m_size, dtype=torch.float64, device="cuda")
         self.points, self.launch_points = points_of(wl, self.shots)
         self.tiles = None
-        if autotune:
+        if tiles:
+            p.set_tiles(tiles.get("tz", 32), tiles.get("ty", 8), tiles.get("bz", 0))
+            p.set_fusion(tiles.get("levels_per_launch", 1) == 2)
+            self.tiles = dict(tiles)
+        elif autotune:
             self.tiles, _ = p.autotune(self.m0, self.q, self.d_obs, probe_steps=32, ws=self.ws)
         self.graph = None
         sync()
@@ -231,7 +282,8 @@ def bench_c2(args):
     import paper_2304_05592_amd as A
     import workloads as W
     wl = W.make_config("c2_grad")
-    run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL), autotune=not args.no_autotune)
+    run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL), autotune=not args.no_autotune,
+                         tiles=args.tiles)
     # timed region 1: eager launches with HIP events around every launch (kernel durations)
     eager_sec, prof = run.run(max(1, min(args.steps, 3)), args.warmup, use_graph=False, profile=True)
     timing = ("HIP events around every launch of an eager timed region of the same step, on the "
@@ -244,11 +296,19 @@ def bench_c2(args):
     else:
         sec = eager_sec
     value = run.points / sec / 1e9
-    kernels = kernel_table(prof, run.launch_points, {"forward": "fp32", "adjoint": "fp32"})
-    names = {"forward": "fwd2d step (forward + stored FP32 copy, 20 B/point)",
-             "adjoint": "adj2d step (adjoint + imaging from stored FP32, 36 B/point)"}
+    fused = bool(run.tiles) and run.tiles.get("levels_per_launch", 1) == 2
+    kernels = kernel_table(prof, run.launch_points, {"forward": "fp32", "adjoint": "fp32"}, fused=fused)
+    names = ({"forward": "fwd2d2 (two forward levels + stored FP32 copies, 28 B/point per launch)",
+              "adjoint": "adj2d2 (two adjoint levels + imaging from stored FP32, 44 B/point per launch)"}
+             if fused else
+             {"forward": "fwd2d step (forward + stored FP32 copy, 20 B/point)",
+              "adjoint": "adj2d step (adjoint + imaging from stored FP32, 36 B/point)"})
     roof = roofline_of(kernels, names)
-    path_bytes = (BYTES[("forward", "fp32")] + BYTES[("adjoint", "fp32")]) * run.points
+    dom_name = (f"adj2d2_kernel<{run.tiles['tz']}, 1>" if fused else f"adj2d_kernel<{run.tiles['tz']}, 1>") \
+        if run.tiles else None
+    roof["traffic"] = traffic_record("kernels2d.hip", dom_name, run.launch_points)
+    path_bytes = ((BYTES[("forward2", "fp32")] + BYTES[("adjoint2", "fp32")]) * run.points // 2 if fused
+                  else (BYTES[("forward", "fp32")] + BYTES[("adjoint", "fp32")]) * run.points)
     loss = float(run.loss.item())
     tiles, points = run.tiles, run.points
     run.release()
@@ -260,6 +320,7 @@ def bench_c2(args):
                   "form": "one shot, one launch per time step, no graph"}
         r1.release()
     cpu = None if args.no_cpu_baseline else cpu_baseline("c2_grad", wl, args.cpu_steps)
+    copy = copy_probe()
     return base_line(args, wl, value, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "FULL FP32",
@@ -267,7 +328,7 @@ def bench_c2(args):
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels, "kernel_timing": timing,
         "path_hbm_fraction": round(path_bytes / sec / 1e9 / PEAK_HBM_GBS, 4),
         "eager": {"value": round(points / eager_sec / 1e9, 3), "ms_per_step": round(eager_sec * 1e3, 3)},
-        "single_shot": single, "loss": loss})
+        "single_shot": single, "copy_probe": copy, "loss": loss})
 
 
 def bench_c3(args):
@@ -369,7 +430,9 @@ def bench_c4(args):
     # launches cover different numbers of active shots: use the pass's summed kernel time
     cnt, ms = prof["forward"]
     est_kernel_s = ms * 1e-3
-    ach = BYTES[("forward", "none")] * points / est_kernel_s / 1e9 if cnt else None
+    fused = bool(tiles) and tiles.get("levels_per_launch", 1) == 2
+    per_level = BYTES[("forward2", "none")] / 2 if fused else BYTES[("forward", "none")]
+    ach = per_level * points / est_kernel_s / 1e9 if cnt else None
     return base_line(args, wl, points / sec / 1e9, sec, {
         "metric": "Gpts/s forward, uneven batching (64 windows) batched vs sequential single-shot",
         "config": {"workload": f"{wl.name}: {wl.description}", "shots": wl.nshot,
@@ -378,7 +441,8 @@ def bench_c4(args):
         "roofline": {"bound": "hbm", "achieved": None if ach is None else round(ach, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": None if ach is None else round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "fwd2d step (16 B/point); summed event time of one eager pass"},
+                     "kernel": ("fwd2d2 (two levels per launch, 20 B/point per launch)" if fused else
+                                "fwd2d step (16 B/point)") + "; summed event time of one eager pass"},
         "sequential_single_shot": {"value": round(points / seq / 1e9, 3), "seconds": round(seq, 4)},
         "cpu_baseline": None})
 
@@ -389,7 +453,8 @@ def bench_c5(args):
     import workloads as W
     wl = W.make_config("c5_3d")
     prec = {"bf16": A.PREC_BF16, "fp16": A.PREC_FP16, "fp32": A.PREC_FP32}[args.prec]
-    run = GradientRunner(wl, [0], A.Storage(A.STORE_FULL, 0, prec), autotune=not args.no_autotune)
+    run = GradientRunner(wl, [0], A.Storage(A.STORE_FULL, 0, prec), autotune=not args.no_autotune,
+                         tiles=args.tiles)
     sec, prof = run.run(args.steps, args.warmup, use_graph=False, profile=True)
     kind = "fp32" if prec == A.PREC_FP32 else "16bit"
     kernels = kernel_table(prof, run.launch_points, {"forward": kind, "adjoint": kind})
@@ -408,10 +473,13 @@ def bench_c5(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this path is built and measured on a single MI355X; "
-              "multi-GPU runs (shots sharded over GPUs, FP64 gradient all-reduce) are not part "
-              "of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X; sharding "
+              "shots over several GPUs (with an FP64 all-reduce of the gradient) is not "
+              "implemented", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        print(json.dumps({"copy_probe": copy_probe()}), flush=True)
+        return
     fn = {"c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4, "c5_3d": bench_c5}[args.config]
     print(json.dumps(fn(args)), flush=True)
 

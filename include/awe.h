@@ -59,7 +59,7 @@ extern "C" {
 typedef enum {
   AWE_OK = 0,
   AWE_ERR_INVALID_ARG = 1,  /* null pointer, bad size, bad enum value */
-  AWE_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+  AWE_ERR_UNSUPPORTED = 2,  /* valid request that the library does not implement */
   AWE_ERR_CFL = 3,          /* vmax dt / h above the leapfrog stability limit */
   AWE_ERR_GEOMETRY = 4,     /* source or receiver outside the computational grid */
   AWE_ERR_WORKSPACE = 5,    /* workspace null or smaller than awe_plan_workspace_size */
@@ -185,22 +185,30 @@ awe_status awe_dot_f64d(const double* a, const double* b, int64_t n, double* out
 awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions,
                                    int64_t cap, int64_t* count);
 
-/* Tile-shape autotuner (setup call, synchronous): for each candidate tile shape (2D: 8, 16,
- * 32 or 64 rows of 64 columns; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth,
- * 128, 64 or 32 planes) times probe_steps forward steps and probe_steps adjoint steps (with
- * imaging when the plan keeps a wavefield) on the given inputs, then keeps the fastest
- * shape for all later calls.  dd may be NULL (the adjoint probe then injects nothing).
- * Rebuilds the plan's device tables (the only allocation), overwrites the workspace and
- * drops any kept forward.  chosen (may be NULL) receives {tz, ty, bz} of the winner and
- * best_ms (may be NULL) its probe time. */
+/* Tile-shape autotuner (setup call, synchronous): for each candidate (2D: 8, 16, 32 or 64
+ * rows of 64 columns, and - where the storage mode allows it - 8, 16 or 32 rows with two
+ * time levels per launch; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth, 128,
+ * 64 or 32 planes) times probe_steps forward and adjoint levels (with imaging when the plan
+ * keeps a wavefield) on the given inputs, then keeps the fastest for all later calls.  dd
+ * may be NULL (the adjoint probe then injects nothing).  Rebuilds the plan's device tables
+ * (the only allocation), overwrites the workspace and drops any kept forward.  chosen (may
+ * be NULL) receives {tz, ty, bz, levels per launch} of the winner and best_ms (may be
+ * NULL) its probe time. */
 awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, const float* dd,
                              int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
-                             int32_t chosen[3], double* best_ms);
+                             int32_t chosen[4], double* best_ms);
 
 /* Set the tile shape explicitly (tz: 8, 16, 32 or 64 rows in 2D; ty: 4, 8 or 16 rows and bz:
  * z-block length, 0 = full depth, in 3D).  Results do not depend on the tile shape (every
  * point's arithmetic and every sum's order are fixed).  Rebuilds the device tables. */
 awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz);
+
+/* 2D only: advance two time levels per launch (two_steps = 1) or one (the default).  The
+ * two-level kernels serve forward solves without storage or with FULL FP32 storage and
+ * reverse sweeps from FULL FP32 storage or without imaging; other modes always use one
+ * level per launch.  Results are bitwise identical either way.  Two levels per launch
+ * need tiles of at most 32 rows (set to 32 when larger). */
+awe_status awe_plan_set_fusion(awe_plan* plan, int32_t two_steps);
 
 /* Kernel timing (measurement aid).  After awe_profile_enable, every stride-th time-step
  * launch of the compute calls on this plan is bracketed by a pair of HIP events recorded on

@@ -25,7 +25,7 @@ PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "awe_forward",
            "awe_backward", "awe_gradient", "awe_adjoint", "awe_born", "awe_reduce_workspace_size",
            "awe_residual", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
-           "awe_plan_autotune", "awe_plan_set_tiles", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
+           "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
            "awe_status_string", "awe_last_error", "awe_version"]
 
 
@@ -86,6 +86,7 @@ def lib():
     L.awe_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, sz, vp,
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     L.awe_plan_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.awe_plan_set_fusion.argtypes = [vp, ctypes.c_int32]
     L.awe_profile_enable.argtypes = [vp, i64, ctypes.c_int32]
     L.awe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.awe_profile_disable.argtypes = [vp]
@@ -95,7 +96,7 @@ def lib():
     L.awe_version.restype = ctypes.c_int
     for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
                  "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_dot_f64",
-                 "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles",
+                 "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion",
                  "awe_profile_enable",
                  "awe_profile_read", "awe_profile_disable"):
         getattr(L, name).restype = ctypes.c_int
@@ -274,14 +275,18 @@ class Plan:
         """Time each candidate tile shape on these inputs and keep the fastest.
         Returns ({'tz', 'ty', 'bz'}, probe ms)."""
         ws = self.workspace(m.device) if ws is None else ws
-        ch = (ctypes.c_int32 * 3)()
+        ch = (ctypes.c_int32 * 4)()
         ms = ctypes.c_double(0.0)
         check(lib().awe_plan_autotune(self._h, _ptr(m), _ptr(q), _ptr(dd), int(probe_steps), _ptr(ws),
                                       self.ws_bytes, _stream_ptr(stream), ch, ctypes.byref(ms)))
-        return {"tz": ch[0], "ty": ch[1], "bz": ch[2]}, ms.value
+        return {"tz": ch[0], "ty": ch[1], "bz": ch[2], "levels_per_launch": ch[3]}, ms.value
 
     def set_tiles(self, tz: int = 32, ty: int = 8, bz: int = 0):
         check(lib().awe_plan_set_tiles(self._h, int(tz), int(ty), int(bz)))
+
+    def set_fusion(self, two_steps: bool):
+        """2D: two time levels per launch or one (default); results are bitwise identical."""
+        check(lib().awe_plan_set_fusion(self._h, int(bool(two_steps))))
 
     # ---------------------------------------------------------------- kernel timing
     def profile_enable(self, max_launches: int, stride: int = 1):

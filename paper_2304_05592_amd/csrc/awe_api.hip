@@ -26,6 +26,7 @@ using awe::RecDev;
 using awe::ShotDev;
 using awe::TileDev;
 using awe::WinDev;
+using awe::kHalo;
 
 namespace {
 
@@ -59,6 +60,7 @@ struct awe_plan {
   awe_storage store{};
   int nshot = 0, max_nt = 0, nsteps = 0;
   int tz = 32;            // 2D tile rows
+  int fuse2 = 0;          // 2D: advance two time levels per launch where the storage allows
   int ty = 8, bz = 0;     // 3D tile rows in y and z-block length
   std::vector<awe_shot> shots;
   std::vector<double> rec_pos;    // copy of the problem's receiver rows
@@ -67,6 +69,7 @@ struct awe_plan {
   std::vector<int> active;        // active[n]: tiles of the shots with off < n
   std::vector<RecDev> recs;
   std::vector<InjPoint> inj_pts;
+  std::vector<InjPoint> ext_pts;
   std::vector<InjEntry> inj_ent;
   std::vector<WinDev> wins;
   std::vector<int> win_shots;
@@ -266,6 +269,39 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
     P->inj_pts.push_back(ip);
     i = j;
   }
+  // 2D: every touched point is also listed for each tile whose 4-cell extended region holds
+  // it (the two-step adjoint injects on the extended region); same CSR entries
+  P->ext_pts.clear();
+  if (nd == 2) {
+    struct Ext { int tile; long long p; InjPoint ip; };
+    std::vector<Ext> ex;
+    for (const InjPoint& ip : P->inj_pts) {
+      const awe_shot& sh = P->shots[ip.shot];
+      const int i = (int)(ip.p % sh.nx), k = (int)(ip.p / sh.nx);
+      const int TZ = P->tz;
+      for (int kz = std::max(0, (k - TZ - kHalo) / TZ - 1); kz <= (k + kHalo) / TZ; ++kz) {
+        for (int kx = std::max(0, (i - awe::kTX - kHalo) / awe::kTX - 1); kx <= (i + kHalo) / awe::kTX; ++kx) {
+          if (kz >= ntz[ip.shot] || kx >= ntx[ip.shot]) continue;
+          const int x0 = kx * awe::kTX, z0 = kz * TZ;
+          const int lx = i - (x0 - kHalo), lz = k - (z0 - kHalo);
+          if (lx < 0 || lx >= awe::kTX + 2 * kHalo || lz < 0 || lz >= TZ + 2 * kHalo) continue;
+          InjPoint e = ip;
+          e.lx = lx;
+          e.lz = lz;
+          ex.push_back({first_tile[ip.shot] + kz * ntx[ip.shot] + kx, ip.p, e});
+        }
+      }
+    }
+    std::stable_sort(ex.begin(), ex.end(), [](const Ext& a, const Ext& b) {
+      return a.tile != b.tile ? a.tile < b.tile : a.p < b.p;
+    });
+    for (size_t q = 0; q < ex.size(); ++q) {
+      TileDev& T = P->tiles[ex[q].tile];
+      if (T.ext_count == 0) T.ext_begin = (int)P->ext_pts.size();
+      T.ext_count++;
+      P->ext_pts.push_back(ex[q].ip);
+    }
+  }
   return AWE_OK;
 }
 
@@ -275,7 +311,8 @@ awe_status upload_tables(awe_plan* P) {
   const long long o_t = o_sd + bytes(P->sd.size(), sizeof(ShotDev));
   const long long o_r = o_t + bytes(P->tiles.size(), sizeof(TileDev));
   const long long o_ip = o_r + bytes(P->recs.size(), sizeof(RecDev));
-  const long long o_ie = o_ip + bytes(P->inj_pts.size(), sizeof(InjPoint));
+  const long long o_xp = o_ip + bytes(P->inj_pts.size(), sizeof(InjPoint));
+  const long long o_ie = o_xp + bytes(P->ext_pts.size(), sizeof(InjPoint));
   const long long o_w = o_ie + bytes(P->inj_ent.size(), sizeof(InjEntry));
   const long long o_ws = o_w + bytes(P->wins.size(), sizeof(WinDev));
   const long long total = o_ws + bytes(P->win_shots.size(), sizeof(int)) + 256;
@@ -285,6 +322,7 @@ awe_status upload_tables(awe_plan* P) {
   put(o_t, P->tiles.data(), P->tiles.size() * sizeof(TileDev));
   put(o_r, P->recs.data(), P->recs.size() * sizeof(RecDev));
   put(o_ip, P->inj_pts.data(), P->inj_pts.size() * sizeof(InjPoint));
+  put(o_xp, P->ext_pts.data(), P->ext_pts.size() * sizeof(InjPoint));
   put(o_ie, P->inj_ent.data(), P->inj_ent.size() * sizeof(InjEntry));
   put(o_w, P->wins.data(), P->wins.size() * sizeof(WinDev));
   put(o_ws, P->win_shots.data(), P->win_shots.size() * sizeof(int));
@@ -299,6 +337,7 @@ awe_status upload_tables(awe_plan* P) {
   P->tab.tiles = reinterpret_cast<const TileDev*>(b + o_t);
   P->tab.recs = reinterpret_cast<const RecDev*>(b + o_r);
   P->tab.inj_pts = reinterpret_cast<const InjPoint*>(b + o_ip);
+  P->tab.ext_pts = reinterpret_cast<const InjPoint*>(b + o_xp);
   P->tab.inj_ent = reinterpret_cast<const InjEntry*>(b + o_ie);
   P->tab.wins = reinterpret_cast<const WinDev*>(b + o_w);
   P->tab.win_shots = reinterpret_cast<const int*>(b + o_ws);
@@ -337,8 +376,8 @@ awe_status prepare(awe_plan* P, const float* m, void* ws, bool zero_fwd, bool ze
   }
   for (int i = 0; i < P->nshot; ++i) {
     const ShotDev& d = P->sd[i];
-    if (zero_fwd) AWE_HIP(awe::launch_fill(w, d.fld, 2 * d.npts * 4, s));
-    if (zero_adj) AWE_HIP(awe::launch_fill(w, d.fld + 2 * d.npts * 4, 2 * d.npts * 4, s));
+    if (zero_fwd) AWE_HIP(awe::launch_fill(w, d.fld, 4 * d.npts * 4, s));
+    if (zero_adj) AWE_HIP(awe::launch_fill(w, d.fld + 4 * d.npts * 4, 4 * d.npts * 4, s));
   }
   return AWE_OK;
 }
@@ -385,6 +424,57 @@ awe_status step_adj(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
   return AWE_OK;
 }
 
+// Two levels per launch (2D): forward levels n, n+1; adjoint levels n, n-1.
+awe_status step_fwd2(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
+  a.step = n;
+  a.ntiles = P->active[n + 1];
+  ProfScope ps(P, 0, s);
+  AWE_HIP(awe::launch_fwd2d2(a, P->tz, store, s));
+  return AWE_OK;
+}
+
+awe_status step_adj2(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
+  a.step = n;
+  a.ntiles = P->active[n];
+  ProfScope ps(P, 1, s);
+  AWE_HIP(awe::launch_adj2d2(a, P->tz, s));
+  return AWE_OK;
+}
+
+bool fused_ok(const awe_plan* P) { return P->ndim == 2 && P->fuse2 && P->tz <= 32; }
+
+// Forward levels 1..nsteps: one single step first when the count is odd, then pairs.
+awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s) {
+  awe_status st;
+  const bool fuse = fused_ok(P) && (store == awe::kStoreNone || store == awe::kStoreF32);
+  int n = 1;
+  if (fuse && (P->nsteps & 1)) {
+    if ((st = step_fwd(P, a, 1, store, s)) != AWE_OK) return st;
+    n = 2;
+  }
+  for (; n <= P->nsteps; n += fuse ? 2 : 1) {
+    st = fuse ? step_fwd2(P, a, n, store, s) : step_fwd(P, a, n, store, s);
+    if (st != AWE_OK) return st;
+  }
+  return AWE_OK;
+}
+
+// Adjoint levels nsteps..1 (same pairing, from the top).
+awe_status adjoint_loop(awe_plan* P, awe::StepArgs& a, hipStream_t s) {
+  awe_status st;
+  const bool fuse = fused_ok(P) && (a.image_src == awe::kImgNone || a.image_src == awe::kImgFull32);
+  int n = P->nsteps;
+  if (fuse && (P->nsteps & 1)) {
+    if ((st = step_adj(P, a, n, s)) != AWE_OK) return st;
+    n -= 1;
+  }
+  for (; n >= 1; n -= fuse ? 2 : 1) {
+    st = fuse ? step_adj2(P, a, n, s) : step_adj(P, a, n, s);
+    if (st != AWE_OK) return st;
+  }
+  return AWE_OK;
+}
+
 awe_status run_slot(awe_plan* P, awe::StepArgs& a, int slot, int state, int dir, hipStream_t s) {
   if (dir == 0 && P->store.prec != AWE_PREC_FP32) {
     for (int i = 0; i < P->nshot; ++i)
@@ -416,7 +506,7 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
       case awe::kRestore:
         if (x < 0) {
           for (int k = 0; k < P->nshot; ++k)
-            AWE_HIP(awe::launch_fill(fa.ws, P->sd[k].fld, 2 * P->sd[k].npts * 4, s));
+            AWE_HIP(awe::launch_fill(fa.ws, P->sd[k].fld, 4 * P->sd[k].npts * 4, s));
         } else {
           awe_status st = run_slot(P, fa, x, y, 1, s);
           if (st != AWE_OK) return st;
@@ -569,7 +659,7 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     d.q = sh.q_offset;
     d.d = sh.d_offset;
     d.fld = off;
-    off = align256(off + 4 * d.npts * 4);
+    off = align256(off + (long long)awe::kFieldBufs * d.npts * 4);
   }
   P->fields_bytes = off - P->fields_off;
   P->acc_off = off;
@@ -651,13 +741,17 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   if (!m || !q || probe_steps < 1) return fail(AWE_ERR_INVALID_ARG, "autotune needs m, q and probe_steps >= 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   P->kept_ws = nullptr;
-  struct Cand { int tz, ty, bz; };
+  struct Cand { int tz, ty, bz, fuse; };
   std::vector<Cand> cands;
   if (P->ndim == 2) {
-    for (int tz : {8, 16, 32, 64}) cands.push_back({tz, P->ty, P->bz});
+    const bool fusable = P->store.mode == AWE_STORE_NONE ||
+                         (P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32);
+    for (int tz : {8, 16, 32, 64}) cands.push_back({tz, P->ty, P->bz, 0});
+    if (fusable)
+      for (int tz : {8, 16, 32}) cands.push_back({tz, P->ty, P->bz, 1});
   } else {
     for (int ty : {4, 8, 16})
-      for (int bz : {0, 128, 64, 32}) cands.push_back({P->tz, ty, bz});
+      for (int bz : {0, 128, 64, 32}) cands.push_back({P->tz, ty, bz, 0});
   }
   const int probe = std::min<int>(probe_steps, P->nsteps);
   hipEvent_t e0, e1;
@@ -669,6 +763,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     P->tz = c.tz;
     P->ty = c.ty;
     P->bz = c.bz;
+    P->fuse2 = c.fuse;
     if ((st = build_tables(P, P->rec_pos.data())) != AWE_OK) return st;
     if ((st = upload_tables(P)) != AWE_OK) return st;
     if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
@@ -679,14 +774,22 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     fa.q = q;
     awe::StepArgs aa = base_args(P, ws);
     aa.dd = dd;
-    aa.image_src = P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
+    const bool full32 = P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32;
+    const int fkind = full32 ? awe::kStoreF32 : awe::kStoreNone;
+    aa.image_src = full32 ? awe::kImgFull32
+                   : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
     const size_t saved = P->prof_ev.size();  // keep the probe out of kernel timing
     std::vector<hipEvent_t> keep_ev;
     keep_ev.swap(P->prof_ev);
     AWE_HIP(hipEventRecord(e0, s));
-    for (int n = 1; n <= probe; ++n)
-      if ((st = step_fwd(P, fa, n, awe::kStoreNone, s)) != AWE_OK) return st;
-    for (int n = P->nsteps; n > P->nsteps - probe; --n) {
+    const bool fuse = fused_ok(P);
+    for (int n = 1; n <= probe; n += fuse ? 2 : 1)
+      if ((st = fuse ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, fkind, s)) != AWE_OK) return st;
+    for (int n = P->nsteps; n > P->nsteps - probe && n >= 2; n -= fuse ? 2 : 1) {
+      if (fuse && aa.image_src != awe::kImgBuffers) {
+        if ((st = step_adj2(P, aa, n, s)) != AWE_OK) return st;
+        continue;
+      }
       aa.step = n;
       aa.ntiles = P->active[n];
       if (P->ndim == 2) AWE_HIP(awe::launch_adj2d(aa, P->tz, s));
@@ -708,12 +811,14 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   P->tz = win.tz;
   P->ty = win.ty;
   P->bz = win.bz;
+  P->fuse2 = win.fuse;
   if ((st = build_tables(P, P->rec_pos.data())) != AWE_OK) return st;
   if ((st = upload_tables(P)) != AWE_OK) return st;
   if (chosen) {
     chosen[0] = P->tz;
     chosen[1] = P->ty;
     chosen[2] = P->bz;
+    chosen[3] = P->fuse2 ? 2 : 1;
   }
   if (best_ms) *best_ms = best;
   return AWE_OK;
@@ -731,6 +836,13 @@ awe_status awe_plan_set_tiles(awe_plan* P, int32_t tz, int32_t ty, int32_t bz) {
   awe_status st = build_tables(P, P->rec_pos.data());
   if (st != AWE_OK) return st;
   return upload_tables(P);
+}
+
+awe_status awe_plan_set_fusion(awe_plan* P, int32_t two_steps) {
+  if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  P->fuse2 = two_steps ? 1 : 0;
+  if (P->fuse2 && P->tz > 32) return awe_plan_set_tiles(P, 32, P->ty, P->bz);
+  return AWE_OK;
 }
 
 awe_status awe_profile_enable(awe_plan* P, int64_t max_launches, int32_t stride) {
@@ -799,8 +911,7 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
         for (int i = 0; i < P->nshot; ++i)
           AWE_HIP(awe::launch_fill(a.ws, P->sd[i].scale, (long long)P->sd[i].nt * awe::kScaleSlots * 4, s));
     }
-    for (int n = 1; n <= P->nsteps; ++n)
-      if ((st = step_fwd(P, a, n, kind, s)) != AWE_OK) return st;
+    if ((st = forward_loop(P, a, kind, s)) != AWE_OK) return st;
     if (kind == awe::kStoreBF16 || kind == awe::kStoreFP16)
       AWE_HIP(awe::launch_store_last(a, P->nshot, P->max_win_npts, s));
   }
@@ -821,7 +932,7 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
   unsigned char* w = static_cast<unsigned char*>(ws);
   for (int i = 0; i < P->nshot; ++i) {
     const ShotDev& d = P->sd[i];
-    AWE_HIP(awe::launch_fill(w, d.fld + 2 * d.npts * 4, 2 * d.npts * 4, s));
+    AWE_HIP(awe::launch_fill(w, d.fld + 4 * d.npts * 4, 4 * d.npts * 4, s));
   }
   if (g)
     for (int i = 0; i < P->nshot; ++i) AWE_HIP(awe::launch_fill(w, P->sd[i].acc, P->sd[i].npts * 8, s));
@@ -834,8 +945,7 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
     aa.image_src = !g ? awe::kImgNone
                    : P->store.prec == AWE_PREC_FP32 ? awe::kImgFull32
                    : P->store.prec == AWE_PREC_BF16 ? awe::kImgFullBF16 : awe::kImgFullFP16;
-    for (int n = P->nsteps; n >= 1; --n)
-      if ((st = step_adj(P, aa, n, s)) != AWE_OK) return st;
+    if ((st = adjoint_loop(P, aa, s)) != AWE_OK) return st;
   } else {
     aa.image_src = g ? awe::kImgBuffers : awe::kImgNone;
     if ((st = run_actions(P, fa, aa, P->sched_first_reverse, P->sched.size() / 3, s)) != AWE_OK) return st;
@@ -868,9 +978,8 @@ awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, v
   awe::StepArgs a = base_args(P, ws);
   a.dd = dd;
   a.v = v;
-  a.image_src = 0;
-  for (int n = P->nsteps; n >= 1; --n)
-    if ((st = step_adj(P, a, n, s)) != AWE_OK) return st;
+  a.image_src = awe::kImgNone;
+  if ((st = adjoint_loop(P, a, s)) != AWE_OK) return st;
   AWE_HIP(awe::launch_src_last(a, P->nshot, s));
   return AWE_OK;
 }
@@ -894,7 +1003,7 @@ awe_status awe_born(awe_plan* P, const float* m, const float* q, const float* dm
     if (P->ndim == 2) AWE_HIP(awe::launch_born2d(a, P->tz, s));
     else AWE_HIP(awe::launch_born3d(a, P->ty, P->bz, s));
   }
-  AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 2, s));
+  AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 1, s));
   return AWE_OK;
 }
 

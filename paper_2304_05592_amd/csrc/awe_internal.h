@@ -15,6 +15,13 @@ constexpr int kThreads = 256;   // 4 wave64 per workgroup
 constexpr int kTX = 64;         // 2D tile width: one wavefront spans the tile row
 constexpr int kHalo = 4;        // stencil radius (8th order)
 
+// Field buffers of a shot: forward level n lives in buffer (n & 3), adjoint / Born-perturbation
+// level n in buffer 4 + (n & 3).  A step producing level n reads levels n-1 and n-2 and writes
+// a third buffer, so no launch writes a buffer it reads (also for negative n: -1 & 3 = 3).
+constexpr int kFieldBufs = 8;
+__host__ __device__ inline int fwd_buf(int n) { return n & 3; }
+__host__ __device__ inline int adj_buf(int n) { return 4 + (n & 3); }
+
 // Storage precision of a kept wavefield.
 enum Prec : int { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
@@ -34,7 +41,7 @@ struct ShotDev {
   int nrec;
   long long npts;          // nx * ny * nz
   long long coef;          // byte offset of the window's FP32 coefficient array
-  long long fld;           // byte offset of field buffer 0; buffer b at fld + b * npts * 4
+  long long fld;           // byte offset of field buffer 0; buffer b at fld + b * npts * 4 (b < kFieldBufs)
   long long acc;           // byte offset of the FP64 gradient accumulator (-1: none)
   long long store;         // byte offset of the kept wavefield (FULL: [nt][npts]; CHECKPOINT: [nslots][2][npts])
   long long scale;         // byte offset of FP32 per-field scales (FULL: [nt]; CHECKPOINT: [nslots][2])
@@ -52,6 +59,7 @@ struct TileDev {
   int x0, y0, z0;
   int gat_begin, gat_count;  // receivers whose base node lies in this tile
   int inj_begin, inj_count;  // points of this tile touched by receivers (adjoint injection)
+  int ext_begin, ext_count;  // touched points of the tile + 4-cell halo (2D two-step adjoint)
 };
 
 // One receiver: column r of the shot's traces, base node and weights.
@@ -89,6 +97,7 @@ struct Tables {
   const TileDev* tiles;
   const RecDev* recs;        // all receivers, grouped by gather tile
   const InjPoint* inj_pts;
+  const InjPoint* ext_pts;   // per tile: touched points of its 4-cell extended region (2D)
   const InjEntry* inj_ent;
   const WinDev* wins;
   const int* win_shots;
@@ -123,13 +132,17 @@ hipError_t launch_fwd2d(const StepArgs& a, int tz, int store, hipStream_t stream
 // Quantise the last forward level u^{nt-1} of every shot into the scaled FULL store.
 hipError_t launch_store_last(const StepArgs& a, int nshot, long long max_npts, hipStream_t stream);
 hipError_t launch_adj2d(const StepArgs& a, int tz, hipStream_t stream);
+// Two 2D steps per launch (levels step, step+1 forward; step, step-1 adjoint); tz 8, 16 or 32.
+hipError_t launch_fwd2d2(const StepArgs& a, int tz, int store, hipStream_t stream);
+hipError_t launch_adj2d2(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_fwd3d(const StepArgs& a, int ty, int bz, int store, hipStream_t stream);
 hipError_t launch_adj3d(const StepArgs& a, int ty, int bz, hipStream_t stream);
 hipError_t launch_born3d(const StepArgs& a, int ty, int bz, hipStream_t stream);
 hipError_t launch_inj3d(const StepArgs& a, int ninj, hipStream_t stream);
-// Gather the last forward sample d^{nt-1} (field = forward buffers) of every shot.
-hipError_t launch_gather_last(const StepArgs& a, int nshot, int total_recs, int buf_base, hipStream_t stream);
+// Gather the last sample d^{nt-1} of every shot from the forward (adj = 0) or the
+// perturbation (adj = 1, Born) buffers.
+hipError_t launch_gather_last(const StepArgs& a, int nshot, int total_recs, int adj, hipStream_t stream);
 // v^0 = R(x_s) w^1 / h^ndim and v^{nt-1} = 0 for every shot.
 hipError_t launch_src_last(const StepArgs& a, int nshot, hipStream_t stream);
 // Checkpoint slot copies: dir 0 = store (fields -> slot), 1 = restore (slot -> fields).

@@ -53,19 +53,29 @@ __device__ __forceinline__ void load_tile(float (*L)[T2<TZ>::W], const float* __
   }
 }
 
-// Difference-form Laplacian at tile-local (row lr, column lc) (both without halo offset).
-template <int TZ>
-__device__ __forceinline__ float lap_at(const float (*L)[T2<TZ>::W], int lr, int lc,
-                                        const float* c) {
-  const int R = lr + kHalo, C = lc + kHalo;
-  const float u = L[R][C];
+// Difference-form Laplacian at *p in an LDS array with row stride `stride` (x neighbours at
+// +-1, z neighbours at +-stride); the order of the sum is fixed for every 2D kernel.
+__device__ __forceinline__ float lap_ptr(const float* p, int stride, const float* c) {
+  const float u = p[0];
   float s = 0.f;
 #pragma unroll
   for (int r = kHalo; r >= 1; --r) {
-    s += c[r] * ((L[R][C - r] - u) + (L[R][C + r] - u));
-    s += c[r] * ((L[R - r][C] - u) + (L[R + r][C] - u));
+    s += c[r] * ((p[-r] - u) + (p[r] - u));
+    s += c[r] * ((p[-r * stride] - u) + (p[r * stride] - u));
   }
   return s;
+}
+
+// Increment coef (L u + s - (eta/dt)(u - u_prev)) of one update; the new level is
+// (u + u - u_prev) + increment.
+__device__ __forceinline__ float step_incr(float u, float um2, float cfv, float lap, float eta) {
+  return cfv * (lap - eta * (u - um2));
+}
+
+template <int TZ>
+__device__ __forceinline__ float lap_at(const float (*L)[T2<TZ>::W], int lr, int lc,
+                                        const float* c) {
+  return lap_ptr(&L[lr + kHalo][lc + kHalo], T2<TZ>::W, c);
 }
 
 template <int TZ>
@@ -91,8 +101,9 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, nz = S.nz;
-  const float* __restrict__ u1 = fbuf(a.ws, S, (k - 1) & 1);
-  float* __restrict__ u2 = fbuf(a.ws, S, k & 1);
+  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
+  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
+  float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = T.x0 + lane;
@@ -135,10 +146,10 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
     if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * qk;
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
-    const float incr = pcf[i] * (lap - eta * (u - pu2[i]));
+    const float incr = step_incr(u, pu2[i], pcf[i], lap, eta);
     const float un = (u + u - pu2[i]) + incr;
     const long long p = (long long)z * nx + x;
-    u2[p] = un;
+    out[p] = un;
     if (SK == kStoreF32) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
     if (SK >= kStoreBF16) {
       lmax = fmaxf(lmax, fabsf(un));
@@ -163,14 +174,15 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
   const int nx = S.nx, nz = S.nz;
-  const float* __restrict__ w1 = fbuf(a.ws, S, 2 + ((j + 1) & 1));
-  float* __restrict__ w2 = fbuf(a.ws, S, 2 + (j & 1));
+  const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
+  const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
+  float* __restrict__ out = fbuf(a.ws, S, adj_buf(j));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const float* __restrict__ uj = nullptr;
   const unsigned short* __restrict__ uj16 = nullptr;
   float usc = 1.f;
   if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, j & 1);
+  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, fwd_buf(j));
   if (IMG >= kImgFullBF16) {
     uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
     usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
@@ -226,9 +238,9 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
     if (has_inj) lap += INJ[lr][lane];
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
-    const float incr = pcf[i] * (lap - eta * (w - pw2[i]));
+    const float incr = step_incr(w, pw2[i], pcf[i], lap, eta);
     const long long p = (long long)z * nx + x;
-    w2[p] = (w + w - pw2[i]) + incr;
+    out[p] = (w + w - pw2[i]) + incr;
     if (IMG) acc[p] = pacc[i] + (double)pu[i] * (double)incr;
   }
 }
@@ -246,10 +258,12 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, nz = S.nz;
-  const float* __restrict__ u1 = fbuf(a.ws, S, (k - 1) & 1);
-  float* __restrict__ u2 = fbuf(a.ws, S, k & 1);
-  const float* __restrict__ d1 = fbuf(a.ws, S, 2 + ((k - 1) & 1));
-  float* __restrict__ d2 = fbuf(a.ws, S, 2 + (k & 1));
+  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
+  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
+  float* __restrict__ uout = fbuf(a.ws, S, fwd_buf(k));
+  const float* __restrict__ d1 = fbuf(a.ws, S, adj_buf(k - 1));
+  const float* __restrict__ d2 = fbuf(a.ws, S, adj_buf(k - 2));
+  float* __restrict__ dout = fbuf(a.ws, S, adj_buf(k));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const float* __restrict__ dm = a.dm + S.m;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -293,12 +307,309 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
     const int bx = x - S.src_i, bz = z - S.src_k;
     if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * qk;
     const float incr = pcf[i] * (lap - eta * (u - pu2[i]));
-    u2[p] = (u + u - pu2[i]) + incr;
+    uout[p] = (u + u - pu2[i]) + incr;
     // scattered field, source -dm (u^k - 2u^{k-1} + u^{k-2}) / dt^2 = -dm incr / dt^2
     const float du = LD[lr + kHalo][lane + kHalo];
     const float lapd = lap_at<TZ>(LD, lr, lane, a.c) - pdm[i] * incr * a.inv_dt2;
     const float incd = pcf[i] * (lapd - eta * (du - pd2[i]));
-    d2[p] = (du + du - pd2[i]) + incd;
+    dout[p] = (du + du - pd2[i]) + incd;
+  }
+}
+
+// ------------------------------------------------------------------------------ two steps per launch
+// Level n-1 is staged with an 8-cell halo (LDS L1); the first step computes level n on the
+// tile plus a 4-cell halo (LDS LE: everything the second step's stencil needs), the second
+// step computes level n+1 (forward) or n-1 (adjoint) on the tile.  Both steps do exactly the
+// arithmetic of the one-step kernels, in the same order, so results are bitwise identical;
+// HBM traffic per two steps falls from 2 x (3 reads + 1 write) to 3 reads + 2 writes.
+template <int TZ>
+struct F2 {
+  static constexpr int W1 = kTX + 4 * kHalo;      // 80: level n-1 with an 8-cell halo
+  static constexpr int H1 = TZ + 4 * kHalo;
+  static constexpr int WE = kTX + 2 * kHalo;      // 72: first-step level on tile + 4
+  static constexpr int HE = TZ + 2 * kHalo;
+  static constexpr int NE = (WE * HE + kThreads - 1) / kThreads;  // extended points per thread
+  static constexpr int RPT = TZ / 4;
+};
+
+template <int TZ>
+__device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const float* __restrict__ f,
+                                           int nx, int nz, int x0, int z0) {
+  constexpr int W = F2<TZ>::W1, H = F2<TZ>::H1;
+  for (int e = threadIdx.x; e < W * H; e += kThreads) {
+    const int r = e / W, c = e - r * W;
+    const int z = z0 - 2 * kHalo + r, x = x0 - 2 * kHalo + c;
+    float v = 0.f;
+    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) v = f[(long long)z * nx + x];
+    L[r][c] = v;
+  }
+}
+
+// Forward: levels k and k+1 (k = step - off); SK = kStoreNone or kStoreF32.
+template <int TZ, int SK>
+__global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
+  using G = F2<TZ>;
+  __shared__ float L1[G::H1][G::W1];
+  __shared__ float LE[G::HE][G::WE];
+  const int tid = xcd_tile(blockIdx.x, a.ntiles);
+  const TileDev T = a.t.tiles[tid];
+  const ShotDev& S = a.t.shots[T.shot];
+  const int k = a.step - S.off;
+  const bool act1 = k >= 1 && k <= S.nt - 1;
+  const bool act2 = k + 1 >= 1 && k + 1 <= S.nt - 1;
+  if (!act1 && !act2) return;
+  const int nx = S.nx, nz = S.nz;
+  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
+  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
+  float* __restrict__ o1 = fbuf(a.ws, S, fwd_buf(k));
+  float* __restrict__ o2 = fbuf(a.ws, S, fwd_buf(k + 1));
+  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
+  float* st = SK == kStoreF32 ? reinterpret_cast<float*>(a.ws + S.store) : nullptr;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  // prefetch level k-2 and coef of this thread's extended points, coef of its tile points
+  float pm2[G::NE], pcf[G::NE], tcf[G::RPT];
+#pragma unroll
+  for (int i = 0; i < G::NE; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    const int r = e / G::WE, c = e - r * G::WE;
+    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
+    const bool in = e < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
+    const long long p = (long long)z * nx + x;
+    pm2[i] = in ? u2[p] : 0.f;
+    pcf[i] = in ? cf[p] : 0.f;
+  }
+  {
+    const int x = T.x0 + lane;
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int z = T.z0 + wv * G::RPT + i;
+      tcf[i] = x < nx && z < nz ? cf[(long long)z * nx + x] : 0.f;
+    }
+  }
+  load_tile8<TZ>(L1, u1, nx, nz, T.x0, T.z0);
+  __syncthreads();
+
+  if (act1 && a.d != nullptr) {
+    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+      const RecDev R = a.t.recs[T.gat_begin + t];
+      const int C = R.i - T.x0 + 2 * kHalo, Rw = R.k - T.z0 + 2 * kHalo;
+      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] =
+          R.w[0] * L1[Rw][C] + R.w[1] * L1[Rw][C + 1] + R.w[2] * L1[Rw + 1][C] + R.w[3] * L1[Rw + 1][C + 1];
+    }
+  }
+  // first step: level k on the tile + 4-cell halo (zero outside the grid)
+  const float q1 = act1 ? a.q[S.q + k - 1] : 0.f;
+#pragma unroll
+  for (int i = 0; i < G::NE; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e >= G::WE * G::HE) break;
+    const int r = e / G::WE, c = e - r * G::WE;
+    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
+    float v = 0.f;
+    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) {
+      const float* pc = &L1[r + kHalo][c + kHalo];
+      const float u = pc[0];
+      float lap = lap_ptr(pc, G::W1, a.c);
+      const int bx = x - S.src_i, bz = z - S.src_k;
+      if (act1 && (unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * q1;
+      const int dx = border_dist(x, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
+      const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
+      const float incr = step_incr(u, pm2[i], pcf[i], lap, eta);
+      v = (u + u - pm2[i]) + incr;
+      if (act1 && r >= kHalo && r < kHalo + TZ && c >= kHalo && c < kHalo + kTX) {
+        const long long p = (long long)z * nx + x;
+        o1[p] = v;
+        if (SK == kStoreF32) st[(long long)k * S.npts + p] = v;
+      }
+    }
+    LE[r][c] = v;
+  }
+  __syncthreads();
+
+  if (act2 && a.d != nullptr) {
+    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+      const RecDev R = a.t.recs[T.gat_begin + t];
+      const int C = R.i - T.x0 + kHalo, Rw = R.k - T.z0 + kHalo;
+      a.d[S.d + (long long)k * S.nrec + R.r] =
+          R.w[0] * LE[Rw][C] + R.w[1] * LE[Rw][C + 1] + R.w[2] * LE[Rw + 1][C] + R.w[3] * LE[Rw + 1][C + 1];
+    }
+  }
+  if (!act2) return;
+  // second step: level k+1 on the tile
+  const float q2 = a.q[S.q + k];
+  const int x = T.x0 + lane;
+  const int dx = border_dist(x, nx, a.nbl);
+#pragma unroll
+  for (int i = 0; i < G::RPT; ++i) {
+    const int lr = wv * G::RPT + i;
+    const int z = T.z0 + lr;
+    if (x >= nx || z >= nz) continue;
+    const float* pc = &LE[lr + kHalo][lane + kHalo];
+    const float u = pc[0];
+    const float um2 = L1[lr + 2 * kHalo][lane + 2 * kHalo];
+    float lap = lap_ptr(pc, G::WE, a.c);
+    const int bx = x - S.src_i, bz = z - S.src_k;
+    if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * q2;
+    const int dz = border_dist(z, nz, a.nbl);
+    const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
+    const float incr = step_incr(u, um2, tcf[i], lap, eta);
+    const float un = (u + u - um2) + incr;
+    const long long p = (long long)z * nx + x;
+    o2[p] = un;
+    if (SK == kStoreF32) st[(long long)(k + 1) * S.npts + p] = un;
+  }
+}
+
+// Adjoint: levels j and j-1 (j = step - off), receiver residual injected in both steps,
+// imaging of both steps accumulated (in step order) into one FP64 read-modify-write.
+// IMG = kImgNone or kImgFull32.
+template <int TZ, int IMG>
+__global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
+  using G = F2<TZ>;
+  __shared__ float L1[G::H1][G::W1];
+  __shared__ float LE[G::HE][G::WE];
+  __shared__ float INJ1[G::HE][G::WE];
+  __shared__ float INJ2[TZ][kTX];
+  __shared__ float INC1[TZ][kTX];
+  const int tid = xcd_tile(blockIdx.x, a.ntiles);
+  const TileDev T = a.t.tiles[tid];
+  const ShotDev& S = a.t.shots[T.shot];
+  const int j = a.step - S.off;
+  const bool act1 = j >= 1 && j <= S.nt - 1;
+  const bool act2 = j - 1 >= 1 && j - 1 <= S.nt - 1;
+  if (!act1 && !act2) return;
+  const int nx = S.nx, nz = S.nz;
+  const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
+  const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
+  float* __restrict__ o1 = fbuf(a.ws, S, adj_buf(j));
+  float* __restrict__ o2 = fbuf(a.ws, S, adj_buf(j - 1));
+  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
+  const float* __restrict__ ust = IMG == kImgFull32 ? reinterpret_cast<const float*>(a.ws + S.store) : nullptr;
+  double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool inj1 = act1 && a.dd != nullptr && T.ext_count > 0;
+  const bool inj2 = act2 && a.dd != nullptr && T.inj_count > 0;
+
+  float pm2[G::NE], pcf[G::NE], tcf[G::RPT], pu1[G::RPT], pu2[G::RPT];
+  double pacc[G::RPT];
+#pragma unroll
+  for (int i = 0; i < G::NE; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    const int r = e / G::WE, c = e - r * G::WE;
+    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
+    const bool in = e < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
+    const long long p = (long long)z * nx + x;
+    pm2[i] = in ? w2[p] : 0.f;
+    pcf[i] = in ? cf[p] : 0.f;
+    if (inj1 && e < G::WE * G::HE) INJ1[r][c] = 0.f;
+  }
+  {
+    const int x = T.x0 + lane;
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int z = T.z0 + wv * G::RPT + i;
+      const bool in = x < nx && z < nz;
+      const long long p = (long long)z * nx + x;
+      tcf[i] = in ? cf[p] : 0.f;
+      if (IMG) {
+        pu1[i] = in && act1 ? ust[(long long)j * S.npts + p] : 0.f;
+        pu2[i] = in && act2 ? ust[(long long)(j - 1) * S.npts + p] : 0.f;
+        pacc[i] = in ? acc[p] : 0.0;
+      }
+      if (inj2) INJ2[wv * G::RPT + i][lane] = 0.f;
+    }
+  }
+  load_tile8<TZ>(L1, w1, nx, nz, T.x0, T.z0);
+  __syncthreads();
+
+  if (inj1 || inj2) {
+    if (inj1) {
+      const float* ddj = a.dd + S.d + (long long)j * S.nrec;
+      for (int t = threadIdx.x; t < T.ext_count; t += kThreads) {
+        const InjPoint Pt = a.t.ext_pts[T.ext_begin + t];
+        float sum = 0.f;
+        for (int e = 0; e < Pt.e_count; ++e) {
+          const InjEntry E = a.t.inj_ent[Pt.e_begin + e];
+          sum += E.w * ddj[E.r];
+        }
+        INJ1[Pt.lz][Pt.lx] = sum;
+      }
+    }
+    if (inj2) {
+      const float* ddj = a.dd + S.d + (long long)(j - 1) * S.nrec;
+      for (int t = threadIdx.x; t < T.inj_count; t += kThreads) {
+        const InjPoint Pt = a.t.inj_pts[T.inj_begin + t];
+        float sum = 0.f;
+        for (int e = 0; e < Pt.e_count; ++e) {
+          const InjEntry E = a.t.inj_ent[Pt.e_begin + e];
+          sum += E.w * ddj[E.r];
+        }
+        INJ2[Pt.lz][Pt.lx] = sum;
+      }
+    }
+    __syncthreads();
+  }
+  if (act1 && a.v != nullptr && tid == S.src_tile && threadIdx.x == 0) {
+    const int C = S.src_i - T.x0 + 2 * kHalo, R = S.src_k - T.z0 + 2 * kHalo;
+    a.v[S.q + j] = S.src_w[0] * L1[R][C] + S.src_w[1] * L1[R][C + 1] + S.src_w[2] * L1[R + 1][C] +
+                   S.src_w[3] * L1[R + 1][C + 1];
+  }
+  // first step: level j on the tile + 4-cell halo
+#pragma unroll
+  for (int i = 0; i < G::NE; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e >= G::WE * G::HE) break;
+    const int r = e / G::WE, c = e - r * G::WE;
+    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
+    float v = 0.f;
+    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) {
+      const float* pc = &L1[r + kHalo][c + kHalo];
+      const float w = pc[0];
+      float lap = lap_ptr(pc, G::W1, a.c);
+      if (inj1) lap += INJ1[r][c];
+      const int dx = border_dist(x, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
+      const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
+      const float incr = step_incr(w, pm2[i], pcf[i], lap, eta);
+      v = (w + w - pm2[i]) + incr;
+      if (r >= kHalo && r < kHalo + TZ && c >= kHalo && c < kHalo + kTX) {
+        if (act1) o1[(long long)z * nx + x] = v;
+        INC1[r - kHalo][c - kHalo] = incr;
+      }
+    }
+    LE[r][c] = v;
+  }
+  __syncthreads();
+
+  if (act2 && a.v != nullptr && tid == S.src_tile && threadIdx.x == 0) {
+    const int C = S.src_i - T.x0 + kHalo, R = S.src_k - T.z0 + kHalo;
+    a.v[S.q + j - 1] = S.src_w[0] * LE[R][C] + S.src_w[1] * LE[R][C + 1] + S.src_w[2] * LE[R + 1][C] +
+                       S.src_w[3] * LE[R + 1][C + 1];
+  }
+  // second step: level j-1 on the tile; imaging of both steps
+  const int x = T.x0 + lane;
+  const int dx = border_dist(x, nx, a.nbl);
+#pragma unroll
+  for (int i = 0; i < G::RPT; ++i) {
+    const int lr = wv * G::RPT + i;
+    const int z = T.z0 + lr;
+    if (x >= nx || z >= nz) continue;
+    const long long p = (long long)z * nx + x;
+    double ac = IMG ? pacc[i] : 0.0;
+    if (IMG && act1) ac = ac + (double)pu1[i] * (double)INC1[lr][lane];
+    if (act2) {
+      const float* pc = &LE[lr + kHalo][lane + kHalo];
+      const float w = pc[0];
+      const float wm2 = L1[lr + 2 * kHalo][lane + 2 * kHalo];
+      float lap = lap_ptr(pc, G::WE, a.c);
+      if (inj2) lap += INJ2[lr][lane];
+      const int dz = border_dist(z, nz, a.nbl);
+      const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
+      const float incr = step_incr(w, wm2, tcf[i], lap, eta);
+      o2[p] = (w + w - wm2) + incr;
+      if (IMG) ac = ac + (double)pu2[i] * (double)incr;
+    }
+    if (IMG) acc[p] = ac;
   }
 }
 
@@ -327,7 +638,47 @@ hipError_t adj2d_tz(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int TZ>
+hipError_t fwd2d2_tz(const StepArgs& a, int store, hipStream_t s) {
+  switch (store) {
+    case kStoreNone: fwd2d2_kernel<TZ, kStoreNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kStoreF32: fwd2d2_kernel<TZ, kStoreF32><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int TZ>
+hipError_t adj2d2_tz(const StepArgs& a, hipStream_t s) {
+  switch (a.image_src) {
+    case kImgNone: adj2d2_kernel<TZ, kImgNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgFull32: adj2d2_kernel<TZ, kImgFull32><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_fwd2d2(const StepArgs& a, int tz, int store, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  switch (tz) {
+    case 8: return fwd2d2_tz<8>(a, store, s);
+    case 16: return fwd2d2_tz<16>(a, store, s);
+    case 32: return fwd2d2_tz<32>(a, store, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj2d2(const StepArgs& a, int tz, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  switch (tz) {
+    case 8: return adj2d2_tz<8>(a, s);
+    case 16: return adj2d2_tz<16>(a, s);
+    case 32: return adj2d2_tz<32>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_fwd2d(const StepArgs& a, int tz, int store, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;

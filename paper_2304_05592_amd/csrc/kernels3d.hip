@@ -138,8 +138,9 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, ny = S.ny, nz = S.nz;
-  const float* __restrict__ u1 = fbuf(a.ws, S, (k - 1) & 1);
-  float* __restrict__ u2 = fbuf(a.ws, S, k & 1);
+  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
+  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
+  float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int x = T.x0 + lane;
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
         const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
         const float un = (u + u - pu2[c]) + incr;
         const long long p = ((long long)z * ny + y) * nx + x;
-        u2[p] = un;
+        out[p] = un;
         if (SK == kStoreF32) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
         if (SK >= kStoreBF16) {
           lmax = fmaxf(lmax, fabsf(un));
@@ -241,14 +242,15 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
   const int nx = S.nx, ny = S.ny, nz = S.nz;
-  const float* __restrict__ w1 = fbuf(a.ws, S, 2 + ((j + 1) & 1));
-  float* __restrict__ w2 = fbuf(a.ws, S, 2 + (j & 1));
+  const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
+  const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
+  float* __restrict__ out = fbuf(a.ws, S, adj_buf(j));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const float* __restrict__ uj = nullptr;
   const unsigned short* __restrict__ uj16 = nullptr;
   float usc = 1.f;
   if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, j & 1);
+  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, fwd_buf(j));
   if (IMG >= kImgFullBF16) {
     uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
     usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
         const float w = Q[c][4];
         const float incr = pcf[c] * (lap - eta * (w - pw2[c]));
         const long long p = ((long long)z * ny + y) * nx + x;
-        w2[p] = (w + w - pw2[c]) + incr;
+        out[p] = (w + w - pw2[c]) + incr;
         if (IMG) acc[p] = pacc[c] + (double)pu[c] * (double)incr;
       }
     }
@@ -359,14 +361,14 @@ __global__ void inj3d_kernel(StepArgs a, int ninj) {
     s += E.w * ddj[E.r];
   }
   const float add = reinterpret_cast<const float*>(a.ws + S.coef)[Pt.p] * s;
-  float* w = fbuf(a.ws, S, 2 + (j & 1));
+  float* w = fbuf(a.ws, S, adj_buf(j));
   w[Pt.p] += add;
   if (a.image_src) {
     float u;
     if (a.image_src == kImgFull32)
       u = reinterpret_cast<const float*>(a.ws + S.store)[(long long)j * S.npts + Pt.p];
     else if (a.image_src == kImgBuffers)
-      u = fbuf(a.ws, S, j & 1)[Pt.p];
+      u = fbuf(a.ws, S, fwd_buf(j))[Pt.p];
     else
       u = dec16(reinterpret_cast<const unsigned short*>(a.ws + S.store)[(long long)j * S.npts + Pt.p],
                 a.image_src == kImgFullBF16) *
@@ -388,10 +390,12 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, ny = S.ny, nz = S.nz;
-  const float* __restrict__ u1 = fbuf(a.ws, S, (k - 1) & 1);
-  float* __restrict__ u2 = fbuf(a.ws, S, k & 1);
-  const float* __restrict__ d1 = fbuf(a.ws, S, 2 + ((k - 1) & 1));
-  float* __restrict__ d2 = fbuf(a.ws, S, 2 + (k & 1));
+  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
+  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
+  float* __restrict__ uout = fbuf(a.ws, S, fwd_buf(k));
+  const float* __restrict__ d1 = fbuf(a.ws, S, adj_buf(k - 1));
+  const float* __restrict__ d2 = fbuf(a.ws, S, adj_buf(k - 2));
+  float* __restrict__ dout = fbuf(a.ws, S, adj_buf(k));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const float* __restrict__ dm = a.dm + S.m;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -467,11 +471,11 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
           lap += S.src_w[bx + 2 * by + 4 * bzz] * qk;
         const float u = QU[c][4];
         const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
-        u2[p] = (u + u - pu2[c]) + incr;
+        uout[p] = (u + u - pu2[c]) + incr;
         const float du = QD[c][4];
         const float lapd = lap3<TY>(PD[b], QD[c], ly, lane, a.c) - pdm[c] * incr * a.inv_dt2;
         const float incd = pcf[c] * (lapd - eta * (du - pd2[c]));
-        d2[p] = (du + du - pd2[c]) + incd;
+        dout[p] = (du + du - pd2[c]) + incd;
       }
     }
     if (more) {

@@ -49,13 +49,13 @@ __global__ void fill_kernel(uint4* __restrict__ p, long long n16, unsigned char*
   if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
 }
 
-__global__ void gather_last_kernel(StepArgs a, int total, int buf_base) {
+__global__ void gather_last_kernel(StepArgs a, int total, int adj) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const RecDev R = a.t.recs[t];
   const ShotDev& S = a.t.shots[R.shot];
   const int k = S.nt - 1;
-  const float* f = fbuf(a.ws, S, buf_base + (k & 1));
+  const float* f = fbuf(a.ws, S, adj ? adj_buf(k) : fwd_buf(k));
   a.d[S.d + (long long)k * S.nrec + R.r] = interp_global(f, S, a.ndim, R.i, R.j, R.k, R.w);
 }
 
@@ -63,19 +63,17 @@ __global__ void src_last_kernel(StepArgs a, int nshot) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nshot) return;
   const ShotDev& S = a.t.shots[s];
-  const float* w1 = fbuf(a.ws, S, 2 + 1);
+  const float* w1 = fbuf(a.ws, S, adj_buf(1));
   a.v[S.q] = interp_global(w1, S, a.ndim, S.src_i, S.src_j, S.src_k, S.src_w);
   a.v[S.q + S.nt - 1] = 0.f;
 }
-
-__device__ __forceinline__ int lpar(int x) { return x & 1; }  // parity, also for negative x
 
 // Max |u| of the two fields of a state into scale[slot][0..1] (atomic max on the float bits
 // of non-negative values, which is exact and order independent).
 __global__ void absmax_kernel(StepArgs a, int slot, int state) {
   const ShotDev& S = a.t.shots[blockIdx.y];
   const int ls = state - S.off;
-  const float* f = fbuf(a.ws, S, lpar(ls - (int)blockIdx.z));
+  const float* f = fbuf(a.ws, S, fwd_buf(ls - (int)blockIdx.z));
   float mx = 0.f;
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < S.npts;
        p += (long long)gridDim.x * blockDim.x)
@@ -97,7 +95,7 @@ __global__ void slot_kernel(StepArgs a, int slot, int state, int dir) {
   const ShotDev& S = a.t.shots[blockIdx.y];
   const int fz = blockIdx.z;
   const int ls = state - S.off;
-  float* f = fbuf(a.ws, S, lpar(ls - fz));
+  float* f = fbuf(a.ws, S, fwd_buf(ls - fz));
   const long long base = ((long long)slot * 2 + fz) * S.npts;
   const int prec = a.store_prec;
   float s = 1.f, inv = 1.f;
@@ -128,7 +126,7 @@ __global__ void store_last_kernel(StepArgs a) {
   const ShotDev& S = a.t.shots[blockIdx.y];
   const int k = S.nt - 1;
   if (k < 1) return;
-  const float* f = fbuf(a.ws, S, k & 1);
+  const float* f = fbuf(a.ws, S, fwd_buf(k));
   const float inv = inv_scale(level_scale(reinterpret_cast<const float*>(a.ws + S.scale), k));
   unsigned short* st = reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)k * S.npts;
   const int bf = a.store_prec == kBF16;
@@ -220,10 +218,10 @@ hipError_t launch_fill(unsigned char* ws, long long off, long long nbytes, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_gather_last(const StepArgs& a, int nshot, int total, int buf_base, hipStream_t s) {
+hipError_t launch_gather_last(const StepArgs& a, int nshot, int total, int adj, hipStream_t s) {
   (void)nshot;
   if (total <= 0 || a.d == nullptr) return hipSuccess;
-  gather_last_kernel<<<(total + kThreads - 1) / kThreads, kThreads, 0, s>>>(a, total, buf_base);
+  gather_last_kernel<<<(total + kThreads - 1) / kThreads, kThreads, 0, s>>>(a, total, adj);
   return hipGetLastError();
 }
 

@@ -1,0 +1,104 @@
+"""Write the full-size parity fixtures (sampled oracle outputs) under tests/golden/.
+
+Calls only the oracle and the seeded input generators.  For each workload the
+oracle runs at full size in FP64 (the forward at the background model, the
+adjoint-state gradient for a seeded synthetic residual per shot, summed over
+shots in ascending order) and a seeded sample of the outputs is stored:
+
+  c2_grad_full.npz    16 shots on the 421 x 730 grid, 3638 samples per shot
+  c4_uneven_full.npz  64 shots, each on its own window (widths 256..1024, 1.0..2.5 s)
+  c5_crop_full.npz    the 64^3 crop of the 3D model (144^3 with the sponge)
+
+Gradient samples are flat indices into each window's computational grid (the
+same number per window); trace samples are every TIME_STRIDE-th time sample of
+every REC_STRIDE-th receiver.
+
+Run from the repository root:
+    python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop]
+The 2D sets take minutes on 8 cores, the 3D crop about half an hour.
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+RESIDUAL_SEED = 1000      # synthetic residual of shot s uses seed RESIDUAL_SEED + s
+SAMPLE_SEED = 20230411
+N_GRAD_SAMPLES = 4096
+REC_STRIDE = {"c2_grad": 20, "c4_uneven": 40, "c5_crop": 33}
+TIME_STRIDE = 8
+SEGMENT = 64              # oracle recomputation segment (result does not depend on it)
+
+
+def residual(wl, s):
+    import workloads as W
+    sh = wl.shots[s]
+    return W.synthetic_residual(sh.nt, len(sh.rec), wl.dt, wl.f0, RESIDUAL_SEED + s)
+
+
+def _shot(args):
+    name, s = args
+    import oracle as O
+    import workloads as W
+    wl = W.make_config(name)
+    sh = wl.shots[s]
+    kw = dict(src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax)
+    t0 = time.perf_counter()
+    g, d = O.gradient(wl.m(sh.window, background=True), wl.q(s), residual(wl, s), segment=SEGMENT,
+                      return_traces=True, **kw)
+    print(f"  {name} shot {s}: {time.perf_counter() - t0:.1f} s", flush=True)
+    return s, g, d
+
+
+def make(name, workers):
+    import workloads as W
+    wl = W.make_config(name)
+    jobs = [(name, s) for s in range(wl.nshot)]
+    if workers > 1 and len(jobs) > 1:
+        with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
+            res = pool.map(_shot, jobs)
+    else:
+        res = [_shot(j) for j in jobs]
+    res.sort(key=lambda r: r[0])
+    gs = [np.zeros(wl.comp_shape(w)) for w in range(wl.nwindow)]
+    for s, g_s, _ in res:         # ascending shot order within each window
+        w = wl.shots[s].window
+        gs[w] = gs[w] + g_s
+    rng = np.random.default_rng(SAMPLE_SEED)
+    per = max(64, N_GRAD_SAMPLES // wl.nwindow)
+    out = {}
+    for w, g in enumerate(gs):
+        gidx = np.sort(rng.choice(g.size, size=min(per, g.size), replace=False))
+        out[f"grad_index_{w}"] = gidx.astype(np.int64)
+        out[f"grad_value_{w}"] = g.ravel()[gidx]
+    for s, _, d in res:
+        nt, nrec = d.shape
+        ti = np.arange(0, nt, TIME_STRIDE)
+        ri = np.arange(0, nrec, REC_STRIDE[name])
+        out[f"trace_t_{s}"] = ti.astype(np.int64)
+        out[f"trace_r_{s}"] = ri.astype(np.int64)
+        out[f"trace_value_{s}"] = d[np.ix_(ti, ri)]
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_full.npz")
+    np.savez_compressed(path, **out)
+    print(f"wrote {path}", flush=True)
+
+
+def main():
+    names = sys.argv[1:] or ["c2_grad", "c4_uneven", "c5_crop"]
+    workers = min(8, len(os.sched_getaffinity(0)))
+    for name in names:
+        t0 = time.perf_counter()
+        make(name, workers)
+        print(f"{name}: {time.perf_counter() - t0:.1f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

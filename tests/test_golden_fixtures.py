@@ -1,0 +1,44 @@
+"""The full-size fixtures are what the oracle computes today on the seeded inputs.
+
+The scheme is causal: a forward run truncated to its first n time samples
+reproduces the first n samples of the full run exactly.  Re-running the oracle
+over a short prefix therefore checks the stored trace samples of a shot (and
+with them the generators, the geometry and the oracle) without the full-length
+run; the gradient samples are checked for shape and finiteness.
+"""
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_spec = importlib.util.spec_from_file_location("make_full_size", os.path.join(GOLD, "make_full_size.py"))
+G = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(G)
+
+
+@pytest.mark.parametrize("name,shot,n", [("c2_grad", 0, 240), ("c2_grad", 15, 240), ("c4_uneven", 3, 200),
+                                         ("c5_crop", 0, 60)])
+def test_fixture_trace_prefix(name, shot, n):
+    path = os.path.join(GOLD, f"{name}_full.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    gold = np.load(path)
+    wl = W.make_config(name)
+    sh = wl.shots[shot]
+    d = O.forward(wl.m(sh.window, background=True), wl.q(shot)[:n], sh.src, sh.rec, h=wl.h, dt=wl.dt,
+                  nbl=wl.nbl, vref=wl.vmax)
+    ti, ri = gold[f"trace_t_{shot}"], gold[f"trace_r_{shot}"]
+    keep = ti < n
+    assert keep.sum() >= n // G.TIME_STRIDE
+    np.testing.assert_allclose(d[np.ix_(ti[keep], ri)], gold[f"trace_value_{shot}"][keep], rtol=0,
+                               atol=1e-12 * np.abs(d).max())
+    for w in range(wl.nwindow):
+        idx, val = gold[f"grad_index_{w}"], gold[f"grad_value_{w}"]
+        assert idx.shape == val.shape and idx.max() < int(np.prod(wl.comp_shape(w)))
+        assert np.isfinite(val).all()
+    assert np.abs(gold["trace_value_0"]).max() > 0

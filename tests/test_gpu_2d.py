@@ -270,3 +270,25 @@ def test_autotune_without_a_residual_injects_nothing():
     _sync()
     assert choice["tz"] in (8, 16, 32, 64) and ms > 0
     assert rel_l2(plan.unpack(d, "d"), oracle_forward(wl)) <= TOL
+
+
+@pytest.mark.parametrize("tz", [8, 16, 32])
+def test_two_levels_per_launch_is_bitwise_the_one_level_path(tz):
+    """Uneven windows, per-shot nt (odd and even step counts, end-aligned offsets): forward
+    traces, F^T dd and the FULL-storage gradient are bitwise identical with two time levels
+    per launch and with one."""
+    wl = W.small_2d(windows=[90, 70, 113], T_per_shot=[400.0, 250.0, 331.0])
+    dds = _residuals(wl)
+    outs = []
+    for fuse in (True, False):
+        plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+        plan.set_tiles(tz=tz)
+        plan.set_fusion(fuse)
+        m, q = gpu_inputs(wl, plan)
+        g, v, d = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+        va = plan.adjoint(m, plan.pack(dds, "d"))
+        _sync()
+        outs.append((g.cpu(), v.cpu(), d.cpu(), va.cpu()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    assert rel_l2(plan.unpack(outs[0][1], "q"), oracle_adjoint(wl, dds)) <= TOL

@@ -1,0 +1,85 @@
+"""Full-size parity on sampled outputs.
+
+The workloads run on the GPU at their full sizes in the launch configuration
+that the benchmark times (every shot in one plan, the autotuned launch shape,
+FULL wavefield storage) and are compared with oracle samples that
+tests/golden/make_full_size.py stored (FP64, same seeded inputs):
+receiver traces of every shot at the background model (every 8th time sample
+of every k-th receiver) and the adjoint-state gradient J^T dd for a seeded
+synthetic residual per shot, at 4096 seeded grid points (split over windows).
+
+Bar: rel-L2 over the samples <= 1e-5 with FP32 storage; with BF16 / FP16
+storage of the wavefield the gradient carries the storage rounding (unit
+roundoff 2^-9 / 2^-12 per stored value), bounded by 2e-2 / 2e-3.
+"""
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+import paper_2304_05592_amd as A
+import workloads as W
+from helpers import make_plan
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_spec = importlib.util.spec_from_file_location("make_full_size", os.path.join(GOLD, "make_full_size.py"))
+G = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(G)
+
+TOL = 1e-5
+
+
+def _fixture(name):
+    path = os.path.join(GOLD, f"{name}_full.npz")
+    assert os.path.exists(path), f"missing fixture {path}: run tests/golden/make_full_size.py {name}"
+    return np.load(path)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _run(name, prec):
+    wl = W.make_config(name)
+    plan = make_plan(wl, A.Storage(A.STORE_FULL, 0, prec))
+    m = plan.pack([wl.m(w, background=True) for w in range(wl.nwindow)], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    dd = plan.pack([G.residual(wl, s) for s in range(wl.nshot)], "d")
+    ws = plan.workspace()
+    tiles, _ = plan.autotune(m, q, dd, probe_steps=32, ws=ws)
+    print(f"{name}: autotuned {tiles}", flush=True)
+    g, _, d = plan.gradient(m, q, dd, d=True, ws=ws)
+    return wl, plan.unpack(g, "m"), plan.unpack(d, "d")
+
+
+def _compare(name, prec, g_tol, d_tol):
+    gold = _fixture(name)
+    wl, gs, ds = _run(name, prec)
+    got_d = np.concatenate([ds[s][np.ix_(gold[f"trace_t_{s}"], gold[f"trace_r_{s}"])].ravel()
+                            for s in range(wl.nshot)])
+    ref_d = np.concatenate([gold[f"trace_value_{s}"].ravel() for s in range(wl.nshot)])
+    got_g = np.concatenate([gs[w].ravel()[gold[f"grad_index_{w}"]] for w in range(wl.nwindow)])
+    ref_g = np.concatenate([gold[f"grad_value_{w}"] for w in range(wl.nwindow)])
+    e_d, e_g = _rel(got_d, ref_d), _rel(got_g, ref_g)
+    print(f"{name}: traces rel-L2 {e_d:.2e} ({ref_d.size} samples), gradient rel-L2 {e_g:.2e} "
+          f"({ref_g.size} samples)", flush=True)
+    assert np.isfinite(got_g).all() and np.isfinite(got_d).all()
+    assert e_d <= d_tol
+    assert e_g <= g_tol
+
+
+@pytest.mark.gpu
+def test_c2_grad_full_size():
+    _compare("c2_grad", A.PREC_FP32, TOL, TOL)
+
+
+@pytest.mark.gpu
+def test_c4_uneven_full_size():
+    _compare("c4_uneven", A.PREC_FP32, TOL, TOL)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec,g_tol", [(A.PREC_FP32, TOL), (A.PREC_BF16, 2e-2), (A.PREC_FP16, 2e-3)])
+def test_c5_crop_full_size(prec, g_tol):
+    _compare("c5_crop", prec, g_tol, TOL)
