@@ -123,7 +123,9 @@ typedef struct awe_plan awe_plan;
 awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, awe_plan** plan);
 
 /* Bytes of device workspace every compute call on this plan needs (256-byte aligned
- * pointer required). */
+ * pointer required).  Inside the workspace every field row (nx values) is padded to a
+ * multiple of 64 elements; FULL storage keeps nt such padded fields per shot, e.g.
+ * nt * ceil(nx/64)*64 * ny * nz * 4 bytes in FP32.  The caller's arrays are not padded. */
 awe_status awe_plan_workspace_size(const awe_plan* plan, size_t* bytes);
 
 /* Free the plan and its device tables.  NULL is ignored. */

@@ -228,7 +228,7 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
         const int i = R.i + dx, j = R.j + dy, k = R.k + dz;
         const int t = tile_of(s, i, j, k);
         const TileDev& T = P->tiles[t];
-        const long long p = ((long long)k * sh.ny + j) * sh.nx + i;
+        const long long p = ((long long)k * sh.ny + j) * P->sd[s].px + i;
         touches.push_back({t, p, s, i - T.x0, j - T.y0, k - T.z0, r, (float)I.w[c]});
       }
     }
@@ -277,7 +277,8 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
     std::vector<Ext> ex;
     for (const InjPoint& ip : P->inj_pts) {
       const awe_shot& sh = P->shots[ip.shot];
-      const int i = (int)(ip.p % sh.nx), k = (int)(ip.p / sh.nx);
+      const int px = P->sd[ip.shot].px;
+      const int i = (int)(ip.p % px), k = (int)(ip.p / px);
       const int TZ = P->tz;
       for (int kz = std::max(0, (k - TZ - kHalo) / TZ - 1); kz <= (k + kHalo) / TZ; ++kz) {
         for (int kx = std::max(0, (i - awe::kTX - kHalo) / awe::kTX - 1); kx <= (i + kHalo) / awe::kTX; ++kx) {
@@ -371,7 +372,7 @@ awe_status prepare(awe_plan* P, const float* m, void* ws, bool zero_fwd, bool ze
   unsigned char* w = static_cast<unsigned char*>(ws);
   for (size_t i = 0; i < P->wins.size(); ++i) {
     AWE_HIP(awe::launch_coef(m, w, P->win_coef[i], P->wins[i].m, P->win_dims[3 * i],
-                             P->win_dims[3 * i + 1], P->win_dims[3 * i + 2], P->nbl, P->h, P->dt,
+                             P->win_dims[3 * i + 1], P->win_dims[3 * i + 2], P->wins[i].px, P->nbl, P->h, P->dt,
                              P->amp, s));
   }
   for (int i = 0; i < P->nshot; ++i) {
@@ -617,7 +618,9 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
       win_of[sh.m_offset] = (int)P->wins.size();
       WinDev w{};
       w.m = sh.m_offset;
-      w.npts = (long long)sh.nx * sh.ny * sh.nz;
+      w.nx = sh.nx;
+      w.px = awe::pitch_of(sh.nx);
+      w.npts = (long long)w.px * sh.ny * sh.nz;
       P->wins.push_back(w);
       P->win_dims.insert(P->win_dims.end(), {sh.nx, sh.ny, sh.nz});
       wshots.emplace_back();
@@ -648,12 +651,13 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     const awe_shot& sh = P->shots[s];
     ShotDev& d = P->sd[s];
     d.nx = sh.nx;
+    d.px = awe::pitch_of(sh.nx);
     d.ny = sh.ny;
     d.nz = sh.nz;
     d.nt = sh.nt;
     d.off = P->max_nt - sh.nt;
     d.nrec = sh.nrec;
-    d.npts = (long long)sh.nx * sh.ny * sh.nz;
+    d.npts = (long long)d.px * sh.ny * sh.nz;
     d.coef = P->win_coef[win_of[sh.m_offset]];
     d.m = sh.m_offset;
     d.q = sh.q_offset;

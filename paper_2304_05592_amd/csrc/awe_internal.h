@@ -14,6 +14,9 @@ namespace awe {
 constexpr int kThreads = 256;   // 4 wave64 per workgroup
 constexpr int kTX = 64;         // 2D tile width: one wavefront spans the tile row
 constexpr int kHalo = 4;        // stencil radius (8th order)
+constexpr int kPitch = 64;      // workspace rows are padded to a multiple of 64 elements, so
+                                // that every 64-column row segment starts on a 256-byte line
+inline int pitch_of(int nx) { return (nx + kPitch - 1) / kPitch * kPitch; }
 
 // Field buffers of a shot: forward level n lives in buffer (n & 3), adjoint / Born-perturbation
 // level n in buffer 4 + (n & 3).  A step producing level n reads levels n-1 and n-2 and writes
@@ -36,10 +39,11 @@ enum StoreKind : int { kStoreNone = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreFP16
 // Per-shot description as the kernels read it.
 struct ShotDev {
   int nx, ny, nz;          // computational grid (ny = 1 in 2D)
+  int px;                  // row pitch of every workspace field (multiple of kPitch >= nx)
   int nt;                  // local samples
   int off;                 // global state index of the shot's local state 0 (end-aligned)
   int nrec;
-  long long npts;          // nx * ny * nz
+  long long npts;          // px * ny * nz (workspace field size, padding included)
   long long coef;          // byte offset of the window's FP32 coefficient array
   long long fld;           // byte offset of field buffer 0; buffer b at fld + b * npts * 4 (b < kFieldBufs)
   long long acc;           // byte offset of the FP64 gradient accumulator (-1: none)
@@ -76,7 +80,7 @@ struct InjPoint {
   int shot;
   int lx, ly, lz;
   int e_begin, e_count;
-  long long p;               // flat point index in the shot grid
+  long long p;               // flat point index in the shot's workspace fields (rows of px)
 };
 
 struct InjEntry {
@@ -86,8 +90,9 @@ struct InjEntry {
 
 // A model window and the shots that run on it (ascending shot order in win_shots).
 struct WinDev {
-  long long m;               // element offset in m, dm, g
-  long long npts;
+  long long m;               // element offset in m, dm, g (rows of nx)
+  long long npts;            // px * ny * nz (coefficient / accumulator layout)
+  int nx, px;
   int sbegin, scount;
 };
 
@@ -125,7 +130,7 @@ struct StepArgs {
 
 // Launchers (defined in the .hip files).  All enqueue on `stream`.
 hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, long long m_off,
-                       int nx, int ny, int nz, int nbl, double h, double dt, double amp,
+                       int nx, int ny, int nz, int px, int nbl, double h, double dt, double amp,
                        hipStream_t stream);
 hipError_t launch_fill(unsigned char* ws, long long off, long long nbytes, hipStream_t stream);
 hipError_t launch_fwd2d(const StepArgs& a, int tz, int store, hipStream_t stream);

@@ -40,15 +40,28 @@ struct T2 {
   static constexpr int RPT = TZ / 4;         // rows per thread
 };
 
+// Stage rows z0-4 .. z0+TZ+3 of a field, columns x0-4 .. x0+67, zero outside the grid.  The
+// 64-column body of each row is one coalesced row segment per wave (aligned: the row pitch and
+// x0 are multiples of 64); the 4 + 4 halo columns of every row follow as one short pass.
 template <int TZ>
 __device__ __forceinline__ void load_tile(float (*L)[T2<TZ>::W], const float* __restrict__ f,
-                                          int nx, int nz, int x0, int z0) {
-  constexpr int W = T2<TZ>::W, H = T2<TZ>::H;
-  for (int e = threadIdx.x; e < W * H; e += kThreads) {
-    const int r = e / W, c = e - r * W;
-    const int z = z0 - kHalo + r, x = x0 - kHalo + c;
+                                          int nx, int nz, int px, int x0, int z0) {
+  constexpr int H = T2<TZ>::H;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = x0 + lane;
+#pragma unroll
+  for (int r = wv; r < H; r += 4) {
+    const int z = z0 - kHalo + r;
     float v = 0.f;
-    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) v = f[(long long)z * nx + x];
+    if (x < nx && (unsigned)z < (unsigned)nz) v = f[(long long)z * px + x];
+    L[r][lane + kHalo] = v;
+  }
+  for (int e = threadIdx.x; e < H * 2 * kHalo; e += kThreads) {
+    const int r = e / (2 * kHalo), c8 = e - r * (2 * kHalo);
+    const int c = c8 < kHalo ? c8 : kTX + c8;
+    const int z = z0 - kHalo + r, xx = x0 - kHalo + c;
+    float v = 0.f;
+    if ((unsigned)z < (unsigned)nz && (unsigned)xx < (unsigned)nx) v = f[(long long)z * px + xx];
     L[r][c] = v;
   }
 }
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
-  const int nx = S.nx, nz = S.nz;
+  const int nx = S.nx, nz = S.nz, px = S.px;
   const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
   const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
   float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
@@ -112,12 +125,12 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     const bool in = x < nx && z < nz;
     pu2[i] = in ? u2[p] : 0.f;
     pcf[i] = in ? cf[p] : 0.f;
   }
-  load_tile<TZ>(L, u1, nx, nz, T.x0, T.z0);
+  load_tile<TZ>(L, u1, nx, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -148,12 +161,13 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(u, pu2[i], pcf[i], lap, eta);
     const float un = (u + u - pu2[i]) + incr;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     out[p] = un;
-    if (SK == kStoreF32) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
+    if (SK == kStoreF32)
+      __builtin_nontemporal_store(un, reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts + p);
     if (SK >= kStoreBF16) {
       lmax = fmaxf(lmax, fabsf(un));
-      if (k >= 2) st16[p] = enc16(u * inv_prev, SK == kStoreBF16);
+      if (k >= 2) __builtin_nontemporal_store(enc16(u * inv_prev, SK == kStoreBF16), st16 + p);
     }
   }
   if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
@@ -173,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
   const ShotDev& S = a.t.shots[T.shot];
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
-  const int nx = S.nx, nz = S.nz;
+  const int nx = S.nx, nz = S.nz, px = S.px;
   const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
   const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
   float* __restrict__ out = fbuf(a.ws, S, adj_buf(j));
@@ -197,18 +211,18 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     const bool in = x < nx && z < nz;
     pw2[i] = in ? w2[p] : 0.f;
     pcf[i] = in ? cf[p] : 0.f;
     if (IMG) {
-      if (IMG >= kImgFullBF16) pu[i] = in ? dec16(uj16[p], IMG == kImgFullBF16) * usc : 0.f;
-      else pu[i] = in ? uj[p] : 0.f;
+      if (IMG >= kImgFullBF16) pu[i] = in ? dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc : 0.f;
+      else pu[i] = in ? (IMG == kImgFull32 ? __builtin_nontemporal_load(uj + p) : uj[p]) : 0.f;
       pacc[i] = in ? acc[p] : 0.0;
     }
     if (has_inj) INJ[wv * RPT + i][lane] = 0.f;
   }
-  load_tile<TZ>(L, w1, nx, nz, T.x0, T.z0);
+  load_tile<TZ>(L, w1, nx, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (has_inj) {
@@ -239,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(w, pw2[i], pcf[i], lap, eta);
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     out[p] = (w + w - pw2[i]) + incr;
     if (IMG) acc[p] = pacc[i] + (double)pu[i] * (double)incr;
   }
@@ -257,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
-  const int nx = S.nx, nz = S.nz;
+  const int nx = S.nx, nz = S.nz, px = S.px;
   const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
   const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
   float* __restrict__ uout = fbuf(a.ws, S, fwd_buf(k));
@@ -273,15 +287,15 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     const bool in = x < nx && z < nz;
     pu2[i] = in ? u2[p] : 0.f;
     pd2[i] = in ? d2[p] : 0.f;
     pcf[i] = in ? cf[p] : 0.f;
-    pdm[i] = in ? dm[p] : 0.f;
+    pdm[i] = in ? dm[(long long)z * nx + x] : 0.f;
   }
-  load_tile<TZ>(LU, u1, nx, nz, T.x0, T.z0);
-  load_tile<TZ>(LD, d1, nx, nz, T.x0, T.z0);
+  load_tile<TZ>(LU, u1, nx, nz, px, T.x0, T.z0);
+  load_tile<TZ>(LD, d1, nx, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -300,7 +314,7 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
     if (x >= nx || z >= nz) continue;
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     // background field
     const float u = LU[lr + kHalo][lane + kHalo];
     float lap = lap_at<TZ>(LU, lr, lane, a.c);
@@ -334,13 +348,13 @@ struct F2 {
 
 template <int TZ>
 __device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const float* __restrict__ f,
-                                           int nx, int nz, int x0, int z0) {
+                                           int nx, int nz, int px, int x0, int z0) {
   constexpr int W = F2<TZ>::W1, H = F2<TZ>::H1;
   for (int e = threadIdx.x; e < W * H; e += kThreads) {
     const int r = e / W, c = e - r * W;
     const int z = z0 - 2 * kHalo + r, x = x0 - 2 * kHalo + c;
     float v = 0.f;
-    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) v = f[(long long)z * nx + x];
+    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) v = f[(long long)z * px + x];
     L[r][c] = v;
   }
 }
@@ -358,7 +372,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
   const bool act1 = k >= 1 && k <= S.nt - 1;
   const bool act2 = k + 1 >= 1 && k + 1 <= S.nt - 1;
   if (!act1 && !act2) return;
-  const int nx = S.nx, nz = S.nz;
+  const int nx = S.nx, nz = S.nz, px = S.px;
   const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
   const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
   float* __restrict__ o1 = fbuf(a.ws, S, fwd_buf(k));
@@ -375,7 +389,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
     const bool in = e < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     pm2[i] = in ? u2[p] : 0.f;
     pcf[i] = in ? cf[p] : 0.f;
   }
@@ -384,10 +398,10 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
 #pragma unroll
     for (int i = 0; i < G::RPT; ++i) {
       const int z = T.z0 + wv * G::RPT + i;
-      tcf[i] = x < nx && z < nz ? cf[(long long)z * nx + x] : 0.f;
+      tcf[i] = x < nx && z < nz ? cf[(long long)z * px + x] : 0.f;
     }
   }
-  load_tile8<TZ>(L1, u1, nx, nz, T.x0, T.z0);
+  load_tile8<TZ>(L1, u1, nx, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (act1 && a.d != nullptr) {
@@ -418,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
       const float incr = step_incr(u, pm2[i], pcf[i], lap, eta);
       v = (u + u - pm2[i]) + incr;
       if (act1 && r >= kHalo && r < kHalo + TZ && c >= kHalo && c < kHalo + kTX) {
-        const long long p = (long long)z * nx + x;
+        const long long p = (long long)z * px + x;
         o1[p] = v;
         if (SK == kStoreF32) st[(long long)k * S.npts + p] = v;
       }
@@ -455,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(u, um2, tcf[i], lap, eta);
     const float un = (u + u - um2) + incr;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     o2[p] = un;
     if (SK == kStoreF32) st[(long long)(k + 1) * S.npts + p] = un;
   }
@@ -479,7 +493,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
   const bool act1 = j >= 1 && j <= S.nt - 1;
   const bool act2 = j - 1 >= 1 && j - 1 <= S.nt - 1;
   if (!act1 && !act2) return;
-  const int nx = S.nx, nz = S.nz;
+  const int nx = S.nx, nz = S.nz, px = S.px;
   const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
   const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
   float* __restrict__ o1 = fbuf(a.ws, S, adj_buf(j));
@@ -499,7 +513,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
     const bool in = e < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     pm2[i] = in ? w2[p] : 0.f;
     pcf[i] = in ? cf[p] : 0.f;
     if (inj1 && e < G::WE * G::HE) INJ1[r][c] = 0.f;
@@ -510,7 +524,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
     for (int i = 0; i < G::RPT; ++i) {
       const int z = T.z0 + wv * G::RPT + i;
       const bool in = x < nx && z < nz;
-      const long long p = (long long)z * nx + x;
+      const long long p = (long long)z * px + x;
       tcf[i] = in ? cf[p] : 0.f;
       if (IMG) {
         pu1[i] = in && act1 ? ust[(long long)j * S.npts + p] : 0.f;
@@ -520,7 +534,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
       if (inj2) INJ2[wv * G::RPT + i][lane] = 0.f;
     }
   }
-  load_tile8<TZ>(L1, w1, nx, nz, T.x0, T.z0);
+  load_tile8<TZ>(L1, w1, nx, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (inj1 || inj2) {
@@ -573,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
       const float incr = step_incr(w, pm2[i], pcf[i], lap, eta);
       v = (w + w - pm2[i]) + incr;
       if (r >= kHalo && r < kHalo + TZ && c >= kHalo && c < kHalo + kTX) {
-        if (act1) o1[(long long)z * nx + x] = v;
+        if (act1) o1[(long long)z * px + x] = v;
         INC1[r - kHalo][c - kHalo] = incr;
       }
     }
@@ -594,7 +608,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
     const int lr = wv * G::RPT + i;
     const int z = T.z0 + lr;
     if (x >= nx || z >= nz) continue;
-    const long long p = (long long)z * nx + x;
+    const long long p = (long long)z * px + x;
     double ac = IMG ? pacc[i] : 0.0;
     if (IMG && act1) ac = ac + (double)pu1[i] * (double)INC1[lr][lane];
     if (act2) {

@@ -31,11 +31,11 @@ __device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int 
 
 __device__ __forceinline__ float interp8(const float* f, const ShotDev& S, int i, int j, int k,
                                          const float* w) {
-  const long long nx = S.nx, nxy = (long long)S.nx * S.ny;
-  const long long p = (long long)k * nxy + (long long)j * nx + i;
-  return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + nx] + w[3] * f[p + nx + 1] +
-         w[4] * f[p + nxy] + w[5] * f[p + nxy + 1] + w[6] * f[p + nxy + nx] +
-         w[7] * f[p + nxy + nx + 1];
+  const long long px = S.px, pxy = (long long)S.px * S.ny;
+  const long long p = (long long)k * pxy + (long long)j * px + i;
+  return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + px] + w[3] * f[p + px + 1] +
+         w[4] * f[p + pxy] + w[5] * f[p + pxy + 1] + w[6] * f[p + pxy + px] +
+         w[7] * f[p + pxy + px + 1];
 }
 
 template <int TY>
@@ -72,7 +72,7 @@ __device__ __forceinline__ void ring_pos(int e, int* r, int* c) {
 
 template <int TY>
 __device__ __forceinline__ void ring_fetch(float (&h)[Ring<TY>::PER], const float* __restrict__ f,
-                                           int nx, int ny, int nz, int x0, int y0, int z) {
+                                           int nx, int ny, int nz, int px, int x0, int y0, int z) {
   const bool zin = (unsigned)z < (unsigned)nz;
   const long long zb = (long long)z * ny;
 #pragma unroll
@@ -83,7 +83,7 @@ __device__ __forceinline__ void ring_fetch(float (&h)[Ring<TY>::PER], const floa
       int r, c;
       ring_pos<TY>(e, &r, &c);
       const int y = y0 - kHalo + r, x = x0 - kHalo + c;
-      if ((unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * nx + x];
+      if ((unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * px + x];
     }
     h[i] = v;
   }
@@ -118,9 +118,9 @@ __device__ __forceinline__ float lap3(const float (*P)[T3<TY>::W], const float* 
 }
 
 template <int TY>
-__device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny, int nz, int x,
-                                     int y, int z) {
-  return (x < nx && y < ny && (unsigned)z < (unsigned)nz) ? f[((long long)z * ny + y) * nx + x] : 0.f;
+__device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny, int nz, int px,
+                                     int x, int y, int z) {
+  return (x < nx && y < ny && (unsigned)z < (unsigned)nz) ? f[((long long)z * ny + y) * px + x] : 0.f;
 }
 
 // ------------------------------------------------------------------------------ forward
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
-  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const int nx = S.nx, ny = S.ny, nz = S.nz, px = S.px;
   const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
   const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
   float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
@@ -165,13 +165,13 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz, x, y, T.z0 - kHalo + t);
-    pu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, x, y, T.z0);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
+    pu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0);
   }
   {
     float h[HP];
-    ring_fetch<TY>(h, u1, nx, ny, nz, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(h, u1, nx, ny, nz, px, T.x0, T.y0, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
@@ -182,13 +182,13 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
     const bool more = z + 1 < zend;
     float h[HP], qn[NC], nu2[NC], ncf[NC];
     if (more) {
-      ring_fetch<TY>(h, u1, nx, ny, nz, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(h, u1, nx, ny, nz, px, T.x0, T.y0, z + 1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int y = T.y0 + g * NC + c;
-        qn[c] = ldc<TY>(u1, nx, ny, nz, x, y, z + 1 + kHalo);
-        nu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, z + 1);
-        ncf[c] = ldc<TY>(cf, nx, ny, nz, x, y, z + 1);
+        qn[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, z + 1 + kHalo);
+        nu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, z + 1);
+        ncf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 1);
       }
     }
     const int dz = border_dist(z, nz, a.nbl);
@@ -206,12 +206,13 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
         const float u = Q[c][4];
         const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
         const float un = (u + u - pu2[c]) + incr;
-        const long long p = ((long long)z * ny + y) * nx + x;
+        const long long p = ((long long)z * ny + y) * px + x;
         out[p] = un;
-        if (SK == kStoreF32) reinterpret_cast<float*>(a.ws + S.store)[(long long)k * S.npts + p] = un;
+        if (SK == kStoreF32)
+          __builtin_nontemporal_store(un, reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts + p);
         if (SK >= kStoreBF16) {
           lmax = fmaxf(lmax, fabsf(un));
-          if (k >= 2) st16[p] = enc16(u * inv_prev, SK == kStoreBF16);
+          if (k >= 2) __builtin_nontemporal_store(enc16(u * inv_prev, SK == kStoreBF16), st16 + p);
         }
       }
     }
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
   const ShotDev& S = a.t.shots[T.shot];
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
-  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const int nx = S.nx, ny = S.ny, nz = S.nz, px = S.px;
   const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
   const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
   float* __restrict__ out = fbuf(a.ws, S, adj_buf(j));
@@ -267,8 +268,9 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
   // imaging inputs of one point: u^j and the accumulator (0 outside the grid)
   auto load_img = [&](int y, int z, float* u, double* ac) {
     const bool in = x < nx && y < ny && z < nz;
-    const long long p = ((long long)z * ny + y) * nx + x;
-    if (IMG >= kImgFullBF16) *u = in ? dec16(uj16[p], IMG == kImgFullBF16) * usc : 0.f;
+    const long long p = ((long long)z * ny + y) * px + x;
+    if (IMG >= kImgFullBF16) *u = in ? dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc : 0.f;
+    else if (IMG == kImgFull32) *u = in ? __builtin_nontemporal_load(uj + p) : 0.f;
     else if (IMG) *u = in ? uj[p] : 0.f;
     if (IMG) *ac = in ? acc[p] : 0.0;
   };
@@ -279,16 +281,16 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, x, y, T.z0 - kHalo + t);
-    pw2[c] = ldc<TY>(w2, nx, ny, nz, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, x, y, T.z0);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
+    pw2[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0);
     pu[c] = 0.f;
     pacc[c] = 0.0;
     load_img(y, T.z0, &pu[c], &pacc[c]);
   }
   {
     float h[HP];
-    ring_fetch<TY>(h, w1, nx, ny, nz, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(h, w1, nx, ny, nz, px, T.x0, T.y0, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
@@ -300,13 +302,13 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
     float h[HP], qn[NC], nw2[NC], ncf[NC], nu[NC];
     double nacc[NC];
     if (more) {
-      ring_fetch<TY>(h, w1, nx, ny, nz, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(h, w1, nx, ny, nz, px, T.x0, T.y0, z + 1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int y = T.y0 + g * NC + c;
-        qn[c] = ldc<TY>(w1, nx, ny, nz, x, y, z + 1 + kHalo);
-        nw2[c] = ldc<TY>(w2, nx, ny, nz, x, y, z + 1);
-        ncf[c] = ldc<TY>(cf, nx, ny, nz, x, y, z + 1);
+        qn[c] = ldc<TY>(w1, nx, ny, nz, px, x, y, z + 1 + kHalo);
+        nw2[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, z + 1);
+        ncf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 1);
         nu[c] = 0.f;
         nacc[c] = 0.0;
         load_img(y, z + 1, &nu[c], &nacc[c]);
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
         const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
         const float w = Q[c][4];
         const float incr = pcf[c] * (lap - eta * (w - pw2[c]));
-        const long long p = ((long long)z * ny + y) * nx + x;
+        const long long p = ((long long)z * ny + y) * px + x;
         out[p] = (w + w - pw2[c]) + incr;
         if (IMG) acc[p] = pacc[c] + (double)pu[c] * (double)incr;
       }
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
-  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const int nx = S.nx, ny = S.ny, nz = S.nz, px = S.px;
   const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
   const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
   float* __restrict__ uout = fbuf(a.ws, S, fwd_buf(k));
@@ -417,18 +419,18 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
     const int y = T.y0 + g * NC + c;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      QU[c][t] = ldc<TY>(u1, nx, ny, nz, x, y, T.z0 - kHalo + t);
-      QD[c][t] = ldc<TY>(d1, nx, ny, nz, x, y, T.z0 - kHalo + t);
+      QU[c][t] = ldc<TY>(u1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
+      QD[c][t] = ldc<TY>(d1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
     }
-    pu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, T.z0);
-    pd2[c] = ldc<TY>(d2, nx, ny, nz, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, x, y, T.z0);
-    pdm[c] = ldc<TY>(dm, nx, ny, nz, x, y, T.z0);
+    pu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, T.z0);
+    pd2[c] = ldc<TY>(d2, nx, ny, nz, px, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0);
+    pdm[c] = ldc<TY>(dm, nx, ny, nz, nx, x, y, T.z0);
   }
   {
     float hu[HP], hd[HP];
-    ring_fetch<TY>(hu, u1, nx, ny, nz, T.x0, T.y0, T.z0);
-    ring_fetch<TY>(hd, d1, nx, ny, nz, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(hu, u1, nx, ny, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(hd, d1, nx, ny, nz, px, T.x0, T.y0, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       PU[0][g * NC + c + kHalo][lane + kHalo] = QU[c][4];
@@ -443,17 +445,17 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
     const bool more = z + 1 < zend;
     float hu[HP], hd[HP], qun[NC], qdn[NC], nu2[NC], nd2[NC], ncf[NC], ndm[NC];
     if (more) {
-      ring_fetch<TY>(hu, u1, nx, ny, nz, T.x0, T.y0, z + 1);
-      ring_fetch<TY>(hd, d1, nx, ny, nz, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(hu, u1, nx, ny, nz, px, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(hd, d1, nx, ny, nz, px, T.x0, T.y0, z + 1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int y = T.y0 + g * NC + c;
-        qun[c] = ldc<TY>(u1, nx, ny, nz, x, y, z + 1 + kHalo);
-        qdn[c] = ldc<TY>(d1, nx, ny, nz, x, y, z + 1 + kHalo);
-        nu2[c] = ldc<TY>(u2, nx, ny, nz, x, y, z + 1);
-        nd2[c] = ldc<TY>(d2, nx, ny, nz, x, y, z + 1);
-        ncf[c] = ldc<TY>(cf, nx, ny, nz, x, y, z + 1);
-        ndm[c] = ldc<TY>(dm, nx, ny, nz, x, y, z + 1);
+        qun[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, z + 1 + kHalo);
+        qdn[c] = ldc<TY>(d1, nx, ny, nz, px, x, y, z + 1 + kHalo);
+        nu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, z + 1);
+        nd2[c] = ldc<TY>(d2, nx, ny, nz, px, x, y, z + 1);
+        ncf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 1);
+        ndm[c] = ldc<TY>(dm, nx, ny, nz, nx, x, y, z + 1);
       }
     }
     const int dz = border_dist(z, nz, a.nbl);
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
       if (x < nx && y < ny) {
         const int dy = border_dist(y, ny, a.nbl);
         const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
-        const long long p = ((long long)z * ny + y) * nx + x;
+        const long long p = ((long long)z * ny + y) * px + x;
         float lap = lap3<TY>(PU[b], QU[c], ly, lane, a.c);
         const int bx = x - S.src_i, by = y - S.src_j, bzz = z - S.src_k;
         if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)

@@ -14,30 +14,36 @@ __device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int 
 
 __device__ __forceinline__ float interp_global(const float* f, const ShotDev& S, int ndim, int i,
                                                int j, int k, const float* w) {
-  const long long nx = S.nx, nxy = (long long)S.nx * S.ny;
-  const long long p = (long long)k * nxy + (long long)j * nx + i;
+  const long long px = S.px, pxy = (long long)S.px * S.ny;
+  const long long p = (long long)k * pxy + (long long)j * px + i;
   if (ndim == 2) {
-    return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + nx] + w[3] * f[p + nx + 1];
+    return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + px] + w[3] * f[p + px + 1];
   }
-  return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + nx] + w[3] * f[p + nx + 1] +
-         w[4] * f[p + nxy] + w[5] * f[p + nxy + 1] + w[6] * f[p + nxy + nx] +
-         w[7] * f[p + nxy + nx + 1];
+  return w[0] * f[p] + w[1] * f[p + 1] + w[2] * f[p + px] + w[3] * f[p + px + 1] +
+         w[4] * f[p + pxy] + w[5] * f[p + pxy + 1] + w[6] * f[p + pxy + px] +
+         w[7] * f[p + pxy + px + 1];
 }
 
-// m -> coef = dt^2 / (m + eta dt / 2), computed in FP64 and rounded once.
+// m (rows of nx) -> coef = dt^2 / (m + eta dt / 2) (rows of px, 0 in the padding), computed
+// in FP64 and rounded once.
 __global__ void coef_kernel(const float* __restrict__ m, float* __restrict__ coef, int nx, int ny,
-                            int nz, int nbl, double dt, double amp_nbl2) {
-  const long long n = (long long)nx * ny * nz;
+                            int nz, int px, int nbl, double dt, double amp_nbl2) {
+  const long long n = (long long)px * ny * nz;
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
        p += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(p % nx);
-    const int j = (int)((p / nx) % ny);
-    const int k = (int)(p / ((long long)nx * ny));
+    const long long row = p / px;
+    const int i = (int)(p - row * px);
+    if (i >= nx) {
+      coef[p] = 0.f;
+      continue;
+    }
+    const int j = (int)(row % ny);
+    const int k = (int)(row / ny);
     const int dx = max(max(nbl - i, i - (nx - 1 - nbl)), 0);
     const int dy = ny > 1 ? max(max(nbl - j, j - (ny - 1 - nbl)), 0) : 0;
     const int dz = max(max(nbl - k, k - (nz - 1 - nbl)), 0);
     const double eta = amp_nbl2 * (double)(dx * dx + dy * dy + dz * dz);
-    coef[p] = (float)(dt * dt / ((double)m[p] + 0.5 * eta * dt));
+    coef[p] = (float)(dt * dt / ((double)m[row * nx + i] + 0.5 * eta * dt));
   }
 }
 
@@ -140,12 +146,15 @@ __global__ void grad_reduce_kernel(Tables t, unsigned char* ws, double* __restri
   const WinDev W = t.wins[blockIdx.y];
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < W.npts;
        p += (long long)gridDim.x * blockDim.x) {
+    const long long row = p / W.px;
+    const int i = (int)(p - row * W.px);
+    if (i >= W.nx) continue;
     double s = 0.0;
-    for (int i = 0; i < W.scount; ++i) {
-      const ShotDev& S = t.shots[t.win_shots[W.sbegin + i]];
+    for (int k = 0; k < W.scount; ++k) {
+      const ShotDev& S = t.shots[t.win_shots[W.sbegin + k]];
       s += reinterpret_cast<const double*>(ws + S.acc)[p];
     }
-    g[W.m + p] = scale * s;
+    g[W.m + row * W.nx + i] = scale * s;
   }
 }
 
@@ -198,13 +207,13 @@ int grid_for(long long n) {
 }  // namespace
 
 hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, long long m_off,
-                       int nx, int ny, int nz, int nbl, double h, double dt, double amp,
+                       int nx, int ny, int nz, int px, int nbl, double h, double dt, double amp,
                        hipStream_t s) {
   (void)h;
-  const long long n = (long long)nx * ny * nz;
+  const long long n = (long long)px * ny * nz;
   const double amp_nbl2 = nbl > 0 ? amp / ((double)nbl * nbl) : 0.0;
   coef_kernel<<<grid_for(n), kThreads, 0, s>>>(m + m_off, reinterpret_cast<float*>(ws + coef_off),
-                                                nx, ny, nz, nbl, dt, amp_nbl2);
+                                                nx, ny, nz, px, nbl, dt, amp_nbl2);
   return hipGetLastError();
 }
 

@@ -33,8 +33,8 @@ if ROOT not in sys.path:
 RESIDUAL_SEED = 1000      # synthetic residual of shot s uses seed RESIDUAL_SEED + s
 SAMPLE_SEED = 20230411
 N_GRAD_SAMPLES = 4096
-REC_STRIDE = {"c2_grad": 20, "c4_uneven": 40, "c5_crop": 33}
-TIME_STRIDE = 8
+REC_STRIDE = {"c2_grad": 40, "c4_uneven": 64, "c5_crop": 64}
+TIME_STRIDE = 32
 SEGMENT = 64              # oracle recomputation segment (result does not depend on it)
 
 

@@ -4,7 +4,7 @@ The workloads run on the GPU at their full sizes in the launch configuration
 that the benchmark times (every shot in one plan, the autotuned launch shape,
 FULL wavefield storage) and are compared with oracle samples that
 tests/golden/make_full_size.py stored (FP64, same seeded inputs):
-receiver traces of every shot at the background model (every 8th time sample
+receiver traces of every shot at the background model (every 32nd time sample
 of every k-th receiver) and the adjoint-state gradient J^T dd for a seeded
 synthetic residual per shot, at 4096 seeded grid points (split over windows).
 
