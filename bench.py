@@ -109,6 +109,18 @@ def sync():
     torch.cuda.synchronize()
 
 
+def choose_tiles(plan, args, m, q, dd, ws=None):
+    """Fixed launch shape from --tiles, else the autotuner's choice (None with --no-autotune)."""
+    if args.tiles:
+        t = args.tiles
+        plan.set_tiles(t.get("tz", 32), t.get("ty", 8), t.get("bz", 0))
+        plan.set_fusion(t.get("levels_per_launch", 1) == 2)
+        return dict(t)
+    if args.no_autotune:
+        return None
+    return plan.autotune(m, q, dd, probe_steps=32, ws=ws)[0]
+
+
 def make_plan(wl, storage, shots):
     import paper_2304_05592_amd as A
     geoms = [A.ShotGeometry(wl.shots[s].window, wl.shots[s].nt, wl.shots[s].src, wl.shots[s].rec)
@@ -150,6 +162,36 @@ def roofline_of(kernels, names):
             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": names[dom]}
 
 
+def timed_gradient(run, args, kind):
+    """Time the gradient step of a GradientRunner.  Region 1: one to three eager steps with HIP
+    events around every launch (per-launch durations; each event pair adds the dispatch latency
+    of one extra command).  Region 2 (headline, unless --no-graph): the step as two HIP graphs,
+    forward sweep + residual and reverse sweep, replayed back to back for args.steps steps with
+    HIP events between the segments; a kernel's average is its segment's time divided by its
+    launches.  Returns (seconds per step, eager seconds per step, kernel table, timing note)."""
+    n_eager = max(1, min(args.steps, 3))
+    eager_sec, prof = run.run(n_eager, args.warmup, use_graph=False, profile=True)
+    fused = bool(run.tiles) and run.tiles.get("levels_per_launch", 1) == 2
+    kernels = kernel_table(prof, run.launch_points, {"forward": kind, "adjoint": kind}, fused=fused)
+    if args.no_graph:
+        return eager_sec, eager_sec, kernels, "HIP events around every launch of the eager timed steps"
+    run.capture()
+    sec, seg = run.run(args.steps, args.warmup, use_graph=True, profile=True)
+    for name, key in (("forward", "forward_ms"), ("adjoint", "backward_ms")):
+        n_l = kernels[name]["launches_timed"] // n_eager
+        avg_ms = sum(seg[key]) / len(seg[key]) / n_l
+        k = kernels[name]
+        k["eager_event_us"] = k["avg_us"]
+        k["avg_us"] = round(avg_ms * 1e3, 3)
+        k["achieved_GBs"] = round(k["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
+        k["segment_ms"] = round(sum(seg[key]) / len(seg[key]), 3)
+    timing = ("HIP events on the launch stream between two graph segments (forward sweep + residual; "
+              "reverse sweep) of every timed step: segment time / launches of its step kernel (the "
+              "segment's auxiliary kernels included); eager_event_us = events around every launch "
+              "of an eager step")
+    return sec, eager_sec, kernels, timing
+
+
 class GradientRunner:
     """Forward (kept wavefield) + residual + reverse sweep on resident inputs."""
 
@@ -179,14 +221,20 @@ class GradientRunner:
         self.graph = None
         sync()
 
-    def step(self):
+    def forward_part(self):
         p = self.plan
         p.forward(self.m0, self.q, d=self.d, keep=True, ws=self.ws)
         _, self.loss = self.A.residual(self.d, self.d_obs, r=self.r)
-        p.backward(self.m0, self.q, self.r, g=self.g, v=None, ws=self.ws)
 
-    def capture(self, profile_stride=0):
-        """Capture one step into a HIP graph (with kernel-timing events every stride-th launch)."""
+    def backward_part(self):
+        self.plan.backward(self.m0, self.q, self.r, g=self.g, v=None, ws=self.ws)
+
+    def step(self):
+        self.forward_part()
+        self.backward_part()
+
+    def capture(self):
+        """Capture the step as two HIP graphs: forward sweep + residual, and the reverse sweep."""
         torch = self.torch
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -194,31 +242,51 @@ class GradientRunner:
             self.step()
         torch.cuda.current_stream().wait_stream(s)
         sync()
-        if profile_stride:
-            nt = max(self.wl.shots[i].nt for i in self.shots)
-            self.plan.profile_enable(2 * nt // profile_stride + 64, profile_stride)
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph, stream=s):
-            self.step()
+        self.graph = (torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph())
+        with torch.cuda.graph(self.graph[0], stream=s):
+            self.forward_part()
+        with torch.cuda.graph(self.graph[1], stream=s):
+            self.backward_part()
         sync()
 
+    def replay(self, ev=None):
+        if ev is not None:
+            ev[0].record()
+        self.graph[0].replay()
+        if ev is not None:
+            ev[1].record()
+        self.graph[1].replay()
+        if ev is not None:
+            ev[2].record()
+
     def run(self, steps, warmup, use_graph, profile):
-        """Seconds per step (and the kernel-timing summary of the timed region)."""
+        """Seconds per step and, with profile: eager = per-launch event summary; graph = event
+        time of the two graph segments per step ({'forward_ms': [...], 'backward_ms': [...]})."""
+        torch = self.torch
         for _ in range(warmup):
-            self.graph.replay() if use_graph else self.step()
+            self.replay() if use_graph else self.step()
         sync()
         if profile and not use_graph:
             nt = max(self.wl.shots[i].nt for i in self.shots)
             self.plan.profile_enable(2 * nt * steps + 64, 1)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)] \
+            if profile and use_graph else None
         sync()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            self.graph.replay() if use_graph else self.step()
+        for i in range(steps):
+            if use_graph:
+                self.replay(evs[i] if evs else None)
+            else:
+                self.step()
         sync()
         sec = (time.perf_counter() - t0) / steps
-        prof = self.plan.profile_read() if profile else None
-        if profile:
+        prof = None
+        if profile and not use_graph:
+            prof = self.plan.profile_read()
             self.plan.profile_disable()
+        if evs:
+            prof = {"forward_ms": [e[0].elapsed_time(e[1]) for e in evs],
+                    "backward_ms": [e[1].elapsed_time(e[2]) for e in evs]}
         return sec, prof
 
     def release(self):
@@ -284,20 +352,10 @@ def bench_c2(args):
     wl = W.make_config("c2_grad")
     run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL), autotune=not args.no_autotune,
                          tiles=args.tiles)
-    # timed region 1: eager launches with HIP events around every launch (kernel durations)
-    eager_sec, prof = run.run(max(1, min(args.steps, 3)), args.warmup, use_graph=False, profile=True)
-    timing = ("HIP events around every launch of an eager timed region of the same step, on the "
-              "launch stream (the graph's kernels are the same launches)")
-    # timed region 2: the step captured into a HIP graph and replayed (headline value)
-    use_graph = not args.no_graph
-    if use_graph:
-        run.capture(profile_stride=0)
-        sec, _ = run.run(args.steps, args.warmup, use_graph=True, profile=False)
-    else:
-        sec = eager_sec
+    sec, eager_sec, kernels, timing = timed_gradient(run, args, "fp32")
     value = run.points / sec / 1e9
     fused = bool(run.tiles) and run.tiles.get("levels_per_launch", 1) == 2
-    kernels = kernel_table(prof, run.launch_points, {"forward": "fp32", "adjoint": "fp32"}, fused=fused)
+    use_graph = not args.no_graph
     names = ({"forward": "fwd2d2 (two forward levels + stored FP32 copies, 28 B/point per launch)",
               "adjoint": "adj2d2 (two adjoint levels + imaging from stored FP32, 44 B/point per launch)"}
              if fused else
@@ -342,7 +400,7 @@ def bench_c3(args):
     m0 = plan.pack([wl.m(0, background=True)], "m")
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     d_obs = plan.forward(m_true, q)
-    tiles = None if args.no_autotune else plan.autotune(m0, q, d_obs, probe_steps=32)[0]
+    tiles = choose_tiles(plan, args, m0, q, d_obs)
     points, launch_points = points_of(wl, range(wl.nshot))
 
     def step():
@@ -386,7 +444,7 @@ def bench_c4(args):
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     ws = plan.workspace()
     d = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
-    tiles = None if args.no_autotune else plan.autotune(m, q, None, probe_steps=32, ws=ws)[0]
+    tiles = choose_tiles(plan, args, m, q, None, ws)
     points, launch_points = points_of(wl, range(wl.nshot))
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -455,16 +513,17 @@ def bench_c5(args):
     prec = {"bf16": A.PREC_BF16, "fp16": A.PREC_FP16, "fp32": A.PREC_FP32}[args.prec]
     run = GradientRunner(wl, [0], A.Storage(A.STORE_FULL, 0, prec), autotune=not args.no_autotune,
                          tiles=args.tiles)
-    sec, prof = run.run(args.steps, args.warmup, use_graph=False, profile=True)
     kind = "fp32" if prec == A.PREC_FP32 else "16bit"
-    kernels = kernel_table(prof, run.launch_points, {"forward": kind, "adjoint": kind})
+    sec, eager_sec, kernels, timing = timed_gradient(run, args, kind)
     names = {"forward": f"fwd3d step (forward + stored {args.prec} copy, {BYTES[('forward', kind)]} B/point)",
              "adjoint": f"adj3d step (adjoint + imaging, {BYTES[('adjoint', kind)]} B/point)"}
     out = base_line(args, wl, run.points / sec / 1e9, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": 1, "nt": int(wl.shots[0].nt), "storage": f"FULL {args.prec}",
-                   "batched": False, "graph": False, "tiles": run.tiles},
+                   "batched": False, "graph": not args.no_graph, "tiles": run.tiles},
         "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
+        "kernel_timing": timing,
+        "eager": {"value": round(run.points / eager_sec / 1e9, 3), "ms_per_step": round(eager_sec * 1e3, 3)},
         "loss": float(run.loss.item())})
     run.release()
     return out
