@@ -200,7 +200,7 @@ awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, con
                              int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
                              int32_t chosen[4], double* best_ms);
 
-/* Set the tile shape explicitly (tz: 8, 16, 32 or 64 rows in 2D; ty: 4, 8 or 16 rows and bz:
+/* Set the tile shape explicitly (tz: 8, 12, 16, 20, 24, 32 or 64 rows in 2D; ty: 4, 8 or 16 rows and bz:
  * z-block length, 0 = full depth, in 3D).  Results do not depend on the tile shape (every
  * point's arithmetic and every sum's order are fixed).  Rebuilds the device tables. */
 awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz);

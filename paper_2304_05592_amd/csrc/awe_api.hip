@@ -442,7 +442,9 @@ awe_status step_adj2(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
   return AWE_OK;
 }
 
-bool fused_ok(const awe_plan* P) { return P->ndim == 2 && P->fuse2 && P->tz <= 32; }
+bool fused_ok(const awe_plan* P) {
+  return P->ndim == 2 && P->fuse2 && (P->tz == 8 || P->tz == 16 || P->tz == 32);
+}
 
 // Forward levels 1..nsteps: one single step first when the count is odd, then pairs.
 awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s) {
@@ -830,7 +832,8 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
 
 awe_status awe_plan_set_tiles(awe_plan* P, int32_t tz, int32_t ty, int32_t bz) {
   if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
-  if (tz != 8 && tz != 16 && tz != 32 && tz != 64) return fail(AWE_ERR_INVALID_ARG, "tz must be 8, 16, 32 or 64");
+  if (tz != 8 && tz != 12 && tz != 16 && tz != 20 && tz != 24 && tz != 32 && tz != 64)
+    return fail(AWE_ERR_INVALID_ARG, "tz must be 8, 12, 16, 20, 24, 32 or 64");
   if (ty != 4 && ty != 8 && ty != 16) return fail(AWE_ERR_INVALID_ARG, "ty must be 4, 8 or 16");
   if (bz < 0) return fail(AWE_ERR_INVALID_ARG, "bz must be >= 0");
   P->tz = tz;
@@ -845,7 +848,9 @@ awe_status awe_plan_set_tiles(awe_plan* P, int32_t tz, int32_t ty, int32_t bz) {
 awe_status awe_plan_set_fusion(awe_plan* P, int32_t two_steps) {
   if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
   P->fuse2 = two_steps ? 1 : 0;
-  if (P->fuse2 && P->tz > 32) return awe_plan_set_tiles(P, 32, P->ty, P->bz);
+  // two-level kernels exist for 8, 16 and 32 rows
+  if (P->fuse2 && P->tz != 8 && P->tz != 16 && P->tz != 32)
+    return awe_plan_set_tiles(P, P->tz < 24 ? 16 : 32, P->ty, P->bz);
   return AWE_OK;
 }
 

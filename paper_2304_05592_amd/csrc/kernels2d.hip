@@ -698,7 +698,10 @@ hipError_t launch_fwd2d(const StepArgs& a, int tz, int store, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   switch (tz) {
     case 8: return fwd2d_tz<8>(a, store, s);
+    case 12: return fwd2d_tz<12>(a, store, s);
     case 16: return fwd2d_tz<16>(a, store, s);
+    case 20: return fwd2d_tz<20>(a, store, s);
+    case 24: return fwd2d_tz<24>(a, store, s);
     case 32: return fwd2d_tz<32>(a, store, s);
     case 64: return fwd2d_tz<64>(a, store, s);
   }
@@ -709,7 +712,10 @@ hipError_t launch_adj2d(const StepArgs& a, int tz, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   switch (tz) {
     case 8: return adj2d_tz<8>(a, s);
+    case 12: return adj2d_tz<12>(a, s);
     case 16: return adj2d_tz<16>(a, s);
+    case 20: return adj2d_tz<20>(a, s);
+    case 24: return adj2d_tz<24>(a, s);
     case 32: return adj2d_tz<32>(a, s);
     case 64: return adj2d_tz<64>(a, s);
   }
@@ -720,7 +726,10 @@ hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   switch (tz) {
     case 8: born2d_kernel<8><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case 12: born2d_kernel<12><<<a.ntiles, kThreads, 0, s>>>(a); break;
     case 16: born2d_kernel<16><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case 20: born2d_kernel<20><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case 24: born2d_kernel<24><<<a.ntiles, kThreads, 0, s>>>(a); break;
     case 32: born2d_kernel<32><<<a.ntiles, kThreads, 0, s>>>(a); break;
     case 64: born2d_kernel<64><<<a.ntiles, kThreads, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
