@@ -200,6 +200,16 @@ awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, con
                              int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
                              int32_t chosen[4], double* best_ms);
 
+/* Shot groups (batching, a12): the plan's shots, sorted by time offset, are split into
+ * groups of consecutive shots; every call runs the time loop of one group after the other
+ * (one launch per step covers the group's shots), so that a step's working set stays in the
+ * 256 MB last-level cache.  ngroups = 0 (the default) chooses the count from the fields'
+ * size (about 160 MB of three FP32 fields per group, at least 8 M points per group);
+ * ngroups >= 1 forces that many (at most one per shot).  Results do not depend on the
+ * grouping.  actual (may be NULL) receives the count in effect.  Rebuilds the device
+ * tables and drops any kept forward.  Errors: INVALID_ARG, HIP. */
+awe_status awe_plan_set_groups(awe_plan* plan, int32_t ngroups, int32_t* actual);
+
 /* Set the tile shape explicitly (tz: 8, 12, 16, 20, 24, 32 or 64 rows in 2D; ty: 4, 8 or 16 rows and bz:
  * z-block length, 0 = full depth, in 3D).  Results do not depend on the tile shape (every
  * point's arithmetic and every sum's order are fixed).  Rebuilds the device tables. */

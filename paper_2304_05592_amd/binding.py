@@ -25,7 +25,7 @@ PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "awe_forward",
            "awe_backward", "awe_gradient", "awe_adjoint", "awe_born", "awe_reduce_workspace_size",
            "awe_residual", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
-           "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
+           "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
            "awe_status_string", "awe_last_error", "awe_version"]
 
 
@@ -87,6 +87,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     L.awe_plan_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.awe_plan_set_fusion.argtypes = [vp, ctypes.c_int32]
+    L.awe_plan_set_groups.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.awe_profile_enable.argtypes = [vp, i64, ctypes.c_int32]
     L.awe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.awe_profile_disable.argtypes = [vp]
@@ -97,7 +98,7 @@ def lib():
     for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
                  "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_dot_f64",
                  "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion",
-                 "awe_profile_enable",
+                 "awe_plan_set_groups", "awe_profile_enable",
                  "awe_profile_read", "awe_profile_disable"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -287,6 +288,13 @@ class Plan:
     def set_fusion(self, two_steps: bool):
         """2D: two time levels per launch or one (default); results are bitwise identical."""
         check(lib().awe_plan_set_fusion(self._h, int(bool(two_steps))))
+
+    def set_groups(self, ngroups: int = 0) -> int:
+        """Shot groups run one after the other (0: automatic, sized to the last-level cache);
+        returns the number of groups in effect.  Results do not depend on the grouping."""
+        n = ctypes.c_int32(0)
+        check(lib().awe_plan_set_groups(self._h, int(ngroups), ctypes.byref(n)))
+        return n.value
 
     # ---------------------------------------------------------------- kernel timing
     def profile_enable(self, max_launches: int, stride: int = 1):

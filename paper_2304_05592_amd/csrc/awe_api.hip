@@ -66,7 +66,15 @@ struct awe_plan {
   std::vector<double> rec_pos;    // copy of the problem's receiver rows
   std::vector<ShotDev> sd;
   std::vector<TileDev> tiles;
-  std::vector<int> active;        // active[n]: tiles of the shots with off < n
+  // Shot groups: consecutive shots of `order` (sorted by time offset) that run their whole
+  // time loop before the next group starts, so that a step's working set stays in the
+  // last-level cache.  Group g owns tiles [g_tile0[g], g_tile0[g + 1]); g_active[g][n] of
+  // them (a prefix) belong to shots with off < n.
+  std::vector<int> order;
+  std::vector<int> g_tile0, g_shot0, g_nshot, g_inj0, g_ninj;
+  std::vector<std::vector<int>> g_active;
+  int groups_req = 0;             // 0: automatic
+  int cur = 0;                    // group of the launches being issued
   std::vector<RecDev> recs;
   std::vector<InjPoint> inj_pts;
   std::vector<InjPoint> ext_pts;
@@ -96,6 +104,12 @@ struct awe_plan {
 };
 
 namespace {
+
+// Automatic shot groups: three FP32 fields of every shot of a group (the working set of one
+// step) within about 160 MB, well inside the 256 MB last-level cache, and at least 8 M points
+// per launch so that a launch still fills the chip.
+constexpr long long kGroupBytes = 160LL << 20;
+constexpr long long kMinGroupPoints = 8LL << 20;
 
 struct Interp {
   int base[3];     // x, y, z base node
@@ -176,13 +190,46 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
     const int TZ = nd == 2 ? P->tz : (P->bz > 0 ? P->bz : sh.nz);
     return first_tile[s] + ((k / TZ) * nty[s] + (j / TY)) * ntx[s] + i / awe::kTX;
   };
-  // active tile prefix per global step
-  P->active.assign(P->nsteps + 2, 0);
-  for (int n = 0; n <= P->nsteps + 1; ++n) {
-    int cnt = 0;
-    for (int s : order)
-      if (P->sd[s].off < n) cnt += ntx[s] * nty[s] * ntz[s];
-    P->active[n] = cnt;
+  // shot groups over `order`, balanced by points
+  P->order = order;
+  {
+    long long pts = 0;
+    for (int s : order) pts += P->sd[s].npts;
+    int ng = P->groups_req;
+    if (ng <= 0) {
+      const long long bytes = 12 * pts;  // three FP32 fields per point touched by every step
+      ng = (int)((bytes + kGroupBytes - 1) / kGroupBytes);
+      ng = (int)std::min<long long>(ng, std::max<long long>(1, pts / kMinGroupPoints));
+    }
+    ng = std::max(1, std::min(ng, P->nshot));
+    P->g_shot0.assign(1, 0);
+    long long acc = 0;
+    for (int i = 0; i < P->nshot; ++i) {
+      const int g = (int)P->g_shot0.size() - 1;
+      acc += P->sd[order[i]].npts;
+      // close group g once it holds its share of the points, or when every later group
+      // needs one of the remaining shots
+      const int later_groups = ng - (g + 1), later_shots = P->nshot - (i + 1);
+      if (later_groups > 0 && (later_shots == later_groups ||
+                               (acc * ng >= pts * (g + 1) && later_shots >= later_groups)))
+        P->g_shot0.push_back(i + 1);
+    }
+    const int G = (int)P->g_shot0.size();
+    P->g_nshot.assign(G, 0);
+    P->g_tile0.assign(G + 1, 0);
+    P->g_active.assign(G, std::vector<int>(P->nsteps + 2, 0));
+    for (int g = 0; g < G; ++g) {
+      const int b = P->g_shot0[g], e = g + 1 < G ? P->g_shot0[g + 1] : P->nshot;
+      P->g_nshot[g] = e - b;
+      P->g_tile0[g] = first_tile[order[b]];
+      for (int n = 0; n <= P->nsteps + 1; ++n) {
+        int cnt = 0;
+        for (int i = b; i < e; ++i)
+          if (P->sd[order[i]].off < n) cnt += ntx[order[i]] * nty[order[i]] * ntz[order[i]];
+        P->g_active[g][n] = cnt;
+      }
+    }
+    P->g_tile0[G] = (int)P->tiles.size();
   }
   // sources
   const double hd = std::pow(P->h, nd);
@@ -269,6 +316,19 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
     P->inj_pts.push_back(ip);
     i = j;
   }
+  {
+    const int G = (int)P->g_nshot.size();
+    P->g_inj0.assign(G, 0);
+    P->g_ninj.assign(G, 0);
+    std::vector<int> grp_of(P->nshot, 0);
+    for (int g = 0; g < G; ++g)
+      for (int i = 0; i < P->g_nshot[g]; ++i) grp_of[order[P->g_shot0[g] + i]] = g;
+    for (size_t i = P->inj_pts.size(); i-- > 0;) {
+      const int g = grp_of[P->inj_pts[i].shot];
+      P->g_inj0[g] = (int)i;
+      P->g_ninj[g]++;
+    }
+  }
   // 2D: every touched point is also listed for each tile whose 4-cell extended region holds
   // it (the two-step adjoint injects on the extended region); same CSR entries
   P->ext_pts.clear();
@@ -316,7 +376,8 @@ awe_status upload_tables(awe_plan* P) {
   const long long o_ie = o_xp + bytes(P->ext_pts.size(), sizeof(InjPoint));
   const long long o_w = o_ie + bytes(P->inj_ent.size(), sizeof(InjEntry));
   const long long o_ws = o_w + bytes(P->wins.size(), sizeof(WinDev));
-  const long long total = o_ws + bytes(P->win_shots.size(), sizeof(int)) + 256;
+  const long long o_or = o_ws + bytes(P->win_shots.size(), sizeof(int));
+  const long long total = o_or + bytes(P->order.size(), sizeof(int)) + 256;
   std::vector<unsigned char> host(total, 0);
   auto put = [&](long long off, const void* src, size_t n) { if (n) std::memcpy(host.data() + off, src, n); };
   put(o_sd, P->sd.data(), P->sd.size() * sizeof(ShotDev));
@@ -327,6 +388,7 @@ awe_status upload_tables(awe_plan* P) {
   put(o_ie, P->inj_ent.data(), P->inj_ent.size() * sizeof(InjEntry));
   put(o_w, P->wins.data(), P->wins.size() * sizeof(WinDev));
   put(o_ws, P->win_shots.data(), P->win_shots.size() * sizeof(int));
+  put(o_or, P->order.data(), P->order.size() * sizeof(int));
   if (P->dev) {
     (void)hipFree(P->dev);
     P->dev = nullptr;
@@ -342,6 +404,7 @@ awe_status upload_tables(awe_plan* P) {
   P->tab.inj_ent = reinterpret_cast<const InjEntry*>(b + o_ie);
   P->tab.wins = reinterpret_cast<const WinDev*>(b + o_w);
   P->tab.win_shots = reinterpret_cast<const int*>(b + o_ws);
+  P->tab.order = reinterpret_cast<const int*>(b + o_or);
   return AWE_OK;
 }
 
@@ -403,9 +466,17 @@ struct ProfScope {
   }
 };
 
-awe_status step_fwd(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
+// Launch geometry of the current group at global step n.
+void set_group(const awe_plan* P, awe::StepArgs& a, int n) {
   a.step = n;
-  a.ntiles = P->active[n];
+  a.ntiles = P->g_active[P->cur][n];
+  a.tile_base = P->g_tile0[P->cur];
+  a.shot_base = P->g_shot0[P->cur];
+}
+
+awe_status step_fwd(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
+  set_group(P, a, n);
+  if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 0, s);
   if (P->ndim == 2) AWE_HIP(awe::launch_fwd2d(a, P->tz, store, s));
   else AWE_HIP(awe::launch_fwd3d(a, P->ty, P->bz, store, s));
@@ -413,30 +484,31 @@ awe_status step_fwd(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t
 }
 
 awe_status step_adj(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
-  a.step = n;
-  a.ntiles = P->active[n];
+  set_group(P, a, n);
+  if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 1, s);
   if (P->ndim == 2) {
     AWE_HIP(awe::launch_adj2d(a, P->tz, s));
   } else {
     AWE_HIP(awe::launch_adj3d(a, P->ty, P->bz, s));
-    AWE_HIP(awe::launch_inj3d(a, (int)P->inj_pts.size(), s));
+    AWE_HIP(awe::launch_inj3d(a, P->g_inj0[P->cur], P->g_ninj[P->cur], s));
   }
   return AWE_OK;
 }
 
 // Two levels per launch (2D): forward levels n, n+1; adjoint levels n, n-1.
 awe_status step_fwd2(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
+  set_group(P, a, n + 1);
   a.step = n;
-  a.ntiles = P->active[n + 1];
+  if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 0, s);
   AWE_HIP(awe::launch_fwd2d2(a, P->tz, store, s));
   return AWE_OK;
 }
 
 awe_status step_adj2(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
-  a.step = n;
-  a.ntiles = P->active[n];
+  set_group(P, a, n);
+  if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 1, s);
   AWE_HIP(awe::launch_adj2d2(a, P->tz, s));
   return AWE_OK;
@@ -479,12 +551,14 @@ awe_status adjoint_loop(awe_plan* P, awe::StepArgs& a, hipStream_t s) {
 }
 
 awe_status run_slot(awe_plan* P, awe::StepArgs& a, int slot, int state, int dir, hipStream_t s) {
+  const int g = P->cur, nsh = P->g_nshot[g];
+  a.shot_base = P->g_shot0[g];
   if (dir == 0 && P->store.prec != AWE_PREC_FP32) {
-    for (int i = 0; i < P->nshot; ++i)
-      AWE_HIP(awe::launch_fill(a.ws, P->sd[i].scale + 8LL * slot, 8, s));
-    AWE_HIP(awe::launch_absmax(a, P->nshot, slot, state, s));
+    for (int i = 0; i < nsh; ++i)
+      AWE_HIP(awe::launch_fill(a.ws, P->sd[P->order[a.shot_base + i]].scale + 8LL * slot, 8, s));
+    AWE_HIP(awe::launch_absmax(a, nsh, slot, state, s));
   }
-  AWE_HIP(awe::launch_slot(a, P->nshot, slot, state, dir, s));
+  AWE_HIP(awe::launch_slot(a, nsh, slot, state, dir, s));
   return AWE_OK;
 }
 
@@ -508,8 +582,10 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
       }
       case awe::kRestore:
         if (x < 0) {
-          for (int k = 0; k < P->nshot; ++k)
-            AWE_HIP(awe::launch_fill(fa.ws, P->sd[k].fld, 4 * P->sd[k].npts * 4, s));
+          for (int i = 0; i < P->g_nshot[P->cur]; ++i) {
+            const ShotDev& d = P->sd[P->order[P->g_shot0[P->cur] + i]];
+            AWE_HIP(awe::launch_fill(fa.ws, d.fld, 4 * d.npts * 4, s));
+          }
         } else {
           awe_status st = run_slot(P, fa, x, y, 1, s);
           if (st != AWE_OK) return st;
@@ -787,6 +863,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     const size_t saved = P->prof_ev.size();  // keep the probe out of kernel timing
     std::vector<hipEvent_t> keep_ev;
     keep_ev.swap(P->prof_ev);
+    P->cur = 0;  // the probe times the first shot group
     AWE_HIP(hipEventRecord(e0, s));
     const bool fuse = fused_ok(P);
     for (int n = 1; n <= probe; n += fuse ? 2 : 1)
@@ -796,8 +873,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
         if ((st = step_adj2(P, aa, n, s)) != AWE_OK) return st;
         continue;
       }
-      aa.step = n;
-      aa.ntiles = P->active[n];
+      set_group(P, aa, n);
       if (P->ndim == 2) AWE_HIP(awe::launch_adj2d(aa, P->tz, s));
       else AWE_HIP(awe::launch_adj3d(aa, P->ty, P->bz, s));
     }
@@ -843,6 +919,17 @@ awe_status awe_plan_set_tiles(awe_plan* P, int32_t tz, int32_t ty, int32_t bz) {
   awe_status st = build_tables(P, P->rec_pos.data());
   if (st != AWE_OK) return st;
   return upload_tables(P);
+}
+
+awe_status awe_plan_set_groups(awe_plan* P, int32_t ngroups, int32_t* actual) {
+  if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  if (ngroups < 0) return fail(AWE_ERR_INVALID_ARG, "ngroups must be >= 0");
+  P->groups_req = ngroups;
+  P->kept_ws = nullptr;
+  awe_status st = build_tables(P, P->rec_pos.data());
+  if (st == AWE_OK) st = upload_tables(P);
+  if (st == AWE_OK && actual) *actual = (int32_t)P->g_nshot.size();
+  return st;
 }
 
 awe_status awe_plan_set_fusion(awe_plan* P, int32_t two_steps) {
@@ -908,9 +995,11 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
   awe::StepArgs a = base_args(P, ws);
   a.q = q;
   a.d = d;
+  const int G = (int)P->g_nshot.size();
   if (store && P->store.mode == AWE_STORE_CHECKPOINT) {
     awe::StepArgs aa = a;
-    if ((st = run_actions(P, a, aa, 0, P->sched_first_reverse, s)) != AWE_OK) return st;
+    for (P->cur = 0; P->cur < G; ++P->cur)
+      if ((st = run_actions(P, a, aa, 0, P->sched_first_reverse, s)) != AWE_OK) return st;
   } else {
     int kind = awe::kStoreNone;
     if (store) {
@@ -920,7 +1009,8 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
         for (int i = 0; i < P->nshot; ++i)
           AWE_HIP(awe::launch_fill(a.ws, P->sd[i].scale, (long long)P->sd[i].nt * awe::kScaleSlots * 4, s));
     }
-    if ((st = forward_loop(P, a, kind, s)) != AWE_OK) return st;
+    for (P->cur = 0; P->cur < G; ++P->cur)
+      if ((st = forward_loop(P, a, kind, s)) != AWE_OK) return st;
     if (kind == awe::kStoreBF16 || kind == awe::kStoreFP16)
       AWE_HIP(awe::launch_store_last(a, P->nshot, P->max_win_npts, s));
   }
@@ -954,10 +1044,12 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
     aa.image_src = !g ? awe::kImgNone
                    : P->store.prec == AWE_PREC_FP32 ? awe::kImgFull32
                    : P->store.prec == AWE_PREC_BF16 ? awe::kImgFullBF16 : awe::kImgFullFP16;
-    if ((st = adjoint_loop(P, aa, s)) != AWE_OK) return st;
+    for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur)
+      if ((st = adjoint_loop(P, aa, s)) != AWE_OK) return st;
   } else {
     aa.image_src = g ? awe::kImgBuffers : awe::kImgNone;
-    if ((st = run_actions(P, fa, aa, P->sched_first_reverse, P->sched.size() / 3, s)) != AWE_OK) return st;
+    for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur)
+      if ((st = run_actions(P, fa, aa, P->sched_first_reverse, P->sched.size() / 3, s)) != AWE_OK) return st;
     P->kept_ws = nullptr;  // the recomputation overwrote the kept forward state
   }
   if (v) AWE_HIP(awe::launch_src_last(aa, P->nshot, s));
@@ -988,7 +1080,8 @@ awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, v
   a.dd = dd;
   a.v = v;
   a.image_src = awe::kImgNone;
-  if ((st = adjoint_loop(P, a, s)) != AWE_OK) return st;
+  for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur)
+    if ((st = adjoint_loop(P, a, s)) != AWE_OK) return st;
   AWE_HIP(awe::launch_src_last(a, P->nshot, s));
   return AWE_OK;
 }
@@ -1005,12 +1098,14 @@ awe_status awe_born(awe_plan* P, const float* m, const float* q, const float* dm
   a.q = q;
   a.dm = dm;
   a.d = dd;
-  for (int n = 1; n <= P->nsteps; ++n) {
-    a.step = n;
-    a.ntiles = P->active[n];
-    ProfScope ps(P, 2, s);
-    if (P->ndim == 2) AWE_HIP(awe::launch_born2d(a, P->tz, s));
-    else AWE_HIP(awe::launch_born3d(a, P->ty, P->bz, s));
+  for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur) {
+    for (int n = 1; n <= P->nsteps; ++n) {
+      set_group(P, a, n);
+      if (a.ntiles <= 0) continue;
+      ProfScope ps(P, 2, s);
+      if (P->ndim == 2) AWE_HIP(awe::launch_born2d(a, P->tz, s));
+      else AWE_HIP(awe::launch_born3d(a, P->ty, P->bz, s));
+    }
   }
   AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 1, s));
   return AWE_OK;

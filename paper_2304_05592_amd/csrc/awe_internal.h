@@ -106,6 +106,7 @@ struct Tables {
   const InjEntry* inj_ent;
   const WinDev* wins;
   const int* win_shots;
+  const int* order;          // shots sorted by time offset; a group is a contiguous range
 };
 
 // Arguments of one time-step launch.
@@ -119,7 +120,9 @@ struct StepArgs {
   const float* dm;           // model perturbation (born)
   int ndim;
   int step;                  // global index of the state being produced
-  int ntiles;                // tiles in this launch (active prefix of the tile list)
+  int ntiles;                // tiles in this launch (active prefix of the group's tiles)
+  int tile_base;             // first tile of the shot group this launch covers
+  int shot_base;             // first position in t.order of the group (per-shot kernels)
   int nbl;
   int store_prec;            // Prec of the kept wavefield (FULL store / checkpoint slots)
   int image_src;             // adjoint imaging source, see ImageSrc
@@ -144,7 +147,8 @@ hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_fwd3d(const StepArgs& a, int ty, int bz, int store, hipStream_t stream);
 hipError_t launch_adj3d(const StepArgs& a, int ty, int bz, hipStream_t stream);
 hipError_t launch_born3d(const StepArgs& a, int ty, int bz, hipStream_t stream);
-hipError_t launch_inj3d(const StepArgs& a, int ninj, hipStream_t stream);
+// Receiver injection over the touched points [first, first + count) (one shot group).
+hipError_t launch_inj3d(const StepArgs& a, int first, int count, hipStream_t stream);
 // Gather the last sample d^{nt-1} of every shot from the forward (adj = 0) or the
 // perturbation (adj = 1, Born) buffers.
 hipError_t launch_gather_last(const StepArgs& a, int nshot, int total_recs, int adj, hipStream_t stream);

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
   constexpr int RPT = T2<TZ>::RPT;
   __shared__ float L[T2<TZ>::H][T2<TZ>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
   __shared__ float L[T2<TZ>::H][T2<TZ>::W];
   __shared__ float INJ[TZ][kTX];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
     }
     __syncthreads();
   }
-  if (a.v != nullptr && tid == S.src_tile && threadIdx.x == 0)
+  if (a.v != nullptr && a.tile_base + tid == S.src_tile && threadIdx.x == 0)
     a.v[S.q + j] = interp_lds<TZ>(L, S.src_i, S.src_k, T.x0, T.z0, S.src_w);
 
   const int dx = border_dist(x, nx, a.nbl);
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
   __shared__ float LU[T2<TZ>::H][T2<TZ>::W];
   __shared__ float LD[T2<TZ>::H][T2<TZ>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
   __shared__ float L1[G::H1][G::W1];
   __shared__ float LE[G::HE][G::WE];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   const bool act1 = k >= 1 && k <= S.nt - 1;
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
   __shared__ float INJ2[TZ][kTX];
   __shared__ float INC1[TZ][kTX];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int j = a.step - S.off;
   const bool act1 = j >= 1 && j <= S.nt - 1;
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
     }
     __syncthreads();
   }
-  if (act1 && a.v != nullptr && tid == S.src_tile && threadIdx.x == 0) {
+  if (act1 && a.v != nullptr && a.tile_base + tid == S.src_tile && threadIdx.x == 0) {
     const int C = S.src_i - T.x0 + 2 * kHalo, R = S.src_k - T.z0 + 2 * kHalo;
     a.v[S.q + j] = S.src_w[0] * L1[R][C] + S.src_w[1] * L1[R][C + 1] + S.src_w[2] * L1[R + 1][C] +
                    S.src_w[3] * L1[R + 1][C + 1];
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
   }
   __syncthreads();
 
-  if (act2 && a.v != nullptr && tid == S.src_tile && threadIdx.x == 0) {
+  if (act2 && a.v != nullptr && a.tile_base + tid == S.src_tile && threadIdx.x == 0) {
     const int C = S.src_i - T.x0 + kHalo, R = S.src_k - T.z0 + kHalo;
     a.v[S.q + j - 1] = S.src_w[0] * LE[R][C] + S.src_w[1] * LE[R][C + 1] + S.src_w[2] * LE[R + 1][C] +
                        S.src_w[3] * LE[R + 1][C + 1];

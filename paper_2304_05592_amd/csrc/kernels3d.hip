@@ -38,11 +38,14 @@ __device__ __forceinline__ float interp8(const float* f, const ShotDev& S, int i
          w[7] * f[p + pxy + px + 1];
 }
 
+// Column block 64 x TY: 4 waves up to TY = 8, 8 waves for TY = 16 (two y-rows per thread).
 template <int TY>
 struct T3 {
-  static constexpr int W = kTX + 2 * kHalo;  // 72
+  static constexpr int NW = TY >= 16 ? 8 : 4;  // waves per workgroup
+  static constexpr int NT = 64 * NW;           // threads per workgroup
+  static constexpr int W = kTX + 2 * kHalo;    // 72
   static constexpr int H = TY + 2 * kHalo;
-  static constexpr int NC = TY / 4;          // y-rows per thread
+  static constexpr int NC = TY / NW;           // y-rows per thread
 };
 
 // Halo ring of one plane: rows y0-4..y0+TY+3 x columns x0-4..x0+67 minus the 64 x TY
@@ -52,7 +55,7 @@ template <int TY>
 struct Ring {
   static constexpr int W = T3<TY>::W;
   static constexpr int COUNT = 8 * W + TY * 8;
-  static constexpr int PER = (COUNT + kThreads - 1) / kThreads;
+  static constexpr int PER = (COUNT + T3<TY>::NT - 1) / T3<TY>::NT;
 };
 
 template <int TY>
@@ -77,7 +80,7 @@ __device__ __forceinline__ void ring_fetch(float (&h)[Ring<TY>::PER], const floa
   const long long zb = (long long)z * ny;
 #pragma unroll
   for (int i = 0; i < Ring<TY>::PER; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * T3<TY>::NT;
     float v = 0.f;
     if (e < Ring<TY>::COUNT && zin) {
       int r, c;
@@ -93,7 +96,7 @@ template <int TY>
 __device__ __forceinline__ void ring_store(float (*P)[T3<TY>::W], const float (&h)[Ring<TY>::PER]) {
 #pragma unroll
   for (int i = 0; i < Ring<TY>::PER; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * T3<TY>::NT;
     if (e < Ring<TY>::COUNT) {
       int r, c;
       ring_pos<TY>(e, &r, &c);
@@ -125,15 +128,15 @@ __device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny
 
 // ------------------------------------------------------------------------------ forward
 // Software-pipelined z-march: after the barrier of plane z each thread issues the global
-// loads of plane z+1 (halo ring, next queue value, u^{k-2}, coef), updates plane z from LDS
-// buffer b and its register queue, then writes plane z+1 into buffer 1-b (every wave has
-// passed the barrier, so nobody still reads the plane z-1 it held).
+// loads of plane z+2 (halo ring, next queue value, u^{k-2}, coef), updates plane z from LDS
+// buffer b and its register queue, then writes plane z+1 (loaded one plane earlier) into
+// buffer 1-b.
 template <int TY, int SK>
-__global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) {
+__global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen) {
   constexpr int NC = T3<TY>::NC, HP = Ring<TY>::PER;
   __shared__ float P[2][T3<TY>::H][T3<TY>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
   const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
 
   if (a.d != nullptr) {
-    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+    for (int t = threadIdx.x; t < T.gat_count; t += T3<TY>::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
       a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp8(u1, S, R.i, R.j, R.k, R.w);
     }
@@ -160,7 +163,11 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
   const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
   float lmax = 0.f;
 
+  // Register state of plane z: queue Q (u^{k-1} at z-4..z+4), u^{k-2} and coef.  Set A holds
+  // the loads of plane z+1 (issued one plane earlier), set B those of plane z+2 (issued right
+  // after the barrier of plane z): two planes of loads are in flight while plane z is updated.
   float Q[NC][9], pu2[NC], pcf[NC];
+  float hA[HP] = {}, qA[NC] = {}, u2A[NC] = {}, cfA[NC] = {};
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
@@ -176,20 +183,34 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
   }
+  if (T.z0 + 1 < zend) {
+    ring_fetch<TY>(hA, u1, nx, ny, nz, px, T.x0, T.y0, T.z0 + 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int y = T.y0 + g * NC + c;
+      qA[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, T.z0 + 1 + kHalo);
+      u2A[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, T.z0 + 1);
+      cfA[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0 + 1);
+    }
+  }
   for (int z = T.z0; z < zend; ++z) {
     const int b = (z - T.z0) & 1;
     __syncthreads();
-    const bool more = z + 1 < zend;
-    float h[HP], qn[NC], nu2[NC], ncf[NC];
-    if (more) {
-      ring_fetch<TY>(h, u1, nx, ny, nz, px, T.x0, T.y0, z + 1);
+    float hB[HP], qB[NC], u2B[NC], cfB[NC];
+    if (z + 2 < zend) {
+      ring_fetch<TY>(hB, u1, nx, ny, nz, px, T.x0, T.y0, z + 2);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int y = T.y0 + g * NC + c;
-        qn[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, z + 1 + kHalo);
-        nu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, z + 1);
-        ncf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 1);
+        qB[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, z + 2 + kHalo);
+        u2B[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, z + 2);
+        cfB[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 2);
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < HP; ++i) hB[i] = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) qB[c] = u2B[c] = cfB[c] = 0.f;
     }
     const int dz = border_dist(z, nz, a.nbl);
 #pragma unroll
@@ -216,17 +237,24 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
         }
       }
     }
-    if (more) {
+    if (z + 1 < zend) {
+      // plane z+1 into the other LDS buffer (every wave has passed the barrier of plane z, so
+      // nobody still reads the plane z-1 it held); advance the register state
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         P[1 - b][g * NC + c + kHalo][lane + kHalo] = Q[c][5];
 #pragma unroll
         for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
-        Q[c][8] = qn[c];
-        pu2[c] = nu2[c];
-        pcf[c] = ncf[c];
+        Q[c][8] = qA[c];
+        pu2[c] = u2A[c];
+        pcf[c] = cfA[c];
+        qA[c] = qB[c];
+        u2A[c] = u2B[c];
+        cfA[c] = cfB[c];
       }
-      ring_store<TY>(P[1 - b], h);
+      ring_store<TY>(P[1 - b], hA);
+#pragma unroll
+      for (int i = 0; i < HP; ++i) hA[i] = hB[i];
     }
   }
   if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
@@ -234,11 +262,11 @@ __global__ __launch_bounds__(kThreads) void fwd3d_kernel(StepArgs a, int bzlen) 
 
 // ------------------------------------------------------------------------------ adjoint
 template <int TY, int IMG>
-__global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) {
+__global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen) {
   constexpr int NC = T3<TY>::NC, HP = Ring<TY>::PER;
   __shared__ float P[2][T3<TY>::H][T3<TY>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
@@ -261,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
   const int x = T.x0 + lane;
   const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
 
-  if (a.v != nullptr && tid == S.src_tile && threadIdx.x == 0)
+  if (a.v != nullptr && a.tile_base + tid == S.src_tile && threadIdx.x == 0)
     a.v[S.q + j] = interp8(w1, S, S.src_i, S.src_j, S.src_k, S.src_w);
   const int dx = border_dist(x, nx, a.nbl);
 
@@ -275,8 +303,12 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
     if (IMG) *ac = in ? acc[p] : 0.0;
   };
 
+  // Register state of plane z (queue of w^{j+1}, w^{j+2}, coef, u^j, accumulator); set A holds
+  // plane z+1, set B plane z+2 (loads issued right after the barrier of plane z).
   float Q[NC][9], pw2[NC], pcf[NC], pu[NC];
   double pacc[NC];
+  float hA[HP] = {}, qA[NC] = {}, w2A[NC] = {}, cfA[NC] = {}, uA[NC] = {};
+  double accA[NC] = {};
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
@@ -295,24 +327,42 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
   }
+  if (T.z0 + 1 < zend) {
+    ring_fetch<TY>(hA, w1, nx, ny, nz, px, T.x0, T.y0, T.z0 + 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int y = T.y0 + g * NC + c;
+      qA[c] = ldc<TY>(w1, nx, ny, nz, px, x, y, T.z0 + 1 + kHalo);
+      w2A[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, T.z0 + 1);
+      cfA[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0 + 1);
+      load_img(y, T.z0 + 1, &uA[c], &accA[c]);
+    }
+  }
   for (int z = T.z0; z < zend; ++z) {
     const int b = (z - T.z0) & 1;
     __syncthreads();
-    const bool more = z + 1 < zend;
-    float h[HP], qn[NC], nw2[NC], ncf[NC], nu[NC];
-    double nacc[NC];
-    if (more) {
-      ring_fetch<TY>(h, w1, nx, ny, nz, px, T.x0, T.y0, z + 1);
+    float hB[HP], qB[NC], w2B[NC], cfB[NC], uB[NC];
+    double accB[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      uB[c] = 0.f;
+      accB[c] = 0.0;
+    }
+    if (z + 2 < zend) {
+      ring_fetch<TY>(hB, w1, nx, ny, nz, px, T.x0, T.y0, z + 2);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int y = T.y0 + g * NC + c;
-        qn[c] = ldc<TY>(w1, nx, ny, nz, px, x, y, z + 1 + kHalo);
-        nw2[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, z + 1);
-        ncf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 1);
-        nu[c] = 0.f;
-        nacc[c] = 0.0;
-        load_img(y, z + 1, &nu[c], &nacc[c]);
+        qB[c] = ldc<TY>(w1, nx, ny, nz, px, x, y, z + 2 + kHalo);
+        w2B[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, z + 2);
+        cfB[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 2);
+        load_img(y, z + 2, &uB[c], &accB[c]);
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < HP; ++i) hB[i] = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) qB[c] = w2B[c] = cfB[c] = 0.f;
     }
     const int dz = border_dist(z, nz, a.nbl);
 #pragma unroll
@@ -330,28 +380,36 @@ __global__ __launch_bounds__(kThreads) void adj3d_kernel(StepArgs a, int bzlen) 
         if (IMG) acc[p] = pacc[c] + (double)pu[c] * (double)incr;
       }
     }
-    if (more) {
+    if (z + 1 < zend) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         P[1 - b][g * NC + c + kHalo][lane + kHalo] = Q[c][5];
 #pragma unroll
         for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
-        Q[c][8] = qn[c];
-        pw2[c] = nw2[c];
-        pcf[c] = ncf[c];
-        pu[c] = nu[c];
-        pacc[c] = nacc[c];
+        Q[c][8] = qA[c];
+        pw2[c] = w2A[c];
+        pcf[c] = cfA[c];
+        pu[c] = uA[c];
+        pacc[c] = accA[c];
+        qA[c] = qB[c];
+        w2A[c] = w2B[c];
+        cfA[c] = cfB[c];
+        uA[c] = uB[c];
+        accA[c] = accB[c];
       }
-      ring_store<TY>(P[1 - b], h);
+      ring_store<TY>(P[1 - b], hA);
+#pragma unroll
+      for (int i = 0; i < HP; ++i) hA[i] = hB[i];
     }
   }
 }
 
 // Receiver injection after the adjoint step: w^j += coef P_r^T dd^j at the touched points
 // (and the matching imaging term).  One thread per touched point, entries in fixed order.
-__global__ void inj3d_kernel(StepArgs a, int ninj) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ninj) return;
+__global__ void inj3d_kernel(StepArgs a, int first, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int t = first + i;
   const InjPoint Pt = a.t.inj_pts[t];
   const ShotDev& S = a.t.shots[Pt.shot];
   const int j = a.step - S.off;
@@ -382,12 +440,12 @@ __global__ void inj3d_kernel(StepArgs a, int ninj) {
 
 // ------------------------------------------------------------------------------ Born
 template <int TY>
-__global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen) {
+__global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzlen) {
   constexpr int NC = T3<TY>::NC, HP = Ring<TY>::PER;
   __shared__ float PU[2][T3<TY>::H][T3<TY>::W];
   __shared__ float PD[2][T3<TY>::H][T3<TY>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
-  const TileDev T = a.t.tiles[tid];
+  const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
@@ -405,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
   const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
 
   if (a.d != nullptr) {
-    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+    for (int t = threadIdx.x; t < T.gat_count; t += T3<TY>::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
       a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp8(d1, S, R.i, R.j, R.k, R.w);
     }
@@ -506,10 +564,10 @@ __global__ __launch_bounds__(kThreads) void born3d_kernel(StepArgs a, int bzlen)
 template <int TY>
 hipError_t fwd3d_ty(const StepArgs& a, int bz, int store, hipStream_t s) {
   switch (store) {
-    case kStoreNone: fwd3d_kernel<TY, kStoreNone><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case kStoreF32: fwd3d_kernel<TY, kStoreF32><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case kStoreBF16: fwd3d_kernel<TY, kStoreBF16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case kStoreFP16: fwd3d_kernel<TY, kStoreFP16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kStoreNone: fwd3d_kernel<TY, kStoreNone><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kStoreF32: fwd3d_kernel<TY, kStoreF32><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kStoreBF16: fwd3d_kernel<TY, kStoreBF16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kStoreFP16: fwd3d_kernel<TY, kStoreFP16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -518,11 +576,11 @@ hipError_t fwd3d_ty(const StepArgs& a, int bz, int store, hipStream_t s) {
 template <int TY>
 hipError_t adj3d_ty(const StepArgs& a, int bz, hipStream_t s) {
   switch (a.image_src) {
-    case kImgNone: adj3d_kernel<TY, kImgNone><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case kImgFull32: adj3d_kernel<TY, kImgFull32><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case kImgBuffers: adj3d_kernel<TY, kImgBuffers><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case kImgFullBF16: adj3d_kernel<TY, kImgFullBF16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
-    case kImgFullFP16: adj3d_kernel<TY, kImgFullFP16><<<a.ntiles, kThreads, 0, s>>>(a, bz); break;
+    case kImgNone: adj3d_kernel<TY, kImgNone><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kImgFull32: adj3d_kernel<TY, kImgFull32><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kImgBuffers: adj3d_kernel<TY, kImgBuffers><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kImgFullBF16: adj3d_kernel<TY, kImgFullBF16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kImgFullFP16: adj3d_kernel<TY, kImgFullFP16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -556,17 +614,17 @@ hipError_t launch_adj3d(const StepArgs& a, int ty, int bz, hipStream_t s) {
 hipError_t launch_born3d(const StepArgs& a, int ty, int bz, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   switch (ty) {
-    case 4: born3d_kernel<4><<<a.ntiles, kThreads, 0, s>>>(a, zlen(bz)); break;
-    case 8: born3d_kernel<8><<<a.ntiles, kThreads, 0, s>>>(a, zlen(bz)); break;
-    case 16: born3d_kernel<16><<<a.ntiles, kThreads, 0, s>>>(a, zlen(bz)); break;
+    case 4: born3d_kernel<4><<<a.ntiles, T3<4>::NT, 0, s>>>(a, zlen(bz)); break;
+    case 8: born3d_kernel<8><<<a.ntiles, T3<8>::NT, 0, s>>>(a, zlen(bz)); break;
+    case 16: born3d_kernel<16><<<a.ntiles, T3<16>::NT, 0, s>>>(a, zlen(bz)); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_inj3d(const StepArgs& a, int ninj, hipStream_t s) {
-  if (ninj <= 0 || a.dd == nullptr) return hipSuccess;
-  inj3d_kernel<<<(ninj + kThreads - 1) / kThreads, kThreads, 0, s>>>(a, ninj);
+hipError_t launch_inj3d(const StepArgs& a, int first, int count, hipStream_t s) {
+  if (count <= 0 || a.dd == nullptr) return hipSuccess;  // no residual: nothing to inject
+  inj3d_kernel<<<(count + kThreads - 1) / kThreads, kThreads, 0, s>>>(a, first, count);
   return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ __global__ void src_last_kernel(StepArgs a, int nshot) {
 // Max |u| of the two fields of a state into scale[slot][0..1] (atomic max on the float bits
 // of non-negative values, which is exact and order independent).
 __global__ void absmax_kernel(StepArgs a, int slot, int state) {
-  const ShotDev& S = a.t.shots[blockIdx.y];
+  const ShotDev& S = a.t.shots[a.t.order[a.shot_base + blockIdx.y]];
   const int ls = state - S.off;
   const float* f = fbuf(a.ws, S, fwd_buf(ls - (int)blockIdx.z));
   float mx = 0.f;
@@ -95,10 +95,10 @@ __global__ void absmax_kernel(StepArgs a, int slot, int state) {
   }
 }
 
-// dir 0: slot <- (u^state, u^{state-1}); dir 1: fields <- slot.  blockIdx.y = shot,
-// blockIdx.z = which of the two fields.
+// dir 0: slot <- (u^state, u^{state-1}); dir 1: fields <- slot.  blockIdx.y = shot of the
+// group (position shot_base + blockIdx.y in t.order), blockIdx.z = which of the two fields.
 __global__ void slot_kernel(StepArgs a, int slot, int state, int dir) {
-  const ShotDev& S = a.t.shots[blockIdx.y];
+  const ShotDev& S = a.t.shots[a.t.order[a.shot_base + blockIdx.y]];
   const int fz = blockIdx.z;
   const int ls = state - S.off;
   float* f = fbuf(a.ws, S, fwd_buf(ls - fz));

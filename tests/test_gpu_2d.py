@@ -292,3 +292,29 @@ def test_two_levels_per_launch_is_bitwise_the_one_level_path(tz):
     for a, b in zip(outs[0], outs[1]):
         assert torch.equal(a, b)
     assert rel_l2(plan.unpack(outs[0][1], "q"), oracle_adjoint(wl, dds)) <= TOL
+
+
+@pytest.mark.parametrize("storage", [A.Storage(A.STORE_FULL), A.Storage(A.STORE_CHECKPOINT, 3),
+                                     A.Storage(A.STORE_FULL, 0, A.PREC_BF16)],
+                         ids=["full32", "checkpoint3", "fullbf16"])
+def test_shot_groups_do_not_change_results(storage):
+    """Running the shots in groups (one time loop per group) gives bitwise the same traces,
+    F^T dd, gradient, adjoint-only and Born results as one group, on uneven windows with
+    per-shot nt (groups of one, two and three shots)."""
+    wl = W.small_2d(windows=[90, 70, 113, 64], T_per_shot=[400.0, 250.0, 331.0, 290.0])
+    dds = _residuals(wl)
+    dms = [W.random_field(wl.comp_shape(w), 17 + w, 2.0) * 0.01 for w in range(wl.nwindow)]
+    outs = []
+    for ng in (1, 2, 3, 4):
+        plan = make_plan(wl, storage=storage)
+        assert plan.set_groups(ng) == ng
+        m, q = gpu_inputs(wl, plan)
+        dd = plan.pack(dds, "d")
+        g, v, d = plan.gradient(m, q, dd, v=True, d=True)
+        va = plan.adjoint(m, dd)
+        b = plan.born(m, q, plan.pack(dms, "m"))
+        _sync()
+        outs.append([t.cpu() for t in (g, v, d, va, b)])
+    for o in outs[1:]:
+        assert all(torch.equal(a, b) for a, b in zip(o, outs[0]))
+    assert rel_l2(plan.unpack(outs[0][2], "d"), oracle_forward(wl)) <= TOL

@@ -107,3 +107,17 @@ def test_3d_results_do_not_depend_on_the_tile_shape_and_autotune_keeps_them():
     print(f"autotuned 3D tiles {choice} ({ms:.3f} ms probe)", flush=True)
     for o in outs[1:] + [(g, v, d)]:
         assert all(torch.equal(a, b) for a, b in zip(o, outs[0]))
+
+
+def test_3d_shot_groups_do_not_change_results():
+    wl = W.small_3d(nshot=3, T=200.0)
+    dds = _residuals(wl)
+    outs = []
+    for ng in (1, 3):
+        plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+        assert plan.set_groups(ng) == ng
+        m, q = gpu_inputs(wl, plan)
+        g, v, d = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+        torch.cuda.synchronize()
+        outs.append([t.cpu() for t in (g, v, d)])
+    assert all(torch.equal(a, b) for a, b in zip(outs[1], outs[0]))
