@@ -218,6 +218,8 @@ class GradientRunner:
             self.tiles = dict(tiles)
         elif autotune:
             self.tiles, _ = p.autotune(self.m0, self.q, self.d_obs, probe_steps=32, ws=self.ws)
+        self.groups = p.set_groups(0)   # shot groups in effect (automatic)
+        self.launch_points //= self.groups
         self.graph = None
         sync()
 
@@ -368,7 +370,7 @@ def bench_c2(args):
     path_bytes = ((BYTES[("forward2", "fp32")] + BYTES[("adjoint2", "fp32")]) * run.points // 2 if fused
                   else (BYTES[("forward", "fp32")] + BYTES[("adjoint", "fp32")]) * run.points)
     loss = float(run.loss.item())
-    tiles, points = run.tiles, run.points
+    tiles, points, groups = run.tiles, run.points, run.groups
     run.release()
     single = None
     if not args.no_single:
@@ -382,7 +384,7 @@ def bench_c2(args):
     return base_line(args, wl, value, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "FULL FP32",
-                   "batched": True, "graph": use_graph, "tiles": tiles},
+                   "batched": True, "graph": use_graph, "tiles": tiles, "shot_groups": groups},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels, "kernel_timing": timing,
         "path_hbm_fraction": round(path_bytes / sec / 1e9 / PEAK_HBM_GBS, 4),
         "eager": {"value": round(points / eager_sec / 1e9, 3), "ms_per_step": round(eager_sec * 1e3, 3)},
@@ -401,7 +403,9 @@ def bench_c3(args):
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     d_obs = plan.forward(m_true, q)
     tiles = choose_tiles(plan, args, m0, q, d_obs)
+    groups = plan.set_groups(0)   # shot groups in effect (automatic); the 32 shots split evenly
     points, launch_points = points_of(wl, range(wl.nshot))
+    launch_points //= groups
 
     def step():
         m = m0.clone().requires_grad_(True)
@@ -427,7 +431,7 @@ def bench_c3(args):
     return base_line(args, wl, points / sec / 1e9, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "CHECKPOINT 16 FP32 slots",
-                   "batched": True, "graph": False, "tiles": tiles},
+                   "batched": True, "graph": False, "tiles": tiles, "shot_groups": groups},
         "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
         "forward_steps_per_gradient": fwd_steps,
         "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item())})
@@ -445,6 +449,7 @@ def bench_c4(args):
     ws = plan.workspace()
     d = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
     tiles = choose_tiles(plan, args, m, q, None, ws)
+    groups = plan.set_groups(0)
     points, launch_points = points_of(wl, range(wl.nshot))
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -495,7 +500,7 @@ def bench_c4(args):
         "metric": "Gpts/s forward, uneven batching (64 windows) batched vs sequential single-shot",
         "config": {"workload": f"{wl.name}: {wl.description}", "shots": wl.nshot,
                    "points_per_pass": points, "storage": "none (forward)", "batched": True,
-                   "graph": True, "tiles": tiles},
+                   "graph": True, "tiles": tiles, "shot_groups": groups},
         "roofline": {"bound": "hbm", "achieved": None if ach is None else round(ach, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": None if ach is None else round(ach / PEAK_HBM_GBS, 4), "traffic": None,

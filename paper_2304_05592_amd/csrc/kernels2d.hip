@@ -127,10 +127,12 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
     const int z = T.z0 + wv * RPT + i;
     const long long p = (long long)z * px + x;
     const bool in = x < nx && z < nz;
-    pu2[i] = in ? u2[p] : 0.f;
+    pu2[i] = in && k >= 3 ? u2[p] : 0.f;
     pcf[i] = in ? cf[p] : 0.f;
   }
-  load_tile<TZ>(L, u1, nx, nz, px, T.x0, T.z0);
+  // levels below 1 are zero (initial state); their buffers may hold older levels after a
+  // checkpoint restore of a state before this shot's start, so they are not read
+  load_tile<TZ>(L, u1, nx, k >= 2 ? nz : 0, px, T.x0, T.z0);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
     const bool in = e < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
     const long long p = (long long)z * px + x;
-    pm2[i] = in ? u2[p] : 0.f;
+    pm2[i] = in && k >= 3 ? u2[p] : 0.f;  // levels below 1 are zero (see fwd2d_kernel)
     pcf[i] = in ? cf[p] : 0.f;
   }
   {
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
       tcf[i] = x < nx && z < nz ? cf[(long long)z * px + x] : 0.f;
     }
   }
-  load_tile8<TZ>(L1, u1, nx, nz, px, T.x0, T.z0);
+  load_tile8<TZ>(L1, u1, nx, k >= 2 ? nz : 0, px, T.x0, T.z0);
   __syncthreads();
 
   if (act1 && a.d != nullptr) {

@@ -141,6 +141,9 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, ny = S.ny, nz = S.nz, px = S.px;
+  // levels below 1 are zero (initial state) and are not read: after a checkpoint restore of a
+  // state before this shot's start their buffers may hold older levels
+  const int nz1 = k >= 2 ? nz : 0, nz2 = k >= 3 ? nz : 0;
   const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
   const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
   float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   if (a.d != nullptr) {
     for (int t = threadIdx.x; t < T.gat_count; t += T3<TY>::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
-      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp8(u1, S, R.i, R.j, R.k, R.w);
+      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = k >= 2 ? interp8(u1, S, R.i, R.j, R.k, R.w) : 0.f;
     }
   }
   const float qk = a.q[S.q + k - 1];
@@ -172,24 +175,24 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
-    pu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, T.z0);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz1, px, x, y, T.z0 - kHalo + t);
+    pu2[c] = ldc<TY>(u2, nx, ny, nz2, px, x, y, T.z0);
     pcf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0);
   }
   {
     float h[HP];
-    ring_fetch<TY>(h, u1, nx, ny, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(h, u1, nx, ny, nz1, px, T.x0, T.y0, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
   }
   if (T.z0 + 1 < zend) {
-    ring_fetch<TY>(hA, u1, nx, ny, nz, px, T.x0, T.y0, T.z0 + 1);
+    ring_fetch<TY>(hA, u1, nx, ny, nz1, px, T.x0, T.y0, T.z0 + 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int y = T.y0 + g * NC + c;
-      qA[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, T.z0 + 1 + kHalo);
-      u2A[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, T.z0 + 1);
+      qA[c] = ldc<TY>(u1, nx, ny, nz1, px, x, y, T.z0 + 1 + kHalo);
+      u2A[c] = ldc<TY>(u2, nx, ny, nz2, px, x, y, T.z0 + 1);
       cfA[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0 + 1);
     }
   }
@@ -198,12 +201,12 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
     __syncthreads();
     float hB[HP], qB[NC], u2B[NC], cfB[NC];
     if (z + 2 < zend) {
-      ring_fetch<TY>(hB, u1, nx, ny, nz, px, T.x0, T.y0, z + 2);
+      ring_fetch<TY>(hB, u1, nx, ny, nz1, px, T.x0, T.y0, z + 2);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int y = T.y0 + g * NC + c;
-        qB[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, z + 2 + kHalo);
-        u2B[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, z + 2);
+        qB[c] = ldc<TY>(u1, nx, ny, nz1, px, x, y, z + 2 + kHalo);
+        u2B[c] = ldc<TY>(u2, nx, ny, nz2, px, x, y, z + 2);
         cfB[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 2);
       }
     } else {

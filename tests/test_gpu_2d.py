@@ -318,3 +318,21 @@ def test_shot_groups_do_not_change_results(storage):
     for o in outs[1:]:
         assert all(torch.equal(a, b) for a, b in zip(o, outs[0]))
     assert rel_l2(plan.unpack(outs[0][2], "d"), oracle_forward(wl)) <= TOL
+
+
+def test_checkpointed_gradient_with_uneven_nt_is_bitwise_the_full_storage_gradient():
+    """Regression: shots of different nt start at different global steps; a checkpoint restore
+    of a state before a shot's start left older levels in that shot's buffers, which its first
+    steps then read.  Levels below 1 are zero by definition and are no longer read."""
+    wl = W.small_2d(windows=[90, 70, 113, 64], T_per_shot=[600.0, 180.0, 400.0, 290.0])
+    dds = _residuals(wl)
+    out = []
+    for st in (A.Storage(A.STORE_FULL), A.Storage(A.STORE_CHECKPOINT, 3), A.Storage(A.STORE_CHECKPOINT, 16)):
+        plan = make_plan(wl, storage=st)
+        m, q = gpu_inputs(wl, plan, background=True)
+        g, v, _ = plan.gradient(m, q, plan.pack(dds, "d"), v=True)
+        _sync()
+        out.append((g.cpu(), v.cpu()))
+    for g, v in out[1:]:
+        assert torch.equal(g, out[0][0])
+        assert torch.equal(v, out[0][1])
