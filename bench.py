@@ -270,7 +270,7 @@ class GradientRunner:
         sync()
         if profile and not use_graph:
             nt = max(self.wl.shots[i].nt for i in self.shots)
-            self.plan.profile_enable(2 * nt * steps + 64, 1)
+            self.plan.profile_enable(2 * nt * steps * self.groups + 64, 1)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)] \
             if profile and use_graph else None
         sync()
@@ -471,7 +471,7 @@ def bench_c4(args):
     sync()
     sec = (time.perf_counter() - t0) / args.steps
     # kernel durations: one eager pass with HIP events around every launch
-    plan.profile_enable(nt_max + 64, 1)
+    plan.profile_enable(groups * nt_max + 64, 1)   # one launch per step and shot group
     plan.forward(m, q, d=d, ws=ws)
     prof = plan.profile_read()
     plan.profile_disable()
