@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI that need no GPU: exported symbols, argument validation,
 and the binomial checkpoint schedule."""
 import math
+import os
 import re
 from functools import lru_cache
 
@@ -144,3 +145,13 @@ def test_checkpoint_schedule_large_counts_binomial_cost():
     acts = A.checkpoint_schedule(5000, 16)
     steps = _simulate(5000, 16, acts)
     assert 3 * 5000 < steps < 5 * 5000
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
