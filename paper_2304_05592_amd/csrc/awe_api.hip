@@ -75,6 +75,8 @@ struct awe_plan {
   std::vector<std::vector<int>> g_active;
   int groups_req = 0;             // 0: automatic
   int cur = 0;                    // group of the launches being issued
+  // per group: the state restored by reference (FP32 slots) when its actions stopped
+  std::vector<int> g_rs_level, g_rs_slot;
   std::vector<RecDev> recs;
   std::vector<InjPoint> inj_pts;
   std::vector<InjPoint> ext_pts;
@@ -418,6 +420,8 @@ awe::StepArgs base_args(const awe_plan* P, void* ws) {
   for (int i = 0; i < 5; ++i) a.c[i] = P->c[i];
   a.eta_dt = P->eta_dt;
   a.inv_dt2 = (float)(1.0 / (P->dt * P->dt));
+  a.rs_level = awe::kNoLevel;
+  a.rs_slot = 0;
   return a;
 }
 
@@ -566,6 +570,18 @@ awe_status run_slot(awe_plan* P, awe::StepArgs& a, int slot, int state, int dir,
 // sampled; REVERSE runs the adjoint step with imaging from the forward buffers.
 awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t begin, size_t end,
                        hipStream_t s) {
+  const int g = P->cur;
+  if (P->g_rs_level.size() != P->g_nshot.size()) {
+    P->g_rs_level.assign(P->g_nshot.size(), awe::kNoLevel);
+    P->g_rs_slot.assign(P->g_nshot.size(), 0);
+  }
+  if (begin == 0) P->g_rs_level[g] = awe::kNoLevel;  // a new forward sweep of this group
+  auto set_rs = [&](int level, int slot) {
+    fa.rs_level = aa.rs_level = level;
+    fa.rs_slot = aa.rs_slot = slot;
+  };
+  set_rs(P->g_rs_level[g], P->g_rs_slot[g]);
+  const bool by_ref = P->store.prec == AWE_PREC_FP32;
   for (size_t i = begin; i < end; ++i) {
     const int op = P->sched[3 * i], x = P->sched[3 * i + 1], y = P->sched[3 * i + 2];
     switch (op) {
@@ -576,6 +592,15 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
         }
         break;
       case awe::kStore: {
+        if (fa.rs_level != awe::kNoLevel && fa.rs_slot == x) {
+          // overwriting the slot that is read by reference: copy its state into the
+          // buffers first
+          awe::StepArgs ca = fa;
+          ca.rs_level = awe::kNoLevel;
+          awe_status st = run_slot(P, ca, x, fa.rs_level, 1, s);
+          if (st != AWE_OK) return st;
+          set_rs(awe::kNoLevel, 0);
+        }
         awe_status st = run_slot(P, fa, x, y, 0, s);
         if (st != AWE_OK) return st;
         break;
@@ -586,7 +611,11 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
             const ShotDev& d = P->sd[P->order[P->g_shot0[P->cur] + i]];
             AWE_HIP(awe::launch_fill(fa.ws, d.fld, 4 * d.npts * 4, s));
           }
+          set_rs(awe::kNoLevel, 0);
+        } else if (by_ref) {
+          set_rs(y, x);  // FP32 slot: levels y and y - 1 are read from the slot in place
         } else {
+          set_rs(awe::kNoLevel, 0);
           awe_status st = run_slot(P, fa, x, y, 1, s);
           if (st != AWE_OK) return st;
         }
@@ -598,6 +627,8 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
       }
     }
   }
+  P->g_rs_level[g] = fa.rs_level;
+  P->g_rs_slot[g] = fa.rs_slot;
   return AWE_OK;
 }
 

@@ -24,6 +24,7 @@ inline int pitch_of(int nx) { return (nx + kPitch - 1) / kPitch * kPitch; }
 constexpr int kFieldBufs = 8;
 __host__ __device__ inline int fwd_buf(int n) { return n & 3; }
 __host__ __device__ inline int adj_buf(int n) { return 4 + (n & 3); }
+constexpr int kNoLevel = -(1 << 29);
 
 // Storage precision of a kept wavefield.
 enum Prec : int { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
@@ -123,6 +124,8 @@ struct StepArgs {
   int ntiles;                // tiles in this launch (active prefix of the group's tiles)
   int tile_base;             // first tile of the shot group this launch covers
   int shot_base;             // first position in t.order of the group (per-shot kernels)
+  int rs_level;              // global state restored by reference from FP32 slot rs_slot
+  int rs_slot;               //   (kNoLevel: none); see fwd_level
   int nbl;
   int store_prec;            // Prec of the kept wavefield (FULL store / checkpoint slots)
   int image_src;             // adjoint imaging source, see ImageSrc
@@ -130,6 +133,16 @@ struct StepArgs {
   float eta_dt;              // damping amplitude / (nbl^2 dt): eta/dt = eta_dt * (dx^2 + dy^2 + dz^2)
   float inv_dt2;             // 1 / dt^2 (Born source)
 };
+
+// Forward level k (local index) of shot S.  After a checkpoint restore of global state n from
+// an FP32 slot, levels n and n - 1 are read from the slot itself until the next restore (no
+// copy); every other level lives in the shot's four rotating forward buffers.
+__device__ __forceinline__ float* fwd_level(const StepArgs& a, const ShotDev& S, int k) {
+  const int d = a.rs_level - (k + S.off);
+  if ((unsigned)d < 2u)
+    return reinterpret_cast<float*>(a.ws + S.store) + ((long long)a.rs_slot * 2 + d) * S.npts;
+  return reinterpret_cast<float*>(a.ws + S.fld) + (long long)fwd_buf(k) * S.npts;
+}
 
 // Launchers (defined in the .hip files).  All enqueue on `stream`.
 hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, long long m_off,

@@ -114,8 +114,8 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, nz = S.nz, px = S.px;
-  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
-  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
+  const float* __restrict__ u1 = fwd_level(a, S, k - 1);
+  const float* __restrict__ u2 = fwd_level(a, S, k - 2);
   float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
   const unsigned short* __restrict__ uj16 = nullptr;
   float usc = 1.f;
   if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, fwd_buf(j));
+  if (IMG == kImgBuffers) uj = fwd_level(a, S, j);
   if (IMG >= kImgFullBF16) {
     uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
     usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);

@@ -144,8 +144,8 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   // levels below 1 are zero (initial state) and are not read: after a checkpoint restore of a
   // state before this shot's start their buffers may hold older levels
   const int nz1 = k >= 2 ? nz : 0, nz2 = k >= 3 ? nz : 0;
-  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
-  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
+  const float* __restrict__ u1 = fwd_level(a, S, k - 1);
+  const float* __restrict__ u2 = fwd_level(a, S, k - 2);
   float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
   const unsigned short* __restrict__ uj16 = nullptr;
   float usc = 1.f;
   if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == kImgBuffers) uj = fbuf(a.ws, S, fwd_buf(j));
+  if (IMG == kImgBuffers) uj = fwd_level(a, S, j);
   if (IMG >= kImgFullBF16) {
     uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
     usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
@@ -431,7 +431,7 @@ __global__ void inj3d_kernel(StepArgs a, int first, int count) {
     if (a.image_src == kImgFull32)
       u = reinterpret_cast<const float*>(a.ws + S.store)[(long long)j * S.npts + Pt.p];
     else if (a.image_src == kImgBuffers)
-      u = fbuf(a.ws, S, fwd_buf(j))[Pt.p];
+      u = fwd_level(a, S, j)[Pt.p];
     else
       u = dec16(reinterpret_cast<const unsigned short*>(a.ws + S.store)[(long long)j * S.npts + Pt.p],
                 a.image_src == kImgFullBF16) *

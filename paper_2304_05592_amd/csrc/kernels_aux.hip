@@ -101,7 +101,7 @@ __global__ void slot_kernel(StepArgs a, int slot, int state, int dir) {
   const ShotDev& S = a.t.shots[a.t.order[a.shot_base + blockIdx.y]];
   const int fz = blockIdx.z;
   const int ls = state - S.off;
-  float* f = fbuf(a.ws, S, fwd_buf(ls - fz));
+  float* f = fwd_level(a, S, ls - fz);  // store: the source may be a slot restored by reference
   const long long base = ((long long)slot * 2 + fz) * S.npts;
   const int prec = a.store_prec;
   float s = 1.f, inv = 1.f;
