@@ -422,6 +422,7 @@ awe::StepArgs base_args(const awe_plan* P, void* ws) {
   a.inv_dt2 = (float)(1.0 / (P->dt * P->dt));
   a.rs_level = awe::kNoLevel;
   a.rs_slot = 0;
+  a.st_slot = -1;
   return a;
 }
 
@@ -585,12 +586,23 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
   for (size_t i = begin; i < end; ++i) {
     const int op = P->sched[3 * i], x = P->sched[3 * i + 1], y = P->sched[3 * i + 2];
     switch (op) {
-      case awe::kAdvance:
+      case awe::kAdvance: {
+        // a store of the reached state that follows is fused into the last step (2D, FP32
+        // slots, and not into the slot the step may still read by reference)
+        int fuse_slot = -1;
+        if (by_ref && P->ndim == 2 && i + 1 < end && P->sched[3 * (i + 1)] == awe::kStore &&
+            P->sched[3 * (i + 1) + 2] == y &&
+            !(fa.rs_level != awe::kNoLevel && fa.rs_slot == P->sched[3 * (i + 1) + 1]))
+          fuse_slot = P->sched[3 * (i + 1) + 1];
         for (int n = x + 1; n <= y; ++n) {
+          fa.st_slot = n == y ? fuse_slot : -1;
           awe_status st = step_fwd(P, fa, n, 0, s);
+          fa.st_slot = -1;
           if (st != AWE_OK) return st;
         }
+        if (fuse_slot >= 0) ++i;  // the store is done
         break;
+      }
       case awe::kStore: {
         if (fa.rs_level != awe::kNoLevel && fa.rs_slot == x) {
           // overwriting the slot that is read by reference: copy its state into the

@@ -126,6 +126,7 @@ struct StepArgs {
   int shot_base;             // first position in t.order of the group (per-shot kernels)
   int rs_level;              // global state restored by reference from FP32 slot rs_slot
   int rs_slot;               //   (kNoLevel: none); see fwd_level
+  int st_slot;               // 2D forward: also write (u^k, u^{k-1}) into this FP32 slot (-1: no)
   int nbl;
   int store_prec;            // Prec of the kept wavefield (FULL store / checkpoint slots)
   int image_src;             // adjoint imaging source, see ImageSrc

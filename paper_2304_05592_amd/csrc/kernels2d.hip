@@ -165,6 +165,12 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
     const float un = (u + u - pu2[i]) + incr;
     const long long p = (long long)z * px + x;
     out[p] = un;
+    if (SK == kStoreNone && a.st_slot >= 0) {
+      // checkpoint store fused into the step that reaches the stored state
+      float* sl = reinterpret_cast<float*>(a.ws + S.store) + (long long)a.st_slot * 2 * S.npts;
+      sl[p] = un;
+      sl[S.npts + p] = u;
+    }
     if (SK == kStoreF32)
       __builtin_nontemporal_store(un, reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts + p);
     if (SK >= kStoreBF16) {
