@@ -37,7 +37,9 @@ template <int TZ>
 struct T2 {
   static constexpr int W = kTX + 2 * kHalo;  // 72
   static constexpr int H = TZ + 2 * kHalo;
-  static constexpr int RPT = TZ / 4;         // rows per thread
+  static constexpr int NW = TZ >= 32 ? 8 : 4;  // waves per workgroup
+  static constexpr int NT = 64 * NW;           // threads per workgroup
+  static constexpr int RPT = TZ / NW;          // rows per thread
 };
 
 // Stage rows z0-4 .. z0+TZ+3 of a field, columns x0-4 .. x0+67, zero outside the grid.  The
@@ -50,13 +52,13 @@ __device__ __forceinline__ void load_tile(float (*L)[T2<TZ>::W], const float* __
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = x0 + lane;
 #pragma unroll
-  for (int r = wv; r < H; r += 4) {
+  for (int r = wv; r < H; r += T2<TZ>::NW) {
     const int z = z0 - kHalo + r;
     float v = 0.f;
     if (x < nx && (unsigned)z < (unsigned)nz) v = f[(long long)z * px + x];
     L[r][lane + kHalo] = v;
   }
-  for (int e = threadIdx.x; e < H * 2 * kHalo; e += kThreads) {
+  for (int e = threadIdx.x; e < H * 2 * kHalo; e += T2<TZ>::NT) {
     const int r = e / (2 * kHalo), c8 = e - r * (2 * kHalo);
     const int c = c8 < kHalo ? c8 : kTX + c8;
     const int z = z0 - kHalo + r, xx = x0 - kHalo + c;
@@ -105,7 +107,7 @@ __device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int 
 // ------------------------------------------------------------------------------ forward
 // Produces u^k (k = step - off) for every shot in the tile list; samples d^{k-1}.
 template <int TZ, int SK>
-__global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
+__global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
   constexpr int RPT = T2<TZ>::RPT;
   __shared__ float L[T2<TZ>::H][T2<TZ>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
   __syncthreads();
 
   if (a.d != nullptr) {
-    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+    for (int t = threadIdx.x; t < T.gat_count; t += T2<TZ>::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
       a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp_lds<TZ>(L, R.i, R.k, T.x0, T.z0, R.w);
     }
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d_kernel(StepArgs a) {
 // v^j = R(x_s) w^{j+1} / h^ndim; IMG adds u^j * (w^j - 2w^{j+1} + w^{j+2}) into the FP64
 // accumulator (u^j from the FULL store or from the recomputed forward buffers).
 template <int TZ, int IMG>
-__global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
+__global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
   constexpr int RPT = T2<TZ>::RPT;
   __shared__ float L[T2<TZ>::H][T2<TZ>::W];
   __shared__ float INJ[TZ][kTX];
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
 
   if (has_inj) {
     const float* ddj = a.dd + S.d + (long long)j * S.nrec;
-    for (int t = threadIdx.x; t < T.inj_count; t += kThreads) {
+    for (int t = threadIdx.x; t < T.inj_count; t += T2<TZ>::NT) {
       const InjPoint P = a.t.inj_pts[T.inj_begin + t];
       float s = 0.f;
       for (int e = 0; e < P.e_count; ++e) {
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void adj2d_kernel(StepArgs a) {
 // ------------------------------------------------------------------------------ Born
 // Produces u^k and du^k together; samples (J dm)^{k-1} = R du^{k-1}.
 template <int TZ>
-__global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
+__global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
   constexpr int RPT = T2<TZ>::RPT;
   __shared__ float LU[T2<TZ>::H][T2<TZ>::W];
   __shared__ float LD[T2<TZ>::H][T2<TZ>::W];
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(kThreads) void born2d_kernel(StepArgs a) {
   __syncthreads();
 
   if (a.d != nullptr) {
-    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+    for (int t = threadIdx.x; t < T.gat_count; t += T2<TZ>::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
       a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp_lds<TZ>(LD, R.i, R.k, T.x0, T.z0, R.w);
     }
@@ -638,10 +640,10 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
 template <int TZ>
 hipError_t fwd2d_tz(const StepArgs& a, int store, hipStream_t s) {
   switch (store) {
-    case kStoreNone: fwd2d_kernel<TZ, kStoreNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kStoreF32: fwd2d_kernel<TZ, kStoreF32><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kStoreBF16: fwd2d_kernel<TZ, kStoreBF16><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kStoreFP16: fwd2d_kernel<TZ, kStoreFP16><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kStoreNone: fwd2d_kernel<TZ, kStoreNone><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kStoreF32: fwd2d_kernel<TZ, kStoreF32><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kStoreBF16: fwd2d_kernel<TZ, kStoreBF16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kStoreFP16: fwd2d_kernel<TZ, kStoreFP16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -650,11 +652,11 @@ hipError_t fwd2d_tz(const StepArgs& a, int store, hipStream_t s) {
 template <int TZ>
 hipError_t adj2d_tz(const StepArgs& a, hipStream_t s) {
   switch (a.image_src) {
-    case kImgNone: adj2d_kernel<TZ, kImgNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kImgFull32: adj2d_kernel<TZ, kImgFull32><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kImgBuffers: adj2d_kernel<TZ, kImgBuffers><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kImgFullBF16: adj2d_kernel<TZ, kImgFullBF16><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kImgFullFP16: adj2d_kernel<TZ, kImgFullFP16><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgNone: adj2d_kernel<TZ, kImgNone><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kImgFull32: adj2d_kernel<TZ, kImgFull32><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kImgBuffers: adj2d_kernel<TZ, kImgBuffers><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kImgFullBF16: adj2d_kernel<TZ, kImgFullBF16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kImgFullFP16: adj2d_kernel<TZ, kImgFullFP16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -733,13 +735,13 @@ hipError_t launch_adj2d(const StepArgs& a, int tz, hipStream_t s) {
 hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   switch (tz) {
-    case 8: born2d_kernel<8><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case 12: born2d_kernel<12><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case 16: born2d_kernel<16><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case 20: born2d_kernel<20><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case 24: born2d_kernel<24><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case 32: born2d_kernel<32><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case 64: born2d_kernel<64><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case 8: born2d_kernel<8><<<a.ntiles, T2<8>::NT, 0, s>>>(a); break;
+    case 12: born2d_kernel<12><<<a.ntiles, T2<12>::NT, 0, s>>>(a); break;
+    case 16: born2d_kernel<16><<<a.ntiles, T2<16>::NT, 0, s>>>(a); break;
+    case 20: born2d_kernel<20><<<a.ntiles, T2<20>::NT, 0, s>>>(a); break;
+    case 24: born2d_kernel<24><<<a.ntiles, T2<24>::NT, 0, s>>>(a); break;
+    case 32: born2d_kernel<32><<<a.ntiles, T2<32>::NT, 0, s>>>(a); break;
+    case 64: born2d_kernel<64><<<a.ntiles, T2<64>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
