@@ -40,6 +40,7 @@ struct T2 {
   static constexpr int NW = TZ >= 32 ? 8 : 4;  // waves per workgroup
   static constexpr int NT = 64 * NW;           // threads per workgroup
   static constexpr int RPT = TZ / NW;          // rows per thread
+  static_assert(TZ % NW == 0, "tile rows must split evenly over the waves");
 };
 
 // Stage rows z0-4 .. z0+TZ+3 of a field, columns x0-4 .. x0+67, zero outside the grid.  The

@@ -46,6 +46,7 @@ struct T3 {
   static constexpr int W = kTX + 2 * kHalo;    // 72
   static constexpr int H = TY + 2 * kHalo;
   static constexpr int NC = TY / NW;           // y-rows per thread
+  static_assert(TY % NW == 0, "block rows must split evenly over the waves");
 };
 
 // Halo ring of one plane: rows y0-4..y0+TY+3 x columns x0-4..x0+67 minus the 64 x TY
