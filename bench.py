@@ -8,7 +8,8 @@ r = d - d_obs with the misfit 1/2 ||r||^2 in FP64, and the reverse sweep g = J^T
 solve + imaging condition, FP64 accumulation), all in the library's HIP kernels, captured
 once into a HIP graph and replayed.  Inputs are resident in HBM before the timed region.
 
-Other workloads (--config): c3_autograd (torch.autograd through the wave operator with 16
+Other workloads (--config): c1_fwd (single-shot 2D forward, 201 x 101, graph vs eager),
+c3_autograd (torch.autograd through the wave operator with 16
 checkpoint slots per shot, 32 shots), c4_uneven (64 uneven windows, forward, batched vs 64
 sequential single-shot runs), c5_3d (256^3, FULL BF16 / FP16 storage gradient).
 
@@ -53,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_grad",
-                    choices=["c2_grad", "c3_autograd", "c4_uneven", "c5_3d"])
+                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
@@ -437,6 +438,58 @@ def bench_c3(args):
         "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item())})
 
 
+def bench_c1(args):
+    """Single-shot 2D forward (201x101 two-layer model, T = 1 s): graph-replayed time loop vs
+    eager launches, and the oracle's forward on the host (the whole shot)."""
+    import torch
+    import oracle as O
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c1_fwd")
+    plan = make_plan(wl, A.Storage(A.STORE_NONE), [0])
+    m = plan.pack([wl.m(0)], "m")
+    q = plan.pack([wl.q(0)], "q")
+    ws = plan.workspace()
+    d = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
+    tiles = choose_tiles(plan, args, m, q, None, ws)
+    points, _ = points_of(wl, [0])
+    for _ in range(max(1, args.warmup)):
+        plan.forward(m, q, d=d, ws=ws)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.forward(m, q, d=d, ws=ws)
+    sync()
+    eager = (time.perf_counter() - t0) / args.steps
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.forward(m, q, d=d, ws=ws)
+    for _ in range(max(1, args.warmup)):
+        graph.replay()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    cpu = None
+    if not args.no_cpu_baseline:
+        sh = wl.shots[0]
+        t0 = time.perf_counter()
+        O.forward(wl.m(0), wl.q(0), sh.src, sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(points / tc / 1e9, 6), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole shot ({sh.nt} samples) in FP64 NumPy, one process; {tc:.1f} s"}
+    return base_line(args, wl, points / sec / 1e9, sec, {
+        "metric": "Gpts/s forward, single shot (launch-bound: 0.03 G point-updates per pass)",
+        "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)), "shots": 1,
+                   "nt": int(wl.shots[0].nt), "storage": "none (forward)", "graph": True, "tiles": tiles},
+        "roofline": None, "cpu_baseline": cpu,
+        "eager": {"value": round(points / eager / 1e9, 3), "ms_per_step": round(eager * 1e3, 3)}})
+
+
 def bench_c4(args):
     """64 uneven windows, forward: one batched graph-captured run vs 64 sequential runs."""
     import torch
@@ -544,7 +597,8 @@ def main():
     if args.copy_probe:
         print(json.dumps({"copy_probe": copy_probe()}), flush=True)
         return
-    fn = {"c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4, "c5_3d": bench_c5}[args.config]
+    fn = {"c1_fwd": bench_c1, "c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4,
+          "c5_3d": bench_c5}[args.config]
     print(json.dumps(fn(args)), flush=True)
 
 
