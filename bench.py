@@ -64,6 +64,8 @@ def parse():
                     help="stored-wavefield precision of the 3D workload")
     ap.add_argument("--tiles", default=None,
                     help="fixed launch shape instead of the autotuner, e.g. tz=32 or tz=16,levels_per_launch=2")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="shot groups per plan (0: automatic, sized to the last-level cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain device-to-device copy probe (PMC calibration)")
     args = ap.parse_args()
@@ -196,7 +198,7 @@ def timed_gradient(run, args, kind):
 class GradientRunner:
     """Forward (kept wavefield) + residual + reverse sweep on resident inputs."""
 
-    def __init__(self, wl, shots, storage, autotune=True, tiles=None):
+    def __init__(self, wl, shots, storage, autotune=True, tiles=None, groups=0):
         import torch
         import paper_2304_05592_amd as A
         self.A, self.torch = A, torch
@@ -219,7 +221,7 @@ class GradientRunner:
             self.tiles = dict(tiles)
         elif autotune:
             self.tiles, _ = p.autotune(self.m0, self.q, self.d_obs, probe_steps=32, ws=self.ws)
-        self.groups = p.set_groups(0)   # shot groups in effect (automatic)
+        self.groups = p.set_groups(groups)   # shot groups in effect (0: automatic)
         self.launch_points //= self.groups
         self.graph = None
         sync()
@@ -354,7 +356,7 @@ def bench_c2(args):
     import workloads as W
     wl = W.make_config("c2_grad")
     run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL), autotune=not args.no_autotune,
-                         tiles=args.tiles)
+                         tiles=args.tiles, groups=args.groups)
     sec, eager_sec, kernels, timing = timed_gradient(run, args, "fp32")
     value = run.points / sec / 1e9
     fused = bool(run.tiles) and run.tiles.get("levels_per_launch", 1) == 2
@@ -404,7 +406,7 @@ def bench_c3(args):
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     d_obs = plan.forward(m_true, q)
     tiles = choose_tiles(plan, args, m0, q, d_obs)
-    groups = plan.set_groups(0)   # shot groups in effect (automatic); the 32 shots split evenly
+    groups = plan.set_groups(args.groups)   # shot groups in effect; the 32 shots split evenly
     points, launch_points = points_of(wl, range(wl.nshot))
     launch_points //= groups
 
@@ -502,7 +504,7 @@ def bench_c4(args):
     ws = plan.workspace()
     d = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
     tiles = choose_tiles(plan, args, m, q, None, ws)
-    groups = plan.set_groups(0)
+    groups = plan.set_groups(args.groups)
     points, launch_points = points_of(wl, range(wl.nshot))
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
