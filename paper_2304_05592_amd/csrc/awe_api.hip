@@ -903,8 +903,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     const int fkind = full32 ? awe::kStoreF32 : awe::kStoreNone;
     aa.image_src = full32 ? awe::kImgFull32
                    : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
-    const size_t saved = P->prof_ev.size();  // keep the probe out of kernel timing
-    std::vector<hipEvent_t> keep_ev;
+    std::vector<hipEvent_t> keep_ev;  // keep the probe out of kernel timing
     keep_ev.swap(P->prof_ev);
     P->cur = 0;  // the probe times the first shot group
     AWE_HIP(hipEventRecord(e0, s));
@@ -923,7 +922,6 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     AWE_HIP(hipEventRecord(e1, s));
     AWE_HIP(hipEventSynchronize(e1));
     keep_ev.swap(P->prof_ev);
-    (void)saved;
     float ms = 0.f;
     AWE_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (ms < best) {
