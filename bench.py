@@ -10,7 +10,8 @@ once into a HIP graph and replayed.  Inputs are resident in HBM before the timed
 
 Other workloads (--config): c1_fwd (single-shot 2D forward, 201 x 101, graph vs eager),
 c3_autograd (torch.autograd through the wave operator with 16
-checkpoint slots per shot, 32 shots), c4_uneven (64 uneven windows, forward, batched vs 64
+checkpoint slots per shot, 32 shots), c6_timelapse (15-vintage crosswell time-lapse gradient
+with respect to wavespeed, 4 sampled shots per vintage), c4_uneven (64 uneven windows, forward, batched vs 64
 sequential single-shot runs), c5_3d (256^3, FULL BF16 / FP16 storage gradient).
 
 Prints one JSON line.  Gpts/s = sum over shots of N_s (nt_s - 1) per step / step time
@@ -54,7 +55,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_grad",
-                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d"])
+                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
@@ -333,8 +334,14 @@ def cpu_baseline(name, wl, n):
     wall = time.perf_counter() - t0
     work = sum(r[0] for r in res)
     busy = max(r[1] for r in res)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(work / busy / 1e9, 6), "unit": "Gpts/s", "cores": workers,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model,
             "sample": f"{workers} shots of {name} in parallel processes (one NumPy thread each), "
                       f"first {jobs[0][2]} of {wl.shots[0].nt} time samples; timed: forward at the "
                       f"starting model + gradient call (forward with stored wavefield, adjoint, "
@@ -391,6 +398,7 @@ def bench_c2(args):
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels, "kernel_timing": timing,
         "path_hbm_fraction": round(path_bytes / sec / 1e9 / PEAK_HBM_GBS, 4),
         "eager": {"value": round(points / eager_sec / 1e9, 3), "ms_per_step": round(eager_sec * 1e3, 3)},
+        "physical_grid_value": round(value * float(np.prod(wl.v[0].shape)) / float(np.prod(wl.comp_shape(0))), 3),
         "single_shot": single, "copy_probe": copy, "loss": loss})
 
 
@@ -490,6 +498,46 @@ def bench_c1(args):
                    "nt": int(wl.shots[0].nt), "storage": "none (forward)", "graph": True, "tiles": tiles},
         "roofline": None, "cpu_baseline": cpu,
         "eager": {"value": round(points / eager / 1e9, 3), "ms_per_step": round(eager * 1e3, 3)}})
+
+
+def bench_c6(args):
+    """Time-lapse inversion iteration: 15 vintages (model windows) x 4 shots drawn with
+    replacement, gradient of 1/2 ||F(m(v)) q - d_obs||^2 with respect to each vintage's
+    wavespeed v through WaveOp and the m = 1/v^2 parameterisation, FULL FP32 storage."""
+    import torch
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c6_timelapse")
+    plan = make_plan(wl, A.Storage(A.STORE_FULL), range(wl.nshot))
+    v_true = plan.pack([W.extend_edge(wl.v[w].astype(np.float32), wl.nbl) for w in range(wl.nwindow)], "m")
+    v0 = plan.pack([W.extend_edge(wl.v0[w].astype(np.float32), wl.nbl) for w in range(wl.nwindow)], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    d_obs = plan.forward(A.slowness2(v_true), q)
+    tiles = choose_tiles(plan, args, A.slowness2(v0), q, d_obs)
+    groups = plan.set_groups(args.groups)
+    points, _ = points_of(wl, range(wl.nshot))
+
+    def step():
+        v = v0.clone().requires_grad_(True)
+        loss = A.misfit(A.wave_forward(A.slowness2_from_velocity(v), q, plan), d_obs)
+        loss.backward()
+        return loss, v.grad
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, g = step()
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    return base_line(args, wl, points / sec / 1e9, sec, {
+        "metric": "Gpts/s time-lapse gradient (wavespeed), 15 vintages x 4 sampled shots",
+        "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
+                   "vintages": wl.nwindow, "shots": wl.nshot, "nt": int(wl.shots[0].nt),
+                   "storage": "FULL FP32", "graph": False, "tiles": tiles, "shot_groups": groups},
+        "roofline": None, "cpu_baseline": None, "loss": float(loss.item()),
+        "grad_norm": float(g.norm().item())})
 
 
 def bench_c4(args):
@@ -600,7 +648,7 @@ def main():
         print(json.dumps({"copy_probe": copy_probe()}), flush=True)
         return
     fn = {"c1_fwd": bench_c1, "c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4,
-          "c5_3d": bench_c5}[args.config]
+          "c5_3d": bench_c5, "c6_timelapse": bench_c6}[args.config]
     print(json.dumps(fn(args)), flush=True)
 
 

@@ -175,6 +175,16 @@ awe_status awe_dot_f64(const float* a, const float* b, int64_t n, double* out, v
 awe_status awe_dot_f64d(const double* a, const double* b, int64_t n, double* out, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* Wavespeed parameterisation ("Putting it all together": the time-lapse operator
+ * diag(F^i(v^i) q^i) is written in terms of the compressional wavespeed v, and the
+ * operators of "Wave-equation-based inversion" take the squared slowness m = 1/v^2).
+ * awe_slowness2: m[i] = 1/v[i]^2.  awe_velocity_gradient: the chain rule of that map,
+ * gv[i] = -2 gm[i] / v[i]^3 (gm = dphi/dm, gv = dphi/dv).  float arrays of n values on the
+ * device (caller-owned; gv may alias gm), computed in FP64 and rounded once.  Errors:
+ * INVALID_ARG (NULL pointer, n < 0), HIP. */
+awe_status awe_slowness2(const float* v, float* m, int64_t n, void* stream);
+awe_status awe_velocity_gradient(const float* v, const float* gm, float* gv, int64_t n, void* stream);
+
 /* Binomial checkpoint schedule (host only, no device work) for a reverse sweep over
  * states S_1..S_{nsteps} with nslots restart slots.  Writes up to cap actions
  * (op, a, b) into actions[3*i..3*i+2] and the count into *count:

@@ -45,7 +45,7 @@ import scipy.sparse as sp
 
 __all__ = ["STENCIL", "STENCIL_EXACT", "laplacian", "damping_profile", "interp_nodes",
            "restriction", "Propagator", "forward", "adjoint", "born", "gradient",
-           "objective", "fold_edge", "stability_limit"]
+           "objective", "fold_edge", "stability_limit", "slowness2", "velocity_gradient"]
 
 # 8th-order central second-derivative weights c0, c1..c4 (standard Taylor-series weights).
 STENCIL_EXACT = (Fraction(-205, 72), Fraction(8, 5), Fraction(-1, 5), Fraction(8, 315),
@@ -325,3 +325,16 @@ def objective(d_pred, d_obs):
     """phi = 1/2 sum (d_pred - d_obs)^2 (plain Euclidean sum; no conjugation for complex input)."""
     r = np.asarray(d_pred) - np.asarray(d_obs)
     return 0.5 * np.sum(r * r)
+
+
+def slowness2(v):
+    """m = 1/v^2: the squared slowness of a compressional wavespeed (the time-lapse operator of
+    "Putting it all together" is parameterised by v, the wave operators by m)."""
+    v = np.asarray(v, dtype=np.float64)
+    return 1.0 / (v * v)
+
+
+def velocity_gradient(v, g_m):
+    """Chain rule of m = 1/v^2: dphi/dv = dphi/dm * dm/dv = -2 g_m / v^3 (elementwise)."""
+    v = np.asarray(v, dtype=np.float64)
+    return -2.0 * np.asarray(g_m, dtype=np.float64) / (v * v * v)

@@ -66,6 +66,30 @@ class Misfit(torch.autograd.Function):
         return (r * gphi.to(r.dtype)), None
 
 
+class Slowness2(torch.autograd.Function):
+    """m = 1/v^2 from the compressional wavespeed v (the time-lapse operator of "Putting it all
+    together" is parameterised by v); the pullback is gv = -2 gm / v^3 (library kernels)."""
+
+    @staticmethod
+    def forward(ctx, v: torch.Tensor):
+        from .binding import slowness2
+        vf = v.detach().to(torch.float32).contiguous()
+        ctx.save_for_backward(vf)
+        ctx.v_dtype = v.dtype
+        return slowness2(vf)
+
+    @staticmethod
+    def backward(ctx, gm: torch.Tensor):
+        from .binding import velocity_gradient
+        (vf,) = ctx.saved_tensors
+        return velocity_gradient(vf, gm.detach().to(torch.float32).contiguous()).to(ctx.v_dtype)
+
+
+def slowness2_from_velocity(v: torch.Tensor) -> torch.Tensor:
+    """Differentiable m = 1/v^2."""
+    return Slowness2.apply(v)
+
+
 def misfit(d: torch.Tensor, d_obs: torch.Tensor) -> torch.Tensor:
     """Differentiable 1/2 ||d - d_obs||^2 (FP64 scalar)."""
     return Misfit.apply(d, d_obs)

@@ -26,7 +26,7 @@ EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "aw
            "awe_backward", "awe_gradient", "awe_adjoint", "awe_born", "awe_reduce_workspace_size",
            "awe_residual", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
            "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
-           "awe_status_string", "awe_last_error", "awe_version"]
+           "awe_slowness2", "awe_velocity_gradient", "awe_status_string", "awe_last_error", "awe_version"]
 
 
 class AweError(RuntimeError):
@@ -88,6 +88,8 @@ def lib():
     L.awe_plan_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.awe_plan_set_fusion.argtypes = [vp, ctypes.c_int32]
     L.awe_plan_set_groups.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.awe_slowness2.argtypes = [vp, vp, i64, vp]
+    L.awe_velocity_gradient.argtypes = [vp, vp, vp, i64, vp]
     L.awe_profile_enable.argtypes = [vp, i64, ctypes.c_int32]
     L.awe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.awe_profile_disable.argtypes = [vp]
@@ -98,7 +100,7 @@ def lib():
     for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
                  "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_dot_f64",
                  "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion",
-                 "awe_plan_set_groups", "awe_profile_enable",
+                 "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_profile_enable",
                  "awe_profile_read", "awe_profile_disable"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -410,6 +412,28 @@ def residual(d_pred, d_obs, r=None, stream=None):
     check(lib().awe_residual(_ptr(d_pred), _ptr(d_obs), _ptr(r), n, _ptr(loss), _ptr(ws),
                              ws.numel() * 8, _stream_ptr(stream)))
     return r, loss
+
+
+def slowness2(v, m=None, stream=None):
+    """m = 1/v^2 (float32 device tensors, computed in FP64 and rounded once)."""
+    import torch
+    if v.dtype != torch.float32 or not v.is_contiguous():
+        raise TypeError("v must be a contiguous float32 tensor")
+    m = torch.empty_like(v) if m is None else m
+    check(lib().awe_slowness2(_ptr(v), _ptr(m), v.numel(), _stream_ptr(stream)))
+    return m
+
+
+def velocity_gradient(v, gm, gv=None, stream=None):
+    """gv = -2 gm / v^3: the gradient with respect to the wavespeed v from the gradient with
+    respect to m = 1/v^2 (float32 device tensors)."""
+    import torch
+    for t, n in ((v, "v"), (gm, "gm")):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{n} must be a contiguous float32 tensor")
+    gv = torch.empty_like(v) if gv is None else gv
+    check(lib().awe_velocity_gradient(_ptr(v), _ptr(gm), _ptr(gv), v.numel(), _stream_ptr(stream)))
+    return gv
 
 
 def dot(a, b, stream=None):

@@ -1182,6 +1182,18 @@ awe_status awe_dot_f64d(const double* a, const double* b, int64_t n, double* out
   return AWE_OK;
 }
 
+awe_status awe_slowness2(const float* v, float* m, int64_t n, void* stream) {
+  if (!v || !m || n < 0) return fail(AWE_ERR_INVALID_ARG, "bad slowness arguments");
+  AWE_HIP(awe::launch_slowness2(v, m, n, static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
+awe_status awe_velocity_gradient(const float* v, const float* gm, float* gv, int64_t n, void* stream) {
+  if (!v || !gm || !gv || n < 0) return fail(AWE_ERR_INVALID_ARG, "bad velocity-gradient arguments");
+  AWE_HIP(awe::launch_velocity_gradient(v, gm, gv, n, static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
 awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions, int64_t cap,
                                    int64_t* count) {
   if (nsteps < 0 || nslots < 0 || !count || (cap > 0 && !actions))

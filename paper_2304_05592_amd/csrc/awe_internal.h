@@ -174,6 +174,9 @@ hipError_t launch_absmax(const StepArgs& a, int nshot, int slot, int state, hipS
 // g[window] = scale * sum over the window's shots (ascending) of their FP64 accumulators.
 hipError_t launch_grad_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws,
                               double* g, double scale, hipStream_t stream);
+hipError_t launch_slowness2(const float* v, float* m, long long n, hipStream_t stream);
+hipError_t launch_velocity_gradient(const float* v, const float* gm, float* gv, long long n,
+                                    hipStream_t stream);
 hipError_t launch_residual(const float* a, const float* b, float* r, long long n, double* loss,
                            unsigned char* ws, hipStream_t stream);
 hipError_t launch_dot(const float* a, const float* b, long long n, double* out, unsigned char* ws,

@@ -199,6 +199,24 @@ __global__ void final_kernel(const double* part, int np, double* out) {
   if (threadIdx.x == 0) *out = s;
 }
 
+// m = 1/v^2 and the chain rule gv = -2 gm / v^3 of the wavespeed parameterisation (FP64
+// arithmetic, one rounding).
+__global__ void slowness2_kernel(const float* __restrict__ v, float* __restrict__ m, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double x = v[i];
+    m[i] = (float)(1.0 / (x * x));
+  }
+}
+
+__global__ void velocity_grad_kernel(const float* v, const float* gm, float* gv, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double x = v[i];
+    gv[i] = (float)(-2.0 * (double)gm[i] / (x * x * x));
+  }
+}
+
 int grid_for(long long n) {
   long long b = (n + kThreads - 1) / kThreads;
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
@@ -258,6 +276,19 @@ hipError_t launch_store_last(const StepArgs& a, int nshot, long long max_npts, h
 hipError_t launch_grad_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws,
                               double* g, double scale, hipStream_t s) {
   grad_reduce_kernel<<<dim3(grid_for(max_npts), nwin), kThreads, 0, s>>>(t, ws, g, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_slowness2(const float* v, float* m, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  slowness2_kernel<<<grid_for(n), kThreads, 0, s>>>(v, m, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_velocity_gradient(const float* v, const float* gm, float* gv, long long n,
+                                    hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  velocity_grad_kernel<<<grid_for(n), kThreads, 0, s>>>(v, gm, gv, n);
   return hipGetLastError();
 }
 

@@ -434,3 +434,22 @@ def test_gradient_does_not_depend_on_checkpoint_segment():
     g_full = O.gradient(m, wl.q(0), dd, **kw)
     g_seg = O.gradient(m, wl.q(0), dd, segment=7, **kw)
     assert np.array_equal(g_full, g_seg)
+
+
+def test_velocity_parameterisation_chain_rule_by_finite_differences():
+    """d/dv of phi(m(v)) with m = 1/v^2 and phi(m) = <a, m> + 1/2 <m, B m>: the oracle's
+    velocity_gradient(v, dphi/dm) against central differences of phi along random directions."""
+    rng = np.random.default_rng(11)
+    v = rng.uniform(1.5, 4.5, size=40)
+    a = rng.standard_normal(40)
+    Bm = rng.standard_normal((40, 40))
+    B = Bm @ Bm.T / 40
+    phi = lambda vv: a @ O.slowness2(vv) + 0.5 * O.slowness2(vv) @ B @ O.slowness2(vv)
+    gm = a + B @ O.slowness2(v)
+    gv = O.velocity_gradient(v, gm)
+    for _ in range(4):
+        e = rng.standard_normal(40)
+        eps = 1e-5
+        fd = (phi(v + eps * e) - phi(v - eps * e)) / (2 * eps)
+        assert abs(fd - gv @ e) <= 1e-8 * max(1.0, abs(fd))
+    assert np.allclose(O.slowness2(np.array([2.0, 0.5])), [0.25, 4.0], rtol=0, atol=0)

@@ -289,8 +289,55 @@ def _c5_crop() -> Workload:
                           crop=((0, 64), (96, 160), (96, 160)))
 
 
+def plume_mask(shape, h: float, vintage: int, nvint: int) -> np.ndarray:
+    """Synthetic stand-in for a CO2 plume at vintage i of n (0 outside, up to 1 inside): an
+    inverted cone above a reservoir layer whose width grows as sqrt(i/n), smoothed over ~2 cells.
+    It only provides time-lapse wavespeed changes of a plausible shape (no flow physics)."""
+    nz, nx = shape
+    z = (np.arange(nz) + 0.5)[:, None] / nz
+    x = (np.arange(nx) + 0.5)[None, :] / nx
+    frac = np.sqrt(max(vintage, 0) / float(nvint))
+    top, bottom = 0.45, 0.70                        # reservoir band (fraction of depth)
+    half = 0.30 * frac * (0.4 + 0.6 * (z - top) / (bottom - top))   # cone: wider at the bottom
+    inside = (z >= top) & (z <= bottom) & (np.abs(x - 0.5) <= half)
+    out = gaussian_filter(inside.astype(np.float64), 2.0, mode="nearest")
+    return np.clip(out, 0.0, 1.0)
+
+
+def timelapse_survey(name="c6_timelapse", nx=512, nz=256, h=6.25, T=1200.0, nvint=15, nsrc=32, nrec=960,
+                     shots_per_vintage=4, iteration=0, seed=6, drop=0.05, nbl=40) -> Workload:
+    """Time-lapse crosswell survey: vintages i = 1..nvint share a layered baseline and differ by
+    a growing low-wavespeed plume (v^i = v_base (1 - drop * plume_i)); sources in the left well,
+    receivers in the right well.  One inversion iteration draws `shots_per_vintage` of the nsrc
+    sources per vintage with replacement (seeded by `iteration`); shot s runs on window = its
+    vintage.  The starting model of every vintage is the smoothed baseline."""
+    v_base = _layered_perturbed((nz, nx), h, seed)
+    vs = [v_base * (1.0 - drop * plume_mask((nz, nx), h, i + 1, nvint)) for i in range(nvint)]
+    vmax = float(max(v.max() for v in vs))
+    dt, nt = cfl_time_grid(T, h, vmax)
+    xs, xr = 0.1 * (nx - 1) * h, 0.9 * (nx - 1) * h
+    src_z = np.linspace(0.1, 0.9, nsrc) * (nz - 1) * h
+    rec = np.zeros((nrec, 3))
+    rec[:, 0] = xr
+    rec[:, 2] = np.linspace(0.05, 0.95, nrec) * (nz - 1) * h
+    rng = np.random.default_rng(1000 * seed + iteration)
+    shots = []
+    for i in range(nvint):
+        for k in rng.integers(0, nsrc, size=shots_per_vintage):
+            shots.append(Shot(i, nt, np.array([xs, 0.0, src_z[k]]), rec))
+    v0 = smooth_background(v_base, h)
+    return Workload(name, 2, h, nbl, dt, 0.015, vmax, 0.4, vs, shots,
+                    f"2D time-lapse crosswell, {nx}x{nz} @ {h} m, {nvint} vintages x {shots_per_vintage} "
+                    f"of {nsrc} shots (with replacement), {nrec} receivers, T = {T / 1000:g} s",
+                    v0=[v0] * nvint, extra={"src_z": src_z, "iteration": iteration})
+
+
+def _c6() -> Workload:
+    return timelapse_survey()
+
+
 _CONFIGS = {"c1_fwd": _c1, "c2_grad": _c2, "c3_autograd": _c3, "c4_uneven": _c4,
-            "c5_3d": _c5, "c5_crop": _c5_crop}
+            "c5_3d": _c5, "c5_crop": _c5_crop, "c6_timelapse": _c6}
 
 
 def config_names():
@@ -298,7 +345,8 @@ def config_names():
 
 
 def make_config(name: str) -> Workload:
-    """Build one of the named workloads (c1_fwd, c2_grad, c3_autograd, c4_uneven, c5_3d, c5_crop)."""
+    """Build one of the named workloads (c1_fwd, c2_grad, c3_autograd, c4_uneven, c5_3d, c5_crop,
+    c6_timelapse)."""
     return _CONFIGS[name]()
 
 
