@@ -45,7 +45,8 @@ import scipy.sparse as sp
 
 __all__ = ["STENCIL", "STENCIL_EXACT", "laplacian", "damping_profile", "interp_nodes",
            "restriction", "Propagator", "forward", "adjoint", "born", "gradient",
-           "objective", "fold_edge", "stability_limit", "slowness2", "velocity_gradient"]
+           "objective", "fold_edge", "stability_limit", "slowness2", "velocity_gradient",
+           "PATCHY_CONSTANTS", "patchy", "patchy_vjp"]
 
 # 8th-order central second-derivative weights c0, c1..c4 (standard Taylor-series weights).
 STENCIL_EXACT = (Fraction(-205, 72), Fraction(8, 5), Fraction(-1, 5), Fraction(8, 315),
@@ -338,3 +339,56 @@ def velocity_gradient(v, g_m):
     """Chain rule of m = 1/v^2: dphi/dv = dphi/dm * dm/dv = -2 g_m / v^3 (elementwise)."""
     v = np.asarray(v, dtype=np.float64)
     return -2.0 * np.asarray(g_m, dtype=np.float64) / (v * v * v)
+
+
+# Rock and fluid constants of the patchy-saturation model in "Putting it all together": bulk
+# moduli of the mineral, the brine and the CO2 (Pa) and the densities of the CO2 and the brine
+# (kg/m^3).
+PATCHY_CONSTANTS = {"k_min": 36.6e9, "k_brine": 2.735e9, "k_co2": 0.125e9,
+                    "rho_co2": 700.0, "rho_brine": 1000.0}
+
+
+def patchy(sw, vp, rho, phi, consts=None):
+    """Rock physics R of "Putting it all together": patchy CO2 saturation sw lowers the wavespeed.
+
+    Inputs per cell: saturation sw in [0, 1], brine-saturated wavespeed vp (km/s), density rho
+    (kg/m^3), porosity phi.  The shear wavespeed is taken as vp / sqrt(3).  Moduli of the
+    brine-saturated rock: shear mu = rho vs^2, bulk K1 = rho vp^2 - 4 mu / 3.  Gassmann's
+    relation, written with r(K) = K / (k_min - K), says r(K_sat) - r(K_fluid) / phi is the same
+    for every pore fluid (it is r of the dry frame), which swaps brine for CO2:
+        r(K2) = r(K1) - r(k_brine) / phi + r(k_co2) / phi,   K2 = k_min r / (1 + r).
+    The patchy mixture's P-wave modulus is the saturation-weighted harmonic average of the two
+    P-wave moduli K + 4 mu / 3; the density mixes the fluids linearly; vp_new follows from the
+    P-wave modulus and density.  Returns (vp_new in km/s, rho_new).  dtype-generic (complex
+    inputs give complex-step derivatives)."""
+    c = dict(PATCHY_CONSTANTS if consts is None else consts)
+    as_arr = lambda a: np.asarray(a) if np.iscomplexobj(a) else np.asarray(a, dtype=np.float64)
+    sw, vp, rho, phi = (as_arr(a) for a in (sw, vp, rho, phi))
+    vp_si = 1e3 * vp                                        # km/s -> m/s
+    vs_si = vp_si / math.sqrt(3.0)
+    mu = rho * vs_si ** 2
+    k_brine_rock = rho * (vp_si ** 2 - 4.0 / 3.0 * vs_si ** 2)
+
+    def r(k):
+        return k / (c["k_min"] - k)
+
+    r_co2_rock = r(k_brine_rock) - r(c["k_brine"]) / phi + r(c["k_co2"]) / phi
+    k_co2_rock = c["k_min"] / (1.0 / r_co2_rock + 1.0)
+    p_brine = k_brine_rock + 4.0 / 3.0 * mu                 # P-wave moduli
+    p_co2 = k_co2_rock + 4.0 / 3.0 * mu
+    p_mix = 1.0 / ((1.0 - sw) / p_brine + sw / p_co2)
+    rho_new = rho + phi * sw * (c["rho_co2"] - c["rho_brine"])
+    vp_new = np.sqrt(p_mix / rho_new) / 1e3
+    return vp_new, rho_new
+
+
+def patchy_vjp(sw, vp, rho, phi, g_vp, g_rho=None, consts=None, step=1e-30):
+    """Pullback of R with respect to the saturation: g_sw = g_vp dvp_new/dsw + g_rho drho_new/dsw
+    (R is elementwise, so its Jacobian in sw is diagonal).  The derivatives are complex-step
+    derivatives Im R(sw + i step) / step, exact up to rounding for this analytic map."""
+    sw = np.asarray(sw, dtype=np.float64)
+    vp_c, rho_c = patchy(sw + 1j * step, vp, rho, phi, consts)
+    g = np.asarray(g_vp, dtype=np.float64) * (vp_c.imag / step)
+    if g_rho is not None:
+        g = g + np.asarray(g_rho, dtype=np.float64) * (rho_c.imag / step)
+    return g

@@ -304,6 +304,29 @@ def plume_mask(shape, h: float, vintage: int, nvint: int) -> np.ndarray:
     return np.clip(out, 0.0, 1.0)
 
 
+def reservoir_rock(shape, seed: int = 7):
+    """Seeded brine-saturated reservoir rock for the patchy-saturation map: wavespeed vp
+    3.1-3.8 km/s, density 2250-2450 kg/m^3 and porosity 0.20-0.30, each a smooth random field
+    (correlation ~8 cells) mapped into its range.  Within these ranges the dry frame implied by
+    the brine-saturated moduli (vs = vp / sqrt 3) is positive, as for a physical sandstone.
+    Returns float32 arrays (vp, rho, phi)."""
+    out = []
+    for k, (lo, hi) in enumerate(((3.1, 3.8), (2250.0, 2450.0), (0.20, 0.30))):
+        f = random_field(shape, seed * 10 + k, smooth_cells=4.0, dtype=np.float64)
+        u = 0.5 * (1.0 + np.tanh(0.8 * f))                      # smooth, in (0, 1)
+        out.append((lo + (hi - lo) * u).astype(np.float32))
+    return tuple(out)
+
+
+def saturation_field(shape, seed: int = 8, zero_frac: float = 0.3, one_frac: float = 0.1):
+    """Seeded CO2 saturation in [0, 1]: a smooth random field whose lowest `zero_frac` of cells
+    are exactly 0 (no CO2) and highest `one_frac` exactly 1 (fully saturated), the rest in
+    between.  float32."""
+    f = random_field(shape, seed, smooth_cells=3.0, dtype=np.float64)
+    lo, hi = np.quantile(f, [zero_frac, 1.0 - one_frac])
+    return np.clip((f - lo) / (hi - lo), 0.0, 1.0).astype(np.float32)
+
+
 def timelapse_survey(name="c6_timelapse", nx=512, nz=256, h=6.25, T=1200.0, nvint=15, nsrc=32, nrec=960,
                      shots_per_vintage=4, iteration=0, seed=6, drop=0.05, nbl=40) -> Workload:
     """Time-lapse crosswell survey: vintages i = 1..nvint share a layered baseline and differ by
