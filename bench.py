@@ -11,7 +11,8 @@ once into a HIP graph and replayed.  Inputs are resident in HBM before the timed
 Other workloads (--config): c1_fwd (single-shot 2D forward, 201 x 101, graph vs eager),
 c3_autograd (torch.autograd through the wave operator with 16
 checkpoint slots per shot, 32 shots), c6_timelapse (15-vintage crosswell time-lapse gradient
-with respect to wavespeed, 4 sampled shots per vintage), c4_uneven (64 uneven windows, forward, batched vs 64
+with respect to wavespeed, 4 sampled shots per vintage), c7_timelapse_rock (the same iteration
+with respect to CO2 saturation through the patchy rock physics), c4_uneven (64 uneven windows, forward, batched vs 64
 sequential single-shot runs), c5_3d (256^3, FULL BF16 / FP16 storage gradient).
 
 Prints one JSON line.  Gpts/s = sum over shots of N_s (nt_s - 1) per step / step time
@@ -55,7 +56,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_grad",
-                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse"])
+                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse",
+                             "c7_timelapse_rock"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
@@ -540,6 +542,93 @@ def bench_c6(args):
         "grad_norm": float(g.norm().item())})
 
 
+def _time_launches(fn, reps):
+    """Mean duration (s) of `fn` (library kernels on torch's current stream) over reps calls,
+    bracketed by events on that stream."""
+    import torch
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def rock_kernel_rates(n_cells):
+    """Achieved bandwidth of the rock-physics kernels on n_cells synthetic reservoir cells:
+    forward reads sw, vp, rho, phi and writes vp_new, rho_new (24 B/cell); the pullback reads
+    sw, vp, rho, phi, g_vp and writes g_sw (24 B/cell)."""
+    import torch
+    import paper_2304_05592_amd as A
+    import workloads as W
+    side = 4096
+    vp, rho, phi = (torch.from_numpy(a.ravel()).cuda() for a in W.reservoir_rock((side,), 7))
+    sw = torch.from_numpy(W.saturation_field((side,), 8).ravel()).cuda()
+    reps = -(-n_cells // side)
+    sw, vp, rho, phi = (t.repeat(reps)[:n_cells].contiguous() for t in (sw, vp, rho, phi))
+    g_vp = torch.ones_like(vp)
+    out = {}
+    for name, fn in (("forward", lambda: A.patchy(sw, vp, rho, phi)),
+                     ("pullback", lambda: A.patchy_vjp(sw, vp, rho, phi, g_vp))):
+        t = _time_launches(fn, 20)
+        out[name] = {"us": round(t * 1e6, 2), "GB/s": round(24.0 * n_cells / t / 1e9, 1),
+                     "frac": round(24.0 * n_cells / t / 1e9 / PEAK_HBM_GBS, 4)}
+    del sw, vp, rho, phi, g_vp
+    torch.cuda.empty_cache()
+    return {"cells": int(n_cells), "bytes_per_cell": 24, **out}
+
+
+def bench_c7(args):
+    """Time-lapse iteration through the rock physics: gradient of 1/2 ||F(m(R(sw))) q - d_obs||^2
+    with respect to every vintage's CO2 saturation sw, with R the patchy-saturation map of the
+    reservoir rock, m = 1/v^2 and WaveOp (15 vintages x 4 sampled shots, FULL FP32 storage).
+    The observed data come from the vintages' true saturations; the gradient is taken at zero
+    saturation (the brine rock)."""
+    import torch
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c7_timelapse_rock")
+    plan = make_plan(wl, A.Storage(A.STORE_FULL), range(wl.nshot))
+    ext = lambda a: W.extend_edge(np.asarray(a, dtype=np.float32), wl.nbl)
+    vp, rho, phi = (plan.pack([ext(wl.extra[k])] * wl.nwindow, "m") for k in ("vp", "rho", "phi"))
+    sw_true = plan.pack([ext(a) for a in wl.extra["sat"]], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    v_true, _ = A.patchy(sw_true, vp, rho, phi)
+    if float(v_true.max()) > wl.vmax:
+        raise RuntimeError("rock physics raised the wavespeed above the plan's vmax")
+    d_obs = plan.forward(A.slowness2(v_true), q)
+    tiles = choose_tiles(plan, args, A.slowness2(vp), q, d_obs)
+    groups = plan.set_groups(args.groups)
+    points, _ = points_of(wl, range(wl.nshot))
+    sw0 = torch.zeros_like(sw_true)
+
+    def step():
+        sw = sw0.clone().requires_grad_(True)
+        v, _ = A.patchy_rock_physics(sw, vp, rho, phi)
+        loss = A.misfit(A.wave_forward(A.slowness2_from_velocity(v), q, plan), d_obs)
+        loss.backward()
+        return loss, sw.grad
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, g = step()
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    rock = {"workload_size": rock_kernel_rates(sw0.numel()), "large": rock_kernel_rates(1 << 28)}
+    return base_line(args, wl, points / sec / 1e9, sec, {
+        "metric": "Gpts/s time-lapse gradient (CO2 saturation through rock physics), 15 vintages x 4 sampled shots",
+        "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
+                   "vintages": wl.nwindow, "shots": wl.nshot, "nt": int(wl.shots[0].nt),
+                   "storage": "FULL FP32", "graph": False, "tiles": tiles, "shot_groups": groups},
+        "roofline": None, "cpu_baseline": None, "loss": float(loss.item()),
+        "grad_norm": float(g.norm().item()), "rock_physics_kernels": rock})
+
+
 def bench_c4(args):
     """64 uneven windows, forward: one batched graph-captured run vs 64 sequential runs."""
     import torch
@@ -648,7 +737,8 @@ def main():
         print(json.dumps({"copy_probe": copy_probe()}), flush=True)
         return
     fn = {"c1_fwd": bench_c1, "c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4,
-          "c5_3d": bench_c5, "c6_timelapse": bench_c6}[args.config]
+          "c5_3d": bench_c5, "c6_timelapse": bench_c6,
+          "c7_timelapse_rock": bench_c7}[args.config]
     print(json.dumps(fn(args)), flush=True)
 
 

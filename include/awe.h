@@ -185,6 +185,30 @@ awe_status awe_dot_f64d(const double* a, const double* b, int64_t n, double* out
 awe_status awe_slowness2(const float* v, float* m, int64_t n, void* stream);
 awe_status awe_velocity_gradient(const float* v, const float* gm, float* gv, int64_t n, void* stream);
 
+/* Patchy-saturation rock physics R ("Putting it all together"): the CO2 saturation s of each
+ * cell lowers its compressional wavespeed.  Per cell, with wavespeed vp (km/s), density rho
+ * (kg/m^3) and porosity phi: the brine-saturated P-wave modulus P1 = rho vp^2 and shear
+ * modulus mu = rho vp^2 / 3 (vs = vp / sqrt 3); Gassmann's relation in the form
+ * r(K) = K / (k_min - K) gives the fully CO2-saturated bulk modulus K2 from
+ * r(K2) = r(K1) - r(k_brine)/phi + r(k_co2)/phi with K1 = P1 - 4 mu / 3, and P2 = K2 + 4 mu / 3;
+ * the patchy mixture's P-wave modulus is the harmonic average M = 1 / ((1 - s)/P1 + s/P2);
+ * rho_new = rho + phi s (rho_co2 - rho_brine) and vp_new = sqrt(M / rho_new).
+ * Constants (NULL: the paper's k_min 36.6e9, k_brine 2.735e9, k_co2 0.125e9 Pa, rho_co2 700,
+ * rho_brine 1000 kg/m^3).  All arrays float, n values on the device, computed in FP64.
+ * awe_patchy writes vp_new and rho_new (rho_new may be NULL); awe_patchy_vjp writes
+ * g_s = g_vp dvp_new/ds + g_rho drho_new/ds (g_rho may be NULL: 0).  s = 0 returns vp and
+ * rho unchanged.  n = 0 does nothing (pointers may then be NULL).  Errors: INVALID_ARG (n < 0,
+ * or a required pointer NULL with n > 0), HIP. */
+typedef struct {
+  double k_min, k_brine, k_co2;   /* bulk moduli of the mineral, brine and CO2 (Pa) */
+  double rho_co2, rho_brine;      /* fluid densities (kg/m^3) */
+} awe_patchy_consts;
+awe_status awe_patchy(const float* s, const float* vp, const float* rho, const float* phi, float* vp_new,
+                      float* rho_new, int64_t n, const awe_patchy_consts* c, void* stream);
+awe_status awe_patchy_vjp(const float* s, const float* vp, const float* rho, const float* phi,
+                          const float* g_vp, const float* g_rho, float* g_s, int64_t n,
+                          const awe_patchy_consts* c, void* stream);
+
 /* Binomial checkpoint schedule (host only, no device work) for a reverse sweep over
  * states S_1..S_{nsteps} with nslots restart slots.  Writes up to cap actions
  * (op, a, b) into actions[3*i..3*i+2] and the count into *count:

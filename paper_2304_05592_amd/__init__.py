@@ -6,16 +6,19 @@ operators itself, and nothing falls back to the CPU.
 """
 from .binding import (EXPORTS, LIB_PATH, PREC_BF16, PREC_FP16, PREC_FP32, STORE_CHECKPOINT,
                       STORE_FULL, STORE_NONE, AweError, Plan, ShotGeometry, Storage,
-                      checkpoint_schedule, dot, lib, residual, slowness2, velocity_gradient)
+                      checkpoint_schedule, dot, lib, patchy, patchy_vjp, residual, slowness2,
+                      velocity_gradient)
 
 __all__ = ["EXPORTS", "LIB_PATH", "PREC_BF16", "PREC_FP16", "PREC_FP32", "STORE_CHECKPOINT",
            "STORE_FULL", "STORE_NONE", "AweError", "Plan", "ShotGeometry", "Storage",
-           "checkpoint_schedule", "dot", "lib", "residual", "slowness2", "velocity_gradient", "WaveOp",
-           "wave_forward", "extend_edge", "misfit", "Slowness2", "slowness2_from_velocity"]
+           "checkpoint_schedule", "dot", "lib", "patchy", "patchy_vjp", "residual", "slowness2",
+           "velocity_gradient", "WaveOp", "wave_forward", "extend_edge", "misfit", "Slowness2",
+           "slowness2_from_velocity", "Patchy", "patchy_rock_physics"]
 
 
 def __getattr__(name):
-    if name in ("WaveOp", "wave_forward", "extend_edge", "misfit", "Slowness2", "slowness2_from_velocity"):
+    if name in ("WaveOp", "wave_forward", "extend_edge", "misfit", "Slowness2", "slowness2_from_velocity",
+                "Patchy", "patchy_rock_physics"):
         from . import autograd
         return getattr(autograd, name)
     raise AttributeError(name)

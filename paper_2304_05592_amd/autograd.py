@@ -90,6 +90,37 @@ def slowness2_from_velocity(v: torch.Tensor) -> torch.Tensor:
     return Slowness2.apply(v)
 
 
+class Patchy(torch.autograd.Function):
+    """Rock physics R of "Putting it all together": (vp_new, rho_new) from the CO2 saturation
+    with the rock's wavespeed, density and porosity held fixed (library kernels).  The pullback
+    reaches the saturation only; asking for gradients of vp, rho or phi is an error."""
+
+    @staticmethod
+    def forward(ctx, sw, vp, rho, phi, consts):
+        from .binding import patchy
+        if any(t.requires_grad for t in (vp, rho, phi)):
+            raise NotImplementedError("patchy_rock_physics differentiates in the saturation only")
+        f32 = lambda t: t.detach().to(torch.float32).contiguous()
+        args = tuple(f32(t) for t in (sw, vp, rho, phi))
+        ctx.save_for_backward(*args)
+        ctx.consts, ctx.sw_dtype = consts, sw.dtype
+        return patchy(*args, consts=consts)
+
+    @staticmethod
+    def backward(ctx, g_vp, g_rho):
+        from .binding import patchy_vjp
+        sw, vp, rho, phi = ctx.saved_tensors
+        f32 = lambda t: None if t is None else t.detach().to(torch.float32).contiguous()
+        g_vp = torch.zeros_like(vp) if g_vp is None else f32(g_vp)
+        g_sw = patchy_vjp(sw, vp, rho, phi, g_vp, f32(g_rho), consts=ctx.consts)
+        return g_sw.to(ctx.sw_dtype), None, None, None, None
+
+
+def patchy_rock_physics(sw, vp, rho, phi, consts=None):
+    """Differentiable (in sw) patchy-saturation map: returns (vp_new, rho_new)."""
+    return Patchy.apply(sw, vp, rho, phi, consts)
+
+
 def misfit(d: torch.Tensor, d_obs: torch.Tensor) -> torch.Tensor:
     """Differentiable 1/2 ||d - d_obs||^2 (FP64 scalar)."""
     return Misfit.apply(d, d_obs)

@@ -26,13 +26,18 @@ EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "aw
            "awe_backward", "awe_gradient", "awe_adjoint", "awe_born", "awe_reduce_workspace_size",
            "awe_residual", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
            "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
-           "awe_slowness2", "awe_velocity_gradient", "awe_status_string", "awe_last_error", "awe_version"]
+           "awe_slowness2", "awe_velocity_gradient", "awe_patchy", "awe_patchy_vjp", "awe_status_string", "awe_last_error", "awe_version"]
 
 
 class AweError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"awe status {STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+class AwePatchyConsts(ctypes.Structure):
+    _fields_ = [("k_min", ctypes.c_double), ("k_brine", ctypes.c_double), ("k_co2", ctypes.c_double),
+                ("rho_co2", ctypes.c_double), ("rho_brine", ctypes.c_double)]
 
 
 class AweShot(ctypes.Structure):
@@ -90,6 +95,9 @@ def lib():
     L.awe_plan_set_groups.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.awe_slowness2.argtypes = [vp, vp, i64, vp]
     L.awe_velocity_gradient.argtypes = [vp, vp, vp, i64, vp]
+    pc = ctypes.POINTER(AwePatchyConsts)
+    L.awe_patchy.argtypes = [vp, vp, vp, vp, vp, vp, i64, pc, vp]
+    L.awe_patchy_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, pc, vp]
     L.awe_profile_enable.argtypes = [vp, i64, ctypes.c_int32]
     L.awe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.awe_profile_disable.argtypes = [vp]
@@ -100,7 +108,8 @@ def lib():
     for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
                  "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_dot_f64",
                  "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion",
-                 "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_profile_enable",
+                 "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_patchy",
+                 "awe_patchy_vjp", "awe_profile_enable",
                  "awe_profile_read", "awe_profile_disable"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -434,6 +443,46 @@ def velocity_gradient(v, gm, gv=None, stream=None):
     gv = torch.empty_like(v) if gv is None else gv
     check(lib().awe_velocity_gradient(_ptr(v), _ptr(gm), _ptr(gv), v.numel(), _stream_ptr(stream)))
     return gv
+
+
+def _patchy_args(tensors, consts):
+    import torch
+    n = tensors[0][0].numel()
+    for t, name in tensors:
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n:
+            raise TypeError(f"{name} must be a contiguous float32 tensor of {n} values")
+    c = None
+    if consts is not None:
+        c = ctypes.byref(AwePatchyConsts(consts["k_min"], consts["k_brine"], consts["k_co2"],
+                                         consts["rho_co2"], consts["rho_brine"]))
+    return n, c
+
+
+def patchy(sw, vp, rho, phi, consts=None, stream=None):
+    """Patchy-saturation rock physics: (vp_new, rho_new) from CO2 saturation sw, wavespeed vp
+    (km/s), density rho (kg/m^3) and porosity phi (float32 device tensors of one size; FP64
+    arithmetic).  consts: dict with k_min, k_brine, k_co2, rho_co2, rho_brine (None: the
+    paper's values)."""
+    import torch
+    n, c = _patchy_args([(sw, "sw"), (vp, "vp"), (rho, "rho"), (phi, "phi")], consts)
+    vp_new, rho_new = torch.empty_like(vp), torch.empty_like(rho)
+    check(lib().awe_patchy(_ptr(sw), _ptr(vp), _ptr(rho), _ptr(phi), _ptr(vp_new), _ptr(rho_new), n, c,
+                           _stream_ptr(stream)))
+    return vp_new, rho_new
+
+
+def patchy_vjp(sw, vp, rho, phi, g_vp, g_rho=None, consts=None, stream=None):
+    """g_sw = g_vp dvp_new/dsw + g_rho drho_new/dsw (g_rho None: 0)."""
+    import torch
+    ts = [(sw, "sw"), (vp, "vp"), (rho, "rho"), (phi, "phi"), (g_vp, "g_vp")]
+    if g_rho is not None:
+        ts.append((g_rho, "g_rho"))
+    n, c = _patchy_args(ts, consts)
+    g_sw = torch.empty_like(sw)
+    check(lib().awe_patchy_vjp(_ptr(sw), _ptr(vp), _ptr(rho), _ptr(phi), _ptr(g_vp),
+                               None if g_rho is None else _ptr(g_rho), _ptr(g_sw), n, c,
+                               _stream_ptr(stream)))
+    return g_sw
 
 
 def dot(a, b, stream=None):

@@ -1194,6 +1194,32 @@ awe_status awe_velocity_gradient(const float* v, const float* gm, float* gv, int
   return AWE_OK;
 }
 
+namespace {
+awe::PatchyConsts patchy_consts(const awe_patchy_consts* c) {
+  if (c) return {c->k_min, c->k_brine, c->k_co2, c->rho_co2, c->rho_brine};
+  return {36.6e9, 2.735e9, 0.125e9, 700.0, 1000.0};
+}
+}  // namespace
+
+awe_status awe_patchy(const float* s, const float* vp, const float* rho, const float* phi, float* vp_new,
+                      float* rho_new, int64_t n, const awe_patchy_consts* c, void* stream) {
+  if (n < 0 || (n > 0 && (!s || !vp || !rho || !phi || !vp_new)))
+    return fail(AWE_ERR_INVALID_ARG, "bad patchy arguments");
+  AWE_HIP(awe::launch_patchy(s, vp, rho, phi, vp_new, rho_new, n, patchy_consts(c),
+                             static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
+awe_status awe_patchy_vjp(const float* s, const float* vp, const float* rho, const float* phi,
+                          const float* g_vp, const float* g_rho, float* g_s, int64_t n,
+                          const awe_patchy_consts* c, void* stream) {
+  if (n < 0 || (n > 0 && (!s || !vp || !rho || !phi || !g_vp || !g_s)))
+    return fail(AWE_ERR_INVALID_ARG, "bad patchy vjp arguments");
+  AWE_HIP(awe::launch_patchy_vjp(s, vp, rho, phi, g_vp, g_rho, g_s, n, patchy_consts(c),
+                                 static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
 awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions, int64_t cap,
                                    int64_t* count) {
   if (nsteps < 0 || nslots < 0 || !count || (cap > 0 && !actions))

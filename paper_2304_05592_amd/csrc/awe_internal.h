@@ -177,6 +177,14 @@ hipError_t launch_grad_reduce(const Tables& t, int nwin, long long max_npts, uns
 hipError_t launch_slowness2(const float* v, float* m, long long n, hipStream_t stream);
 hipError_t launch_velocity_gradient(const float* v, const float* gm, float* gv, long long n,
                                     hipStream_t stream);
+struct PatchyConsts {
+  double k_min, k_brine, k_co2, rho_co2, rho_brine;
+};
+hipError_t launch_patchy(const float* s, const float* vp, const float* rho, const float* phi,
+                         float* vp_new, float* rho_new, long long n, PatchyConsts c, hipStream_t stream);
+hipError_t launch_patchy_vjp(const float* s, const float* vp, const float* rho, const float* phi,
+                             const float* g_vp, const float* g_rho, float* g_s, long long n,
+                             PatchyConsts c, hipStream_t stream);
 hipError_t launch_residual(const float* a, const float* b, float* r, long long n, double* loss,
                            unsigned char* ws, hipStream_t stream);
 hipError_t launch_dot(const float* a, const float* b, long long n, double* out, unsigned char* ws,

@@ -4,6 +4,9 @@
 #include "awe_internal.h"
 #include "codec.h"
 
+#include <cstdint>
+#include <initializer_list>
+
 namespace awe {
 
 namespace {
@@ -217,6 +220,132 @@ __global__ void velocity_grad_kernel(const float* v, const float* gm, float* gv,
   }
 }
 
+// Patchy saturation.  With P1 = rho vp^2 (brine rock), mu = P1 / 3, K1 = 5 P1 / 9 and
+// r(K) = K / (k_min - K), Gassmann's fluid swap r(K2) = r(K1) + D / phi (D = r(k_co2) - r(k_brine))
+// gives, with a = k_min - K1, B = K1 phi + D a and Q = k_min phi + D a:  K2 = k_min B / Q.  The
+// CO2 rock's P-wave modulus is P2 = N / Q with N = k_min B + 4/9 P1 Q, the harmonic patchy mix is
+// 1/M = Den / (P1 N) with Den = (1 - s) N + s Q P1, and vp_new^2 = M / rho_new, so
+//     vp_new = vp sqrt(rho N / (rho_new Den)),
+//     dvp_new/ds = -vp_new / 2 (phi drho Den + (Q P1 - N) rho_new) / (rho_new Den),
+// one FP64 division and one square root per cell (drho = rho_co2 - rho_brine).
+struct PatchyPre {
+  double k_min, d, drho;
+};
+
+struct PatchyOut {
+  double vp_new, rho_new, dvp;
+};
+
+template <bool kVjp>
+__device__ __forceinline__ PatchyOut patchy_eval(double s, double v, double rho, double phi,
+                                                 const PatchyPre& c) {
+  const double p1 = 1e6 * rho * v * v;           // vp in km/s -> Pa
+  const double a = c.k_min - (5.0 / 9.0) * p1;
+  const double b = (5.0 / 9.0) * p1 * phi + c.d * a;
+  const double q = c.k_min * phi + c.d * a;
+  const double nn = c.k_min * b + (4.0 / 9.0) * p1 * q;
+  const double den = (1.0 - s) * nn + s * q * p1;
+  PatchyOut o;
+  o.rho_new = rho + phi * s * c.drho;
+  const double inv = 1.0 / (o.rho_new * den);
+  o.vp_new = v * sqrt(rho * nn * inv);
+  o.dvp = kVjp ? -0.5 * o.vp_new * (phi * c.drho * den + (q * p1 - nn) * o.rho_new) * inv : 0.0;
+  return o;
+}
+
+// Streamed once: 16-byte nontemporal loads and stores (the arrays are not reused by the next
+// kernel from the cache).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 ld_nt4(const float* p, long long g) {
+  return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + g);
+}
+
+__device__ __forceinline__ void st_nt4(float* p, long long g, float a, float b, float c, float d) {
+  const f32x4 v = {a, b, c, d};
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p) + g);
+}
+
+// Four cells per thread with 16-byte loads when every array is 16-byte aligned (VEC 4), else
+// one cell per thread (VEC 1); one group per thread over a grid that covers the array (the
+// stride loop only matters past 2^30 workgroups), the last n % VEC cells by the first threads.
+template <int VEC>
+__global__ void patchy_kernel(const float* __restrict__ s, const float* __restrict__ vp,
+                              const float* __restrict__ rho, const float* __restrict__ phi,
+                              float* __restrict__ vp_new, float* __restrict__ rho_new, long long n,
+                              PatchyPre c) {
+  const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long ng = n / VEC;
+  for (long long g = tid; g < ng; g += stride) {
+    if constexpr (VEC == 4) {
+      const f32x4 S = ld_nt4(s, g), V = ld_nt4(vp, g), R = ld_nt4(rho, g), F = ld_nt4(phi, g);
+      const PatchyOut o0 = patchy_eval<false>(S.x, V.x, R.x, F.x, c);
+      const PatchyOut o1 = patchy_eval<false>(S.y, V.y, R.y, F.y, c);
+      const PatchyOut o2 = patchy_eval<false>(S.z, V.z, R.z, F.z, c);
+      const PatchyOut o3 = patchy_eval<false>(S.w, V.w, R.w, F.w, c);
+      st_nt4(vp_new, g, (float)o0.vp_new, (float)o1.vp_new, (float)o2.vp_new, (float)o3.vp_new);
+      if (rho_new)
+        st_nt4(rho_new, g, (float)o0.rho_new, (float)o1.rho_new, (float)o2.rho_new, (float)o3.rho_new);
+    } else {
+      const PatchyOut o = patchy_eval<false>(s[g], vp[g], rho[g], phi[g], c);
+      vp_new[g] = (float)o.vp_new;
+      if (rho_new) rho_new[g] = (float)o.rho_new;
+    }
+  }
+  const long long i = ng * VEC + tid;
+  if (VEC > 1 && i < n) {
+    const PatchyOut o = patchy_eval<false>(s[i], vp[i], rho[i], phi[i], c);
+    vp_new[i] = (float)o.vp_new;
+    if (rho_new) rho_new[i] = (float)o.rho_new;
+  }
+}
+
+// g_s = g_vp dvp_new/ds + g_rho phi drho (g_rho may be null).
+template <int VEC>
+__global__ void patchy_vjp_kernel(const float* __restrict__ s, const float* __restrict__ vp,
+                                  const float* __restrict__ rho, const float* __restrict__ phi,
+                                  const float* __restrict__ g_vp, const float* __restrict__ g_rho,
+                                  float* __restrict__ g_s, long long n, PatchyPre c) {
+  const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long ng = n / VEC;
+  auto one = [&](float sv, float vv, float rv, float fv, float gv, float gr) {
+    const PatchyOut o = patchy_eval<true>(sv, vv, rv, fv, c);
+    return (float)((double)gv * o.dvp + (double)gr * (double)fv * c.drho);
+  };
+  for (long long g = tid; g < ng; g += stride) {
+    if constexpr (VEC == 4) {
+      const f32x4 S = ld_nt4(s, g), V = ld_nt4(vp, g), R = ld_nt4(rho, g), F = ld_nt4(phi, g);
+      const f32x4 G = ld_nt4(g_vp, g);
+      const f32x4 H = g_rho ? ld_nt4(g_rho, g) : f32x4{0.f, 0.f, 0.f, 0.f};
+      st_nt4(g_s, g, one(S.x, V.x, R.x, F.x, G.x, H.x), one(S.y, V.y, R.y, F.y, G.y, H.y),
+             one(S.z, V.z, R.z, F.z, G.z, H.z), one(S.w, V.w, R.w, F.w, G.w, H.w));
+    } else {
+      g_s[g] = one(s[g], vp[g], rho[g], phi[g], g_vp[g], g_rho ? g_rho[g] : 0.f);
+    }
+  }
+  const long long i = ng * VEC + tid;
+  if (VEC > 1 && i < n) g_s[i] = one(s[i], vp[i], rho[i], phi[i], g_vp[i], g_rho ? g_rho[i] : 0.f);
+}
+
+PatchyPre patchy_pre(const PatchyConsts& c) {
+  auto r = [&](double k) { return k / (c.k_min - k); };
+  return {c.k_min, r(c.k_co2) - r(c.k_brine), c.rho_co2 - c.rho_brine};
+}
+
+// Workgroups covering `units` threads (capped at 2^30; kernels stride beyond that).
+int grid_cover(long long units) {
+  const long long b = (units + kThreads - 1) / kThreads;
+  return (int)(b < 1 ? 1 : (b > (1LL << 30) ? (1LL << 30) : b));
+}
+
+bool aligned16(std::initializer_list<const void*> ps) {
+  for (const void* p : ps)
+    if (p && (reinterpret_cast<uintptr_t>(p) & 15u)) return false;
+  return true;
+}
+
 int grid_for(long long n) {
   long long b = (n + kThreads - 1) / kThreads;
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
@@ -289,6 +418,29 @@ hipError_t launch_velocity_gradient(const float* v, const float* gm, float* gv, 
                                     hipStream_t s) {
   if (n <= 0) return hipSuccess;
   velocity_grad_kernel<<<grid_for(n), kThreads, 0, s>>>(v, gm, gv, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_patchy(const float* s, const float* vp, const float* rho, const float* phi,
+                         float* vp_new, float* rho_new, long long n, PatchyConsts c, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const PatchyPre pre = patchy_pre(c);
+  if (aligned16({s, vp, rho, phi, vp_new, rho_new}))
+    patchy_kernel<4><<<grid_cover(n / 4), kThreads, 0, st>>>(s, vp, rho, phi, vp_new, rho_new, n, pre);
+  else
+    patchy_kernel<1><<<grid_cover(n), kThreads, 0, st>>>(s, vp, rho, phi, vp_new, rho_new, n, pre);
+  return hipGetLastError();
+}
+
+hipError_t launch_patchy_vjp(const float* s, const float* vp, const float* rho, const float* phi,
+                             const float* g_vp, const float* g_rho, float* g_s, long long n,
+                             PatchyConsts c, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const PatchyPre pre = patchy_pre(c);
+  if (aligned16({s, vp, rho, phi, g_vp, g_rho, g_s}))
+    patchy_vjp_kernel<4><<<grid_cover(n / 4), kThreads, 0, st>>>(s, vp, rho, phi, g_vp, g_rho, g_s, n, pre);
+  else
+    patchy_vjp_kernel<1><<<grid_cover(n), kThreads, 0, st>>>(s, vp, rho, phi, g_vp, g_rho, g_s, n, pre);
   return hipGetLastError();
 }
 

@@ -155,3 +155,14 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_patchy_argument_checks_raise_before_any_device_call():
+    import torch
+    a = torch.zeros(5)
+    with pytest.raises(TypeError):
+        A.patchy(a, a, a, torch.zeros(4))             # size mismatch
+    with pytest.raises(TypeError):
+        A.patchy_vjp(a, a, a, a, a.double())          # wrong dtype
+    with pytest.raises(NotImplementedError):
+        A.patchy_rock_physics(a, a.clone().requires_grad_(True), a, a)

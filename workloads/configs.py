@@ -328,14 +328,26 @@ def saturation_field(shape, seed: int = 8, zero_frac: float = 0.3, one_frac: flo
 
 
 def timelapse_survey(name="c6_timelapse", nx=512, nz=256, h=6.25, T=1200.0, nvint=15, nsrc=32, nrec=960,
-                     shots_per_vintage=4, iteration=0, seed=6, drop=0.05, nbl=40) -> Workload:
+                     shots_per_vintage=4, iteration=0, seed=6, drop=0.05, nbl=40,
+                     rock_seed=None, saturation=0.9) -> Workload:
     """Time-lapse crosswell survey: vintages i = 1..nvint share a layered baseline and differ by
     a growing low-wavespeed plume (v^i = v_base (1 - drop * plume_i)); sources in the left well,
     receivers in the right well.  One inversion iteration draws `shots_per_vintage` of the nsrc
     sources per vintage with replacement (seeded by `iteration`); shot s runs on window = its
-    vintage.  The starting model of every vintage is the smoothed baseline."""
-    v_base = _layered_perturbed((nz, nx), h, seed)
-    vs = [v_base * (1.0 - drop * plume_mask((nz, nx), h, i + 1, nvint)) for i in range(nvint)]
+    vintage.  The starting model of every vintage is the smoothed baseline.
+
+    With `rock_seed`, the medium is instead the brine-saturated reservoir rock of
+    `reservoir_rock` (vp, rho, phi) and vintage i is described by its CO2 saturation
+    `saturation * plume_i` (extra["sat"], physical grid); its wavespeed is the rock physics
+    map of that saturation, which the consumer evaluates.  v and v0 then hold the brine rock
+    (zero saturation), which bounds every vintage's wavespeed for this soft rock."""
+    rock = None
+    if rock_seed is not None:
+        rock = [a.astype(np.float64) for a in reservoir_rock((nz, nx), rock_seed)]
+        vs = [rock[0]] * nvint
+    else:
+        v_base = _layered_perturbed((nz, nx), h, seed)
+        vs = [v_base * (1.0 - drop * plume_mask((nz, nx), h, i + 1, nvint)) for i in range(nvint)]
     vmax = float(max(v.max() for v in vs))
     dt, nt = cfl_time_grid(T, h, vmax)
     xs, xr = 0.1 * (nx - 1) * h, 0.9 * (nx - 1) * h
@@ -348,19 +360,31 @@ def timelapse_survey(name="c6_timelapse", nx=512, nz=256, h=6.25, T=1200.0, nvin
     for i in range(nvint):
         for k in rng.integers(0, nsrc, size=shots_per_vintage):
             shots.append(Shot(i, nt, np.array([xs, 0.0, src_z[k]]), rec))
+    extra = {"src_z": src_z, "iteration": iteration}
+    desc = (f"2D time-lapse crosswell, {nx}x{nz} @ {h} m, {nvint} vintages x {shots_per_vintage} "
+            f"of {nsrc} shots (with replacement), {nrec} receivers, T = {T / 1000:g} s")
+    if rock is not None:
+        extra.update(vp=rock[0], rho=rock[1], phi=rock[2],
+                     sat=[saturation * plume_mask((nz, nx), h, i + 1, nvint) for i in range(nvint)])
+        return Workload(name, 2, h, nbl, dt, 0.015, vmax, 0.4, vs, shots,
+                        desc + f", reservoir rock, CO2 saturation up to {saturation:g}",
+                        v0=list(vs), extra=extra)
     v0 = smooth_background(v_base, h)
-    return Workload(name, 2, h, nbl, dt, 0.015, vmax, 0.4, vs, shots,
-                    f"2D time-lapse crosswell, {nx}x{nz} @ {h} m, {nvint} vintages x {shots_per_vintage} "
-                    f"of {nsrc} shots (with replacement), {nrec} receivers, T = {T / 1000:g} s",
-                    v0=[v0] * nvint, extra={"src_z": src_z, "iteration": iteration})
+    return Workload(name, 2, h, nbl, dt, 0.015, vmax, 0.4, vs, shots, desc, v0=[v0] * nvint,
+                    extra=extra)
 
 
 def _c6() -> Workload:
     return timelapse_survey()
 
 
+def _c7() -> Workload:
+    return timelapse_survey("c7_timelapse_rock", rock_seed=7)
+
+
 _CONFIGS = {"c1_fwd": _c1, "c2_grad": _c2, "c3_autograd": _c3, "c4_uneven": _c4,
-            "c5_3d": _c5, "c5_crop": _c5_crop, "c6_timelapse": _c6}
+            "c5_3d": _c5, "c5_crop": _c5_crop, "c6_timelapse": _c6,
+            "c7_timelapse_rock": _c7}
 
 
 def config_names():
@@ -369,7 +393,7 @@ def config_names():
 
 def make_config(name: str) -> Workload:
     """Build one of the named workloads (c1_fwd, c2_grad, c3_autograd, c4_uneven, c5_3d, c5_crop,
-    c6_timelapse)."""
+    c6_timelapse, c7_timelapse_rock)."""
     return _CONFIGS[name]()
 
 
