@@ -12,7 +12,8 @@ Other workloads (--config): c1_fwd (single-shot 2D forward, 201 x 101, graph vs 
 c3_autograd (torch.autograd through the wave operator with 16
 checkpoint slots per shot, 32 shots), c6_timelapse (15-vintage crosswell time-lapse gradient
 with respect to wavespeed, 4 sampled shots per vintage), c7_timelapse_rock (the same iteration
-with respect to CO2 saturation through the patchy rock physics), c4_uneven (64 uneven windows, forward, batched vs 64
+with respect to CO2 saturation through the patchy rock physics), c8_born (batched Born
+modelling of the c2_grad survey), c4_uneven (64 uneven windows, forward, batched vs 64
 sequential single-shot runs), c5_3d (256^3, FULL BF16 / FP16 storage gradient).
 
 Prints one JSON line.  Gpts/s = sum over shots of N_s (nt_s - 1) per step / step time
@@ -47,6 +48,7 @@ BYTES = {
     ("forward2", "none"): 20,   # read u^{k-1}, u^{k-2}, coef; write u^k, u^{k+1}
     ("forward2", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
     ("adjoint2", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
+    ("born", "none"): 32,       # read u^{k-1}, u^{k-2}, du^{k-1}, du^{k-2}, coef, dm; write u^k, du^k
 }
 
 
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_grad",
                     choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse",
-                             "c7_timelapse_rock"])
+                             "c7_timelapse_rock", "c8_born"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
@@ -629,6 +631,73 @@ def bench_c7(args):
         "grad_norm": float(g.norm().item()), "rock_physics_kernels": rock})
 
 
+def bench_c8(args):
+    """Batched Born modelling dd = J(m0, q) dm of the c2_grad survey (16 shots, dm = m - m0):
+    background and scattered wavefields advanced together by one fused kernel per time step,
+    the whole pass captured into a HIP graph and replayed."""
+    import torch
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    plan = make_plan(wl, A.Storage(A.STORE_NONE), range(wl.nshot))
+    m0 = plan.pack([wl.m(0, background=True)], "m")
+    dm = plan.pack([wl.m(0) - wl.m(0, background=True)], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    ws = plan.workspace()
+    dd = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
+    tiles = choose_tiles(plan, args, m0, q, None, ws)
+    groups = plan.set_groups(args.groups)
+    points, launch_points = points_of(wl, range(wl.nshot))
+    launch_points //= groups
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.born(m0, q, dm, dd=dd, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    sync()
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            plan.born(m0, q, dm, dd=dd, ws=ws)
+        sync()
+    run = (lambda: graph.replay()) if graph is not None else (lambda: plan.born(m0, q, dm, dd=dd, ws=ws))
+    for _ in range(args.warmup):
+        run()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    nt = wl.shots[0].nt
+    plan.profile_enable(groups * nt + 64, 1)
+    plan.born(m0, q, dm, dd=dd, ws=ws)
+    prof = plan.profile_read()
+    plan.profile_disable()
+    kernels = kernel_table(prof, launch_points, {"born": "none"})
+    k = kernels["born"]
+    k["eager_event_us"] = k["avg_us"]
+    timing = "HIP events around every launch of one eager pass"
+    if graph is not None:
+        # graph replay: the pass's time over its step launches (fills and the last gather included)
+        avg_s = sec / (k["launches_timed"] // groups * groups)
+        k["avg_us"] = round(avg_s * 1e6, 3)
+        k["achieved_GBs"] = round(k["bytes_per_launch"] / avg_s / 1e9, 1)
+        timing = ("graph replay time per pass / step launches of the pass (auxiliary kernels included); "
+                  "eager_event_us = HIP events around every launch of one eager pass")
+    names = {"born": "born2d step (background + scattered field, 32 B/point)"}
+    return base_line(args, wl, points / sec / 1e9, sec, {
+        "metric": "Gpts/s Born modelling J dm (batched, 16 shots)",
+        "config": {"workload": "c8_born: Born modelling of the c2_grad survey (650x341 @ 6.25 m + 40-cell "
+                               "border, 16 shots, 650 receivers, T = 1.8 s), dm = true model - smoothed "
+                               "background, no wavefield storage",
+                   "grid": list(wl.comp_shape(0)), "shots": wl.nshot, "nt": int(nt), "storage": "none",
+                   "batched": True, "graph": graph is not None, "tiles": tiles, "shot_groups": groups},
+        "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
+        "kernel_timing": timing, "dd_norm": float(dd.norm().item())})
+
+
 def bench_c4(args):
     """64 uneven windows, forward: one batched graph-captured run vs 64 sequential runs."""
     import torch
@@ -738,7 +807,7 @@ def main():
         return
     fn = {"c1_fwd": bench_c1, "c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4,
           "c5_3d": bench_c5, "c6_timelapse": bench_c6,
-          "c7_timelapse_rock": bench_c7}[args.config]
+          "c7_timelapse_rock": bench_c7, "c8_born": bench_c8}[args.config]
     print(json.dumps(fn(args)), flush=True)
 
 

@@ -13,12 +13,12 @@ __all__ = ["EXPORTS", "LIB_PATH", "PREC_BF16", "PREC_FP16", "PREC_FP32", "STORE_
            "STORE_FULL", "STORE_NONE", "AweError", "Plan", "ShotGeometry", "Storage",
            "checkpoint_schedule", "dot", "lib", "patchy", "patchy_vjp", "residual", "slowness2",
            "velocity_gradient", "WaveOp", "wave_forward", "extend_edge", "misfit", "Slowness2",
-           "slowness2_from_velocity", "Patchy", "patchy_rock_physics"]
+           "slowness2_from_velocity", "Patchy", "patchy_rock_physics", "BornOp", "born_forward"]
 
 
 def __getattr__(name):
     if name in ("WaveOp", "wave_forward", "extend_edge", "misfit", "Slowness2", "slowness2_from_velocity",
-                "Patchy", "patchy_rock_physics"):
+                "Patchy", "patchy_rock_physics", "BornOp", "born_forward"):
         from . import autograd
         return getattr(autograd, name)
     raise AttributeError(name)

@@ -49,6 +49,40 @@ class WaveOp(torch.autograd.Function):
         return gm, gq, None
 
 
+class BornOp(torch.autograd.Function):
+    """dd = J(m, q) dm, the Born (linearised) data of a model perturbation dm about the background
+    m (section "Wave-equation-based inversion": the Jacobian whose transpose gives the gradient).
+    Linear in dm, so its pullback is the adjoint-state gradient J^T dy, which needs a plan with
+    FULL or CHECKPOINT storage.  m and q are the fixed background; asking for their gradients is
+    an error."""
+
+    @staticmethod
+    def forward(ctx, dm: torch.Tensor, m: torch.Tensor, q: torch.Tensor, plan: Plan):
+        if m.requires_grad or q.requires_grad:
+            raise NotImplementedError("born_forward differentiates in dm only (m and q are the background)")
+        f32 = lambda t: t.detach().to(torch.float32).contiguous()
+        mf, qf = f32(m), f32(q)
+        ws = plan.workspace(mf.device)
+        dd = plan.born(mf, qf, f32(dm), ws=ws)
+        ctx.plan, ctx.ws, ctx.dm_dtype = plan, ws, dm.dtype
+        ctx.save_for_backward(mf, qf)
+        return dd
+
+    @staticmethod
+    def backward(ctx, dy: torch.Tensor):
+        mf, qf = ctx.saved_tensors
+        if ctx.plan.storage.mode == STORE_NONE:
+            raise RuntimeError("the pullback of born_forward needs a plan with FULL or CHECKPOINT storage")
+        g, _, _ = ctx.plan.gradient(mf, qf, dy.detach().to(torch.float32).contiguous(), ws=ctx.ws)
+        ctx.ws = None
+        return g.to(ctx.dm_dtype), None, None, None
+
+
+def born_forward(dm: torch.Tensor, m: torch.Tensor, q: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable (in dm) Born modelling J(m, q) dm."""
+    return BornOp.apply(dm, m, q, plan)
+
+
 class Misfit(torch.autograd.Function):
     """phi = 1/2 ||d - d_obs||^2 on the library's residual kernel (FP64 accumulation); the
     pullback of phi is r = d - d_obs (the loss of the paper's AD listing)."""

@@ -389,6 +389,12 @@ class Plan:
                                 _stream_ptr(stream)))
         return v
 
+    def rtm(self, m, q, d, ws=None, stream=None):
+        """Reverse-time migration image J(m, q)^T d of recorded data d (FP64, packed like m): the
+        adjoint-state imaging condition applied to the data themselves, i.e. the gradient sweep
+        with d in place of a residual (needs FULL or CHECKPOINT storage)."""
+        return self.gradient(m, q, d, ws=ws, stream=stream)[0]
+
     def born(self, m, q, dm, dd=None, ws=None, stream=None):
         """dd = J(m, q) dm (packed traces)."""
         import torch

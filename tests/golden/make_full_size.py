@@ -8,13 +8,15 @@ shots in ascending order) and a seeded sample of the outputs is stored:
   c2_grad_full.npz    16 shots on the 421 x 730 grid, 3638 samples per shot
   c4_uneven_full.npz  64 shots, each on its own window (widths 256..1024, 1.0..2.5 s)
   c5_crop_full.npz    the 64^3 crop of the 3D model (144^3 with the sponge)
+  c2_born_full.npz    Born traces J(m0) dm of the 16 c2_grad shots, dm = m - m0 (the
+                      model minus its smoothed background, float32)
 
 Gradient samples are flat indices into each window's computational grid (the
 same number per window); trace samples are every TIME_STRIDE-th time sample of
 every REC_STRIDE-th receiver.
 
 Run from the repository root:
-    python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop]
+    python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop] [c2_born]
 The 2D sets take minutes on 8 cores, the 3D crop about half an hour.
 """
 from __future__ import annotations
@@ -58,6 +60,41 @@ def _shot(args):
     return s, g, d
 
 
+def born_perturbation(wl, w=0):
+    """dm = m - m0 of window w in float32 (the true model minus the smoothed background)."""
+    return wl.m(w) - wl.m(w, background=True)
+
+
+def _born_shot(s):
+    import oracle as O
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    sh = wl.shots[s]
+    t0 = time.perf_counter()
+    d = O.born(wl.m(sh.window, background=True), wl.q(s), born_perturbation(wl, sh.window), sh.src,
+               sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax)
+    print(f"  c2_born shot {s}: {time.perf_counter() - t0:.1f} s", flush=True)
+    return s, d
+
+
+def make_born(workers):
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    with mp.get_context("spawn").Pool(min(workers, wl.nshot)) as pool:
+        res = sorted(pool.map(_born_shot, range(wl.nshot)), key=lambda r: r[0])
+    out = {}
+    for s, d in res:
+        nt, nrec = d.shape
+        ti = np.arange(0, nt, TIME_STRIDE)
+        ri = np.arange(0, nrec, REC_STRIDE["c2_grad"])
+        out[f"trace_t_{s}"] = ti.astype(np.int64)
+        out[f"trace_r_{s}"] = ri.astype(np.int64)
+        out[f"trace_value_{s}"] = d[np.ix_(ti, ri)]
+    path = os.path.join(ROOT, "tests", "golden", "c2_born_full.npz")
+    np.savez_compressed(path, **out)
+    print(f"wrote {path}", flush=True)
+
+
 def make(name, workers):
     import workloads as W
     wl = W.make_config(name)
@@ -96,7 +133,7 @@ def main():
     workers = min(8, len(os.sched_getaffinity(0)))
     for name in names:
         t0 = time.perf_counter()
-        make(name, workers)
+        make_born(workers) if name == "c2_born" else make(name, workers)
         print(f"{name}: {time.perf_counter() - t0:.1f} s", flush=True)
 
 

@@ -166,3 +166,10 @@ def test_patchy_argument_checks_raise_before_any_device_call():
         A.patchy_vjp(a, a, a, a, a.double())          # wrong dtype
     with pytest.raises(NotImplementedError):
         A.patchy_rock_physics(a, a.clone().requires_grad_(True), a, a)
+
+
+def test_born_forward_refuses_gradients_of_the_background():
+    import torch
+    z = torch.zeros(3)
+    with pytest.raises(NotImplementedError):
+        A.born_forward(z, z.clone().requires_grad_(True), z, None)

@@ -42,3 +42,20 @@ def test_fixture_trace_prefix(name, shot, n):
         assert idx.shape == val.shape and idx.max() < int(np.prod(wl.comp_shape(w)))
         assert np.isfinite(val).all()
     assert np.abs(gold["trace_value_0"]).max() > 0
+
+
+@pytest.mark.parametrize("shot,n", [(0, 240), (11, 240)])
+def test_born_fixture_trace_prefix(shot, n):
+    path = os.path.join(GOLD, "c2_born_full.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    gold = np.load(path)
+    wl = W.make_config("c2_grad")
+    sh = wl.shots[shot]
+    d = O.born(wl.m(0, background=True), wl.q(shot)[:n], G.born_perturbation(wl), sh.src, sh.rec, h=wl.h,
+               dt=wl.dt, nbl=wl.nbl, vref=wl.vmax)
+    ti, ri = gold[f"trace_t_{shot}"], gold[f"trace_r_{shot}"]
+    keep = ti < n
+    np.testing.assert_allclose(d[np.ix_(ti[keep], ri)], gold[f"trace_value_{shot}"][keep], rtol=0,
+                               atol=1e-12 * np.abs(d).max())
+    assert np.abs(d).max() > 0 and np.abs(gold[f"trace_value_{shot}"]).max() > 0

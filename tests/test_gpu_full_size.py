@@ -7,7 +7,8 @@ full wavefields would not fit) and are compared with oracle samples that
 tests/golden/make_full_size.py stored (FP64, same seeded inputs):
 receiver traces of every shot at the background model (every 32nd time sample
 of every k-th receiver) and the adjoint-state gradient J^T dd for a seeded
-synthetic residual per shot, at 4096 seeded grid points (split over windows).
+synthetic residual per shot, at 4096 seeded grid points (split over windows);
+and the Born traces J(m0) dm of the c2_grad shots for dm = m - m0.
 
 Bar: rel-L2 over the samples <= 1e-5 with FP32 storage; with BF16 / FP16
 storage of the wavefield the gradient carries the storage rounding (unit
@@ -88,3 +89,41 @@ def test_c4_uneven_full_size():
 @pytest.mark.parametrize("prec,g_tol", [(A.PREC_FP32, TOL), (A.PREC_BF16, 2e-2), (A.PREC_FP16, 2e-3)])
 def test_c5_crop_full_size(prec, g_tol):
     _compare("c5_crop", prec, g_tol, TOL)
+
+
+@pytest.mark.gpu
+def test_c2_born_full_size():
+    """Batched Born modelling of the 16 c2_grad shots (dm = m - m0), in the launch configuration
+    the Born benchmark times (one plan, no storage, autotuned shape without a residual), against
+    the oracle's Born traces.
+
+    Bar 2e-5: the Born data come out of two stacked FP32 recursions (the background field,
+    whose rounding reaches the scattered field through its source term, and the scattered field
+    itself), each held to the 1e-5 trace bar.  Also J(2 dm) = 2 J(dm) up to rounding: every
+    operation of the linearised recursion scales exactly by two, except where values are
+    subnormal; such a difference flips a rounding somewhere in the 3638 steps and from there the
+    two runs differ by rounding noise."""
+    import torch
+    torch.cuda.empty_cache()
+    gold = _fixture("c2_born")
+    wl = W.make_config("c2_grad")
+    plan = make_plan(wl, A.Storage(A.STORE_NONE))
+    m = plan.pack([wl.m(0, background=True)], "m")
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    dm = plan.pack([G.born_perturbation(wl)], "m")
+    ws = plan.workspace()
+    tiles, _ = plan.autotune(m, q, None, probe_steps=32, ws=ws)
+    print(f"c2_born: autotuned {tiles}", flush=True)
+    dd = plan.born(m, q, dm, ws=ws)
+    dd2 = plan.born(m, q, 2.0 * dm, ws=ws)
+    torch.cuda.synchronize()
+    lin = float((dd2 - 2.0 * dd).norm() / (2.0 * dd).norm())
+    ds = plan.unpack(dd, "d")
+    got = np.concatenate([ds[s][np.ix_(gold[f"trace_t_{s}"], gold[f"trace_r_{s}"])].ravel()
+                          for s in range(wl.nshot)])
+    ref = np.concatenate([gold[f"trace_value_{s}"].ravel() for s in range(wl.nshot)])
+    err = _rel(got, ref)
+    print(f"c2_born: Born traces rel-L2 {err:.2e} ({ref.size} samples); J(2dm) vs 2 J(dm) rel-L2 {lin:.2e}",
+          flush=True)
+    assert np.isfinite(got).all() and err <= 2e-5
+    assert lin <= TOL
