@@ -74,22 +74,31 @@ __device__ __forceinline__ void ring_pos(int e, int* r, int* c) {
   }
 }
 
+// Loads in the z-march read clamped coordinates (rows past the grid read its last row, planes
+// past it its last plane, columns the padded row) and replace the value by 0 where the point
+// lies outside, so no load sits on a branch: the compiler can then count the loads in flight
+// exactly and keep the next planes' loads outstanding while it waits for the older ones.
+// nzv <= nz is the depth that may be read (0 for a level that is zero by definition).
+__device__ __forceinline__ long long cidx(int x, int y, int z, int ny, int nz, int px) {
+  const int xc = min(max(x, 0), px - 1), yc = min(max(y, 0), ny - 1), zc = min(max(z, 0), nz - 1);
+  return ((long long)zc * ny + yc) * px + xc;
+}
+
 template <int TY>
 __device__ __forceinline__ void ring_fetch(float (&h)[Ring<TY>::PER], const float* __restrict__ f,
-                                           int nx, int ny, int nz, int px, int x0, int y0, int z) {
-  const bool zin = (unsigned)z < (unsigned)nz;
-  const long long zb = (long long)z * ny;
+                                           int nx, int ny, int nzv, int nz, int px, int x0, int y0,
+                                           int z) {
+  const bool zin = (unsigned)z < (unsigned)nzv;
 #pragma unroll
   for (int i = 0; i < Ring<TY>::PER; ++i) {
-    const int e = threadIdx.x + i * T3<TY>::NT;
-    float v = 0.f;
-    if (e < Ring<TY>::COUNT && zin) {
-      int r, c;
-      ring_pos<TY>(e, &r, &c);
-      const int y = y0 - kHalo + r, x = x0 - kHalo + c;
-      if ((unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx) v = f[(zb + y) * px + x];
-    }
-    h[i] = v;
+    const int e0 = threadIdx.x + i * T3<TY>::NT;
+    const int e = e0 < Ring<TY>::COUNT ? e0 : Ring<TY>::COUNT - 1;
+    int r, c;
+    ring_pos<TY>(e, &r, &c);
+    const int y = y0 - kHalo + r, x = x0 - kHalo + c;
+    const float v = f[cidx(x, y, z, ny, nz, px)];
+    const bool in = e0 < Ring<TY>::COUNT && zin && (unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx;
+    h[i] = in ? v : 0.f;
   }
 }
 
@@ -122,9 +131,10 @@ __device__ __forceinline__ float lap3(const float (*P)[T3<TY>::W], const float* 
 }
 
 template <int TY>
-__device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny, int nz, int px,
-                                     int x, int y, int z) {
-  return (x < nx && y < ny && (unsigned)z < (unsigned)nz) ? f[((long long)z * ny + y) * px + x] : 0.f;
+__device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny, int nzv, int nz,
+                                     int px, int x, int y, int z) {
+  const float v = f[cidx(x, y, z, ny, nz, px)];
+  return (x < nx && y < ny && (unsigned)z < (unsigned)nzv) ? v : 0.f;
 }
 
 // ------------------------------------------------------------------------------ forward
@@ -161,6 +171,20 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   }
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
+  // shot fields used inside the z-march, copied to registers: stores through `out` could alias
+  // the shot table as far as the compiler knows, and reloading them would wait for every load
+  // in flight
+  const int src_i = S.src_i, src_j = S.src_j, src_k = S.src_k;
+  float srcw[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) srcw[i] = S.src_w[i];
+  auto src_weight = [&](int i) {
+    float w = srcw[0];
+#pragma unroll
+    for (int t = 1; t < 8; ++t) w = i == t ? srcw[t] : w;
+    return w;
+  };
+  float* st32 = SK == kStoreF32 ? reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts : nullptr;
   float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
   unsigned short* st16 = SK >= kStoreBF16
       ? reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts : nullptr;
@@ -176,45 +200,44 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz1, px, x, y, T.z0 - kHalo + t);
-    pu2[c] = ldc<TY>(u2, nx, ny, nz2, px, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz1, nz, px, x, y, T.z0 - kHalo + t);
+    pu2[c] = ldc<TY>(u2, nx, ny, nz2, nz, px, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0);
   }
   {
     float h[HP];
-    ring_fetch<TY>(h, u1, nx, ny, nz1, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(h, u1, nx, ny, nz1, nz, px, T.x0, T.y0, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
   }
   if (T.z0 + 1 < zend) {
-    ring_fetch<TY>(hA, u1, nx, ny, nz1, px, T.x0, T.y0, T.z0 + 1);
+    ring_fetch<TY>(hA, u1, nx, ny, nz1, nz, px, T.x0, T.y0, T.z0 + 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int y = T.y0 + g * NC + c;
-      qA[c] = ldc<TY>(u1, nx, ny, nz1, px, x, y, T.z0 + 1 + kHalo);
-      u2A[c] = ldc<TY>(u2, nx, ny, nz2, px, x, y, T.z0 + 1);
-      cfA[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0 + 1);
+      qA[c] = ldc<TY>(u1, nx, ny, nz1, nz, px, x, y, T.z0 + 1 + kHalo);
+      u2A[c] = ldc<TY>(u2, nx, ny, nz2, nz, px, x, y, T.z0 + 1);
+      cfA[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0 + 1);
     }
   }
-  for (int z = T.z0; z < zend; ++z) {
+  // One plane: hN.. hold the loads of plane z+1 (issued one plane earlier) and are consumed at
+  // the end; hL.. receive the loads of plane z+2.  The loop runs two planes per trip with the
+  // two register sets swapping roles, so no register that a load is still filling is copied
+  // (a copy would make every plane wait for the loads just issued).
+  float hB[HP] = {}, qB[NC] = {}, u2B[NC] = {}, cfB[NC] = {};
+  auto plane = [&](int z, float (&hN)[HP], float (&qN)[NC], float (&u2N)[NC], float (&cfN)[NC],
+                   float (&hL)[HP], float (&qL)[NC], float (&u2L)[NC], float (&cfL)[NC]) {
     const int b = (z - T.z0) & 1;
     __syncthreads();
-    float hB[HP], qB[NC], u2B[NC], cfB[NC];
-    if (z + 2 < zend) {
-      ring_fetch<TY>(hB, u1, nx, ny, nz1, px, T.x0, T.y0, z + 2);
+    // loads of plane z+2, unconditional (beyond the block they are simply not used)
+    ring_fetch<TY>(hL, u1, nx, ny, nz1, nz, px, T.x0, T.y0, z + 2);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int y = T.y0 + g * NC + c;
-        qB[c] = ldc<TY>(u1, nx, ny, nz1, px, x, y, z + 2 + kHalo);
-        u2B[c] = ldc<TY>(u2, nx, ny, nz2, px, x, y, z + 2);
-        cfB[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 2);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < HP; ++i) hB[i] = 0.f;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) qB[c] = u2B[c] = cfB[c] = 0.f;
+    for (int c = 0; c < NC; ++c) {
+      const int y = T.y0 + g * NC + c;
+      qL[c] = ldc<TY>(u1, nx, ny, nz1, nz, px, x, y, z + 2 + kHalo);
+      u2L[c] = ldc<TY>(u2, nx, ny, nz2, nz, px, x, y, z + 2);
+      cfL[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, z + 2);
     }
     const int dz = border_dist(z, nz, a.nbl);
 #pragma unroll
@@ -223,9 +246,9 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
       const int y = T.y0 + ly;
       if (x < nx && y < ny) {
         float lap = lap3<TY>(P[b], Q[c], ly, lane, a.c);
-        const int bx = x - S.src_i, by = y - S.src_j, bzz = z - S.src_k;
+        const int bx = x - src_i, by = y - src_j, bzz = z - src_k;
         if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
-          lap += S.src_w[bx + 2 * by + 4 * bzz] * qk;
+          lap += src_weight(bx + 2 * by + 4 * bzz) * qk;
         const int dy = border_dist(y, ny, a.nbl);
         const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
         const float u = Q[c][4];
@@ -233,8 +256,7 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
         const float un = (u + u - pu2[c]) + incr;
         const long long p = ((long long)z * ny + y) * px + x;
         out[p] = un;
-        if (SK == kStoreF32)
-          __builtin_nontemporal_store(un, reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts + p);
+        if (SK == kStoreF32) __builtin_nontemporal_store(un, st32 + p);
         if (SK >= kStoreBF16) {
           lmax = fmaxf(lmax, fabsf(un));
           if (k >= 2) __builtin_nontemporal_store(enc16(u * inv_prev, SK == kStoreBF16), st16 + p);
@@ -249,17 +271,19 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
         P[1 - b][g * NC + c + kHalo][lane + kHalo] = Q[c][5];
 #pragma unroll
         for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
-        Q[c][8] = qA[c];
-        pu2[c] = u2A[c];
-        pcf[c] = cfA[c];
-        qA[c] = qB[c];
-        u2A[c] = u2B[c];
-        cfA[c] = cfB[c];
+        Q[c][8] = qN[c];
+        pu2[c] = u2N[c];
+        pcf[c] = cfN[c];
       }
-      ring_store<TY>(P[1 - b], hA);
-#pragma unroll
-      for (int i = 0; i < HP; ++i) hA[i] = hB[i];
+      ring_store<TY>(P[1 - b], hN);
     }
+  };
+  // the prologue's loads complete before the march, so the loop head only ever sees the loads
+  // of the previous trip in flight
+  __builtin_amdgcn_s_waitcnt(0);
+  for (int z = T.z0; z < zend; z += 2) {
+    plane(z, hA, qA, u2A, cfA, hB, qB, u2B, cfB);
+    if (z + 1 < zend) plane(z + 1, hB, qB, u2B, cfB, hA, qA, u2A, cfA);
   }
   if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
 }
@@ -300,11 +324,21 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
   // imaging inputs of one point: u^j and the accumulator (0 outside the grid)
   auto load_img = [&](int y, int z, float* u, double* ac) {
     const bool in = x < nx && y < ny && z < nz;
-    const long long p = ((long long)z * ny + y) * px + x;
-    if (IMG >= kImgFullBF16) *u = in ? dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc : 0.f;
-    else if (IMG == kImgFull32) *u = in ? __builtin_nontemporal_load(uj + p) : 0.f;
-    else if (IMG) *u = in ? uj[p] : 0.f;
-    if (IMG) *ac = in ? acc[p] : 0.0;
+    const long long p = cidx(x, y, z, ny, nz, px);
+    if (IMG >= kImgFullBF16) {
+      const float v = dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc;
+      *u = in ? v : 0.f;
+    } else if (IMG == kImgFull32) {
+      const float v = __builtin_nontemporal_load(uj + p);
+      *u = in ? v : 0.f;
+    } else if (IMG) {
+      const float v = uj[p];
+      *u = in ? v : 0.f;
+    }
+    if (IMG) {
+      const double v = acc[p];
+      *ac = in ? v : 0.0;
+    }
   };
 
   // Register state of plane z (queue of w^{j+1}, w^{j+2}, coef, u^j, accumulator); set A holds
@@ -317,56 +351,47 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
-    pw2[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, nz, px, x, y, T.z0 - kHalo + t);
+    pw2[c] = ldc<TY>(w2, nx, ny, nz, nz, px, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0);
     pu[c] = 0.f;
     pacc[c] = 0.0;
     load_img(y, T.z0, &pu[c], &pacc[c]);
   }
   {
     float h[HP];
-    ring_fetch<TY>(h, w1, nx, ny, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(h, w1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
   }
   if (T.z0 + 1 < zend) {
-    ring_fetch<TY>(hA, w1, nx, ny, nz, px, T.x0, T.y0, T.z0 + 1);
+    ring_fetch<TY>(hA, w1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0 + 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int y = T.y0 + g * NC + c;
-      qA[c] = ldc<TY>(w1, nx, ny, nz, px, x, y, T.z0 + 1 + kHalo);
-      w2A[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, T.z0 + 1);
-      cfA[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0 + 1);
+      qA[c] = ldc<TY>(w1, nx, ny, nz, nz, px, x, y, T.z0 + 1 + kHalo);
+      w2A[c] = ldc<TY>(w2, nx, ny, nz, nz, px, x, y, T.z0 + 1);
+      cfA[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0 + 1);
       load_img(y, T.z0 + 1, &uA[c], &accA[c]);
     }
   }
-  for (int z = T.z0; z < zend; ++z) {
+  // Two planes per trip with the register sets swapping roles (see the forward kernel).
+  float hB[HP] = {}, qB[NC] = {}, w2B[NC] = {}, cfB[NC] = {}, uB[NC] = {};
+  double accB[NC] = {};
+  auto plane = [&](int z, float (&hN)[HP], float (&qN)[NC], float (&w2N)[NC], float (&cfN)[NC],
+                   float (&uN)[NC], double (&accN)[NC], float (&hL)[HP], float (&qL)[NC],
+                   float (&w2L)[NC], float (&cfL)[NC], float (&uL)[NC], double (&accL)[NC]) {
     const int b = (z - T.z0) & 1;
     __syncthreads();
-    float hB[HP], qB[NC], w2B[NC], cfB[NC], uB[NC];
-    double accB[NC];
+    ring_fetch<TY>(hL, w1, nx, ny, nz, nz, px, T.x0, T.y0, z + 2);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      uB[c] = 0.f;
-      accB[c] = 0.0;
-    }
-    if (z + 2 < zend) {
-      ring_fetch<TY>(hB, w1, nx, ny, nz, px, T.x0, T.y0, z + 2);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int y = T.y0 + g * NC + c;
-        qB[c] = ldc<TY>(w1, nx, ny, nz, px, x, y, z + 2 + kHalo);
-        w2B[c] = ldc<TY>(w2, nx, ny, nz, px, x, y, z + 2);
-        cfB[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 2);
-        load_img(y, z + 2, &uB[c], &accB[c]);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < HP; ++i) hB[i] = 0.f;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) qB[c] = w2B[c] = cfB[c] = 0.f;
+      const int y = T.y0 + g * NC + c;
+      qL[c] = ldc<TY>(w1, nx, ny, nz, nz, px, x, y, z + 2 + kHalo);
+      w2L[c] = ldc<TY>(w2, nx, ny, nz, nz, px, x, y, z + 2);
+      cfL[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, z + 2);
+      load_img(y, z + 2, &uL[c], &accL[c]);
     }
     const int dz = border_dist(z, nz, a.nbl);
 #pragma unroll
@@ -390,21 +415,19 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
         P[1 - b][g * NC + c + kHalo][lane + kHalo] = Q[c][5];
 #pragma unroll
         for (int t = 0; t < 8; ++t) Q[c][t] = Q[c][t + 1];
-        Q[c][8] = qA[c];
-        pw2[c] = w2A[c];
-        pcf[c] = cfA[c];
-        pu[c] = uA[c];
-        pacc[c] = accA[c];
-        qA[c] = qB[c];
-        w2A[c] = w2B[c];
-        cfA[c] = cfB[c];
-        uA[c] = uB[c];
-        accA[c] = accB[c];
+        Q[c][8] = qN[c];
+        pw2[c] = w2N[c];
+        pcf[c] = cfN[c];
+        pu[c] = uN[c];
+        pacc[c] = accN[c];
       }
-      ring_store<TY>(P[1 - b], hA);
-#pragma unroll
-      for (int i = 0; i < HP; ++i) hA[i] = hB[i];
+      ring_store<TY>(P[1 - b], hN);
     }
+  };
+  __builtin_amdgcn_s_waitcnt(0);   // see the forward kernel
+  for (int z = T.z0; z < zend; z += 2) {
+    plane(z, hA, qA, w2A, cfA, uA, accA, hB, qB, w2B, cfB, uB, accB);
+    if (z + 1 < zend) plane(z + 1, hB, qB, w2B, cfB, uB, accB, hA, qA, w2A, cfA, uA, accA);
   }
 }
 
@@ -474,6 +497,16 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
   }
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
+  const int src_i = S.src_i, src_j = S.src_j, src_k = S.src_k;   // kept in registers (see fwd3d)
+  float srcw[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) srcw[i] = S.src_w[i];
+  auto src_weight = [&](int i) {
+    float w = srcw[0];
+#pragma unroll
+    for (int t = 1; t < 8; ++t) w = i == t ? srcw[t] : w;
+    return w;
+  };
 
   float QU[NC][9], QD[NC][9], pu2[NC], pd2[NC], pcf[NC], pdm[NC];
 #pragma unroll
@@ -481,18 +514,18 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
     const int y = T.y0 + g * NC + c;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      QU[c][t] = ldc<TY>(u1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
-      QD[c][t] = ldc<TY>(d1, nx, ny, nz, px, x, y, T.z0 - kHalo + t);
+      QU[c][t] = ldc<TY>(u1, nx, ny, nz, nz, px, x, y, T.z0 - kHalo + t);
+      QD[c][t] = ldc<TY>(d1, nx, ny, nz, nz, px, x, y, T.z0 - kHalo + t);
     }
-    pu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, T.z0);
-    pd2[c] = ldc<TY>(d2, nx, ny, nz, px, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, T.z0);
-    pdm[c] = ldc<TY>(dm, nx, ny, nz, nx, x, y, T.z0);
+    pu2[c] = ldc<TY>(u2, nx, ny, nz, nz, px, x, y, T.z0);
+    pd2[c] = ldc<TY>(d2, nx, ny, nz, nz, px, x, y, T.z0);
+    pcf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0);
+    pdm[c] = ldc<TY>(dm, nx, ny, nz, nz, nx, x, y, T.z0);
   }
   {
     float hu[HP], hd[HP];
-    ring_fetch<TY>(hu, u1, nx, ny, nz, px, T.x0, T.y0, T.z0);
-    ring_fetch<TY>(hd, d1, nx, ny, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(hu, u1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(hd, d1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       PU[0][g * NC + c + kHalo][lane + kHalo] = QU[c][4];
@@ -507,17 +540,17 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
     const bool more = z + 1 < zend;
     float hu[HP], hd[HP], qun[NC], qdn[NC], nu2[NC], nd2[NC], ncf[NC], ndm[NC];
     if (more) {
-      ring_fetch<TY>(hu, u1, nx, ny, nz, px, T.x0, T.y0, z + 1);
-      ring_fetch<TY>(hd, d1, nx, ny, nz, px, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(hu, u1, nx, ny, nz, nz, px, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(hd, d1, nx, ny, nz, nz, px, T.x0, T.y0, z + 1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int y = T.y0 + g * NC + c;
-        qun[c] = ldc<TY>(u1, nx, ny, nz, px, x, y, z + 1 + kHalo);
-        qdn[c] = ldc<TY>(d1, nx, ny, nz, px, x, y, z + 1 + kHalo);
-        nu2[c] = ldc<TY>(u2, nx, ny, nz, px, x, y, z + 1);
-        nd2[c] = ldc<TY>(d2, nx, ny, nz, px, x, y, z + 1);
-        ncf[c] = ldc<TY>(cf, nx, ny, nz, px, x, y, z + 1);
-        ndm[c] = ldc<TY>(dm, nx, ny, nz, nx, x, y, z + 1);
+        qun[c] = ldc<TY>(u1, nx, ny, nz, nz, px, x, y, z + 1 + kHalo);
+        qdn[c] = ldc<TY>(d1, nx, ny, nz, nz, px, x, y, z + 1 + kHalo);
+        nu2[c] = ldc<TY>(u2, nx, ny, nz, nz, px, x, y, z + 1);
+        nd2[c] = ldc<TY>(d2, nx, ny, nz, nz, px, x, y, z + 1);
+        ncf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, z + 1);
+        ndm[c] = ldc<TY>(dm, nx, ny, nz, nz, nx, x, y, z + 1);
       }
     }
     const int dz = border_dist(z, nz, a.nbl);
@@ -530,9 +563,9 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
         const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
         const long long p = ((long long)z * ny + y) * px + x;
         float lap = lap3<TY>(PU[b], QU[c], ly, lane, a.c);
-        const int bx = x - S.src_i, by = y - S.src_j, bzz = z - S.src_k;
+        const int bx = x - src_i, by = y - src_j, bzz = z - src_k;
         if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
-          lap += S.src_w[bx + 2 * by + 4 * bzz] * qk;
+          lap += src_weight(bx + 2 * by + 4 * bzz) * qk;
         const float u = QU[c][4];
         const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
         uout[p] = (u + u - pu2[c]) + incr;
