@@ -46,26 +46,49 @@ struct T2 {
 // Stage rows z0-4 .. z0+TZ+3 of a field, columns x0-4 .. x0+67, zero outside the grid.  The
 // 64-column body of each row is one coalesced row segment per wave (aligned: the row pitch and
 // x0 are multiples of 64); the 4 + 4 halo columns of every row follow as one short pass.
+// Loads read clamped, always valid addresses (rows past the grid read its last row, columns
+// the padded row) and the value is zeroed where the point lies outside: no load sits on a
+// branch, so all of a thread's loads are issued before the first wait.
+__device__ __forceinline__ long long cidx2(int x, int z, int nz, int px) {
+  const int xc = min(max(x, 0), px - 1), zc = min(max(z, 0), nz - 1);
+  return (long long)zc * px + xc;
+}
+
+// Tile of f (rows z0-4 .. z0+TZ+3, columns x0-4 .. x0+67) into LDS; rows z >= nzv (or < 0)
+// and columns outside [0, nx) read as 0.  nzv <= nz: 0 for a level that is zero by definition.
 template <int TZ>
 __device__ __forceinline__ void load_tile(float (*L)[T2<TZ>::W], const float* __restrict__ f,
-                                          int nx, int nz, int px, int x0, int z0) {
-  constexpr int H = T2<TZ>::H;
+                                          int nx, int nzv, int nz, int px, int x0, int z0) {
+  constexpr int H = T2<TZ>::H, NW = T2<TZ>::NW, NT = T2<TZ>::NT;
+  constexpr int NB = (H + NW - 1) / NW;                      // body rows per thread
+  constexpr int NE = H * 2 * kHalo, NH = (NE + NT - 1) / NT; // side-halo cells per thread
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = x0 + lane;
+  float vb[NB], vh[NH];
 #pragma unroll
-  for (int r = wv; r < H; r += T2<TZ>::NW) {
-    const int z = z0 - kHalo + r;
-    float v = 0.f;
-    if (x < nx && (unsigned)z < (unsigned)nz) v = f[(long long)z * px + x];
-    L[r][lane + kHalo] = v;
-  }
-  for (int e = threadIdx.x; e < H * 2 * kHalo; e += T2<TZ>::NT) {
+  for (int i = 0; i < NB; ++i) vb[i] = f[cidx2(x, z0 - kHalo + wv + i * NW, nz, px)];
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const int e = min((int)threadIdx.x + i * NT, NE - 1);
     const int r = e / (2 * kHalo), c8 = e - r * (2 * kHalo);
     const int c = c8 < kHalo ? c8 : kTX + c8;
-    const int z = z0 - kHalo + r, xx = x0 - kHalo + c;
-    float v = 0.f;
-    if ((unsigned)z < (unsigned)nz && (unsigned)xx < (unsigned)nx) v = f[(long long)z * px + xx];
-    L[r][c] = v;
+    vh[i] = f[cidx2(x0 - kHalo + c, z0 - kHalo + r, nz, px)];
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int r = wv + i * NW;
+    const int z = z0 - kHalo + r;
+    if (r < H) L[r][lane + kHalo] = (x < nx && (unsigned)z < (unsigned)nzv) ? vb[i] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if (e < NE) {
+      const int r = e / (2 * kHalo), c8 = e - r * (2 * kHalo);
+      const int c = c8 < kHalo ? c8 : kTX + c8;
+      const int z = z0 - kHalo + r, xx = x0 - kHalo + c;
+      L[r][c] = ((unsigned)z < (unsigned)nzv && (unsigned)xx < (unsigned)nx) ? vh[i] : 0.f;
+    }
   }
 }
 
@@ -128,14 +151,15 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = (long long)z * px + x;
+    const long long p = cidx2(x, z, nz, px);
     const bool in = x < nx && z < nz;
-    pu2[i] = in && k >= 3 ? u2[p] : 0.f;
-    pcf[i] = in ? cf[p] : 0.f;
+    const float v2 = u2[p], vc = cf[p];
+    pu2[i] = in && k >= 3 ? v2 : 0.f;
+    pcf[i] = in ? vc : 0.f;
   }
   // levels below 1 are zero (initial state); their buffers may hold older levels after a
-  // checkpoint restore of a state before this shot's start, so they are not read
-  load_tile<TZ>(L, u1, nx, k >= 2 ? nz : 0, px, T.x0, T.z0);
+  // checkpoint restore of a state before this shot's start, so their values are not used
+  load_tile<TZ>(L, u1, nx, k >= 2 ? nz : 0, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -147,6 +171,14 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
 
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
+  // shot fields used in the row loop, in registers: a reload after a store through `out` would
+  // wait for every store in flight
+  const int src_i = S.src_i, src_k = S.src_k;
+  const float sw0 = S.src_w[0], sw1 = S.src_w[1], sw2 = S.src_w[2], sw3 = S.src_w[3];
+  float* st32 = SK == kStoreF32 ? reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts : nullptr;
+  float* sl = SK == kStoreNone && a.st_slot >= 0
+      ? reinterpret_cast<float*>(a.ws + S.store) + (long long)a.st_slot * 2 * S.npts : nullptr;
+  const long long npts = S.npts;
   // 16-bit store: u^{k-1} (the centre values read here) is quantised with its finished scale
   float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
   unsigned short* st16 = SK >= kStoreBF16
@@ -160,22 +192,23 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
     if (x >= nx || z >= nz) continue;
     const float u = L[lr + kHalo][lane + kHalo];
     float lap = lap_at<TZ>(L, lr, lane, a.c);
-    const int bx = x - S.src_i, bz = z - S.src_k;
-    if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * qk;
+    const int bx = x - src_i, bz = z - src_k;
+    if ((unsigned)bx < 2u && (unsigned)bz < 2u) {
+      const int w = bx + 2 * bz;
+      lap += (w == 0 ? sw0 : w == 1 ? sw1 : w == 2 ? sw2 : sw3) * qk;
+    }
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(u, pu2[i], pcf[i], lap, eta);
     const float un = (u + u - pu2[i]) + incr;
     const long long p = (long long)z * px + x;
     out[p] = un;
-    if (SK == kStoreNone && a.st_slot >= 0) {
+    if (SK == kStoreNone && sl != nullptr) {
       // checkpoint store fused into the step that reaches the stored state
-      float* sl = reinterpret_cast<float*>(a.ws + S.store) + (long long)a.st_slot * 2 * S.npts;
       sl[p] = un;
-      sl[S.npts + p] = u;
+      sl[npts + p] = u;
     }
-    if (SK == kStoreF32)
-      __builtin_nontemporal_store(un, reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts + p);
+    if (SK == kStoreF32) __builtin_nontemporal_store(un, st32 + p);
     if (SK >= kStoreBF16) {
       lmax = fmaxf(lmax, fabsf(un));
       if (k >= 2) __builtin_nontemporal_store(enc16(u * inv_prev, SK == kStoreBF16), st16 + p);
@@ -222,18 +255,23 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = (long long)z * px + x;
+    const long long p = cidx2(x, z, nz, px);
     const bool in = x < nx && z < nz;
-    pw2[i] = in ? w2[p] : 0.f;
-    pcf[i] = in ? cf[p] : 0.f;
+    const float v2 = w2[p], vc = cf[p];
+    pw2[i] = in ? v2 : 0.f;
+    pcf[i] = in ? vc : 0.f;
     if (IMG) {
-      if (IMG >= kImgFullBF16) pu[i] = in ? dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc : 0.f;
-      else pu[i] = in ? (IMG == kImgFull32 ? __builtin_nontemporal_load(uj + p) : uj[p]) : 0.f;
-      pacc[i] = in ? acc[p] : 0.0;
+      float vu;
+      if (IMG >= kImgFullBF16) vu = dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc;
+      else if (IMG == kImgFull32) vu = __builtin_nontemporal_load(uj + p);
+      else vu = uj[p];
+      const double va = acc[p];
+      pu[i] = in ? vu : 0.f;
+      pacc[i] = in ? va : 0.0;
     }
     if (has_inj) INJ[wv * RPT + i][lane] = 0.f;
   }
-  load_tile<TZ>(L, w1, nx, nz, px, T.x0, T.z0);
+  load_tile<TZ>(L, w1, nx, nz, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (has_inj) {
@@ -298,15 +336,16 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = (long long)z * px + x;
+    const long long p = cidx2(x, z, nz, px);
     const bool in = x < nx && z < nz;
-    pu2[i] = in ? u2[p] : 0.f;
-    pd2[i] = in ? d2[p] : 0.f;
-    pcf[i] = in ? cf[p] : 0.f;
-    pdm[i] = in ? dm[(long long)z * nx + x] : 0.f;
+    const float v2 = u2[p], vd = d2[p], vc = cf[p], vm = dm[cidx2(x, z, nz, nx)];
+    pu2[i] = in ? v2 : 0.f;
+    pd2[i] = in ? vd : 0.f;
+    pcf[i] = in ? vc : 0.f;
+    pdm[i] = in ? vm : 0.f;
   }
-  load_tile<TZ>(LU, u1, nx, nz, px, T.x0, T.z0);
-  load_tile<TZ>(LD, d1, nx, nz, px, T.x0, T.z0);
+  load_tile<TZ>(LU, u1, nx, nz, nz, px, T.x0, T.z0);
+  load_tile<TZ>(LD, d1, nx, nz, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -316,6 +355,8 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
     }
   }
 
+  const int src_i = S.src_i, src_k = S.src_k;   // in registers (see the forward kernel)
+  const float sw0 = S.src_w[0], sw1 = S.src_w[1], sw2 = S.src_w[2], sw3 = S.src_w[3];
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
 #pragma unroll
@@ -329,8 +370,11 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
     // background field
     const float u = LU[lr + kHalo][lane + kHalo];
     float lap = lap_at<TZ>(LU, lr, lane, a.c);
-    const int bx = x - S.src_i, bz = z - S.src_k;
-    if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * qk;
+    const int bx = x - src_i, bz = z - src_k;
+    if ((unsigned)bx < 2u && (unsigned)bz < 2u) {
+      const int w = bx + 2 * bz;
+      lap += (w == 0 ? sw0 : w == 1 ? sw1 : w == 2 ? sw2 : sw3) * qk;
+    }
     const float incr = pcf[i] * (lap - eta * (u - pu2[i]));
     uout[p] = (u + u - pu2[i]) + incr;
     // scattered field, source -dm (u^k - 2u^{k-1} + u^{k-2}) / dt^2 = -dm incr / dt^2
