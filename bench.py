@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "fp32"],
                     help="stored-wavefield precision of the 3D workload")
     ap.add_argument("--tiles", default=None,
-                    help="fixed launch shape instead of the autotuner, e.g. tz=32 or tz=16,levels_per_launch=2")
+                    help="fixed launch shape instead of the autotuner, e.g. tz=32 or tz=16,fusion=2 "
+                         "(two levels per launch: 1 forward, 2 reverse sweep, 3 both)")
     ap.add_argument("--groups", type=int, default=0,
                     help="shot groups per plan (0: automatic, sized to the last-level cache)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -117,12 +118,22 @@ def sync():
     torch.cuda.synchronize()
 
 
+def fusion_of(tiles):
+    """Two-levels-per-launch mode of a launch shape (bit 0 forward, bit 1 reverse sweep); the
+    older key levels_per_launch=2 means both."""
+    if not tiles:
+        return 0
+    if "fusion" in tiles:
+        return int(tiles["fusion"])
+    return 3 if tiles.get("levels_per_launch", 1) == 2 else 0
+
+
 def choose_tiles(plan, args, m, q, dd, ws=None):
     """Fixed launch shape from --tiles, else the autotuner's choice (None with --no-autotune)."""
     if args.tiles:
         t = args.tiles
         plan.set_tiles(t.get("tz", 32), t.get("ty", 8), t.get("bz", 0))
-        plan.set_fusion(t.get("levels_per_launch", 1) == 2)
+        plan.set_fusion(fusion_of(t))
         return dict(t)
     if args.no_autotune:
         return None
@@ -144,16 +155,18 @@ def points_of(wl, shots):
     return per_step, per_launch
 
 
-def kernel_table(prof, launch_points, kinds, fused=False):
-    """Per kernel class: launches, average event time and achieved algorithmic GB/s.  With
-    two levels per launch the bytes are those of a two-level launch."""
+def kernel_table(prof, launch_points, kinds, fused=0):
+    """Per kernel class: launches, average event time and achieved algorithmic GB/s.  For a
+    class that runs two levels per launch (fused: bit 0 forward, bit 1 adjoint) the bytes are
+    those of a two-level launch."""
     out = {}
     for name, kind in kinds.items():
         cnt, ms = prof[name]
         if cnt == 0:
             continue
         avg_ms = ms / cnt
-        key = (name + "2", kind) if fused and (name + "2", kind) in BYTES else (name, kind)
+        two = bool(fused & (1 if name == "forward" else 2 if name == "adjoint" else 0))
+        key = (name + "2", kind) if two and (name + "2", kind) in BYTES else (name, kind)
         b = BYTES[key] * launch_points
         out[name] = {"launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 3), "bytes_per_point": BYTES[key],
                      "levels_per_launch": 2 if key[0].endswith("2") else 1,
@@ -162,9 +175,9 @@ def kernel_table(prof, launch_points, kinds, fused=False):
 
 
 def roofline_of(kernels, names):
-    # every forward launch is paired with one adjoint launch: the dominant kernel is the
-    # one with the longer average launch
-    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    # the dominant kernel is the one with the larger share of the step's time (launches can
+    # differ when one direction runs two levels per launch)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches_timed"])
     ach = kernels[dom]["achieved_GBs"]
     return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": names[dom]}
@@ -179,8 +192,8 @@ def timed_gradient(run, args, kind):
     launches.  Returns (seconds per step, eager seconds per step, kernel table, timing note)."""
     n_eager = max(1, min(args.steps, 3))
     eager_sec, prof = run.run(n_eager, args.warmup, use_graph=False, profile=True)
-    fused = bool(run.tiles) and run.tiles.get("levels_per_launch", 1) == 2
-    kernels = kernel_table(prof, run.launch_points, {"forward": kind, "adjoint": kind}, fused=fused)
+    kernels = kernel_table(prof, run.launch_points, {"forward": kind, "adjoint": kind},
+                           fused=fusion_of(run.tiles))
     if args.no_graph:
         return eager_sec, eager_sec, kernels, "HIP events around every launch of the eager timed steps"
     run.capture()
@@ -222,7 +235,7 @@ class GradientRunner:
         self.tiles = None
         if tiles:
             p.set_tiles(tiles.get("tz", 32), tiles.get("ty", 8), tiles.get("bz", 0))
-            p.set_fusion(tiles.get("levels_per_launch", 1) == 2)
+            p.set_fusion(fusion_of(tiles))
             self.tiles = dict(tiles)
         elif autotune:
             self.tiles, _ = p.autotune(self.m0, self.q, self.d_obs, probe_steps=32, ws=self.ws)
@@ -370,19 +383,19 @@ def bench_c2(args):
                          tiles=args.tiles, groups=args.groups)
     sec, eager_sec, kernels, timing = timed_gradient(run, args, "fp32")
     value = run.points / sec / 1e9
-    fused = bool(run.tiles) and run.tiles.get("levels_per_launch", 1) == 2
+    mode = fusion_of(run.tiles)
+    ff, fa = bool(mode & 1), bool(mode & 2)
     use_graph = not args.no_graph
-    names = ({"forward": "fwd2d2 (two forward levels + stored FP32 copies, 28 B/point per launch)",
-              "adjoint": "adj2d2 (two adjoint levels + imaging from stored FP32, 44 B/point per launch)"}
-             if fused else
-             {"forward": "fwd2d step (forward + stored FP32 copy, 20 B/point)",
-              "adjoint": "adj2d step (adjoint + imaging from stored FP32, 36 B/point)"})
+    names = {"forward": ("fwd2d2 (two forward levels + stored FP32 copies, 28 B/point per launch)" if ff else
+                         "fwd2d step (forward + stored FP32 copy, 20 B/point)"),
+             "adjoint": ("adj2d2 (two adjoint levels + imaging from stored FP32, 44 B/point per launch)" if fa
+                         else "adj2d step (adjoint + imaging from stored FP32, 36 B/point)")}
     roof = roofline_of(kernels, names)
-    dom_name = (f"adj2d2_kernel<{run.tiles['tz']}, 1>" if fused else f"adj2d_kernel<{run.tiles['tz']}, 1>") \
+    dom_name = (f"adj2d2_kernel<{run.tiles['tz']}, 1>" if fa else f"adj2d_kernel<{run.tiles['tz']}, 1>") \
         if run.tiles else None
     roof["traffic"] = traffic_record("kernels2d.hip", dom_name, run.launch_points)
-    path_bytes = ((BYTES[("forward2", "fp32")] + BYTES[("adjoint2", "fp32")]) * run.points // 2 if fused
-                  else (BYTES[("forward", "fp32")] + BYTES[("adjoint", "fp32")]) * run.points)
+    path_bytes = ((BYTES[("forward2", "fp32")] / 2 if ff else BYTES[("forward", "fp32")]) +
+                  (BYTES[("adjoint2", "fp32")] / 2 if fa else BYTES[("adjoint", "fp32")])) * run.points
     loss = float(run.loss.item())
     tiles, points, groups = run.tiles, run.points, run.groups
     run.release()
@@ -754,7 +767,7 @@ def bench_c4(args):
     # launches cover different numbers of active shots: use the pass's summed kernel time
     cnt, ms = prof["forward"]
     est_kernel_s = ms * 1e-3
-    fused = bool(tiles) and tiles.get("levels_per_launch", 1) == 2
+    fused = bool(fusion_of(tiles) & 1)
     per_level = BYTES[("forward2", "none")] / 2 if fused else BYTES[("forward", "none")]
     ach = per_level * points / est_kernel_s / 1e9 if cnt else None
     return base_line(args, wl, points / sec / 1e9, sec, {

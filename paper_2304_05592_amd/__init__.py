@@ -4,12 +4,12 @@ The computation lives in libawe.so (hand-written HIP kernels behind a C ABI, inc
 this package is its Python binding and a torch.autograd rule.  Nothing here computes the
 operators itself, and nothing falls back to the CPU.
 """
-from .binding import (EXPORTS, LIB_PATH, PREC_BF16, PREC_FP16, PREC_FP32, STORE_CHECKPOINT,
+from .binding import (EXPORTS, FUSE_ADJOINT, FUSE_BOTH, FUSE_FORWARD, FUSE_NONE, LIB_PATH, PREC_BF16, PREC_FP16, PREC_FP32, STORE_CHECKPOINT,
                       STORE_FULL, STORE_NONE, AweError, Plan, ShotGeometry, Storage,
                       checkpoint_schedule, dot, lib, patchy, patchy_vjp, residual, slowness2,
                       velocity_gradient)
 
-__all__ = ["EXPORTS", "LIB_PATH", "PREC_BF16", "PREC_FP16", "PREC_FP32", "STORE_CHECKPOINT",
+__all__ = ["EXPORTS", "FUSE_ADJOINT", "FUSE_BOTH", "FUSE_FORWARD", "FUSE_NONE", "LIB_PATH", "PREC_BF16", "PREC_FP16", "PREC_FP32", "STORE_CHECKPOINT",
            "STORE_FULL", "STORE_NONE", "AweError", "Plan", "ShotGeometry", "Storage",
            "checkpoint_schedule", "dot", "lib", "patchy", "patchy_vjp", "residual", "slowness2",
            "velocity_gradient", "WaveOp", "wave_forward", "extend_edge", "misfit", "Slowness2",

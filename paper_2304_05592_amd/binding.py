@@ -29,6 +29,9 @@ EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "aw
            "awe_slowness2", "awe_velocity_gradient", "awe_patchy", "awe_patchy_vjp", "awe_status_string", "awe_last_error", "awe_version"]
 
 
+FUSE_NONE, FUSE_FORWARD, FUSE_ADJOINT, FUSE_BOTH = 0, 1, 2, 3
+
+
 class AweError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"awe status {STATUS.get(status, status)}: {message}")
@@ -291,14 +294,16 @@ class Plan:
         ms = ctypes.c_double(0.0)
         check(lib().awe_plan_autotune(self._h, _ptr(m), _ptr(q), _ptr(dd), int(probe_steps), _ptr(ws),
                                       self.ws_bytes, _stream_ptr(stream), ch, ctypes.byref(ms)))
-        return {"tz": ch[0], "ty": ch[1], "bz": ch[2], "levels_per_launch": ch[3]}, ms.value
+        return {"tz": ch[0], "ty": ch[1], "bz": ch[2], "fusion": ch[3]}, ms.value
 
     def set_tiles(self, tz: int = 32, ty: int = 8, bz: int = 0):
         check(lib().awe_plan_set_tiles(self._h, int(tz), int(ty), int(bz)))
 
-    def set_fusion(self, two_steps: bool):
-        """2D: two time levels per launch or one (default); results are bitwise identical."""
-        check(lib().awe_plan_set_fusion(self._h, int(bool(two_steps))))
+    def set_fusion(self, mode):
+        """Two time levels per launch (2D): mode bit 0 = forward solves, bit 1 = reverse sweeps
+        (FUSE_FORWARD, FUSE_ADJOINT, FUSE_BOTH); True means both, False neither."""
+        mode = (FUSE_BOTH if mode else FUSE_NONE) if isinstance(mode, bool) else int(mode)
+        check(lib().awe_plan_set_fusion(self._h, mode))
 
     def set_groups(self, ngroups: int = 0) -> int:
         """Shot groups run one after the other (0: automatic, sized to the last-level cache);

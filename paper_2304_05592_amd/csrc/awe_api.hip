@@ -60,7 +60,8 @@ struct awe_plan {
   awe_storage store{};
   int nshot = 0, max_nt = 0, nsteps = 0;
   int tz = 32;            // 2D tile rows
-  int fuse2 = 0;          // 2D: advance two time levels per launch where the storage allows
+  int fuse2 = 0;          // 2D: two time levels per launch where the storage allows
+                          // (bit 0: forward solves, bit 1: reverse sweeps)
   int ty = 8, bz = 0;     // 3D tile rows in y and z-block length
   std::vector<awe_shot> shots;
   std::vector<double> rec_pos;    // copy of the problem's receiver rows
@@ -519,14 +520,14 @@ awe_status step_adj2(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
   return AWE_OK;
 }
 
-bool fused_ok(const awe_plan* P) {
-  return P->ndim == 2 && P->fuse2 && (P->tz == 8 || P->tz == 16 || P->tz == 32);
+bool fused_ok(const awe_plan* P, int bit) {
+  return P->ndim == 2 && (P->fuse2 & bit) && (P->tz == 8 || P->tz == 16 || P->tz == 32);
 }
 
 // Forward levels 1..nsteps: one single step first when the count is odd, then pairs.
 awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s) {
   awe_status st;
-  const bool fuse = fused_ok(P) && (store == awe::kStoreNone || store == awe::kStoreF32);
+  const bool fuse = fused_ok(P, AWE_FUSE_FORWARD) && (store == awe::kStoreNone || store == awe::kStoreF32);
   int n = 1;
   if (fuse && (P->nsteps & 1)) {
     if ((st = step_fwd(P, a, 1, store, s)) != AWE_OK) return st;
@@ -542,7 +543,7 @@ awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s)
 // Adjoint levels nsteps..1 (same pairing, from the top).
 awe_status adjoint_loop(awe_plan* P, awe::StepArgs& a, hipStream_t s) {
   awe_status st;
-  const bool fuse = fused_ok(P) && (a.image_src == awe::kImgNone || a.image_src == awe::kImgFull32);
+  const bool fuse = fused_ok(P, AWE_FUSE_ADJOINT) && (a.image_src == awe::kImgNone || a.image_src == awe::kImgFull32);
   int n = P->nsteps;
   if (fuse && (P->nsteps & 1)) {
     if ((st = step_adj(P, a, n, s)) != AWE_OK) return st;
@@ -873,7 +874,8 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
                          (P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32);
     for (int tz : {8, 16, 32, 64}) cands.push_back({tz, P->ty, P->bz, 0});
     if (fusable)
-      for (int tz : {8, 16, 32}) cands.push_back({tz, P->ty, P->bz, 1});
+      for (int tz : {8, 16, 32})
+        for (int mode : {AWE_FUSE_FORWARD, AWE_FUSE_ADJOINT, AWE_FUSE_BOTH}) cands.push_back({tz, P->ty, P->bz, mode});
   } else {
     for (int ty : {4, 8, 16})
       for (int bz : {0, 128, 64, 32}) cands.push_back({P->tz, ty, bz, 0});
@@ -907,11 +909,11 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     keep_ev.swap(P->prof_ev);
     P->cur = 0;  // the probe times the first shot group
     AWE_HIP(hipEventRecord(e0, s));
-    const bool fuse = fused_ok(P);
-    for (int n = 1; n <= probe; n += fuse ? 2 : 1)
-      if ((st = fuse ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, fkind, s)) != AWE_OK) return st;
-    for (int n = P->nsteps; n > P->nsteps - probe && n >= 2; n -= fuse ? 2 : 1) {
-      if (fuse && aa.image_src != awe::kImgBuffers) {
+    const bool fuse_f = fused_ok(P, AWE_FUSE_FORWARD), fuse_a = fused_ok(P, AWE_FUSE_ADJOINT);
+    for (int n = 1; n <= probe; n += fuse_f ? 2 : 1)
+      if ((st = fuse_f ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, fkind, s)) != AWE_OK) return st;
+    for (int n = P->nsteps; n > P->nsteps - probe && n >= 2; n -= fuse_a ? 2 : 1) {
+      if (fuse_a && aa.image_src != awe::kImgBuffers) {
         if ((st = step_adj2(P, aa, n, s)) != AWE_OK) return st;
         continue;
       }
@@ -941,7 +943,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     chosen[0] = P->tz;
     chosen[1] = P->ty;
     chosen[2] = P->bz;
-    chosen[3] = P->fuse2 ? 2 : 1;
+    chosen[3] = P->fuse2;
   }
   if (best_ms) *best_ms = best;
   return AWE_OK;
@@ -973,9 +975,10 @@ awe_status awe_plan_set_groups(awe_plan* P, int32_t ngroups, int32_t* actual) {
   return st;
 }
 
-awe_status awe_plan_set_fusion(awe_plan* P, int32_t two_steps) {
+awe_status awe_plan_set_fusion(awe_plan* P, int32_t mode) {
   if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
-  P->fuse2 = two_steps ? 1 : 0;
+  if (mode < 0 || mode > AWE_FUSE_BOTH) return fail(AWE_ERR_INVALID_ARG, "fusion mode must be 0..3");
+  P->fuse2 = mode;
   // two-level kernels exist for 8, 16 and 32 rows
   if (P->fuse2 && P->tz != 8 && P->tz != 16 && P->tz != 32)
     return awe_plan_set_tiles(P, P->tz < 24 ? 16 : 32, P->ty, P->bz);

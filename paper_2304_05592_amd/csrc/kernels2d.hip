@@ -401,16 +401,27 @@ struct F2 {
   static constexpr int RPT = TZ / 4;
 };
 
+// Level n-1 with an 8-cell halo into LDS: all loads first (clamped addresses, as load_tile),
+// then the LDS writes; rows z >= nzv read as 0.
 template <int TZ>
 __device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const float* __restrict__ f,
-                                           int nx, int nz, int px, int x0, int z0) {
-  constexpr int W = F2<TZ>::W1, H = F2<TZ>::H1;
-  for (int e = threadIdx.x; e < W * H; e += kThreads) {
+                                           int nx, int nzv, int nz, int px, int x0, int z0) {
+  constexpr int W = F2<TZ>::W1, H = F2<TZ>::H1, N = W * H, NL = (N + kThreads - 1) / kThreads;
+  float v[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int e = min((int)threadIdx.x + i * kThreads, N - 1);
     const int r = e / W, c = e - r * W;
-    const int z = z0 - 2 * kHalo + r, x = x0 - 2 * kHalo + c;
-    float v = 0.f;
-    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) v = f[(long long)z * px + x];
-    L[r][c] = v;
+    v[i] = f[cidx2(x0 - 2 * kHalo + c, z0 - 2 * kHalo + r, nz, px)];
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int e = (int)threadIdx.x + i * kThreads;
+    if (e < N) {
+      const int r = e / W, c = e - r * W;
+      const int z = z0 - 2 * kHalo + r, x = x0 - 2 * kHalo + c;
+      L[r][c] = ((unsigned)z < (unsigned)nzv && (unsigned)x < (unsigned)nx) ? v[i] : 0.f;
+    }
   }
 }
 
@@ -440,23 +451,26 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
   float pm2[G::NE], pcf[G::NE], tcf[G::RPT];
 #pragma unroll
   for (int i = 0; i < G::NE; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e0 = threadIdx.x + i * kThreads;
+    const int e = min(e0, G::WE * G::HE - 1);
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
-    const bool in = e < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
-    const long long p = (long long)z * px + x;
-    pm2[i] = in && k >= 3 ? u2[p] : 0.f;  // levels below 1 are zero (see fwd2d_kernel)
-    pcf[i] = in ? cf[p] : 0.f;
+    const bool in = e0 < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
+    const long long p = cidx2(x, z, nz, px);
+    const float v2 = u2[p], vc = cf[p];
+    pm2[i] = in && k >= 3 ? v2 : 0.f;  // levels below 1 are zero (see fwd2d_kernel)
+    pcf[i] = in ? vc : 0.f;
   }
   {
     const int x = T.x0 + lane;
 #pragma unroll
     for (int i = 0; i < G::RPT; ++i) {
       const int z = T.z0 + wv * G::RPT + i;
-      tcf[i] = x < nx && z < nz ? cf[(long long)z * px + x] : 0.f;
+      const float vc = cf[cidx2(x, z, nz, px)];
+      tcf[i] = x < nx && z < nz ? vc : 0.f;
     }
   }
-  load_tile8<TZ>(L1, u1, nx, k >= 2 ? nz : 0, px, T.x0, T.z0);
+  load_tile8<TZ>(L1, u1, nx, k >= 2 ? nz : 0, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (act1 && a.d != nullptr) {
@@ -467,6 +481,11 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
           R.w[0] * L1[Rw][C] + R.w[1] * L1[Rw][C + 1] + R.w[2] * L1[Rw + 1][C] + R.w[3] * L1[Rw + 1][C + 1];
     }
   }
+  // shot fields used after stores, in registers (see fwd2d_kernel)
+  const int src_i = S.src_i, src_k = S.src_k;
+  const float sw0 = S.src_w[0], sw1 = S.src_w[1], sw2 = S.src_w[2], sw3 = S.src_w[3];
+  auto src_weight = [&](int w) { return w == 0 ? sw0 : w == 1 ? sw1 : w == 2 ? sw2 : sw3; };
+  const long long npts = S.npts;
   // first step: level k on the tile + 4-cell halo (zero outside the grid)
   const float q1 = act1 ? a.q[S.q + k - 1] : 0.f;
 #pragma unroll
@@ -480,8 +499,8 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
       const float* pc = &L1[r + kHalo][c + kHalo];
       const float u = pc[0];
       float lap = lap_ptr(pc, G::W1, a.c);
-      const int bx = x - S.src_i, bz = z - S.src_k;
-      if (act1 && (unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * q1;
+      const int bx = x - src_i, bz = z - src_k;
+      if (act1 && (unsigned)bx < 2u && (unsigned)bz < 2u) lap += src_weight(bx + 2 * bz) * q1;
       const int dx = border_dist(x, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
       const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
       const float incr = step_incr(u, pm2[i], pcf[i], lap, eta);
@@ -489,7 +508,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
       if (act1 && r >= kHalo && r < kHalo + TZ && c >= kHalo && c < kHalo + kTX) {
         const long long p = (long long)z * px + x;
         o1[p] = v;
-        if (SK == kStoreF32) st[(long long)k * S.npts + p] = v;
+        if (SK == kStoreF32) st[(long long)k * npts + p] = v;
       }
     }
     LE[r][c] = v;
@@ -518,15 +537,15 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
     const float u = pc[0];
     const float um2 = L1[lr + 2 * kHalo][lane + 2 * kHalo];
     float lap = lap_ptr(pc, G::WE, a.c);
-    const int bx = x - S.src_i, bz = z - S.src_k;
-    if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += S.src_w[bx + 2 * bz] * q2;
+    const int bx = x - src_i, bz = z - src_k;
+    if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += src_weight(bx + 2 * bz) * q2;
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(u, um2, tcf[i], lap, eta);
     const float un = (u + u - um2) + incr;
     const long long p = (long long)z * px + x;
     o2[p] = un;
-    if (SK == kStoreF32) st[(long long)(k + 1) * S.npts + p] = un;
+    if (SK == kStoreF32) st[(long long)(k + 1) * npts + p] = un;
   }
 }
 
@@ -564,32 +583,41 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
   double pacc[G::RPT];
 #pragma unroll
   for (int i = 0; i < G::NE; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e0 = threadIdx.x + i * kThreads;
+    const int e = min(e0, G::WE * G::HE - 1);
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
-    const bool in = e < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
-    const long long p = (long long)z * px + x;
-    pm2[i] = in ? w2[p] : 0.f;
-    pcf[i] = in ? cf[p] : 0.f;
-    if (inj1 && e < G::WE * G::HE) INJ1[r][c] = 0.f;
+    const bool in = e0 < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
+    const long long p = cidx2(x, z, nz, px);
+    const float v2 = w2[p], vc = cf[p];
+    pm2[i] = in ? v2 : 0.f;
+    pcf[i] = in ? vc : 0.f;
+    if (inj1 && e0 < G::WE * G::HE) INJ1[r][c] = 0.f;
   }
   {
     const int x = T.x0 + lane;
+    // store levels j and j-1, clamped to the stored range 0..nt-1 (a level outside it belongs
+    // to an inactive step and its value is not used)
+    const long long lv1 = min(j, S.nt - 1), lv2 = max(j - 1, 0);
 #pragma unroll
     for (int i = 0; i < G::RPT; ++i) {
       const int z = T.z0 + wv * G::RPT + i;
       const bool in = x < nx && z < nz;
-      const long long p = (long long)z * px + x;
-      tcf[i] = in ? cf[p] : 0.f;
+      const long long p = cidx2(x, z, nz, px);
+      const float vc = cf[p];
+      tcf[i] = in ? vc : 0.f;
       if (IMG) {
-        pu1[i] = in && act1 ? ust[(long long)j * S.npts + p] : 0.f;
-        pu2[i] = in && act2 ? ust[(long long)(j - 1) * S.npts + p] : 0.f;
-        pacc[i] = in ? acc[p] : 0.0;
+        const float a1 = ust[lv1 * S.npts + p];
+        const float a2 = ust[lv2 * S.npts + p];
+        const double va = acc[p];
+        pu1[i] = in && act1 ? a1 : 0.f;
+        pu2[i] = in && act2 ? a2 : 0.f;
+        pacc[i] = in ? va : 0.0;
       }
       if (inj2) INJ2[wv * G::RPT + i][lane] = 0.f;
     }
   }
-  load_tile8<TZ>(L1, w1, nx, nz, px, T.x0, T.z0);
+  load_tile8<TZ>(L1, w1, nx, nz, nz, px, T.x0, T.z0);
   __syncthreads();
 
   if (inj1 || inj2) {

@@ -280,7 +280,8 @@ def test_two_levels_per_launch_is_bitwise_the_one_level_path(tz):
     wl = W.small_2d(windows=[90, 70, 113], T_per_shot=[400.0, 250.0, 331.0])
     dds = _residuals(wl)
     outs = []
-    for fuse in (True, False):
+    # two levels per launch in both directions, forward only, reverse sweep only; then none
+    for fuse in (A.FUSE_BOTH, A.FUSE_FORWARD, A.FUSE_ADJOINT, A.FUSE_NONE):
         plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
         plan.set_tiles(tz=tz)
         plan.set_fusion(fuse)
@@ -289,8 +290,9 @@ def test_two_levels_per_launch_is_bitwise_the_one_level_path(tz):
         va = plan.adjoint(m, plan.pack(dds, "d"))
         _sync()
         outs.append((g.cpu(), v.cpu(), d.cpu(), va.cpu()))
-    for a, b in zip(outs[0], outs[1]):
-        assert torch.equal(a, b)
+    for other in outs[:-1]:
+        for a, b in zip(other, outs[-1]):
+            assert torch.equal(a, b)
     assert rel_l2(plan.unpack(outs[0][1], "q"), oracle_adjoint(wl, dds)) <= TOL
 
 
