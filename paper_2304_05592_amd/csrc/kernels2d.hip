@@ -652,11 +652,12 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
     a.v[S.q + j] = S.src_w[0] * L1[R][C] + S.src_w[1] * L1[R][C + 1] + S.src_w[2] * L1[R + 1][C] +
                    S.src_w[3] * L1[R + 1][C + 1];
   }
-  // first step: level j on the tile + 4-cell halo
+  // first step: level j on the tile + 4-cell halo (the loop has no early exit, so it unrolls
+  // completely and pm2 / pcf stay in registers)
 #pragma unroll
   for (int i = 0; i < G::NE; ++i) {
     const int e = threadIdx.x + i * kThreads;
-    if (e >= G::WE * G::HE) break;
+    if (e >= G::WE * G::HE) continue;
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
     float v = 0.f;
