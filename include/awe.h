@@ -225,8 +225,9 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
  * rows of 64 columns, and - where the storage mode allows it - 8, 16 or 32 rows with two
  * time levels per launch in the forward solve, the reverse sweep or both, see
  * awe_plan_set_fusion; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth, 128,
- * 64 or 32 planes) times probe_steps forward and adjoint levels (with imaging when the plan
- * keeps a wavefield) on the given inputs, then keeps the fastest for all later calls.  dd
+ * 64 or 32 planes) times the last probe_steps forward and adjoint levels of the sweep (with
+ * imaging when the plan keeps a wavefield) on the given inputs, then keeps the fastest for all
+ * later calls.  dd
  * may be NULL (the adjoint probe then injects nothing).  Rebuilds the plan's device tables
  * (the only allocation), overwrites the workspace and drops any kept forward.  chosen (may
  * be NULL) receives {tz, ty, bz, fusion mode} of the winner and best_ms (may be

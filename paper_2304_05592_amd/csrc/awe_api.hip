@@ -910,7 +910,9 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     P->cur = 0;  // the probe times the first shot group
     AWE_HIP(hipEventRecord(e0, s));
     const bool fuse_f = fused_ok(P, AWE_FUSE_FORWARD), fuse_a = fused_ok(P, AWE_FUSE_ADJOINT);
-    for (int n = 1; n <= probe; n += fuse_f ? 2 : 1)
+    // the last levels of the sweep, where every shot of an end-aligned batch is active (the
+    // first levels of uneven batches cover only the longest shots)
+    for (int n = std::max(1, P->nsteps - probe + 1); n + (fuse_f ? 1 : 0) <= P->nsteps; n += fuse_f ? 2 : 1)
       if ((st = fuse_f ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, fkind, s)) != AWE_OK) return st;
     for (int n = P->nsteps; n > P->nsteps - probe && n >= 2; n -= fuse_a ? 2 : 1) {
       if (fuse_a && aa.image_src != awe::kImgBuffers) {
