@@ -397,8 +397,11 @@ struct F2 {
   static constexpr int H1 = TZ + 4 * kHalo;
   static constexpr int WE = kTX + 2 * kHalo;      // 72: first-step level on tile + 4
   static constexpr int HE = TZ + 2 * kHalo;
-  static constexpr int NE = (WE * HE + kThreads - 1) / kThreads;  // extended points per thread
-  static constexpr int RPT = TZ / 4;
+  static constexpr int NW = TZ >= 32 ? 8 : 4;    // waves per workgroup
+  static constexpr int NT = 64 * NW;
+  static constexpr int NE = (WE * HE + NT - 1) / NT;  // extended points per thread
+  static constexpr int RPT = TZ / NW;                // tile rows per thread
+  static_assert(TZ % NW == 0, "tile rows must split evenly over the waves");
 };
 
 // Level n-1 with an 8-cell halo into LDS: all loads first (clamped addresses, as load_tile),
@@ -406,17 +409,17 @@ struct F2 {
 template <int TZ>
 __device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const float* __restrict__ f,
                                            int nx, int nzv, int nz, int px, int x0, int z0) {
-  constexpr int W = F2<TZ>::W1, H = F2<TZ>::H1, N = W * H, NL = (N + kThreads - 1) / kThreads;
+  constexpr int W = F2<TZ>::W1, H = F2<TZ>::H1, N = W * H, NT = F2<TZ>::NT, NL = (N + NT - 1) / NT;
   float v[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    const int e = min((int)threadIdx.x + i * kThreads, N - 1);
+    const int e = min((int)threadIdx.x + i * NT, N - 1);
     const int r = e / W, c = e - r * W;
     v[i] = f[cidx2(x0 - 2 * kHalo + c, z0 - 2 * kHalo + r, nz, px)];
   }
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    const int e = (int)threadIdx.x + i * kThreads;
+    const int e = (int)threadIdx.x + i * NT;
     if (e < N) {
       const int r = e / W, c = e - r * W;
       const int z = z0 - 2 * kHalo + r, x = x0 - 2 * kHalo + c;
@@ -427,7 +430,7 @@ __device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const float* 
 
 // Forward: levels k and k+1 (k = step - off); SK = kStoreNone or kStoreF32.
 template <int TZ, int SK>
-__global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
+__global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   using G = F2<TZ>;
   __shared__ float L1[G::H1][G::W1];
   __shared__ float LE[G::HE][G::WE];
@@ -451,7 +454,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
   float pm2[G::NE], pcf[G::NE], tcf[G::RPT];
 #pragma unroll
   for (int i = 0; i < G::NE; ++i) {
-    const int e0 = threadIdx.x + i * kThreads;
+    const int e0 = threadIdx.x + i * G::NT;
     const int e = min(e0, G::WE * G::HE - 1);
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
@@ -474,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
   __syncthreads();
 
   if (act1 && a.d != nullptr) {
-    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+    for (int t = threadIdx.x; t < T.gat_count; t += G::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
       const int C = R.i - T.x0 + 2 * kHalo, Rw = R.k - T.z0 + 2 * kHalo;
       a.d[S.d + (long long)(k - 1) * S.nrec + R.r] =
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
   const float q1 = act1 ? a.q[S.q + k - 1] : 0.f;
 #pragma unroll
   for (int i = 0; i < G::NE; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * G::NT;
     if (e >= G::WE * G::HE) break;
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
   __syncthreads();
 
   if (act2 && a.d != nullptr) {
-    for (int t = threadIdx.x; t < T.gat_count; t += kThreads) {
+    for (int t = threadIdx.x; t < T.gat_count; t += G::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
       const int C = R.i - T.x0 + kHalo, Rw = R.k - T.z0 + kHalo;
       a.d[S.d + (long long)k * S.nrec + R.r] =
@@ -553,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void fwd2d2_kernel(StepArgs a) {
 // imaging of both steps accumulated (in step order) into one FP64 read-modify-write.
 // IMG = kImgNone or kImgFull32.
 template <int TZ, int IMG>
-__global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
+__global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   using G = F2<TZ>;
   __shared__ float L1[G::H1][G::W1];
   __shared__ float LE[G::HE][G::WE];
@@ -583,7 +586,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
   double pacc[G::RPT];
 #pragma unroll
   for (int i = 0; i < G::NE; ++i) {
-    const int e0 = threadIdx.x + i * kThreads;
+    const int e0 = threadIdx.x + i * G::NT;
     const int e = min(e0, G::WE * G::HE - 1);
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
   if (inj1 || inj2) {
     if (inj1) {
       const float* ddj = a.dd + S.d + (long long)j * S.nrec;
-      for (int t = threadIdx.x; t < T.ext_count; t += kThreads) {
+      for (int t = threadIdx.x; t < T.ext_count; t += G::NT) {
         const InjPoint Pt = a.t.ext_pts[T.ext_begin + t];
         float sum = 0.f;
         for (int e = 0; e < Pt.e_count; ++e) {
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
     }
     if (inj2) {
       const float* ddj = a.dd + S.d + (long long)(j - 1) * S.nrec;
-      for (int t = threadIdx.x; t < T.inj_count; t += kThreads) {
+      for (int t = threadIdx.x; t < T.inj_count; t += G::NT) {
         const InjPoint Pt = a.t.inj_pts[T.inj_begin + t];
         float sum = 0.f;
         for (int e = 0; e < Pt.e_count; ++e) {
@@ -656,7 +659,7 @@ __global__ __launch_bounds__(kThreads) void adj2d2_kernel(StepArgs a) {
   // completely and pm2 / pcf stay in registers)
 #pragma unroll
   for (int i = 0; i < G::NE; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * G::NT;
     if (e >= G::WE * G::HE) continue;
     const int r = e / G::WE, c = e - r * G::WE;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
@@ -739,8 +742,8 @@ hipError_t adj2d_tz(const StepArgs& a, hipStream_t s) {
 template <int TZ>
 hipError_t fwd2d2_tz(const StepArgs& a, int store, hipStream_t s) {
   switch (store) {
-    case kStoreNone: fwd2d2_kernel<TZ, kStoreNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kStoreF32: fwd2d2_kernel<TZ, kStoreF32><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kStoreNone: fwd2d2_kernel<TZ, kStoreNone><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
+    case kStoreF32: fwd2d2_kernel<TZ, kStoreF32><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -749,8 +752,8 @@ hipError_t fwd2d2_tz(const StepArgs& a, int store, hipStream_t s) {
 template <int TZ>
 hipError_t adj2d2_tz(const StepArgs& a, hipStream_t s) {
   switch (a.image_src) {
-    case kImgNone: adj2d2_kernel<TZ, kImgNone><<<a.ntiles, kThreads, 0, s>>>(a); break;
-    case kImgFull32: adj2d2_kernel<TZ, kImgFull32><<<a.ntiles, kThreads, 0, s>>>(a); break;
+    case kImgNone: adj2d2_kernel<TZ, kImgNone><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
+    case kImgFull32: adj2d2_kernel<TZ, kImgFull32><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
