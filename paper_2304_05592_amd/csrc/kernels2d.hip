@@ -397,7 +397,7 @@ struct F2 {
   static constexpr int H1 = TZ + 4 * kHalo;
   static constexpr int WE = kTX + 2 * kHalo;      // 72: first-step level on tile + 4
   static constexpr int HE = TZ + 2 * kHalo;
-  static constexpr int NW = TZ >= 32 ? 8 : 4;    // waves per workgroup
+  static constexpr int NW = TZ >= 16 ? 8 : 4;    // waves per workgroup
   static constexpr int NT = 64 * NW;
   static constexpr int NE = (WE * HE + NT - 1) / NT;  // extended points per thread
   static constexpr int RPT = TZ / NW;                // tile rows per thread
