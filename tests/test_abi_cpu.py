@@ -173,3 +173,33 @@ def test_born_forward_refuses_gradients_of_the_background():
     z = torch.zeros(3)
     with pytest.raises(NotImplementedError):
         A.born_forward(z, z.clone().requires_grad_(True), z, None)
+
+
+def _bench_module():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(root, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_roofline_bookkeeping():
+    """Launch shapes map to fusion modes; a class that runs two levels per launch is charged the
+    bytes of a two-level launch; the dominant kernel is the one with the larger time share."""
+    bench = _bench_module()
+    assert bench.fusion_of(None) == 0
+    assert bench.fusion_of({"tz": 16}) == 0
+    assert bench.fusion_of({"tz": 16, "levels_per_launch": 2}) == 3
+    assert bench.fusion_of({"tz": 16, "fusion": 2}) == 2
+    prof = {"forward": (3637, 3637 * 0.018), "adjoint": (1819, 1819 * 0.051)}
+    k = bench.kernel_table(prof, 1000, {"forward": "fp32", "adjoint": "fp32"}, fused=2)
+    assert k["forward"]["bytes_per_point"] == bench.BYTES[("forward", "fp32")]
+    assert k["adjoint"]["bytes_per_point"] == bench.BYTES[("adjoint2", "fp32")]
+    assert k["adjoint"]["levels_per_launch"] == 2 and k["forward"]["levels_per_launch"] == 1
+    roof = bench.roofline_of(k, {"forward": "f", "adjoint": "a"})
+    assert roof["kernel"] == "a"                       # 1819 x 51 us > 3637 x 18 us
+    assert abs(roof["frac"] - roof["achieved"] / bench.PEAK_HBM_GBS) < 1e-4
+    k1 = bench.kernel_table({"forward": (100, 100 * 0.02), "adjoint": (100, 100 * 0.03)}, 1000,
+                            {"forward": "fp32", "adjoint": "fp32"}, fused=0)
+    assert bench.roofline_of(k1, {"forward": "f", "adjoint": "a"})["kernel"] == "a"
