@@ -498,14 +498,10 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
   const int src_i = S.src_i, src_j = S.src_j, src_k = S.src_k;   // kept in registers (see fwd3d)
-  float srcw[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) srcw[i] = S.src_w[i];
-  auto src_weight = [&](int i) {
-    float w = srcw[0];
-#pragma unroll
-    for (int t = 1; t < 8; ++t) w = i == t ? srcw[t] : w;
-    return w;
+  const float w0 = S.src_w[0], w1 = S.src_w[1], w2 = S.src_w[2], w3 = S.src_w[3];
+  const float w4 = S.src_w[4], w5 = S.src_w[5], w6 = S.src_w[6], w7 = S.src_w[7];
+  auto src_weight = [=](int i) {
+    return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : i == 3 ? w3 : i == 4 ? w4 : i == 5 ? w5 : i == 6 ? w6 : w7;
   };
 
   float QU[NC][9], QD[NC][9], pu2[NC], pd2[NC], pcf[NC], pdm[NC];
