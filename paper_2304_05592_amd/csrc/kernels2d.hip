@@ -399,10 +399,32 @@ struct F2 {
   static constexpr int HE = TZ + 2 * kHalo;
   static constexpr int NW = TZ >= 16 ? 8 : 4;    // waves per workgroup
   static constexpr int NT = 64 * NW;
-  static constexpr int NE = (WE * HE + NT - 1) / NT;  // extended points per thread
   static constexpr int RPT = TZ / NW;                // tile rows per thread
   static_assert(TZ % NW == 0, "tile rows must split evenly over the waves");
+  // first-step points of a thread: NB in the 64 body columns (one wave per row, aligned
+  // 256-byte rows), NH in the 4 + 4 side columns of every row
+  static constexpr int NB = (HE + NW - 1) / NW;
+  static constexpr int NH = (2 * kHalo * HE + NT - 1) / NT;
+  static constexpr int NS = NB + NH;
 };
+
+// Slot i of this thread among the first-step points (row r, column c of the WE x HE region);
+// false for an unused slot (its r, c are then a valid point, not to be written).
+template <int TZ>
+__device__ __forceinline__ bool ext_slot(int i, int* r, int* c) {
+  using G = F2<TZ>;
+  if (i < G::NB) {
+    *r = (int)(threadIdx.x >> 6) + i * G::NW;
+    *c = kHalo + (int)(threadIdx.x & 63);
+    return *r < G::HE;
+  }
+  const int e0 = (int)threadIdx.x + (i - G::NB) * G::NT;
+  const int e = min(e0, 2 * kHalo * G::HE - 1);
+  *r = e / (2 * kHalo);
+  const int cc = e - *r * (2 * kHalo);
+  *c = cc < kHalo ? cc : kTX + cc;
+  return e0 < 2 * kHalo * G::HE;
+}
 
 // Level n-1 with an 8-cell halo into LDS: all loads first (clamped addresses, as load_tile),
 // then the LDS writes; rows z >= nzv read as 0.
@@ -451,14 +473,13 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   // prefetch level k-2 and coef of this thread's extended points, coef of its tile points
-  float pm2[G::NE], pcf[G::NE], tcf[G::RPT];
+  float pm2[G::NS], pcf[G::NS], tcf[G::RPT];
 #pragma unroll
-  for (int i = 0; i < G::NE; ++i) {
-    const int e0 = threadIdx.x + i * G::NT;
-    const int e = min(e0, G::WE * G::HE - 1);
-    const int r = e / G::WE, c = e - r * G::WE;
+  for (int i = 0; i < G::NS; ++i) {
+    int r, c;
+    const bool ok = ext_slot<TZ>(i, &r, &c);
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
-    const bool in = e0 < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
+    const bool in = ok && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
     const long long p = cidx2(x, z, nz, px);
     const float v2 = u2[p], vc = cf[p];
     pm2[i] = in && k >= 3 ? v2 : 0.f;  // levels below 1 are zero (see fwd2d_kernel)
@@ -492,10 +513,9 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   // first step: level k on the tile + 4-cell halo (zero outside the grid)
   const float q1 = act1 ? a.q[S.q + k - 1] : 0.f;
 #pragma unroll
-  for (int i = 0; i < G::NE; ++i) {
-    const int e = threadIdx.x + i * G::NT;
-    if (e >= G::WE * G::HE) break;
-    const int r = e / G::WE, c = e - r * G::WE;
+  for (int i = 0; i < G::NS; ++i) {
+    int r, c;
+    if (!ext_slot<TZ>(i, &r, &c)) continue;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
     float v = 0.f;
     if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) {
@@ -582,20 +602,19 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   const bool inj1 = act1 && a.dd != nullptr && T.ext_count > 0;
   const bool inj2 = act2 && a.dd != nullptr && T.inj_count > 0;
 
-  float pm2[G::NE], pcf[G::NE], tcf[G::RPT], pu1[G::RPT], pu2[G::RPT];
+  float pm2[G::NS], pcf[G::NS], tcf[G::RPT], pu1[G::RPT], pu2[G::RPT];
   double pacc[G::RPT];
 #pragma unroll
-  for (int i = 0; i < G::NE; ++i) {
-    const int e0 = threadIdx.x + i * G::NT;
-    const int e = min(e0, G::WE * G::HE - 1);
-    const int r = e / G::WE, c = e - r * G::WE;
+  for (int i = 0; i < G::NS; ++i) {
+    int r, c;
+    const bool ok = ext_slot<TZ>(i, &r, &c);
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
-    const bool in = e0 < G::WE * G::HE && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
+    const bool in = ok && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
     const long long p = cidx2(x, z, nz, px);
     const float v2 = w2[p], vc = cf[p];
     pm2[i] = in ? v2 : 0.f;
     pcf[i] = in ? vc : 0.f;
-    if (inj1 && e0 < G::WE * G::HE) INJ1[r][c] = 0.f;
+    if (inj1 && ok) INJ1[r][c] = 0.f;
   }
   {
     const int x = T.x0 + lane;
@@ -658,10 +677,9 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   // first step: level j on the tile + 4-cell halo (the loop has no early exit, so it unrolls
   // completely and pm2 / pcf stay in registers)
 #pragma unroll
-  for (int i = 0; i < G::NE; ++i) {
-    const int e = threadIdx.x + i * G::NT;
-    if (e >= G::WE * G::HE) continue;
-    const int r = e / G::WE, c = e - r * G::WE;
+  for (int i = 0; i < G::NS; ++i) {
+    int r, c;
+    if (!ext_slot<TZ>(i, &r, &c)) continue;
     const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
     float v = 0.f;
     if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) {
