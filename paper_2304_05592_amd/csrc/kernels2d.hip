@@ -431,21 +431,36 @@ __device__ __forceinline__ bool ext_slot(int i, int* r, int* c) {
 template <int TZ>
 __device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const float* __restrict__ f,
                                            int nx, int nzv, int nz, int px, int x0, int z0) {
-  constexpr int W = F2<TZ>::W1, H = F2<TZ>::H1, N = W * H, NT = F2<TZ>::NT, NL = (N + NT - 1) / NT;
-  float v[NL];
+  // body: the tile's 64 columns of every row, one aligned 256-byte load per wave and row;
+  // halo: the 8 + 8 side columns of every row
+  constexpr int H = F2<TZ>::H1, NW = F2<TZ>::NW, NT = F2<TZ>::NT, HW = 4 * kHalo;  // 16 side cells
+  constexpr int NB = (H + NW - 1) / NW, NE = HW * H, NH = (NE + NT - 1) / NT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = x0 + lane;
+  float vb[NB], vh[NH];
 #pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    const int e = min((int)threadIdx.x + i * NT, N - 1);
-    const int r = e / W, c = e - r * W;
-    v[i] = f[cidx2(x0 - 2 * kHalo + c, z0 - 2 * kHalo + r, nz, px)];
+  for (int i = 0; i < NB; ++i) vb[i] = f[cidx2(x, z0 - 2 * kHalo + wv + i * NW, nz, px)];
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const int e = min((int)threadIdx.x + i * NT, NE - 1);
+    const int r = e / HW, cc = e - r * HW;
+    const int c = cc < 2 * kHalo ? cc : kTX + cc;           // columns 0..7 and 72..79
+    vh[i] = f[cidx2(x0 - 2 * kHalo + c, z0 - 2 * kHalo + r, nz, px)];
   }
 #pragma unroll
-  for (int i = 0; i < NL; ++i) {
+  for (int i = 0; i < NB; ++i) {
+    const int r = wv + i * NW;
+    const int z = z0 - 2 * kHalo + r;
+    if (r < H) L[r][lane + 2 * kHalo] = (x < nx && (unsigned)z < (unsigned)nzv) ? vb[i] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
     const int e = (int)threadIdx.x + i * NT;
-    if (e < N) {
-      const int r = e / W, c = e - r * W;
-      const int z = z0 - 2 * kHalo + r, x = x0 - 2 * kHalo + c;
-      L[r][c] = ((unsigned)z < (unsigned)nzv && (unsigned)x < (unsigned)nx) ? v[i] : 0.f;
+    if (e < NE) {
+      const int r = e / HW, cc = e - r * HW;
+      const int c = cc < 2 * kHalo ? cc : kTX + cc;
+      const int z = z0 - 2 * kHalo + r, xx = x0 - 2 * kHalo + c;
+      L[r][c] = ((unsigned)z < (unsigned)nzv && (unsigned)xx < (unsigned)nx) ? vh[i] : 0.f;
     }
   }
 }
