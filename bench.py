@@ -174,33 +174,6 @@ def kernel_table(prof, launch_points, kinds, fused=0):
     return out
 
 
-def recompute_launches(sched, fused):
-    """(one-level, two-level) forward launches of a checkpointed gradient of one shot group:
-    the advances of the schedule run in pairs when fused, except the step that also writes a
-    FP32 checkpoint slot (a store of the reached state that follows, not into the slot being
-    read by reference), which stays a one-level launch."""
-    one = two = 0
-    rs_slot = None                           # slot read by reference since the last restore
-    for i, (op, a, b) in enumerate(sched):
-        if op == 0:                          # advance a -> b
-            nxt = sched[i + 1] if i + 1 < len(sched) else None
-            store = nxt is not None and nxt[0] == 1 and nxt[2] == b and nxt[1] != rs_slot
-            last_pair = b - 1 if store else b
-            n = a + 1
-            while n <= b:
-                if fused and n + 1 <= last_pair:
-                    two += 1
-                    n += 2
-                else:
-                    one += 1
-                    n += 1
-        elif op == 1 and a == rs_slot:       # the slot read by reference is overwritten
-            rs_slot = None
-        elif op == 2:
-            rs_slot = a if a >= 0 else None
-    return one, two
-
-
 def roofline_of(kernels, names):
     # the dominant kernel is the one with the larger share of the step's time (launches can
     # differ when one direction runs two levels per launch)
@@ -479,22 +452,10 @@ def bench_c3(args):
     sec = (time.perf_counter() - t0) / args.steps
     prof = plan.profile_read()
     kernels = kernel_table(prof, launch_points, {"forward": "none", "adjoint": "buffers"})
-    sched = A.checkpoint_schedule(wl.shots[0].nt - 1, 16)
-    fwd_steps = int(sum(b - a for op, a, b in sched if op == 0))   # forward steps per gradient
-    one, two = recompute_launches(sched.tolist(), fusion_of(tiles) & 1)
     names = {"forward": "fwd2d step (forward / recompute, 16 B/point)",
              "adjoint": "adj2d step (adjoint + imaging from recomputed buffers, 36 B/point)"}
-    if two:
-        # sampled launches mix one- and two-level recompute launches: bytes of the average
-        # launch from the schedule's counts
-        f = kernels["forward"]
-        bpp = (one * BYTES[("forward", "none")] + two * BYTES[("forward2", "none")]) / (one + two)
-        f["bytes_per_point"] = round(bpp, 3)
-        f["levels_per_launch"] = round(fwd_steps / (one + two), 3)
-        f["bytes_per_launch"] = int(bpp * launch_points)
-        f["achieved_GBs"] = round(f["bytes_per_launch"] / (f["avg_us"] * 1e-6) / 1e9, 1)
-        names["forward"] = (f"fwd2d / fwd2d2 recompute ({two} two-level and {one} one-level launches "
-                            f"per group and gradient, {bpp:.2f} B/point per launch)")
+    sched = A.checkpoint_schedule(wl.shots[0].nt - 1, 16)
+    fwd_steps = int(sum(b - a for op, a, b in sched if op == 0))   # forward steps per gradient
     return base_line(args, wl, points / sec / 1e9, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "CHECKPOINT 16 FP32 slots",

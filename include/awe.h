@@ -223,8 +223,7 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
 
 /* Tile-shape autotuner (setup call, synchronous): for each candidate (2D: 8, 16, 32 or 64
  * rows of 64 columns, and - where the storage mode allows it - 8, 16 or 32 rows with two
- * time levels per launch in the forward solve, the reverse sweep or both (CHECKPOINT: the
- * forward sweeps only), see
+ * time levels per launch in the forward solve, the reverse sweep or both, see
  * awe_plan_set_fusion; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth, 128,
  * 64 or 32 planes) times the last probe_steps forward and adjoint levels of the sweep (with
  * imaging when the plan keeps a wavefield) on the given inputs, then keeps the fastest for all
@@ -255,11 +254,10 @@ awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz
 /* 2D only: advance two time levels per launch, chosen per direction by the bits of mode:
  * AWE_FUSE_FORWARD for forward solves, AWE_FUSE_ADJOINT for reverse sweeps (0, the default:
  * one level per launch everywhere).  The two-level kernels serve forward solves without
- * storage or with FULL FP32 storage, the recomputing forward sweeps of CHECKPOINT storage
- * (a step that also writes a checkpoint slot stays one level per launch) and reverse sweeps
- * from FULL FP32 storage or without imaging; other modes always use one level per launch.
- * Results are bitwise identical either way.  Two levels per launch need tiles of 8, 16 or 32
- * rows (16 or 32 are set otherwise).  Errors: INVALID_ARG (mode outside 0..3), HIP. */
+ * storage or with FULL FP32 storage and reverse sweeps from FULL FP32 storage or without
+ * imaging; other modes always use one level per launch.  Results are bitwise identical
+ * either way.  Two levels per launch need tiles of 8, 16 or 32 rows (16 or 32 are set
+ * otherwise).  Errors: INVALID_ARG (mode outside 0..3), HIP. */
 enum { AWE_FUSE_NONE = 0, AWE_FUSE_FORWARD = 1, AWE_FUSE_ADJOINT = 2, AWE_FUSE_BOTH = 3 };
 awe_status awe_plan_set_fusion(awe_plan* plan, int32_t mode);
 

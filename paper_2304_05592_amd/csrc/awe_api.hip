@@ -595,21 +595,10 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
             P->sched[3 * (i + 1) + 2] == y &&
             !(fa.rs_level != awe::kNoLevel && fa.rs_slot == P->sched[3 * (i + 1) + 1]))
           fuse_slot = P->sched[3 * (i + 1) + 1];
-        // two levels per launch where enabled; the step that also writes the checkpoint slot
-        // stays a one-level launch
-        const bool pair = fused_ok(P, AWE_FUSE_FORWARD);
-        const int last_pair = fuse_slot >= 0 ? y - 1 : y;
-        for (int n = x + 1; n <= y;) {
-          awe_status st;
-          if (pair && n + 1 <= last_pair) {
-            st = step_fwd2(P, fa, n, 0, s);
-            n += 2;
-          } else {
-            fa.st_slot = n == y ? fuse_slot : -1;
-            st = step_fwd(P, fa, n, 0, s);
-            fa.st_slot = -1;
-            n += 1;
-          }
+        for (int n = x + 1; n <= y; ++n) {
+          fa.st_slot = n == y ? fuse_slot : -1;
+          awe_status st = step_fwd(P, fa, n, 0, s);
+          fa.st_slot = -1;
           if (st != AWE_OK) return st;
         }
         if (fuse_slot >= 0) ++i;  // the store is done
@@ -887,10 +876,6 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     if (fusable)
       for (int tz : {8, 16, 32})
         for (int mode : {AWE_FUSE_FORWARD, AWE_FUSE_ADJOINT, AWE_FUSE_BOTH}) cands.push_back({tz, P->ty, P->bz, mode});
-    // checkpointing: the recomputing forward sweeps can run two levels per launch; the reverse
-    // steps image from the recomputed level, one level per launch
-    if (P->store.mode == AWE_STORE_CHECKPOINT)
-      for (int tz : {8, 16, 32}) cands.push_back({tz, P->ty, P->bz, AWE_FUSE_FORWARD});
   } else {
     for (int ty : {4, 8, 16})
       for (int bz : {0, 128, 64, 32}) cands.push_back({P->tz, ty, bz, 0});

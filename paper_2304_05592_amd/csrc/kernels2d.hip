@@ -479,8 +479,8 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   const bool act2 = k + 1 >= 1 && k + 1 <= S.nt - 1;
   if (!act1 && !act2) return;
   const int nx = S.nx, nz = S.nz, px = S.px;
-  const float* __restrict__ u1 = fwd_level(a, S, k - 1);  // may be a slot restored by reference
-  const float* __restrict__ u2 = fwd_level(a, S, k - 2);
+  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
+  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
   float* __restrict__ o1 = fbuf(a.ws, S, fwd_buf(k));
   float* __restrict__ o2 = fbuf(a.ws, S, fwd_buf(k + 1));
   const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);

@@ -203,17 +203,3 @@ def test_bench_roofline_bookkeeping():
     k1 = bench.kernel_table({"forward": (100, 100 * 0.02), "adjoint": (100, 100 * 0.03)}, 1000,
                             {"forward": "fp32", "adjoint": "fp32"}, fused=0)
     assert bench.roofline_of(k1, {"forward": "f", "adjoint": "a"})["kernel"] == "a"
-
-
-@pytest.mark.parametrize("n,s", [(48, 2), (300, 3), (5190, 16)])
-def test_bench_counts_recompute_launches_of_the_checkpoint_schedule(n, s):
-    """The benchmark's count of one- and two-level recompute launches covers every forward step
-    of the schedule exactly once; with pairs off every launch is one level."""
-    bench = _bench_module()
-    acts = A.checkpoint_schedule(n, s).tolist()
-    steps = sum(b - a for op, a, b in acts if op == 0)
-    assert bench.recompute_launches(acts, 0) == (steps, 0)
-    one, two = bench.recompute_launches(acts, 1)
-    assert one + 2 * two == steps and two > 0
-    # every advance of k >= 2 steps runs at least one pair unless it ends in a slot write
-    assert one <= sum(1 for op, a, b in acts if op == 0) * 2

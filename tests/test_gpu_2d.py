@@ -338,31 +338,3 @@ def test_checkpointed_gradient_with_uneven_nt_is_bitwise_the_full_storage_gradie
     for g, v in out[1:]:
         assert torch.equal(g, out[0][0])
         assert torch.equal(v, out[0][1])
-
-
-@pytest.mark.parametrize("tz", [8, 16, 32])
-def test_checkpoint_recompute_two_levels_per_launch_is_bitwise_the_one_level_path(tz):
-    """The recomputing forward sweeps of CHECKPOINT storage with two time levels per launch
-    (pairs start right after restores by reference; the step that writes a slot stays a
-    one-level launch): gradient, F^T dd and traces are bitwise those of one level per launch,
-    for FP32 slots (and then bitwise the FULL-storage gradient) and BF16 slots, on uneven
-    windows with per-shot nt."""
-    wl = W.small_2d(windows=[90, 70, 113, 64], T_per_shot=[600.0, 180.0, 400.0, 290.0])
-    dds = _residuals(wl)
-
-    def run(storage, fuse):
-        plan = make_plan(wl, storage=storage)
-        plan.set_tiles(tz=tz)
-        plan.set_fusion(fuse)
-        m, q = gpu_inputs(wl, plan, background=True)
-        g, v, d = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
-        _sync()
-        return [t.cpu() for t in (g, v, d)]
-
-    full = run(A.Storage(A.STORE_FULL), A.FUSE_NONE)
-    for slots, prec in ((3, A.PREC_FP32), (16, A.PREC_FP32), (3, A.PREC_BF16)):
-        one = run(A.Storage(A.STORE_CHECKPOINT, slots, prec), A.FUSE_NONE)
-        two = run(A.Storage(A.STORE_CHECKPOINT, slots, prec), A.FUSE_FORWARD)
-        assert all(torch.equal(a, b) for a, b in zip(two, one)), (slots, prec)
-        if prec == A.PREC_FP32:
-            assert all(torch.equal(a, b) for a, b in zip(two, full)), (slots, prec)
