@@ -1,10 +1,11 @@
-"""Degenerate cases of the 2D path against the oracle, through the C ABI: a computational
-grid smaller than one tile, a single time step (nt = 2), a shot without receivers in a
+"""Degenerate cases against the oracle, through the C ABI: a computational grid smaller than
+one tile (2D and 3D), a single time step (nt = 2; 2D and 3D), a shot without receivers in a
 batch, and sources and receivers exactly on grid nodes (one interpolation weight 1).
 
-Each case runs traces, F^T dd and the gradient with one and with two time levels per
-launch (odd step counts included) and compares them with the oracle at rel-L2 <= 1e-5;
-the CHECKPOINT gradient must be bitwise the FULL one."""
+Each 2D case runs traces, F^T dd and the gradient with one and with two time levels per
+launch (odd step counts included) and compares them with the oracle at rel-L2 <= 1e-5; the
+CHECKPOINT gradient must be bitwise the FULL one.  The 3D cases run two launch shapes (the
+whole depth in one z-block, and 8-plane z-blocks with a ragged last one)."""
 import numpy as np
 import pytest
 import torch
@@ -95,3 +96,46 @@ def test_source_and_receivers_on_grid_nodes():
         s.rec[:, 0] = np.arange(len(s.rec)) * h
         s.rec[:, 2] = 2.0 * h
     _check_against_oracle(wl, _residuals(wl), "on-node geometry")
+
+
+def _check_3d(wl, case):
+    dds = _residuals(wl)
+    ms = [wl.m(0, background=True)]
+    ref_d, ref_v = oracle_forward(wl, ms=ms), oracle_adjoint(wl, dds, ms=ms)
+    ref_g = oracle_gradient(wl, dds, ms=ms)
+    outs = []
+    for ty, bz in ((8, 0), (4, 8)):                 # whole depth; 8-plane blocks + a ragged one
+        plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+        plan.set_tiles(tz=32, ty=ty, bz=bz)
+        m, q = gpu_inputs(wl, plan, background=True)
+        g, v, d = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+        torch.cuda.synchronize()
+        errs = (rel_l2(plan.unpack(d, "d"), ref_d), rel_l2(plan.unpack(v, "q"), ref_v),
+                rel_l2(plan.unpack(g, "m"), ref_g))
+        print(f"{case} ty {ty} bz {bz}: traces {errs[0]:.2e}, F^T dd {errs[1]:.2e}, "
+              f"gradient {errs[2]:.2e}", flush=True)
+        assert max(errs) <= TOL, (case, ty, bz, errs)
+        outs.append([t.cpu() for t in (g, v, d)])
+    assert all(torch.equal(a, b) for a, b in zip(*outs))
+    return plan.unpack(v, "q"), plan.unpack(d, "d")
+
+
+def test_3d_grid_smaller_than_one_column_block():
+    """7 x 5 x 6 physical cells + 4-cell borders: 15 x 13 columns (a block is 64 wide) and
+    14 planes."""
+    wl = W.small_3d(n=(6, 5, 7), h=12.5, nbl=4, T=200.0, nrec_side=2, nshot=2)
+    assert wl.comp_shape(0) == (14, 13, 15)
+    _check_3d(wl, "3D tiny grid")
+
+
+def test_3d_single_time_step():
+    """nt = 2 in 3D.  After one step u^1 is nonzero only on the source's eight nodes and w^1 only
+    on the receivers' nodes, so one receiver per shot sits next to the source (otherwise every
+    output is exactly zero)."""
+    wl = W.small_3d(n=(6, 5, 7), h=12.5, nbl=4, T=1.0, nrec_side=2, nshot=2)
+    assert all(s.nt == 2 for s in wl.shots)
+    for s in wl.shots:
+        s.rec = s.rec.copy()
+        s.rec[0] = s.src + 0.3 * wl.h
+    v, d = _check_3d(wl, "3D nt = 2")
+    assert all(not x[0].any() for x in d) and all(x[1] == 0 for x in v)
