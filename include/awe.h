@@ -227,10 +227,9 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
  * awe_plan_set_fusion; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth, 128,
  * 64 or 32 planes) times the last probe_steps forward and adjoint levels of the sweep (with
  * imaging when the plan keeps a wavefield) on the given inputs, then keeps the fastest for all
- * later calls.  dd
- * may be NULL (the adjoint probe then injects nothing).  Rebuilds the plan's device tables
- * (the only allocation), overwrites the workspace and drops any kept forward.  chosen (may
- * be NULL) receives {tz, ty, bz, fusion mode} of the winner and best_ms (may be
+ * later calls.  dd may be NULL (the adjoint probe then injects nothing).  Rebuilds the plan's
+ * device tables (the only allocation), overwrites the workspace and drops any kept forward.
+ * chosen (may be NULL) receives {tz, ty, bz, fusion mode} of the winner and best_ms (may be
  * NULL) its probe time. */
 awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, const float* dd,
                              int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
@@ -246,9 +245,10 @@ awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, con
  * tables and drops any kept forward.  Errors: INVALID_ARG, HIP. */
 awe_status awe_plan_set_groups(awe_plan* plan, int32_t ngroups, int32_t* actual);
 
-/* Set the tile shape explicitly (tz: 8, 12, 16, 20, 24, 32 or 64 rows in 2D; ty: 4, 8 or 16 rows and bz:
- * z-block length, 0 = full depth, in 3D).  Results do not depend on the tile shape (every
- * point's arithmetic and every sum's order are fixed).  Rebuilds the device tables. */
+/* Set the tile shape explicitly (tz: 8, 12, 16, 20, 24, 32 or 64 rows in 2D; ty: 4, 8 or 16
+ * rows and bz: z-block length, 0 = full depth, in 3D).  Results do not depend on the tile
+ * shape (every point's arithmetic and every sum's order are fixed).  Rebuilds the device
+ * tables. */
 awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz);
 
 /* 2D only: advance two time levels per launch, chosen per direction by the bits of mode:
