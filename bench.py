@@ -140,6 +140,26 @@ def choose_tiles(plan, args, m, q, dd, ws=None):
     return plan.autotune(m, q, dd, probe_steps=32, ws=ws)[0]
 
 
+def choose_born_tiles(plan, args, run_born):
+    """Tile height for the Born pass: fixed by --tiles, else one timed eager pass per 2D tile
+    height (the library's autotuner probes forward and adjoint levels, not the Born kernel)."""
+    if args.tiles or args.no_autotune:
+        return choose_tiles(plan, args, None, None, None)
+    best = None
+    for tz in (8, 16, 32, 64):
+        plan.set_tiles(tz)
+        run_born()
+        sync()
+        t0 = time.perf_counter()
+        run_born()
+        sync()
+        t = time.perf_counter() - t0
+        if best is None or t < best[0]:
+            best = (t, tz)
+    plan.set_tiles(best[1])
+    return {"tz": best[1], "ty": 8, "bz": 0, "fusion": 0}
+
+
 def make_plan(wl, storage, shots):
     import paper_2304_05592_amd as A
     geoms = [A.ShotGeometry(wl.shots[s].window, wl.shots[s].nt, wl.shots[s].src, wl.shots[s].rec)
@@ -658,7 +678,7 @@ def bench_c8(args):
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     ws = plan.workspace()
     dd = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
-    tiles = choose_tiles(plan, args, m0, q, None, ws)
+    tiles = choose_born_tiles(plan, args, lambda: plan.born(m0, q, dm, dd=dd, ws=ws))
     groups = plan.set_groups(args.groups)
     points, launch_points = points_of(wl, range(wl.nshot))
     launch_points //= groups
