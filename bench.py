@@ -140,24 +140,30 @@ def choose_tiles(plan, args, m, q, dd, ws=None):
     return plan.autotune(m, q, dd, probe_steps=32, ws=ws)[0]
 
 
-def choose_born_tiles(plan, args, run_born):
-    """Tile height for the Born pass: fixed by --tiles, else one timed eager pass per 2D tile
-    height (the library's autotuner probes forward and adjoint levels, not the Born kernel)."""
+def choose_pass_tiles(plan, args, run, fusions=(0,)):
+    """Launch shape of a benchmark that times one kind of pass (forward only, Born): fixed by
+    --tiles, else one timed eager pass per 2D tile height and forward fusion mode (the
+    library's autotuner scores forward and adjoint levels together, and no Born levels)."""
     if args.tiles or args.no_autotune:
         return choose_tiles(plan, args, None, None, None)
     best = None
     for tz in (8, 16, 32, 64):
-        plan.set_tiles(tz)
-        run_born()
-        sync()
-        t0 = time.perf_counter()
-        run_born()
-        sync()
-        t = time.perf_counter() - t0
-        if best is None or t < best[0]:
-            best = (t, tz)
+        for fu in fusions:
+            if fu and tz == 64:                # two-level kernels exist for 8, 16, 32 rows
+                continue
+            plan.set_tiles(tz)
+            plan.set_fusion(fu)
+            run()
+            sync()
+            t0 = time.perf_counter()
+            run()
+            sync()
+            t = time.perf_counter() - t0
+            if best is None or t < best[0]:
+                best = (t, tz, fu)
     plan.set_tiles(best[1])
-    return {"tz": best[1], "ty": 8, "bz": 0, "fusion": 0}
+    plan.set_fusion(best[2])
+    return {"tz": best[1], "ty": 8, "bz": 0, "fusion": best[2]}
 
 
 def make_plan(wl, storage, shots):
@@ -678,7 +684,7 @@ def bench_c8(args):
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     ws = plan.workspace()
     dd = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
-    tiles = choose_born_tiles(plan, args, lambda: plan.born(m0, q, dm, dd=dd, ws=ws))
+    tiles = choose_pass_tiles(plan, args, lambda: plan.born(m0, q, dm, dd=dd, ws=ws))
     groups = plan.set_groups(args.groups)
     points, launch_points = points_of(wl, range(wl.nshot))
     launch_points //= groups
@@ -742,7 +748,8 @@ def bench_c4(args):
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     ws = plan.workspace()
     d = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
-    tiles = choose_tiles(plan, args, m, q, None, ws)
+    tiles = choose_pass_tiles(plan, args, lambda: plan.forward(m, q, d=d, ws=ws),
+                              fusions=(A.FUSE_NONE, A.FUSE_FORWARD))
     groups = plan.set_groups(args.groups)
     points, launch_points = points_of(wl, range(wl.nshot))
     s = torch.cuda.Stream()
