@@ -504,7 +504,8 @@ def bench_c1(args):
     q = plan.pack([wl.q(0)], "q")
     ws = plan.workspace()
     d = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
-    tiles = choose_tiles(plan, args, m, q, None, ws)
+    tiles = choose_pass_tiles(plan, args, lambda: plan.forward(m, q, d=d, ws=ws),
+                              fusions=(A.FUSE_NONE, A.FUSE_FORWARD))
     points, _ = points_of(wl, [0])
     for _ in range(max(1, args.warmup)):
         plan.forward(m, q, d=d, ws=ws)
