@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI that need no GPU: exported symbols, argument validation,
 and the binomial checkpoint schedule."""
+import argparse
 import math
 import os
 import re
@@ -203,3 +204,39 @@ def test_bench_roofline_bookkeeping():
     k1 = bench.kernel_table({"forward": (100, 100 * 0.02), "adjoint": (100, 100 * 0.03)}, 1000,
                             {"forward": "fp32", "adjoint": "fp32"}, fused=0)
     assert bench.roofline_of(k1, {"forward": "f", "adjoint": "a"})["kernel"] == "a"
+
+
+def test_bench_picks_the_fastest_pass_shape(monkeypatch):
+    """The benchmark's own tile choice for single-pass workloads times every (tile height,
+    forward fusion) candidate, skips two levels with 64-row tiles (no such kernel), keeps the
+    cheapest and leaves the plan set to it; --tiles bypasses the search."""
+    bench = _bench_module()
+    cost = {(8, 0): 5.0, (16, 0): 4.0, (32, 0): 3.5, (64, 0): 3.2, (8, 1): 4.5, (16, 1): 3.0,
+            (32, 1): 3.1}
+    clock = [0.0]
+
+    class FakePlan:
+        tz = fu = None
+        seen = []
+
+        def set_tiles(self, tz, ty=8, bz=0):
+            self.tz = tz
+
+        def set_fusion(self, fu):
+            self.fu = int(fu)
+
+    plan = FakePlan()
+
+    def run():
+        plan.seen.append((plan.tz, plan.fu))
+        clock[0] += cost[(plan.tz, plan.fu)]
+
+    monkeypatch.setattr(bench, "sync", lambda: None)
+    monkeypatch.setattr(bench.time, "perf_counter", lambda: clock[0])
+    args = argparse.Namespace(tiles=None, no_autotune=False)
+    tiles = bench.choose_pass_tiles(plan, args, run, fusions=(0, 1))
+    assert tiles == {"tz": 16, "ty": 8, "bz": 0, "fusion": 1}
+    assert (plan.tz, plan.fu) == (16, 1)
+    assert (64, 1) not in plan.seen and len(set(plan.seen)) == 7
+    fixed = argparse.Namespace(tiles={"tz": 32, "fusion": 0}, no_autotune=False)
+    assert bench.choose_pass_tiles(plan, fixed, run) == {"tz": 32, "fusion": 0}
