@@ -74,6 +74,9 @@ def parse():
                     help="shot groups per plan (0: automatic, sized to the last-level cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain device-to-device copy probe (PMC calibration)")
+    ap.add_argument("--counter-step", action="store_true",
+                    help="only run one eager c2_grad gradient step, without timing events (for "
+                         "profiler counter passes)")
     args = ap.parse_args()
     if args.tiles:
         args.tiles = {k: int(v) for k, v in (kv.split("=") for kv in args.tiles.split(","))}
@@ -491,6 +494,19 @@ def bench_c3(args):
         "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item())})
 
 
+def counter_step(args):
+    """One eager gradient step of c2_grad at the given launch shape (else the autotuner's), with
+    no HIP events between launches: the program a profiler's counter pass runs."""
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL), autotune=not args.no_autotune,
+                         tiles=args.tiles, groups=args.groups)
+    run.step()
+    sync()
+    print(json.dumps({"counter_step": "c2_grad", "tiles": run.tiles}), flush=True)
+
+
 def bench_c1(args):
     """Single-shot 2D forward (201x101 two-layer model, T = 1 s): graph-replayed time loop vs
     eager launches, and the oracle's forward on the host (the whole shot)."""
@@ -845,6 +861,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         print(json.dumps({"copy_probe": copy_probe()}), flush=True)
+        return
+    if args.counter_step:
+        counter_step(args)
         return
     fn = {"c1_fwd": bench_c1, "c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4,
           "c5_3d": bench_c5, "c6_timelapse": bench_c6,
