@@ -109,7 +109,8 @@ def lib():
     L.awe_last_error.restype = ctypes.c_char_p
     L.awe_version.restype = ctypes.c_int
     for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
-                 "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_dot_f64",
+                 "awe_gradient", "awe_adjoint", "awe_born", "awe_residual",
+                 "awe_dot_f64",
                  "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion",
                  "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_patchy",
                  "awe_patchy_vjp", "awe_profile_enable",
@@ -175,6 +176,56 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def describe(ndim, h, dt, nbl, vmax, windows, shots, damp_vref=None, damp_R=1e-3):
+    """The awe_problem of a survey (windows = computational-grid shapes, shots = ShotGeometry
+    list) and the packed-array layout.  Returns (problem, layout, shot array, receiver rows);
+    the last two must stay alive while the problem is used."""
+    windows = [tuple(int(n) for n in w) for w in windows]
+    lay = Layout(windows)
+    off = 0
+    for w in windows:
+        lay.m_offset.append(off)
+        off += int(np.prod(w))
+    lay.m_size = off
+    qo = do = 0
+    recs = []
+    cs = (AweShot * len(shots))()
+    roff = 0
+    for i, s in enumerate(shots):
+        shape = windows[s.window]
+        if ndim == 2:
+            nz, nx = shape
+            ny = 1
+        else:
+            nz, ny, nx = shape
+        rec = np.asarray(s.rec, dtype=np.float64).reshape(-1, 3)
+        cs[i].nx, cs[i].ny, cs[i].nz, cs[i].nt = nx, ny, nz, int(s.nt)
+        cs[i].m_offset = lay.m_offset[s.window]
+        cs[i].q_offset = qo
+        cs[i].d_offset = do
+        cs[i].rec_offset = roff
+        cs[i].nrec = rec.shape[0]
+        for a in range(3):
+            cs[i].src[a] = float(s.src[a])
+        lay.q_offset.append(qo)
+        lay.d_offset.append(do)
+        qo += int(s.nt)
+        do += int(s.nt) * rec.shape[0]
+        roff += rec.shape[0]
+        recs.append(rec)
+    lay.q_size, lay.d_size = qo, do
+    rec_rows = np.ascontiguousarray(np.concatenate(recs, axis=0) if recs else np.zeros((1, 3)))
+    prob = AweProblem()
+    prob.ndim, prob.nbl, prob.h, prob.dt = ndim, int(nbl), float(h), float(dt)
+    prob.vmax = float(vmax)
+    prob.damp_vref = float(vmax if damp_vref is None else damp_vref)
+    prob.damp_R = float(damp_R)
+    prob.nshot = len(shots)
+    prob.shots = ctypes.cast(cs, ctypes.POINTER(AweShot))
+    prob.rec_pos = rec_rows.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return prob, lay, cs, rec_rows
+
+
 class Plan:
     """A survey on one GPU: windows (computational-grid shapes) and shots.
 
@@ -190,50 +241,8 @@ class Plan:
         self.storage = storage or Storage()
         self.windows = [tuple(int(n) for n in w) for w in windows]
         self.shots = shots
-        lay = Layout(self.windows)
-        off = 0
-        for w in self.windows:
-            lay.m_offset.append(off)
-            off += int(np.prod(w))
-        lay.m_size = off
-        qo = do = 0
-        recs = []
-        cs = (AweShot * len(shots))()
-        roff = 0
-        for i, s in enumerate(shots):
-            shape = self.windows[s.window]
-            if ndim == 2:
-                nz, nx = shape
-                ny = 1
-            else:
-                nz, ny, nx = shape
-            rec = np.asarray(s.rec, dtype=np.float64).reshape(-1, 3)
-            cs[i].nx, cs[i].ny, cs[i].nz, cs[i].nt = nx, ny, nz, int(s.nt)
-            cs[i].m_offset = lay.m_offset[s.window]
-            cs[i].q_offset = qo
-            cs[i].d_offset = do
-            cs[i].rec_offset = roff
-            cs[i].nrec = rec.shape[0]
-            for a in range(3):
-                cs[i].src[a] = float(s.src[a])
-            lay.q_offset.append(qo)
-            lay.d_offset.append(do)
-            qo += int(s.nt)
-            do += int(s.nt) * rec.shape[0]
-            roff += rec.shape[0]
-            recs.append(rec)
-        lay.q_size, lay.d_size = qo, do
-        self.layout = lay
-        self._rec = np.ascontiguousarray(np.concatenate(recs, axis=0) if recs else np.zeros((1, 3)))
-        self._cshots = cs
-        prob = AweProblem()
-        prob.ndim, prob.nbl, prob.h, prob.dt = ndim, self.nbl, self.h, self.dt
-        prob.vmax = float(vmax)
-        prob.damp_vref = float(vmax if damp_vref is None else damp_vref)
-        prob.damp_R = float(damp_R)
-        prob.nshot = len(shots)
-        prob.shots = ctypes.cast(cs, ctypes.POINTER(AweShot))
-        prob.rec_pos = self._rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        prob, self.layout, self._cshots, self._rec = describe(ndim, h, dt, nbl, vmax, self.windows, shots,
+                                                             damp_vref, damp_R)
         st = AweStorage(self.storage.mode, self.storage.nslots, self.storage.prec, 0)
         handle = ctypes.c_void_p()
         check(L.awe_plan_create(ctypes.byref(prob), ctypes.byref(st), ctypes.byref(handle)))
