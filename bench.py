@@ -34,8 +34,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "Gpts/s (fwd+adjoint gradient) batched vs single-shot; % HBM roofline"
-# Algorithmic HBM bytes per grid point per launch of each step kernel (FP32 fields, FP64
-# accumulator); see the kernel table of the design notes.
+# Algorithmic HBM bytes per point-update of each step (FP32 fields, FP64 accumulator): the
+# per-step table of the design notes.  A launch that advances two time levels performs two
+# point-updates per grid point, so its algorithmic bytes are twice these.
 BYTES = {
     ("forward", "none"): 16,   # read u^{k-1}, u^{k-2}, coef; write u^k
     ("forward", "fp32"): 20,   # + stored copy of u^k
@@ -44,12 +45,18 @@ BYTES = {
     ("adjoint", "fp32"): 36,   # + stored u^j (4) + accumulator read and write (16)
     ("adjoint", "16bit"): 34,  # + 16-bit stored u^j (2) + accumulator (16)
     ("adjoint", "buffers"): 36,  # u^j from the recomputed forward buffer (4) + accumulator
-    # two time levels per launch (2D): inputs read once, both new levels written
-    ("forward2", "none"): 20,   # read u^{k-1}, u^{k-2}, coef; write u^k, u^{k+1}
-    ("forward2", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
-    ("adjoint2", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
     ("born", "none"): 32,       # read u^{k-1}, u^{k-2}, du^{k-1}, du^{k-2}, coef, dm; write u^k, du^k
 }
+# What a two-level launch itself moves per grid point (inputs read once, both new levels
+# written): reported beside the algorithmic figure, not used for the roofline fraction.
+FUSED_BYTES = {
+    ("forward", "none"): 20,   # read u^{k-1}, u^{k-2}, coef; write u^k, u^{k+1}
+    ("forward", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
+    ("adjoint", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
+}
+TRAFFIC_NOTE = ("rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (TCC-to-fabric bytes: L2 misses served by "
+                "the Infinity Cache are counted too), each scaled by the counter's reading for a 1 GiB "
+                "device copy")
 
 
 def parse():
@@ -64,7 +71,7 @@ def parse():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1000, help="time steps of the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=600, help="time steps of the oracle sample")
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "fp32"],
                     help="stored-wavefield precision of the 3D workload")
     ap.add_argument("--tiles", default=None,
@@ -75,8 +82,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain device-to-device copy probe (PMC calibration)")
     ap.add_argument("--counter-step", action="store_true",
-                    help="only run one eager c2_grad gradient step, without timing events (for "
-                         "profiler counter passes)")
+                    help="only run one eager gradient step of c2_grad (or c5_3d with --config), "
+                         "without timing events (for profiler counter passes)")
     args = ap.parse_args()
     if args.tiles:
         args.tiles = {k: int(v) for k, v in (kv.split("=") for kv in args.tiles.split(","))}
@@ -185,22 +192,37 @@ def points_of(wl, shots):
 
 
 def kernel_table(prof, launch_points, kinds, fused=0):
-    """Per kernel class: launches, average event time and achieved algorithmic GB/s.  For a
-    class that runs two levels per launch (fused: bit 0 forward, bit 1 adjoint) the bytes are
-    those of a two-level launch."""
+    """Per kernel class: launches, average event time and achieved algorithmic GB/s.  A class
+    that runs two levels per launch (fused: bit 0 forward, bit 1 adjoint) performs two
+    point-updates per grid point and launch; its own (fused) bytes are reported beside."""
     out = {}
     for name, kind in kinds.items():
         cnt, ms = prof[name]
         if cnt == 0:
             continue
         avg_ms = ms / cnt
-        two = bool(fused & (1 if name == "forward" else 2 if name == "adjoint" else 0))
-        key = (name + "2", kind) if two and (name + "2", kind) in BYTES else (name, kind)
-        b = BYTES[key] * launch_points
-        out[name] = {"launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 3), "bytes_per_point": BYTES[key],
-                     "levels_per_launch": 2 if key[0].endswith("2") else 1,
-                     "bytes_per_launch": b, "achieved_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1)}
+        two = bool(fused & (1 if name == "forward" else 2 if name == "adjoint" else 0)) and \
+            (name, kind) in FUSED_BYTES
+        levels = 2 if two else 1
+        b = BYTES[(name, kind)] * levels * launch_points
+        k = {"launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 3), "bytes_per_point_update": BYTES[(name, kind)],
+             "levels_per_launch": levels, "bytes_per_launch": b,
+             "achieved_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1)}
+        if two:
+            fb = FUSED_BYTES[(name, kind)] * launch_points
+            k["fused_bytes_per_point"] = FUSED_BYTES[(name, kind)]
+            k["fused_bytes_per_launch"] = fb
+            k["fused_GBs"] = round(fb / (avg_ms * 1e-3) / 1e9, 1)
+        out[name] = k
     return out
+
+
+def refresh_rates(k):
+    """Recompute a kernel entry's rates after its avg_us changed."""
+    s = k["avg_us"] * 1e-6
+    k["achieved_GBs"] = round(k["bytes_per_launch"] / s / 1e9, 1)
+    if "fused_bytes_per_launch" in k:
+        k["fused_GBs"] = round(k["fused_bytes_per_launch"] / s / 1e9, 1)
 
 
 def roofline_of(kernels, names):
@@ -208,8 +230,12 @@ def roofline_of(kernels, names):
     # differ when one direction runs two levels per launch)
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches_timed"])
     ach = kernels[dom]["achieved_GBs"]
-    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": names[dom]}
+    out = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": names[dom]}
+    if "fused_GBs" in kernels[dom]:
+        out["fused_bytes_achieved"] = kernels[dom]["fused_GBs"]
+        out["fused_bytes_frac"] = round(kernels[dom]["fused_GBs"] / PEAK_HBM_GBS, 4)
+    return out
 
 
 def timed_gradient(run, args, kind):
@@ -233,7 +259,7 @@ def timed_gradient(run, args, kind):
         k = kernels[name]
         k["eager_event_us"] = k["avg_us"]
         k["avg_us"] = round(avg_ms * 1e3, 3)
-        k["achieved_GBs"] = round(k["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
+        refresh_rates(k)
         k["segment_ms"] = round(sum(seg[key]) / len(seg[key]), 3)
     timing = ("HIP events on the launch stream between two graph segments (forward sweep + residual; "
               "reverse sweep) of every timed step: segment time / launches of its step kernel (the "
@@ -351,12 +377,12 @@ class GradientRunner:
 # ------------------------------------------------------------------------------ CPU baseline
 def _oracle_worker(args):
     """Oracle gradient of one shot over its first n samples (runs in a worker process)."""
-    name, s, n = args
+    name, s, n, dtype = args
     import workloads as W
     import oracle as O
     wl = W.make_config(name)
     sh = wl.shots[s]
-    kw = dict(src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax)
+    kw = dict(src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax, dtype=dtype)
     m_true, m0 = wl.m(sh.window), wl.m(sh.window, background=True)
     q = wl.q(s)[:n]
     d_obs = O.forward(m_true, q, **kw)
@@ -367,31 +393,43 @@ def _oracle_worker(args):
     return npts * (n - 1), (t2 - t1), float(np.abs(g).max())
 
 
-def cpu_baseline(name, wl, n):
-    """The oracle (as written) on the host cores: one process per shot, bounded sample."""
+def _oracle_sample(name, wl, n, workers, dtype):
     import multiprocessing as mp
-    ncpu = len(os.sched_getaffinity(0))
-    workers = max(1, min(8, ncpu, wl.nshot))
-    jobs = [(name, s, min(n, wl.shots[s].nt)) for s in range(workers)]
-    ctx = mp.get_context("spawn")
+    jobs = [(name, s, min(n, wl.shots[s].nt), dtype) for s in range(workers)]
     t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
+    with mp.get_context("spawn").Pool(workers) as pool:
         res = pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t0
-    work = sum(r[0] for r in res)
-    busy = max(r[1] for r in res)
+    return sum(r[0] for r in res), max(r[1] for r in res), wall, jobs[0][2]
+
+
+def cpu_baseline(name, wl, n):
+    """The oracle (as written) on the host cores: one process per shot, bounded sample, in FP64
+    (the reference) and float32 (the oracle's float32 emulation); the whole workload's time at
+    the measured rate is stated beside."""
+    ncpu = len(os.sched_getaffinity(0))
+    workers = max(1, min(8, ncpu, wl.nshot))
+    work, busy, wall, nsamp = _oracle_sample(name, wl, n, workers, np.float64)
+    work32, busy32, _, _ = _oracle_sample(name, wl, n, workers, np.float32)
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as f:
             cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": round(work / busy / 1e9, 6), "unit": "Gpts/s", "cores": workers,
+    full_work = sum(int(np.prod(wl.comp_shape(sh.window))) * (sh.nt - 1) for sh in wl.shots)
+    rate = work / busy
+    return {"value": round(rate / 1e9, 6), "unit": "Gpts/s", "cores": workers,
             "kind": "oracle", "cpu": cpu_model,
             "sample": f"{workers} shots of {name} in parallel processes (one NumPy thread each), "
-                      f"first {jobs[0][2]} of {wl.shots[0].nt} time samples; timed: forward at the "
+                      f"first {nsamp} of {wl.shots[0].nt} time samples; timed: forward at the "
                       f"starting model + gradient call (forward with stored wavefield, adjoint, "
-                      f"imaging) in FP64; wall {wall:.1f} s including process start"}
+                      f"imaging) in FP64; wall {wall:.1f} s including process start",
+            "fp32_value": round(work32 / busy32 / 1e9, 6),
+            "full_workload_seconds_at_this_rate": round(full_work / rate, 1),
+            "full_workload_note": f"all {wl.nshot} shots x all time steps on the same {workers} cores "
+                                  f"({full_work / 1e9:.2f} G point-updates), extrapolated from the sample's "
+                                  f"measured rate"}
 
 
 def base_line(args, wl, value, sec, extra):
@@ -415,16 +453,19 @@ def bench_c2(args):
     mode = fusion_of(run.tiles)
     ff, fa = bool(mode & 1), bool(mode & 2)
     use_graph = not args.no_graph
-    names = {"forward": ("fwd2d2 (two forward levels + stored FP32 copies, 28 B/point per launch)" if ff else
-                         "fwd2d step (forward + stored FP32 copy, 20 B/point)"),
-             "adjoint": ("adj2d2 (two adjoint levels + imaging from stored FP32, 44 B/point per launch)" if fa
-                         else "adj2d step (adjoint + imaging from stored FP32, 36 B/point)")}
+    names = {"forward": ("fwd2d2 (two forward levels + stored FP32 copies per launch; 20 B per point-update, "
+                         "the launch itself moves 28 B per point)" if ff else
+                         "fwd2d step (forward + stored FP32 copy, 20 B per point-update)"),
+             "adjoint": ("adj2d2 (two adjoint levels + imaging from stored FP32 per launch; 36 B per "
+                         "point-update, the launch itself moves 44 B per point)" if fa
+                         else "adj2d step (adjoint + imaging from stored FP32, 36 B per point-update)")}
     roof = roofline_of(kernels, names)
     dom_name = (f"adj2d2_kernel<{run.tiles['tz']}, 1>" if fa else f"adj2d_kernel<{run.tiles['tz']}, 1>") \
         if run.tiles else None
     roof["traffic"] = traffic_record("kernels2d.hip", dom_name, run.launch_points)
-    path_bytes = ((BYTES[("forward2", "fp32")] / 2 if ff else BYTES[("forward", "fp32")]) +
-                  (BYTES[("adjoint2", "fp32")] / 2 if fa else BYTES[("adjoint", "fp32")])) * run.points
+    roof["traffic_counter"] = TRAFFIC_NOTE
+    # the whole step against the per-step table: 20 B forward + 36 B adjoint per point-update
+    path_bytes = (BYTES[("forward", "fp32")] + BYTES[("adjoint", "fp32")]) * run.points
     loss = float(run.loss.item())
     tiles, points, groups = run.tiles, run.points, run.groups
     run.release()
@@ -495,16 +536,21 @@ def bench_c3(args):
 
 
 def counter_step(args):
-    """One eager gradient step of c2_grad at the given launch shape (else the autotuner's), with
-    no HIP events between launches: the program a profiler's counter pass runs."""
+    """One eager gradient step of c2_grad (FULL FP32) or c5_3d (FULL, --prec) at the given launch
+    shape (else the autotuner's), with no HIP events between launches: the program a profiler's
+    counter pass runs."""
     import paper_2304_05592_amd as A
     import workloads as W
-    wl = W.make_config("c2_grad")
-    run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL), autotune=not args.no_autotune,
+    name = args.config if args.config in ("c2_grad", "c5_3d") else "c2_grad"
+    wl = W.make_config(name)
+    prec = {"bf16": A.PREC_BF16, "fp16": A.PREC_FP16, "fp32": A.PREC_FP32}[args.prec] if name == "c5_3d" \
+        else A.PREC_FP32
+    run = GradientRunner(wl, range(wl.nshot), A.Storage(A.STORE_FULL, 0, prec), autotune=not args.no_autotune,
                          tiles=args.tiles, groups=args.groups)
     run.step()
     sync()
-    print(json.dumps({"counter_step": "c2_grad", "tiles": run.tiles}), flush=True)
+    print(json.dumps({"counter_step": name, "tiles": run.tiles, "points_per_launch": run.launch_points}),
+          flush=True)
 
 
 def bench_c1(args):
@@ -739,7 +785,7 @@ def bench_c8(args):
         # graph replay: the pass's time over its step launches (fills and the last gather included)
         avg_s = sec / (k["launches_timed"] // groups * groups)
         k["avg_us"] = round(avg_s * 1e6, 3)
-        k["achieved_GBs"] = round(k["bytes_per_launch"] / avg_s / 1e9, 1)
+        refresh_rates(k)
         timing = ("graph replay time per pass / step launches of the pass (auxiliary kernels included); "
                   "eager_event_us = HIP events around every launch of one eager pass")
     names = {"born": "born2d step (background + scattered field, 32 B/point)"}
@@ -812,8 +858,7 @@ def bench_c4(args):
     cnt, ms = prof["forward"]
     est_kernel_s = ms * 1e-3
     fused = bool(fusion_of(tiles) & 1)
-    per_level = BYTES[("forward2", "none")] / 2 if fused else BYTES[("forward", "none")]
-    ach = per_level * points / est_kernel_s / 1e9 if cnt else None
+    ach = BYTES[("forward", "none")] * points / est_kernel_s / 1e9 if cnt else None
     return base_line(args, wl, points / sec / 1e9, sec, {
         "metric": "Gpts/s forward, uneven batching (64 windows) batched vs sequential single-shot",
         "config": {"workload": f"{wl.name}: {wl.description}", "shots": wl.nshot,
@@ -822,8 +867,9 @@ def bench_c4(args):
         "roofline": {"bound": "hbm", "achieved": None if ach is None else round(ach, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": None if ach is None else round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": ("fwd2d2 (two levels per launch, 20 B/point per launch)" if fused else
-                                "fwd2d step (16 B/point)") + "; summed event time of one eager pass"},
+                     "kernel": ("fwd2d2 (two levels per launch, 16 B per point-update; the launch itself "
+                                "moves 20 B per point)" if fused else "fwd2d step (16 B per point-update)")
+                               + "; summed event time of one eager pass"},
         "sequential_single_shot": {"value": round(points / seq / 1e9, 3), "seconds": round(seq, 4)},
         "cpu_baseline": None})
 

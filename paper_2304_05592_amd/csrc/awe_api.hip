@@ -339,7 +339,6 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
     struct Ext { int tile; long long p; InjPoint ip; };
     std::vector<Ext> ex;
     for (const InjPoint& ip : P->inj_pts) {
-      const awe_shot& sh = P->shots[ip.shot];
       const int px = P->sd[ip.shot].px;
       const int i = (int)(ip.p % px), k = (int)(ip.p / px);
       const int TZ = P->tz;
@@ -861,7 +860,7 @@ void awe_plan_destroy(awe_plan* plan) {
 
 awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const float* dd,
                              int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
-                             int32_t chosen[3], double* best_ms) {
+                             int32_t chosen[4], double* best_ms) {
   awe_status st = check_ws(P, ws, ws_bytes);
   if (st != AWE_OK) return st;
   if (!m || !q || probe_steps < 1) return fail(AWE_ERR_INVALID_ARG, "autotune needs m, q and probe_steps >= 1");

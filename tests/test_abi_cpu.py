@@ -187,7 +187,9 @@ def _bench_module():
 
 def test_bench_roofline_bookkeeping():
     """Launch shapes map to fusion modes; a class that runs two levels per launch is charged the
-    bytes of a two-level launch; the dominant kernel is the one with the larger time share."""
+    algorithmic bytes of two point-updates per grid point (the per-step table), with the
+    launch's own fused bytes reported beside; the dominant kernel is the one with the larger
+    time share."""
     bench = _bench_module()
     assert bench.fusion_of(None) == 0
     assert bench.fusion_of({"tz": 16}) == 0
@@ -195,15 +197,22 @@ def test_bench_roofline_bookkeeping():
     assert bench.fusion_of({"tz": 16, "fusion": 2}) == 2
     prof = {"forward": (3637, 3637 * 0.018), "adjoint": (1819, 1819 * 0.051)}
     k = bench.kernel_table(prof, 1000, {"forward": "fp32", "adjoint": "fp32"}, fused=2)
-    assert k["forward"]["bytes_per_point"] == bench.BYTES[("forward", "fp32")]
-    assert k["adjoint"]["bytes_per_point"] == bench.BYTES[("adjoint2", "fp32")]
+    assert k["forward"]["bytes_per_launch"] == 20 * 1000
+    assert k["adjoint"]["bytes_per_launch"] == 2 * 36 * 1000        # two point-updates per point
+    assert k["adjoint"]["fused_bytes_per_launch"] == 44 * 1000
+    assert "fused_bytes_per_launch" not in k["forward"]
     assert k["adjoint"]["levels_per_launch"] == 2 and k["forward"]["levels_per_launch"] == 1
+    assert abs(k["adjoint"]["achieved_GBs"] - 72e3 / 51e-6 / 1e9) < 0.1
     roof = bench.roofline_of(k, {"forward": "f", "adjoint": "a"})
     assert roof["kernel"] == "a"                       # 1819 x 51 us > 3637 x 18 us
     assert abs(roof["frac"] - roof["achieved"] / bench.PEAK_HBM_GBS) < 1e-4
+    assert roof["fused_bytes_achieved"] == k["adjoint"]["fused_GBs"]
     k1 = bench.kernel_table({"forward": (100, 100 * 0.02), "adjoint": (100, 100 * 0.03)}, 1000,
                             {"forward": "fp32", "adjoint": "fp32"}, fused=0)
     assert bench.roofline_of(k1, {"forward": "f", "adjoint": "a"})["kernel"] == "a"
+    k1["adjoint"]["avg_us"] = 15.0
+    bench.refresh_rates(k1["adjoint"])
+    assert abs(k1["adjoint"]["achieved_GBs"] - 36e3 / 15e-6 / 1e9) < 0.1
 
 
 def test_bench_picks_the_fastest_pass_shape(monkeypatch):

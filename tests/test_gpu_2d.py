@@ -175,9 +175,15 @@ def _dot_errors(a, b, na, nb):
     return abs(a - b) / max(abs(a), abs(b)), abs(a - b) / (na * nb)
 
 
+# Dot tests with FP32 operators and FP64 inner products: the float32-emulated oracle reaches
+# 4.7e-7 (F) and 5.6e-6 (J) relative on these vectors (tests/golden/fp32_floor.json), below
+# 1e-5, so the plain relative difference is held to 1e-5 for both.
+DOT_TOL = 1e-5
+
+
 def test_dot_tests_on_gpu_with_fp64_inner_products():
-    """FP32 operators, FP64 inner products: |<Fx,y> - <x,F^T y>| / (||Fx|| ||y||) <= 1e-6
-    (a few float32 roundings per trace sample); the plain relative difference is reported."""
+    """FP32 operators, FP64 inner products: |<Fx,y> - <x,F^T y>| / max(|a|, |b|) <= 1e-5 (and
+    the difference scaled by ||Fx|| ||y|| <= 1e-6)."""
     wl = W.small_2d(nshot=2)
     plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
     m, _ = gpu_inputs(wl, plan)
@@ -190,7 +196,7 @@ def test_dot_tests_on_gpu_with_fp64_inner_products():
     rel, scaled = _dot_errors(a, b, torch.linalg.norm(fx.double()).item(), torch.linalg.norm(y.double()).item())
     _report("GPU F dot test (relative)", rel)
     _report("GPU F dot test (scaled)", scaled)
-    assert scaled <= 1e-6 and rel <= 1e-3
+    assert scaled <= 1e-6 and rel <= DOT_TOL
     dm = plan.pack([W.random_field(wl.comp_shape(0), 1)], "m")
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     jdm = plan.born(m, q, dm)
@@ -200,7 +206,7 @@ def test_dot_tests_on_gpu_with_fp64_inner_products():
     rel, scaled = _dot_errors(a, b, torch.linalg.norm(jdm.double()).item(), torch.linalg.norm(y.double()).item())
     _report("GPU J dot test (relative)", rel)
     _report("GPU J dot test (scaled)", scaled)
-    assert scaled <= 1e-6 and rel <= 1e-3
+    assert scaled <= 1e-6 and rel <= DOT_TOL
 
 
 def test_residual_and_dot_kernels():
