@@ -167,6 +167,17 @@ size_t awe_reduce_workspace_size(int64_t n);
 awe_status awe_residual(const float* d_pred, const float* d_obs, float* r, int64_t n,
                         double* loss, void* ws, size_t ws_bytes, void* stream);
 
+/* awe_residual without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * partial sums live in a static scratch array of the library (1024 FP64 values, 8 KiB, one copy
+ * per GPU, kept until the process ends; its device address is looked up on the first call on each
+ * GPU).  The scratch size does not depend on n (fixed partition), so no n >= 0 is refused.  Same
+ * results as awe_residual, bit for bit.  Calls that overlap on one GPU (other streams, other
+ * threads) share the scratch and race; the last call's partial sums stay in it.  Allocates
+ * nothing.  Errors: INVALID_ARG (NULL input, n < 0), HIP. */
+awe_status awe_residual_noalloc(const float* d_pred, const float* d_obs, float* r, int64_t n,
+                                double* loss, void* stream);
+
 /* *out = sum a_i b_i in FP64 (device pointer), deterministic. */
 awe_status awe_dot_f64(const float* a, const float* b, int64_t n, double* out, void* ws,
                        size_t ws_bytes, void* stream);

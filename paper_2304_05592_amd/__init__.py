@@ -6,12 +6,12 @@ operators itself, and nothing falls back to the CPU.
 """
 from .binding import (EXPORTS, FUSE_ADJOINT, FUSE_BOTH, FUSE_FORWARD, FUSE_NONE, LIB_PATH, PREC_BF16, PREC_FP16, PREC_FP32, STORE_CHECKPOINT,
                       STORE_FULL, STORE_NONE, AweError, Plan, ShotGeometry, Storage,
-                      checkpoint_schedule, dot, lib, patchy, patchy_vjp, residual, slowness2,
-                      velocity_gradient)
+                      checkpoint_schedule, dot, lib, patchy, patchy_vjp, residual, residual_noalloc,
+                      slowness2, velocity_gradient)
 
 __all__ = ["EXPORTS", "FUSE_ADJOINT", "FUSE_BOTH", "FUSE_FORWARD", "FUSE_NONE", "LIB_PATH", "PREC_BF16", "PREC_FP16", "PREC_FP32", "STORE_CHECKPOINT",
            "STORE_FULL", "STORE_NONE", "AweError", "Plan", "ShotGeometry", "Storage",
-           "checkpoint_schedule", "dot", "lib", "patchy", "patchy_vjp", "residual", "slowness2",
+           "checkpoint_schedule", "dot", "lib", "patchy", "patchy_vjp", "residual", "residual_noalloc", "slowness2",
            "velocity_gradient", "WaveOp", "wave_forward", "extend_edge", "misfit", "Slowness2",
            "slowness2_from_velocity", "Patchy", "patchy_rock_physics", "BornOp", "born_forward"]
 

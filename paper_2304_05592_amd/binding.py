@@ -24,7 +24,7 @@ PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 
 EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "awe_forward",
            "awe_backward", "awe_gradient", "awe_adjoint", "awe_born", "awe_reduce_workspace_size",
-           "awe_residual", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
+           "awe_residual", "awe_residual_noalloc", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
            "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
            "awe_slowness2", "awe_velocity_gradient", "awe_patchy", "awe_patchy_vjp", "awe_status_string", "awe_last_error", "awe_version"]
 
@@ -87,6 +87,7 @@ def lib():
     L.awe_reduce_workspace_size.argtypes = [i64]
     L.awe_reduce_workspace_size.restype = sz
     L.awe_residual.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+    L.awe_residual_noalloc.argtypes = [vp, vp, vp, i64, vp, vp]
     L.awe_dot_f64.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     L.awe_dot_f64d.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     L.awe_checkpoint_schedule.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -109,7 +110,7 @@ def lib():
     L.awe_last_error.restype = ctypes.c_char_p
     L.awe_version.restype = ctypes.c_int
     for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
-                 "awe_gradient", "awe_adjoint", "awe_born", "awe_residual",
+                 "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_residual_noalloc",
                  "awe_dot_f64",
                  "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion",
                  "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_patchy",
@@ -440,6 +441,16 @@ def residual(d_pred, d_obs, r=None, stream=None):
     ws = _reduce_ws(n, d_pred.device)
     check(lib().awe_residual(_ptr(d_pred), _ptr(d_obs), _ptr(r), n, _ptr(loss), _ptr(ws),
                              ws.numel() * 8, _stream_ptr(stream)))
+    return r, loss
+
+
+def residual_noalloc(d_pred, d_obs, r, loss, stream=None):
+    """awe_residual_noalloc: r = d_pred - d_obs and loss[0] = 1/2 sum r^2 into the given tensors
+    (r may be d_pred; loss may be None), using the library's static scratch instead of a
+    workspace - nothing is allocated, so it can run where allocation is not allowed."""
+    n = d_pred.numel()
+    check(lib().awe_residual_noalloc(_ptr(d_pred), _ptr(d_obs), _ptr(r), n, _ptr(loss),
+                                     _stream_ptr(stream)))
     return r, loss
 
 

@@ -1170,6 +1170,16 @@ awe_status awe_residual(const float* d_pred, const float* d_obs, float* r, int64
   return AWE_OK;
 }
 
+awe_status awe_residual_noalloc(const float* d_pred, const float* d_obs, float* r, int64_t n,
+                                double* loss, void* stream) {
+  if (!d_pred || !d_obs || n < 0) return fail(AWE_ERR_INVALID_ARG, "bad residual arguments");
+  double* part = nullptr;
+  AWE_HIP(awe::scratch_partials(&part));
+  AWE_HIP(awe::launch_residual(d_pred, d_obs, r, n, loss, reinterpret_cast<unsigned char*>(part),
+                               static_cast<hipStream_t>(stream)));
+  return AWE_OK;
+}
+
 awe_status awe_dot_f64(const float* a, const float* b, int64_t n, double* out, void* ws,
                        size_t ws_bytes, void* stream) {
   if (!a || !b || !out || n < 0) return fail(AWE_ERR_INVALID_ARG, "bad dot arguments");

@@ -192,5 +192,9 @@ hipError_t launch_dot(const float* a, const float* b, long long n, double* out, 
 hipError_t launch_dotd(const double* a, const double* b, long long n, double* out,
                        unsigned char* ws, hipStream_t stream);
 constexpr int kReduceBlocks = 1024;
+// Device address (current GPU) of the library's static reduction scratch of kScratchDoubles
+// FP64 values, for the allocation-free residual entry point.
+constexpr int kScratchDoubles = 1024;
+hipError_t scratch_partials(double** out);
 
 }  // namespace awe

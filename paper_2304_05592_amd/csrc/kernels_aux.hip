@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <initializer_list>
+#include <mutex>
 
 namespace awe {
 
@@ -442,6 +443,36 @@ hipError_t launch_patchy_vjp(const float* s, const float* vp, const float* rho, 
   else
     patchy_vjp_kernel<1><<<grid_cover(n), kThreads, 0, st>>>(s, vp, rho, phi, g_vp, g_rho, g_s, n, pre);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free residual entry point: the kReduceBlocks FP64 partial sums of
+// the fixed reduction partition (8 KiB, whatever the length reduced).  The array exists once on
+// every GPU the library runs on; host code uses the device address hipGetSymbolAddress returns
+// for the current device (the array's name is a host-side stand-in), looked up on the first call
+// on each device and kept.  Calls that overlap on one GPU share the array and race.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static_assert(kScratchDoubles >= kReduceBlocks, "the scratch holds one partial per reduction block");
+
+namespace {
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+hipError_t scratch_partials(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_residual(const float* a, const float* b, float* r, long long n, double* loss,
