@@ -54,6 +54,11 @@ FUSED_BYTES = {
     ("forward", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
     ("adjoint", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
 }
+# Per-launch event timing records two HIP events around a launch; a profiler's counter pass over
+# tens of thousands of such records once ended in a host fault inside the runtime, so the eager
+# timing samples at most this many launches (evenly strided) and counter passes run the
+# event-free --counter-step program.
+MAX_TIMED_LAUNCHES = 4096
 TRAFFIC_NOTE = ("rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (TCC-to-fabric bytes: L2 misses served by "
                 "the Infinity Cache are counted too), each scaled by the counter's reading for a 1 GiB "
                 "device copy")
@@ -253,8 +258,10 @@ def timed_gradient(run, args, kind):
         return eager_sec, eager_sec, kernels, "HIP events around every launch of the eager timed steps"
     run.capture()
     sec, seg = run.run(args.steps, args.warmup, use_graph=True, profile=True)
+    nsteps = max(run.wl.shots[i].nt for i in run.shots) - 1
     for name, key in (("forward", "forward_ms"), ("adjoint", "backward_ms")):
-        n_l = kernels[name]["launches_timed"] // n_eager
+        # launches of this class per step: one per time level, or per pair of levels
+        n_l = run.groups * -(-nsteps // kernels[name]["levels_per_launch"])
         avg_ms = sum(seg[key]) / len(seg[key]) / n_l
         k = kernels[name]
         k["eager_event_us"] = k["avg_us"]
@@ -346,7 +353,10 @@ class GradientRunner:
         sync()
         if profile and not use_graph:
             nt = max(self.wl.shots[i].nt for i in self.shots)
-            self.plan.profile_enable(2 * nt * steps * self.groups + 64, 1)
+            launches = 2 * nt * steps * self.groups + 64
+            # at most MAX_TIMED_LAUNCHES event pairs: every stride-th launch is timed
+            stride = -(-launches // MAX_TIMED_LAUNCHES)
+            self.plan.profile_enable(-(-launches // stride), stride)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)] \
             if profile and use_graph else None
         sync()

@@ -779,6 +779,13 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     d.off = P->max_nt - sh.nt;
     d.nrec = sh.nrec;
     d.npts = (long long)d.px * sh.ny * sh.nz;
+    // the step kernels address a field through a buffer resource with 32-bit byte offsets: the
+    // largest per-point field (the FP64 accumulator) must not exceed 1 GiB
+    if (d.npts * 8 > (1LL << 30)) {
+      delete P;
+      return fail(AWE_ERR_UNSUPPORTED, "shot " + std::to_string(s) + ": " + std::to_string(d.npts) +
+                                           " workspace points per field exceed the 2^27 the kernels address");
+    }
     d.coef = P->win_coef[win_of[sh.m_offset]];
     d.m = sh.m_offset;
     d.q = sh.q_offset;

@@ -15,7 +15,14 @@
 // field loses few digits to cancellation.  incr equals u^k - 2u^{k-1} + u^{k-2} exactly
 // before rounding, which gives the imaging condition and the Born source without the
 // cancellation of a second time difference.
+//
+// Fields are read and written through buffer resources (bufio.h): a lane's byte offset within
+// a row is fixed (kOOB for a column outside the grid: its loads read 0, its stores are
+// dropped, and it costs no memory traffic) and the row's offset is wave-uniform, so rows cost
+// no vector instructions for addresses, clamps or masks.  Rows outside the grid, and levels
+// that are zero by definition, are read through a resource of size 0.
 #include "awe_internal.h"
+#include "bufio.h"
 #include "codec.h"
 
 namespace awe {
@@ -43,53 +50,72 @@ struct T2 {
   static_assert(TZ % NW == 0, "tile rows must split evenly over the waves");
 };
 
-// Stage rows z0-4 .. z0+TZ+3 of a field, columns x0-4 .. x0+67, zero outside the grid.  The
-// 64-column body of each row is one coalesced row segment per wave (aligned: the row pitch and
-// x0 are multiples of 64); the 4 + 4 halo columns of every row follow as one short pass.
-// Loads read clamped, always valid addresses (rows past the grid read its last row, columns
-// the padded row) and the value is zeroed where the point lies outside: no load sits on a
-// branch, so all of a thread's loads are issued before the first wait.
-__device__ __forceinline__ long long cidx2(int x, int z, int nz, int px) {
-  const int xc = min(max(x, 0), px - 1), zc = min(max(z, 0), nz - 1);
-  return (long long)zc * px + xc;
+// Plane offsets of this thread's side-halo cells of a tile staged with an HW-cell halo: cell e
+// of the 2 HW columns left and right of the 64-column body of each of the H rows, starting at
+// row z0 - HW (kOOB outside the grid or past the last cell).
+template <int NT, int H, int HW>
+struct SideHalo {
+  static constexpr int NE = H * 2 * HW;
+  static constexpr int NH = (NE + NT - 1) / NT;
+};
+
+template <int NT, int H, int HW>
+__device__ __forceinline__ void side_cell(int i, int* r, int* c) {
+  constexpr int NE = SideHalo<NT, H, HW>::NE;
+  const int e = min((int)threadIdx.x + i * NT, NE - 1);
+  *r = e / (2 * HW);
+  const int cc = e - *r * (2 * HW);
+  *c = cc < HW ? cc : kTX + cc;          // columns 0 .. HW-1 and 64+HW .. 64+2HW-1
 }
 
-// Tile of f (rows z0-4 .. z0+TZ+3, columns x0-4 .. x0+67) into LDS; rows z >= nzv (or < 0)
-// and columns outside [0, nx) read as 0.  nzv <= nz: 0 for a level that is zero by definition.
-template <int TZ>
-__device__ __forceinline__ void load_tile(float (*L)[T2<TZ>::W], const float* __restrict__ f,
-                                          int nx, int nzv, int nz, int px, int x0, int z0) {
-  constexpr int H = T2<TZ>::H, NW = T2<TZ>::NW, NT = T2<TZ>::NT;
-  constexpr int NB = (H + NW - 1) / NW;                      // body rows per thread
-  constexpr int NE = H * 2 * kHalo, NH = (NE + NT - 1) / NT; // side-halo cells per thread
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int x = x0 + lane;
+template <int NT, int H, int HW>
+__device__ __forceinline__ void side_offsets(int (&ho)[(SideHalo<NT, H, HW>::NH)], int nx, int nz, int px,
+                                             int x0, int z0) {
+#pragma unroll
+  for (int i = 0; i < SideHalo<NT, H, HW>::NH; ++i) {
+    int r, c;
+    side_cell<NT, H, HW>(i, &r, &c);
+    const bool used = (int)threadIdx.x + i * NT < SideHalo<NT, H, HW>::NE;
+    ho[i] = used ? col_off(x0 - HW + c, z0 - HW + r, nx, nz, px, 4) : kOOB;
+  }
+}
+
+// Stage rows z0-HW .. z0+TZ+HW-1, columns x0-HW .. x0+63+HW of a field into LDS (W = 64 + 2 HW
+// columns, H rows), zero outside the grid: the 64-column body of each row is one aligned
+// 256-byte row segment per wave (row offset wave-uniform, column offset cx = 4 x or kOOB), the
+// side cells follow from their precomputed offsets.  All loads are issued before the first LDS
+// write.
+template <int NT, int NW, int H, int HW, int W>
+__device__ __forceinline__ void stage(float (*L)[W], const Planes& f, int cx,
+                                      const int (&ho)[(SideHalo<NT, H, HW>::NH)], int z0) {
+  constexpr int NB = H / NW, NH = SideHalo<NT, H, HW>::NH, NE = SideHalo<NT, H, HW>::NE;
+  // every wave stages whole rows: no row condition, so no branch separates the loads from
+  // their use (a branch would make the compiler wait for all loads at its start)
+  static_assert(H % NW == 0, "staged rows must split evenly over the waves");
+  const int lane = threadIdx.x & 63, wv = wave_id();
   float vb[NB], vh[NH];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) vb[i] = f[cidx2(x, z0 - kHalo + wv + i * NW, nz, px)];
+  for (int i = 0; i < NB; ++i) vb[i] = ldp(f, cx, z0 - HW + wv + i * NW);
+#pragma unroll
+  for (int i = 0; i < NH; ++i) vh[i] = ldp_at(f, ho[i]);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) L[wv + i * NW][lane + HW] = vb[i];
 #pragma unroll
   for (int i = 0; i < NH; ++i) {
-    const int e = min((int)threadIdx.x + i * NT, NE - 1);
-    const int r = e / (2 * kHalo), c8 = e - r * (2 * kHalo);
-    const int c = c8 < kHalo ? c8 : kTX + c8;
-    vh[i] = f[cidx2(x0 - kHalo + c, z0 - kHalo + r, nz, px)];
+    int r, c;
+    side_cell<NT, H, HW>(i, &r, &c);
+    if ((int)threadIdx.x + i * NT < NE) L[r][c] = vh[i];
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int r = wv + i * NW;
-    const int z = z0 - kHalo + r;
-    if (r < H) L[r][lane + kHalo] = (x < nx && (unsigned)z < (unsigned)nzv) ? vb[i] : 0.f;
-  }
-#pragma unroll
-  for (int i = 0; i < NH; ++i) {
-    const int e = (int)threadIdx.x + i * NT;
-    if (e < NE) {
-      const int r = e / (2 * kHalo), c8 = e - r * (2 * kHalo);
-      const int c = c8 < kHalo ? c8 : kTX + c8;
-      const int z = z0 - kHalo + r, xx = x0 - kHalo + c;
-      L[r][c] = ((unsigned)z < (unsigned)nzv && (unsigned)xx < (unsigned)nx) ? vh[i] : 0.f;
-    }
-  }
+}
+
+template <int TZ>
+using Side4 = SideHalo<T2<TZ>::NT, T2<TZ>::H, kHalo>;
+
+// The previous level with a 4-cell halo (one-step kernels).
+template <int TZ>
+__device__ __forceinline__ void load_tile(float (*L)[T2<TZ>::W], const Planes& f, int cx,
+                                          const int (&ho)[Side4<TZ>::NH], int z0) {
+  stage<T2<TZ>::NT, T2<TZ>::NW, T2<TZ>::H, kHalo, T2<TZ>::W>(L, f, cx, ho, z0);
 }
 
 // Difference-form Laplacian at *p in an LDS array with row stride `stride` (x neighbours at
@@ -140,26 +166,27 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, nz = S.nz, px = S.px;
-  const float* __restrict__ u1 = fwd_level(a, S, k - 1);
-  const float* __restrict__ u2 = fwd_level(a, S, k - 2);
-  float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row4 = 4 * px;
+  // levels below 1 are zero (initial state); their buffers may hold older levels after a
+  // checkpoint restore of a state before this shot's start, so they are not read
+  const Planes u1 = planes(fwd_level(a, S, k - 1), nz, k >= 2 ? nz : 0, row4);
+  const Planes u2 = planes(fwd_level(a, S, k - 2), nz, k >= 3 ? nz : 0, row4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
+  const brsrc rout = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), nz * row4);
+  const int lane = threadIdx.x & 63, wv = wave_id();
   const int x = T.x0 + lane;
+  const int cx = x < nx ? 4 * x : kOOB;
 
   float pu2[RPT], pcf[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = cidx2(x, z, nz, px);
-    const bool in = x < nx && z < nz;
-    const float v2 = u2[p], vc = cf[p];
-    pu2[i] = in && k >= 3 ? v2 : 0.f;
-    pcf[i] = in ? vc : 0.f;
+    pu2[i] = ldp(u2, cx, z);
+    pcf[i] = ldp(cf, cx, z);
   }
-  // levels below 1 are zero (initial state); their buffers may hold older levels after a
-  // checkpoint restore of a state before this shot's start, so their values are not used
-  load_tile<TZ>(L, u1, nx, k >= 2 ? nz : 0, nz, px, T.x0, T.z0);
+  int ho[Side4<TZ>::NH];
+  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  load_tile<TZ>(L, u1, cx, ho, T.z0);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -171,25 +198,30 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
 
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
-  // shot fields used in the row loop, in registers: a reload after a store through `out` would
-  // wait for every store in flight
+  // shot fields used in the row loop, in registers: a reload after a store would wait for every
+  // store in flight
   const int src_i = S.src_i, src_k = S.src_k;
   const float sw0 = S.src_w[0], sw1 = S.src_w[1], sw2 = S.src_w[2], sw3 = S.src_w[3];
-  float* st32 = SK == kStoreF32 ? reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts : nullptr;
-  float* sl = SK == kStoreNone && a.st_slot >= 0
-      ? reinterpret_cast<float*>(a.ws + S.store) + (long long)a.st_slot * 2 * S.npts : nullptr;
   const long long npts = S.npts;
-  // 16-bit store: u^{k-1} (the centre values read here) is quantised with its finished scale
+  // FULL store: level k (FP32) or level k-1 (16 bits, quantised with its finished scale)
+  const brsrc rst = SK == kStoreF32
+      ? make_rsrc(reinterpret_cast<float*>(a.ws + S.store) + (long long)k * npts, nz * row4)
+      : make_rsrc(reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * npts, nz * row4 / 2);
+  // checkpoint store fused into the step that reaches the stored state: (u^k, u^{k-1}) into slot
+  const bool to_slot = SK == kStoreNone && a.st_slot >= 0;
+  float* sl = reinterpret_cast<float*>(a.ws + S.store) + (long long)(to_slot ? a.st_slot : 0) * 2 * npts;
+  const brsrc rsl0 = make_rsrc(sl, to_slot ? nz * row4 : 0);
+  const brsrc rsl1 = make_rsrc(sl + npts, to_slot ? nz * row4 : 0);
+  const int cx2 = x < nx ? 2 * x : kOOB;
   float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
-  unsigned short* st16 = SK >= kStoreBF16
-      ? reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts : nullptr;
   const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
   float lmax = 0.f;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
+    // every lane computes; outside the grid u, u^{k-2} and coef read 0 (so the new value is 0)
+    // and the stores are dropped
     const int lr = wv * RPT + i;
     const int z = T.z0 + lr;
-    if (x >= nx || z >= nz) continue;
     const float u = L[lr + kHalo][lane + kHalo];
     float lap = lap_at<TZ>(L, lr, lane, a.c);
     const int bx = x - src_i, bz = z - src_k;
@@ -201,17 +233,16 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(u, pu2[i], pcf[i], lap, eta);
     const float un = (u + u - pu2[i]) + incr;
-    const long long p = (long long)z * px + x;
-    out[p] = un;
-    if (SK == kStoreNone && sl != nullptr) {
-      // checkpoint store fused into the step that reaches the stored state
-      sl[p] = un;
-      sl[npts + p] = u;
+    const int zo = z * row4;
+    stb(rout, un, cx, zo);
+    if (to_slot) {
+      stb(rsl0, un, cx, zo);
+      stb(rsl1, u, cx, zo);
     }
-    if (SK == kStoreF32) __builtin_nontemporal_store(un, st32 + p);
+    if (SK == kStoreF32) stb_nt(rst, un, cx, zo);
     if (SK >= kStoreBF16) {
       lmax = fmaxf(lmax, fabsf(un));
-      if (k >= 2) __builtin_nontemporal_store(enc16(u * inv_prev, SK == kStoreBF16), st16 + p);
+      if (k >= 2) stb16_nt(rst, enc16(u * inv_prev, SK == kStoreBF16), cx2, zo / 2);
     }
   }
   if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
@@ -232,22 +263,25 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
   const int nx = S.nx, nz = S.nz, px = S.px;
-  const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
-  const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
-  float* __restrict__ out = fbuf(a.ws, S, adj_buf(j));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
-  const float* __restrict__ uj = nullptr;
-  const unsigned short* __restrict__ uj16 = nullptr;
-  float usc = 1.f;
-  if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == kImgBuffers) uj = fwd_level(a, S, j);
-  if (IMG >= kImgFullBF16) {
-    uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
-    usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
-  }
-  double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row4 = 4 * px;
+  const Planes w1 = planes(fbuf(a.ws, S, adj_buf(j + 1)), nz, nz, row4);
+  const Planes w2 = planes(fbuf(a.ws, S, adj_buf(j + 2)), nz, nz, row4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
+  const brsrc rout = make_rsrc(fbuf(a.ws, S, adj_buf(j)), nz * row4);
+  // imaging: u^j from the FULL store (FP32, or 16 bits with the level's scale) or the forward
+  // buffers, and the FP64 accumulator
+  const void* ubase = IMG == kImgBuffers ? (const void*)fwd_level(a, S, j)
+                      : IMG == kImgFull32 ? (const void*)(reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts)
+                      : (const void*)(reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts);
+  const Planes uj = planes(ubase, nz, IMG ? nz : 0, IMG >= kImgFullBF16 ? row4 / 2 : row4);
+  const float usc = IMG >= kImgFullBF16 ? level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j) : 1.f;
+  const Planes acc = planes(a.ws + S.acc, nz, IMG ? nz : 0, 2 * row4);
+  const brsrc racc = make_rsrc(a.ws + S.acc, IMG ? 2 * nz * row4 : 0);
+  const int lane = threadIdx.x & 63, wv = wave_id();
   const int x = T.x0 + lane;
+  const int cx = x < nx ? 4 * x : kOOB;
+  const int cxu = x < nx ? (IMG >= kImgFullBF16 ? 2 : 4) * x : kOOB;
+  const int cx8 = x < nx ? 8 * x : kOOB;
   const bool has_inj = T.inj_count > 0 && a.dd != nullptr;  // no residual: nothing to inject
 
   float pw2[RPT], pcf[RPT], pu[RPT];
@@ -255,23 +289,17 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = cidx2(x, z, nz, px);
-    const bool in = x < nx && z < nz;
-    const float v2 = w2[p], vc = cf[p];
-    pw2[i] = in ? v2 : 0.f;
-    pcf[i] = in ? vc : 0.f;
-    if (IMG) {
-      float vu;
-      if (IMG >= kImgFullBF16) vu = dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc;
-      else if (IMG == kImgFull32) vu = __builtin_nontemporal_load(uj + p);
-      else vu = uj[p];
-      const double va = acc[p];
-      pu[i] = in ? vu : 0.f;
-      pacc[i] = in ? va : 0.0;
-    }
+    pw2[i] = ldp(w2, cx, z);
+    pcf[i] = ldp(cf, cx, z);
+    if (IMG >= kImgFullBF16) pu[i] = dec16(ldp16_nt(uj, cxu, z), IMG == kImgFullBF16) * usc;
+    else if (IMG == kImgFull32) pu[i] = ldp_nt(uj, cxu, z);
+    else if (IMG) pu[i] = ldp(uj, cxu, z);
+    if (IMG) pacc[i] = ldp64(acc, cx8, z);
     if (has_inj) INJ[wv * RPT + i][lane] = 0.f;
   }
-  load_tile<TZ>(L, w1, nx, nz, nz, px, T.x0, T.z0);
+  int ho[Side4<TZ>::NH];
+  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  load_tile<TZ>(L, w1, cx, ho, T.z0);
   __syncthreads();
 
   if (has_inj) {
@@ -293,18 +321,18 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
   const int dx = border_dist(x, nx, a.nbl);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
+    // every lane computes; outside the grid the stores are dropped
     const int lr = wv * RPT + i;
     const int z = T.z0 + lr;
-    if (x >= nx || z >= nz) continue;
     const float w = L[lr + kHalo][lane + kHalo];
     float lap = lap_at<TZ>(L, lr, lane, a.c);
     if (has_inj) lap += INJ[lr][lane];
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(w, pw2[i], pcf[i], lap, eta);
-    const long long p = (long long)z * px + x;
-    out[p] = (w + w - pw2[i]) + incr;
-    if (IMG) acc[p] = pacc[i] + (double)pu[i] * (double)incr;
+    const int zo = z * row4;
+    stb(rout, (w + w - pw2[i]) + incr, cx, zo);
+    if (IMG) stb64(racc, pacc[i] + (double)pu[i] * (double)incr, cx8, 2 * zo);
   }
 }
 
@@ -321,31 +349,32 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, nz = S.nz, px = S.px;
-  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
-  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
-  float* __restrict__ uout = fbuf(a.ws, S, fwd_buf(k));
-  const float* __restrict__ d1 = fbuf(a.ws, S, adj_buf(k - 1));
-  const float* __restrict__ d2 = fbuf(a.ws, S, adj_buf(k - 2));
-  float* __restrict__ dout = fbuf(a.ws, S, adj_buf(k));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
-  const float* __restrict__ dm = a.dm + S.m;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row4 = 4 * px;
+  const Planes u1 = planes(fbuf(a.ws, S, fwd_buf(k - 1)), nz, nz, row4);
+  const Planes u2 = planes(fbuf(a.ws, S, fwd_buf(k - 2)), nz, nz, row4);
+  const Planes d1 = planes(fbuf(a.ws, S, adj_buf(k - 1)), nz, nz, row4);
+  const Planes d2 = planes(fbuf(a.ws, S, adj_buf(k - 2)), nz, nz, row4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
+  const Planes dm = planes(a.dm + S.m, nz, nz, 4LL * nx);   // caller's layout: rows of nx
+  const brsrc ruo = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), nz * row4);
+  const brsrc rdo = make_rsrc(fbuf(a.ws, S, adj_buf(k)), nz * row4);
+  const int lane = threadIdx.x & 63, wv = wave_id();
   const int x = T.x0 + lane;
+  const int cx = x < nx ? 4 * x : kOOB;
 
   float pu2[RPT], pd2[RPT], pcf[RPT], pdm[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int z = T.z0 + wv * RPT + i;
-    const long long p = cidx2(x, z, nz, px);
-    const bool in = x < nx && z < nz;
-    const float v2 = u2[p], vd = d2[p], vc = cf[p], vm = dm[cidx2(x, z, nz, nx)];
-    pu2[i] = in ? v2 : 0.f;
-    pd2[i] = in ? vd : 0.f;
-    pcf[i] = in ? vc : 0.f;
-    pdm[i] = in ? vm : 0.f;
+    pu2[i] = ldp(u2, cx, z);
+    pd2[i] = ldp(d2, cx, z);
+    pcf[i] = ldp(cf, cx, z);
+    pdm[i] = ldp(dm, cx, z);
   }
-  load_tile<TZ>(LU, u1, nx, nz, nz, px, T.x0, T.z0);
-  load_tile<TZ>(LD, d1, nx, nz, nz, px, T.x0, T.z0);
+  int ho[Side4<TZ>::NH];
+  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  load_tile<TZ>(LU, u1, cx, ho, T.z0);
+  load_tile<TZ>(LD, d1, cx, ho, T.z0);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -361,12 +390,12 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
   const int dx = border_dist(x, nx, a.nbl);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
+    // every lane computes; outside the grid the stores are dropped
     const int lr = wv * RPT + i;
     const int z = T.z0 + lr;
-    if (x >= nx || z >= nz) continue;
     const int dz = border_dist(z, nz, a.nbl);
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
-    const long long p = (long long)z * px + x;
+    const int zo = z * row4;
     // background field
     const float u = LU[lr + kHalo][lane + kHalo];
     float lap = lap_at<TZ>(LU, lr, lane, a.c);
@@ -376,12 +405,12 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
       lap += (w == 0 ? sw0 : w == 1 ? sw1 : w == 2 ? sw2 : sw3) * qk;
     }
     const float incr = pcf[i] * (lap - eta * (u - pu2[i]));
-    uout[p] = (u + u - pu2[i]) + incr;
+    stb(ruo, (u + u - pu2[i]) + incr, cx, zo);
     // scattered field, source -dm (u^k - 2u^{k-1} + u^{k-2}) / dt^2 = -dm incr / dt^2
     const float du = LD[lr + kHalo][lane + kHalo];
     const float lapd = lap_at<TZ>(LD, lr, lane, a.c) - pdm[i] * incr * a.inv_dt2;
     const float incd = pcf[i] * (lapd - eta * (du - pd2[i]));
-    dout[p] = (du + du - pd2[i]) + incd;
+    stb(rdo, (du + du - pd2[i]) + incd, cx, zo);
   }
 }
 
@@ -403,7 +432,8 @@ struct F2 {
   static_assert(TZ % NW == 0, "tile rows must split evenly over the waves");
   // first-step points of a thread: NB in the 64 body columns (one wave per row, aligned
   // 256-byte rows), NH in the 4 + 4 side columns of every row
-  static constexpr int NB = (HE + NW - 1) / NW;
+  static constexpr int NB = HE / NW;
+  static_assert(HE % NW == 0, "extended rows must split evenly over the waves");
   static constexpr int NH = (2 * kHalo * HE + NT - 1) / NT;
   static constexpr int NS = NB + NH;
 };
@@ -413,10 +443,10 @@ struct F2 {
 template <int TZ>
 __device__ __forceinline__ bool ext_slot(int i, int* r, int* c) {
   using G = F2<TZ>;
-  if (i < G::NB) {
-    *r = (int)(threadIdx.x >> 6) + i * G::NW;
+  if (i < G::NB) {       // body slots: every row of the extended region is a whole wave's row
+    *r = wave_id() + i * G::NW;
     *c = kHalo + (int)(threadIdx.x & 63);
-    return *r < G::HE;
+    return true;
   }
   const int e0 = (int)threadIdx.x + (i - G::NB) * G::NT;
   const int e = min(e0, 2 * kHalo * G::HE - 1);
@@ -426,43 +456,36 @@ __device__ __forceinline__ bool ext_slot(int i, int* r, int* c) {
   return e0 < 2 * kHalo * G::HE;
 }
 
-// Level n-1 with an 8-cell halo into LDS: all loads first (clamped addresses, as load_tile),
-// then the LDS writes; rows z >= nzv read as 0.
 template <int TZ>
-__device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const float* __restrict__ f,
-                                           int nx, int nzv, int nz, int px, int x0, int z0) {
-  // body: the tile's 64 columns of every row, one aligned 256-byte load per wave and row;
-  // halo: the 8 + 8 side columns of every row
-  constexpr int H = F2<TZ>::H1, NW = F2<TZ>::NW, NT = F2<TZ>::NT, HW = 4 * kHalo;  // 16 side cells
-  constexpr int NB = (H + NW - 1) / NW, NE = HW * H, NH = (NE + NT - 1) / NT;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int x = x0 + lane;
-  float vb[NB], vh[NH];
+using Side8 = SideHalo<F2<TZ>::NT, F2<TZ>::H1, 2 * kHalo>;
+
+// Level n-1 with an 8-cell halo into LDS (two-step kernels).
+template <int TZ>
+__device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const Planes& f, int cx,
+                                           const int (&ho)[Side8<TZ>::NH], int z0) {
+  stage<F2<TZ>::NT, F2<TZ>::NW, F2<TZ>::H1, 2 * kHalo, F2<TZ>::W1>(L, f, cx, ho, z0);
+}
+
+// Plane offsets of this thread's first-step points that lie in the 4 + 4 side columns (the
+// extended slots past the NB body slots); kOOB outside the grid or for an unused slot.
+template <int TZ>
+__device__ __forceinline__ void ext_offsets(int (&eo)[F2<TZ>::NH], int nx, int nz, int px, int x0, int z0) {
+  using G = F2<TZ>;
 #pragma unroll
-  for (int i = 0; i < NB; ++i) vb[i] = f[cidx2(x, z0 - 2 * kHalo + wv + i * NW, nz, px)];
-#pragma unroll
-  for (int i = 0; i < NH; ++i) {
-    const int e = min((int)threadIdx.x + i * NT, NE - 1);
-    const int r = e / HW, cc = e - r * HW;
-    const int c = cc < 2 * kHalo ? cc : kTX + cc;           // columns 0..7 and 72..79
-    vh[i] = f[cidx2(x0 - 2 * kHalo + c, z0 - 2 * kHalo + r, nz, px)];
+  for (int i = 0; i < G::NH; ++i) {
+    int r, c;
+    const bool ok = ext_slot<TZ>(G::NB + i, &r, &c);
+    eo[i] = ok ? col_off(x0 - kHalo + c, z0 - kHalo + r, nx, nz, px, 4) : kOOB;
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int r = wv + i * NW;
-    const int z = z0 - 2 * kHalo + r;
-    if (r < H) L[r][lane + 2 * kHalo] = (x < nx && (unsigned)z < (unsigned)nzv) ? vb[i] : 0.f;
-  }
-#pragma unroll
-  for (int i = 0; i < NH; ++i) {
-    const int e = (int)threadIdx.x + i * NT;
-    if (e < NE) {
-      const int r = e / HW, cc = e - r * HW;
-      const int c = cc < 2 * kHalo ? cc : kTX + cc;
-      const int z = z0 - 2 * kHalo + r, xx = x0 - 2 * kHalo + c;
-      L[r][c] = ((unsigned)z < (unsigned)nzv && (unsigned)xx < (unsigned)nx) ? vh[i] : 0.f;
-    }
-  }
+}
+
+// Load of a first-step point: body slots read the row z0-4+r (wave-uniform) at column offset cx,
+// side slots their own offset.
+template <int TZ>
+__device__ __forceinline__ float ld_ext(const Planes& f, int i, int cx, const int (&eo)[F2<TZ>::NH], int z0) {
+  using G = F2<TZ>;
+  if (i < G::NB) return ldp(f, cx, z0 - kHalo + wave_id() + i * G::NW);
+  return ldp_at(f, eo[i - G::NB]);
 }
 
 // Forward: levels k and k+1 (k = step - off); SK = kStoreNone or kStoreF32.
@@ -479,37 +502,38 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   const bool act2 = k + 1 >= 1 && k + 1 <= S.nt - 1;
   if (!act1 && !act2) return;
   const int nx = S.nx, nz = S.nz, px = S.px;
-  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
-  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
-  float* __restrict__ o1 = fbuf(a.ws, S, fwd_buf(k));
-  float* __restrict__ o2 = fbuf(a.ws, S, fwd_buf(k + 1));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
-  float* st = SK == kStoreF32 ? reinterpret_cast<float*>(a.ws + S.store) : nullptr;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row4 = 4 * px;
+  // levels below 1 are zero (see fwd2d_kernel)
+  const Planes u1 = planes(fbuf(a.ws, S, fwd_buf(k - 1)), nz, k >= 2 ? nz : 0, row4);
+  const Planes u2 = planes(fbuf(a.ws, S, fwd_buf(k - 2)), nz, k >= 3 ? nz : 0, row4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
+  const long long npts = S.npts;
+  // new levels k and k+1 (a level outside 1..nt-1 belongs to an inactive step: no records)
+  const brsrc ro1 = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), act1 ? nz * row4 : 0);
+  const brsrc ro2 = make_rsrc(fbuf(a.ws, S, fwd_buf(k + 1)), act2 ? nz * row4 : 0);
+  float* st = reinterpret_cast<float*>(a.ws + S.store);
+  const brsrc rs1 = make_rsrc(st + (long long)(SK == kStoreF32 ? k : 0) * npts,
+                              SK == kStoreF32 && act1 ? nz * row4 : 0);
+  const brsrc rs2 = make_rsrc(st + (long long)(SK == kStoreF32 ? k + 1 : 0) * npts,
+                              SK == kStoreF32 && act2 ? nz * row4 : 0);
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int x = T.x0 + lane;
+  const int cx = x < nx ? 4 * x : kOOB;
 
   // prefetch level k-2 and coef of this thread's extended points, coef of its tile points
+  int eo[G::NH];
+  ext_offsets<TZ>(eo, nx, nz, px, T.x0, T.z0);
   float pm2[G::NS], pcf[G::NS], tcf[G::RPT];
 #pragma unroll
   for (int i = 0; i < G::NS; ++i) {
-    int r, c;
-    const bool ok = ext_slot<TZ>(i, &r, &c);
-    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
-    const bool in = ok && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
-    const long long p = cidx2(x, z, nz, px);
-    const float v2 = u2[p], vc = cf[p];
-    pm2[i] = in && k >= 3 ? v2 : 0.f;  // levels below 1 are zero (see fwd2d_kernel)
-    pcf[i] = in ? vc : 0.f;
+    pm2[i] = ld_ext<TZ>(u2, i, cx, eo, T.z0);
+    pcf[i] = ld_ext<TZ>(cf, i, cx, eo, T.z0);
   }
-  {
-    const int x = T.x0 + lane;
 #pragma unroll
-    for (int i = 0; i < G::RPT; ++i) {
-      const int z = T.z0 + wv * G::RPT + i;
-      const float vc = cf[cidx2(x, z, nz, px)];
-      tcf[i] = x < nx && z < nz ? vc : 0.f;
-    }
-  }
-  load_tile8<TZ>(L1, u1, nx, k >= 2 ? nz : 0, nz, px, T.x0, T.z0);
+  for (int i = 0; i < G::RPT; ++i) tcf[i] = ldp(cf, cx, T.z0 + wv * G::RPT + i);
+  int ho[Side8<TZ>::NH];
+  side_offsets<G::NT, G::H1, 2 * kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  load_tile8<TZ>(L1, u1, cx, ho, T.z0);
   __syncthreads();
 
   if (act1 && a.d != nullptr) {
@@ -524,30 +548,29 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   const int src_i = S.src_i, src_k = S.src_k;
   const float sw0 = S.src_w[0], sw1 = S.src_w[1], sw2 = S.src_w[2], sw3 = S.src_w[3];
   auto src_weight = [&](int w) { return w == 0 ? sw0 : w == 1 ? sw1 : w == 2 ? sw2 : sw3; };
-  const long long npts = S.npts;
   // first step: level k on the tile + 4-cell halo (zero outside the grid)
   const float q1 = act1 ? a.q[S.q + k - 1] : 0.f;
 #pragma unroll
   for (int i = 0; i < G::NS; ++i) {
     int r, c;
     if (!ext_slot<TZ>(i, &r, &c)) continue;
-    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
+    const int z = T.z0 - kHalo + r, xx = T.x0 - kHalo + c;
     float v = 0.f;
-    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) {
+    if ((unsigned)z < (unsigned)nz && (unsigned)xx < (unsigned)nx) {
       const float* pc = &L1[r + kHalo][c + kHalo];
       const float u = pc[0];
       float lap = lap_ptr(pc, G::W1, a.c);
-      const int bx = x - src_i, bz = z - src_k;
+      const int bx = xx - src_i, bz = z - src_k;
       if (act1 && (unsigned)bx < 2u && (unsigned)bz < 2u) lap += src_weight(bx + 2 * bz) * q1;
-      const int dx = border_dist(x, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
+      const int dx = border_dist(xx, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
       const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
       const float incr = step_incr(u, pm2[i], pcf[i], lap, eta);
       v = (u + u - pm2[i]) + incr;
-      if (act1 && r >= kHalo && r < kHalo + TZ && c >= kHalo && c < kHalo + kTX) {
-        const long long p = (long long)z * px + x;
-        o1[p] = v;
-        if (SK == kStoreF32) st[(long long)k * npts + p] = v;
-      }
+    }
+    // body slots on tile rows store level k (wave-uniform condition; columns outside drop)
+    if (i < G::NB && r >= kHalo && r < kHalo + TZ) {
+      stb(ro1, v, cx, z * row4);
+      if (SK == kStoreF32) stb_nt(rs1, v, cx, z * row4);
     }
     LE[r][c] = v;
   }
@@ -562,15 +585,13 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     }
   }
   if (!act2) return;
-  // second step: level k+1 on the tile
+  // second step: level k+1 on the tile (every lane computes; stores outside the grid drop)
   const float q2 = a.q[S.q + k];
-  const int x = T.x0 + lane;
   const int dx = border_dist(x, nx, a.nbl);
 #pragma unroll
   for (int i = 0; i < G::RPT; ++i) {
     const int lr = wv * G::RPT + i;
     const int z = T.z0 + lr;
-    if (x >= nx || z >= nz) continue;
     const float* pc = &LE[lr + kHalo][lane + kHalo];
     const float u = pc[0];
     const float um2 = L1[lr + 2 * kHalo][lane + 2 * kHalo];
@@ -581,9 +602,8 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(u, um2, tcf[i], lap, eta);
     const float un = (u + u - um2) + incr;
-    const long long p = (long long)z * px + x;
-    o2[p] = un;
-    if (SK == kStoreF32) st[(long long)(k + 1) * npts + p] = un;
+    stb(ro2, un, cx, z * row4);
+    if (SK == kStoreF32) stb_nt(rs2, un, cx, z * row4);
   }
 }
 
@@ -606,55 +626,51 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   const bool act2 = j - 1 >= 1 && j - 1 <= S.nt - 1;
   if (!act1 && !act2) return;
   const int nx = S.nx, nz = S.nz, px = S.px;
-  const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
-  const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
-  float* __restrict__ o1 = fbuf(a.ws, S, adj_buf(j));
-  float* __restrict__ o2 = fbuf(a.ws, S, adj_buf(j - 1));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
-  const float* __restrict__ ust = IMG == kImgFull32 ? reinterpret_cast<const float*>(a.ws + S.store) : nullptr;
-  double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row4 = 4 * px;
+  const Planes w1 = planes(fbuf(a.ws, S, adj_buf(j + 1)), nz, nz, row4);
+  const Planes w2 = planes(fbuf(a.ws, S, adj_buf(j + 2)), nz, nz, row4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
+  // new levels j and j-1 (a level of an inactive step gets no records: its stores drop)
+  const brsrc ro1 = make_rsrc(fbuf(a.ws, S, adj_buf(j)), act1 ? nz * row4 : 0);
+  const brsrc ro2 = make_rsrc(fbuf(a.ws, S, adj_buf(j - 1)), act2 ? nz * row4 : 0);
+  // imaging: stored u^j and u^{j-1} (levels of inactive steps read 0) and the FP64 accumulator
+  const float* ust = reinterpret_cast<const float*>(a.ws + S.store);
+  const Planes us1 = planes(ust + (long long)(IMG && act1 ? j : 0) * S.npts, nz, IMG && act1 ? nz : 0, row4);
+  const Planes us2 = planes(ust + (long long)(IMG && act2 ? j - 1 : 0) * S.npts, nz, IMG && act2 ? nz : 0, row4);
+  const Planes acc = planes(a.ws + S.acc, nz, IMG ? nz : 0, 2 * row4);
+  const brsrc racc = make_rsrc(a.ws + S.acc, IMG ? 2 * nz * row4 : 0);
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int x = T.x0 + lane;
+  const int cx = x < nx ? 4 * x : kOOB;
+  const int cx8 = x < nx ? 8 * x : kOOB;
   const bool inj1 = act1 && a.dd != nullptr && T.ext_count > 0;
   const bool inj2 = act2 && a.dd != nullptr && T.inj_count > 0;
 
+  int eo[G::NH];
+  ext_offsets<TZ>(eo, nx, nz, px, T.x0, T.z0);
   float pm2[G::NS], pcf[G::NS], tcf[G::RPT], pu1[G::RPT], pu2[G::RPT];
   double pacc[G::RPT];
 #pragma unroll
   for (int i = 0; i < G::NS; ++i) {
+    pm2[i] = ld_ext<TZ>(w2, i, cx, eo, T.z0);
+    pcf[i] = ld_ext<TZ>(cf, i, cx, eo, T.z0);
     int r, c;
-    const bool ok = ext_slot<TZ>(i, &r, &c);
-    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
-    const bool in = ok && (unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx;
-    const long long p = cidx2(x, z, nz, px);
-    const float v2 = w2[p], vc = cf[p];
-    pm2[i] = in ? v2 : 0.f;
-    pcf[i] = in ? vc : 0.f;
-    if (inj1 && ok) INJ1[r][c] = 0.f;
+    if (inj1 && ext_slot<TZ>(i, &r, &c)) INJ1[r][c] = 0.f;
   }
-  {
-    const int x = T.x0 + lane;
-    // store levels j and j-1, clamped to the stored range 0..nt-1 (a level outside it belongs
-    // to an inactive step and its value is not used)
-    const long long lv1 = min(j, S.nt - 1), lv2 = max(j - 1, 0);
 #pragma unroll
-    for (int i = 0; i < G::RPT; ++i) {
-      const int z = T.z0 + wv * G::RPT + i;
-      const bool in = x < nx && z < nz;
-      const long long p = cidx2(x, z, nz, px);
-      const float vc = cf[p];
-      tcf[i] = in ? vc : 0.f;
-      if (IMG) {
-        const float a1 = ust[lv1 * S.npts + p];
-        const float a2 = ust[lv2 * S.npts + p];
-        const double va = acc[p];
-        pu1[i] = in && act1 ? a1 : 0.f;
-        pu2[i] = in && act2 ? a2 : 0.f;
-        pacc[i] = in ? va : 0.0;
-      }
-      if (inj2) INJ2[wv * G::RPT + i][lane] = 0.f;
+  for (int i = 0; i < G::RPT; ++i) {
+    const int z = T.z0 + wv * G::RPT + i;
+    tcf[i] = ldp(cf, cx, z);
+    if (IMG) {
+      pu1[i] = ldp_nt(us1, cx, z);
+      pu2[i] = ldp_nt(us2, cx, z);
+      pacc[i] = ldp64(acc, cx8, z);
     }
+    if (inj2) INJ2[wv * G::RPT + i][lane] = 0.f;
   }
-  load_tile8<TZ>(L1, w1, nx, nz, nz, px, T.x0, T.z0);
+  int ho[Side8<TZ>::NH];
+  side_offsets<G::NT, G::H1, 2 * kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  load_tile8<TZ>(L1, w1, cx, ho, T.z0);
   __syncthreads();
 
   if (inj1 || inj2) {
@@ -695,21 +711,22 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   for (int i = 0; i < G::NS; ++i) {
     int r, c;
     if (!ext_slot<TZ>(i, &r, &c)) continue;
-    const int z = T.z0 - kHalo + r, x = T.x0 - kHalo + c;
-    float v = 0.f;
-    if ((unsigned)z < (unsigned)nz && (unsigned)x < (unsigned)nx) {
+    const int z = T.z0 - kHalo + r, xx = T.x0 - kHalo + c;
+    float v = 0.f, incr = 0.f;
+    if ((unsigned)z < (unsigned)nz && (unsigned)xx < (unsigned)nx) {
       const float* pc = &L1[r + kHalo][c + kHalo];
       const float w = pc[0];
       float lap = lap_ptr(pc, G::W1, a.c);
       if (inj1) lap += INJ1[r][c];
-      const int dx = border_dist(x, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
+      const int dx = border_dist(xx, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
       const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
-      const float incr = step_incr(w, pm2[i], pcf[i], lap, eta);
+      incr = step_incr(w, pm2[i], pcf[i], lap, eta);
       v = (w + w - pm2[i]) + incr;
-      if (r >= kHalo && r < kHalo + TZ && c >= kHalo && c < kHalo + kTX) {
-        if (act1) o1[(long long)z * px + x] = v;
-        INC1[r - kHalo][c - kHalo] = incr;
-      }
+    }
+    // body slots on tile rows: level j out, and its increment kept for the imaging
+    if (i < G::NB && r >= kHalo && r < kHalo + TZ) {
+      stb(ro1, v, cx, z * row4);
+      INC1[r - kHalo][c - kHalo] = incr;
     }
     LE[r][c] = v;
   }
@@ -720,15 +737,13 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
     a.v[S.q + j - 1] = S.src_w[0] * LE[R][C] + S.src_w[1] * LE[R][C + 1] + S.src_w[2] * LE[R + 1][C] +
                        S.src_w[3] * LE[R + 1][C + 1];
   }
-  // second step: level j-1 on the tile; imaging of both steps
-  const int x = T.x0 + lane;
+  // second step: level j-1 on the tile; imaging of both steps (every lane computes; outside
+  // the grid the stores drop)
   const int dx = border_dist(x, nx, a.nbl);
 #pragma unroll
   for (int i = 0; i < G::RPT; ++i) {
     const int lr = wv * G::RPT + i;
     const int z = T.z0 + lr;
-    if (x >= nx || z >= nz) continue;
-    const long long p = (long long)z * px + x;
     double ac = IMG ? pacc[i] : 0.0;
     if (IMG && act1) ac = ac + (double)pu1[i] * (double)INC1[lr][lane];
     if (act2) {
@@ -740,10 +755,10 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
       const int dz = border_dist(z, nz, a.nbl);
       const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
       const float incr = step_incr(w, wm2, tcf[i], lap, eta);
-      o2[p] = (w + w - wm2) + incr;
+      stb(ro2, (w + w - wm2) + incr, cx, z * row4);
       if (IMG) ac = ac + (double)pu2[i] * (double)incr;
     }
-    if (IMG) acc[p] = ac;
+    if (IMG) stb64(racc, ac, cx8, 2 * z * row4);
   }
 }
 

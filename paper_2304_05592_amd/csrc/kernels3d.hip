@@ -9,7 +9,17 @@
 // kernels2d.hip).  Receivers whose base node lies in the block are sampled from the
 // previous level (read-only during the step); the adjoint's receiver injection is a
 // separate pass over the touched points (launch_inj3d), applied after the step.
+//
+// Field planes are read and written through buffer resources (bufio.h): a lane's byte offset
+// within a plane is fixed for the whole march (kOOB for a point outside the grid, whose loads
+// then read 0 and whose stores are dropped) and the plane's offset is wave-uniform, so the
+// march spends no vector instructions on addresses, clamps or masks, and points outside the
+// grid cost no memory traffic.  Fields that a block reads only at its own points (u^{k-2},
+// coef, the accumulator) and the new level are streamed with nontemporal accesses: a 3D
+// step's working set exceeds the last-level cache, and keeping these streams out of the caches
+// leaves them to the neighbour planes and halos that are re-read.
 #include "awe_internal.h"
+#include "bufio.h"
 #include "codec.h"
 
 namespace awe {
@@ -74,32 +84,25 @@ __device__ __forceinline__ void ring_pos(int e, int* r, int* c) {
   }
 }
 
-// Loads in the z-march read clamped coordinates (rows past the grid read its last row, planes
-// past it its last plane, columns the padded row) and replace the value by 0 where the point
-// lies outside, so no load sits on a branch: the compiler can then count the loads in flight
-// exactly and keep the next planes' loads outstanding while it waits for the older ones.
-// nzv <= nz is the depth that may be read (0 for a level that is zero by definition).
-__device__ __forceinline__ long long cidx(int x, int y, int z, int ny, int nz, int px) {
-  const int xc = min(max(x, 0), px - 1), yc = min(max(y, 0), ny - 1), zc = min(max(z, 0), nz - 1);
-  return ((long long)zc * ny + yc) * px + xc;
-}
-
+// Per-lane plane offsets of this thread's ring elements (kOOB outside the grid or past the ring).
 template <int TY>
-__device__ __forceinline__ void ring_fetch(float (&h)[Ring<TY>::PER], const float* __restrict__ f,
-                                           int nx, int ny, int nzv, int nz, int px, int x0, int y0,
-                                           int z) {
-  const bool zin = (unsigned)z < (unsigned)nzv;
+__device__ __forceinline__ void ring_offsets(int (&rv)[Ring<TY>::PER], int nx, int ny, int px, int x0,
+                                             int y0) {
 #pragma unroll
   for (int i = 0; i < Ring<TY>::PER; ++i) {
     const int e0 = threadIdx.x + i * T3<TY>::NT;
     const int e = e0 < Ring<TY>::COUNT ? e0 : Ring<TY>::COUNT - 1;
     int r, c;
     ring_pos<TY>(e, &r, &c);
-    const int y = y0 - kHalo + r, x = x0 - kHalo + c;
-    const float v = f[cidx(x, y, z, ny, nz, px)];
-    const bool in = e0 < Ring<TY>::COUNT && zin && (unsigned)y < (unsigned)ny && (unsigned)x < (unsigned)nx;
-    h[i] = in ? v : 0.f;
+    rv[i] = e0 < Ring<TY>::COUNT ? col_off(x0 - kHalo + c, y0 - kHalo + r, nx, ny, px, 4) : kOOB;
   }
+}
+
+template <int TY>
+__device__ __forceinline__ void ring_fetch(float (&h)[Ring<TY>::PER], const Planes& f,
+                                           const int (&rv)[Ring<TY>::PER], int z) {
+#pragma unroll
+  for (int i = 0; i < Ring<TY>::PER; ++i) h[i] = ldp(f, rv[i], z);
 }
 
 template <int TY>
@@ -130,13 +133,6 @@ __device__ __forceinline__ float lap3(const float (*P)[T3<TY>::W], const float* 
   return s;
 }
 
-template <int TY>
-__device__ __forceinline__ float ldc(const float* __restrict__ f, int nx, int ny, int nzv, int nz,
-                                     int px, int x, int y, int z) {
-  const float v = f[cidx(x, y, z, ny, nz, px)];
-  return (x < nx && y < ny && (unsigned)z < (unsigned)nzv) ? v : 0.f;
-}
-
 // ------------------------------------------------------------------------------ forward
 // Software-pipelined z-march: after the barrier of plane z each thread issues the global
 // loads of plane z+2 (halo ring, next queue value, u^{k-2}, coef), updates plane z from LDS
@@ -152,13 +148,14 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, ny = S.ny, nz = S.nz, px = S.px;
+  const long long plane4 = 4LL * px * ny;
   // levels below 1 are zero (initial state) and are not read: after a checkpoint restore of a
   // state before this shot's start their buffers may hold older levels
-  const int nz1 = k >= 2 ? nz : 0, nz2 = k >= 3 ? nz : 0;
-  const float* __restrict__ u1 = fwd_level(a, S, k - 1);
-  const float* __restrict__ u2 = fwd_level(a, S, k - 2);
-  float* __restrict__ out = fbuf(a.ws, S, fwd_buf(k));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
+  const float* u1p = fwd_level(a, S, k - 1);
+  const Planes u1 = planes(u1p, nz, k >= 2 ? nz : 0, plane4);
+  const Planes u2 = planes(fwd_level(a, S, k - 2), nz, k >= 3 ? nz : 0, plane4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, plane4);
+  const brsrc rout = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), (int)(nz * plane4));
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int x = T.x0 + lane;
   const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
@@ -166,14 +163,13 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   if (a.d != nullptr) {
     for (int t = threadIdx.x; t < T.gat_count; t += T3<TY>::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
-      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = k >= 2 ? interp8(u1, S, R.i, R.j, R.k, R.w) : 0.f;
+      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = k >= 2 ? interp8(u1p, S, R.i, R.j, R.k, R.w) : 0.f;
     }
   }
   const float qk = a.q[S.q + k - 1];
   const int dx = border_dist(x, nx, a.nbl);
-  // shot fields used inside the z-march, copied to registers: stores through `out` could alias
-  // the shot table as far as the compiler knows, and reloading them would wait for every load
-  // in flight
+  // shot fields used inside the z-march, copied to registers: stores could alias the shot
+  // table as far as the compiler knows, and reloading them would wait for every load in flight
   const int src_i = S.src_i, src_j = S.src_j, src_k = S.src_k;
   float srcw[8];
 #pragma unroll
@@ -184,12 +180,24 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
     for (int t = 1; t < 8; ++t) w = i == t ? srcw[t] : w;
     return w;
   };
-  float* st32 = SK == kStoreF32 ? reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts : nullptr;
+  // FULL store: level k (FP32) or level k-1 (16 bits, quantised once its scale is complete)
+  const brsrc rst = SK == kStoreF32
+      ? make_rsrc(reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts, (int)(nz * plane4))
+      : make_rsrc(reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts,
+                  (int)(nz * plane4 / 2));
   float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
-  unsigned short* st16 = SK >= kStoreBF16
-      ? reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts : nullptr;
   const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
   float lmax = 0.f;
+
+  // per-lane plane offsets (fixed for the march): own columns (4- and 2-byte elements), ring
+  int cv[NC], cv2[NC], rv[HP];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int y = T.y0 + g * NC + c;
+    cv[c] = col_off(x, y, nx, ny, px, 4);
+    cv2[c] = col_off(x, y, nx, ny, px, 2);
+  }
+  ring_offsets<TY>(rv, nx, ny, px, T.x0, T.y0);
 
   // Register state of plane z: queue Q (u^{k-1} at z-4..z+4), u^{k-2} and coef.  Set A holds
   // the loads of plane z+1 (issued one plane earlier), set B those of plane z+2 (issued right
@@ -198,27 +206,25 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
   float hA[HP] = {}, qA[NC] = {}, u2A[NC] = {}, cfA[NC] = {};
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(u1, nx, ny, nz1, nz, px, x, y, T.z0 - kHalo + t);
-    pu2[c] = ldc<TY>(u2, nx, ny, nz2, nz, px, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldp(u1, cv[c], T.z0 - kHalo + t);
+    pu2[c] = ldp(u2, cv[c], T.z0);
+    pcf[c] = ldp(cf, cv[c], T.z0);
   }
   {
     float h[HP];
-    ring_fetch<TY>(h, u1, nx, ny, nz1, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(h, u1, rv, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
   }
   if (T.z0 + 1 < zend) {
-    ring_fetch<TY>(hA, u1, nx, ny, nz1, nz, px, T.x0, T.y0, T.z0 + 1);
+    ring_fetch<TY>(hA, u1, rv, T.z0 + 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int y = T.y0 + g * NC + c;
-      qA[c] = ldc<TY>(u1, nx, ny, nz1, nz, px, x, y, T.z0 + 1 + kHalo);
-      u2A[c] = ldc<TY>(u2, nx, ny, nz2, nz, px, x, y, T.z0 + 1);
-      cfA[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0 + 1);
+      qA[c] = ldp(u1, cv[c], T.z0 + 1 + kHalo);
+      u2A[c] = ldp_nt(u2, cv[c], T.z0 + 1);
+      cfA[c] = ldp_nt(cf, cv[c], T.z0 + 1);
     }
   }
   // One plane: hN.. hold the loads of plane z+1 (issued one plane earlier) and are consumed at
@@ -231,36 +237,35 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
     const int b = (z - T.z0) & 1;
     __syncthreads();
     // loads of plane z+2, unconditional (beyond the block they are simply not used)
-    ring_fetch<TY>(hL, u1, nx, ny, nz1, nz, px, T.x0, T.y0, z + 2);
+    ring_fetch<TY>(hL, u1, rv, z + 2);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int y = T.y0 + g * NC + c;
-      qL[c] = ldc<TY>(u1, nx, ny, nz1, nz, px, x, y, z + 2 + kHalo);
-      u2L[c] = ldc<TY>(u2, nx, ny, nz2, nz, px, x, y, z + 2);
-      cfL[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, z + 2);
+      qL[c] = ldp(u1, cv[c], z + 2 + kHalo);
+      u2L[c] = ldp_nt(u2, cv[c], z + 2);
+      cfL[c] = ldp_nt(cf, cv[c], z + 2);
     }
     const int dz = border_dist(z, nz, a.nbl);
+    const int zo = z * (int)plane4;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      // every lane computes; the stores of points outside the grid are dropped (offset kOOB)
       const int ly = g * NC + c;
       const int y = T.y0 + ly;
-      if (x < nx && y < ny) {
-        float lap = lap3<TY>(P[b], Q[c], ly, lane, a.c);
-        const int bx = x - src_i, by = y - src_j, bzz = z - src_k;
-        if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
-          lap += src_weight(bx + 2 * by + 4 * bzz) * qk;
-        const int dy = border_dist(y, ny, a.nbl);
-        const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
-        const float u = Q[c][4];
-        const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
-        const float un = (u + u - pu2[c]) + incr;
-        const long long p = ((long long)z * ny + y) * px + x;
-        out[p] = un;
-        if (SK == kStoreF32) __builtin_nontemporal_store(un, st32 + p);
-        if (SK >= kStoreBF16) {
-          lmax = fmaxf(lmax, fabsf(un));
-          if (k >= 2) __builtin_nontemporal_store(enc16(u * inv_prev, SK == kStoreBF16), st16 + p);
-        }
+      float lap = lap3<TY>(P[b], Q[c], ly, lane, a.c);
+      const int bx = x - src_i, by = y - src_j, bzz = z - src_k;
+      if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
+        lap += src_weight(bx + 2 * by + 4 * bzz) * qk;
+      const int dy = border_dist(y, ny, a.nbl);
+      const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
+      const float u = Q[c][4];
+      const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
+      const float un = (u + u - pu2[c]) + incr;
+      stb_nt(rout, un, cv[c], zo);
+      if (SK == kStoreF32) stb_nt(rst, un, cv[c], zo);
+      if (SK >= kStoreBF16) {
+        // outside the grid u, u^{k-2} and coef read 0, so un = 0 there
+        lmax = fmaxf(lmax, fabsf(un));
+        if (k >= 2) stb16_nt(rst, enc16(u * inv_prev, SK == kStoreBF16), cv2[c], zo / 2);
       }
     }
     if (z + 1 < zend) {
@@ -299,46 +304,46 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
   const int j = a.step - S.off;
   if (j < 1 || j >= S.nt) return;
   const int nx = S.nx, ny = S.ny, nz = S.nz, px = S.px;
-  const float* __restrict__ w1 = fbuf(a.ws, S, adj_buf(j + 1));
-  const float* __restrict__ w2 = fbuf(a.ws, S, adj_buf(j + 2));
-  float* __restrict__ out = fbuf(a.ws, S, adj_buf(j));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
-  const float* __restrict__ uj = nullptr;
-  const unsigned short* __restrict__ uj16 = nullptr;
-  float usc = 1.f;
-  if (IMG == kImgFull32) uj = reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts;
-  if (IMG == kImgBuffers) uj = fwd_level(a, S, j);
-  if (IMG >= kImgFullBF16) {
-    uj16 = reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts;
-    usc = level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j);
-  }
-  double* __restrict__ acc = IMG ? reinterpret_cast<double*>(a.ws + S.acc) : nullptr;
+  const long long plane4 = 4LL * px * ny;
+  const float* w1p = fbuf(a.ws, S, adj_buf(j + 1));
+  const Planes w1 = planes(w1p, nz, nz, plane4);
+  const Planes w2 = planes(fbuf(a.ws, S, adj_buf(j + 2)), nz, nz, plane4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, plane4);
+  const brsrc rout = make_rsrc(fbuf(a.ws, S, adj_buf(j)), (int)(nz * plane4));
+  // imaging: u^j from the FULL store (FP32, or 16 bits with the level's scale) or the forward
+  // buffers, and the FP64 accumulator
+  const void* ubase = IMG == kImgBuffers ? (const void*)fwd_level(a, S, j)
+                      : IMG == kImgFull32 ? (const void*)(reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts)
+                      : (const void*)(reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts);
+  const Planes uj = planes(ubase, nz, IMG ? nz : 0, IMG >= kImgFullBF16 ? plane4 / 2 : plane4);
+  const float usc = IMG >= kImgFullBF16 ? level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j) : 1.f;
+  const Planes acc = planes(a.ws + S.acc, nz, IMG ? nz : 0, 2 * plane4);
+  const brsrc racc = make_rsrc(a.ws + S.acc, IMG ? (int)(nz * 2 * plane4) : 0);
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int x = T.x0 + lane;
   const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
 
   if (a.v != nullptr && a.tile_base + tid == S.src_tile && threadIdx.x == 0)
-    a.v[S.q + j] = interp8(w1, S, S.src_i, S.src_j, S.src_k, S.src_w);
+    a.v[S.q + j] = interp8(w1p, S, S.src_i, S.src_j, S.src_k, S.src_w);
   const int dx = border_dist(x, nx, a.nbl);
 
+  // per-lane plane offsets (fixed for the march): own columns for 4-, 2- and 8-byte elements, ring
+  int cv[NC], cvu[NC], cv8[NC], rv[HP];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int y = T.y0 + g * NC + c;
+    cv[c] = col_off(x, y, nx, ny, px, 4);
+    cvu[c] = col_off(x, y, nx, ny, px, IMG >= kImgFullBF16 ? 2 : 4);
+    cv8[c] = col_off(x, y, nx, ny, px, 8);
+  }
+  ring_offsets<TY>(rv, nx, ny, px, T.x0, T.y0);
+
   // imaging inputs of one point: u^j and the accumulator (0 outside the grid)
-  auto load_img = [&](int y, int z, float* u, double* ac) {
-    const bool in = x < nx && y < ny && z < nz;
-    const long long p = cidx(x, y, z, ny, nz, px);
-    if (IMG >= kImgFullBF16) {
-      const float v = dec16(__builtin_nontemporal_load(uj16 + p), IMG == kImgFullBF16) * usc;
-      *u = in ? v : 0.f;
-    } else if (IMG == kImgFull32) {
-      const float v = __builtin_nontemporal_load(uj + p);
-      *u = in ? v : 0.f;
-    } else if (IMG) {
-      const float v = uj[p];
-      *u = in ? v : 0.f;
-    }
-    if (IMG) {
-      const double v = acc[p];
-      *ac = in ? v : 0.0;
-    }
+  auto load_img = [&](int c, int z, float* u, double* ac) {
+    if (IMG >= kImgFullBF16) *u = dec16(ldp16_nt(uj, cvu[c], z), IMG == kImgFullBF16) * usc;
+    else if (IMG == kImgFull32) *u = ldp_nt(uj, cvu[c], z);
+    else if (IMG) *u = ldp(uj, cvu[c], z);
+    if (IMG) *ac = ldp64_nt(acc, cv8[c], z);
   };
 
   // Register state of plane z (queue of w^{j+1}, w^{j+2}, coef, u^j, accumulator); set A holds
@@ -349,31 +354,29 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
   double accA[NC] = {};
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int y = T.y0 + g * NC + c;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) Q[c][t] = ldc<TY>(w1, nx, ny, nz, nz, px, x, y, T.z0 - kHalo + t);
-    pw2[c] = ldc<TY>(w2, nx, ny, nz, nz, px, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0);
+    for (int t = 0; t < 9; ++t) Q[c][t] = ldp(w1, cv[c], T.z0 - kHalo + t);
+    pw2[c] = ldp(w2, cv[c], T.z0);
+    pcf[c] = ldp(cf, cv[c], T.z0);
     pu[c] = 0.f;
     pacc[c] = 0.0;
-    load_img(y, T.z0, &pu[c], &pacc[c]);
+    load_img(c, T.z0, &pu[c], &pacc[c]);
   }
   {
     float h[HP];
-    ring_fetch<TY>(h, w1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(h, w1, rv, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) P[0][g * NC + c + kHalo][lane + kHalo] = Q[c][4];
     ring_store<TY>(P[0], h);
   }
   if (T.z0 + 1 < zend) {
-    ring_fetch<TY>(hA, w1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0 + 1);
+    ring_fetch<TY>(hA, w1, rv, T.z0 + 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int y = T.y0 + g * NC + c;
-      qA[c] = ldc<TY>(w1, nx, ny, nz, nz, px, x, y, T.z0 + 1 + kHalo);
-      w2A[c] = ldc<TY>(w2, nx, ny, nz, nz, px, x, y, T.z0 + 1);
-      cfA[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0 + 1);
-      load_img(y, T.z0 + 1, &uA[c], &accA[c]);
+      qA[c] = ldp(w1, cv[c], T.z0 + 1 + kHalo);
+      w2A[c] = ldp_nt(w2, cv[c], T.z0 + 1);
+      cfA[c] = ldp_nt(cf, cv[c], T.z0 + 1);
+      load_img(c, T.z0 + 1, &uA[c], &accA[c]);
     }
   }
   // Two planes per trip with the register sets swapping roles (see the forward kernel).
@@ -384,30 +387,28 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
                    float (&w2L)[NC], float (&cfL)[NC], float (&uL)[NC], double (&accL)[NC]) {
     const int b = (z - T.z0) & 1;
     __syncthreads();
-    ring_fetch<TY>(hL, w1, nx, ny, nz, nz, px, T.x0, T.y0, z + 2);
+    ring_fetch<TY>(hL, w1, rv, z + 2);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int y = T.y0 + g * NC + c;
-      qL[c] = ldc<TY>(w1, nx, ny, nz, nz, px, x, y, z + 2 + kHalo);
-      w2L[c] = ldc<TY>(w2, nx, ny, nz, nz, px, x, y, z + 2);
-      cfL[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, z + 2);
-      load_img(y, z + 2, &uL[c], &accL[c]);
+      qL[c] = ldp(w1, cv[c], z + 2 + kHalo);
+      w2L[c] = ldp_nt(w2, cv[c], z + 2);
+      cfL[c] = ldp_nt(cf, cv[c], z + 2);
+      load_img(c, z + 2, &uL[c], &accL[c]);
     }
     const int dz = border_dist(z, nz, a.nbl);
+    const int zo = z * (int)plane4;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      // every lane computes; the stores of points outside the grid are dropped (offset kOOB)
       const int ly = g * NC + c;
       const int y = T.y0 + ly;
-      if (x < nx && y < ny) {
-        const float lap = lap3<TY>(P[b], Q[c], ly, lane, a.c);
-        const int dy = border_dist(y, ny, a.nbl);
-        const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
-        const float w = Q[c][4];
-        const float incr = pcf[c] * (lap - eta * (w - pw2[c]));
-        const long long p = ((long long)z * ny + y) * px + x;
-        out[p] = (w + w - pw2[c]) + incr;
-        if (IMG) acc[p] = pacc[c] + (double)pu[c] * (double)incr;
-      }
+      const float lap = lap3<TY>(P[b], Q[c], ly, lane, a.c);
+      const int dy = border_dist(y, ny, a.nbl);
+      const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
+      const float w = Q[c][4];
+      const float incr = pcf[c] * (lap - eta * (w - pw2[c]));
+      stb_nt(rout, (w + w - pw2[c]) + incr, cv[c], zo);
+      if (IMG) stb64_nt(racc, pacc[c] + (double)pu[c] * (double)incr, cv8[c], 2 * zo);
     }
     if (z + 1 < zend) {
 #pragma unroll
@@ -477,14 +478,16 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
   const int k = a.step - S.off;
   if (k < 1 || k >= S.nt) return;
   const int nx = S.nx, ny = S.ny, nz = S.nz, px = S.px;
-  const float* __restrict__ u1 = fbuf(a.ws, S, fwd_buf(k - 1));
-  const float* __restrict__ u2 = fbuf(a.ws, S, fwd_buf(k - 2));
-  float* __restrict__ uout = fbuf(a.ws, S, fwd_buf(k));
-  const float* __restrict__ d1 = fbuf(a.ws, S, adj_buf(k - 1));
-  const float* __restrict__ d2 = fbuf(a.ws, S, adj_buf(k - 2));
-  float* __restrict__ dout = fbuf(a.ws, S, adj_buf(k));
-  const float* __restrict__ cf = reinterpret_cast<const float*>(a.ws + S.coef);
-  const float* __restrict__ dm = a.dm + S.m;
+  const long long plane4 = 4LL * px * ny;
+  const Planes u1 = planes(fbuf(a.ws, S, fwd_buf(k - 1)), nz, nz, plane4);
+  const Planes u2 = planes(fbuf(a.ws, S, fwd_buf(k - 2)), nz, nz, plane4);
+  const float* d1p = fbuf(a.ws, S, adj_buf(k - 1));
+  const Planes d1 = planes(d1p, nz, nz, plane4);
+  const Planes d2 = planes(fbuf(a.ws, S, adj_buf(k - 2)), nz, nz, plane4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, plane4);
+  const Planes dm = planes(a.dm + S.m, nz, nz, 4LL * nx * ny);   // caller's layout: rows of nx
+  const brsrc ruo = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), (int)(nz * plane4));
+  const brsrc rdo = make_rsrc(fbuf(a.ws, S, adj_buf(k)), (int)(nz * plane4));
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int x = T.x0 + lane;
   const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
   if (a.d != nullptr) {
     for (int t = threadIdx.x; t < T.gat_count; t += T3<TY>::NT) {
       const RecDev R = a.t.recs[T.gat_begin + t];
-      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp8(d1, S, R.i, R.j, R.k, R.w);
+      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] = interp8(d1p, S, R.i, R.j, R.k, R.w);
     }
   }
   const float qk = a.q[S.q + k - 1];
@@ -503,25 +506,32 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
   auto src_weight = [=](int i) {
     return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : i == 3 ? w3 : i == 4 ? w4 : i == 5 ? w5 : i == 6 ? w6 : w7;
   };
+  int cv[NC], cvm[NC], rv[HP];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int y = T.y0 + g * NC + c;
+    cv[c] = col_off(x, y, nx, ny, px, 4);
+    cvm[c] = col_off(x, y, nx, ny, nx, 4);
+  }
+  ring_offsets<TY>(rv, nx, ny, px, T.x0, T.y0);
 
   float QU[NC][9], QD[NC][9], pu2[NC], pd2[NC], pcf[NC], pdm[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int y = T.y0 + g * NC + c;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      QU[c][t] = ldc<TY>(u1, nx, ny, nz, nz, px, x, y, T.z0 - kHalo + t);
-      QD[c][t] = ldc<TY>(d1, nx, ny, nz, nz, px, x, y, T.z0 - kHalo + t);
+      QU[c][t] = ldp(u1, cv[c], T.z0 - kHalo + t);
+      QD[c][t] = ldp(d1, cv[c], T.z0 - kHalo + t);
     }
-    pu2[c] = ldc<TY>(u2, nx, ny, nz, nz, px, x, y, T.z0);
-    pd2[c] = ldc<TY>(d2, nx, ny, nz, nz, px, x, y, T.z0);
-    pcf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, T.z0);
-    pdm[c] = ldc<TY>(dm, nx, ny, nz, nz, nx, x, y, T.z0);
+    pu2[c] = ldp(u2, cv[c], T.z0);
+    pd2[c] = ldp(d2, cv[c], T.z0);
+    pcf[c] = ldp(cf, cv[c], T.z0);
+    pdm[c] = ldp(dm, cvm[c], T.z0);
   }
   {
     float hu[HP], hd[HP];
-    ring_fetch<TY>(hu, u1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0);
-    ring_fetch<TY>(hd, d1, nx, ny, nz, nz, px, T.x0, T.y0, T.z0);
+    ring_fetch<TY>(hu, u1, rv, T.z0);
+    ring_fetch<TY>(hd, d1, rv, T.z0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       PU[0][g * NC + c + kHalo][lane + kHalo] = QU[c][4];
@@ -536,40 +546,38 @@ __global__ __launch_bounds__(T3<TY>::NT) void born3d_kernel(StepArgs a, int bzle
     const bool more = z + 1 < zend;
     float hu[HP], hd[HP], qun[NC], qdn[NC], nu2[NC], nd2[NC], ncf[NC], ndm[NC];
     if (more) {
-      ring_fetch<TY>(hu, u1, nx, ny, nz, nz, px, T.x0, T.y0, z + 1);
-      ring_fetch<TY>(hd, d1, nx, ny, nz, nz, px, T.x0, T.y0, z + 1);
+      ring_fetch<TY>(hu, u1, rv, z + 1);
+      ring_fetch<TY>(hd, d1, rv, z + 1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const int y = T.y0 + g * NC + c;
-        qun[c] = ldc<TY>(u1, nx, ny, nz, nz, px, x, y, z + 1 + kHalo);
-        qdn[c] = ldc<TY>(d1, nx, ny, nz, nz, px, x, y, z + 1 + kHalo);
-        nu2[c] = ldc<TY>(u2, nx, ny, nz, nz, px, x, y, z + 1);
-        nd2[c] = ldc<TY>(d2, nx, ny, nz, nz, px, x, y, z + 1);
-        ncf[c] = ldc<TY>(cf, nx, ny, nz, nz, px, x, y, z + 1);
-        ndm[c] = ldc<TY>(dm, nx, ny, nz, nz, nx, x, y, z + 1);
+        qun[c] = ldp(u1, cv[c], z + 1 + kHalo);
+        qdn[c] = ldp(d1, cv[c], z + 1 + kHalo);
+        nu2[c] = ldp(u2, cv[c], z + 1);
+        nd2[c] = ldp(d2, cv[c], z + 1);
+        ncf[c] = ldp(cf, cv[c], z + 1);
+        ndm[c] = ldp(dm, cvm[c], z + 1);
       }
     }
     const int dz = border_dist(z, nz, a.nbl);
+    const int zo = z * (int)plane4;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      // every lane computes; the stores of points outside the grid are dropped (offset kOOB)
+      const int y = T.y0 + g * NC + c;
       const int ly = g * NC + c;
-      const int y = T.y0 + ly;
-      if (x < nx && y < ny) {
-        const int dy = border_dist(y, ny, a.nbl);
-        const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
-        const long long p = ((long long)z * ny + y) * px + x;
-        float lap = lap3<TY>(PU[b], QU[c], ly, lane, a.c);
-        const int bx = x - src_i, by = y - src_j, bzz = z - src_k;
-        if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
-          lap += src_weight(bx + 2 * by + 4 * bzz) * qk;
-        const float u = QU[c][4];
-        const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
-        uout[p] = (u + u - pu2[c]) + incr;
-        const float du = QD[c][4];
-        const float lapd = lap3<TY>(PD[b], QD[c], ly, lane, a.c) - pdm[c] * incr * a.inv_dt2;
-        const float incd = pcf[c] * (lapd - eta * (du - pd2[c]));
-        dout[p] = (du + du - pd2[c]) + incd;
-      }
+      const int dy = border_dist(y, ny, a.nbl);
+      const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
+      float lap = lap3<TY>(PU[b], QU[c], ly, lane, a.c);
+      const int bx = x - src_i, by = y - src_j, bzz = z - src_k;
+      if ((unsigned)bx < 2u && (unsigned)by < 2u && (unsigned)bzz < 2u)
+        lap += src_weight(bx + 2 * by + 4 * bzz) * qk;
+      const float u = QU[c][4];
+      const float incr = pcf[c] * (lap - eta * (u - pu2[c]));
+      stb(ruo, (u + u - pu2[c]) + incr, cv[c], zo);
+      const float du = QD[c][4];
+      const float lapd = lap3<TY>(PD[b], QD[c], ly, lane, a.c) - pdm[c] * incr * a.inv_dt2;
+      const float incd = pcf[c] * (lapd - eta * (du - pd2[c]));
+      stb(rdo, (du + du - pd2[c]) + incd, cv[c], zo);
     }
     if (more) {
 #pragma unroll

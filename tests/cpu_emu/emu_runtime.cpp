@@ -140,6 +140,20 @@ void resume(int t) {
 
 unsigned long long* xchg_slots() { return slots.data(); }
 
+char* buffer_at(const __amdgpu_buffer_rsrc_t& r, int voff, int soff, unsigned size) {
+  const unsigned long long off = (unsigned long long)(unsigned)voff + (unsigned)soff;
+  if (off >> 32) {
+    std::fprintf(stderr, "emu: buffer offset %u + %u wraps 32 bits\n", (unsigned)voff, (unsigned)soff);
+    std::abort();
+  }
+  if ((off & (size - 1)) != 0) {
+    std::fprintf(stderr, "emu: misaligned buffer access at offset %llu (size %u)\n", off, size);
+    std::abort();
+  }
+  if (off + size > r.bytes) return nullptr;
+  return r.base + off;
+}
+
 void syncthreads() {
   if (cur < 0) {
     std::fprintf(stderr, "emu: __syncthreads outside a kernel\n");

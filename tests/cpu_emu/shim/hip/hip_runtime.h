@@ -45,6 +45,8 @@ unsigned long long* xchg_slots();
 #define gridDim (::emu::grid_dim)
 
 inline void __syncthreads() { ::emu::syncthreads(); }
+// lane 0's value of a wave-uniform operand (every lane holds the same value where it is used)
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
 #define __builtin_amdgcn_s_waitcnt(x) ((void)(x))
 
 template <class T>
@@ -85,6 +87,54 @@ inline float atomicAdd(float* p, float v) { const float o = *p; *p = o + v; retu
 
 struct uint4 { unsigned x, y, z, w; };
 inline uint4 make_uint4(unsigned x, unsigned y, unsigned z, unsigned w) { return {x, y, z, w}; }
+
+// ---------------------------------------------------------------- buffer resources
+// A raw buffer resource: base and size in bytes.  An access whose byte offset (per-lane plus
+// uniform part, summed without wrapping) reaches past the size loads 0 and stores nothing; a
+// sum that would wrap 32 bits is reported, since the hardware's 32-bit sum would then differ.
+struct __amdgpu_buffer_rsrc_t {
+  char* base;
+  unsigned bytes;
+};
+namespace emu {
+char* buffer_at(const __amdgpu_buffer_rsrc_t& r, int voff, int soff, unsigned size);
+}
+inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void* p, short stride, int bytes, int flags) {
+  (void)stride;
+  (void)flags;
+  return {static_cast<char*>(p), (unsigned)bytes};
+}
+inline unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int voff, int soff, int aux) {
+  (void)aux;
+  unsigned v = 0;
+  if (char* p = ::emu::buffer_at(r, voff, soff, 4)) std::memcpy(&v, p, 4);
+  return v;
+}
+inline unsigned short __builtin_amdgcn_raw_buffer_load_b16(__amdgpu_buffer_rsrc_t r, int voff, int soff, int aux) {
+  (void)aux;
+  unsigned short v = 0;
+  if (char* p = ::emu::buffer_at(r, voff, soff, 2)) std::memcpy(&v, p, 2);
+  return v;
+}
+typedef unsigned emu_u32x2 __attribute__((ext_vector_type(2)));
+inline emu_u32x2 __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, int voff, int soff, int aux) {
+  (void)aux;
+  emu_u32x2 v = {0u, 0u};
+  if (char* p = ::emu::buffer_at(r, voff, soff, 8)) std::memcpy(&v, p, 8);
+  return v;
+}
+inline void __builtin_amdgcn_raw_buffer_store_b32(unsigned v, __amdgpu_buffer_rsrc_t r, int voff, int soff, int aux) {
+  (void)aux;
+  if (char* p = ::emu::buffer_at(r, voff, soff, 4)) std::memcpy(p, &v, 4);
+}
+inline void __builtin_amdgcn_raw_buffer_store_b16(unsigned short v, __amdgpu_buffer_rsrc_t r, int voff, int soff, int aux) {
+  (void)aux;
+  if (char* p = ::emu::buffer_at(r, voff, soff, 2)) std::memcpy(p, &v, 2);
+}
+inline void __builtin_amdgcn_raw_buffer_store_b64(emu_u32x2 v, __amdgpu_buffer_rsrc_t r, int voff, int soff, int aux) {
+  (void)aux;
+  if (char* p = ::emu::buffer_at(r, voff, soff, 8)) std::memcpy(p, &v, 8);
+}
 
 // ---------------------------------------------------------------- runtime
 typedef int hipError_t;
