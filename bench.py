@@ -80,8 +80,9 @@ def parse():
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "fp32"],
                     help="stored-wavefield precision of the 3D workload")
     ap.add_argument("--tiles", default=None,
-                    help="fixed launch shape instead of the autotuner, e.g. tz=32 or tz=16,fusion=2 "
-                         "(two levels per launch: 1 forward, 2 reverse sweep, 3 both)")
+                    help="fixed launch shape instead of the autotuner, e.g. tz=32 or tz=32,atz=16,fusion=3 "
+                         "(tz/ty/bz both directions, atz/aty/abz adjoint steps only; two levels per "
+                         "launch: fusion 1 forward, 2 reverse sweep, 3 both)")
     ap.add_argument("--groups", type=int, default=0,
                     help="shot groups per plan (0: automatic, sized to the last-level cache)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -143,13 +144,26 @@ def fusion_of(tiles):
     return 3 if tiles.get("levels_per_launch", 1) == 2 else 0
 
 
+def apply_tiles(plan, t):
+    """Set a fixed launch shape: tz / ty / bz for both directions, atz / aty / abz (optional) for
+    the adjoint steps only, and the fusion mode; returns the shapes in effect."""
+    plan.set_tiles(t.get("tz", 32), t.get("ty", 8), t.get("bz", 0))
+    if any(k in t for k in ("atz", "aty", "abz")):
+        plan.set_tiles(t.get("atz", t.get("tz", 32)), t.get("aty", t.get("ty", 8)), t.get("abz", t.get("bz", 0)),
+                       dirs=2)
+    plan.set_fusion(fusion_of(t))
+    return plan.get_tiles()
+
+
+def adjoint_tz(tiles):
+    """Row count of the adjoint steps' tiles in a launch-shape record."""
+    return tiles.get("adjoint", {}).get("tz", tiles.get("atz", tiles.get("tz")))
+
+
 def choose_tiles(plan, args, m, q, dd, ws=None):
     """Fixed launch shape from --tiles, else the autotuner's choice (None with --no-autotune)."""
     if args.tiles:
-        t = args.tiles
-        plan.set_tiles(t.get("tz", 32), t.get("ty", 8), t.get("bz", 0))
-        plan.set_fusion(fusion_of(t))
-        return dict(t)
+        return apply_tiles(plan, args.tiles)
     if args.no_autotune:
         return None
     return plan.autotune(m, q, dd, probe_steps=32, ws=ws)[0]
@@ -296,9 +310,7 @@ class GradientRunner:
         self.points, self.launch_points = points_of(wl, self.shots)
         self.tiles = None
         if tiles:
-            p.set_tiles(tiles.get("tz", 32), tiles.get("ty", 8), tiles.get("bz", 0))
-            p.set_fusion(fusion_of(tiles))
-            self.tiles = dict(tiles)
+            self.tiles = apply_tiles(p, tiles)
         elif autotune:
             self.tiles, _ = p.autotune(self.m0, self.q, self.d_obs, probe_steps=32, ws=self.ws)
         self.groups = p.set_groups(groups)   # shot groups in effect (0: automatic)
@@ -470,7 +482,7 @@ def bench_c2(args):
                          "point-update, the launch itself moves 44 B per point)" if fa
                          else "adj2d step (adjoint + imaging from stored FP32, 36 B per point-update)")}
     roof = roofline_of(kernels, names)
-    dom_name = (f"adj2d2_kernel<{run.tiles['tz']}, 1>" if fa else f"adj2d_kernel<{run.tiles['tz']}, 1>") \
+    dom_name = (f"adj2d2_kernel<{adjoint_tz(run.tiles)}, 1>" if fa else f"adj2d_kernel<{adjoint_tz(run.tiles)}, 1>") \
         if run.tiles else None
     roof["traffic"] = traffic_record("kernels2d.hip", dom_name, run.launch_points)
     roof["traffic_counter"] = TRAFFIC_NOTE

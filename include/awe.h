@@ -232,19 +232,26 @@ awe_status awe_patchy_vjp(const float* s, const float* vp, const float* rho, con
 awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions,
                                    int64_t cap, int64_t* count);
 
-/* Tile-shape autotuner (setup call, synchronous): for each candidate (2D: 8, 16, 32 or 64
- * rows of 64 columns, and - where the storage mode allows it - 8, 16 or 32 rows with two
- * time levels per launch in the forward solve, the reverse sweep or both, see
- * awe_plan_set_fusion; 3D: 64 x {4, 8, 16} columns with z-blocks of the full depth, 128,
- * 64 or 32 planes) times the last probe_steps forward and adjoint levels of the sweep (with
- * imaging when the plan keeps a wavefield) on the given inputs, then keeps the fastest for all
- * later calls.  dd may be NULL (the adjoint probe then injects nothing).  Rebuilds the plan's
- * device tables (the only allocation), overwrites the workspace and drops any kept forward.
- * chosen (may be NULL) receives {tz, ty, bz, fusion mode} of the winner and best_ms (may be
- * NULL) its probe time. */
+/* Tile-shape autotuner (setup call, synchronous).  The plan has a launch shape for its forward
+ * solves (and Born modelling) and one for its adjoint steps (reverse sweeps and awe_adjoint); the
+ * autotuner chooses each separately.  Candidates: 2D 8, 16, 32 or 64 rows of 64 columns, and -
+ * where the storage mode allows it - 8, 16 or 32 rows with two time levels per launch (see
+ * awe_plan_set_fusion); 3D 64 x {4, 8, 16} columns with z-blocks of the full depth, 128, 64 or
+ * 32 planes.  The forward probe times the last probe_steps forward levels of the sweep (storing
+ * the wavefield when the plan keeps one in FP32), the adjoint probe the last probe_steps adjoint
+ * levels (with imaging when the plan keeps a wavefield), on the given inputs; the fastest of
+ * each is kept for all later calls.  dd may be NULL (the adjoint probe then injects nothing).
+ * Rebuilds the plan's device tables (the only allocation), overwrites the workspace and drops
+ * any kept forward.  chosen (may be NULL) receives {tz, ty, bz} of the forward shape and the
+ * fusion mode (awe_plan_get_tiles gives both shapes); best_ms (may be NULL) the sum of the two
+ * winning probe times. */
 awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, const float* dd,
                              int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
                              int32_t chosen[4], double* best_ms);
+
+/* The launch shapes in effect: fwd / adj (each may be NULL) receive {tz, ty, bz} of the forward
+ * solves and of the adjoint steps; fusion (may be NULL) the two-levels-per-launch mode. */
+awe_status awe_plan_get_tiles(const awe_plan* plan, int32_t fwd[3], int32_t adj[3], int32_t* fusion);
 
 /* Shot groups (batching, a12): the plan's shots, sorted by time offset, are split into
  * groups of consecutive shots; every call runs the time loop of one group after the other
@@ -257,9 +264,13 @@ awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, con
 awe_status awe_plan_set_groups(awe_plan* plan, int32_t ngroups, int32_t* actual);
 
 /* Set the tile shape explicitly (tz: 8, 12, 16, 20, 24, 32 or 64 rows in 2D; ty: 4, 8 or 16
- * rows and bz: z-block length, 0 = full depth, in 3D).  Results do not depend on the tile
- * shape (every point's arithmetic and every sum's order are fixed).  Rebuilds the device
- * tables. */
+ * rows and bz: z-block length, 0 = full depth, in 3D) of the forward solves and Born modelling
+ * (dirs bit AWE_DIR_FORWARD), of the adjoint steps (AWE_DIR_ADJOINT) or of both;
+ * awe_plan_set_tiles sets both.  Results do not depend on the tile shapes (every point's
+ * arithmetic and every sum's order are fixed).  Rebuilds the device tables of the directions
+ * set. */
+enum { AWE_DIR_FORWARD = 1, AWE_DIR_ADJOINT = 2, AWE_DIR_BOTH = 3 };
+awe_status awe_plan_set_tiles_dir(awe_plan* plan, int32_t dirs, int32_t tz, int32_t ty, int32_t bz);
 awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz);
 
 /* 2D only: advance two time levels per launch, chosen per direction by the bits of mode:

@@ -25,7 +25,8 @@ PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "awe_forward",
            "awe_backward", "awe_gradient", "awe_adjoint", "awe_born", "awe_reduce_workspace_size",
            "awe_residual", "awe_residual_noalloc", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
-           "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
+           "awe_plan_autotune", "awe_plan_get_tiles", "awe_plan_set_tiles", "awe_plan_set_tiles_dir",
+           "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
            "awe_slowness2", "awe_velocity_gradient", "awe_patchy", "awe_patchy_vjp", "awe_status_string", "awe_last_error", "awe_version"]
 
 
@@ -95,6 +96,9 @@ def lib():
     L.awe_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, sz, vp,
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     L.awe_plan_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.awe_plan_set_tiles_dir.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.awe_plan_get_tiles.argtypes = [vp, i32p, i32p, i32p]
     L.awe_plan_set_fusion.argtypes = [vp, ctypes.c_int32]
     L.awe_plan_set_groups.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.awe_slowness2.argtypes = [vp, vp, i64, vp]
@@ -112,8 +116,8 @@ def lib():
     for name in ("awe_plan_create", "awe_plan_workspace_size", "awe_forward", "awe_backward",
                  "awe_gradient", "awe_adjoint", "awe_born", "awe_residual", "awe_residual_noalloc",
                  "awe_dot_f64",
-                 "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_set_tiles", "awe_plan_set_fusion",
-                 "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_patchy",
+                 "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_get_tiles", "awe_plan_set_tiles",
+                 "awe_plan_set_tiles_dir", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_patchy",
                  "awe_patchy_vjp", "awe_profile_enable",
                  "awe_profile_read", "awe_profile_disable"):
         getattr(L, name).restype = ctypes.c_int
@@ -297,17 +301,27 @@ class Plan:
 
     # ---------------------------------------------------------------- tile autotuning
     def autotune(self, m, q, dd=None, probe_steps: int = 24, ws=None, stream=None):
-        """Time each candidate tile shape on these inputs and keep the fastest.
-        Returns ({'tz', 'ty', 'bz'}, probe ms)."""
+        """Time the candidate launch shapes of each direction on these inputs and keep the
+        fastest.  Returns ({'tz', 'ty', 'bz', 'fusion', 'adjoint': {'tz', 'ty', 'bz'}}, probe ms):
+        the forward shape, the fusion mode and the adjoint shape."""
         ws = self.workspace(m.device) if ws is None else ws
         ch = (ctypes.c_int32 * 4)()
         ms = ctypes.c_double(0.0)
         check(lib().awe_plan_autotune(self._h, _ptr(m), _ptr(q), _ptr(dd), int(probe_steps), _ptr(ws),
                                       self.ws_bytes, _stream_ptr(stream), ch, ctypes.byref(ms)))
-        return {"tz": ch[0], "ty": ch[1], "bz": ch[2], "fusion": ch[3]}, ms.value
+        return self.get_tiles(), ms.value
 
-    def set_tiles(self, tz: int = 32, ty: int = 8, bz: int = 0):
-        check(lib().awe_plan_set_tiles(self._h, int(tz), int(ty), int(bz)))
+    def get_tiles(self):
+        """{'tz', 'ty', 'bz', 'fusion', 'adjoint': {'tz', 'ty', 'bz'}}: the launch shapes in effect
+        (forward solves and Born; adjoint steps) and the two-levels-per-launch mode."""
+        fw, adj, fu = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)(), ctypes.c_int32(0)
+        check(lib().awe_plan_get_tiles(self._h, fw, adj, ctypes.byref(fu)))
+        return {"tz": fw[0], "ty": fw[1], "bz": fw[2], "fusion": fu.value,
+                "adjoint": {"tz": adj[0], "ty": adj[1], "bz": adj[2]}}
+
+    def set_tiles(self, tz: int = 32, ty: int = 8, bz: int = 0, dirs: int = 3):
+        """Launch shape of the forward solves (dirs 1), the adjoint steps (2) or both (3)."""
+        check(lib().awe_plan_set_tiles_dir(self._h, int(dirs), int(tz), int(ty), int(bz)))
 
     def set_fusion(self, mode):
         """Two time levels per launch (2D): mode bit 0 = forward solves, bit 1 = reverse sweeps

@@ -54,34 +54,47 @@ long long align256(long long x) { return (x + 255) & ~255LL; }
 
 }  // namespace
 
+// Everything that depends on the launch shape: the tile list, the per-tile receiver and
+// injection lists, the shot groups' tile ranges and the device tables.  A plan keeps one for its
+// forward solves (and Born modelling) and one for its adjoint steps (reverse sweeps and F^T), so
+// that each direction runs the tile shape that suits its kernel.
+struct Tiling {
+  int tz = 32;            // 2D tile rows
+  int ty = 8, bz = 0;     // 3D tile rows in y and z-block length
+  std::vector<TileDev> tiles;
+  std::vector<int> src_tile;        // per shot: tile owning the source base node
+  // group g owns tiles [g_tile0[g], g_tile0[g + 1]); g_active[g][n] of them (a prefix) belong
+  // to shots with off < n; its touched points are inj_pts[g_inj0[g] .. + g_ninj[g])
+  std::vector<int> g_tile0, g_inj0, g_ninj;
+  std::vector<std::vector<int>> g_active;
+  std::vector<RecDev> recs;
+  std::vector<InjPoint> inj_pts;
+  std::vector<InjPoint> ext_pts;
+  std::vector<InjEntry> inj_ent;
+  void* dev = nullptr;
+  awe::Tables tab{};
+};
+
 struct awe_plan {
   int ndim = 2, nbl = 0;
   double h = 0, dt = 0, vmax = 0, vref = 0, R = 1e-3;
   awe_storage store{};
   int nshot = 0, max_nt = 0, nsteps = 0;
-  int tz = 32;            // 2D tile rows
   int fuse2 = 0;          // 2D: two time levels per launch where the storage allows
                           // (bit 0: forward solves, bit 1: reverse sweeps)
-  int ty = 8, bz = 0;     // 3D tile rows in y and z-block length
+  Tiling fw, rv;          // launch shapes of forward solves / adjoint steps
   std::vector<awe_shot> shots;
   std::vector<double> rec_pos;    // copy of the problem's receiver rows
   std::vector<ShotDev> sd;
-  std::vector<TileDev> tiles;
   // Shot groups: consecutive shots of `order` (sorted by time offset) that run their whole
   // time loop before the next group starts, so that a step's working set stays in the
-  // last-level cache.  Group g owns tiles [g_tile0[g], g_tile0[g + 1]); g_active[g][n] of
-  // them (a prefix) belong to shots with off < n.
+  // last-level cache.
   std::vector<int> order;
-  std::vector<int> g_tile0, g_shot0, g_nshot, g_inj0, g_ninj;
-  std::vector<std::vector<int>> g_active;
+  std::vector<int> g_shot0, g_nshot;
   int groups_req = 0;             // 0: automatic
   int cur = 0;                    // group of the launches being issued
   // per group: the state restored by reference (FP32 slots) when its actions stopped
   std::vector<int> g_rs_level, g_rs_slot;
-  std::vector<RecDev> recs;
-  std::vector<InjPoint> inj_pts;
-  std::vector<InjPoint> ext_pts;
-  std::vector<InjEntry> inj_ent;
   std::vector<WinDev> wins;
   std::vector<int> win_shots;
   std::vector<long long> win_coef;
@@ -90,8 +103,6 @@ struct awe_plan {
   int total_recs = 0;
   size_t ws_bytes = 0;
   long long fields_off = 0, fields_bytes = 0, acc_off = 0, acc_bytes = 0;
-  void* dev = nullptr;
-  awe::Tables tab{};
   std::vector<int32_t> sched;
   size_t sched_first_reverse = 0;
   const void* kept_ws = nullptr;
@@ -159,83 +170,38 @@ void corner(int ndim, int c, int* dx, int* dy, int* dz) {
   }
 }
 
-awe_status build_tables(awe_plan* P, const double* rec_pos) {
-  const int nd = P->ndim;
-  // shots sorted by time offset (longest first), stable
+// Shot order (by time offset, stable) and shot groups balanced by points; source positions.
+awe_status build_groups(awe_plan* P) {
   std::vector<int> order(P->nshot);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return P->sd[a].off < P->sd[b].off; });
-  P->tiles.clear();
-  std::vector<int> first_tile(P->nshot), ntx(P->nshot), nty(P->nshot), ntz(P->nshot);
-  const int TY = nd == 2 ? 1 : P->ty;
-  for (int s : order) {
-    const awe_shot& sh = P->shots[s];
-    const int TZ = nd == 2 ? P->tz : (P->bz > 0 ? P->bz : sh.nz);
-    ntx[s] = (sh.nx + awe::kTX - 1) / awe::kTX;
-    nty[s] = nd == 2 ? 1 : (sh.ny + TY - 1) / TY;
-    ntz[s] = (sh.nz + TZ - 1) / TZ;
-    first_tile[s] = (int)P->tiles.size();
-    for (int kz = 0; kz < ntz[s]; ++kz)
-      for (int ky = 0; ky < nty[s]; ++ky)
-        for (int kx = 0; kx < ntx[s]; ++kx) {
-          TileDev t{};
-          t.shot = s;
-          t.x0 = kx * awe::kTX;
-          t.y0 = ky * TY;
-          t.z0 = kz * TZ;
-          P->tiles.push_back(t);
-        }
-  }
-  if (P->tiles.size() > (size_t)0x7fffffff) return fail(AWE_ERR_UNSUPPORTED, "too many tiles");
-  auto tile_of = [&](int s, int i, int j, int k) {
-    const awe_shot& sh = P->shots[s];
-    const int TZ = nd == 2 ? P->tz : (P->bz > 0 ? P->bz : sh.nz);
-    return first_tile[s] + ((k / TZ) * nty[s] + (j / TY)) * ntx[s] + i / awe::kTX;
-  };
-  // shot groups over `order`, balanced by points
   P->order = order;
-  {
-    long long pts = 0;
-    for (int s : order) pts += P->sd[s].npts;
-    int ng = P->groups_req;
-    if (ng <= 0) {
-      const long long bytes = 12 * pts;  // three FP32 fields per point touched by every step
-      ng = (int)((bytes + kGroupBytes - 1) / kGroupBytes);
-      ng = (int)std::min<long long>(ng, std::max<long long>(1, pts / kMinGroupPoints));
-    }
-    ng = std::max(1, std::min(ng, P->nshot));
-    P->g_shot0.assign(1, 0);
-    long long acc = 0;
-    for (int i = 0; i < P->nshot; ++i) {
-      const int g = (int)P->g_shot0.size() - 1;
-      acc += P->sd[order[i]].npts;
-      // close group g once it holds its share of the points, or when every later group
-      // needs one of the remaining shots
-      const int later_groups = ng - (g + 1), later_shots = P->nshot - (i + 1);
-      if (later_groups > 0 && (later_shots == later_groups ||
-                               (acc * ng >= pts * (g + 1) && later_shots >= later_groups)))
-        P->g_shot0.push_back(i + 1);
-    }
-    const int G = (int)P->g_shot0.size();
-    P->g_nshot.assign(G, 0);
-    P->g_tile0.assign(G + 1, 0);
-    P->g_active.assign(G, std::vector<int>(P->nsteps + 2, 0));
-    for (int g = 0; g < G; ++g) {
-      const int b = P->g_shot0[g], e = g + 1 < G ? P->g_shot0[g + 1] : P->nshot;
-      P->g_nshot[g] = e - b;
-      P->g_tile0[g] = first_tile[order[b]];
-      for (int n = 0; n <= P->nsteps + 1; ++n) {
-        int cnt = 0;
-        for (int i = b; i < e; ++i)
-          if (P->sd[order[i]].off < n) cnt += ntx[order[i]] * nty[order[i]] * ntz[order[i]];
-        P->g_active[g][n] = cnt;
-      }
-    }
-    P->g_tile0[G] = (int)P->tiles.size();
+  long long pts = 0;
+  for (int s : order) pts += P->sd[s].npts;
+  int ng = P->groups_req;
+  if (ng <= 0) {
+    const long long bytes = 12 * pts;  // three FP32 fields per point touched by every step
+    ng = (int)((bytes + kGroupBytes - 1) / kGroupBytes);
+    ng = (int)std::min<long long>(ng, std::max<long long>(1, pts / kMinGroupPoints));
   }
-  // sources
-  const double hd = std::pow(P->h, nd);
+  ng = std::max(1, std::min(ng, P->nshot));
+  P->g_shot0.assign(1, 0);
+  long long acc = 0;
+  for (int i = 0; i < P->nshot; ++i) {
+    const int g = (int)P->g_shot0.size() - 1;
+    acc += P->sd[order[i]].npts;
+    // close group g once it holds its share of the points, or when every later group
+    // needs one of the remaining shots
+    const int later_groups = ng - (g + 1), later_shots = P->nshot - (i + 1);
+    if (later_groups > 0 && (later_shots == later_groups ||
+                             (acc * ng >= pts * (g + 1) && later_shots >= later_groups)))
+      P->g_shot0.push_back(i + 1);
+  }
+  const int G = (int)P->g_shot0.size();
+  P->g_nshot.assign(G, 0);
+  for (int g = 0; g < G; ++g) P->g_nshot[g] = (g + 1 < G ? P->g_shot0[g + 1] : P->nshot) - P->g_shot0[g];
+  const double hd = std::pow(P->h, P->ndim);
   for (int s = 0; s < P->nshot; ++s) {
     Interp I;
     if (!interp(P, P->shots[s], P->shots[s].src, &I))
@@ -246,8 +212,58 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
     d.src_j = I.base[1];
     d.src_k = I.base[2];
     for (int c = 0; c < 8; ++c) d.src_w[c] = (float)(I.w[c] / hd);
-    d.src_tile = tile_of(s, I.base[0], I.base[1], I.base[2]);
   }
+  return AWE_OK;
+}
+
+// Tiles of every shot (in shot order) for the launch shape of T, the groups' tile ranges, and
+// the per-tile receiver gather lists and injection CSR.
+awe_status build_tiling(awe_plan* P, Tiling& T) {
+  const int nd = P->ndim;
+  const std::vector<int>& order = P->order;
+  T.tiles.clear();
+  std::vector<int> first_tile(P->nshot), ntx(P->nshot), nty(P->nshot), ntz(P->nshot);
+  const int TY = nd == 2 ? 1 : T.ty;
+  auto tz_of = [&](int s) { return nd == 2 ? T.tz : (T.bz > 0 ? T.bz : P->shots[s].nz); };
+  for (int s : order) {
+    const awe_shot& sh = P->shots[s];
+    const int TZ = tz_of(s);
+    ntx[s] = (sh.nx + awe::kTX - 1) / awe::kTX;
+    nty[s] = nd == 2 ? 1 : (sh.ny + TY - 1) / TY;
+    ntz[s] = (sh.nz + TZ - 1) / TZ;
+    first_tile[s] = (int)T.tiles.size();
+    for (int kz = 0; kz < ntz[s]; ++kz)
+      for (int ky = 0; ky < nty[s]; ++ky)
+        for (int kx = 0; kx < ntx[s]; ++kx) {
+          TileDev t{};
+          t.shot = s;
+          t.x0 = kx * awe::kTX;
+          t.y0 = ky * TY;
+          t.z0 = kz * TZ;
+          T.tiles.push_back(t);
+        }
+  }
+  if (T.tiles.size() > (size_t)0x7fffffff) return fail(AWE_ERR_UNSUPPORTED, "too many tiles");
+  auto tile_of = [&](int s, int i, int j, int k) {
+    return first_tile[s] + ((k / tz_of(s)) * nty[s] + (j / TY)) * ntx[s] + i / awe::kTX;
+  };
+  // groups' tile ranges and active prefixes
+  const int G = (int)P->g_shot0.size();
+  T.g_tile0.assign(G + 1, 0);
+  T.g_active.assign(G, std::vector<int>(P->nsteps + 2, 0));
+  for (int g = 0; g < G; ++g) {
+    const int b = P->g_shot0[g], e = b + P->g_nshot[g];
+    T.g_tile0[g] = first_tile[order[b]];
+    for (int n = 0; n <= P->nsteps + 1; ++n) {
+      int cnt = 0;
+      for (int i = b; i < e; ++i)
+        if (P->sd[order[i]].off < n) cnt += ntx[order[i]] * nty[order[i]] * ntz[order[i]];
+      T.g_active[g][n] = cnt;
+    }
+  }
+  T.g_tile0[G] = (int)T.tiles.size();
+  T.src_tile.assign(P->nshot, 0);
+  for (int s = 0; s < P->nshot; ++s) T.src_tile[s] = tile_of(s, P->sd[s].src_i, P->sd[s].src_j, P->sd[s].src_k);
   // receivers: gather list grouped by owning tile; injection CSR by touched point
   struct RecTmp { int tile; RecDev r; };
   std::vector<RecTmp> rt;
@@ -257,7 +273,7 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
   for (int s = 0; s < P->nshot; ++s) {
     const awe_shot& sh = P->shots[s];
     for (int r = 0; r < sh.nrec; ++r) {
-      const double* pos = rec_pos + 3 * (sh.rec_offset + r);
+      const double* pos = P->rec_pos.data() + 3 * (sh.rec_offset + r);
       Interp I;
       if (!interp(P, sh, pos, &I))
         return fail(AWE_ERR_GEOMETRY, "receiver " + std::to_string(r) + " of shot " +
@@ -277,28 +293,28 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
         corner(nd, c, &dx, &dy, &dz);
         const int i = R.i + dx, j = R.j + dy, k = R.k + dz;
         const int t = tile_of(s, i, j, k);
-        const TileDev& T = P->tiles[t];
+        const TileDev& Tl = T.tiles[t];
         const long long p = ((long long)k * sh.ny + j) * P->sd[s].px + i;
-        touches.push_back({t, p, s, i - T.x0, j - T.y0, k - T.z0, r, (float)I.w[c]});
+        touches.push_back({t, p, s, i - Tl.x0, j - Tl.y0, k - Tl.z0, r, (float)I.w[c]});
       }
     }
     P->total_recs += sh.nrec;
   }
   std::stable_sort(rt.begin(), rt.end(), [](const RecTmp& a, const RecTmp& b) { return a.tile < b.tile; });
-  P->recs.clear();
+  T.recs.clear();
   for (size_t i = 0; i < rt.size(); ++i) {
-    TileDev& T = P->tiles[rt[i].tile];
-    if (T.gat_count == 0) T.gat_begin = (int)i;
-    T.gat_count++;
-    P->recs.push_back(rt[i].r);
+    TileDev& Tl = T.tiles[rt[i].tile];
+    if (Tl.gat_count == 0) Tl.gat_begin = (int)i;
+    Tl.gat_count++;
+    T.recs.push_back(rt[i].r);
   }
   std::stable_sort(touches.begin(), touches.end(), [](const Touch& a, const Touch& b) {
     if (a.tile != b.tile) return a.tile < b.tile;
     if (a.p != b.p) return a.p < b.p;
     return a.r < b.r;
   });
-  P->inj_pts.clear();
-  P->inj_ent.clear();
+  T.inj_pts.clear();
+  T.inj_ent.clear();
   for (size_t i = 0; i < touches.size();) {
     size_t j = i;
     InjPoint ip{};
@@ -307,41 +323,40 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
     ip.ly = touches[i].ly;
     ip.lz = touches[i].lz;
     ip.p = touches[i].p;
-    ip.e_begin = (int)P->inj_ent.size();
+    ip.e_begin = (int)T.inj_ent.size();
     while (j < touches.size() && touches[j].tile == touches[i].tile && touches[j].p == touches[i].p) {
-      P->inj_ent.push_back({touches[j].r, touches[j].w});
+      T.inj_ent.push_back({touches[j].r, touches[j].w});
       ++j;
     }
     ip.e_count = (int)(j - i);
-    TileDev& T = P->tiles[touches[i].tile];
-    if (T.inj_count == 0) T.inj_begin = (int)P->inj_pts.size();
-    T.inj_count++;
-    P->inj_pts.push_back(ip);
+    TileDev& Tl = T.tiles[touches[i].tile];
+    if (Tl.inj_count == 0) Tl.inj_begin = (int)T.inj_pts.size();
+    Tl.inj_count++;
+    T.inj_pts.push_back(ip);
     i = j;
   }
   {
-    const int G = (int)P->g_nshot.size();
-    P->g_inj0.assign(G, 0);
-    P->g_ninj.assign(G, 0);
+    T.g_inj0.assign(G, 0);
+    T.g_ninj.assign(G, 0);
     std::vector<int> grp_of(P->nshot, 0);
     for (int g = 0; g < G; ++g)
       for (int i = 0; i < P->g_nshot[g]; ++i) grp_of[order[P->g_shot0[g] + i]] = g;
-    for (size_t i = P->inj_pts.size(); i-- > 0;) {
-      const int g = grp_of[P->inj_pts[i].shot];
-      P->g_inj0[g] = (int)i;
-      P->g_ninj[g]++;
+    for (size_t i = T.inj_pts.size(); i-- > 0;) {
+      const int g = grp_of[T.inj_pts[i].shot];
+      T.g_inj0[g] = (int)i;
+      T.g_ninj[g]++;
     }
   }
   // 2D: every touched point is also listed for each tile whose 4-cell extended region holds
   // it (the two-step adjoint injects on the extended region); same CSR entries
-  P->ext_pts.clear();
+  T.ext_pts.clear();
   if (nd == 2) {
     struct Ext { int tile; long long p; InjPoint ip; };
     std::vector<Ext> ex;
-    for (const InjPoint& ip : P->inj_pts) {
+    for (const InjPoint& ip : T.inj_pts) {
       const int px = P->sd[ip.shot].px;
       const int i = (int)(ip.p % px), k = (int)(ip.p / px);
-      const int TZ = P->tz;
+      const int TZ = T.tz;
       for (int kz = std::max(0, (k - TZ - kHalo) / TZ - 1); kz <= (k + kHalo) / TZ; ++kz) {
         for (int kx = std::max(0, (i - awe::kTX - kHalo) / awe::kTX - 1); kx <= (i + kHalo) / awe::kTX; ++kx) {
           if (kz >= ntz[ip.shot] || kx >= ntx[ip.shot]) continue;
@@ -359,60 +374,77 @@ awe_status build_tables(awe_plan* P, const double* rec_pos) {
       return a.tile != b.tile ? a.tile < b.tile : a.p < b.p;
     });
     for (size_t q = 0; q < ex.size(); ++q) {
-      TileDev& T = P->tiles[ex[q].tile];
-      if (T.ext_count == 0) T.ext_begin = (int)P->ext_pts.size();
-      T.ext_count++;
-      P->ext_pts.push_back(ex[q].ip);
+      TileDev& Tl = T.tiles[ex[q].tile];
+      if (Tl.ext_count == 0) Tl.ext_begin = (int)T.ext_pts.size();
+      Tl.ext_count++;
+      T.ext_pts.push_back(ex[q].ip);
     }
   }
   return AWE_OK;
 }
 
-awe_status upload_tables(awe_plan* P) {
+awe_status upload_tiling(awe_plan* P, Tiling& T) {
   auto bytes = [](size_t n, size_t e) { return (long long)align256((long long)(n * e)); };
+  std::vector<ShotDev> sd = P->sd;
+  for (int s = 0; s < P->nshot; ++s) sd[s].src_tile = T.src_tile[s];
   const long long o_sd = 0;
-  const long long o_t = o_sd + bytes(P->sd.size(), sizeof(ShotDev));
-  const long long o_r = o_t + bytes(P->tiles.size(), sizeof(TileDev));
-  const long long o_ip = o_r + bytes(P->recs.size(), sizeof(RecDev));
-  const long long o_xp = o_ip + bytes(P->inj_pts.size(), sizeof(InjPoint));
-  const long long o_ie = o_xp + bytes(P->ext_pts.size(), sizeof(InjPoint));
-  const long long o_w = o_ie + bytes(P->inj_ent.size(), sizeof(InjEntry));
+  const long long o_t = o_sd + bytes(sd.size(), sizeof(ShotDev));
+  const long long o_r = o_t + bytes(T.tiles.size(), sizeof(TileDev));
+  const long long o_ip = o_r + bytes(T.recs.size(), sizeof(RecDev));
+  const long long o_xp = o_ip + bytes(T.inj_pts.size(), sizeof(InjPoint));
+  const long long o_ie = o_xp + bytes(T.ext_pts.size(), sizeof(InjPoint));
+  const long long o_w = o_ie + bytes(T.inj_ent.size(), sizeof(InjEntry));
   const long long o_ws = o_w + bytes(P->wins.size(), sizeof(WinDev));
   const long long o_or = o_ws + bytes(P->win_shots.size(), sizeof(int));
   const long long total = o_or + bytes(P->order.size(), sizeof(int)) + 256;
   std::vector<unsigned char> host(total, 0);
   auto put = [&](long long off, const void* src, size_t n) { if (n) std::memcpy(host.data() + off, src, n); };
-  put(o_sd, P->sd.data(), P->sd.size() * sizeof(ShotDev));
-  put(o_t, P->tiles.data(), P->tiles.size() * sizeof(TileDev));
-  put(o_r, P->recs.data(), P->recs.size() * sizeof(RecDev));
-  put(o_ip, P->inj_pts.data(), P->inj_pts.size() * sizeof(InjPoint));
-  put(o_xp, P->ext_pts.data(), P->ext_pts.size() * sizeof(InjPoint));
-  put(o_ie, P->inj_ent.data(), P->inj_ent.size() * sizeof(InjEntry));
+  put(o_sd, sd.data(), sd.size() * sizeof(ShotDev));
+  put(o_t, T.tiles.data(), T.tiles.size() * sizeof(TileDev));
+  put(o_r, T.recs.data(), T.recs.size() * sizeof(RecDev));
+  put(o_ip, T.inj_pts.data(), T.inj_pts.size() * sizeof(InjPoint));
+  put(o_xp, T.ext_pts.data(), T.ext_pts.size() * sizeof(InjPoint));
+  put(o_ie, T.inj_ent.data(), T.inj_ent.size() * sizeof(InjEntry));
   put(o_w, P->wins.data(), P->wins.size() * sizeof(WinDev));
   put(o_ws, P->win_shots.data(), P->win_shots.size() * sizeof(int));
   put(o_or, P->order.data(), P->order.size() * sizeof(int));
-  if (P->dev) {
-    (void)hipFree(P->dev);
-    P->dev = nullptr;
+  if (T.dev) {
+    (void)hipFree(T.dev);
+    T.dev = nullptr;
   }
-  AWE_HIP(hipMalloc(&P->dev, total));
-  AWE_HIP(hipMemcpy(P->dev, host.data(), total, hipMemcpyHostToDevice));
-  unsigned char* b = static_cast<unsigned char*>(P->dev);
-  P->tab.shots = reinterpret_cast<const ShotDev*>(b + o_sd);
-  P->tab.tiles = reinterpret_cast<const TileDev*>(b + o_t);
-  P->tab.recs = reinterpret_cast<const RecDev*>(b + o_r);
-  P->tab.inj_pts = reinterpret_cast<const InjPoint*>(b + o_ip);
-  P->tab.ext_pts = reinterpret_cast<const InjPoint*>(b + o_xp);
-  P->tab.inj_ent = reinterpret_cast<const InjEntry*>(b + o_ie);
-  P->tab.wins = reinterpret_cast<const WinDev*>(b + o_w);
-  P->tab.win_shots = reinterpret_cast<const int*>(b + o_ws);
-  P->tab.order = reinterpret_cast<const int*>(b + o_or);
+  AWE_HIP(hipMalloc(&T.dev, total));
+  AWE_HIP(hipMemcpy(T.dev, host.data(), total, hipMemcpyHostToDevice));
+  unsigned char* b = static_cast<unsigned char*>(T.dev);
+  T.tab.shots = reinterpret_cast<const ShotDev*>(b + o_sd);
+  T.tab.tiles = reinterpret_cast<const TileDev*>(b + o_t);
+  T.tab.recs = reinterpret_cast<const RecDev*>(b + o_r);
+  T.tab.inj_pts = reinterpret_cast<const InjPoint*>(b + o_ip);
+  T.tab.ext_pts = reinterpret_cast<const InjPoint*>(b + o_xp);
+  T.tab.inj_ent = reinterpret_cast<const InjEntry*>(b + o_ie);
+  T.tab.wins = reinterpret_cast<const WinDev*>(b + o_w);
+  T.tab.win_shots = reinterpret_cast<const int*>(b + o_ws);
+  T.tab.order = reinterpret_cast<const int*>(b + o_or);
   return AWE_OK;
 }
 
-awe::StepArgs base_args(const awe_plan* P, void* ws) {
+// Shot groups and the tilings of the directions in `dirs` (bit 0 forward, bit 1 adjoint; the
+// groups change both, so a change of groups rebuilds both), built and uploaded.
+awe_status rebuild(awe_plan* P, int dirs) {
+  awe_status st = build_groups(P);
+  if (st != AWE_OK) return st;
+  for (Tiling* T : {&P->fw, &P->rv}) {
+    if (!(dirs & (T == &P->fw ? 1 : 2))) continue;
+    if ((st = build_tiling(P, *T)) != AWE_OK) return st;
+    if ((st = upload_tiling(P, *T)) != AWE_OK) return st;
+  }
+  return AWE_OK;
+}
+
+// Launch arguments on the tables of tiling T (P->fw for forward solves and Born modelling,
+// P->rv for adjoint steps).
+awe::StepArgs base_args(const awe_plan* P, const Tiling& T, void* ws) {
   awe::StepArgs a{};
-  a.t = P->tab;
+  a.t = T.tab;
   a.ws = static_cast<unsigned char*>(ws);
   a.ndim = P->ndim;
   a.nbl = P->nbl;
@@ -471,56 +503,58 @@ struct ProfScope {
   }
 };
 
-// Launch geometry of the current group at global step n.
-void set_group(const awe_plan* P, awe::StepArgs& a, int n) {
+// Launch geometry of the current group at global step n on tiling T.
+void set_group(const awe_plan* P, const Tiling& T, awe::StepArgs& a, int n) {
   a.step = n;
-  a.ntiles = P->g_active[P->cur][n];
-  a.tile_base = P->g_tile0[P->cur];
+  a.ntiles = T.g_active[P->cur][n];
+  a.tile_base = T.g_tile0[P->cur];
   a.shot_base = P->g_shot0[P->cur];
 }
 
 awe_status step_fwd(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
-  set_group(P, a, n);
+  set_group(P, P->fw, a, n);
   if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 0, s);
-  if (P->ndim == 2) AWE_HIP(awe::launch_fwd2d(a, P->tz, store, s));
-  else AWE_HIP(awe::launch_fwd3d(a, P->ty, P->bz, store, s));
+  if (P->ndim == 2) AWE_HIP(awe::launch_fwd2d(a, P->fw.tz, store, s));
+  else AWE_HIP(awe::launch_fwd3d(a, P->fw.ty, P->fw.bz, store, s));
   return AWE_OK;
 }
 
 awe_status step_adj(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
-  set_group(P, a, n);
+  set_group(P, P->rv, a, n);
   if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 1, s);
   if (P->ndim == 2) {
-    AWE_HIP(awe::launch_adj2d(a, P->tz, s));
+    AWE_HIP(awe::launch_adj2d(a, P->rv.tz, s));
   } else {
-    AWE_HIP(awe::launch_adj3d(a, P->ty, P->bz, s));
-    AWE_HIP(awe::launch_inj3d(a, P->g_inj0[P->cur], P->g_ninj[P->cur], s));
+    AWE_HIP(awe::launch_adj3d(a, P->rv.ty, P->rv.bz, s));
+    AWE_HIP(awe::launch_inj3d(a, P->rv.g_inj0[P->cur], P->rv.g_ninj[P->cur], s));
   }
   return AWE_OK;
 }
 
 // Two levels per launch (2D): forward levels n, n+1; adjoint levels n, n-1.
 awe_status step_fwd2(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
-  set_group(P, a, n + 1);
+  set_group(P, P->fw, a, n + 1);
   a.step = n;
   if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 0, s);
-  AWE_HIP(awe::launch_fwd2d2(a, P->tz, store, s));
+  AWE_HIP(awe::launch_fwd2d2(a, P->fw.tz, store, s));
   return AWE_OK;
 }
 
 awe_status step_adj2(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
-  set_group(P, a, n);
+  set_group(P, P->rv, a, n);
   if (a.ntiles <= 0) return AWE_OK;
   ProfScope ps(P, 1, s);
-  AWE_HIP(awe::launch_adj2d2(a, P->tz, s));
+  AWE_HIP(awe::launch_adj2d2(a, P->rv.tz, s));
   return AWE_OK;
 }
 
+// Two-level kernels exist for 8, 16 and 32 rows (2D).
 bool fused_ok(const awe_plan* P, int bit) {
-  return P->ndim == 2 && (P->fuse2 & bit) && (P->tz == 8 || P->tz == 16 || P->tz == 32);
+  const int tz = bit == AWE_FUSE_FORWARD ? P->fw.tz : P->rv.tz;
+  return P->ndim == 2 && (P->fuse2 & bit) && (tz == 8 || tz == 16 || tz == 32);
 }
 
 // Forward levels 1..nsteps: one single step first when the count is odd, then pairs.
@@ -724,7 +758,6 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     P->max_nt = std::max(P->max_nt, sh.nt);
   }
   P->nsteps = P->max_nt - 1;
-  const int nd = P->ndim;
   for (int r = 0; r < 5; ++r) P->c[r] = (float)(kStencil[r] / (P->h * P->h));
   P->amp = P->nbl > 0 ? 3.0 * std::log(1.0 / P->R) / (2.0 * P->nbl * P->h * P->vref) : 0.0;
   P->eta_dt = P->nbl > 0 ? (float)(P->amp / ((double)P->nbl * P->nbl) / P->dt) : 0.f;
@@ -821,16 +854,21 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
   }
   P->ws_bytes = (size_t)off;
 
-  if (nd == 3) {
-    P->ty = 8;
-    P->bz = 0;
-  }
+  // default launch shapes (the fastest measured on MI355X for the 2D and 3D workloads; the
+  // autotuner or awe_plan_set_tiles choose others): 2D 32-row forward and 16-row adjoint
+  // tiles; 3D 64 x 8 column blocks with 128-plane z-blocks forward, 64 x 16 with 64 adjoint
+  P->fw.tz = 32;
+  P->rv.tz = 16;
+  P->fw.ty = 8;
+  P->fw.bz = 128;
+  P->rv.ty = 16;
+  P->rv.bz = 64;
   P->rec_pos.assign(3 * (size_t)std::max<long long>(rec_rows, 1), 0.0);
   if (prob->rec_pos && rec_rows > 0)
     std::copy(prob->rec_pos, prob->rec_pos + 3 * rec_rows, P->rec_pos.begin());
-  awe_status st = build_tables(P, P->rec_pos.data());
+  awe_status st = rebuild(P, 3);
   if (st != AWE_OK) {
-    delete P;
+    awe_plan_destroy(P);
     return st;
   }
   if (store->mode == AWE_STORE_CHECKPOINT) {
@@ -842,11 +880,6 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
         P->sched_first_reverse = i;
         break;
       }
-  }
-  st = upload_tables(P);
-  if (st != AWE_OK) {
-    delete P;
-    return st;
   }
   *out = P;
   return AWE_OK;
@@ -861,7 +894,8 @@ awe_status awe_plan_workspace_size(const awe_plan* plan, size_t* bytes) {
 void awe_plan_destroy(awe_plan* plan) {
   if (!plan) return;
   for (hipEvent_t e : plan->prof_ev) (void)hipEventDestroy(e);
-  if (plan->dev) (void)hipFree(plan->dev);
+  if (plan->fw.dev) (void)hipFree(plan->fw.dev);
+  if (plan->rv.dev) (void)hipFree(plan->rv.dev);
   delete plan;
 }
 
@@ -873,103 +907,138 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   if (!m || !q || probe_steps < 1) return fail(AWE_ERR_INVALID_ARG, "autotune needs m, q and probe_steps >= 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   P->kept_ws = nullptr;
+  // one candidate list per direction; the forward probe times forward levels only, the adjoint
+  // probe adjoint levels only, so each direction keeps its own fastest shape
   struct Cand { int tz, ty, bz, fuse; };
   std::vector<Cand> cands;
+  const bool fusable = P->store.mode == AWE_STORE_NONE ||
+                       (P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32);
   if (P->ndim == 2) {
-    const bool fusable = P->store.mode == AWE_STORE_NONE ||
-                         (P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32);
-    for (int tz : {8, 16, 32, 64}) cands.push_back({tz, P->ty, P->bz, 0});
-    if (fusable)
-      for (int tz : {8, 16, 32})
-        for (int mode : {AWE_FUSE_FORWARD, AWE_FUSE_ADJOINT, AWE_FUSE_BOTH}) cands.push_back({tz, P->ty, P->bz, mode});
+    for (int tz : {8, 16, 32, 64}) {
+      cands.push_back({tz, 8, 0, 0});
+      if (fusable && tz != 64) cands.push_back({tz, 8, 0, 1});
+    }
   } else {
     for (int ty : {4, 8, 16})
-      for (int bz : {0, 128, 64, 32}) cands.push_back({P->tz, ty, bz, 0});
+      for (int bz : {0, 128, 64, 32}) cands.push_back({32, ty, bz, 0});
   }
   const int probe = std::min<int>(probe_steps, P->nsteps);
   hipEvent_t e0, e1;
   AWE_HIP(hipEventCreate(&e0));
   AWE_HIP(hipEventCreate(&e1));
-  double best = 1e300;
-  Cand win = cands[0];
-  for (const Cand& c : cands) {
-    P->tz = c.tz;
-    P->ty = c.ty;
-    P->bz = c.bz;
-    P->fuse2 = c.fuse;
-    if ((st = build_tables(P, P->rec_pos.data())) != AWE_OK) return st;
-    if ((st = upload_tables(P)) != AWE_OK) return st;
-    if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
-    for (int i = 0; i < P->nshot; ++i)
-      if (P->sd[i].acc >= 0)
-        AWE_HIP(awe::launch_fill(static_cast<unsigned char*>(ws), P->sd[i].acc, P->sd[i].npts * 8, s));
-    awe::StepArgs fa = base_args(P, ws);
-    fa.q = q;
-    awe::StepArgs aa = base_args(P, ws);
-    aa.dd = dd;
-    const bool full32 = P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32;
-    const int fkind = full32 ? awe::kStoreF32 : awe::kStoreNone;
-    aa.image_src = full32 ? awe::kImgFull32
-                   : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
-    std::vector<hipEvent_t> keep_ev;  // keep the probe out of kernel timing
+  std::vector<hipEvent_t> keep_ev;  // keep the probes out of kernel timing
+  keep_ev.swap(P->prof_ev);
+  const bool full32 = P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32;
+  const int fkind = full32 ? awe::kStoreF32 : awe::kStoreNone;
+  const int img = full32 ? awe::kImgFull32 : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
+  double best[2] = {1e300, 1e300};
+  Cand win[2] = {cands[0], cands[0]};
+  P->cur = 0;  // the probes time the first shot group
+  auto fail_out = [&](awe_status e) {
     keep_ev.swap(P->prof_ev);
-    P->cur = 0;  // the probe times the first shot group
-    AWE_HIP(hipEventRecord(e0, s));
-    const bool fuse_f = fused_ok(P, AWE_FUSE_FORWARD), fuse_a = fused_ok(P, AWE_FUSE_ADJOINT);
-    // the last levels of the sweep, where every shot of an end-aligned batch is active (the
-    // first levels of uneven batches cover only the longest shots)
-    for (int n = std::max(1, P->nsteps - probe + 1); n + (fuse_f ? 1 : 0) <= P->nsteps; n += fuse_f ? 2 : 1)
-      if ((st = fuse_f ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, fkind, s)) != AWE_OK) return st;
-    for (int n = P->nsteps; n > P->nsteps - probe && n >= 2; n -= fuse_a ? 2 : 1) {
-      if (fuse_a && aa.image_src != awe::kImgBuffers) {
-        if ((st = step_adj2(P, aa, n, s)) != AWE_OK) return st;
-        continue;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return e;
+  };
+  for (int dir = 0; dir < 2; ++dir) {
+    Tiling& T = dir == 0 ? P->fw : P->rv;
+    const int bit = dir == 0 ? AWE_FUSE_FORWARD : AWE_FUSE_ADJOINT;
+    for (const Cand& c : cands) {
+      if (c.fuse && dir == 1 && img == awe::kImgBuffers) continue;  // no two-level recompute sweep
+      T.tz = c.tz;
+      T.ty = c.ty;
+      T.bz = c.bz;
+      P->fuse2 = (P->fuse2 & ~bit) | (c.fuse ? bit : 0);
+      if ((st = rebuild(P, dir == 0 ? 1 : 2)) != AWE_OK) return fail_out(st);
+      if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return fail_out(st);
+      for (int i = 0; i < P->nshot; ++i)
+        if (P->sd[i].acc >= 0)
+          if (hipError_t e = awe::launch_fill(static_cast<unsigned char*>(ws), P->sd[i].acc, P->sd[i].npts * 8, s))
+            return fail_out(hip_fail(e, "autotune fill"));
+      awe::StepArgs fa = base_args(P, P->fw, ws);
+      fa.q = q;
+      awe::StepArgs aa = base_args(P, P->rv, ws);
+      aa.dd = dd;
+      aa.image_src = img;
+      if (hipError_t e = hipEventRecord(e0, s)) return fail_out(hip_fail(e, "autotune event"));
+      // the last levels of the sweep, where every shot of an end-aligned batch is active (the
+      // first levels of uneven batches cover only the longest shots)
+      if (dir == 0) {
+        const bool f2 = fused_ok(P, AWE_FUSE_FORWARD);
+        for (int n = std::max(1, P->nsteps - probe + 1); n + (f2 ? 1 : 0) <= P->nsteps; n += f2 ? 2 : 1)
+          if ((st = f2 ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, fkind, s)) != AWE_OK)
+            return fail_out(st);
+      } else {
+        const bool a2 = fused_ok(P, AWE_FUSE_ADJOINT);
+        for (int n = P->nsteps; n > P->nsteps - probe && n >= 2; n -= a2 ? 2 : 1)
+          if ((st = a2 ? step_adj2(P, aa, n, s) : step_adj(P, aa, n, s)) != AWE_OK) return fail_out(st);
       }
-      set_group(P, aa, n);
-      if (P->ndim == 2) AWE_HIP(awe::launch_adj2d(aa, P->tz, s));
-      else AWE_HIP(awe::launch_adj3d(aa, P->ty, P->bz, s));
-    }
-    AWE_HIP(hipEventRecord(e1, s));
-    AWE_HIP(hipEventSynchronize(e1));
-    keep_ev.swap(P->prof_ev);
-    float ms = 0.f;
-    AWE_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      win = c;
+      if (hipError_t e = hipEventRecord(e1, s)) return fail_out(hip_fail(e, "autotune event"));
+      if (hipError_t e = hipEventSynchronize(e1)) return fail_out(hip_fail(e, "autotune event"));
+      float ms = 0.f;
+      if (hipError_t e = hipEventElapsedTime(&ms, e0, e1)) return fail_out(hip_fail(e, "autotune event"));
+      if (ms < best[dir]) {
+        best[dir] = ms;
+        win[dir] = c;
+      }
     }
   }
+  keep_ev.swap(P->prof_ev);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  P->tz = win.tz;
-  P->ty = win.ty;
-  P->bz = win.bz;
-  P->fuse2 = win.fuse;
-  if ((st = build_tables(P, P->rec_pos.data())) != AWE_OK) return st;
-  if ((st = upload_tables(P)) != AWE_OK) return st;
+  P->fw.tz = win[0].tz;
+  P->fw.ty = win[0].ty;
+  P->fw.bz = win[0].bz;
+  P->rv.tz = win[1].tz;
+  P->rv.ty = win[1].ty;
+  P->rv.bz = win[1].bz;
+  P->fuse2 = (win[0].fuse ? AWE_FUSE_FORWARD : 0) | (win[1].fuse ? AWE_FUSE_ADJOINT : 0);
+  if ((st = rebuild(P, 3)) != AWE_OK) return st;
   if (chosen) {
-    chosen[0] = P->tz;
-    chosen[1] = P->ty;
-    chosen[2] = P->bz;
+    chosen[0] = P->fw.tz;
+    chosen[1] = P->fw.ty;
+    chosen[2] = P->fw.bz;
     chosen[3] = P->fuse2;
   }
-  if (best_ms) *best_ms = best;
+  if (best_ms) *best_ms = best[0] + best[1];
   return AWE_OK;
 }
 
-awe_status awe_plan_set_tiles(awe_plan* P, int32_t tz, int32_t ty, int32_t bz) {
+awe_status awe_plan_get_tiles(const awe_plan* P, int32_t fwd[3], int32_t adj[3], int32_t* fusion) {
   if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  if (fwd) {
+    fwd[0] = P->fw.tz;
+    fwd[1] = P->fw.ty;
+    fwd[2] = P->fw.bz;
+  }
+  if (adj) {
+    adj[0] = P->rv.tz;
+    adj[1] = P->rv.ty;
+    adj[2] = P->rv.bz;
+  }
+  if (fusion) *fusion = P->fuse2;
+  return AWE_OK;
+}
+
+awe_status awe_plan_set_tiles_dir(awe_plan* P, int32_t dirs, int32_t tz, int32_t ty, int32_t bz) {
+  if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  if (dirs < 1 || dirs > 3) return fail(AWE_ERR_INVALID_ARG, "dirs must be 1 (forward), 2 (adjoint) or 3");
   if (tz != 8 && tz != 12 && tz != 16 && tz != 20 && tz != 24 && tz != 32 && tz != 64)
     return fail(AWE_ERR_INVALID_ARG, "tz must be 8, 12, 16, 20, 24, 32 or 64");
   if (ty != 4 && ty != 8 && ty != 16) return fail(AWE_ERR_INVALID_ARG, "ty must be 4, 8 or 16");
   if (bz < 0) return fail(AWE_ERR_INVALID_ARG, "bz must be >= 0");
-  P->tz = tz;
-  P->ty = ty;
-  P->bz = bz;
+  for (Tiling* T : {&P->fw, &P->rv}) {
+    if (!(dirs & (T == &P->fw ? 1 : 2))) continue;
+    T->tz = tz;
+    T->ty = ty;
+    T->bz = bz;
+  }
   P->kept_ws = nullptr;
-  awe_status st = build_tables(P, P->rec_pos.data());
-  if (st != AWE_OK) return st;
-  return upload_tables(P);
+  return rebuild(P, dirs);
+}
+
+awe_status awe_plan_set_tiles(awe_plan* P, int32_t tz, int32_t ty, int32_t bz) {
+  return awe_plan_set_tiles_dir(P, 3, tz, ty, bz);
 }
 
 awe_status awe_plan_set_groups(awe_plan* P, int32_t ngroups, int32_t* actual) {
@@ -977,8 +1046,7 @@ awe_status awe_plan_set_groups(awe_plan* P, int32_t ngroups, int32_t* actual) {
   if (ngroups < 0) return fail(AWE_ERR_INVALID_ARG, "ngroups must be >= 0");
   P->groups_req = ngroups;
   P->kept_ws = nullptr;
-  awe_status st = build_tables(P, P->rec_pos.data());
-  if (st == AWE_OK) st = upload_tables(P);
+  awe_status st = rebuild(P, 3);
   if (st == AWE_OK && actual) *actual = (int32_t)P->g_nshot.size();
   return st;
 }
@@ -988,9 +1056,13 @@ awe_status awe_plan_set_fusion(awe_plan* P, int32_t mode) {
   if (mode < 0 || mode > AWE_FUSE_BOTH) return fail(AWE_ERR_INVALID_ARG, "fusion mode must be 0..3");
   P->fuse2 = mode;
   // two-level kernels exist for 8, 16 and 32 rows
-  if (P->fuse2 && P->tz != 8 && P->tz != 16 && P->tz != 32)
-    return awe_plan_set_tiles(P, P->tz < 24 ? 16 : 32, P->ty, P->bz);
-  return AWE_OK;
+  awe_status st = AWE_OK;
+  for (int bit : {AWE_FUSE_FORWARD, AWE_FUSE_ADJOINT}) {
+    Tiling& T = bit == AWE_FUSE_FORWARD ? P->fw : P->rv;
+    if ((mode & bit) && T.tz != 8 && T.tz != 16 && T.tz != 32)
+      if ((st = awe_plan_set_tiles_dir(P, bit, T.tz < 24 ? 16 : 32, T.ty, T.bz)) != AWE_OK) return st;
+  }
+  return st;
 }
 
 awe_status awe_profile_enable(awe_plan* P, int64_t max_launches, int32_t stride) {
@@ -1044,12 +1116,12 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
   const bool store = keep && P->store.mode != AWE_STORE_NONE;
   P->kept_ws = nullptr;
   if ((st = prepare(P, m, ws, true, false, s)) != AWE_OK) return st;
-  awe::StepArgs a = base_args(P, ws);
+  awe::StepArgs a = base_args(P, P->fw, ws);
   a.q = q;
   a.d = d;
   const int G = (int)P->g_nshot.size();
   if (store && P->store.mode == AWE_STORE_CHECKPOINT) {
-    awe::StepArgs aa = a;
+    awe::StepArgs aa = base_args(P, P->rv, ws);  // no adjoint step runs before the first reverse
     for (P->cur = 0; P->cur < G; ++P->cur)
       if ((st = run_actions(P, a, aa, 0, P->sched_first_reverse, s)) != AWE_OK) return st;
   } else {
@@ -1087,9 +1159,9 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
   }
   if (g)
     for (int i = 0; i < P->nshot; ++i) AWE_HIP(awe::launch_fill(w, P->sd[i].acc, P->sd[i].npts * 8, s));
-  awe::StepArgs fa = base_args(P, ws);
+  awe::StepArgs fa = base_args(P, P->fw, ws);
   fa.q = q;
-  awe::StepArgs aa = base_args(P, ws);
+  awe::StepArgs aa = base_args(P, P->rv, ws);
   aa.dd = dd;
   aa.v = v;
   if (P->store.mode == AWE_STORE_FULL) {
@@ -1106,7 +1178,7 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
   }
   if (v) AWE_HIP(awe::launch_src_last(aa, P->nshot, s));
   if (g)
-    AWE_HIP(awe::launch_grad_reduce(P->tab, (int)P->wins.size(), P->max_win_npts, w, g,
+    AWE_HIP(awe::launch_grad_reduce(P->rv.tab, (int)P->wins.size(), P->max_win_npts, w, g,
                                     -1.0 / (P->dt * P->dt), s));
   return AWE_OK;
 }
@@ -1128,7 +1200,7 @@ awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, v
   hipStream_t s = static_cast<hipStream_t>(stream);
   P->kept_ws = nullptr;
   if ((st = prepare(P, m, ws, false, true, s)) != AWE_OK) return st;
-  awe::StepArgs a = base_args(P, ws);
+  awe::StepArgs a = base_args(P, P->rv, ws);
   a.dd = dd;
   a.v = v;
   a.image_src = awe::kImgNone;
@@ -1146,17 +1218,17 @@ awe_status awe_born(awe_plan* P, const float* m, const float* q, const float* dm
   hipStream_t s = static_cast<hipStream_t>(stream);
   P->kept_ws = nullptr;
   if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
-  awe::StepArgs a = base_args(P, ws);
+  awe::StepArgs a = base_args(P, P->fw, ws);
   a.q = q;
   a.dm = dm;
   a.d = dd;
   for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur) {
     for (int n = 1; n <= P->nsteps; ++n) {
-      set_group(P, a, n);
+      set_group(P, P->fw, a, n);
       if (a.ntiles <= 0) continue;
       ProfScope ps(P, 2, s);
-      if (P->ndim == 2) AWE_HIP(awe::launch_born2d(a, P->tz, s));
-      else AWE_HIP(awe::launch_born3d(a, P->ty, P->bz, s));
+      if (P->ndim == 2) AWE_HIP(awe::launch_born2d(a, P->fw.tz, s));
+      else AWE_HIP(awe::launch_born3d(a, P->fw.ty, P->fw.bz, s));
     }
   }
   AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 1, s));

@@ -36,6 +36,8 @@ class EmuLib:
         L.awe_adjoint.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         L.awe_born.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
         for name, args in (("awe_plan_set_tiles", [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+                           ("awe_plan_set_tiles_dir", [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.c_int32]),
                            ("awe_plan_set_fusion", [vp, ctypes.c_int32]),
                            ("awe_plan_set_groups", [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)])):
             if hasattr(L, name):
@@ -108,8 +110,11 @@ class EmuPlan:
         self._raw = raw            # keep alive
         return ws
 
-    def set_tiles(self, tz=32, ty=8, bz=0):
-        self.lib.check(self.L.awe_plan_set_tiles(self.h, tz, ty, bz))
+    def set_tiles(self, tz=32, ty=8, bz=0, dirs=3):
+        if dirs == 3:
+            self.lib.check(self.L.awe_plan_set_tiles(self.h, tz, ty, bz))
+        else:
+            self.lib.check(self.L.awe_plan_set_tiles_dir(self.h, dirs, tz, ty, bz))
 
     def set_groups(self, n):
         a = ctypes.c_int32()

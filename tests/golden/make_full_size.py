@@ -10,13 +10,16 @@ shots in ascending order) and a seeded sample of the outputs is stored:
   c5_crop_full.npz    the 64^3 crop of the 3D model (144^3 with the sponge)
   c2_born_full.npz    Born traces J(m0) dm of the 16 c2_grad shots, dm = m - m0 (the
                       model minus its smoothed background, float32)
+  c3_autograd_full.npz  shots 0 and 31 of the 32 c3_autograd shots on the 592 x 1104 grid,
+                      5191 samples per shot (a stated subset: the oracle takes minutes per
+                      shot at this size)
 
 Gradient samples are flat indices into each window's computational grid (the
 same number per window); trace samples are every TIME_STRIDE-th time sample of
 every REC_STRIDE-th receiver.
 
 Run from the repository root:
-    python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop] [c2_born]
+    python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop] [c2_born] [c3_autograd]
 The 2D sets take minutes on 8 cores, the 3D crop about half an hour.
 """
 from __future__ import annotations
@@ -35,7 +38,8 @@ if ROOT not in sys.path:
 RESIDUAL_SEED = 1000      # synthetic residual of shot s uses seed RESIDUAL_SEED + s
 SAMPLE_SEED = 20230411
 N_GRAD_SAMPLES = 4096
-REC_STRIDE = {"c2_grad": 40, "c4_uneven": 64, "c5_crop": 64}
+REC_STRIDE = {"c2_grad": 40, "c4_uneven": 64, "c5_crop": 64, "c3_autograd": 64}
+SHOT_SUBSET = {"c3_autograd": (0, 31)}   # shots whose full-size oracle results are stored
 TIME_STRIDE = 32
 SEGMENT = 64              # oracle recomputation segment (result does not depend on it)
 
@@ -98,7 +102,8 @@ def make_born(workers):
 def make(name, workers):
     import workloads as W
     wl = W.make_config(name)
-    jobs = [(name, s) for s in range(wl.nshot)]
+    shots = SHOT_SUBSET.get(name, tuple(range(wl.nshot)))
+    jobs = [(name, s) for s in shots]
     if workers > 1 and len(jobs) > 1:
         with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
             res = pool.map(_shot, jobs)
@@ -111,7 +116,7 @@ def make(name, workers):
         gs[w] = gs[w] + g_s
     rng = np.random.default_rng(SAMPLE_SEED)
     per = max(64, N_GRAD_SAMPLES // wl.nwindow)
-    out = {}
+    out = {"shots": np.asarray(shots, dtype=np.int64)}
     for w, g in enumerate(gs):
         gidx = np.sort(rng.choice(g.size, size=min(per, g.size), replace=False))
         out[f"grad_index_{w}"] = gidx.astype(np.int64)

@@ -228,11 +228,14 @@ def test_bench_picks_the_fastest_pass_shape(monkeypatch):
         tz = fu = None
         seen = []
 
-        def set_tiles(self, tz, ty=8, bz=0):
+        def set_tiles(self, tz, ty=8, bz=0, dirs=3):
             self.tz = tz
 
         def set_fusion(self, fu):
             self.fu = int(fu)
+
+        def get_tiles(self):
+            return {"tz": self.tz, "fusion": self.fu}
 
     plan = FakePlan()
 

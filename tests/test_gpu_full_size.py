@@ -129,3 +129,56 @@ def test_c2_born_full_size():
           flush=True)
     assert np.isfinite(got).all() and err <= 2e-5
     assert lin <= TOL
+
+
+@pytest.mark.gpu
+def test_c3_autograd_full_size():
+    """The c3_autograd workload at its configured size through the autograd rule: 1104 x 592
+    computational grid, nt 5191, 16 FP32 checkpoint slots per shot, for shots 0 and 31 of the 32
+    (the subset whose oracle results are stored).  The pullback of the stored synthetic residual
+    dy through wave_forward gives J^T dy, compared with the oracle at the sampled points; the
+    traces are compared too (both <= 1e-5).  Central differences of phi(m) = <F(m) q, dy> (FP64
+    inner product) on 8 seeded smooth directions, eps = 1e-2 of the model scale, must agree with
+    <J^T dy, dm> (FP32 noise in phi limits the agreement to ~1e-3; gate 1e-2)."""
+    import torch
+    torch.cuda.empty_cache()
+    gold = _fixture("c3_autograd")
+    shots = [int(s) for s in gold["shots"]]
+    wl = W.make_config("c3_autograd")
+    plan = make_plan(wl, A.Storage(A.STORE_CHECKPOINT, 16, A.PREC_FP32), shots=shots)
+    m0 = plan.pack([wl.m(0, background=True)], "m")
+    q = plan.pack([wl.q(s) for s in shots], "q")
+    dy = plan.pack([G.residual(wl, s) for s in shots], "d")
+    ws = plan.workspace()
+    tiles, _ = plan.autotune(m0, q, dy, probe_steps=32, ws=ws)
+    print(f"c3_autograd: autotuned {tiles}", flush=True)
+    del ws
+    m = m0.clone().requires_grad_(True)
+    d = A.wave_forward(m, q, plan)
+    d.backward(dy)
+    torch.cuda.synchronize()
+    g = plan.unpack(m.grad.double(), "m")[0]
+    ds = plan.unpack(d, "d")
+    got_g = g.ravel()[gold["grad_index_0"]]
+    ref_g = gold["grad_value_0"]
+    got_d = np.concatenate([ds[i][np.ix_(gold[f"trace_t_{s}"], gold[f"trace_r_{s}"])].ravel()
+                            for i, s in enumerate(shots)])
+    ref_d = np.concatenate([gold[f"trace_value_{s}"].ravel() for s in shots])
+    e_g, e_d = _rel(got_g, ref_g), _rel(got_d, ref_d)
+    print(f"c3_autograd: gradient rel-L2 {e_g:.2e} ({ref_g.size} samples), traces {e_d:.2e} "
+          f"({ref_d.size} samples)", flush=True)
+    assert np.isfinite(got_g).all() and e_g <= TOL and e_d <= TOL
+    gm = m.grad.double()
+
+    def phi(mm):
+        return A.dot(plan.forward(mm, q), dy).item()
+
+    errs = []
+    for k in range(8):
+        dm = plan.pack([W.random_field(wl.comp_shape(0), 300 + k, smooth_cells=8.0)], "m")
+        eps = 1e-2 * m0.abs().max().item() / dm.abs().max().item()
+        fd = (phi(m0 + eps * dm) - phi(m0 - eps * dm)) / (2 * eps)
+        ad = torch.dot(gm, dm.double()).item()
+        errs.append(abs(fd - ad) / abs(fd))
+    print("c3_autograd finite-difference relative errors:", ", ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= 1e-2
