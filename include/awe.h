@@ -64,7 +64,9 @@ typedef enum {
   AWE_ERR_GEOMETRY = 4,     /* source or receiver outside the computational grid */
   AWE_ERR_WORKSPACE = 5,    /* workspace null or smaller than awe_plan_workspace_size */
   AWE_ERR_STATE = 6,        /* awe_backward without a preceding awe_forward(keep=1) */
-  AWE_ERR_HIP = 7           /* a HIP runtime call failed */
+  AWE_ERR_HIP = 7,          /* a HIP runtime call failed */
+  AWE_ERR_NONFINITE = 8     /* screening on (awe_plan_set_checks): an input or output holds a
+                               value that is not finite */
 } awe_status;
 
 /* One shot: a model window, its time axis and its acquisition. */
@@ -97,8 +99,12 @@ typedef struct {
 typedef enum {
   AWE_STORE_NONE = 0,       /* forward only: no wavefield kept (forward, adjoint, born) */
   AWE_STORE_FULL = 1,       /* every u^n kept in the workspace */
-  AWE_STORE_CHECKPOINT = 2  /* nslots restart pairs (u^n, u^{n-1}) per shot, binomial
+  AWE_STORE_CHECKPOINT = 2, /* nslots restart pairs (u^n, u^{n-1}) per shot, binomial
                                recomputation schedule */
+  AWE_STORE_AUTO = 3        /* FULL if its workspace fits the memory budget, else CHECKPOINT
+                               with the most restart slots per shot that fit (at most nslots
+                               when nslots > 0, at most the number of time steps); the plan
+                               reports the choice (awe_plan_get_storage) */
 } awe_store_mode;
 
 typedef enum {
@@ -108,10 +114,12 @@ typedef enum {
 } awe_store_prec;
 
 typedef struct {
-  int32_t mode;    /* awe_store_mode */
-  int32_t nslots;  /* CHECKPOINT: restart slots per shot (>= 1); ignored otherwise */
-  int32_t prec;    /* awe_store_prec of the stored wavefield */
-  int32_t reserved0;
+  int32_t mode;        /* awe_store_mode */
+  int32_t nslots;      /* CHECKPOINT: restart slots per shot (>= 1); AUTO: at most this many
+                          (0: no limit); ignored otherwise */
+  int32_t prec;        /* awe_store_prec of the stored wavefield */
+  int32_t budget_mib;  /* AUTO: workspace budget in MiB; 0 = 90 % of the current device's free
+                          memory at plan creation (hipMemGetInfo).  Ignored otherwise. */
 } awe_storage;
 
 typedef struct awe_plan awe_plan;
@@ -119,8 +127,33 @@ typedef struct awe_plan awe_plan;
 /* Validate the problem, build geometry tables (device copies allocated here), choose
  * tile shapes and lay out the workspace.  Uses the current HIP device.
  * Shots may have different nt: their time axes are aligned at the last sample.
- * Errors: INVALID_ARG, CFL, GEOMETRY, UNSUPPORTED (CHECKPOINT storage in 3D), HIP. */
+ * Errors: INVALID_ARG, CFL, GEOMETRY, UNSUPPORTED (CHECKPOINT storage in 3D, also when AUTO
+ * would need it), WORKSPACE (AUTO: not even one restart slot per shot fits the budget), HIP. */
 awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, awe_plan** plan);
+
+/* The storage awe_plan_create would put in effect for (prob, store) and the workspace bytes
+ * it needs, without creating a plan.  Runs on the host only (no device call) unless store is
+ * AUTO with budget_mib = 0, which reads the device's free memory.  Same errors as
+ * awe_plan_create, GEOMETRY and HIP table uploads aside. */
+awe_status awe_storage_select(const awe_problem* prob, const awe_storage* store, awe_storage* chosen,
+                              size_t* ws_bytes);
+
+/* The storage in effect for the plan: the one requested, or for AUTO the FULL or
+ * CHECKPOINT storage it resolved to (mode, nslots, prec; budget_mib 0). */
+awe_status awe_plan_get_storage(const awe_plan* plan, awe_storage* out);
+
+/* Optional screening of caller arrays (flags, default 0 = off):
+ *   AWE_CHECK_INPUTS:  before any compute work, m, q, dd and dm (those the call reads) are
+ *     checked for values that are not finite (error NONFINITE), and m for values below
+ *     1/vmax^2 by more than one part in 10^6, i.e. velocities above the plan's vmax, for which
+ *     the leapfrog may be unstable (error CFL).  No compute work is enqueued on error.
+ *   AWE_CHECK_OUTPUTS: after the call's work, d, g, v and dd (those it writes) are checked for
+ *     values that are not finite (error NONFINITE; the outputs are then invalid).
+ * With any flag set the compute calls synchronise the stream once per screened group of arrays
+ * and must not be captured into a graph.  Each screened element is read once more from HBM.
+ * Errors: INVALID_ARG, HIP (counter allocation on first use). */
+enum { AWE_CHECK_INPUTS = 1, AWE_CHECK_OUTPUTS = 2 };
+awe_status awe_plan_set_checks(awe_plan* plan, int32_t flags);
 
 /* Bytes of device workspace every compute call on this plan needs (256-byte aligned
  * pointer required).  Inside the workspace every field row (nx values) is padded to a
@@ -236,15 +269,25 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
  * solves (and Born modelling) and one for its adjoint steps (reverse sweeps and awe_adjoint); the
  * autotuner chooses each separately.  Candidates: 2D 8, 16, 32 or 64 rows of 64 columns, and -
  * where the storage mode allows it - 8, 16 or 32 rows with two time levels per launch (see
- * awe_plan_set_fusion); 3D 64 x {4, 8, 16} columns with z-blocks of the full depth, 128, 64 or
- * 32 planes.  The forward probe times the last probe_steps forward levels of the sweep (storing
+ * awe_plan_set_fusion); 3D 64 x {4, 8, 16} columns with z-blocks of the full depth, of 128, 64 or
+ * 32 planes, and of the depth split evenly in 2, 3 or 4 (rounded up to an even plane count).  The forward probe times the last probe_steps forward levels of the sweep (storing
  * the wavefield when the plan keeps one in FP32), the adjoint probe the last probe_steps adjoint
  * levels (with imaging when the plan keeps a wavefield), on the given inputs; the fastest of
  * each is kept for all later calls.  dd may be NULL (the adjoint probe then injects nothing).
  * Rebuilds the plan's device tables (the only allocation), overwrites the workspace and drops
  * any kept forward.  chosen (may be NULL) receives {tz, ty, bz} of the forward shape and the
  * fusion mode (awe_plan_get_tiles gives both shapes); best_ms (may be NULL) the sum of the two
- * winning probe times. */
+ * winning probe times.
+ * Result cache: when the environment variable AWE_TUNE_CACHE names a file, the call first looks
+ * up a key made of the device (architecture name, compute units), the problem's shape (ndim,
+ * shot count and a hash of every shot's grid, nt, receiver count and window), the storage, the
+ * shot grouping and probe_steps.  A valid entry found there is put in effect without running
+ * any probe (best_ms then returns the stored time); otherwise the probes run and the result is
+ * added to the file.  The file is a JSON object with one entry per line,
+ *   "key": {"fw": [tz, ty, bz], "rv": [tz, ty, bz], "fusion": f, "ms": t}
+ * rewritten whole through a temporary file and a rename; lines of any other form are ignored
+ * (and dropped at the next rewrite), and a file that cannot be written leaves the call's
+ * result unaffected. */
 awe_status awe_plan_autotune(awe_plan* plan, const float* m, const float* q, const float* dd,
                              int32_t probe_steps, void* ws, size_t ws_bytes, void* stream,
                              int32_t chosen[4], double* best_ms);

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import warnings
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -18,8 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libawe.so")
 
 AWE_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "CFL", 4: "GEOMETRY", 5: "WORKSPACE",
-          6: "STATE", 7: "HIP"}
-STORE_NONE, STORE_FULL, STORE_CHECKPOINT = 0, 1, 2
+          6: "STATE", 7: "HIP", 8: "NONFINITE"}
+AWE_ERR_CFL, AWE_ERR_WORKSPACE, AWE_ERR_NONFINITE = 3, 5, 8
+STORE_NONE, STORE_FULL, STORE_CHECKPOINT, STORE_AUTO = 0, 1, 2, 3
+CHECK_INPUTS, CHECK_OUTPUTS = 1, 2
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 
 EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "awe_forward",
@@ -27,7 +30,8 @@ EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "aw
            "awe_residual", "awe_residual_noalloc", "awe_dot_f64", "awe_dot_f64d", "awe_checkpoint_schedule",
            "awe_plan_autotune", "awe_plan_get_tiles", "awe_plan_set_tiles", "awe_plan_set_tiles_dir",
            "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
-           "awe_slowness2", "awe_velocity_gradient", "awe_patchy", "awe_patchy_vjp", "awe_status_string", "awe_last_error", "awe_version"]
+           "awe_slowness2", "awe_velocity_gradient", "awe_patchy", "awe_patchy_vjp", "awe_status_string", "awe_last_error", "awe_version",
+           "awe_storage_select", "awe_plan_get_storage", "awe_plan_set_checks"]
 
 
 FUSE_NONE, FUSE_FORWARD, FUSE_ADJOINT, FUSE_BOTH = 0, 1, 2, 3
@@ -61,7 +65,7 @@ class AweProblem(ctypes.Structure):
 
 class AweStorage(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("nslots", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32)]
+                ("budget_mib", ctypes.c_int32)]
 
 
 _lib = None
@@ -80,6 +84,10 @@ def lib():
     L.awe_plan_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     L.awe_plan_destroy.argtypes = [vp]
     L.awe_plan_destroy.restype = None
+    L.awe_storage_select.argtypes = [ctypes.POINTER(AweProblem), ctypes.POINTER(AweStorage),
+                                     ctypes.POINTER(AweStorage), ctypes.POINTER(sz)]
+    L.awe_plan_get_storage.argtypes = [vp, ctypes.POINTER(AweStorage)]
+    L.awe_plan_set_checks.argtypes = [vp, ctypes.c_int32]
     L.awe_forward.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
     L.awe_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.awe_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -119,7 +127,8 @@ def lib():
                  "awe_dot_f64d", "awe_checkpoint_schedule", "awe_plan_autotune", "awe_plan_get_tiles", "awe_plan_set_tiles",
                  "awe_plan_set_tiles_dir", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_patchy",
                  "awe_patchy_vjp", "awe_profile_enable",
-                 "awe_profile_read", "awe_profile_disable"):
+                 "awe_profile_read", "awe_profile_disable", "awe_storage_select", "awe_plan_get_storage",
+                 "awe_plan_set_checks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -154,9 +163,25 @@ class ShotGeometry:
 
 @dataclass
 class Storage:
+    """Wavefield storage of a plan.  STORE_AUTO: FULL if its workspace fits budget_mib MiB (0: 90 %
+    of the device's free memory), else CHECKPOINT with the most slots that fit (at most nslots
+    when nslots > 0)."""
     mode: int = STORE_NONE
     nslots: int = 0
     prec: int = PREC_FP32
+    budget_mib: int = 0
+
+    def c(self):
+        return AweStorage(int(self.mode), int(self.nslots), int(self.prec), int(self.budget_mib))
+
+
+def select_storage(ndim, h, dt, nbl, vmax, windows, shots, storage: Storage, damp_vref=None, damp_R=1e-3):
+    """(storage in effect, workspace bytes) that a plan of this survey would get, computed on the
+    host without creating a plan (no device call unless AUTO with budget_mib = 0)."""
+    prob, _, _cs, _rec = describe(ndim, h, dt, nbl, vmax, windows, shots, damp_vref, damp_R)
+    st, out, nb = storage.c(), AweStorage(), ctypes.c_size_t(0)
+    check(lib().awe_storage_select(ctypes.byref(prob), ctypes.byref(st), ctypes.byref(out), ctypes.byref(nb)))
+    return Storage(out.mode, out.nslots, out.prec), nb.value
 
 
 @dataclass
@@ -248,13 +273,27 @@ class Plan:
         self.shots = shots
         prob, self.layout, self._cshots, self._rec = describe(ndim, h, dt, nbl, vmax, self.windows, shots,
                                                              damp_vref, damp_R)
-        st = AweStorage(self.storage.mode, self.storage.nslots, self.storage.prec, 0)
+        st = self.storage.c()
         handle = ctypes.c_void_p()
         check(L.awe_plan_create(ctypes.byref(prob), ctypes.byref(st), ctypes.byref(handle)))
         self._h = handle
         sz = ctypes.c_size_t(0)
         check(L.awe_plan_workspace_size(self._h, ctypes.byref(sz)))
         self.ws_bytes = sz.value
+        eff = AweStorage()
+        check(L.awe_plan_get_storage(self._h, ctypes.byref(eff)))
+        #: the storage in effect (AUTO resolved to FULL or CHECKPOINT)
+        self.storage_in_effect = Storage(eff.mode, eff.nslots, eff.prec)
+        if self.storage.mode == STORE_AUTO and eff.mode == STORE_CHECKPOINT:
+            warnings.warn(f"AUTO storage: FULL storage does not fit the memory budget; the plan "
+                          f"recomputes from CHECKPOINT storage with {eff.nslots} slots per shot "
+                          f"({self.ws_bytes} bytes of workspace)", RuntimeWarning, stacklevel=2)
+
+    def set_checks(self, flags: int):
+        """Screen the inputs (CHECK_INPUTS: non-finite values -> NONFINITE, m above the vmax bound ->
+        CFL) and / or the outputs (CHECK_OUTPUTS) of every later compute call; 0 turns it off.
+        Screening synchronises the stream."""
+        check(lib().awe_plan_set_checks(self._h, int(flags)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -6,9 +6,12 @@
 // covers the tiles of the shots with off_s < n, which are a prefix of the tile list
 // because shots are ordered by off_s.  Every shot then runs its own nt - 1 steps, and one
 // checkpoint schedule over max_nt - 1 global steps serves all shots.
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -78,7 +81,10 @@ struct Tiling {
 struct awe_plan {
   int ndim = 2, nbl = 0;
   double h = 0, dt = 0, vmax = 0, vref = 0, R = 1e-3;
-  awe_storage store{};
+  awe_storage store{};    // the storage in effect (AUTO resolved to FULL or CHECKPOINT)
+  awe_storage store_req{};  // the storage asked for
+  int checks = 0;         // awe_plan_set_checks flags
+  unsigned long long* chk_dev = nullptr;  // screening counters (2 per screened array)
   int nshot = 0, max_nt = 0, nsteps = 0;
   int fuse2 = 0;          // 2D: two time levels per launch where the storage allows
                           // (bit 0: forward solves, bit 1: reverse sweeps)
@@ -97,6 +103,7 @@ struct awe_plan {
   std::vector<int> g_rs_level, g_rs_slot;
   std::vector<WinDev> wins;
   std::vector<int> win_shots;
+  std::vector<int> shot_win;      // window of each shot
   std::vector<long long> win_coef;
   std::vector<int> win_dims;
   long long max_win_npts = 0;
@@ -678,6 +685,152 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
   return AWE_OK;
 }
 
+// ---- autotuner result cache: a JSON object of "key": {"fw": [tz, ty, bz], "rv": [...],
+// "fusion": f, "ms": t} entries, one per line, in the file named by AWE_TUNE_CACHE.
+struct TuneEntry {
+  int fw[3], rv[3], fusion;
+  double ms;
+};
+
+// Device, problem shape, storage, grouping and probe length: what the timing of the candidate
+// shapes depends on.  The shots' grids, time axes, receiver counts and windows enter through a
+// 64-bit FNV-1a hash.
+std::string tune_key(const awe_plan* P, int probe) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char& c : arch)
+    if (c == '"' || c == '\\' || c < 32) c = '_';
+  unsigned long long h = 1469598103934665603ull;
+  auto mix = [&](long long v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (unsigned char)(v >> (8 * i));
+      h *= 1099511628211ull;
+    }
+  };
+  for (const awe_shot& sh : P->shots) {
+    mix(sh.nx);
+    mix(sh.ny);
+    mix(sh.nz);
+    mix(sh.nt);
+    mix(sh.nrec);
+    mix(sh.m_offset);
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "v%d/%s/%dcu/%dd/n%d/st%d.%d.%d/g%zu/p%d/%016llx", AWE_VERSION, arch.c_str(),
+                cus, P->ndim, P->nshot, P->store.mode, P->store.nslots, P->store.prec, P->g_nshot.size(),
+                probe, h);
+  return buf;
+}
+
+std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
+  std::map<std::string, TuneEntry> out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[2048], key[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    TuneEntry e{};
+    if (std::sscanf(line, " \"%1023[^\"]\": {\"fw\": [%d, %d, %d], \"rv\": [%d, %d, %d], \"fusion\": %d, \"ms\": %lf}",
+                    key, &e.fw[0], &e.fw[1], &e.fw[2], &e.rv[0], &e.rv[1], &e.rv[2], &e.fusion, &e.ms) == 9)
+      out[key] = e;
+  }
+  std::fclose(f);
+  return out;
+}
+
+// Rewrite the cache through a temporary file and a rename, so that a reader never sees half a
+// file (concurrent writers: the last rename wins).  Failures leave the cache as it was.
+void write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& entries) {
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& [k, e] : entries)
+    std::fprintf(f, "  \"%s\": {\"fw\": [%d, %d, %d], \"rv\": [%d, %d, %d], \"fusion\": %d, \"ms\": %.6f}%s\n",
+                 k.c_str(), e.fw[0], e.fw[1], e.fw[2], e.rv[0], e.rv[1], e.rv[2], e.fusion, e.ms,
+                 ++i < entries.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
+}
+
+bool valid_tz(int tz) { return tz == 8 || tz == 12 || tz == 16 || tz == 20 || tz == 24 || tz == 32 || tz == 64; }
+
+// Put a cached result in effect; false (plan unchanged) if the entry is not a valid shape.
+bool apply_tune_entry(awe_plan* P, const TuneEntry& e, awe_status* st) {
+  for (const int* t : {e.fw, e.rv})
+    if (!valid_tz(t[0]) || (t[1] != 4 && t[1] != 8 && t[1] != 16) || t[2] < 0) return false;
+  if (e.fusion < 0 || e.fusion > AWE_FUSE_BOTH) return false;
+  if ((e.fusion & AWE_FUSE_FORWARD) && e.fw[0] != 8 && e.fw[0] != 16 && e.fw[0] != 32) return false;
+  if ((e.fusion & AWE_FUSE_ADJOINT) && e.rv[0] != 8 && e.rv[0] != 16 && e.rv[0] != 32) return false;
+  P->fw.tz = e.fw[0];
+  P->fw.ty = e.fw[1];
+  P->fw.bz = e.fw[2];
+  P->rv.tz = e.rv[0];
+  P->rv.ty = e.rv[1];
+  P->rv.bz = e.rv[2];
+  P->fuse2 = e.fusion;
+  P->kept_ws = nullptr;
+  *st = rebuild(P, 3);
+  return true;
+}
+
+// ---- optional screening of caller arrays (awe_plan_set_checks)
+enum ArrKind { kPerWindow, kPerShotQ, kPerShotD };
+struct Screened {
+  const void* p;
+  bool f64;
+  ArrKind kind;
+  const char* name;
+  bool vmax_bound;  // also count values below 1/vmax^2 (squared slowness above the velocity bound)
+};
+constexpr int kMaxScreened = 8;
+
+awe_status screen(awe_plan* P, std::initializer_list<Screened> arrays, hipStream_t s) {
+  if (arrays.size() > (size_t)kMaxScreened) return fail(AWE_ERR_INVALID_ARG, "too many screened arrays");
+  AWE_HIP(awe::launch_fill(reinterpret_cast<unsigned char*>(P->chk_dev), 0, 2 * kMaxScreened * 8, s));
+  int i = 0;
+  for (const Screened& a : arrays) {
+    unsigned long long* cnt = P->chk_dev + 2 * i++;
+    if (!a.p) continue;
+    const double lo = a.vmax_bound ? (1.0 - 1e-6) / (P->vmax * P->vmax) : -HUGE_VAL;
+    auto run = [&](long long off, long long n) -> hipError_t {
+      return a.f64 ? awe::launch_screen(static_cast<const double*>(a.p) + off, n, lo, cnt, s)
+                   : awe::launch_screen(static_cast<const float*>(a.p) + off, n, lo, cnt, s);
+    };
+    if (a.kind == kPerWindow) {
+      for (size_t w = 0; w < P->wins.size(); ++w)
+        AWE_HIP(run(P->wins[w].m, (long long)P->win_dims[3 * w] * P->win_dims[3 * w + 1] * P->win_dims[3 * w + 2]));
+    } else {
+      for (const awe_shot& sh : P->shots)
+        AWE_HIP(a.kind == kPerShotQ ? run(sh.q_offset, sh.nt) : run(sh.d_offset, (long long)sh.nt * sh.nrec));
+    }
+  }
+  unsigned long long host[2 * kMaxScreened] = {};
+  AWE_HIP(hipMemcpyAsync(host, P->chk_dev, sizeof host, hipMemcpyDeviceToHost, s));
+  AWE_HIP(hipStreamSynchronize(s));
+  i = 0;
+  for (const Screened& a : arrays) {
+    const unsigned long long bad = host[2 * i], low = host[2 * i + 1];
+    ++i;
+    if (bad)
+      return fail(AWE_ERR_NONFINITE, std::string(a.name) + ": " + std::to_string(bad) + " values are not finite");
+    if (low) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf, "%s: %llu values below 1/vmax^2 = %.6g (velocity above the plan's vmax "
+                    "%.6g km/s, the leapfrog may be unstable)", a.name, low, 1.0 / (P->vmax * P->vmax), P->vmax);
+      return fail(AWE_ERR_CFL, buf);
+    }
+  }
+  return AWE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -696,13 +849,14 @@ const char* awe_status_string(awe_status s) {
     case AWE_ERR_WORKSPACE: return "workspace too small or misaligned";
     case AWE_ERR_STATE: return "no kept forward wavefield";
     case AWE_ERR_HIP: return "HIP runtime error";
+    case AWE_ERR_NONFINITE: return "value not finite";
   }
   return "unknown status";
 }
 
-awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, awe_plan** out) {
-  if (!out) return fail(AWE_ERR_INVALID_ARG, "plan output pointer is NULL");
-  *out = nullptr;
+namespace {
+
+awe_status validate(const awe_problem* prob, const awe_storage* store) {
   if (!prob || !store) return fail(AWE_ERR_INVALID_ARG, "problem or storage is NULL");
   if (prob->ndim != 2 && prob->ndim != 3) return fail(AWE_ERR_INVALID_ARG, "ndim must be 2 or 3");
   if (prob->nshot < 1 || !prob->shots) return fail(AWE_ERR_INVALID_ARG, "need at least one shot");
@@ -710,12 +864,14 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     return fail(AWE_ERR_INVALID_ARG, "h, dt, vmax and damp_vref must be positive");
   if (!(prob->damp_R > 0) || prob->damp_R > 1) return fail(AWE_ERR_INVALID_ARG, "damp_R must be in (0, 1]");
   if (prob->nbl < 0) return fail(AWE_ERR_INVALID_ARG, "nbl must be >= 0");
-  if (store->mode < AWE_STORE_NONE || store->mode > AWE_STORE_CHECKPOINT)
+  if (store->mode < AWE_STORE_NONE || store->mode > AWE_STORE_AUTO)
     return fail(AWE_ERR_INVALID_ARG, "bad storage mode");
   if (store->prec < AWE_PREC_FP32 || store->prec > AWE_PREC_FP16)
     return fail(AWE_ERR_INVALID_ARG, "bad storage precision");
   if (store->mode == AWE_STORE_CHECKPOINT && store->nslots < 1)
     return fail(AWE_ERR_INVALID_ARG, "CHECKPOINT storage needs nslots >= 1");
+  if (store->mode == AWE_STORE_AUTO && (store->nslots < 0 || store->budget_mib < 0))
+    return fail(AWE_ERR_INVALID_ARG, "AUTO storage needs nslots >= 0 and budget_mib >= 0");
   if (store->mode == AWE_STORE_CHECKPOINT && prob->ndim == 3)
     return fail(AWE_ERR_UNSUPPORTED,
                 "CHECKPOINT storage is disabled in 3D: its first GPU run faulted and the cause "
@@ -730,8 +886,99 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     std::snprintf(buf, sizeof buf, "vmax dt / h = %.6f exceeds the stability limit %.6f", cfl, limit);
     return fail(AWE_ERR_CFL, buf);
   }
+  return AWE_OK;
+}
 
-  awe_plan* P = new awe_plan();
+// Offsets of every workspace sub-buffer for the plan's storage (P->store), and the total size.
+void layout_ws(awe_plan* P) {
+  long long off = align256((long long)awe::kReduceBlocks * 8);
+  P->win_coef.resize(P->wins.size());
+  for (size_t w = 0; w < P->wins.size(); ++w) {
+    P->win_coef[w] = off;
+    off = align256(off + P->wins[w].npts * 4);
+  }
+  const awe_storage& st = P->store;
+  const int esz = st.prec == AWE_PREC_FP32 ? 4 : 2;
+  P->fields_off = off;
+  for (int s = 0; s < P->nshot; ++s) {
+    ShotDev& d = P->sd[s];
+    d.coef = P->win_coef[P->shot_win[s]];
+    d.fld = off;
+    off = align256(off + (long long)awe::kFieldBufs * d.npts * 4);
+  }
+  P->fields_bytes = off - P->fields_off;
+  P->acc_off = off;
+  for (int s = 0; s < P->nshot; ++s) {
+    ShotDev& d = P->sd[s];
+    d.acc = -1;
+    d.store = -1;
+    d.scale = -1;
+    if (st.mode == AWE_STORE_NONE) continue;
+    d.acc = off;
+    off = align256(off + d.npts * 8);
+  }
+  P->acc_bytes = off - P->acc_off;
+  for (int s = 0; s < P->nshot; ++s) {
+    ShotDev& d = P->sd[s];
+    if (st.mode == AWE_STORE_FULL) {
+      d.store = off;
+      off = align256(off + (long long)d.nt * d.npts * esz);
+      d.scale = off;
+      off = align256(off + (long long)d.nt * awe::kScaleSlots * 4);
+    } else if (st.mode == AWE_STORE_CHECKPOINT) {
+      d.store = off;
+      off = align256(off + (long long)st.nslots * 2 * d.npts * esz);
+      d.scale = off;
+      off = align256(off + (long long)st.nslots * 2 * 4);
+    }
+  }
+  P->ws_bytes = (size_t)off;
+}
+
+// AUTO storage: FULL when its workspace fits the budget, else CHECKPOINT with the most restart
+// slots per shot that fit (at most nslots when nslots > 0, and at most the number of steps).
+awe_status choose_storage(awe_plan* P) {
+  const awe_storage& req = P->store_req;
+  long long budget = (long long)req.budget_mib << 20;
+  if (req.budget_mib == 0) {
+    size_t free_b = 0, total_b = 0;
+    AWE_HIP(hipMemGetInfo(&free_b, &total_b));
+    budget = (long long)(0.9 * (double)free_b);
+  }
+  P->store = {AWE_STORE_FULL, 0, req.prec, 0};
+  layout_ws(P);
+  if ((long long)P->ws_bytes <= budget) return AWE_OK;
+  const long long full = (long long)P->ws_bytes;
+  char buf[256];
+  if (P->ndim == 3) {
+    std::snprintf(buf, sizeof buf, "FULL storage needs %lld bytes of workspace, over the budget of %lld, "
+                  "and CHECKPOINT storage is disabled in 3D", full, budget);
+    return fail(AWE_ERR_UNSUPPORTED, buf);
+  }
+  const int kmax = std::max(1, req.nslots > 0 ? std::min(req.nslots, P->nsteps) : P->nsteps);
+  auto fits = [&](int k) {
+    P->store = {AWE_STORE_CHECKPOINT, k, req.prec, 0};
+    layout_ws(P);
+    return (long long)P->ws_bytes <= budget;
+  };
+  if (!fits(1)) {
+    std::snprintf(buf, sizeof buf, "FULL storage needs %lld bytes of workspace and CHECKPOINT with one "
+                  "restart slot %zu, both over the budget of %lld", full, P->ws_bytes, budget);
+    return fail(AWE_ERR_WORKSPACE, buf);
+  }
+  int lo = 1, hi = kmax;  // fits(lo) holds
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if (fits(mid)) lo = mid;
+    else hi = mid - 1;
+  }
+  fits(lo);
+  return AWE_OK;
+}
+
+// Everything of a plan that needs no device: shots, windows, storage choice and workspace
+// layout.  P is filled in place; on error the caller deletes it.
+awe_status plan_host(const awe_problem* prob, const awe_storage* store, awe_plan* P) {
   P->ndim = prob->ndim;
   P->nbl = prob->nbl;
   P->h = prob->h;
@@ -740,9 +987,10 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
   P->vref = prob->damp_vref;
   P->R = prob->damp_R;
   P->store = *store;
+  P->store_req = *store;
   P->nshot = prob->nshot;
   P->shots.assign(prob->shots, prob->shots + prob->nshot);
-  auto bad = [&](const std::string& m) { delete P; return fail(AWE_ERR_INVALID_ARG, m); };
+  auto bad = [&](const std::string& m) { return fail(AWE_ERR_INVALID_ARG, m); };
   long long rec_rows = 0;
   for (int s = 0; s < P->nshot; ++s) {
     const awe_shot& sh = P->shots[s];
@@ -791,16 +1039,8 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     P->max_win_npts = std::max(P->max_win_npts, P->wins[w].npts);
   }
 
-  // workspace layout
-  long long off = align256((long long)awe::kReduceBlocks * 8);
-  P->win_coef.resize(P->wins.size());
-  for (size_t w = 0; w < P->wins.size(); ++w) {
-    P->win_coef[w] = off;
-    off = align256(off + P->wins[w].npts * 4);
-  }
-  const int esz = store->prec == AWE_PREC_FP32 ? 4 : 2;
   P->sd.resize(P->nshot);
-  P->fields_off = off;
+  P->shot_win.resize(P->nshot);
   for (int s = 0; s < P->nshot; ++s) {
     const awe_shot& sh = P->shots[s];
     ShotDev& d = P->sd[s];
@@ -814,46 +1054,34 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
     d.npts = (long long)d.px * sh.ny * sh.nz;
     // the step kernels address a field through a buffer resource with 32-bit byte offsets: the
     // largest per-point field (the FP64 accumulator) must not exceed 1 GiB
-    if (d.npts * 8 > (1LL << 30)) {
-      delete P;
+    if (d.npts * 8 > (1LL << 30))
       return fail(AWE_ERR_UNSUPPORTED, "shot " + std::to_string(s) + ": " + std::to_string(d.npts) +
                                            " workspace points per field exceed the 2^27 the kernels address");
-    }
-    d.coef = P->win_coef[win_of[sh.m_offset]];
+    P->shot_win[s] = win_of[sh.m_offset];
     d.m = sh.m_offset;
     d.q = sh.q_offset;
     d.d = sh.d_offset;
-    d.fld = off;
-    off = align256(off + (long long)awe::kFieldBufs * d.npts * 4);
   }
-  P->fields_bytes = off - P->fields_off;
-  P->acc_off = off;
-  for (int s = 0; s < P->nshot; ++s) {
-    ShotDev& d = P->sd[s];
-    d.acc = -1;
-    d.store = -1;
-    d.scale = -1;
-    if (store->mode == AWE_STORE_NONE) continue;
-    d.acc = off;
-    off = align256(off + d.npts * 8);
-  }
-  P->acc_bytes = off - P->acc_off;
-  for (int s = 0; s < P->nshot; ++s) {
-    ShotDev& d = P->sd[s];
-    if (store->mode == AWE_STORE_FULL) {
-      d.store = off;
-      off = align256(off + (long long)d.nt * d.npts * esz);
-      d.scale = off;
-      off = align256(off + (long long)d.nt * awe::kScaleSlots * 4);
-    } else if (store->mode == AWE_STORE_CHECKPOINT) {
-      d.store = off;
-      off = align256(off + (long long)store->nslots * 2 * d.npts * esz);
-      d.scale = off;
-      off = align256(off + (long long)store->nslots * 2 * 4);
-    }
-  }
-  P->ws_bytes = (size_t)off;
+  P->rec_pos.assign(3 * (size_t)std::max<long long>(rec_rows, 1), 0.0);
+  if (prob->rec_pos && rec_rows > 0)
+    std::copy(prob->rec_pos, prob->rec_pos + 3 * rec_rows, P->rec_pos.begin());
+  if (store->mode == AWE_STORE_AUTO) return choose_storage(P);
+  layout_ws(P);
+  return AWE_OK;
+}
 
+}  // namespace
+
+awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, awe_plan** out) {
+  if (!out) return fail(AWE_ERR_INVALID_ARG, "plan output pointer is NULL");
+  *out = nullptr;
+  awe_status st = validate(prob, store);
+  if (st != AWE_OK) return st;
+  awe_plan* P = new awe_plan();
+  if ((st = plan_host(prob, store, P)) != AWE_OK) {
+    delete P;
+    return st;
+  }
   // default launch shapes (the fastest measured on MI355X for the 2D and 3D workloads; the
   // autotuner or awe_plan_set_tiles choose others): 2D 32-row forward and 16-row adjoint
   // tiles; 3D 64 x 8 column blocks with 128-plane z-blocks forward, 64 x 16 with 64 adjoint
@@ -863,16 +1091,12 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
   P->fw.bz = 128;
   P->rv.ty = 16;
   P->rv.bz = 64;
-  P->rec_pos.assign(3 * (size_t)std::max<long long>(rec_rows, 1), 0.0);
-  if (prob->rec_pos && rec_rows > 0)
-    std::copy(prob->rec_pos, prob->rec_pos + 3 * rec_rows, P->rec_pos.begin());
-  awe_status st = rebuild(P, 3);
-  if (st != AWE_OK) {
+  if ((st = rebuild(P, 3)) != AWE_OK) {
     awe_plan_destroy(P);
     return st;
   }
-  if (store->mode == AWE_STORE_CHECKPOINT) {
-    awe::build_schedule(P->nsteps, store->nslots, P->sched);
+  if (P->store.mode == AWE_STORE_CHECKPOINT) {
+    awe::build_schedule(P->nsteps, P->store.nslots, P->sched);
     const size_t na = P->sched.size() / 3;
     P->sched_first_reverse = na;
     for (size_t i = 0; i < na; ++i)
@@ -882,6 +1106,23 @@ awe_status awe_plan_create(const awe_problem* prob, const awe_storage* store, aw
       }
   }
   *out = P;
+  return AWE_OK;
+}
+
+awe_status awe_storage_select(const awe_problem* prob, const awe_storage* store, awe_storage* chosen,
+                              size_t* ws_bytes) {
+  awe_status st = validate(prob, store);
+  if (st != AWE_OK) return st;
+  awe_plan P;
+  if ((st = plan_host(prob, store, &P)) != AWE_OK) return st;
+  if (chosen) *chosen = P.store;
+  if (ws_bytes) *ws_bytes = P.ws_bytes;
+  return AWE_OK;
+}
+
+awe_status awe_plan_get_storage(const awe_plan* plan, awe_storage* out) {
+  if (!plan || !out) return fail(AWE_ERR_INVALID_ARG, "NULL argument");
+  *out = plan->store;
   return AWE_OK;
 }
 
@@ -896,6 +1137,7 @@ void awe_plan_destroy(awe_plan* plan) {
   for (hipEvent_t e : plan->prof_ev) (void)hipEventDestroy(e);
   if (plan->fw.dev) (void)hipFree(plan->fw.dev);
   if (plan->rv.dev) (void)hipFree(plan->rv.dev);
+  if (plan->chk_dev) (void)hipFree(plan->chk_dev);
   delete plan;
 }
 
@@ -907,6 +1149,25 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   if (!m || !q || probe_steps < 1) return fail(AWE_ERR_INVALID_ARG, "autotune needs m, q and probe_steps >= 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   P->kept_ws = nullptr;
+  const int probe = std::min<int>(probe_steps, P->nsteps);
+  const char* cache = std::getenv("AWE_TUNE_CACHE");
+  std::string key;
+  if (cache && *cache) {
+    key = tune_key(P, probe);
+    const auto entries = read_tune_cache(cache);
+    const auto it = entries.find(key);
+    if (it != entries.end() && apply_tune_entry(P, it->second, &st)) {
+      if (st != AWE_OK) return st;
+      if (chosen) {
+        chosen[0] = P->fw.tz;
+        chosen[1] = P->fw.ty;
+        chosen[2] = P->fw.bz;
+        chosen[3] = P->fuse2;
+      }
+      if (best_ms) *best_ms = it->second.ms;
+      return AWE_OK;
+    }
+  }
   // one candidate list per direction; the forward probe times forward levels only, the adjoint
   // probe adjoint levels only, so each direction keeps its own fastest shape
   struct Cand { int tz, ty, bz, fuse; };
@@ -919,10 +1180,18 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
       if (fusable && tz != 64) cands.push_back({tz, 8, 0, 1});
     }
   } else {
+    // z-blocks of the full depth, of fixed lengths, and of the depth split evenly into 2, 3 or 4
+    // (no short last block)
+    int nz = 0;
+    for (const ShotDev& d : P->sd) nz = std::max(nz, d.nz);
+    std::vector<int> bzs = {0, 128, 64, 32};
+    for (int k = 2; k <= 4; ++k) {
+      const int b = ((nz + k - 1) / k + 1) & ~1;
+      if (b >= 16 && std::find(bzs.begin(), bzs.end(), b) == bzs.end()) bzs.push_back(b);
+    }
     for (int ty : {4, 8, 16})
-      for (int bz : {0, 128, 64, 32}) cands.push_back({32, ty, bz, 0});
+      for (int bz : bzs) cands.push_back({32, ty, bz, 0});
   }
-  const int probe = std::min<int>(probe_steps, P->nsteps);
   hipEvent_t e0, e1;
   AWE_HIP(hipEventCreate(&e0));
   AWE_HIP(hipEventCreate(&e1));
@@ -1001,6 +1270,21 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     chosen[3] = P->fuse2;
   }
   if (best_ms) *best_ms = best[0] + best[1];
+  if (cache && *cache) {
+    auto entries = read_tune_cache(cache);
+    entries[key] = TuneEntry{{P->fw.tz, P->fw.ty, P->fw.bz}, {P->rv.tz, P->rv.ty, P->rv.bz}, P->fuse2,
+                             best[0] + best[1]};
+    write_tune_cache(cache, entries);
+  }
+  return AWE_OK;
+}
+
+awe_status awe_plan_set_checks(awe_plan* P, int32_t flags) {
+  if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
+  if (flags < 0 || flags > (AWE_CHECK_INPUTS | AWE_CHECK_OUTPUTS))
+    return fail(AWE_ERR_INVALID_ARG, "flags must combine AWE_CHECK_INPUTS and AWE_CHECK_OUTPUTS");
+  if (flags && !P->chk_dev) AWE_HIP(hipMalloc(&P->chk_dev, 2 * kMaxScreened * sizeof(unsigned long long)));
+  P->checks = flags;
   return AWE_OK;
 }
 
@@ -1113,6 +1397,9 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
   if (st != AWE_OK) return st;
   if (!m || !q) return fail(AWE_ERR_INVALID_ARG, "m and q must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((P->checks & AWE_CHECK_INPUTS) &&
+      (st = screen(P, {{m, false, kPerWindow, "m", true}, {q, false, kPerShotQ, "q", false}}, s)) != AWE_OK)
+    return st;
   const bool store = keep && P->store.mode != AWE_STORE_NONE;
   P->kept_ws = nullptr;
   if ((st = prepare(P, m, ws, true, false, s)) != AWE_OK) return st;
@@ -1140,6 +1427,8 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
   }
   if (d) AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 0, s));
   if (store) P->kept_ws = ws;
+  if ((P->checks & AWE_CHECK_OUTPUTS) && d && (st = screen(P, {{d, false, kPerShotD, "d", false}}, s)) != AWE_OK)
+    return st;
   return AWE_OK;
 }
 
@@ -1152,6 +1441,9 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
     return fail(AWE_ERR_STATE, "the workspace holds no kept forward wavefield of this plan");
   (void)m;  // the coefficients of the kept forward are reused
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((P->checks & AWE_CHECK_INPUTS) &&
+      (st = screen(P, {{q, false, kPerShotQ, "q", false}, {dd, false, kPerShotD, "dd", false}}, s)) != AWE_OK)
+    return st;
   unsigned char* w = static_cast<unsigned char*>(ws);
   for (int i = 0; i < P->nshot; ++i) {
     const ShotDev& d = P->sd[i];
@@ -1180,6 +1472,9 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
   if (g)
     AWE_HIP(awe::launch_grad_reduce(P->rv.tab, (int)P->wins.size(), P->max_win_npts, w, g,
                                     -1.0 / (P->dt * P->dt), s));
+  if ((P->checks & AWE_CHECK_OUTPUTS) && (g || v) &&
+      (st = screen(P, {{g, true, kPerWindow, "g", false}, {v, false, kPerShotQ, "v", false}}, s)) != AWE_OK)
+    return st;
   return AWE_OK;
 }
 
@@ -1187,9 +1482,21 @@ awe_status awe_gradient(awe_plan* P, const float* m, const float* q, const float
                         float* v, float* d, void* ws, size_t ws_bytes, void* stream) {
   if (P && P->store.mode == AWE_STORE_NONE)
     return fail(AWE_ERR_UNSUPPORTED, "gradient needs FULL or CHECKPOINT storage");
-  awe_status st = awe_forward(P, m, q, d, 1, ws, ws_bytes, stream);
-  if (st != AWE_OK) return st;
-  return awe_backward(P, m, q, dd, g, v, ws, ws_bytes, stream);
+  awe_status st = AWE_OK;
+  const int checks = P ? P->checks : 0;
+  if (checks & AWE_CHECK_INPUTS) {
+    // all three inputs before any compute work; the two sweeps then skip their own input screening
+    if ((st = check_ws(P, ws, ws_bytes)) != AWE_OK) return st;
+    if (!m || !q || !dd) return fail(AWE_ERR_INVALID_ARG, "m, q and dd must not be NULL");
+    if ((st = screen(P, {{m, false, kPerWindow, "m", true}, {q, false, kPerShotQ, "q", false},
+                         {dd, false, kPerShotD, "dd", false}}, static_cast<hipStream_t>(stream))) != AWE_OK)
+      return st;
+    P->checks &= ~AWE_CHECK_INPUTS;
+  }
+  st = awe_forward(P, m, q, d, 1, ws, ws_bytes, stream);
+  if (st == AWE_OK) st = awe_backward(P, m, q, dd, g, v, ws, ws_bytes, stream);
+  if (P) P->checks = checks;
+  return st;
 }
 
 awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, void* ws,
@@ -1198,6 +1505,9 @@ awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, v
   if (st != AWE_OK) return st;
   if (!m || !dd || !v) return fail(AWE_ERR_INVALID_ARG, "m, dd and v must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((P->checks & AWE_CHECK_INPUTS) &&
+      (st = screen(P, {{m, false, kPerWindow, "m", true}, {dd, false, kPerShotD, "dd", false}}, s)) != AWE_OK)
+    return st;
   P->kept_ws = nullptr;
   if ((st = prepare(P, m, ws, false, true, s)) != AWE_OK) return st;
   awe::StepArgs a = base_args(P, P->rv, ws);
@@ -1207,6 +1517,8 @@ awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, v
   for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur)
     if ((st = adjoint_loop(P, a, s)) != AWE_OK) return st;
   AWE_HIP(awe::launch_src_last(a, P->nshot, s));
+  if ((P->checks & AWE_CHECK_OUTPUTS) && (st = screen(P, {{v, false, kPerShotQ, "v", false}}, s)) != AWE_OK)
+    return st;
   return AWE_OK;
 }
 
@@ -1216,6 +1528,10 @@ awe_status awe_born(awe_plan* P, const float* m, const float* q, const float* dm
   if (st != AWE_OK) return st;
   if (!m || !q || !dm || !dd) return fail(AWE_ERR_INVALID_ARG, "m, q, dm and dd must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((P->checks & AWE_CHECK_INPUTS) &&
+      (st = screen(P, {{m, false, kPerWindow, "m", true}, {q, false, kPerShotQ, "q", false},
+                       {dm, false, kPerWindow, "dm", false}}, s)) != AWE_OK)
+    return st;
   P->kept_ws = nullptr;
   if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
   awe::StepArgs a = base_args(P, P->fw, ws);
@@ -1232,6 +1548,8 @@ awe_status awe_born(awe_plan* P, const float* m, const float* q, const float* dm
     }
   }
   AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 1, s));
+  if ((P->checks & AWE_CHECK_OUTPUTS) && (st = screen(P, {{dd, false, kPerShotD, "dd", false}}, s)) != AWE_OK)
+    return st;
   return AWE_OK;
 }
 

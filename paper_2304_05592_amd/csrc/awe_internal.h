@@ -150,6 +150,9 @@ hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, lo
                        int nx, int ny, int nz, int px, int nbl, double h, double dt, double amp,
                        hipStream_t stream);
 hipError_t launch_fill(unsigned char* ws, long long off, long long nbytes, hipStream_t stream);
+// Add to cnt[0] the values of x[0, n) that are not finite and to cnt[1] the finite ones below lo.
+hipError_t launch_screen(const float* x, long long n, double lo, unsigned long long* cnt, hipStream_t stream);
+hipError_t launch_screen(const double* x, long long n, double lo, unsigned long long* cnt, hipStream_t stream);
 hipError_t launch_fwd2d(const StepArgs& a, int tz, int store, hipStream_t stream);
 // Quantise the last forward level u^{nt-1} of every shot into the scaled FULL store.
 hipError_t launch_store_last(const StepArgs& a, int nshot, long long max_npts, hipStream_t stream);

@@ -352,6 +352,39 @@ int grid_for(long long n) {
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
+// Screening of a caller array: cnt[0] += values that are not finite, cnt[1] += finite values
+// below lo.  Integer counts added with one atomic per workgroup, so they do not depend on the
+// order in which workgroups run.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) screen_kernel(const T* __restrict__ x, long long n,
+                                                           double lo, unsigned long long* cnt) {
+  unsigned long long bad = 0, low = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = (double)x[i];
+    if (!__builtin_isfinite(v)) ++bad;
+    else if (v < lo) ++low;
+  }
+  __shared__ unsigned long long red[2][kThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    bad += __shfl_xor(bad, o, 64);
+    low += __shfl_xor(low, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = bad;
+    red[1][threadIdx.x >> 6] = low;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) {
+      bad += red[0][w];
+      low += red[1][w];
+    }
+    if (bad) atomicAdd(cnt, bad);
+    if (low) atomicAdd(cnt + 1, low);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, long long m_off,
@@ -372,6 +405,18 @@ hipError_t launch_fill(unsigned char* ws, long long off, long long nbytes, hipSt
   const int ntail = (int)(nbytes - n16 * 16);
   fill_kernel<<<grid_for(n16), kThreads, 0, s>>>(reinterpret_cast<uint4*>(ws + off), n16,
                                                  ws + off + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen(const float* x, long long n, double lo, unsigned long long* cnt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  screen_kernel<float><<<grid_for(n), kThreads, 0, s>>>(x, n, lo, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen(const double* x, long long n, double lo, unsigned long long* cnt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  screen_kernel<double><<<grid_for(n), kThreads, 0, s>>>(x, n, lo, cnt);
   return hipGetLastError();
 }
 

@@ -39,6 +39,11 @@ class EmuLib:
                            ("awe_plan_set_tiles_dir", [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                        ctypes.c_int32]),
                            ("awe_plan_set_fusion", [vp, ctypes.c_int32]),
+                           ("awe_plan_set_checks", [vp, ctypes.c_int32]),
+                           ("awe_plan_get_storage", [vp, ctypes.POINTER(B.AweStorage)]),
+                           ("awe_plan_get_tiles", [vp] + [ctypes.POINTER(ctypes.c_int32)] * 3),
+                           ("awe_plan_autotune", [vp, vp, vp, vp, ctypes.c_int32, vp, sz, vp,
+                                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
                            ("awe_plan_set_groups", [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)])):
             if hasattr(L, name):
                 getattr(L, name).argtypes = args
@@ -75,7 +80,7 @@ class EmuPlan:
         self.storage = storage or B.Storage()
         prob, self.layout, self._cs, self._rec = B.describe(wl.ndim, wl.h, wl.dt, wl.nbl, wl.vmax, windows,
                                                             self.geoms, wl.vmax)
-        st = B.AweStorage(self.storage.mode, self.storage.nslots, self.storage.prec, 0)
+        st = self.storage.c()
         h = ctypes.c_void_p()
         lib.check(self.L.awe_plan_create(ctypes.byref(prob), ctypes.byref(st), ctypes.byref(h)))
         self.h = h
@@ -94,7 +99,7 @@ class EmuPlan:
     def workspace(self):
         """A fresh 256-byte aligned workspace with the gaps between sub-buffers poisoned."""
         n = self.ws_bytes()
-        raw = np.zeros(n + 256, dtype=np.uint8)
+        raw = _filled(n + 256)
         shift = (-raw.ctypes.data) % 256
         ws = raw[shift:shift + n]
         cap = 4096
@@ -116,6 +121,26 @@ class EmuPlan:
         else:
             self.lib.check(self.L.awe_plan_set_tiles_dir(self.h, dirs, tz, ty, bz))
 
+    def get_storage(self):
+        out = B.AweStorage()
+        self.lib.check(self.L.awe_plan_get_storage(self.h, ctypes.byref(out)))
+        return B.Storage(out.mode, out.nslots, out.prec)
+
+    def set_checks(self, flags):
+        self.lib.check(self.L.awe_plan_set_checks(self.h, flags))
+
+    def get_tiles(self):
+        fw, adj, fu = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)(), ctypes.c_int32(0)
+        self.lib.check(self.L.awe_plan_get_tiles(self.h, fw, adj, ctypes.byref(fu)))
+        return tuple(fw), tuple(adj), fu.value
+
+    def autotune(self, m, q, dd=None, probe_steps=4):
+        ws = self.workspace()
+        ch, ms = (ctypes.c_int32 * 4)(), ctypes.c_double(0.0)
+        self.lib.check(self.L.awe_plan_autotune(self.h, _p(m), _p(q), _p(dd), probe_steps, _p(ws), ws.nbytes,
+                                                None, ch, ctypes.byref(ms)))
+        return self.get_tiles(), ms.value
+
     def set_groups(self, n):
         a = ctypes.c_int32()
         self.lib.check(self.L.awe_plan_set_groups(self.h, n, ctypes.byref(a)))
@@ -129,31 +154,44 @@ class EmuPlan:
 
     def gradient(self, m, q, dd, v=False, d=False, ws=None):
         lay = self.layout
-        g = np.zeros(lay.m_size, dtype=np.float64)
-        vv = np.zeros(lay.q_size, dtype=np.float32) if v else None
-        dt = np.zeros(lay.d_size, dtype=np.float32) if d else None
+        g = _filled(lay.m_size * 8).view(np.float64)
+        vv = _filled(lay.q_size * 4).view(np.float32) if v else None
+        dt = _filled(lay.d_size * 4).view(np.float32) if d else None
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_gradient(self.h, _p(m), _p(q), _p(dd), _p(g), _p(vv), _p(dt), _p(ws),
                                            ws.nbytes, None))
         return g, vv, dt
 
     def forward(self, m, q, ws=None):
-        d = np.zeros(self.layout.d_size, dtype=np.float32)
+        d = _filled(self.layout.d_size * 4).view(np.float32)
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_forward(self.h, _p(m), _p(q), _p(d), 0, _p(ws), ws.nbytes, None))
         return d
 
     def adjoint(self, m, dd, ws=None):
-        v = np.zeros(self.layout.q_size, dtype=np.float32)
+        v = _filled(self.layout.q_size * 4).view(np.float32)
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_adjoint(self.h, _p(m), _p(dd), _p(v), _p(ws), ws.nbytes, None))
         return v
 
     def born(self, m, q, dm, ws=None):
-        dd = np.zeros(self.layout.d_size, dtype=np.float32)
+        dd = _filled(self.layout.d_size * 4).view(np.float32)
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_born(self.h, _p(m), _p(q), _p(dm), _p(dd), _p(ws), ws.nbytes, None))
         return dd
+
+
+def _filled(nbytes):
+    """Bytes for a workspace or an output array. On the GPU both come from a caching allocator
+    and hold whatever an earlier tensor left there; EMU_FILL makes that visible here: a byte
+    value (e.g. 255: every float NaN, every int -1) or "random" (seeded by EMU_FILL_SEED)."""
+    f = os.environ.get("EMU_FILL")
+    if f is None:
+        return np.zeros(nbytes, dtype=np.uint8)
+    if f == "random":
+        rng = np.random.default_rng(int(os.environ.get("EMU_FILL_SEED", "1")))
+        return rng.integers(0, 256, nbytes, dtype=np.uint8)
+    return np.full(nbytes, int(f, 0), dtype=np.uint8)
 
 
 def run(script_args, so_path, env_extra=None, timeout=1800):

@@ -10,6 +10,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <vector>
 
@@ -220,8 +221,22 @@ struct emu_event_t { int recorded = 0; };
 
 hipError_t hipMalloc(void** p, size_t n) {
   if (!p) return hipErrorInvalidValue;
-  void* q = std::aligned_alloc(256, (n + 255) / 256 * 256 + 256);
+  const size_t cap = (n + 255) / 256 * 256 + 256;
+  void* q = std::aligned_alloc(256, cap);
   if (!q) return hipErrorMemoryAllocation;
+  // Device memory is not cleared by hipMalloc; EMU_FILL=<byte> gives it a known non-zero content
+  // so a read before the first write shows up (the driver fills workspaces the same way).
+  if (const char* f = std::getenv("EMU_FILL")) {
+    if (std::strcmp(f, "random") == 0) {
+      unsigned long long x = 0x9E3779B97F4A7C15ull ^ (unsigned long long)allocs.size();
+      for (size_t i = 0; i < cap; ++i) {
+        x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+        static_cast<unsigned char*>(q)[i] = (unsigned char)x;
+      }
+    } else {
+      std::memset(q, (int)std::strtol(f, nullptr, 0), cap);
+    }
+  }
   allocs[q] = n;
   *p = q;
   return hipSuccess;
@@ -260,6 +275,15 @@ hipError_t hipMemGetInfo(size_t* free_b, size_t* total_b) {
 hipError_t hipGetDevice(int* dev) { if (dev) *dev = 0; return hipSuccess; }
 hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipGetDeviceCount(int* n) { if (n) *n = 1; return hipSuccess; }
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
+  if (!p) return hipErrorInvalidValue;
+  *p = hipDeviceProp_t{};
+  std::snprintf(p->name, sizeof p->name, "CPU emulation");
+  std::snprintf(p->gcnArchName, sizeof p->gcnArchName, "emu");
+  p->totalGlobalMem = (size_t)288 << 30;
+  p->multiProcessorCount = 1;
+  return hipSuccess;
+}
 hipError_t hipGetSymbolAddress(void** p, const void* sym) {
   if (!p || !sym) return hipErrorInvalidSymbol;
   *p = const_cast<void*>(sym);

@@ -84,6 +84,7 @@ inline int atomicMax(int* p, int v) { const int o = *p; if (v > o) *p = v; retur
 inline unsigned atomicAdd(unsigned* p, unsigned v) { const unsigned o = *p; *p = o + v; return o; }
 inline double atomicAdd(double* p, double v) { const double o = *p; *p = o + v; return o; }
 inline float atomicAdd(float* p, float v) { const float o = *p; *p = o + v; return o; }
+inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) { const unsigned long long o = *p; *p = o + v; return o; }
 
 struct uint4 { unsigned x, y, z, w; };
 inline uint4 make_uint4(unsigned x, unsigned y, unsigned z, unsigned w) { return {x, y, z, w}; }
@@ -144,7 +145,7 @@ typedef struct emu_stream* hipStream_t;
 typedef struct emu_event* hipEvent_t;
 enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                      hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 };
-struct hipDeviceProp_t { char name[256]; size_t totalGlobalMem; int multiProcessorCount; };
+struct hipDeviceProp_t { char name[256]; char gcnArchName[256]; size_t totalGlobalMem; int multiProcessorCount; };
 
 hipError_t hipMalloc(void** p, size_t n);
 template <class T> inline hipError_t hipMalloc(T** p, size_t n) { return hipMalloc((void**)p, n); }
@@ -156,6 +157,7 @@ hipError_t hipMemGetInfo(size_t* free_b, size_t* total_b);
 hipError_t hipGetDevice(int* dev);
 hipError_t hipSetDevice(int dev);
 hipError_t hipGetDeviceCount(int* n);
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int dev);
 hipError_t hipGetSymbolAddress(void** p, const void* sym);
 hipError_t hipEventCreate(hipEvent_t* e);
 hipError_t hipEventDestroy(hipEvent_t e);

@@ -90,6 +90,52 @@ def test_bad_storage_is_rejected():
     assert _create(p3, mode=2, nslots=4)[0] == 2
 
 
+def _select(p, mode, nslots=0, prec=0, budget_mib=0):
+    """(status, storage in effect, workspace bytes) from awe_storage_select (host only)."""
+    st, out, nb = B.AweStorage(mode, nslots, prec, budget_mib), B.AweStorage(), B.ctypes.c_size_t(0)
+    s = A.lib().awe_storage_select(B.ctypes.byref(p), B.ctypes.byref(st), B.ctypes.byref(out), B.ctypes.byref(nb))
+    return s, (out.mode, out.nslots, out.prec), nb.value
+
+
+def test_auto_storage_falls_back_to_checkpoint_under_a_memory_budget():
+    """AUTO storage against a mocked budget: FULL while its workspace fits, else CHECKPOINT with
+    the largest slot count whose workspace fits; WORKSPACE when not even one slot fits."""
+    p, keep = _problem(nx=500, nz=400, nt=1000)
+    s, full, F = _select(p, 1)
+    assert s == 0 and full == (1, 0, 0)
+    ck = {k: _select(p, 2, k)[2] for k in (1, 2, 16, 17, 63, 64, 65)}
+    assert all(ck[a] < ck[b] for a, b in zip(sorted(ck), sorted(ck)[1:]))
+    assert ck[1] < F
+    mib = 1 << 20
+    s, eff, nb = _select(p, 3, budget_mib=-(-F // mib))
+    assert s == 0 and eff == (1, 0, 0) and nb == F
+    budget = 100
+    s, eff, nb = _select(p, 3, budget_mib=budget)
+    assert s == 0 and eff[0] == 2 and eff[2] == 0
+    k = eff[1]
+    assert nb == _select(p, 2, k)[2] <= budget * mib < _select(p, 2, k + 1)[2]
+    s, eff, _ = _select(p, 3, nslots=16, budget_mib=budget)
+    assert s == 0 and eff == (2, 16, 0)
+    s, eff, nb = _select(p, 3, prec=1, budget_mib=budget)      # BF16 slots: more of them fit
+    assert s == 0 and eff[0] == 2 and eff[1] > k and nb <= budget * mib
+    s, _, _ = _select(p, 3, budget_mib=ck[1] // mib)
+    assert s == 5 and "budget" in A.lib().awe_last_error().decode()
+    assert _select(p, 3, nslots=-1, budget_mib=10)[0] == 1
+    assert _select(p, 3, budget_mib=-1)[0] == 1
+    p3, keep3 = _problem(ndim=3, ny=40, nx=60, nz=60, nt=400)
+    s, eff, nb = _select(p3, 3, budget_mib=4)
+    assert s == 2 and "disabled in 3D" in A.lib().awe_last_error().decode()
+    s, full3, F3 = _select(p3, 1)
+    assert _select(p3, 3, budget_mib=-(-F3 // mib))[:2] == (0, (1, 0, 0))
+
+
+def test_auto_storage_binding_reports_the_choice():
+    st, nb = B.select_storage(2, 10.0, 1.0, 5, 3.0, [(400, 500)],
+                              [B.ShotGeometry(0, 1000, (100.0, 0.0, 50.0), np.array([[10.0, 0, 20.0]]))],
+                              B.Storage(B.STORE_AUTO, 0, B.PREC_FP32, 50))
+    assert st.mode == B.STORE_CHECKPOINT and st.nslots >= 1 and nb <= 50 << 20
+
+
 # ------------------------------------------------------------------------------ schedule
 @lru_cache(None)
 def _dp(l, s):

@@ -63,3 +63,15 @@ def test_3d_checkpointed_gradient_on_the_cpu_build(emu_lib):
     assert res["fp32_slots_bitwise_full"]
     assert res["grad_rel_ckpt_fp32"] <= 1e-5 and res["traces_rel"] <= 1e-5
     assert 0 < res["grad_rel_ckpt_bf16"] <= 2e-2
+
+
+def test_failure_paths_on_the_cpu_build(emu_lib):
+    """AUTO storage falls back to CHECKPOINT under a mocked free-memory figure (bitwise the FULL
+    gradient); input screening reports NaN (NONFINITE) and velocities above vmax (CFL) before any
+    compute kernel; output screening reports a blow-up; the autotuner cache is written, and a
+    cached entry is applied without running a kernel."""
+    import driver
+    r = driver.run([os.path.join(EMU, "case_failure_paths.py")], emu_lib, timeout=900)
+    print(r.stdout[-2000:])
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert r.stdout.strip().splitlines()[-1] == "CASE OK"

@@ -1,0 +1,97 @@
+"""Failure paths of a plan on the GPU, through the C ABI: AUTO storage falling back from FULL to
+CHECKPOINT under a memory budget (gradient bitwise the FULL one), the optional screening of
+inputs (NaN -> NONFINITE, velocity above the plan's vmax -> CFL) and outputs (a leapfrog blow-up
+-> NONFINITE), and the autotuner's result cache."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2304_05592_amd as A
+import workloads as W
+from helpers import gpu_inputs, make_plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup():
+    wl = W.small_2d(nshot=2, T=200.0)
+    dds = [W.synthetic_residual(s.nt, len(s.rec), wl.dt, wl.f0, 3 + i) for i, s in enumerate(wl.shots)]
+    return wl, dds
+
+
+def test_auto_storage_falls_back_to_checkpoint_and_matches_full():
+    wl, dds = _setup()
+    full = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, full)
+    g_full = full.gradient(m, q, full.pack(dds, "d"))[0]
+    fits = make_plan(wl, storage=A.Storage(A.STORE_AUTO, budget_mib=-(-full.ws_bytes // (1 << 20))))
+    assert fits.storage_in_effect.mode == A.STORE_FULL and fits.ws_bytes == full.ws_bytes
+    budget = full.ws_bytes // 2 // (1 << 20)
+    with pytest.warns(RuntimeWarning, match="CHECKPOINT"):
+        auto = make_plan(wl, storage=A.Storage(A.STORE_AUTO, budget_mib=budget))
+    eff = auto.storage_in_effect
+    assert eff.mode == A.STORE_CHECKPOINT and eff.nslots >= 1 and auto.ws_bytes <= budget << 20
+    g_auto = auto.gradient(m, q, auto.pack(dds, "d"))[0]
+    torch.cuda.synchronize()
+    print(f"AUTO under {budget} MiB: CHECKPOINT with {eff.nslots} slots", flush=True)
+    assert torch.equal(g_auto, g_full)
+    # the free-memory default (budget_mib = 0) keeps FULL storage for a small survey
+    assert make_plan(wl, storage=A.Storage(A.STORE_AUTO)).storage_in_effect.mode == A.STORE_FULL
+
+
+def test_input_and_output_screening():
+    wl, dds = _setup()
+    plan = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, plan)
+    dd = plan.pack(dds, "d")
+    g_ref = plan.gradient(m, q, dd)[0]
+    plan.set_checks(A.CHECK_INPUTS | A.CHECK_OUTPUTS)
+    assert torch.equal(plan.gradient(m, q, dd)[0], g_ref)
+    bad = m.clone()
+    bad[bad.numel() // 3] = float("nan")
+    with pytest.raises(A.AweError, match="m: 1 values are not finite") as e:
+        plan.gradient(bad, q, dd)
+    assert e.value.status == A.AWE_ERR_NONFINITE
+    bad_dd = dd.clone()
+    bad_dd[-1] = float("inf")
+    with pytest.raises(A.AweError, match="dd: 1 values") as e:
+        plan.gradient(m, q, bad_dd)
+    assert e.value.status == A.AWE_ERR_NONFINITE
+    fast = m / 100.0                      # ten times the velocity bound
+    with pytest.raises(A.AweError, match="vmax") as e:
+        plan.forward(fast, q)
+    assert e.value.status == A.AWE_ERR_CFL
+    plan.set_checks(A.CHECK_OUTPUTS)
+    with pytest.raises(A.AweError, match="d: .* not finite") as e:
+        plan.forward(fast, q)
+    assert e.value.status == A.AWE_ERR_NONFINITE
+    plan.set_checks(0)
+    d = plan.forward(fast, q)
+    torch.cuda.synchronize()
+    assert not torch.isfinite(d).all()
+    assert torch.equal(plan.gradient(m, q, dd)[0], g_ref)
+
+
+def test_autotune_cache_is_written_and_reused(tmp_path, monkeypatch):
+    wl, dds = _setup()
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("AWE_TUNE_CACHE", str(path))
+    p1 = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    m, q = gpu_inputs(wl, p1)
+    dd = p1.pack(dds, "d")
+    g_ref = p1.gradient(m, q, dd)[0]
+    tiles1, ms1 = p1.autotune(m, q, dd, probe_steps=8)
+    entries = json.loads(path.read_text())
+    assert len(entries) == 1
+    key, e = next(iter(entries.items()))
+    assert e["fw"] == [tiles1["tz"], tiles1["ty"], tiles1["bz"]] and e["fusion"] == tiles1["fusion"]
+    assert e["rv"] == [tiles1["adjoint"][k] for k in ("tz", "ty", "bz")]
+    assert abs(e["ms"] - ms1) <= 1e-5 * max(1.0, ms1)
+    path.write_text('{\n  "%s": {"fw": [8, 8, 0], "rv": [64, 8, 0], "fusion": 1, "ms": 42.500000}\n}\n' % key)
+    p2 = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    tiles2, ms2 = p2.autotune(m, q, dd, probe_steps=8)
+    assert ms2 == 42.5
+    assert (tiles2["tz"], tiles2["fusion"], tiles2["adjoint"]["tz"]) == (8, 1, 64)
+    assert torch.equal(p2.gradient(m, q, dd)[0], g_ref)
