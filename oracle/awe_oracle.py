@@ -44,7 +44,7 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = ["STENCIL", "STENCIL_EXACT", "laplacian", "damping_profile", "interp_nodes",
-           "restriction", "Propagator", "forward", "adjoint", "born", "gradient",
+           "restriction", "Propagator", "forward", "adjoint", "born", "gradient", "gradient_probed",
            "objective", "fold_edge", "stability_limit", "slowness2", "velocity_gradient",
            "PATCHY_CONSTANTS", "patchy", "patchy_vjp"]
 
@@ -319,6 +319,56 @@ def gradient(m, q, dd, src, rec, *, h, dt, nbl, vref, R=1e-3, dtype=None, segmen
         w2, w1 = w1, w
     if return_traces:
         return g, traces
+    return g
+
+
+def gradient_probed(m, q, dd, src, rec, C, s, *, h, dt, nbl, vref, R=1e-3, dtype=None):
+    """Estimate of J^T dd from r probes of the time axis instead of the stored wavefield.
+
+    The section "Remaining challenges" names the memory of the adjoint-state gradient as a
+    bottleneck and cites randomized trace estimation (Louboutin and Herrmann, 2022 and 2023);
+    on-the-fly Fourier transforms (Witte et al., 2019, cited in "Wave-equation-based
+    inversion") are the deterministic variant.  Both replace the nt stored fields by a few
+    weighted sums over time.  Written out: the exact gradient (see `gradient`) is
+        g = -(1/dt^2) sum_k w^k b^k,  b^k = u^k - 2u^{k-1} + u^{k-2},  k = 1..nt-1,
+    i.e. at every point the inner product of the two time series w and b.  With a table
+    C [r][nt] (column k weights level k) and weights s [r], the forward sweep keeps the r fields
+    B_j = sum_k C[j,k] b^k, the adjoint sweep the r fields A_j = sum_k C[j,k] w^k, and
+        g~ = -(1/dt^2) sum_j s_j A_j B_j = -(1/dt^2) sum_{k,l} w^k M_kl b^l,  M = C^T diag(s) C.
+    g~ = g when M = I (C = I, or the rows of a complete orthogonal basis with the inverse
+    squared norms as weights, e.g. the real DFT); with Rademacher rows and s = 1/r, E[M] = I
+    and g~ is Hutchinson's unbiased estimate.  Column 0 of C is not used (w^0, b^0 do not
+    enter).  Memory: 2 r fields instead of nt.
+    """
+    P = Propagator(m, src, rec, h=h, dt=dt, nbl=nbl, vref=vref, R=R, dtype=dtype)
+    q = np.asarray(q)
+    dd = np.asarray(dd)
+    nt = len(q)
+    dtype = np.result_type(P.dtype, q.dtype, dd.dtype)
+    C = np.asarray(C, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    r = C.shape[0]
+    assert C.shape[1] >= nt and s.shape == (r,)
+    B = np.zeros((r,) + P.shape, dtype=dtype)
+    A = np.zeros((r,) + P.shape, dtype=dtype)
+
+    def probe_forward(k, u, u1, u2):
+        if k >= 1:
+            b = u - 2 * u1 + u2
+            for j in range(r):
+                B[j] += C[j, k] * b
+
+    _forward_fields(P, q.astype(dtype), nt, probe_forward)
+    w1 = _zeros(P, dtype)
+    w2 = _zeros(P, dtype)
+    for k in range(nt - 1, 0, -1):
+        w = P.step(w1, w2, P.inject_receivers(dd[k]))
+        for j in range(r):
+            A[j] += C[j, k] * w
+        w2, w1 = w1, w
+    g = np.zeros(P.shape, dtype=dtype)
+    for j in range(r):
+        g -= s[j] * A[j] * B[j] / P.dt2
     return g
 
 

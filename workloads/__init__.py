@@ -19,12 +19,12 @@ media with smooth random heterogeneity and many shots per survey.
 """
 from .configs import (Shot, Workload, ricker, layered_velocity, two_layer_velocity,
                       smooth_perturbation, smooth_background, extend_edge, cfl_time_grid,
-                      make_config, config_names, small_2d, small_3d, synthetic_residual,
+                      make_config, config_names, small_2d, small_3d, synthetic_residual, probe_table,
                       random_field, timelapse_survey, plume_mask, reservoir_rock,
                       saturation_field)
 
 __all__ = ["Shot", "Workload", "ricker", "layered_velocity", "two_layer_velocity",
            "smooth_perturbation", "smooth_background", "extend_edge", "cfl_time_grid",
-           "make_config", "config_names", "small_2d", "small_3d", "synthetic_residual",
+           "make_config", "config_names", "small_2d", "small_3d", "synthetic_residual", "probe_table",
            "random_field", "timelapse_survey", "plume_mask", "reservoir_rock",
            "saturation_field"]

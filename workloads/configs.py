@@ -387,6 +387,38 @@ _CONFIGS = {"c1_fwd": _c1, "c2_grad": _c2, "c3_autograd": _c3, "c4_uneven": _c4,
             "c7_timelapse_rock": _c7}
 
 
+def probe_table(kind: str, nt: int, r: int = 0, seed: int = 0, freqs=None, dtype=np.float32):
+    """Coefficients C [r][nt] (dtype) and weights s [r] (float64) of a probed gradient:
+    'identity' (r = nt, s = 1), 'rademacher' (seeded +-1 rows, s = 1/r) or 'dft' (the real DFT
+    of length N = nt - 1 over the levels k = 1..nt-1 at the integer frequencies `freqs`: a cos
+    row, and a sin row unless f is 0 or N/2, with weights 1/N for f = 0 and N/2, 2/N otherwise;
+    all frequencies 0..N/2 give a complete orthogonal basis).  Column 0 is zero."""
+    if kind == "identity":
+        C = np.eye(nt, dtype=dtype)
+        C[0, 0] = 0.0
+        return C, np.ones(nt)
+    if kind == "rademacher":
+        rng = np.random.default_rng(seed)
+        C = np.where(rng.random((r, nt)) < 0.5, -1.0, 1.0).astype(dtype)
+        C[:, 0] = 0.0
+        return C, np.full(r, 1.0 / r)
+    if kind == "dft":
+        N = nt - 1
+        k = np.arange(1, nt)
+        rows, wts = [], []
+        for f in freqs:
+            edge = f == 0 or 2 * f == N
+            rows.append(np.cos(2 * np.pi * f * (k - 1) / N))
+            wts.append((1.0 if edge else 2.0) / N)
+            if not edge:
+                rows.append(np.sin(2 * np.pi * f * (k - 1) / N))
+                wts.append(2.0 / N)
+        C = np.zeros((len(rows), nt), dtype=np.float64)
+        C[:, 1:] = np.array(rows)
+        return C.astype(dtype), np.array(wts)
+    raise ValueError(kind)
+
+
 def config_names():
     return list(_CONFIGS)
 
