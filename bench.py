@@ -113,11 +113,12 @@ def copy_probe(nbytes=1 << 30, reps=5):
     return {"bytes_copied": nbytes, "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
 
 
-def traffic_record(kernel_file, kernel_name, launch_points):
-    """HBM bytes per launch measured by rocprofv3 PMC counters (profiles/traffic_*.json), or
-    None when the record is missing or the kernel source changed since it was taken."""
+def traffic_record(workload, kernel_file, kernel_name, launch_points, shape=None):
+    """HBM bytes per launch measured by rocprofv3 PMC counters (profiles/traffic_<workload>.json),
+    or None when the record is missing, was taken for another kernel, size or launch shape, or the
+    kernel source changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_c2_grad.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     src = os.path.join(ROOT, "paper_2304_05592_amd", "csrc", kernel_file)
     if not os.path.exists(path) or not os.path.exists(src):
         return None
@@ -125,6 +126,8 @@ def traffic_record(kernel_file, kernel_name, launch_points):
     if rec.get("kernel_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
     if rec.get("kernel") != kernel_name or rec.get("launch_points") != launch_points:
+        return None
+    if shape is not None and rec.get("shape") != shape:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -484,7 +487,7 @@ def bench_c2(args):
     roof = roofline_of(kernels, names)
     dom_name = (f"adj2d2_kernel<{adjoint_tz(run.tiles)}, 1>" if fa else f"adj2d_kernel<{adjoint_tz(run.tiles)}, 1>") \
         if run.tiles else None
-    roof["traffic"] = traffic_record("kernels2d.hip", dom_name, run.launch_points)
+    roof["traffic"] = traffic_record("c2_grad", "kernels2d.hip", dom_name, run.launch_points)
     roof["traffic_counter"] = TRAFFIC_NOTE
     # the whole step against the per-step table: 20 B forward + 36 B adjoint per point-update
     path_bytes = (BYTES[("forward", "fp32")] + BYTES[("adjoint", "fp32")]) * run.points
@@ -908,11 +911,18 @@ def bench_c5(args):
     sec, eager_sec, kernels, timing = timed_gradient(run, args, kind)
     names = {"forward": f"fwd3d step (forward + stored {args.prec} copy, {BYTES[('forward', kind)]} B/point)",
              "adjoint": f"adj3d step (adjoint + imaging, {BYTES[('adjoint', kind)]} B/point)"}
+    roof = roofline_of(kernels, names)
+    if run.tiles and roof.get("kernel") == names["adjoint"]:
+        adj = run.tiles["adjoint"]
+        img = {A.PREC_FP32: 1, A.PREC_BF16: 3, A.PREC_FP16: 4}[prec]
+        roof["traffic"] = traffic_record("c5_3d", "kernels3d.hip", f"adj3d_kernel<{adj['ty']}, {img}>",
+                                         run.launch_points, {"ty": adj["ty"], "bz": adj["bz"]})
+        roof["traffic_counter"] = TRAFFIC_NOTE
     out = base_line(args, wl, run.points / sec / 1e9, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": 1, "nt": int(wl.shots[0].nt), "storage": f"FULL {args.prec}",
                    "batched": False, "graph": not args.no_graph, "tiles": run.tiles},
-        "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
+        "roofline": roof, "cpu_baseline": None, "kernels": kernels,
         "kernel_timing": timing,
         "eager": {"value": round(run.points / eager_sec / 1e9, 3), "ms_per_step": round(eager_sec * 1e3, 3)},
         "loss": float(run.loss.item())})

@@ -1197,9 +1197,16 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   AWE_HIP(hipEventCreate(&e1));
   std::vector<hipEvent_t> keep_ev;  // keep the probes out of kernel timing
   keep_ev.swap(P->prof_ev);
-  const bool full32 = P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32;
-  const int fkind = full32 ? awe::kStoreF32 : awe::kStoreNone;
-  const int img = full32 ? awe::kImgFull32 : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
+  // the probes run the kernels the plan's calls run: with FULL storage the forward stores its
+  // levels (FP32 or scaled 16-bit) and the adjoint images from the store; with CHECKPOINT storage
+  // the reverse sweep images from the recomputed forward buffers
+  const bool full = P->store.mode == AWE_STORE_FULL;
+  const int prec = P->store.prec;
+  const int fkind = !full ? awe::kStoreNone
+                    : prec == AWE_PREC_FP32 ? awe::kStoreF32 : prec == AWE_PREC_BF16 ? awe::kStoreBF16 : awe::kStoreFP16;
+  const int img = full ? (prec == AWE_PREC_FP32 ? awe::kImgFull32 : prec == AWE_PREC_BF16 ? awe::kImgFullBF16
+                                                                                        : awe::kImgFullFP16)
+                       : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
   double best[2] = {1e300, 1e300};
   Cand win[2] = {cands[0], cands[0]};
   P->cur = 0;  // the probes time the first shot group
@@ -1220,10 +1227,15 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
       P->fuse2 = (P->fuse2 & ~bit) | (c.fuse ? bit : 0);
       if ((st = rebuild(P, dir == 0 ? 1 : 2)) != AWE_OK) return fail_out(st);
       if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return fail_out(st);
-      for (int i = 0; i < P->nshot; ++i)
+      for (int i = 0; i < P->nshot; ++i) {
         if (P->sd[i].acc >= 0)
           if (hipError_t e = awe::launch_fill(static_cast<unsigned char*>(ws), P->sd[i].acc, P->sd[i].npts * 8, s))
             return fail_out(hip_fail(e, "autotune fill"));
+        if (full && prec != AWE_PREC_FP32)  // per-level scales the 16-bit stores take their maxima into
+          if (hipError_t e = awe::launch_fill(static_cast<unsigned char*>(ws), P->sd[i].scale,
+                                              (long long)P->sd[i].nt * awe::kScaleSlots * 4, s))
+            return fail_out(hip_fail(e, "autotune fill"));
+      }
       awe::StepArgs fa = base_args(P, P->fw, ws);
       fa.q = q;
       awe::StepArgs aa = base_args(P, P->rv, ws);
