@@ -70,9 +70,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_grad",
-                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse",
+                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse", "c9_probed",
                              "c7_timelapse_rock", "c8_born"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probes", type=int, default=8, help="c9_probed: time-axis probes (1..64)")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph")
     ap.add_argument("--no-autotune", action="store_true")
@@ -825,6 +826,79 @@ def bench_c8(args):
         "kernel_timing": timing, "dd_norm": float(dd.norm().item())})
 
 
+def bench_c9(args):
+    """Probed gradient of the c2_grad survey (16 shots): no stored wavefield, r Rademacher probes
+    of the time axis accumulated in FP64 by the forward and adjoint step kernels, the estimate
+    formed per point at the end.  One call captured into a HIP graph and replayed."""
+    import torch
+    import paper_2304_05592_amd as A
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    r = args.probes
+    shots = range(wl.nshot)
+    plan = make_plan(wl, A.Storage(A.STORE_PROBED, r), shots)
+    m = plan.pack([wl.m(0, background=True)], "m")
+    q = plan.pack([wl.q(i) for i in shots], "q")
+    dd = plan.pack([W.synthetic_residual(wl.shots[i].nt, len(wl.shots[i].rec), wl.dt, wl.f0, 100 + i)
+                    for i in shots], "d")
+    max_nt = max(wl.shots[i].nt for i in shots)
+    C, sw = W.probe_table("rademacher", max_nt, r=r, seed=1)
+    Cd = torch.from_numpy(C).cuda()
+    ws = plan.workspace()
+    call = lambda: plan.gradient_probed(m, q, dd, Cd, sw, ws=ws)    # noqa: E731
+    tiles = choose_pass_tiles(plan, args, call)
+    groups = plan.set_groups(args.groups)
+    points, launch_points = points_of(wl, shots)
+    launch_points //= groups
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        g = call()[0]
+    torch.cuda.current_stream().wait_stream(st)
+    sync()
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=st):
+            g = call()[0]
+        sync()
+    run = (lambda: graph.replay()) if graph is not None else call
+    for _ in range(args.warmup):
+        run()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    kind = f"probe{r}"
+    BYTES[("forward", kind)] = BYTES[("forward", "none")] + 16 * r   # + FP64 read and write of B_1..B_r
+    BYTES[("adjoint", kind)] = BYTES[("adjoint", "none")] + 16 * r   # + FP64 read and write of A_1..A_r
+    n_launch = 2 * groups * max_nt
+    plan.profile_enable(min(n_launch, MAX_TIMED_LAUNCHES), -(-n_launch // MAX_TIMED_LAUNCHES))
+    call()
+    prof = plan.profile_read()
+    plan.profile_disable()
+    kernels = kernel_table(prof, launch_points, {"forward": kind, "adjoint": kind})
+    names = {"forward": f"fwd2d step + {r} FP64 probe sums ({BYTES[('forward', kind)]} B/point)",
+             "adjoint": f"adj2d step + {r} FP64 probe sums ({BYTES[('adjoint', kind)]} B/point)"}
+    _, full_ws = A.select_storage(wl.ndim, wl.h, wl.dt, wl.nbl, wl.vmax, [wl.comp_shape(0)],
+                                  [A.ShotGeometry(wl.shots[i].window, wl.shots[i].nt, wl.shots[i].src,
+                                                  wl.shots[i].rec) for i in shots],
+                                  A.Storage(A.STORE_FULL), damp_vref=wl.vmax)
+    return base_line(args, wl, points / sec / 1e9, sec, {
+        "metric": "Gpts/s probed gradient (batched, 16 shots)",
+        "config": {"workload": f"c9_probed: the c2_grad survey's gradient from {r} Rademacher probes of the "
+                               "time axis (no stored wavefield)",
+                   "grid": list(wl.comp_shape(0)), "shots": wl.nshot, "nt": int(max_nt),
+                   "storage": f"PROBED {r}", "batched": True, "graph": graph is not None, "tiles": tiles,
+                   "shot_groups": groups},
+        "workspace_bytes": plan.ws_bytes, "full_storage_workspace_bytes": full_ws,
+        "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
+        "kernel_timing": "HIP events around every launch of one eager call; value from graph replays",
+        "g_norm": float(g.norm().item())})
+
+
 def bench_c4(args):
     """64 uneven windows, forward: one batched graph-captured run vs 64 sequential runs."""
     import torch
@@ -945,7 +1019,7 @@ def main():
         return
     fn = {"c1_fwd": bench_c1, "c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4,
           "c5_3d": bench_c5, "c6_timelapse": bench_c6,
-          "c7_timelapse_rock": bench_c7, "c8_born": bench_c8}[args.config]
+          "c7_timelapse_rock": bench_c7, "c8_born": bench_c8, "c9_probed": bench_c9}[args.config]
     print(json.dumps(fn(args)), flush=True)
 
 

@@ -101,10 +101,13 @@ typedef enum {
   AWE_STORE_FULL = 1,       /* every u^n kept in the workspace */
   AWE_STORE_CHECKPOINT = 2, /* nslots restart pairs (u^n, u^{n-1}) per shot, binomial
                                recomputation schedule */
-  AWE_STORE_AUTO = 3        /* FULL if its workspace fits the memory budget, else CHECKPOINT
+  AWE_STORE_AUTO = 3,       /* FULL if its workspace fits the memory budget, else CHECKPOINT
                                with the most restart slots per shot that fit (at most nslots
                                when nslots > 0, at most the number of time steps); the plan
                                reports the choice (awe_plan_get_storage) */
+  AWE_STORE_PROBED = 4      /* no wavefield kept: nslots = r probes of the time axis (1..64),
+                               2 r FP64 fields per shot; gradients by awe_gradient_probed
+                               (2D plans) */
 } awe_store_mode;
 
 typedef enum {
@@ -183,6 +186,24 @@ awe_status awe_backward(awe_plan* plan, const float* m, const float* q, const fl
 /* awe_forward(keep = 1) followed by awe_backward.  d may be NULL (traces not returned). */
 awe_status awe_gradient(awe_plan* plan, const float* m, const float* q, const float* dd,
                         double* g, float* v, float* d, void* ws, size_t ws_bytes, void* stream);
+
+/* Probed gradient: an estimate of J^T dd from r sums over the time axis instead of the stored
+ * wavefield (randomized trace estimation and on-the-fly Fourier transforms, which the section
+ * "Remaining challenges" cites against the memory bottleneck of the adjoint-state gradient).
+ * The exact gradient is g = -(1/dt^2) sum_k w^k b^k with b^k = u^k - 2u^{k-1} + u^{k-2}
+ * (k = 1..nt-1, w the adjoint field); the forward sweep accumulates B_j = sum_k C[j][k] b^k, the
+ * reverse sweep A_j = sum_k C[j][k] w^k (both FP64), and g = -(1/dt^2) sum_j s_j A_j B_j: exact
+ * when C^T diag(s) C = I, unbiased when its expectation is I (Rademacher rows, s_j = 1/r).
+ * Plan: 2D, storage AWE_STORE_PROBED with nslots = r.  C: device float [r][max_nt] row-major,
+ * column k weights every shot's local level k (max_nt = the largest nt of the plan; column 0 is
+ * not used).  s: host double [r], read during the call.  g: FP64 as in awe_backward; v, d (may
+ * be NULL) as in awe_gradient.  One call runs the forward and the reverse sweep; no forward is
+ * kept.  Workspace: the plan's (2 r FP64 fields per shot besides the field buffers).
+ * Errors: INVALID_ARG, UNSUPPORTED (storage not PROBED), WORKSPACE, HIP, and the screening
+ * errors of awe_plan_set_checks. */
+awe_status awe_gradient_probed(awe_plan* plan, const float* m, const float* q, const float* dd,
+                               const float* C, const double* s, double* g, float* v, float* d, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /* v = F(m)^T dd: float [nt] per shot at q_offset. */
 awe_status awe_adjoint(awe_plan* plan, const float* m, const float* dd, float* v, void* ws,

@@ -21,7 +21,7 @@ AWE_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "CFL", 4: "GEOMETRY", 5: "WORKSPACE",
           6: "STATE", 7: "HIP", 8: "NONFINITE"}
 AWE_ERR_CFL, AWE_ERR_WORKSPACE, AWE_ERR_NONFINITE = 3, 5, 8
-STORE_NONE, STORE_FULL, STORE_CHECKPOINT, STORE_AUTO = 0, 1, 2, 3
+STORE_NONE, STORE_FULL, STORE_CHECKPOINT, STORE_AUTO, STORE_PROBED = 0, 1, 2, 3, 4
 CHECK_INPUTS, CHECK_OUTPUTS = 1, 2
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 
@@ -31,7 +31,7 @@ EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "aw
            "awe_plan_autotune", "awe_plan_get_tiles", "awe_plan_set_tiles", "awe_plan_set_tiles_dir",
            "awe_plan_set_fusion", "awe_plan_set_groups", "awe_profile_enable", "awe_profile_read", "awe_profile_disable",
            "awe_slowness2", "awe_velocity_gradient", "awe_patchy", "awe_patchy_vjp", "awe_status_string", "awe_last_error", "awe_version",
-           "awe_storage_select", "awe_plan_get_storage", "awe_plan_set_checks"]
+           "awe_storage_select", "awe_plan_get_storage", "awe_plan_set_checks", "awe_gradient_probed"]
 
 
 FUSE_NONE, FUSE_FORWARD, FUSE_ADJOINT, FUSE_BOTH = 0, 1, 2, 3
@@ -91,6 +91,7 @@ def lib():
     L.awe_forward.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
     L.awe_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.awe_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.awe_gradient_probed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.awe_adjoint.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     L.awe_born.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.awe_reduce_workspace_size.argtypes = [i64]
@@ -128,7 +129,7 @@ def lib():
                  "awe_plan_set_tiles_dir", "awe_plan_set_fusion", "awe_plan_set_groups", "awe_slowness2", "awe_velocity_gradient", "awe_patchy",
                  "awe_patchy_vjp", "awe_profile_enable",
                  "awe_profile_read", "awe_profile_disable", "awe_storage_select", "awe_plan_get_storage",
-                 "awe_plan_set_checks"):
+                 "awe_plan_set_checks", "awe_gradient_probed"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -165,7 +166,7 @@ class ShotGeometry:
 class Storage:
     """Wavefield storage of a plan.  STORE_AUTO: FULL if its workspace fits budget_mib MiB (0: 90 %
     of the device's free memory), else CHECKPOINT with the most slots that fit (at most nslots
-    when nslots > 0)."""
+    when nslots > 0).  STORE_PROBED: no wavefield, nslots probes (Plan.gradient_probed)."""
     mode: int = STORE_NONE
     nslots: int = 0
     prec: int = PREC_FP32
@@ -442,6 +443,34 @@ class Plan:
         ws = self.workspace(m.device) if ws is None else ws
         check(lib().awe_gradient(self._h, _ptr(m), _ptr(q), _ptr(dd), _ptr(gt), _ptr(vt), _ptr(dt_),
                                  _ptr(ws), self.ws_bytes, _stream_ptr(stream)))
+        return gt, vt, dt_
+
+    def gradient_probed(self, m, q, dd, C, s, v=False, d=False, ws=None, stream=None):
+        """(g, v, d) with g the probed estimate of J^T dd (plan storage STORE_PROBED, r probes):
+        C float32 [r][max_nt] (column k weights local level k; a device tensor, or an array that
+        is copied to the device), s the r weights.  See awe_gradient_probed."""
+        import torch
+        lay = self.layout
+        r = self.storage.nslots
+        max_nt = max(int(sh.nt) for sh in self.shots)
+        self._check(m, lay.m_size, torch.float32, "m")
+        self._check(q, lay.q_size, torch.float32, "q")
+        self._check(dd, lay.d_size, torch.float32, "dd")
+        if not isinstance(C, torch.Tensor):
+            C = torch.from_numpy(np.ascontiguousarray(C, dtype=np.float32)).to(m.device)
+        if tuple(C.shape) != (r, max_nt):
+            raise ValueError(f"C must be [{r}][{max_nt}] (probes x largest nt), got {tuple(C.shape)}")
+        self._check(C, r * max_nt, torch.float32, "C")
+        sw = np.ascontiguousarray(s, dtype=np.float64)
+        if sw.shape != (r,):
+            raise ValueError(f"s must hold {r} weights")
+        gt = torch.empty(lay.m_size, dtype=torch.float64, device=m.device)
+        vt = torch.empty(lay.q_size, dtype=torch.float32, device=m.device) if v else None
+        dt_ = torch.empty(lay.d_size, dtype=torch.float32, device=m.device) if d else None
+        ws = self.workspace(m.device) if ws is None else ws
+        check(lib().awe_gradient_probed(self._h, _ptr(m), _ptr(q), _ptr(dd), _ptr(C),
+                                        sw.ctypes.data_as(ctypes.c_void_p), _ptr(gt), _ptr(vt), _ptr(dt_),
+                                        _ptr(ws), self.ws_bytes, _stream_ptr(stream)))
         return gt, vt, dt_
 
     def adjoint(self, m, dd, v=None, ws=None, stream=None):

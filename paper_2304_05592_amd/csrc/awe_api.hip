@@ -864,8 +864,12 @@ awe_status validate(const awe_problem* prob, const awe_storage* store) {
     return fail(AWE_ERR_INVALID_ARG, "h, dt, vmax and damp_vref must be positive");
   if (!(prob->damp_R > 0) || prob->damp_R > 1) return fail(AWE_ERR_INVALID_ARG, "damp_R must be in (0, 1]");
   if (prob->nbl < 0) return fail(AWE_ERR_INVALID_ARG, "nbl must be >= 0");
-  if (store->mode < AWE_STORE_NONE || store->mode > AWE_STORE_AUTO)
+  if (store->mode < AWE_STORE_NONE || store->mode > AWE_STORE_PROBED)
     return fail(AWE_ERR_INVALID_ARG, "bad storage mode");
+  if (store->mode == AWE_STORE_PROBED && (store->nslots < 1 || store->nslots > awe::kMaxProbes))
+    return fail(AWE_ERR_INVALID_ARG, "PROBED storage needs 1 <= nslots <= " + std::to_string(awe::kMaxProbes) + " probes");
+  if (store->mode == AWE_STORE_PROBED && prob->ndim == 3)
+    return fail(AWE_ERR_UNSUPPORTED, "PROBED storage is implemented for 2D plans only");
   if (store->prec < AWE_PREC_FP32 || store->prec > AWE_PREC_FP16)
     return fail(AWE_ERR_INVALID_ARG, "bad storage precision");
   if (store->mode == AWE_STORE_CHECKPOINT && store->nslots < 1)
@@ -913,7 +917,7 @@ void layout_ws(awe_plan* P) {
     d.acc = -1;
     d.store = -1;
     d.scale = -1;
-    if (st.mode == AWE_STORE_NONE) continue;
+    if (st.mode != AWE_STORE_FULL && st.mode != AWE_STORE_CHECKPOINT) continue;
     d.acc = off;
     off = align256(off + d.npts * 8);
   }
@@ -930,6 +934,9 @@ void layout_ws(awe_plan* P) {
       off = align256(off + (long long)st.nslots * 2 * d.npts * esz);
       d.scale = off;
       off = align256(off + (long long)st.nslots * 2 * 4);
+    } else if (st.mode == AWE_STORE_PROBED) {
+      d.store = off;  // FP64 probe sums B [r][npts], then A [r][npts]
+      off = align256(off + (long long)st.nslots * 2 * d.npts * 8);
     }
   }
   P->ws_bytes = (size_t)off;
@@ -1412,7 +1419,7 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
   if ((P->checks & AWE_CHECK_INPUTS) &&
       (st = screen(P, {{m, false, kPerWindow, "m", true}, {q, false, kPerShotQ, "q", false}}, s)) != AWE_OK)
     return st;
-  const bool store = keep && P->store.mode != AWE_STORE_NONE;
+  const bool store = keep && (P->store.mode == AWE_STORE_FULL || P->store.mode == AWE_STORE_CHECKPOINT);
   P->kept_ws = nullptr;
   if ((st = prepare(P, m, ws, true, false, s)) != AWE_OK) return st;
   awe::StepArgs a = base_args(P, P->fw, ws);
@@ -1449,7 +1456,7 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
   awe_status st = check_ws(P, ws, ws_bytes);
   if (st != AWE_OK) return st;
   if (!dd || !q) return fail(AWE_ERR_INVALID_ARG, "q and dd must not be NULL");
-  if (P->store.mode == AWE_STORE_NONE || P->kept_ws != ws)
+  if ((P->store.mode != AWE_STORE_FULL && P->store.mode != AWE_STORE_CHECKPOINT) || P->kept_ws != ws)
     return fail(AWE_ERR_STATE, "the workspace holds no kept forward wavefield of this plan");
   (void)m;  // the coefficients of the kept forward are reused
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1492,8 +1499,10 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
 
 awe_status awe_gradient(awe_plan* P, const float* m, const float* q, const float* dd, double* g,
                         float* v, float* d, void* ws, size_t ws_bytes, void* stream) {
-  if (P && P->store.mode == AWE_STORE_NONE)
-    return fail(AWE_ERR_UNSUPPORTED, "gradient needs FULL or CHECKPOINT storage");
+  if (P && P->store.mode != AWE_STORE_FULL && P->store.mode != AWE_STORE_CHECKPOINT)
+    return fail(AWE_ERR_UNSUPPORTED, P->store.mode == AWE_STORE_PROBED
+                                         ? "PROBED storage: use awe_gradient_probed"
+                                         : "gradient needs FULL or CHECKPOINT storage");
   awe_status st = AWE_OK;
   const int checks = P ? P->checks : 0;
   if (checks & AWE_CHECK_INPUTS) {
@@ -1509,6 +1518,56 @@ awe_status awe_gradient(awe_plan* P, const float* m, const float* q, const float
   if (st == AWE_OK) st = awe_backward(P, m, q, dd, g, v, ws, ws_bytes, stream);
   if (P) P->checks = checks;
   return st;
+}
+
+awe_status awe_gradient_probed(awe_plan* P, const float* m, const float* q, const float* dd, const float* C,
+                               const double* s_w, double* g, float* v, float* d, void* ws, size_t ws_bytes,
+                               void* stream) {
+  awe_status st = check_ws(P, ws, ws_bytes);
+  if (st != AWE_OK) return st;
+  if (P->store.mode != AWE_STORE_PROBED) return fail(AWE_ERR_UNSUPPORTED, "the plan's storage is not PROBED");
+  if (!m || !q || !dd || !C || !s_w || !g) return fail(AWE_ERR_INVALID_ARG, "m, q, dd, C, s and g must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((P->checks & AWE_CHECK_INPUTS) &&
+      (st = screen(P, {{m, false, kPerWindow, "m", true}, {q, false, kPerShotQ, "q", false},
+                       {dd, false, kPerShotD, "dd", false}}, s)) != AWE_OK)
+    return st;
+  const int r = P->store.nslots;
+  awe::ProbeWeights w{};
+  for (int j = 0; j < r; ++j) w.s[j] = s_w[j];
+  P->kept_ws = nullptr;
+  if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  for (int i = 0; i < P->nshot; ++i)
+    AWE_HIP(awe::launch_fill(wsb, P->sd[i].store, (long long)r * 2 * P->sd[i].npts * 8, s));
+  // forward sweep: B_j += C[j][k] (u^k - 2u^{k-1} + u^{k-2}) in the step kernels
+  awe::StepArgs a = base_args(P, P->fw, ws);
+  a.q = q;
+  a.d = d;
+  a.probe_c = C;
+  a.probe_r = r;
+  a.probe_pitch = P->max_nt;
+  for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur)
+    if ((st = forward_loop(P, a, awe::kStoreProbe, s)) != AWE_OK) return st;
+  if (d) AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 0, s));
+  // reverse sweep: A_j += C[j][k] w^k in the adjoint step kernels
+  awe::StepArgs aa = base_args(P, P->rv, ws);
+  aa.dd = dd;
+  aa.v = v;
+  aa.image_src = awe::kImgProbe;
+  aa.probe_c = C;
+  aa.probe_r = r;
+  aa.probe_pitch = P->max_nt;
+  for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur)
+    if ((st = adjoint_loop(P, aa, s)) != AWE_OK) return st;
+  if (v) AWE_HIP(awe::launch_src_last(aa, P->nshot, s));
+  AWE_HIP(awe::launch_probe_reduce(P->rv.tab, (int)P->wins.size(), P->max_win_npts, wsb, r, w, g,
+                                   -1.0 / (P->dt * P->dt), s));
+  if ((P->checks & AWE_CHECK_OUTPUTS) &&
+      (st = screen(P, {{g, true, kPerWindow, "g", false}, {v, false, kPerShotQ, "v", false},
+                       {d, false, kPerShotD, "d", false}}, s)) != AWE_OK)
+    return st;
+  return AWE_OK;
 }
 
 awe_status awe_adjoint(awe_plan* P, const float* m, const float* dd, float* v, void* ws,

@@ -31,11 +31,18 @@ enum Prec : int { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
 // Where the adjoint's imaging condition reads u^j: nowhere, the FULL store (FP32 / BF16 /
 // FP16, the latter two scaled per level) or the recomputed forward buffers.
-enum ImageSrc : int { kImgNone = 0, kImgFull32 = 1, kImgBuffers = 2, kImgFullBF16 = 3, kImgFullFP16 = 4 };
+enum ImageSrc : int { kImgNone = 0, kImgFull32 = 1, kImgBuffers = 2, kImgFullBF16 = 3, kImgFullFP16 = 4,
+                      kImgProbe = 5 };  // kImgProbe: A_j += C[j][level] w^level (probed gradient)
 
 // Forward-step storage of each level: none, FP32 copy, or scaled BF16 / FP16 (the level is
 // quantised one step later, once its max |u| is complete).
-enum StoreKind : int { kStoreNone = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreFP16 = 3 };
+// kStoreProbe: B_j += C[j][level] (u^k - 2u^{k-1} + u^{k-2}) instead of a stored level (probed
+// gradient; the second difference is the step's increment).
+enum StoreKind : int { kStoreNone = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreFP16 = 3, kStoreProbe = 4 };
+
+// Probed gradient: at most this many probes; a shot's accumulators are FP64 fields [2][r][npts] at
+// ShotDev::store, B (forward second differences) first, then A (adjoint levels).
+constexpr int kMaxProbes = 64;
 
 // Per-shot description as the kernels read it.
 struct ShotDev {
@@ -133,6 +140,8 @@ struct StepArgs {
   float c[5];                // stencil weights / h^2
   float eta_dt;              // damping amplitude / (nbl^2 dt): eta/dt = eta_dt * (dx^2 + dy^2 + dz^2)
   float inv_dt2;             // 1 / dt^2 (Born source)
+  const float* probe_c;      // probed gradient: coefficients [probe_r][probe_pitch], column = local level
+  int probe_r, probe_pitch;
 };
 
 // Forward level k (local index) of shot S.  After a checkpoint restore of global state n from
@@ -177,6 +186,13 @@ hipError_t launch_absmax(const StepArgs& a, int nshot, int slot, int state, hipS
 // g[window] = scale * sum over the window's shots (ascending) of their FP64 accumulators.
 hipError_t launch_grad_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws,
                               double* g, double scale, hipStream_t stream);
+// Probed gradient: g[window] = scale * sum over the window's shots (ascending) of
+// sum_j s[j] A_j B_j, in FP64.
+struct ProbeWeights {
+  double s[kMaxProbes];
+};
+hipError_t launch_probe_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws, int r,
+                               const ProbeWeights& w, double* g, double scale, hipStream_t stream);
 hipError_t launch_slowness2(const float* v, float* m, long long n, hipStream_t stream);
 hipError_t launch_velocity_gradient(const float* v, const float* gm, float* gv, long long n,
                                     hipStream_t stream);

@@ -206,15 +206,20 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
   // FULL store: level k (FP32) or level k-1 (16 bits, quantised with its finished scale)
   const brsrc rst = SK == kStoreF32
       ? make_rsrc(reinterpret_cast<float*>(a.ws + S.store) + (long long)k * npts, nz * row4)
-      : make_rsrc(reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * npts, nz * row4 / 2);
+      : make_rsrc(reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * npts,
+                  SK == kStoreBF16 || SK == kStoreFP16 ? nz * row4 / 2 : 0);
   // checkpoint store fused into the step that reaches the stored state: (u^k, u^{k-1}) into slot
   const bool to_slot = SK == kStoreNone && a.st_slot >= 0;
   float* sl = reinterpret_cast<float*>(a.ws + S.store) + (long long)(to_slot ? a.st_slot : 0) * 2 * npts;
   const brsrc rsl0 = make_rsrc(sl, to_slot ? nz * row4 : 0);
   const brsrc rsl1 = make_rsrc(sl + npts, to_slot ? nz * row4 : 0);
   const int cx2 = x < nx ? 2 * x : kOOB;
-  float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
-  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
+  constexpr bool S16 = SK == kStoreBF16 || SK == kStoreFP16;
+  float* scl = S16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
+  const float inv_prev = S16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
+  // probed gradient: the r FP64 sums B_j of this shot, and this level's coefficients
+  double* pb = SK == kStoreProbe ? reinterpret_cast<double*>(a.ws + S.store) : nullptr;
+  const float* pc = SK == kStoreProbe ? a.probe_c + k : nullptr;
   float lmax = 0.f;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
@@ -240,12 +245,18 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
       stb(rsl1, u, cx, zo);
     }
     if (SK == kStoreF32) stb_nt(rst, un, cx, zo);
-    if (SK >= kStoreBF16) {
+    if (S16) {
       lmax = fmaxf(lmax, fabsf(un));
       if (k >= 2) stb16_nt(rst, enc16(u * inv_prev, SK == kStoreBF16), cx2, zo / 2);
     }
+    if (SK == kStoreProbe && x < nx && z < nz) {
+      // u^k - 2u^{k-1} + u^{k-2} = incr (increment form of the step)
+      const long long p = (long long)z * px + x;
+      const double b = (double)incr;
+      for (int j = 0; j < a.probe_r; ++j) pb[j * npts + p] += (double)pc[(long long)j * a.probe_pitch] * b;
+    }
   }
-  if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
+  if (S16) block_max_to_slot(lmax, scl, k);
 }
 
 // ------------------------------------------------------------------------------ adjoint
@@ -270,17 +281,22 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
   const brsrc rout = make_rsrc(fbuf(a.ws, S, adj_buf(j)), nz * row4);
   // imaging: u^j from the FULL store (FP32, or 16 bits with the level's scale) or the forward
   // buffers, and the FP64 accumulator
+  constexpr bool I16 = IMG == kImgFullBF16 || IMG == kImgFullFP16;
+  constexpr bool IACC = IMG != kImgNone && IMG != kImgProbe;  // imaging into the FP64 accumulator
   const void* ubase = IMG == kImgBuffers ? (const void*)fwd_level(a, S, j)
                       : IMG == kImgFull32 ? (const void*)(reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts)
                       : (const void*)(reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts);
-  const Planes uj = planes(ubase, nz, IMG ? nz : 0, IMG >= kImgFullBF16 ? row4 / 2 : row4);
-  const float usc = IMG >= kImgFullBF16 ? level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j) : 1.f;
-  const Planes acc = planes(a.ws + S.acc, nz, IMG ? nz : 0, 2 * row4);
-  const brsrc racc = make_rsrc(a.ws + S.acc, IMG ? 2 * nz * row4 : 0);
+  const Planes uj = planes(ubase, nz, IACC ? nz : 0, I16 ? row4 / 2 : row4);
+  const float usc = I16 ? level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j) : 1.f;
+  const Planes acc = planes(a.ws + S.acc, nz, IACC ? nz : 0, 2 * row4);
+  const brsrc racc = make_rsrc(a.ws + S.acc, IACC ? 2 * nz * row4 : 0);
+  // probed gradient: the r FP64 sums A_j of this shot (after its B_j), and this level's coefficients
+  double* pa = IMG == kImgProbe ? reinterpret_cast<double*>(a.ws + S.store) + (long long)a.probe_r * S.npts : nullptr;
+  const float* pc = IMG == kImgProbe ? a.probe_c + j : nullptr;
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int x = T.x0 + lane;
   const int cx = x < nx ? 4 * x : kOOB;
-  const int cxu = x < nx ? (IMG >= kImgFullBF16 ? 2 : 4) * x : kOOB;
+  const int cxu = x < nx ? (I16 ? 2 : 4) * x : kOOB;
   const int cx8 = x < nx ? 8 * x : kOOB;
   const bool has_inj = T.inj_count > 0 && a.dd != nullptr;  // no residual: nothing to inject
 
@@ -291,10 +307,10 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
     const int z = T.z0 + wv * RPT + i;
     pw2[i] = ldp(w2, cx, z);
     pcf[i] = ldp(cf, cx, z);
-    if (IMG >= kImgFullBF16) pu[i] = dec16(ldp16_nt(uj, cxu, z), IMG == kImgFullBF16) * usc;
+    if (I16) pu[i] = dec16(ldp16_nt(uj, cxu, z), IMG == kImgFullBF16) * usc;
     else if (IMG == kImgFull32) pu[i] = ldp_nt(uj, cxu, z);
-    else if (IMG) pu[i] = ldp(uj, cxu, z);
-    if (IMG) pacc[i] = ldp64(acc, cx8, z);
+    else if (IACC) pu[i] = ldp(uj, cxu, z);
+    if (IACC) pacc[i] = ldp64(acc, cx8, z);
     if (has_inj) INJ[wv * RPT + i][lane] = 0.f;
   }
   int ho[Side4<TZ>::NH];
@@ -331,8 +347,14 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
     const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
     const float incr = step_incr(w, pw2[i], pcf[i], lap, eta);
     const int zo = z * row4;
-    stb(rout, (w + w - pw2[i]) + incr, cx, zo);
-    if (IMG) stb64(racc, pacc[i] + (double)pu[i] * (double)incr, cx8, 2 * zo);
+    const float wn = (w + w - pw2[i]) + incr;
+    stb(rout, wn, cx, zo);
+    if (IACC) stb64(racc, pacc[i] + (double)pu[i] * (double)incr, cx8, 2 * zo);
+    if (IMG == kImgProbe && x < nx && z < nz) {
+      const long long p = (long long)z * px + x;
+      const double wv64 = (double)wn;
+      for (int jj = 0; jj < a.probe_r; ++jj) pa[jj * S.npts + p] += (double)pc[(long long)jj * a.probe_pitch] * wv64;
+    }
   }
 }
 
@@ -769,6 +791,7 @@ hipError_t fwd2d_tz(const StepArgs& a, int store, hipStream_t s) {
     case kStoreF32: fwd2d_kernel<TZ, kStoreF32><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kStoreBF16: fwd2d_kernel<TZ, kStoreBF16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kStoreFP16: fwd2d_kernel<TZ, kStoreFP16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kStoreProbe: fwd2d_kernel<TZ, kStoreProbe><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -782,6 +805,7 @@ hipError_t adj2d_tz(const StepArgs& a, hipStream_t s) {
     case kImgBuffers: adj2d_kernel<TZ, kImgBuffers><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kImgFullBF16: adj2d_kernel<TZ, kImgFullBF16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kImgFullFP16: adj2d_kernel<TZ, kImgFullFP16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kImgProbe: adj2d_kernel<TZ, kImgProbe><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

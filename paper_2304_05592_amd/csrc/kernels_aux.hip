@@ -162,6 +162,29 @@ __global__ void grad_reduce_kernel(Tables t, unsigned char* ws, double* __restri
   }
 }
 
+// Probed gradient: g = scale * sum over the window's shots (ascending) of sum_j s_j A_j B_j, with
+// B_j, A_j the shot's FP64 probe sums [2][r][npts] at S.store.
+__global__ void probe_reduce_kernel(Tables t, unsigned char* ws, int r, ProbeWeights w, double* __restrict__ g,
+                                    double scale) {
+  const WinDev W = t.wins[blockIdx.y];
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < W.npts;
+       p += (long long)gridDim.x * blockDim.x) {
+    const long long row = p / W.px;
+    const int i = (int)(p - row * W.px);
+    if (i >= W.nx) continue;
+    double s = 0.0;
+    for (int k = 0; k < W.scount; ++k) {
+      const ShotDev& S = t.shots[t.win_shots[W.sbegin + k]];
+      const double* B = reinterpret_cast<const double*>(ws + S.store);
+      const double* A = B + (long long)r * S.npts;
+      double e = 0.0;
+      for (int j = 0; j < r; ++j) e += w.s[j] * (A[j * S.npts + p] * B[j * S.npts + p]);
+      s += e;
+    }
+    g[W.m + row * W.nx + i] = scale * s;
+  }
+}
+
 // Deterministic reduction: block b sums a fixed contiguous chunk in a fixed order, then one
 // block sums the kReduceBlocks partials.
 __device__ __forceinline__ double block_sum(double v) {
@@ -451,6 +474,12 @@ hipError_t launch_store_last(const StepArgs& a, int nshot, long long max_npts, h
 hipError_t launch_grad_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws,
                               double* g, double scale, hipStream_t s) {
   grad_reduce_kernel<<<dim3(grid_for(max_npts), nwin), kThreads, 0, s>>>(t, ws, g, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_reduce(const Tables& t, int nwin, long long max_npts, unsigned char* ws, int r,
+                               const ProbeWeights& w, double* g, double scale, hipStream_t s) {
+  probe_reduce_kernel<<<dim3(grid_for(max_npts), nwin), kThreads, 0, s>>>(t, ws, r, w, g, scale);
   return hipGetLastError();
 }
 

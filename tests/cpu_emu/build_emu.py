@@ -112,6 +112,10 @@ extern "C" int awe_emu_subbuffers(const awe_plan* P, long long* out, int cap) {
     } else if (P->store.mode == AWE_STORE_CHECKPOINT) {
       add(d.store, (long long)P->store.nslots * 2 * d.npts * esz);
       add(d.scale, (long long)P->store.nslots * 2 * 4);
+    } else if (P->store.mode == AWE_STORE_PROBED) {
+      // the B and A probe sums as separate sub-buffers: an access of one past its end is caught
+      add(d.store, (long long)P->store.nslots * d.npts * 8);
+      add(d.store + (long long)P->store.nslots * d.npts * 8, (long long)P->store.nslots * d.npts * 8);
     }
   }
   const int n = (int)(r.size() / 2);

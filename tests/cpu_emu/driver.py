@@ -35,6 +35,8 @@ class EmuLib:
         L.awe_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.awe_adjoint.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         L.awe_born.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+        if hasattr(L, "awe_gradient_probed"):
+            L.awe_gradient_probed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         for name, args in (("awe_plan_set_tiles", [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
                            ("awe_plan_set_tiles_dir", [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                        ctypes.c_int32]),
@@ -160,6 +162,18 @@ class EmuPlan:
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_gradient(self.h, _p(m), _p(q), _p(dd), _p(g), _p(vv), _p(dt), _p(ws),
                                            ws.nbytes, None))
+        return g, vv, dt
+
+    def gradient_probed(self, m, q, dd, C, s, v=False, d=False, ws=None):
+        lay = self.layout
+        g = _filled(lay.m_size * 8).view(np.float64)
+        vv = _filled(lay.q_size * 4).view(np.float32) if v else None
+        dt = _filled(lay.d_size * 4).view(np.float32) if d else None
+        ws = self.workspace() if ws is None else ws
+        C = np.ascontiguousarray(C, dtype=np.float32)
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        self.lib.check(self.L.awe_gradient_probed(self.h, _p(m), _p(q), _p(dd), _p(C), _p(s), _p(g), _p(vv),
+                                                  _p(dt), _p(ws), ws.nbytes, None))
         return g, vv, dt
 
     def forward(self, m, q, ws=None):

@@ -75,3 +75,16 @@ def test_failure_paths_on_the_cpu_build(emu_lib):
     print(r.stdout[-2000:])
     assert r.returncode == 0, r.stderr[-4000:]
     assert r.stdout.strip().splitlines()[-1] == "CASE OK"
+
+
+def test_probed_gradient_on_the_cpu_build(emu_lib):
+    """PROBED storage on an uneven 2D batch against the oracle's gradient_probed (Rademacher
+    probes) and against the exact gradient (identity table), under AddressSanitizer; the result
+    does not depend on the launch shape or the shot grouping."""
+    import driver
+    r = driver.run([os.path.join(EMU, "case_probed.py")], emu_lib, timeout=900)
+    assert r.returncode == 0, r.stderr[-4000:]
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    print(res)
+    assert res["rademacher"] <= 1e-5 and res["identity"] <= 1e-5 and res["identity_vs_exact"] <= 1e-5
+    assert res["shape_invariant"]
