@@ -65,8 +65,10 @@ typedef enum {
   AWE_ERR_WORKSPACE = 5,    /* workspace null or smaller than awe_plan_workspace_size */
   AWE_ERR_STATE = 6,        /* awe_backward without a preceding awe_forward(keep=1) */
   AWE_ERR_HIP = 7,          /* a HIP runtime call failed */
-  AWE_ERR_NONFINITE = 8     /* screening on (awe_plan_set_checks): an input or output holds a
+  AWE_ERR_NONFINITE = 8,    /* screening on (awe_plan_set_checks): an input or output holds a
                                value that is not finite */
+  AWE_ERR_INTERNAL = 9      /* launch checks on (awe_plan_set_checks): a launch would touch bytes
+                               outside its workspace sub-buffer or tables (a library defect) */
 } awe_status;
 
 /* One shot: a model window, its time axis and its acquisition. */
@@ -152,10 +154,16 @@ awe_status awe_plan_get_storage(const awe_plan* plan, awe_storage* out);
  *     the leapfrog may be unstable (error CFL).  No compute work is enqueued on error.
  *   AWE_CHECK_OUTPUTS: after the call's work, d, g, v and dd (those it writes) are checked for
  *     values that are not finite (error NONFINITE; the outputs are then invalid).
- * With any flag set the compute calls synchronise the stream once per screened group of arrays
- * and must not be captured into a graph.  Each screened element is read once more from HBM.
- * Errors: INVALID_ARG, HIP (counter allocation on first use). */
-enum { AWE_CHECK_INPUTS = 1, AWE_CHECK_OUTPUTS = 2 };
+ *   AWE_CHECK_LAUNCHES: before every launch the host checks what it computed for it against
+ *     the plan's layout: each workspace fill and checkpoint-slot copy lies inside one
+ *     sub-buffer, a step's levels lie in 1..nsteps, its tiles belong to the current shot group,
+ *     restore and store slots exist, and 3D injection ranges lie inside their table.  A failed
+ *     check returns INTERNAL before that launch (work already enqueued stays enqueued).  Host
+ *     cost only (about a microsecond per launch and tile list); no synchronisation.
+ * With INPUTS or OUTPUTS set the compute calls synchronise the stream once per screened group of
+ * arrays and must not be captured into a graph.  Each screened element is read once more from
+ * HBM.  Errors: INVALID_ARG, HIP (counter allocation on first use). */
+enum { AWE_CHECK_INPUTS = 1, AWE_CHECK_OUTPUTS = 2, AWE_CHECK_LAUNCHES = 4 };
 awe_status awe_plan_set_checks(awe_plan* plan, int32_t flags);
 
 /* Bytes of device workspace every compute call on this plan needs (256-byte aligned

@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libawe.so")
 
 AWE_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "CFL", 4: "GEOMETRY", 5: "WORKSPACE",
-          6: "STATE", 7: "HIP", 8: "NONFINITE"}
+          6: "STATE", 7: "HIP", 8: "NONFINITE", 9: "INTERNAL"}
 AWE_ERR_CFL, AWE_ERR_WORKSPACE, AWE_ERR_NONFINITE = 3, 5, 8
 STORE_NONE, STORE_FULL, STORE_CHECKPOINT, STORE_AUTO, STORE_PROBED = 0, 1, 2, 3, 4
-CHECK_INPUTS, CHECK_OUTPUTS = 1, 2
+CHECK_INPUTS, CHECK_OUTPUTS, CHECK_LAUNCHES = 1, 2, 4
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 
 EXPORTS = ["awe_plan_create", "awe_plan_workspace_size", "awe_plan_destroy", "awe_forward",
@@ -292,8 +292,9 @@ class Plan:
 
     def set_checks(self, flags: int):
         """Screen the inputs (CHECK_INPUTS: non-finite values -> NONFINITE, m above the vmax bound ->
-        CFL) and / or the outputs (CHECK_OUTPUTS) of every later compute call; 0 turns it off.
-        Screening synchronises the stream."""
+        CFL) and / or the outputs (CHECK_OUTPUTS) of every later compute call, and / or check every
+        launch's ranges against the plan's layout on the host (CHECK_LAUNCHES -> INTERNAL); 0
+        turns it off.  Screening synchronises the stream."""
         check(lib().awe_plan_set_checks(self._h, int(flags)))
 
     def __del__(self):

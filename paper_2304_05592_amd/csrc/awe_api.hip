@@ -475,6 +475,79 @@ awe_status check_ws(const awe_plan* P, void* ws, size_t ws_bytes) {
   return AWE_OK;
 }
 
+// ---- host-side launch checks (AWE_CHECK_LAUNCHES): before a launch, the byte ranges and
+// indices the host computed for it are checked against the plan's workspace layout and tables.
+
+// [begin, end) of every workspace sub-buffer.
+std::vector<std::pair<long long, long long>> sub_buffers(const awe_plan* P) {
+  std::vector<std::pair<long long, long long>> r;
+  auto add = [&](long long off, long long n) {
+    if (off >= 0 && n > 0) r.emplace_back(off, off + n);
+  };
+  add(0, (long long)awe::kReduceBlocks * 8);
+  for (size_t w = 0; w < P->wins.size(); ++w) add(P->win_coef[w], P->wins[w].npts * 4);
+  const awe_storage& st = P->store;
+  const int esz = st.prec == AWE_PREC_FP32 ? 4 : 2;
+  for (const ShotDev& d : P->sd) {
+    add(d.fld, (long long)awe::kFieldBufs * d.npts * 4);
+    add(d.acc, d.npts * 8);
+    if (st.mode == AWE_STORE_FULL) {
+      add(d.store, (long long)d.nt * d.npts * esz);
+      add(d.scale, (long long)d.nt * awe::kScaleSlots * 4);
+    } else if (st.mode == AWE_STORE_CHECKPOINT) {
+      add(d.store, (long long)st.nslots * 2 * d.npts * esz);
+      add(d.scale, (long long)st.nslots * 2 * 4);
+    } else if (st.mode == AWE_STORE_PROBED) {
+      add(d.store, (long long)st.nslots * 2 * d.npts * 8);
+    }
+  }
+  return r;
+}
+
+awe_status launch_fault(const std::string& what) {
+  return fail(AWE_ERR_INTERNAL, "launch check: " + what);
+}
+
+// [off, off + n) must lie inside one sub-buffer.
+awe_status check_range(const awe_plan* P, long long off, long long n, const char* what) {
+  if (!(P->checks & AWE_CHECK_LAUNCHES) || n <= 0) return AWE_OK;
+  for (const auto& [b, e] : sub_buffers(P))
+    if (off >= b && off + n <= e) return AWE_OK;
+  return launch_fault(std::string(what) + ": bytes [" + std::to_string(off) + ", " + std::to_string(off + n) +
+                      ") are not inside one workspace sub-buffer");
+}
+
+awe_status fill(const awe_plan* P, unsigned char* ws, long long off, long long n, hipStream_t s, const char* what) {
+  awe_status st = check_range(P, off, n, what);
+  if (st != AWE_OK) return st;
+  AWE_HIP(awe::launch_fill(ws, off, n, s));
+  return AWE_OK;
+}
+
+// A step launch producing levels [lo, hi] of the current group on tiling T.
+awe_status check_step(const awe_plan* P, const Tiling& T, const awe::StepArgs& a, int lo, int hi, const char* what) {
+  if (!(P->checks & AWE_CHECK_LAUNCHES)) return AWE_OK;
+  const std::string id = std::string(what) + " levels " + std::to_string(lo) + ".." + std::to_string(hi);
+  if (lo < 1 || hi > P->nsteps || lo > hi) return launch_fault(id + ": outside 1.." + std::to_string(P->nsteps));
+  const int g = P->cur;
+  if (g < 0 || g >= (int)P->g_nshot.size()) return launch_fault(id + ": no current shot group");
+  if (a.tile_base != T.g_tile0[g] || a.ntiles < 0 || a.tile_base + a.ntiles > T.g_tile0[g + 1])
+    return launch_fault(id + ": tiles outside the group's range");
+  if (a.shot_base != P->g_shot0[g]) return launch_fault(id + ": wrong first shot of the group");
+  std::vector<char> in_group(P->nshot, 0);
+  for (int i = 0; i < P->g_nshot[g]; ++i) in_group[P->order[P->g_shot0[g] + i]] = 1;
+  for (int t = a.tile_base; t < a.tile_base + a.ntiles; ++t) {
+    const int sh = T.tiles[t].shot;
+    if (sh < 0 || sh >= P->nshot || !in_group[sh]) return launch_fault(id + ": tile of a shot outside the group");
+  }
+  const bool ckpt = P->store.mode == AWE_STORE_CHECKPOINT;
+  if (a.rs_level != awe::kNoLevel && (!ckpt || a.rs_slot < 0 || a.rs_slot >= P->store.nslots))
+    return launch_fault(id + ": restore-by-reference slot " + std::to_string(a.rs_slot) + " out of range");
+  if (a.st_slot >= 0 && (!ckpt || a.st_slot >= P->store.nslots))
+    return launch_fault(id + ": fused store slot " + std::to_string(a.st_slot) + " out of range");
+  return AWE_OK;
+}
+
 awe_status prepare(awe_plan* P, const float* m, void* ws, bool zero_fwd, bool zero_adj, hipStream_t s) {
   unsigned char* w = static_cast<unsigned char*>(ws);
   for (size_t i = 0; i < P->wins.size(); ++i) {
@@ -484,8 +557,10 @@ awe_status prepare(awe_plan* P, const float* m, void* ws, bool zero_fwd, bool ze
   }
   for (int i = 0; i < P->nshot; ++i) {
     const ShotDev& d = P->sd[i];
-    if (zero_fwd) AWE_HIP(awe::launch_fill(w, d.fld, 4 * d.npts * 4, s));
-    if (zero_adj) AWE_HIP(awe::launch_fill(w, d.fld + 4 * d.npts * 4, 4 * d.npts * 4, s));
+    awe_status st;
+    if (zero_fwd && (st = fill(P, w, d.fld, 4 * d.npts * 4, s, "forward buffers")) != AWE_OK) return st;
+    if (zero_adj && (st = fill(P, w, d.fld + 4 * d.npts * 4, 4 * d.npts * 4, s, "adjoint buffers")) != AWE_OK)
+      return st;
   }
   return AWE_OK;
 }
@@ -521,6 +596,7 @@ void set_group(const awe_plan* P, const Tiling& T, awe::StepArgs& a, int n) {
 awe_status step_fwd(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t s) {
   set_group(P, P->fw, a, n);
   if (a.ntiles <= 0) return AWE_OK;
+  if (awe_status st = check_step(P, P->fw, a, n, n, "forward step")) return st;
   ProfScope ps(P, 0, s);
   if (P->ndim == 2) AWE_HIP(awe::launch_fwd2d(a, P->fw.tz, store, s));
   else AWE_HIP(awe::launch_fwd3d(a, P->fw.ty, P->fw.bz, store, s));
@@ -530,6 +606,10 @@ awe_status step_fwd(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_t
 awe_status step_adj(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
   set_group(P, P->rv, a, n);
   if (a.ntiles <= 0) return AWE_OK;
+  if (awe_status st = check_step(P, P->rv, a, n, n, "adjoint step")) return st;
+  if (P->ndim == 3 && (P->checks & AWE_CHECK_LAUNCHES) &&
+      P->rv.g_inj0[P->cur] + P->rv.g_ninj[P->cur] > (int)P->rv.inj_pts.size())
+    return launch_fault("receiver injection: touched points outside the table");
   ProfScope ps(P, 1, s);
   if (P->ndim == 2) {
     AWE_HIP(awe::launch_adj2d(a, P->rv.tz, s));
@@ -545,6 +625,7 @@ awe_status step_fwd2(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_
   set_group(P, P->fw, a, n + 1);
   a.step = n;
   if (a.ntiles <= 0) return AWE_OK;
+  if (awe_status st = check_step(P, P->fw, a, n, n + 1, "two-level forward step")) return st;
   ProfScope ps(P, 0, s);
   AWE_HIP(awe::launch_fwd2d2(a, P->fw.tz, store, s));
   return AWE_OK;
@@ -553,6 +634,7 @@ awe_status step_fwd2(awe_plan* P, awe::StepArgs& a, int n, int store, hipStream_
 awe_status step_adj2(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
   set_group(P, P->rv, a, n);
   if (a.ntiles <= 0) return AWE_OK;
+  if (awe_status st = check_step(P, P->rv, a, n - 1, n, "two-level adjoint step")) return st;
   ProfScope ps(P, 1, s);
   AWE_HIP(awe::launch_adj2d2(a, P->rv.tz, s));
   return AWE_OK;
@@ -599,9 +681,21 @@ awe_status adjoint_loop(awe_plan* P, awe::StepArgs& a, hipStream_t s) {
 awe_status run_slot(awe_plan* P, awe::StepArgs& a, int slot, int state, int dir, hipStream_t s) {
   const int g = P->cur, nsh = P->g_nshot[g];
   a.shot_base = P->g_shot0[g];
+  if (P->checks & AWE_CHECK_LAUNCHES) {
+    if (P->store.mode != AWE_STORE_CHECKPOINT || slot < 0 || slot >= P->store.nslots || state < 0 ||
+        state > P->nsteps)
+      return launch_fault("slot copy: slot " + std::to_string(slot) + " state " + std::to_string(state) + " out of range");
+    const int esz = P->store.prec == AWE_PREC_FP32 ? 4 : 2;
+    for (int i = 0; i < nsh; ++i) {
+      const ShotDev& d = P->sd[P->order[a.shot_base + i]];
+      if (awe_status st = check_range(P, d.store + (long long)slot * 2 * d.npts * esz, 2 * d.npts * esz, "slot copy"))
+        return st;
+    }
+  }
   if (dir == 0 && P->store.prec != AWE_PREC_FP32) {
     for (int i = 0; i < nsh; ++i)
-      AWE_HIP(awe::launch_fill(a.ws, P->sd[P->order[a.shot_base + i]].scale + 8LL * slot, 8, s));
+      if (awe_status st = fill(P, a.ws, P->sd[P->order[a.shot_base + i]].scale + 8LL * slot, 8, s, "slot scales"))
+        return st;
     AWE_HIP(awe::launch_absmax(a, nsh, slot, state, s));
   }
   AWE_HIP(awe::launch_slot(a, nsh, slot, state, dir, s));
@@ -662,7 +756,7 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
         if (x < 0) {
           for (int i = 0; i < P->g_nshot[P->cur]; ++i) {
             const ShotDev& d = P->sd[P->order[P->g_shot0[P->cur] + i]];
-            AWE_HIP(awe::launch_fill(fa.ws, d.fld, 4 * d.npts * 4, s));
+            if (awe_status st = fill(P, fa.ws, d.fld, 4 * d.npts * 4, s, "forward buffers (zero state)")) return st;
           }
           set_rs(awe::kNoLevel, 0);
         } else if (by_ref) {
@@ -850,6 +944,7 @@ const char* awe_status_string(awe_status s) {
     case AWE_ERR_STATE: return "no kept forward wavefield";
     case AWE_ERR_HIP: return "HIP runtime error";
     case AWE_ERR_NONFINITE: return "value not finite";
+    case AWE_ERR_INTERNAL: return "internal launch check failed";
   }
   return "unknown status";
 }
@@ -1300,9 +1395,9 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
 
 awe_status awe_plan_set_checks(awe_plan* P, int32_t flags) {
   if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
-  if (flags < 0 || flags > (AWE_CHECK_INPUTS | AWE_CHECK_OUTPUTS))
-    return fail(AWE_ERR_INVALID_ARG, "flags must combine AWE_CHECK_INPUTS and AWE_CHECK_OUTPUTS");
-  if (flags && !P->chk_dev) AWE_HIP(hipMalloc(&P->chk_dev, 2 * kMaxScreened * sizeof(unsigned long long)));
+  if (flags < 0 || flags > (AWE_CHECK_INPUTS | AWE_CHECK_OUTPUTS | AWE_CHECK_LAUNCHES))
+    return fail(AWE_ERR_INVALID_ARG, "flags must combine AWE_CHECK_INPUTS, AWE_CHECK_OUTPUTS, AWE_CHECK_LAUNCHES");
+  if ((flags & (AWE_CHECK_INPUTS | AWE_CHECK_OUTPUTS)) && !P->chk_dev) AWE_HIP(hipMalloc(&P->chk_dev, 2 * kMaxScreened * sizeof(unsigned long long)));
   P->checks = flags;
   return AWE_OK;
 }
@@ -1437,7 +1532,8 @@ awe_status awe_forward(awe_plan* P, const float* m, const float* q, float* d, in
              : P->store.prec == AWE_PREC_BF16 ? awe::kStoreBF16 : awe::kStoreFP16;
       if (kind != awe::kStoreF32)
         for (int i = 0; i < P->nshot; ++i)
-          AWE_HIP(awe::launch_fill(a.ws, P->sd[i].scale, (long long)P->sd[i].nt * awe::kScaleSlots * 4, s));
+          if ((st = fill(P, a.ws, P->sd[i].scale, (long long)P->sd[i].nt * awe::kScaleSlots * 4, s, "level scales")) != AWE_OK)
+            return st;
     }
     for (P->cur = 0; P->cur < G; ++P->cur)
       if ((st = forward_loop(P, a, kind, s)) != AWE_OK) return st;
@@ -1466,10 +1562,11 @@ awe_status awe_backward(awe_plan* P, const float* m, const float* q, const float
   unsigned char* w = static_cast<unsigned char*>(ws);
   for (int i = 0; i < P->nshot; ++i) {
     const ShotDev& d = P->sd[i];
-    AWE_HIP(awe::launch_fill(w, d.fld + 4 * d.npts * 4, 4 * d.npts * 4, s));
+    if ((st = fill(P, w, d.fld + 4 * d.npts * 4, 4 * d.npts * 4, s, "adjoint buffers")) != AWE_OK) return st;
   }
   if (g)
-    for (int i = 0; i < P->nshot; ++i) AWE_HIP(awe::launch_fill(w, P->sd[i].acc, P->sd[i].npts * 8, s));
+    for (int i = 0; i < P->nshot; ++i)
+      if ((st = fill(P, w, P->sd[i].acc, P->sd[i].npts * 8, s, "accumulator")) != AWE_OK) return st;
   awe::StepArgs fa = base_args(P, P->fw, ws);
   fa.q = q;
   awe::StepArgs aa = base_args(P, P->rv, ws);
@@ -1539,7 +1636,7 @@ awe_status awe_gradient_probed(awe_plan* P, const float* m, const float* q, cons
   if ((st = prepare(P, m, ws, true, true, s)) != AWE_OK) return st;
   unsigned char* wsb = static_cast<unsigned char*>(ws);
   for (int i = 0; i < P->nshot; ++i)
-    AWE_HIP(awe::launch_fill(wsb, P->sd[i].store, (long long)r * 2 * P->sd[i].npts * 8, s));
+    if ((st = fill(P, wsb, P->sd[i].store, (long long)r * 2 * P->sd[i].npts * 8, s, "probe sums")) != AWE_OK) return st;
   // forward sweep: B_j += C[j][k] (u^k - 2u^{k-1} + u^{k-2}) in the step kernels
   awe::StepArgs a = base_args(P, P->fw, ws);
   a.q = q;

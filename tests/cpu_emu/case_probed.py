@@ -42,6 +42,7 @@ def main():
                          ("identity", W.probe_table("identity", max_nt))):
         r = C.shape[0]
         plan = D.EmuPlan(lib, wl, storage=B.Storage(B.STORE_PROBED, r))
+        plan.set_checks(4)   # host-side launch checks
         m = plan.pack([wl.m(w) for w in range(wl.nwindow)])
         q = plan.pack([wl.q(i) for i in range(wl.nshot)])
         dd = plan.pack(dds)

@@ -27,6 +27,7 @@ def main():
     for tag, st in (("full", B.Storage(B.STORE_FULL)), ("ckpt_fp32", B.Storage(B.STORE_CHECKPOINT, 3)),
                     ("ckpt_bf16", B.Storage(B.STORE_CHECKPOINT, 3, B.PREC_BF16))):
         plan = D.EmuPlan(lib, wl, storage=st)
+        plan.set_checks(int(os.environ.get("CASE_CHECKS", "0")))   # 4: host-side launch checks
         g, v, d = plan.gradient(plan.pack([wl.m(0)]), plan.pack([wl.q(0)]), plan.pack([dd]), v=True, d=True)
         gs[tag] = (g, v, d)
         del plan

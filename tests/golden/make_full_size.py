@@ -13,13 +13,15 @@ shots in ascending order) and a seeded sample of the outputs is stored:
   c3_autograd_full.npz  shots 0 and 31 of the 32 c3_autograd shots on the 592 x 1104 grid,
                       5191 samples per shot (a stated subset: the oracle takes minutes per
                       shot at this size)
+  c9_probed_full.npz  the probed gradient of shots 0 and 8 of the c2_grad survey with
+                      PROBES Rademacher probes (table seed PROBE_SEED, columns = local levels)
 
 Gradient samples are flat indices into each window's computational grid (the
 same number per window); trace samples are every TIME_STRIDE-th time sample of
 every REC_STRIDE-th receiver.
 
 Run from the repository root:
-    python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop] [c2_born] [c3_autograd]
+    python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop] [c2_born] [c3_autograd] [c9_probed]
 The 2D sets take minutes on 8 cores, the 3D crop about half an hour.
 """
 from __future__ import annotations
@@ -39,7 +41,8 @@ RESIDUAL_SEED = 1000      # synthetic residual of shot s uses seed RESIDUAL_SEED
 SAMPLE_SEED = 20230411
 N_GRAD_SAMPLES = 4096
 REC_STRIDE = {"c2_grad": 40, "c4_uneven": 64, "c5_crop": 64, "c3_autograd": 64}
-SHOT_SUBSET = {"c3_autograd": (0, 31)}   # shots whose full-size oracle results are stored
+SHOT_SUBSET = {"c3_autograd": (0, 31), "c9_probed": (0, 8)}   # shots whose full-size oracle results are stored
+PROBES, PROBE_SEED = 8, 1
 TIME_STRIDE = 32
 SEGMENT = 64              # oracle recomputation segment (result does not depend on it)
 
@@ -62,6 +65,43 @@ def _shot(args):
                       return_traces=True, **kw)
     print(f"  {name} shot {s}: {time.perf_counter() - t0:.1f} s", flush=True)
     return s, g, d
+
+
+def probe_table(nt):
+    import workloads as W
+    return W.probe_table("rademacher", nt, r=PROBES, seed=PROBE_SEED)
+
+
+def _probed_shot(s):
+    import oracle as O
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    sh = wl.shots[s]
+    C, sw = probe_table(max(x.nt for x in wl.shots))
+    t0 = time.perf_counter()
+    g = O.gradient_probed(wl.m(sh.window, background=True), wl.q(s), residual(wl, s),
+                          C=C[:, :sh.nt].astype(np.float64), s=sw, src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt,
+                          nbl=wl.nbl, vref=wl.vmax)
+    print(f"  c9_probed shot {s}: {time.perf_counter() - t0:.1f} s", flush=True)
+    return s, g
+
+
+def make_probed(workers):
+    import workloads as W
+    wl = W.make_config("c2_grad")
+    shots = SHOT_SUBSET["c9_probed"]
+    with mp.get_context("spawn").Pool(min(workers, len(shots))) as pool:
+        res = sorted(pool.map(_probed_shot, shots), key=lambda r: r[0])
+    g = np.zeros(wl.comp_shape(0))
+    for _, g_s in res:
+        g = g + g_s
+    rng = np.random.default_rng(SAMPLE_SEED)
+    gidx = np.sort(rng.choice(g.size, size=N_GRAD_SAMPLES, replace=False))
+    path = os.path.join(ROOT, "tests", "golden", "c9_probed_full.npz")
+    np.savez_compressed(path, shots=np.asarray(shots, dtype=np.int64), probes=PROBES, probe_seed=PROBE_SEED,
+                        grad_index_0=gidx.astype(np.int64), grad_value_0=g.ravel()[gidx],
+                        grad_norm=np.linalg.norm(g))
+    print(f"wrote {path}", flush=True)
 
 
 def born_perturbation(wl, w=0):
@@ -138,7 +178,12 @@ def main():
     workers = min(8, len(os.sched_getaffinity(0)))
     for name in names:
         t0 = time.perf_counter()
-        make_born(workers) if name == "c2_born" else make(name, workers)
+        if name == "c2_born":
+            make_born(workers)
+        elif name == "c9_probed":
+            make_probed(workers)
+        else:
+            make(name, workers)
         print(f"{name}: {time.perf_counter() - t0:.1f} s", flush=True)
 
 

@@ -8,9 +8,12 @@ against the FP64 result.  Calls only the oracle and the seeded input generators:
     of tests/golden/c2_born_full.npz, and their forward traces F(m0) q vs
     tests/golden/c2_grad_full.npz;
   * the F and J dot tests of the 2-shot small 2D survey with the GPU test's seeded vectors:
-    float32 operators, FP64 inner products, |a - b| / max(|a|, |b|).
+    float32 operators, FP64 inner products, |a - b| / max(|a|, |b|);
+  * the probed gradient of c2_grad shots 0 and 8 with 8 Rademacher probes (float32 oracle vs
+    the FP64 samples of tests/golden/c9_probed_full.npz).
 
-Run from the repository root:  python tests/golden/measure_fp32_floor.py
+Run from the repository root:  python tests/golden/measure_fp32_floor.py [c2_grad] [dots] [c9_probed]
+(no argument: all; a subset updates only its entries of the record).
 """
 from __future__ import annotations
 
@@ -95,12 +98,47 @@ def dot_floor():
     return out
 
 
-def main():
+def _probed(s):
+    import oracle as O
+    import workloads as W
+    spec = __import__("importlib.util").util.spec_from_file_location("mfs", os.path.join(GOLD, "make_full_size.py"))
+    G = __import__("importlib.util").util.module_from_spec(spec)
+    spec.loader.exec_module(G)
+    wl = W.make_config("c2_grad")
+    sh = wl.shots[s]
+    C, sw = G.probe_table(max(x.nt for x in wl.shots))
     t0 = time.perf_counter()
-    rec = {"what": "float32-emulated oracle against the FP64 oracle (rel-L2) and its own dot tests",
-           "c2_grad": c2_floor(), "small_2d_dot_tests": dot_floor()}
-    rec["seconds"] = round(time.perf_counter() - t0, 1)
+    g = O.gradient_probed(wl.m(sh.window, background=True), wl.q(s), G.residual(wl, s),
+                          C=C[:, :sh.nt].astype(np.float64), s=sw, src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt,
+                          nbl=wl.nbl, vref=wl.vmax, dtype=np.float32)
+    print(f"  probed shot {s}: {time.perf_counter() - t0:.1f} s", flush=True)
+    return s, g
+
+
+def probed_floor():
+    gold = np.load(os.path.join(GOLD, "c9_probed_full.npz"))
+    shots = tuple(int(s) for s in gold["shots"])
+    with mp.get_context("spawn").Pool(len(shots)) as pool:
+        res = sorted(pool.map(_probed, shots), key=lambda r: r[0])
+    g = sum(r[1].astype(np.float64) for r in res)
+    return {"shots": list(shots), "probes": int(gold["probes"]),
+            "gradient_rel_l2": _rel(g.ravel()[gold["grad_index_0"]], gold["grad_value_0"])}
+
+
+def main():
+    parts = sys.argv[1:] or ["c2_grad", "dots", "c9_probed"]
     path = os.path.join(GOLD, "fp32_floor.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    rec["what"] = "float32-emulated oracle against the FP64 oracle (rel-L2) and its own dot tests"
+    t0 = time.perf_counter()
+    if "c2_grad" in parts:
+        rec["c2_grad"] = c2_floor()
+    if "dots" in parts:
+        rec["small_2d_dot_tests"] = dot_floor()
+    if "c9_probed" in parts:
+        rec["c9_probed"] = probed_floor()
+    rec["seconds_last_run"] = round(time.perf_counter() - t0, 1)
+    rec.pop("seconds", None)
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))

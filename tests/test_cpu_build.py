@@ -54,8 +54,10 @@ def test_launch_rewrite_keeps_template_kernels_and_arguments():
 
 
 def test_3d_checkpointed_gradient_on_the_cpu_build(emu_lib):
+    """FULL, CHECKPOINT FP32 and CHECKPOINT BF16 3D gradients on the CPU build, with the library's
+    host-side launch checks on (every fill, slot copy and step range checked against the layout)."""
     import driver
-    r = driver.run([os.path.join(EMU, "case_small.py")], emu_lib, {"CASE_T": "20"}, timeout=900)
+    r = driver.run([os.path.join(EMU, "case_small.py")], emu_lib, {"CASE_T": "20", "CASE_CHECKS": "4"}, timeout=900)
     assert r.returncode == 0, r.stderr[-4000:]
     res = json.loads(r.stdout.strip().splitlines()[-1])
     print(res)

@@ -95,3 +95,27 @@ def test_autotune_cache_is_written_and_reused(tmp_path, monkeypatch):
     assert ms2 == 42.5
     assert (tiles2["tz"], tiles2["fusion"], tiles2["adjoint"]["tz"]) == (8, 1, 64)
     assert torch.equal(p2.gradient(m, q, dd)[0], g_ref)
+
+
+@pytest.mark.parametrize("storage", ["checkpoint2d", "full3d"])
+def test_launch_checks_pass_and_change_nothing(storage):
+    """With the host-side launch checks on, a checkpointed 2D gradient (slot copies, restores
+    by reference, fused stores, two shot groups) and a 3D FULL gradient (receiver injection)
+    pass every check and give the same bits as without them."""
+    if storage == "checkpoint2d":
+        wl = W.small_2d(windows=[70, 130, 96], T_per_shot=[160.0, 100.0, 130.0])
+        st = A.Storage(A.STORE_CHECKPOINT, 3)
+    else:
+        wl = W.small_3d(n=(26, 20, 30), nbl=8, T=60.0, nrec_side=6)
+        st = A.Storage(A.STORE_FULL)
+    dds = [W.synthetic_residual(s.nt, len(s.rec), wl.dt, wl.f0, 3 + i) for i, s in enumerate(wl.shots)]
+    plan = make_plan(wl, storage=st)
+    if storage == "checkpoint2d":
+        plan.set_groups(2)
+    m, q = gpu_inputs(wl, plan)
+    dd = plan.pack(dds, "d")
+    ref = plan.gradient(m, q, dd, v=True, d=True)
+    plan.set_checks(A.CHECK_LAUNCHES)
+    got = plan.gradient(m, q, dd, v=True, d=True)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(got, ref))

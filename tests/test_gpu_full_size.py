@@ -182,3 +182,34 @@ def test_c3_autograd_full_size():
         errs.append(abs(fd - ad) / abs(fd))
     print("c3_autograd finite-difference relative errors:", ", ".join(f"{e:.2e}" for e in errs), flush=True)
     assert max(errs) <= 1e-2
+
+
+@pytest.mark.gpu
+def test_c9_probed_full_size():
+    """The probed gradient at full size: shots 0 and 8 of the c2_grad survey (the stated subset
+    whose oracle results are stored) on the 421 x 730 grid, nt 3638, with 8 Rademacher probes
+    of the time axis, against the oracle's gradient_probed at 4096 sampled points.
+    The launch shape changes no bit of this gradient (test_gpu_probed), so the default shape
+    stands for the one the benchmark picks.
+
+    Bar 1.5e-4: every product A_j B_j of the estimate is a sum over all 3638 levels of signed
+    field values, so the FP32 rounding of the fields enters it without the cancellation that
+    the exact inner product sum_k w^k b^k enjoys; the float32-emulated oracle's own estimate of
+    the same shots is 2.0e-4 from the FP64 one (tests/golden/fp32_floor.json), so 1e-5 lies
+    below the float32 floor of this estimator, and the bar is set under that floor."""
+    import torch
+    torch.cuda.empty_cache()
+    gold = _fixture("c9_probed")
+    wl = W.make_config("c2_grad")
+    shots = [int(s) for s in gold["shots"]]
+    r = int(gold["probes"])
+    plan = make_plan(wl, A.Storage(A.STORE_PROBED, r), shots=shots)
+    m = plan.pack([wl.m(0, background=True)], "m")
+    q = plan.pack([wl.q(s) for s in shots], "q")
+    dd = plan.pack([G.residual(wl, s) for s in shots], "d")
+    C, sw = G.probe_table(max(wl.shots[s].nt for s in shots))
+    g = plan.gradient_probed(m, q, dd, C, sw)[0]
+    got = plan.unpack(g, "m")[0].ravel()[gold["grad_index_0"]]
+    err = _rel(got, gold["grad_value_0"])
+    print(f"c9_probed: gradient rel-L2 {err:.2e} ({got.size} samples, {r} probes, shots {shots})", flush=True)
+    assert np.isfinite(got).all() and err <= 1.5e-4
