@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_grad",
-                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse", "c9_probed",
+                    choices=["c1_fwd", "c2_grad", "c3_autograd", "c4_uneven", "c5_3d", "c6_timelapse", "c9_probed", "c9_probed_3d",
                              "c7_timelapse_rock", "c8_born"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", type=int, default=8, help="c9_probed: time-axis probes (1..64)")
@@ -826,14 +826,15 @@ def bench_c8(args):
         "kernel_timing": timing, "dd_norm": float(dd.norm().item())})
 
 
-def bench_c9(args):
-    """Probed gradient of the c2_grad survey (16 shots): no stored wavefield, r Rademacher probes
-    of the time axis accumulated in FP64 by the forward and adjoint step kernels, the estimate
-    formed per point at the end.  One call captured into a HIP graph and replayed."""
+def bench_c9(args, base="c2_grad"):
+    """Probed gradient of the c2_grad survey (16 shots) or of the 3D c5_3d shot: no stored
+    wavefield, r Rademacher probes of the time axis accumulated in FP64 by the forward and adjoint
+    step kernels, the estimate formed per point at the end.  One call captured into a HIP graph
+    and replayed."""
     import torch
     import paper_2304_05592_amd as A
     import workloads as W
-    wl = W.make_config("c2_grad")
+    wl = W.make_config(base)
     r = args.probes
     shots = range(wl.nshot)
     plan = make_plan(wl, A.Storage(A.STORE_PROBED, r), shots)
@@ -846,7 +847,7 @@ def bench_c9(args):
     Cd = torch.from_numpy(C).cuda()
     ws = plan.workspace()
     call = lambda: plan.gradient_probed(m, q, dd, Cd, sw, ws=ws)    # noqa: E731
-    tiles = choose_pass_tiles(plan, args, call)
+    tiles = choose_pass_tiles(plan, args, call) if wl.ndim == 2 else choose_tiles(plan, args, m, q, dd, ws)
     groups = plan.set_groups(args.groups)
     points, launch_points = points_of(wl, shots)
     launch_points //= groups
@@ -880,20 +881,23 @@ def bench_c9(args):
     prof = plan.profile_read()
     plan.profile_disable()
     kernels = kernel_table(prof, launch_points, {"forward": kind, "adjoint": kind})
-    names = {"forward": f"fwd2d step + {r} FP64 probe sums ({BYTES[('forward', kind)]} B/point)",
-             "adjoint": f"adj2d step + {r} FP64 probe sums ({BYTES[('adjoint', kind)]} B/point)"}
+    dim = f"{wl.ndim}d"
+    names = {"forward": f"fwd{dim} step + {r} FP64 probe sums ({BYTES[('forward', kind)]} B/point)",
+             "adjoint": f"adj{dim} step + {r} FP64 probe sums ({BYTES[('adjoint', kind)]} B/point)"}
     _, full_ws = A.select_storage(wl.ndim, wl.h, wl.dt, wl.nbl, wl.vmax, [wl.comp_shape(0)],
                                   [A.ShotGeometry(wl.shots[i].window, wl.shots[i].nt, wl.shots[i].src,
                                                   wl.shots[i].rec) for i in shots],
-                                  A.Storage(A.STORE_FULL), damp_vref=wl.vmax)
+                                  A.Storage(A.STORE_FULL, 0, A.PREC_FP32 if wl.ndim == 2 else A.PREC_BF16),
+                                  damp_vref=wl.vmax)
     return base_line(args, wl, points / sec / 1e9, sec, {
-        "metric": "Gpts/s probed gradient (batched, 16 shots)",
-        "config": {"workload": f"c9_probed: the c2_grad survey's gradient from {r} Rademacher probes of the "
+        "metric": f"Gpts/s probed gradient ({wl.nshot} shots)",
+        "config": {"workload": f"{args.config}: the {base} gradient from {r} Rademacher probes of the "
                                "time axis (no stored wavefield)",
                    "grid": list(wl.comp_shape(0)), "shots": wl.nshot, "nt": int(max_nt),
                    "storage": f"PROBED {r}", "batched": True, "graph": graph is not None, "tiles": tiles,
                    "shot_groups": groups},
         "workspace_bytes": plan.ws_bytes, "full_storage_workspace_bytes": full_ws,
+        "full_storage_precision": "fp32" if wl.ndim == 2 else "bf16",
         "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
         "kernel_timing": "HIP events around every launch of one eager call; value from graph replays",
         "g_norm": float(g.norm().item())})
@@ -1019,7 +1023,8 @@ def main():
         return
     fn = {"c1_fwd": bench_c1, "c2_grad": bench_c2, "c3_autograd": bench_c3, "c4_uneven": bench_c4,
           "c5_3d": bench_c5, "c6_timelapse": bench_c6,
-          "c7_timelapse_rock": bench_c7, "c8_born": bench_c8, "c9_probed": bench_c9}[args.config]
+          "c7_timelapse_rock": bench_c7, "c8_born": bench_c8, "c9_probed": bench_c9,
+          "c9_probed_3d": lambda a: bench_c9(a, "c5_3d")}[args.config]
     print(json.dumps(fn(args)), flush=True)
 
 

@@ -108,8 +108,7 @@ typedef enum {
                                when nslots > 0, at most the number of time steps); the plan
                                reports the choice (awe_plan_get_storage) */
   AWE_STORE_PROBED = 4      /* no wavefield kept: nslots = r probes of the time axis (1..64),
-                               2 r FP64 fields per shot; gradients by awe_gradient_probed
-                               (2D plans) */
+                               2 r FP64 fields per shot; gradients by awe_gradient_probed */
 } awe_store_mode;
 
 typedef enum {
@@ -202,7 +201,7 @@ awe_status awe_gradient(awe_plan* plan, const float* m, const float* q, const fl
  * (k = 1..nt-1, w the adjoint field); the forward sweep accumulates B_j = sum_k C[j][k] b^k, the
  * reverse sweep A_j = sum_k C[j][k] w^k (both FP64), and g = -(1/dt^2) sum_j s_j A_j B_j: exact
  * when C^T diag(s) C = I, unbiased when its expectation is I (Rademacher rows, s_j = 1/r).
- * Plan: 2D, storage AWE_STORE_PROBED with nslots = r.  C: device float [r][max_nt] row-major,
+ * Plan: storage AWE_STORE_PROBED with nslots = r (2D or 3D).  C: device float [r][max_nt] row-major,
  * column k weights every shot's local level k (max_nt = the largest nt of the plan; column 0 is
  * not used).  s: host double [r], read during the call.  g: FP64 as in awe_backward; v, d (may
  * be NULL) as in awe_gradient.  One call runs the forward and the reverse sweep; no forward is

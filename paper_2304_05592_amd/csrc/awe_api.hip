@@ -963,8 +963,6 @@ awe_status validate(const awe_problem* prob, const awe_storage* store) {
     return fail(AWE_ERR_INVALID_ARG, "bad storage mode");
   if (store->mode == AWE_STORE_PROBED && (store->nslots < 1 || store->nslots > awe::kMaxProbes))
     return fail(AWE_ERR_INVALID_ARG, "PROBED storage needs 1 <= nslots <= " + std::to_string(awe::kMaxProbes) + " probes");
-  if (store->mode == AWE_STORE_PROBED && prob->ndim == 3)
-    return fail(AWE_ERR_UNSUPPORTED, "PROBED storage is implemented for 2D plans only");
   if (store->prec < AWE_PREC_FP32 || store->prec > AWE_PREC_FP16)
     return fail(AWE_ERR_INVALID_ARG, "bad storage precision");
   if (store->mode == AWE_STORE_CHECKPOINT && store->nslots < 1)

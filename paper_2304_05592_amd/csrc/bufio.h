@@ -34,6 +34,14 @@ __device__ __forceinline__ brsrc make_rsrc(const void* base, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, kBufWord3);
 }
 
+// The same for a base and size that are wave-uniform although the compiler cannot prove it: a
+// resource it takes for divergent makes every access loop over the lanes' distinct resources.
+__device__ __forceinline__ brsrc make_rsrc_uniform(const void* base, int bytes) {
+  const unsigned long long b = reinterpret_cast<unsigned long long>(base);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b), hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return make_rsrc(reinterpret_cast<const void*>(((unsigned long long)hi << 32) | lo), __builtin_amdgcn_readfirstlane(bytes));
+}
+
 __device__ __forceinline__ float ldb(brsrc r, int voff, int soff) {
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }

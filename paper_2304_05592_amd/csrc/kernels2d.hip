@@ -73,10 +73,11 @@ __device__ __forceinline__ void side_offsets(int (&ho)[(SideHalo<NT, H, HW>::NH)
                                              int x0, int z0) {
 #pragma unroll
   for (int i = 0; i < SideHalo<NT, H, HW>::NH; ++i) {
+    // a slot past the last side cell takes the last cell (side_cell clamps): it loads and
+    // writes the same value as that cell's owner, so the staging needs no condition
     int r, c;
     side_cell<NT, H, HW>(i, &r, &c);
-    const bool used = (int)threadIdx.x + i * NT < SideHalo<NT, H, HW>::NE;
-    ho[i] = used ? col_off(x0 - HW + c, z0 - HW + r, nx, nz, px, 4) : kOOB;
+    ho[i] = col_off(x0 - HW + c, z0 - HW + r, nx, nz, px, 4);
   }
 }
 
@@ -85,37 +86,59 @@ __device__ __forceinline__ void side_offsets(int (&ho)[(SideHalo<NT, H, HW>::NH)
 // 256-byte row segment per wave (row offset wave-uniform, column offset cx = 4 x or kOOB), the
 // side cells follow from their precomputed offsets.  All loads are issued before the first LDS
 // write.
-template <int NT, int NW, int H, int HW, int W>
-__device__ __forceinline__ void stage(float (*L)[W], const Planes& f, int cx,
-                                      const int (&ho)[(SideHalo<NT, H, HW>::NH)], int z0) {
-  constexpr int NB = H / NW, NH = SideHalo<NT, H, HW>::NH, NE = SideHalo<NT, H, HW>::NE;
+// The staging is split in two: `issue` loads this thread's cells into registers, `commit` writes
+// them to LDS.  A kernel issues its tile before its other prefetches: loads complete in issue
+// order, so the LDS writes then wait for the tile's loads alone, not for every prefetch.
+template <int NT, int NW, int H, int HW>
+struct Staged {
+  static constexpr int NB = H / NW, NH = SideHalo<NT, H, HW>::NH;
+  float vb[NB], vh[NH];
+};
+
+template <int NT, int NW, int H, int HW>
+__device__ __forceinline__ void stage_issue(Staged<NT, NW, H, HW>& s, const Planes& f, int cx,
+                                            const int (&ho)[(SideHalo<NT, H, HW>::NH)], int z0) {
   // every wave stages whole rows: no row condition, so no branch separates the loads from
   // their use (a branch would make the compiler wait for all loads at its start)
   static_assert(H % NW == 0, "staged rows must split evenly over the waves");
+  const int wv = wave_id();
+#pragma unroll
+  for (int i = 0; i < Staged<NT, NW, H, HW>::NB; ++i) s.vb[i] = ldp(f, cx, z0 - HW + wv + i * NW);
+#pragma unroll
+  for (int i = 0; i < Staged<NT, NW, H, HW>::NH; ++i) s.vh[i] = ldp_at(f, ho[i]);
+}
+
+template <int NT, int NW, int H, int HW, int W>
+__device__ __forceinline__ void stage_commit(float (*L)[W], const Staged<NT, NW, H, HW>& s) {
   const int lane = threadIdx.x & 63, wv = wave_id();
-  float vb[NB], vh[NH];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) vb[i] = ldp(f, cx, z0 - HW + wv + i * NW);
+  for (int i = 0; i < Staged<NT, NW, H, HW>::NB; ++i) L[wv + i * NW][lane + HW] = s.vb[i];
+  // unconditional: threads past the last side cell write that cell's own value again (a
+  // condition here would let the compiler sink the load into it and wait for every load)
 #pragma unroll
-  for (int i = 0; i < NH; ++i) vh[i] = ldp_at(f, ho[i]);
-#pragma unroll
-  for (int i = 0; i < NB; ++i) L[wv + i * NW][lane + HW] = vb[i];
-#pragma unroll
-  for (int i = 0; i < NH; ++i) {
+  for (int i = 0; i < Staged<NT, NW, H, HW>::NH; ++i) {
     int r, c;
     side_cell<NT, H, HW>(i, &r, &c);
-    if ((int)threadIdx.x + i * NT < NE) L[r][c] = vh[i];
+    L[r][c] = s.vh[i];
   }
 }
 
 template <int TZ>
 using Side4 = SideHalo<T2<TZ>::NT, T2<TZ>::H, kHalo>;
 
-// The previous level with a 4-cell halo (one-step kernels).
+// The previous level with a 4-cell halo (one-step kernels): issue, then commit to LDS.
 template <int TZ>
-__device__ __forceinline__ void load_tile(float (*L)[T2<TZ>::W], const Planes& f, int cx,
-                                          const int (&ho)[Side4<TZ>::NH], int z0) {
-  stage<T2<TZ>::NT, T2<TZ>::NW, T2<TZ>::H, kHalo, T2<TZ>::W>(L, f, cx, ho, z0);
+using Tile4 = Staged<T2<TZ>::NT, T2<TZ>::NW, T2<TZ>::H, kHalo>;
+
+template <int TZ>
+__device__ __forceinline__ void tile_issue(Tile4<TZ>& t, const Planes& f, int cx, const int (&ho)[Side4<TZ>::NH],
+                                           int z0) {
+  stage_issue<T2<TZ>::NT, T2<TZ>::NW, T2<TZ>::H, kHalo>(t, f, cx, ho, z0);
+}
+
+template <int TZ>
+__device__ __forceinline__ void tile_commit(float (*L)[T2<TZ>::W], const Tile4<TZ>& t) {
+  stage_commit<T2<TZ>::NT, T2<TZ>::NW, T2<TZ>::H, kHalo, T2<TZ>::W>(L, t);
 }
 
 // Difference-form Laplacian at *p in an LDS array with row stride `stride` (x neighbours at
@@ -177,6 +200,10 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
   const int x = T.x0 + lane;
   const int cx = x < nx ? 4 * x : kOOB;
 
+  int ho[Side4<TZ>::NH];
+  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  Tile4<TZ> tile;
+  tile_issue<TZ>(tile, u1, cx, ho, T.z0);
   float pu2[RPT], pcf[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
@@ -184,9 +211,7 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
     pu2[i] = ldp(u2, cx, z);
     pcf[i] = ldp(cf, cx, z);
   }
-  int ho[Side4<TZ>::NH];
-  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
-  load_tile<TZ>(L, u1, cx, ho, T.z0);
+  tile_commit<TZ>(L, tile);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -300,6 +325,10 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
   const int cx8 = x < nx ? 8 * x : kOOB;
   const bool has_inj = T.inj_count > 0 && a.dd != nullptr;  // no residual: nothing to inject
 
+  int ho[Side4<TZ>::NH];
+  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  Tile4<TZ> tile;
+  tile_issue<TZ>(tile, w1, cx, ho, T.z0);
   float pw2[RPT], pcf[RPT], pu[RPT];
   double pacc[RPT];
 #pragma unroll
@@ -313,9 +342,7 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
     if (IACC) pacc[i] = ldp64(acc, cx8, z);
     if (has_inj) INJ[wv * RPT + i][lane] = 0.f;
   }
-  int ho[Side4<TZ>::NH];
-  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
-  load_tile<TZ>(L, w1, cx, ho, T.z0);
+  tile_commit<TZ>(L, tile);
   __syncthreads();
 
   if (has_inj) {
@@ -384,6 +411,11 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
   const int x = T.x0 + lane;
   const int cx = x < nx ? 4 * x : kOOB;
 
+  int ho[Side4<TZ>::NH];
+  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  Tile4<TZ> tu, td;
+  tile_issue<TZ>(tu, u1, cx, ho, T.z0);
+  tile_issue<TZ>(td, d1, cx, ho, T.z0);
   float pu2[RPT], pd2[RPT], pcf[RPT], pdm[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
@@ -393,10 +425,8 @@ __global__ __launch_bounds__(T2<TZ>::NT) void born2d_kernel(StepArgs a) {
     pcf[i] = ldp(cf, cx, z);
     pdm[i] = ldp(dm, cx, z);
   }
-  int ho[Side4<TZ>::NH];
-  side_offsets<T2<TZ>::NT, T2<TZ>::H, kHalo>(ho, nx, nz, px, T.x0, T.z0);
-  load_tile<TZ>(LU, u1, cx, ho, T.z0);
-  load_tile<TZ>(LD, d1, cx, ho, T.z0);
+  tile_commit<TZ>(LU, tu);
+  tile_commit<TZ>(LD, td);
   __syncthreads();
 
   if (a.d != nullptr) {
@@ -481,11 +511,19 @@ __device__ __forceinline__ bool ext_slot(int i, int* r, int* c) {
 template <int TZ>
 using Side8 = SideHalo<F2<TZ>::NT, F2<TZ>::H1, 2 * kHalo>;
 
-// Level n-1 with an 8-cell halo into LDS (two-step kernels).
+// Level n-1 with an 8-cell halo (two-step kernels): issue, then commit to LDS.
 template <int TZ>
-__device__ __forceinline__ void load_tile8(float (*L)[F2<TZ>::W1], const Planes& f, int cx,
-                                           const int (&ho)[Side8<TZ>::NH], int z0) {
-  stage<F2<TZ>::NT, F2<TZ>::NW, F2<TZ>::H1, 2 * kHalo, F2<TZ>::W1>(L, f, cx, ho, z0);
+using Tile8 = Staged<F2<TZ>::NT, F2<TZ>::NW, F2<TZ>::H1, 2 * kHalo>;
+
+template <int TZ>
+__device__ __forceinline__ void tile8_issue(Tile8<TZ>& t, const Planes& f, int cx, const int (&ho)[Side8<TZ>::NH],
+                                            int z0) {
+  stage_issue<F2<TZ>::NT, F2<TZ>::NW, F2<TZ>::H1, 2 * kHalo>(t, f, cx, ho, z0);
+}
+
+template <int TZ>
+__device__ __forceinline__ void tile8_commit(float (*L)[F2<TZ>::W1], const Tile8<TZ>& t) {
+  stage_commit<F2<TZ>::NT, F2<TZ>::NW, F2<TZ>::H1, 2 * kHalo, F2<TZ>::W1>(L, t);
 }
 
 // Plane offsets of this thread's first-step points that lie in the 4 + 4 side columns (the
@@ -542,7 +580,12 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   const int x = T.x0 + lane;
   const int cx = x < nx ? 4 * x : kOOB;
 
-  // prefetch level k-2 and coef of this thread's extended points, coef of its tile points
+  // the level k-1 tile first, then level k-2 and coef of this thread's extended points and coef
+  // of its tile points
+  int ho[Side8<TZ>::NH];
+  side_offsets<G::NT, G::H1, 2 * kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  Tile8<TZ> tile;
+  tile8_issue<TZ>(tile, u1, cx, ho, T.z0);
   int eo[G::NH];
   ext_offsets<TZ>(eo, nx, nz, px, T.x0, T.z0);
   float pm2[G::NS], pcf[G::NS], tcf[G::RPT];
@@ -553,9 +596,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   }
 #pragma unroll
   for (int i = 0; i < G::RPT; ++i) tcf[i] = ldp(cf, cx, T.z0 + wv * G::RPT + i);
-  int ho[Side8<TZ>::NH];
-  side_offsets<G::NT, G::H1, 2 * kHalo>(ho, nx, nz, px, T.x0, T.z0);
-  load_tile8<TZ>(L1, u1, cx, ho, T.z0);
+  tile8_commit<TZ>(L1, tile);
   __syncthreads();
 
   if (act1 && a.d != nullptr) {
@@ -668,6 +709,10 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   const bool inj1 = act1 && a.dd != nullptr && T.ext_count > 0;
   const bool inj2 = act2 && a.dd != nullptr && T.inj_count > 0;
 
+  int ho[Side8<TZ>::NH];
+  side_offsets<G::NT, G::H1, 2 * kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  Tile8<TZ> tile;
+  tile8_issue<TZ>(tile, w1, cx, ho, T.z0);
   int eo[G::NH];
   ext_offsets<TZ>(eo, nx, nz, px, T.x0, T.z0);
   float pm2[G::NS], pcf[G::NS], tcf[G::RPT], pu1[G::RPT], pu2[G::RPT];
@@ -690,9 +735,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
     }
     if (inj2) INJ2[wv * G::RPT + i][lane] = 0.f;
   }
-  int ho[Side8<TZ>::NH];
-  side_offsets<G::NT, G::H1, 2 * kHalo>(ho, nx, nz, px, T.x0, T.z0);
-  load_tile8<TZ>(L1, w1, cx, ho, T.z0);
+  tile8_commit<TZ>(L1, tile);
   __syncthreads();
 
   if (inj1 || inj2) {

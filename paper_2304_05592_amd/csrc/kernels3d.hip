@@ -181,12 +181,17 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
     return w;
   };
   // FULL store: level k (FP32) or level k-1 (16 bits, quantised once its scale is complete)
+  constexpr bool S16 = SK == kStoreBF16 || SK == kStoreFP16;
   const brsrc rst = SK == kStoreF32
       ? make_rsrc(reinterpret_cast<float*>(a.ws + S.store) + (long long)k * S.npts, (int)(nz * plane4))
-      : make_rsrc(reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts,
-                  (int)(nz * plane4 / 2));
-  float* scl = SK >= kStoreBF16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
-  const float inv_prev = SK >= kStoreBF16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
+      : make_rsrc_uniform(reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * S.npts,
+                          S16 ? (int)(nz * plane4 / 2) : 0);
+  float* scl = S16 ? reinterpret_cast<float*>(a.ws + S.scale) : nullptr;
+  const float inv_prev = S16 && k >= 2 ? inv_scale(level_scale(scl, k - 1)) : 0.f;
+  // probed gradient: the r FP64 sums B_j of this shot, and this level's coefficients
+  double* pb = SK == kStoreProbe ? reinterpret_cast<double*>(a.ws + S.store) : nullptr;
+  const float* pcol = SK == kStoreProbe ? a.probe_c + k : nullptr;
+  const long long plane_pts = (long long)px * ny;
   float lmax = 0.f;
 
   // per-lane plane offsets (fixed for the march): own columns (4- and 2-byte elements), ring
@@ -262,10 +267,17 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
       const float un = (u + u - pu2[c]) + incr;
       stb_nt(rout, un, cv[c], zo);
       if (SK == kStoreF32) stb_nt(rst, un, cv[c], zo);
-      if (SK >= kStoreBF16) {
+      if (S16) {
         // outside the grid u, u^{k-2} and coef read 0, so un = 0 there
         lmax = fmaxf(lmax, fabsf(un));
         if (k >= 2) stb16_nt(rst, enc16(u * inv_prev, SK == kStoreBF16), cv2[c], zo / 2);
+      }
+      if (SK == kStoreProbe && cv[c] != kOOB) {
+        // u^k - 2u^{k-1} + u^{k-2} = incr (increment form of the step)
+        const long long p = z * plane_pts + (cv[c] >> 2);
+        const double bv = (double)incr;
+        for (int jj = 0; jj < a.probe_r; ++jj)
+          pb[jj * S.npts + p] += (double)pcol[(long long)jj * a.probe_pitch] * bv;
       }
     }
     if (z + 1 < zend) {
@@ -290,7 +302,7 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
     plane(z, hA, qA, u2A, cfA, hB, qB, u2B, cfB);
     if (z + 1 < zend) plane(z + 1, hB, qB, u2B, cfB, hA, qA, u2A, cfA);
   }
-  if (SK >= kStoreBF16) block_max_to_slot(lmax, scl, k);
+  if (S16) block_max_to_slot(lmax, scl, k);
 }
 
 // ------------------------------------------------------------------------------ adjoint
@@ -315,10 +327,17 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
   const void* ubase = IMG == kImgBuffers ? (const void*)fwd_level(a, S, j)
                       : IMG == kImgFull32 ? (const void*)(reinterpret_cast<const float*>(a.ws + S.store) + (long long)j * S.npts)
                       : (const void*)(reinterpret_cast<const unsigned short*>(a.ws + S.store) + (long long)j * S.npts);
-  const Planes uj = planes(ubase, nz, IMG ? nz : 0, IMG >= kImgFullBF16 ? plane4 / 2 : plane4);
-  const float usc = IMG >= kImgFullBF16 ? level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j) : 1.f;
-  const Planes acc = planes(a.ws + S.acc, nz, IMG ? nz : 0, 2 * plane4);
-  const brsrc racc = make_rsrc(a.ws + S.acc, IMG ? (int)(nz * 2 * plane4) : 0);
+  constexpr bool I16 = IMG == kImgFullBF16 || IMG == kImgFullFP16;
+  constexpr bool IACC = IMG != kImgNone && IMG != kImgProbe;  // imaging into the FP64 accumulator
+  const Planes uj = planes(ubase, nz, IACC ? nz : 0, I16 ? plane4 / 2 : plane4);
+  const float usc = I16 ? level_scale(reinterpret_cast<const float*>(a.ws + S.scale), j) : 1.f;
+  const Planes acc = planes(a.ws + S.acc, nz, IACC ? nz : 0, 2 * plane4);
+  const brsrc racc = make_rsrc(a.ws + S.acc, IACC ? (int)(nz * 2 * plane4) : 0);
+  // probed gradient: the r FP64 sums A_j of this shot (after its B_j), and this level's
+  // coefficients; receiver injection adds its part afterwards (inj3d_kernel)
+  double* pa = IMG == kImgProbe ? reinterpret_cast<double*>(a.ws + S.store) + (long long)a.probe_r * S.npts : nullptr;
+  const float* pcol = IMG == kImgProbe ? a.probe_c + j : nullptr;
+  const long long plane_pts = (long long)px * ny;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int x = T.x0 + lane;
   const int zend = bzlen >= nz - T.z0 ? nz : T.z0 + bzlen;
@@ -333,17 +352,17 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
   for (int c = 0; c < NC; ++c) {
     const int y = T.y0 + g * NC + c;
     cv[c] = col_off(x, y, nx, ny, px, 4);
-    cvu[c] = col_off(x, y, nx, ny, px, IMG >= kImgFullBF16 ? 2 : 4);
+    cvu[c] = col_off(x, y, nx, ny, px, I16 ? 2 : 4);
     cv8[c] = col_off(x, y, nx, ny, px, 8);
   }
   ring_offsets<TY>(rv, nx, ny, px, T.x0, T.y0);
 
   // imaging inputs of one point: u^j and the accumulator (0 outside the grid)
   auto load_img = [&](int c, int z, float* u, double* ac) {
-    if (IMG >= kImgFullBF16) *u = dec16(ldp16_nt(uj, cvu[c], z), IMG == kImgFullBF16) * usc;
+    if (I16) *u = dec16(ldp16_nt(uj, cvu[c], z), IMG == kImgFullBF16) * usc;
     else if (IMG == kImgFull32) *u = ldp_nt(uj, cvu[c], z);
-    else if (IMG) *u = ldp(uj, cvu[c], z);
-    if (IMG) *ac = ldp64_nt(acc, cv8[c], z);
+    else if (IACC) *u = ldp(uj, cvu[c], z);
+    if (IACC) *ac = ldp64_nt(acc, cv8[c], z);
   };
 
   // Register state of plane z (queue of w^{j+1}, w^{j+2}, coef, u^j, accumulator); set A holds
@@ -407,8 +426,15 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
       const float eta = a.eta_dt * (float)(dx * dx + dy * dy + dz * dz);
       const float w = Q[c][4];
       const float incr = pcf[c] * (lap - eta * (w - pw2[c]));
-      stb_nt(rout, (w + w - pw2[c]) + incr, cv[c], zo);
-      if (IMG) stb64_nt(racc, pacc[c] + (double)pu[c] * (double)incr, cv8[c], 2 * zo);
+      const float wn = (w + w - pw2[c]) + incr;
+      stb_nt(rout, wn, cv[c], zo);
+      if (IACC) stb64_nt(racc, pacc[c] + (double)pu[c] * (double)incr, cv8[c], 2 * zo);
+      if (IMG == kImgProbe && cv[c] != kOOB) {
+        const long long p = z * plane_pts + (cv[c] >> 2);
+        const double wv64 = (double)wn;
+        for (int jj = 0; jj < a.probe_r; ++jj)
+          pa[jj * S.npts + p] += (double)pcol[(long long)jj * a.probe_pitch] * wv64;
+      }
     }
     if (z + 1 < zend) {
 #pragma unroll
@@ -451,7 +477,13 @@ __global__ void inj3d_kernel(StepArgs a, int first, int count) {
   const float add = reinterpret_cast<const float*>(a.ws + S.coef)[Pt.p] * s;
   float* w = fbuf(a.ws, S, adj_buf(j));
   w[Pt.p] += add;
-  if (a.image_src) {
+  if (a.image_src == kImgProbe) {
+    // A_j holds C[j][level] times the step's value before injection: add C[j][level] times the
+    // injected part (the sums are linear in w^j)
+    double* pa = reinterpret_cast<double*>(a.ws + S.store) + (long long)a.probe_r * S.npts;
+    for (int jj = 0; jj < a.probe_r; ++jj)
+      pa[jj * S.npts + Pt.p] += (double)a.probe_c[(long long)jj * a.probe_pitch + j] * (double)add;
+  } else if (a.image_src) {
     float u;
     if (a.image_src == kImgFull32)
       u = reinterpret_cast<const float*>(a.ws + S.store)[(long long)j * S.npts + Pt.p];
@@ -609,6 +641,7 @@ hipError_t fwd3d_ty(const StepArgs& a, int bz, int store, hipStream_t s) {
     case kStoreF32: fwd3d_kernel<TY, kStoreF32><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     case kStoreBF16: fwd3d_kernel<TY, kStoreBF16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     case kStoreFP16: fwd3d_kernel<TY, kStoreFP16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kStoreProbe: fwd3d_kernel<TY, kStoreProbe><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -622,6 +655,7 @@ hipError_t adj3d_ty(const StepArgs& a, int bz, hipStream_t s) {
     case kImgBuffers: adj3d_kernel<TY, kImgBuffers><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     case kImgFullBF16: adj3d_kernel<TY, kImgFullBF16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     case kImgFullFP16: adj3d_kernel<TY, kImgFullFP16><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
+    case kImgProbe: adj3d_kernel<TY, kImgProbe><<<a.ntiles, T3<TY>::NT, 0, s>>>(a, bz); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

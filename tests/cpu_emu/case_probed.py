@@ -61,6 +61,20 @@ def main():
             g2 = plan.gradient_probed(m, q, dd, C, s)[0]
             out["shape_invariant"] = bool(np.array_equal(g, g2))
         print(name, out, flush=True)
+    # 3D: one shot with receivers injected by the post-step pass (its part of A_j is added there)
+    w3 = W.small_3d(n=(26, 20, 30), nbl=8, T=40.0, nrec_side=6)
+    sh = w3.shots[0]
+    dd3 = W.synthetic_residual(sh.nt, len(sh.rec), w3.dt, w3.f0, 5)
+    for name, (C, s) in (("rademacher3d", W.probe_table("rademacher", sh.nt, r=4, seed=12)),):
+        plan = D.EmuPlan(lib, w3, storage=B.Storage(B.STORE_PROBED, C.shape[0]))
+        plan.set_checks(4)
+        g = plan.gradient_probed(plan.pack([w3.m(0)]), plan.pack([w3.q(0)]), plan.pack([dd3]), C, s)[0]
+        ref = O.gradient_probed(w3.m(0), w3.q(0), dd3, C=C.astype(np.float64), s=s, **shot_kwargs(w3, 0))
+        out[name] = rel(g.reshape(ref.shape), ref)
+        plan.set_tiles(32, 4, 7)
+        g2 = plan.gradient_probed(plan.pack([w3.m(0)]), plan.pack([w3.q(0)]), plan.pack([dd3]), C, s)[0]
+        out["shape_invariant3d"] = bool(np.array_equal(g, g2))
+        print(name, out, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -47,6 +47,7 @@ unsigned long long* xchg_slots();
 inline void __syncthreads() { ::emu::syncthreads(); }
 // lane 0's value of a wave-uniform operand (every lane holds the same value where it is used)
 inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
+inline unsigned __builtin_amdgcn_readfirstlane(unsigned v) { return v; }
 #define __builtin_amdgcn_s_waitcnt(x) ((void)(x))
 
 template <class T>

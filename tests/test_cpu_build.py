@@ -81,8 +81,8 @@ def test_failure_paths_on_the_cpu_build(emu_lib):
 
 def test_probed_gradient_on_the_cpu_build(emu_lib):
     """PROBED storage on an uneven 2D batch against the oracle's gradient_probed (Rademacher
-    probes) and against the exact gradient (identity table), under AddressSanitizer; the result
-    does not depend on the launch shape or the shot grouping."""
+    probes) and against the exact gradient (identity table), and on a 3D shot (Rademacher), under
+    AddressSanitizer; the result does not depend on the launch shape or the shot grouping."""
     import driver
     r = driver.run([os.path.join(EMU, "case_probed.py")], emu_lib, timeout=900)
     assert r.returncode == 0, r.stderr[-4000:]
@@ -90,3 +90,4 @@ def test_probed_gradient_on_the_cpu_build(emu_lib):
     print(res)
     assert res["rademacher"] <= 1e-5 and res["identity"] <= 1e-5 and res["identity_vs_exact"] <= 1e-5
     assert res["shape_invariant"]
+    assert res["rademacher3d"] <= 1e-5 and res["shape_invariant3d"]

@@ -101,3 +101,24 @@ def _raw_probed(plan, m, q, dds):
     B.check(B.lib().awe_gradient_probed(plan._h, B._ptr(m), B._ptr(q), B._ptr(dd), B._ptr(C),
                                         s.ctypes.data_as(ctypes.c_void_p), B._ptr(g), None, None, B._ptr(ws),
                                         plan.ws_bytes, B._stream_ptr(None)))
+
+
+def test_probed_gradient_3d_matches_the_oracle():
+    """3D: one shot whose receivers the post-step injection pass adds (it also adds its part of
+    the probe sums A_j), 8 Rademacher probes, against the oracle; two launch shapes give the
+    same bits."""
+    wl = W.small_3d(n=(26, 20, 30), nbl=8, T=60.0, nrec_side=6)
+    sh = wl.shots[0]
+    dd = W.synthetic_residual(sh.nt, len(sh.rec), wl.dt, wl.f0, 5)
+    C, s = W.probe_table("rademacher", sh.nt, r=8, seed=13)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_PROBED, 8))
+    m, q = gpu_inputs(wl, plan)
+    ddt = plan.pack([dd], "d")
+    g = plan.gradient_probed(m, q, ddt, C, s)[0]
+    plan.set_tiles(32, 4, 7)
+    g2 = plan.gradient_probed(m, q, ddt, C, s)[0]
+    torch.cuda.synchronize()
+    ref = O.gradient_probed(wl.m(0), wl.q(0), dd, C=C.astype(np.float64), s=s, **shot_kwargs(wl, 0))
+    err = rel_l2(plan.unpack(g, "m")[0], ref)
+    print(f"probed gradient 3D (r = 8): rel-L2 {err:.3e}", flush=True)
+    assert err <= TOL and torch.equal(g, g2)
