@@ -177,6 +177,25 @@ __device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int 
   return reinterpret_cast<float*>(ws + S.fld) + (long long)b * S.npts;
 }
 
+// Where a forward step reads level k of shot S.  With the FULL FP32 store every level is kept
+// bit for bit in the store, so the steps read their two previous levels from it (written by
+// the launch before, with ordinary stores that leave them in the caches) and the rotating
+// buffers are not needed; otherwise the rotating buffers, or a checkpoint slot restored by
+// reference.
+template <int SK>
+__device__ __forceinline__ const float* fwd_src(const StepArgs& a, const ShotDev& S, int k) {
+  if (SK == kStoreF32) return reinterpret_cast<const float*>(a.ws + S.store) + (long long)k * S.npts;
+  return fwd_level(a, S, k);
+}
+
+// Bytes of the rotating buffer a forward step writes level k into: with the FULL FP32 store only
+// the last level goes there too (the receivers' last sample is taken from it), so the other
+// levels' buffer stores are dropped by the range check.
+template <int SK>
+__device__ __forceinline__ int fwd_ring_bytes(const ShotDev& S, int k, int bytes) {
+  return SK != kStoreF32 || k == S.nt - 1 ? bytes : 0;
+}
+
 // ------------------------------------------------------------------------------ forward
 // Produces u^k (k = step - off) for every shot in the tile list; samples d^{k-1}.
 template <int TZ, int SK>
@@ -192,10 +211,10 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
   const int row4 = 4 * px;
   // levels below 1 are zero (initial state); their buffers may hold older levels after a
   // checkpoint restore of a state before this shot's start, so they are not read
-  const Planes u1 = planes(fwd_level(a, S, k - 1), nz, k >= 2 ? nz : 0, row4);
-  const Planes u2 = planes(fwd_level(a, S, k - 2), nz, k >= 3 ? nz : 0, row4);
+  const Planes u1 = planes(fwd_src<SK>(a, S, k - 1), nz, k >= 2 ? nz : 0, row4);
+  const Planes u2 = planes(fwd_src<SK>(a, S, k - 2), nz, k >= 3 ? nz : 0, row4);
   const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
-  const brsrc rout = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), nz * row4);
+  const brsrc rout = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), fwd_ring_bytes<SK>(S, k, nz * row4));
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int x = T.x0 + lane;
   const int cx = x < nx ? 4 * x : kOOB;
@@ -269,7 +288,7 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
       stb(rsl0, un, cx, zo);
       stb(rsl1, u, cx, zo);
     }
-    if (SK == kStoreF32) stb_nt(rst, un, cx, zo);
+    if (SK == kStoreF32) stb(rst, un, cx, zo);
     if (S16) {
       lmax = fmaxf(lmax, fabsf(un));
       if (k >= 2) stb16_nt(rst, enc16(u * inv_prev, SK == kStoreBF16), cx2, zo / 2);
@@ -564,13 +583,13 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   const int nx = S.nx, nz = S.nz, px = S.px;
   const int row4 = 4 * px;
   // levels below 1 are zero (see fwd2d_kernel)
-  const Planes u1 = planes(fbuf(a.ws, S, fwd_buf(k - 1)), nz, k >= 2 ? nz : 0, row4);
-  const Planes u2 = planes(fbuf(a.ws, S, fwd_buf(k - 2)), nz, k >= 3 ? nz : 0, row4);
+  const Planes u1 = planes(fwd_src<SK>(a, S, k - 1), nz, k >= 2 ? nz : 0, row4);
+  const Planes u2 = planes(fwd_src<SK>(a, S, k - 2), nz, k >= 3 ? nz : 0, row4);
   const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
   const long long npts = S.npts;
   // new levels k and k+1 (a level outside 1..nt-1 belongs to an inactive step: no records)
-  const brsrc ro1 = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), act1 ? nz * row4 : 0);
-  const brsrc ro2 = make_rsrc(fbuf(a.ws, S, fwd_buf(k + 1)), act2 ? nz * row4 : 0);
+  const brsrc ro1 = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), act1 ? fwd_ring_bytes<SK>(S, k, nz * row4) : 0);
+  const brsrc ro2 = make_rsrc(fbuf(a.ws, S, fwd_buf(k + 1)), act2 ? fwd_ring_bytes<SK>(S, k + 1, nz * row4) : 0);
   float* st = reinterpret_cast<float*>(a.ws + S.store);
   const brsrc rs1 = make_rsrc(st + (long long)(SK == kStoreF32 ? k : 0) * npts,
                               SK == kStoreF32 && act1 ? nz * row4 : 0);
@@ -633,7 +652,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     // body slots on tile rows store level k (wave-uniform condition; columns outside drop)
     if (i < G::NB && r >= kHalo && r < kHalo + TZ) {
       stb(ro1, v, cx, z * row4);
-      if (SK == kStoreF32) stb_nt(rs1, v, cx, z * row4);
+      if (SK == kStoreF32) stb(rs1, v, cx, z * row4);
     }
     LE[r][c] = v;
   }
@@ -666,7 +685,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     const float incr = step_incr(u, um2, tcf[i], lap, eta);
     const float un = (u + u - um2) + incr;
     stb(ro2, un, cx, z * row4);
-    if (SK == kStoreF32) stb_nt(rs2, un, cx, z * row4);
+    if (SK == kStoreF32) stb(rs2, un, cx, z * row4);
   }
 }
 

@@ -20,7 +20,9 @@ CSRC = os.path.join(ROOT, "paper_2304_05592_amd", "csrc")
 SOURCES = ["awe_api.hip", "kernels2d.hip", "kernels3d.hip", "kernels_aux.hip", "schedule.cpp"]
 CLANG = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 ASAN_RT = "/opt/rocm/llvm/lib/clang/{ver}/lib/linux/libclang_rt.asan-x86_64.so"
-GUARD = 4096   # bytes of poisoned gap after every workspace sub-buffer
+# bytes of poisoned gap after every workspace sub-buffer (EMU_GUARD widens it, so that an
+# index that jumps whole fields past a sub-buffer's end still lands in a gap)
+GUARD = int(os.environ.get("EMU_GUARD", "4096"))
 
 
 def _kernel_start(text: str, i: int) -> int:

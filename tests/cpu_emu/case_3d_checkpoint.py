@@ -24,7 +24,8 @@ def main():
     for st in (B.Storage(B.STORE_FULL), B.Storage(B.STORE_CHECKPOINT, int(os.environ.get("CASE_SLOTS", "4")))):
         t0 = time.time()
         plan = D.EmuPlan(lib, wl, storage=st)
-        plan.set_checks(int(os.environ.get("CASE_CHECKS", "0")))   # 4: host-side launch checks
+        if int(os.environ.get("CASE_CHECKS", "0")):
+            plan.set_checks(int(os.environ["CASE_CHECKS"]))   # 4: host-side launch checks
         m = plan.pack([wl.m(0)])
         q = plan.pack([wl.q(s) for s in range(wl.nshot)])
         dd = plan.pack(dds)

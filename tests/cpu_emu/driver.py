@@ -70,6 +70,43 @@ def _p(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
 
+_POISON = None
+
+
+def _poison(addr, n):
+    """Mark [addr, addr + n) as unaddressable for AddressSanitizer (no-op without it)."""
+    global _POISON
+    if _POISON is None:
+        try:
+            _POISON = getattr(ctypes.CDLL(None), "__asan_poison_memory_region")
+            _POISON.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+        except AttributeError:
+            _POISON = False
+    if _POISON and n > 0:
+        _POISON(ctypes.c_void_p(addr), n)
+
+
+def _guarded(nbytes):
+    """`_filled(nbytes)` as a 256-byte aligned view with EMU_ARRAY_GUARD poisoned bytes (or
+    more) on both sides: an access that runs off the front or the end of an array the library
+    is given, by any distance up to the guard, is reported.  On the GPU such an access lands in
+    whatever the caching allocator placed next to the tensor, or in unmapped memory."""
+    g = int(os.environ.get("EMU_ARRAY_GUARD", "0"))
+    raw = _filled(nbytes + 2 * g + 256)
+    off = g + (-(raw.ctypes.data + g)) % 256
+    if g > 0:
+        _poison(raw.ctypes.data, off)
+        _poison(raw.ctypes.data + off + nbytes, raw.nbytes - off - nbytes)
+    return raw[off:off + nbytes]
+
+
+def _guarded_copy(a):
+    a = np.ascontiguousarray(a)
+    out = _guarded(a.nbytes).view(a.dtype)
+    out[:] = a.ravel()
+    return out
+
+
 class EmuPlan:
     """The survey of `binding.Plan` on the CPU build; arrays are numpy (packed as there)."""
 
@@ -101,9 +138,7 @@ class EmuPlan:
     def workspace(self):
         """A fresh 256-byte aligned workspace with the gaps between sub-buffers poisoned."""
         n = self.ws_bytes()
-        raw = _filled(n + 256)
-        shift = (-raw.ctypes.data) % 256
-        ws = raw[shift:shift + n]
+        ws = _guarded(n)
         cap = 4096
         buf = (ctypes.c_longlong * (2 * cap))()
         cnt = self.L.awe_emu_subbuffers(self.h, buf, cap)
@@ -114,7 +149,6 @@ class EmuPlan:
                 if b > cur:
                     self.lib.asan(ctypes.c_void_p(ws.ctypes.data + cur), b - cur)
                 cur = max(cur, e)
-        self._raw = raw            # keep alive
         return ws
 
     def set_tiles(self, tz=32, ty=8, bz=0, dirs=3):
@@ -152,13 +186,13 @@ class EmuPlan:
         self.lib.check(self.L.awe_plan_set_fusion(self.h, mode))
 
     def pack(self, arrays, dtype=np.float32):
-        return np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=dtype).ravel() for a in arrays]))
+        return _guarded_copy(np.concatenate([np.asarray(a, dtype=dtype).ravel() for a in arrays]))
 
     def gradient(self, m, q, dd, v=False, d=False, ws=None):
         lay = self.layout
-        g = _filled(lay.m_size * 8).view(np.float64)
-        vv = _filled(lay.q_size * 4).view(np.float32) if v else None
-        dt = _filled(lay.d_size * 4).view(np.float32) if d else None
+        g = _guarded(lay.m_size * 8).view(np.float64)
+        vv = _guarded(lay.q_size * 4).view(np.float32) if v else None
+        dt = _guarded(lay.d_size * 4).view(np.float32) if d else None
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_gradient(self.h, _p(m), _p(q), _p(dd), _p(g), _p(vv), _p(dt), _p(ws),
                                            ws.nbytes, None))
@@ -166,30 +200,30 @@ class EmuPlan:
 
     def gradient_probed(self, m, q, dd, C, s, v=False, d=False, ws=None):
         lay = self.layout
-        g = _filled(lay.m_size * 8).view(np.float64)
-        vv = _filled(lay.q_size * 4).view(np.float32) if v else None
-        dt = _filled(lay.d_size * 4).view(np.float32) if d else None
+        g = _guarded(lay.m_size * 8).view(np.float64)
+        vv = _guarded(lay.q_size * 4).view(np.float32) if v else None
+        dt = _guarded(lay.d_size * 4).view(np.float32) if d else None
         ws = self.workspace() if ws is None else ws
-        C = np.ascontiguousarray(C, dtype=np.float32)
-        s = np.ascontiguousarray(s, dtype=np.float64)
+        C = _guarded_copy(np.asarray(C, dtype=np.float32))
+        s = _guarded_copy(np.asarray(s, dtype=np.float64))
         self.lib.check(self.L.awe_gradient_probed(self.h, _p(m), _p(q), _p(dd), _p(C), _p(s), _p(g), _p(vv),
                                                   _p(dt), _p(ws), ws.nbytes, None))
         return g, vv, dt
 
     def forward(self, m, q, ws=None):
-        d = _filled(self.layout.d_size * 4).view(np.float32)
+        d = _guarded(self.layout.d_size * 4).view(np.float32)
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_forward(self.h, _p(m), _p(q), _p(d), 0, _p(ws), ws.nbytes, None))
         return d
 
     def adjoint(self, m, dd, ws=None):
-        v = _filled(self.layout.q_size * 4).view(np.float32)
+        v = _guarded(self.layout.q_size * 4).view(np.float32)
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_adjoint(self.h, _p(m), _p(dd), _p(v), _p(ws), ws.nbytes, None))
         return v
 
     def born(self, m, q, dm, ws=None):
-        dd = _filled(self.layout.d_size * 4).view(np.float32)
+        dd = _guarded(self.layout.d_size * 4).view(np.float32)
         ws = self.workspace() if ws is None else ws
         self.lib.check(self.L.awe_born(self.h, _p(m), _p(q), _p(dm), _p(dd), _p(ws), ws.nbytes, None))
         return dd
