@@ -300,8 +300,9 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
  * awe_plan_set_fusion); 3D 64 x {4, 8, 16} columns with z-blocks of the full depth, of 128, 64 or
  * 32 planes, and of the depth split evenly in 2, 3 or 4 (rounded up to an even plane count).  The forward probe times the last probe_steps forward levels of the sweep (storing
  * the wavefield when the plan keeps one in FP32), the adjoint probe the last probe_steps adjoint
- * levels (with imaging when the plan keeps a wavefield), on the given inputs; the fastest of
- * each is kept for all later calls.  dd may be NULL (the adjoint probe then injects nothing).
+ * levels (with imaging when the plan keeps a wavefield; with PROBED storage both probes add to
+ * the probe sums, taking their coefficients from the workspace), on the given inputs; the
+ * fastest of each is kept for all later calls.  dd may be NULL (the adjoint probe then injects nothing).
  * Rebuilds the plan's device tables (the only allocation), overwrites the workspace and drops
  * any kept forward.  chosen (may be NULL) receives {tz, ty, bz} of the forward shape and the
  * fusion mode (awe_plan_get_tiles gives both shapes); best_ms (may be NULL) the sum of the two
@@ -347,9 +348,10 @@ awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz
 /* 2D only: advance two time levels per launch, chosen per direction by the bits of mode:
  * AWE_FUSE_FORWARD for forward solves, AWE_FUSE_ADJOINT for reverse sweeps (0, the default:
  * one level per launch everywhere).  The two-level kernels serve forward solves without
- * storage or with FULL FP32 storage and reverse sweeps from FULL FP32 storage or without
- * imaging; other modes always use one level per launch.  Results are bitwise identical
- * either way.  Two levels per launch need tiles of 8, 16 or 32 rows (16 or 32 are set
+ * storage, with FULL FP32 storage or into PROBED sums, and reverse sweeps from FULL FP32
+ * storage, into PROBED sums or without imaging; other modes always use one level per launch.
+ * Results are bitwise identical either way (a two-level launch adds both levels' terms to an
+ * FP64 sum in the order two launches would).  Two levels per launch need tiles of 8, 16 or 32 rows (16 or 32 are set
  * otherwise).  Errors: INVALID_ARG (mode outside 0..3), HIP. */
 enum { AWE_FUSE_NONE = 0, AWE_FUSE_FORWARD = 1, AWE_FUSE_ADJOINT = 2, AWE_FUSE_BOTH = 3 };
 awe_status awe_plan_set_fusion(awe_plan* plan, int32_t mode);

@@ -649,7 +649,8 @@ bool fused_ok(const awe_plan* P, int bit) {
 // Forward levels 1..nsteps: one single step first when the count is odd, then pairs.
 awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s) {
   awe_status st;
-  const bool fuse = fused_ok(P, AWE_FUSE_FORWARD) && (store == awe::kStoreNone || store == awe::kStoreF32);
+  const bool fuse = fused_ok(P, AWE_FUSE_FORWARD) &&
+                    (store == awe::kStoreNone || store == awe::kStoreF32 || store == awe::kStoreProbe);
   int n = 1;
   if (fuse && (P->nsteps & 1)) {
     if ((st = step_fwd(P, a, 1, store, s)) != AWE_OK) return st;
@@ -665,7 +666,8 @@ awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s)
 // Adjoint levels nsteps..1 (same pairing, from the top).
 awe_status adjoint_loop(awe_plan* P, awe::StepArgs& a, hipStream_t s) {
   awe_status st;
-  const bool fuse = fused_ok(P, AWE_FUSE_ADJOINT) && (a.image_src == awe::kImgNone || a.image_src == awe::kImgFull32);
+  const bool fuse = fused_ok(P, AWE_FUSE_ADJOINT) &&
+                    (a.image_src == awe::kImgNone || a.image_src == awe::kImgFull32 || a.image_src == awe::kImgProbe);
   int n = P->nsteps;
   if (fuse && (P->nsteps & 1)) {
     if ((st = step_adj(P, a, n, s)) != AWE_OK) return st;
@@ -1272,7 +1274,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   // probe adjoint levels only, so each direction keeps its own fastest shape
   struct Cand { int tz, ty, bz, fuse; };
   std::vector<Cand> cands;
-  const bool fusable = P->store.mode == AWE_STORE_NONE ||
+  const bool fusable = P->store.mode == AWE_STORE_NONE || P->store.mode == AWE_STORE_PROBED ||
                        (P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32);
   if (P->ndim == 2) {
     for (int tz : {8, 16, 32, 64}) {
@@ -1302,11 +1304,19 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   // the reverse sweep images from the recomputed forward buffers
   const bool full = P->store.mode == AWE_STORE_FULL;
   const int prec = P->store.prec;
-  const int fkind = !full ? awe::kStoreNone
+  // PROBED storage: the probes accumulate into the probe sums too.  Their coefficients are read
+  // from the sums the direction does not write (the forward reads the A sums, the adjoint the B
+  // sums; every probe takes the same column, pitch 0), which hold max_nt floats when
+  // max_nt <= 2 r npts; timing does not depend on the values.
+  const bool probed = P->store.mode == AWE_STORE_PROBED &&
+                      (long long)P->max_nt <= 2LL * P->store.nslots * P->sd[0].npts;
+  const int fkind = probed ? awe::kStoreProbe
+                    : !full ? awe::kStoreNone
                     : prec == AWE_PREC_FP32 ? awe::kStoreF32 : prec == AWE_PREC_BF16 ? awe::kStoreBF16 : awe::kStoreFP16;
-  const int img = full ? (prec == AWE_PREC_FP32 ? awe::kImgFull32 : prec == AWE_PREC_BF16 ? awe::kImgFullBF16
-                                                                                        : awe::kImgFullFP16)
-                       : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
+  const int img = probed ? awe::kImgProbe
+                  : full ? (prec == AWE_PREC_FP32 ? awe::kImgFull32 : prec == AWE_PREC_BF16 ? awe::kImgFullBF16
+                                                                                          : awe::kImgFullFP16)
+                         : P->sd[0].acc >= 0 ? awe::kImgBuffers : awe::kImgNone;
   double best[2] = {1e300, 1e300};
   Cand win[2] = {cands[0], cands[0]};
   P->cur = 0;  // the probes time the first shot group
@@ -1341,6 +1351,14 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
       awe::StepArgs aa = base_args(P, P->rv, ws);
       aa.dd = dd;
       aa.image_src = img;
+      if (probed) {
+        const ShotDev& d0 = P->sd[0];
+        unsigned char* wsb = static_cast<unsigned char*>(ws);
+        fa.probe_c = reinterpret_cast<const float*>(wsb + d0.store + (long long)P->store.nslots * d0.npts * 8);
+        aa.probe_c = reinterpret_cast<const float*>(wsb + d0.store);
+        fa.probe_r = aa.probe_r = P->store.nslots;
+        fa.probe_pitch = aa.probe_pitch = 0;
+      }
       if (hipError_t e = hipEventRecord(e0, s)) return fail_out(hip_fail(e, "autotune event"));
       // the last levels of the sweep, where every shot of an end-aligned batch is active (the
       // first levels of uneven batches cover only the longest shots)

@@ -154,6 +154,31 @@ __device__ __forceinline__ float* fwd_level(const StepArgs& a, const ShotDev& S,
   return reinterpret_cast<float*>(a.ws + S.fld) + (long long)fwd_buf(k) * S.npts;
 }
 
+// Probed gradient: for j < r, sum[j * stride] += c1[j * pitch] * v1 (when t1), then
+// += c2[j * pitch] * v2 (when t2), in FP64 (each product of two floats is exact, so the order of
+// the two additions alone fixes the result).  The sums are read in groups of kProbeGroup before
+// any of them is written back: a group's loads are in flight together instead of each waiting
+// for the store before it (the compiler cannot tell the sums of one point apart).
+constexpr int kProbeGroup = 8;
+__device__ __forceinline__ void probe_add(double* sum, long long stride, int r, const float* c1, double v1,
+                                          bool t1, const float* c2, double v2, bool t2, long long pitch) {
+  for (int j0 = 0; j0 < r; j0 += kProbeGroup) {
+    double t[kProbeGroup];
+#pragma unroll
+    for (int u = 0; u < kProbeGroup; ++u)
+      if (j0 + u < r) t[u] = sum[(j0 + u) * stride];
+#pragma unroll
+    for (int u = 0; u < kProbeGroup; ++u)
+      if (j0 + u < r) {
+        if (t1) t[u] += (double)c1[(j0 + u) * pitch] * v1;
+        if (t2) t[u] += (double)c2[(j0 + u) * pitch] * v2;
+      }
+#pragma unroll
+    for (int u = 0; u < kProbeGroup; ++u)
+      if (j0 + u < r) sum[(j0 + u) * stride] = t[u];
+  }
+}
+
 // Launchers (defined in the .hip files).  All enqueue on `stream`.
 hipError_t launch_coef(const float* m, unsigned char* ws, long long coef_off, long long m_off,
                        int nx, int ny, int nz, int px, int nbl, double h, double dt, double amp,

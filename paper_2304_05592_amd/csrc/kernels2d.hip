@@ -296,8 +296,7 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
     if (SK == kStoreProbe && x < nx && z < nz) {
       // u^k - 2u^{k-1} + u^{k-2} = incr (increment form of the step)
       const long long p = (long long)z * px + x;
-      const double b = (double)incr;
-      for (int j = 0; j < a.probe_r; ++j) pb[j * npts + p] += (double)pc[(long long)j * a.probe_pitch] * b;
+      probe_add(pb + p, npts, a.probe_r, pc, (double)incr, true, nullptr, 0.0, false, a.probe_pitch);
     }
   }
   if (S16) block_max_to_slot(lmax, scl, k);
@@ -398,8 +397,7 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
     if (IACC) stb64(racc, pacc[i] + (double)pu[i] * (double)incr, cx8, 2 * zo);
     if (IMG == kImgProbe && x < nx && z < nz) {
       const long long p = (long long)z * px + x;
-      const double wv64 = (double)wn;
-      for (int jj = 0; jj < a.probe_r; ++jj) pa[jj * S.npts + p] += (double)pc[(long long)jj * a.probe_pitch] * wv64;
+      probe_add(pa + p, S.npts, a.probe_r, pc, (double)wn, true, nullptr, 0.0, false, a.probe_pitch);
     }
   }
 }
@@ -567,12 +565,15 @@ __device__ __forceinline__ float ld_ext(const Planes& f, int i, int cx, const in
   return ldp_at(f, eo[i - G::NB]);
 }
 
-// Forward: levels k and k+1 (k = step - off); SK = kStoreNone or kStoreF32.
+// Forward: levels k and k+1 (k = step - off); SK = kStoreNone, kStoreF32 or kStoreProbe (both
+// levels' increments added to the probe sums in one FP64 read-modify-write, level k first).
 template <int TZ, int SK>
 __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   using G = F2<TZ>;
+  constexpr bool PRB = SK == kStoreProbe;
   __shared__ float L1[G::H1][G::W1];
   __shared__ float LE[G::HE][G::WE];
+  __shared__ float INC1[PRB ? TZ : 1][kTX];  // probe: level k's increment on the tile
   const int tid = xcd_tile(blockIdx.x, a.ntiles);
   const TileDev T = a.t.tiles[a.tile_base + tid];
   const ShotDev& S = a.t.shots[T.shot];
@@ -637,7 +638,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     int r, c;
     if (!ext_slot<TZ>(i, &r, &c)) continue;
     const int z = T.z0 - kHalo + r, xx = T.x0 - kHalo + c;
-    float v = 0.f;
+    float v = 0.f, incr = 0.f;
     if ((unsigned)z < (unsigned)nz && (unsigned)xx < (unsigned)nx) {
       const float* pc = &L1[r + kHalo][c + kHalo];
       const float u = pc[0];
@@ -646,13 +647,14 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
       if (act1 && (unsigned)bx < 2u && (unsigned)bz < 2u) lap += src_weight(bx + 2 * bz) * q1;
       const int dx = border_dist(xx, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
       const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
-      const float incr = step_incr(u, pm2[i], pcf[i], lap, eta);
+      incr = step_incr(u, pm2[i], pcf[i], lap, eta);
       v = (u + u - pm2[i]) + incr;
     }
     // body slots on tile rows store level k (wave-uniform condition; columns outside drop)
     if (i < G::NB && r >= kHalo && r < kHalo + TZ) {
       stb(ro1, v, cx, z * row4);
       if (SK == kStoreF32) stb(rs1, v, cx, z * row4);
+      if (PRB) INC1[r - kHalo][c - kHalo] = incr;
     }
     LE[r][c] = v;
   }
@@ -666,10 +668,14 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
           R.w[0] * LE[Rw][C] + R.w[1] * LE[Rw][C + 1] + R.w[2] * LE[Rw + 1][C] + R.w[3] * LE[Rw + 1][C + 1];
     }
   }
-  if (!act2) return;
-  // second step: level k+1 on the tile (every lane computes; stores outside the grid drop)
-  const float q2 = a.q[S.q + k];
+  if (!act2 && !PRB) return;  // probe: level k's increments are still to be added
+  // second step: level k+1 on the tile (every lane computes; stores outside the grid drop, as
+  // do those of an inactive level k+1)
+  const float q2 = act2 ? a.q[S.q + k] : 0.f;
   const int dx = border_dist(x, nx, a.nbl);
+  double* pb = PRB ? reinterpret_cast<double*>(a.ws + S.store) : nullptr;
+  const float* pc1 = PRB ? a.probe_c + k : nullptr;
+  const float* pc2 = PRB ? a.probe_c + k + 1 : nullptr;
 #pragma unroll
   for (int i = 0; i < G::RPT; ++i) {
     const int lr = wv * G::RPT + i;
@@ -686,15 +692,23 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     const float un = (u + u - um2) + incr;
     stb(ro2, un, cx, z * row4);
     if (SK == kStoreF32) stb(rs2, un, cx, z * row4);
+    if (PRB && x < nx && z < nz) {
+      // the same two FP64 additions, in the same order, as two one-level launches
+      const long long p = (long long)z * px + x;
+      probe_add(pb + p, npts, a.probe_r, pc1, (double)INC1[lr][lane], act1, pc2, (double)incr, act2,
+                a.probe_pitch);
+    }
   }
 }
 
 // Adjoint: levels j and j-1 (j = step - off), receiver residual injected in both steps,
 // imaging of both steps accumulated (in step order) into one FP64 read-modify-write.
-// IMG = kImgNone or kImgFull32.
+// IMG = kImgNone, kImgFull32 or kImgProbe (both levels added to the probe sums A_j in one FP64
+// read-modify-write, level j first).
 template <int TZ, int IMG>
 __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   using G = F2<TZ>;
+  constexpr bool IACC = IMG == kImgFull32;
   __shared__ float L1[G::H1][G::W1];
   __shared__ float LE[G::HE][G::WE];
   __shared__ float INJ1[G::HE][G::WE];
@@ -717,10 +731,10 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   const brsrc ro2 = make_rsrc(fbuf(a.ws, S, adj_buf(j - 1)), act2 ? nz * row4 : 0);
   // imaging: stored u^j and u^{j-1} (levels of inactive steps read 0) and the FP64 accumulator
   const float* ust = reinterpret_cast<const float*>(a.ws + S.store);
-  const Planes us1 = planes(ust + (long long)(IMG && act1 ? j : 0) * S.npts, nz, IMG && act1 ? nz : 0, row4);
-  const Planes us2 = planes(ust + (long long)(IMG && act2 ? j - 1 : 0) * S.npts, nz, IMG && act2 ? nz : 0, row4);
-  const Planes acc = planes(a.ws + S.acc, nz, IMG ? nz : 0, 2 * row4);
-  const brsrc racc = make_rsrc(a.ws + S.acc, IMG ? 2 * nz * row4 : 0);
+  const Planes us1 = planes(ust + (long long)(IACC && act1 ? j : 0) * S.npts, nz, IACC && act1 ? nz : 0, row4);
+  const Planes us2 = planes(ust + (long long)(IACC && act2 ? j - 1 : 0) * S.npts, nz, IACC && act2 ? nz : 0, row4);
+  const Planes acc = planes(a.ws + S.acc, nz, IACC ? nz : 0, 2 * row4);
+  const brsrc racc = make_rsrc(a.ws + S.acc, IACC ? 2 * nz * row4 : 0);
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int x = T.x0 + lane;
   const int cx = x < nx ? 4 * x : kOOB;
@@ -747,7 +761,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   for (int i = 0; i < G::RPT; ++i) {
     const int z = T.z0 + wv * G::RPT + i;
     tcf[i] = ldp(cf, cx, z);
-    if (IMG) {
+    if (IACC) {
       pu1[i] = ldp_nt(us1, cx, z);
       pu2[i] = ldp_nt(us2, cx, z);
       pacc[i] = ldp64(acc, cx8, z);
@@ -824,25 +838,36 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   // second step: level j-1 on the tile; imaging of both steps (every lane computes; outside
   // the grid the stores drop)
   const int dx = border_dist(x, nx, a.nbl);
+  double* pa = IMG == kImgProbe ? reinterpret_cast<double*>(a.ws + S.store) + (long long)a.probe_r * S.npts
+                                : nullptr;
+  const float* pc1 = IMG == kImgProbe ? a.probe_c + j : nullptr;
+  const float* pc2 = IMG == kImgProbe ? a.probe_c + j - 1 : nullptr;
 #pragma unroll
   for (int i = 0; i < G::RPT; ++i) {
     const int lr = wv * G::RPT + i;
     const int z = T.z0 + lr;
-    double ac = IMG ? pacc[i] : 0.0;
-    if (IMG && act1) ac = ac + (double)pu1[i] * (double)INC1[lr][lane];
+    double ac = IACC ? pacc[i] : 0.0;
+    if (IACC && act1) ac = ac + (double)pu1[i] * (double)INC1[lr][lane];
+    const float w = LE[lr + kHalo][lane + kHalo];  // level j on the tile
+    float wn = 0.f;
     if (act2) {
       const float* pc = &LE[lr + kHalo][lane + kHalo];
-      const float w = pc[0];
       const float wm2 = L1[lr + 2 * kHalo][lane + 2 * kHalo];
       float lap = lap_ptr(pc, G::WE, a.c);
       if (inj2) lap += INJ2[lr][lane];
       const int dz = border_dist(z, nz, a.nbl);
       const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
       const float incr = step_incr(w, wm2, tcf[i], lap, eta);
-      stb(ro2, (w + w - wm2) + incr, cx, z * row4);
-      if (IMG) ac = ac + (double)pu2[i] * (double)incr;
+      wn = (w + w - wm2) + incr;
+      stb(ro2, wn, cx, z * row4);
+      if (IACC) ac = ac + (double)pu2[i] * (double)incr;
     }
-    if (IMG) stb64(racc, ac, cx8, 2 * z * row4);
+    if (IACC) stb64(racc, ac, cx8, 2 * z * row4);
+    if (IMG == kImgProbe && x < nx && z < nz) {
+      // the same two FP64 additions, in the same order, as two one-level launches
+      const long long p = (long long)z * px + x;
+      probe_add(pa + p, S.npts, a.probe_r, pc1, (double)w, act1, pc2, (double)wn, act2, a.probe_pitch);
+    }
   }
 }
 
@@ -878,6 +903,7 @@ hipError_t fwd2d2_tz(const StepArgs& a, int store, hipStream_t s) {
   switch (store) {
     case kStoreNone: fwd2d2_kernel<TZ, kStoreNone><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     case kStoreF32: fwd2d2_kernel<TZ, kStoreF32><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
+    case kStoreProbe: fwd2d2_kernel<TZ, kStoreProbe><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -888,6 +914,7 @@ hipError_t adj2d2_tz(const StepArgs& a, hipStream_t s) {
   switch (a.image_src) {
     case kImgNone: adj2d2_kernel<TZ, kImgNone><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     case kImgFull32: adj2d2_kernel<TZ, kImgFull32><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
+    case kImgProbe: adj2d2_kernel<TZ, kImgProbe><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

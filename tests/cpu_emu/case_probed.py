@@ -2,7 +2,7 @@
 gradient_probed on an uneven 2D batch (three shots, two windows, different nt), with
 Rademacher probes and with the identity table (which gives the exact gradient), under
 AddressSanitizer with poisoned gaps between the workspace's sub-buffers; the probed gradient
-does not depend on the launch shape or the shot grouping."""
+does not depend on the launch shape, the number of levels per launch or the shot grouping."""
 import json
 import os
 
@@ -59,7 +59,12 @@ def main():
             plan.set_tiles(8, 8, 0)
             plan.set_groups(3)
             g2 = plan.gradient_probed(m, q, dd, C, s)[0]
-            out["shape_invariant"] = bool(np.array_equal(g, g2))
+            # two levels per launch in both sweeps (uneven nt: odd and even level counts)
+            plan.set_tiles(16, 8, 0)
+            plan.set_fusion(3)
+            plan.set_groups(1)
+            g3 = plan.gradient_probed(m, q, dd, C, s)[0]
+            out["shape_invariant"] = bool(np.array_equal(g, g2) and np.array_equal(g, g3))
         print(name, out, flush=True)
     # 3D: one shot with receivers injected by the post-step pass (its part of A_j is added there)
     w3 = W.small_3d(n=(26, 20, 30), nbl=8, T=40.0, nrec_side=6)
