@@ -158,7 +158,8 @@ __device__ __forceinline__ float* fwd_level(const StepArgs& a, const ShotDev& S,
 // += c2[j * pitch] * v2 (when t2), in FP64 (each product of two floats is exact, so the order of
 // the two additions alone fixes the result).  The sums are read in groups of kProbeGroup before
 // any of them is written back: a group's loads are in flight together instead of each waiting
-// for the store before it (the compiler cannot tell the sums of one point apart).
+// for the store before it (the compiler cannot tell the sums of one point apart).  They are read
+// and written once per launch and outgrow the caches, so both accesses are nontemporal.
 constexpr int kProbeGroup = 8;
 __device__ __forceinline__ void probe_add(double* sum, long long stride, int r, const float* c1, double v1,
                                           bool t1, const float* c2, double v2, bool t2, long long pitch) {
@@ -166,7 +167,7 @@ __device__ __forceinline__ void probe_add(double* sum, long long stride, int r, 
     double t[kProbeGroup];
 #pragma unroll
     for (int u = 0; u < kProbeGroup; ++u)
-      if (j0 + u < r) t[u] = sum[(j0 + u) * stride];
+      if (j0 + u < r) t[u] = __builtin_nontemporal_load(&sum[(j0 + u) * stride]);
 #pragma unroll
     for (int u = 0; u < kProbeGroup; ++u)
       if (j0 + u < r) {
@@ -175,7 +176,7 @@ __device__ __forceinline__ void probe_add(double* sum, long long stride, int r, 
       }
 #pragma unroll
     for (int u = 0; u < kProbeGroup; ++u)
-      if (j0 + u < r) sum[(j0 + u) * stride] = t[u];
+      if (j0 + u < r) __builtin_nontemporal_store(t[u], &sum[(j0 + u) * stride]);
   }
 }
 
