@@ -1030,7 +1030,7 @@ void layout_ws(awe_plan* P) {
       d.scale = off;
       off = align256(off + (long long)st.nslots * 2 * 4);
     } else if (st.mode == AWE_STORE_PROBED) {
-      d.store = off;  // FP64 probe sums B [r][npts], then A [r][npts]
+      d.store = off;  // FP64 probe sums B, then A, r per point in blocks of 64 points (probe_sums)
       off = align256(off + (long long)st.nslots * 2 * d.npts * 8);
     }
   }

@@ -154,29 +154,40 @@ __device__ __forceinline__ float* fwd_level(const StepArgs& a, const ShotDev& S,
   return reinterpret_cast<float*>(a.ws + S.fld) + (long long)fwd_buf(k) * S.npts;
 }
 
-// Probed gradient: for j < r, sum[j * stride] += c1[j * pitch] * v1 (when t1), then
-// += c2[j * pitch] * v2 (when t2), in FP64 (each product of two floats is exact, so the order of
-// the two additions alone fixes the result).  The sums are read in groups of kProbeGroup before
-// any of them is written back: a group's loads are in flight together instead of each waiting
-// for the store before it (the compiler cannot tell the sums of one point apart).  They are read
-// and written once per launch and outgrow the caches, so both accesses are nontemporal.
+// Probed gradient sums, FP64, r per point: blocks of 64 consecutive points (rows are padded to a
+// multiple of 64, so a block is the 64 columns a wave updates), each block holding its points'
+// sum 0, then sum 1, ...  The sum j of point p lies at ((p / 64) r + j) 64 + p % 64: a wave reads
+// sum j of its 64 points as one contiguous 512-byte run, and its r sums as one 512 r-byte range.
+static_assert(kPitch % 64 == 0, "probe-sum blocks of 64 points need rows padded to a multiple of 64");
+__device__ __forceinline__ double* probe_sums(double* region, long long p, int r) {
+  return region + ((p >> 6) * r) * 64 + (p & 63);
+}
+
+// For j < r, sum[64 j] += c1[j * pitch] * v1 (when t1), then += c2[j * pitch] * v2 (when t2),
+// in FP64 (each product of two floats is exact, so the order of the two additions alone fixes
+// the result); sum from probe_sums.  The sums are read in groups of kProbeGroup before any of
+// them is written back (the loads of a group are in flight together instead of each waiting for
+// the store before it), and since they are read and written once per launch and outgrow the
+// caches, both accesses are nontemporal.
 constexpr int kProbeGroup = 8;
-__device__ __forceinline__ void probe_add(double* sum, long long stride, int r, const float* c1, double v1,
-                                          bool t1, const float* c2, double v2, bool t2, long long pitch) {
+__device__ __forceinline__ void probe_add(double* sum, int r, const float* c1, double v1, bool t1,
+                                          const float* c2, double v2, bool t2, long long pitch) {
   for (int j0 = 0; j0 < r; j0 += kProbeGroup) {
     double t[kProbeGroup];
+    const int n = r - j0 < kProbeGroup ? r - j0 : kProbeGroup;
+    double* s = sum + j0 * 64;
 #pragma unroll
     for (int u = 0; u < kProbeGroup; ++u)
-      if (j0 + u < r) t[u] = __builtin_nontemporal_load(&sum[(j0 + u) * stride]);
+      if (u < n) t[u] = __builtin_nontemporal_load(s + u * 64);
 #pragma unroll
     for (int u = 0; u < kProbeGroup; ++u)
-      if (j0 + u < r) {
+      if (u < n) {
         if (t1) t[u] += (double)c1[(j0 + u) * pitch] * v1;
         if (t2) t[u] += (double)c2[(j0 + u) * pitch] * v2;
       }
 #pragma unroll
     for (int u = 0; u < kProbeGroup; ++u)
-      if (j0 + u < r) __builtin_nontemporal_store(t[u], &sum[(j0 + u) * stride]);
+      if (u < n) __builtin_nontemporal_store(t[u], s + u * 64);
   }
 }
 

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
     if (SK == kStoreProbe && x < nx && z < nz) {
       // u^k - 2u^{k-1} + u^{k-2} = incr (increment form of the step)
       const long long p = (long long)z * px + x;
-      probe_add(pb + p, npts, a.probe_r, pc, (double)incr, true, nullptr, 0.0, false, a.probe_pitch);
+      probe_add(probe_sums(pb, p, a.probe_r), a.probe_r, pc, (double)incr, true, nullptr, 0.0, false, a.probe_pitch);
     }
   }
   if (S16) block_max_to_slot(lmax, scl, k);
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(T2<TZ>::NT) void adj2d_kernel(StepArgs a) {
     if (IACC) stb64(racc, pacc[i] + (double)pu[i] * (double)incr, cx8, 2 * zo);
     if (IMG == kImgProbe && x < nx && z < nz) {
       const long long p = (long long)z * px + x;
-      probe_add(pa + p, S.npts, a.probe_r, pc, (double)wn, true, nullptr, 0.0, false, a.probe_pitch);
+      probe_add(probe_sums(pa, p, a.probe_r), a.probe_r, pc, (double)wn, true, nullptr, 0.0, false, a.probe_pitch);
     }
   }
 }
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     if (PRB && x < nx && z < nz) {
       // the same two FP64 additions, in the same order, as two one-level launches
       const long long p = (long long)z * px + x;
-      probe_add(pb + p, npts, a.probe_r, pc1, (double)INC1[lr][lane], act1, pc2, (double)incr, act2,
+      probe_add(probe_sums(pb, p, a.probe_r), a.probe_r, pc1, (double)INC1[lr][lane], act1, pc2, (double)incr, act2,
                 a.probe_pitch);
     }
   }
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
     if (IMG == kImgProbe && x < nx && z < nz) {
       // the same two FP64 additions, in the same order, as two one-level launches
       const long long p = (long long)z * px + x;
-      probe_add(pa + p, S.npts, a.probe_r, pc1, (double)w, act1, pc2, (double)wn, act2, a.probe_pitch);
+      probe_add(probe_sums(pa, p, a.probe_r), a.probe_r, pc1, (double)w, act1, pc2, (double)wn, act2, a.probe_pitch);
     }
   }
 }

@@ -275,7 +275,7 @@ __global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen
       if (SK == kStoreProbe && cv[c] != kOOB) {
         // u^k - 2u^{k-1} + u^{k-2} = incr (increment form of the step)
         const long long p = z * plane_pts + (cv[c] >> 2);
-        probe_add(pb + p, S.npts, a.probe_r, pcol, (double)incr, true, nullptr, 0.0, false, a.probe_pitch);
+        probe_add(probe_sums(pb, p, a.probe_r), a.probe_r, pcol, (double)incr, true, nullptr, 0.0, false, a.probe_pitch);
       }
     }
     if (z + 1 < zend) {
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(T3<TY>::NT) void adj3d_kernel(StepArgs a, int bzlen
       if (IACC) stb64_nt(racc, pacc[c] + (double)pu[c] * (double)incr, cv8[c], 2 * zo);
       if (IMG == kImgProbe && cv[c] != kOOB) {
         const long long p = z * plane_pts + (cv[c] >> 2);
-        probe_add(pa + p, S.npts, a.probe_r, pcol, (double)wn, true, nullptr, 0.0, false, a.probe_pitch);
+        probe_add(probe_sums(pa, p, a.probe_r), a.probe_r, pcol, (double)wn, true, nullptr, 0.0, false, a.probe_pitch);
       }
     }
     if (z + 1 < zend) {
@@ -477,7 +477,7 @@ __global__ void inj3d_kernel(StepArgs a, int first, int count) {
     // A_j holds C[j][level] times the step's value before injection: add C[j][level] times the
     // injected part (the sums are linear in w^j)
     double* pa = reinterpret_cast<double*>(a.ws + S.store) + (long long)a.probe_r * S.npts;
-    probe_add(pa + Pt.p, S.npts, a.probe_r, a.probe_c + j, (double)add, true, nullptr, 0.0, false, a.probe_pitch);
+    probe_add(probe_sums(pa, Pt.p, a.probe_r), a.probe_r, a.probe_c + j, (double)add, true, nullptr, 0.0, false, a.probe_pitch);
   } else if (a.image_src) {
     float u;
     if (a.image_src == kImgFull32)

@@ -177,8 +177,9 @@ __global__ void probe_reduce_kernel(Tables t, unsigned char* ws, int r, ProbeWei
       const ShotDev& S = t.shots[t.win_shots[W.sbegin + k]];
       const double* B = reinterpret_cast<const double*>(ws + S.store);
       const double* A = B + (long long)r * S.npts;
+      const long long o = ((p >> 6) * r) * 64 + (p & 63);  // sums of p: see probe_sums
       double e = 0.0;
-      for (int j = 0; j < r; ++j) e += w.s[j] * (A[j * S.npts + p] * B[j * S.npts + p]);
+      for (int j = 0; j < r; ++j) e += w.s[j] * (A[o + j * 64] * B[o + j * 64]);
       s += e;
     }
     g[W.m + row * W.nx + i] = scale * s;
