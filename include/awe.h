@@ -298,7 +298,7 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
  * autotuner chooses each separately.  Candidates: 2D 8, 16, 32 or 64 rows of 64 columns, and -
  * where the storage mode allows it - 8, 16 or 32 rows with two time levels per launch (see
  * awe_plan_set_fusion); 3D 64 x {4, 8, 16} columns with z-blocks of the full depth, of 128, 64 or
- * 32 planes, and of the depth split evenly in 2, 3 or 4 (rounded up to an even plane count).  The forward probe times the last probe_steps forward levels of the sweep (storing
+ * 32 planes, and of the depth split evenly in 2 to 8 (rounded up to an even plane count).  The forward probe times the last probe_steps forward levels of the sweep (storing
  * the wavefield when the plan keeps one in FP32), the adjoint probe the last probe_steps adjoint
  * levels (with imaging when the plan keeps a wavefield; with PROBED storage both probes add to
  * the probe sums, taking their coefficients from the workspace), on the given inputs; the

@@ -1282,12 +1282,12 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
       if (fusable && tz != 64) cands.push_back({tz, 8, 0, 1});
     }
   } else {
-    // z-blocks of the full depth, of fixed lengths, and of the depth split evenly into 2, 3 or 4
+    // z-blocks of the full depth, of fixed lengths, and of the depth split evenly into 2 to 8
     // (no short last block)
     int nz = 0;
     for (const ShotDev& d : P->sd) nz = std::max(nz, d.nz);
     std::vector<int> bzs = {0, 128, 64, 32};
-    for (int k = 2; k <= 4; ++k) {
+    for (int k = 2; k <= 8; ++k) {
       const int b = ((nz + k - 1) / k + 1) & ~1;
       if (b >= 16 && std::find(bzs.begin(), bzs.end(), b) == bzs.end()) bzs.push_back(b);
     }

@@ -139,7 +139,11 @@ __device__ __forceinline__ float lap3(const float (*P)[T3<TY>::W], const float* 
 // buffer b and its register queue, then writes plane z+1 (loaded one plane earlier) into
 // buffer 1-b.
 template <int TY, int SK>
-__global__ __launch_bounds__(T3<TY>::NT) void fwd3d_kernel(StepArgs a, int bzlen) {
+// Six waves per SIMD (at most 80 VGPRs) for the step and its stores: the z-march is bound by the
+// latency of its plane loads, and the register budget costs no spills; the probe kind, with its
+// sums in flight, keeps the compiler's own budget.
+__global__ __launch_bounds__(T3<TY>::NT) __attribute__((amdgpu_waves_per_eu(SK == kStoreProbe ? 4 : 6, 8)))
+void fwd3d_kernel(StepArgs a, int bzlen) {
   constexpr int NC = T3<TY>::NC, HP = Ring<TY>::PER;
   __shared__ float P[2][T3<TY>::H][T3<TY>::W];
   const int tid = xcd_tile(blockIdx.x, a.ntiles);

@@ -21,6 +21,8 @@
 #define __host__
 #define __forceinline__ inline __attribute__((always_inline))
 #define __launch_bounds__(...)
+// register-budget hints of kernels mean nothing on the host (the attribute list is left empty)
+#define amdgpu_waves_per_eu(...)
 #define __shared__ static
 #define __align__(n) __attribute__((aligned(n)))
 #define HIP_SYMBOL(x) (&(x))
