@@ -890,6 +890,13 @@ def bench_c9(args, base="c2_grad"):
     prof = plan.profile_read()
     plan.profile_disable()
     kernels = kernel_table(prof, launch_points, {"forward": kind, "adjoint": kind}, fused=fused)
+    for k in kernels.values():
+        if "fused_bytes_per_launch" in k:
+            # twice the per-step figure is no lower bound here (one read-modify-write of the sums
+            # serves both levels): a two-level launch is priced at the bytes it moves
+            k["per_step_table_bytes_per_launch"] = k["bytes_per_launch"]
+            k["bytes_per_launch"] = k["fused_bytes_per_launch"]
+            refresh_rates(k)
     dim = f"{wl.ndim}d"
     names = {d: (f"{d[:3]}{dim}2 two steps + {r} FP64 probe sums ({FUSED_BYTES[(d, kind)]} B/point per launch)"
                  if fused & (1 if d == "forward" else 2) else
