@@ -72,6 +72,24 @@ def test_probed_gradient_does_not_depend_on_shape_or_grouping():
         assert torch.equal(plan.gradient_probed(m, q, dd, Cd, s)[0], ref), (tz, fusion, groups)
 
 
+def test_autotuner_on_a_probed_plan_keeps_the_result():
+    """The autotuner times the probe kernels on a PROBED plan (their coefficients read from the
+    workspace); whatever shape and fusion it keeps, the gradient is bitwise the one before."""
+    wl, dds = _batch()
+    max_nt = max(s.nt for s in wl.shots)
+    C, s = _tables(max_nt)["rademacher"]
+    plan = make_plan(wl, storage=A.Storage(A.STORE_PROBED, C.shape[0]))
+    m, q = gpu_inputs(wl, plan)
+    dd = plan.pack(dds, "d")
+    Cd = torch.from_numpy(C).cuda()
+    ref = plan.gradient_probed(m, q, dd, Cd, s)[0].clone()
+    choice, ms = plan.autotune(m, q, dd, probe_steps=8)
+    torch.cuda.synchronize()
+    print(f"probed autotune: {choice}, {ms:.3f} ms", flush=True)
+    assert ms > 0
+    assert torch.equal(plan.gradient_probed(m, q, dd, Cd, s)[0], ref)
+
+
 def test_probed_storage_refusals_and_workspace():
     wl, dds = _batch()
     r = 8
