@@ -15,6 +15,8 @@ shots in ascending order) and a seeded sample of the outputs is stored:
                       shot at this size)
   c9_probed_full.npz  the probed gradient of shots 0 and 8 of the c2_grad survey with
                       PROBES Rademacher probes (table seed PROBE_SEED, columns = local levels)
+  c9_probed_crop_full.npz  the probed gradient of the 3D crop's shot (144^3 with the sponge,
+                      nt 2308) with the same probes
 
 Gradient samples are flat indices into each window's computational grid (the
 same number per window); trace samples are every TIME_STRIDE-th time sample of
@@ -22,7 +24,8 @@ every REC_STRIDE-th receiver.
 
 Run from the repository root:
     python tests/golden/make_full_size.py [c2_grad] [c4_uneven] [c5_crop] [c2_born] [c3_autograd] [c9_probed]
-The 2D sets take minutes on 8 cores, the 3D crop about half an hour.
+                                          [c9_probed_crop]
+The 2D sets take minutes on 8 cores, each 3D crop set about half an hour.
 """
 from __future__ import annotations
 
@@ -104,6 +107,24 @@ def make_probed(workers):
     print(f"wrote {path}", flush=True)
 
 
+def make_probed_crop():
+    import oracle as O
+    import workloads as W
+    wl = W.make_config("c5_crop")
+    sh = wl.shots[0]
+    C, sw = probe_table(sh.nt)
+    t0 = time.perf_counter()
+    g = O.gradient_probed(wl.m(0, background=True), wl.q(0), residual(wl, 0), C=C.astype(np.float64), s=sw,
+                          src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax)
+    print(f"  c9_probed_crop: {time.perf_counter() - t0:.1f} s", flush=True)
+    rng = np.random.default_rng(SAMPLE_SEED)
+    gidx = np.sort(rng.choice(g.size, size=N_GRAD_SAMPLES, replace=False))
+    path = os.path.join(ROOT, "tests", "golden", "c9_probed_crop_full.npz")
+    np.savez_compressed(path, probes=PROBES, probe_seed=PROBE_SEED, grad_index_0=gidx.astype(np.int64),
+                        grad_value_0=g.ravel()[gidx], grad_norm=np.linalg.norm(g))
+    print(f"wrote {path}", flush=True)
+
+
 def born_perturbation(wl, w=0):
     """dm = m - m0 of window w in float32 (the true model minus the smoothed background)."""
     return wl.m(w) - wl.m(w, background=True)
@@ -182,6 +203,8 @@ def main():
             make_born(workers)
         elif name == "c9_probed":
             make_probed(workers)
+        elif name == "c9_probed_crop":
+            make_probed_crop()
         else:
             make(name, workers)
         print(f"{name}: {time.perf_counter() - t0:.1f} s", flush=True)

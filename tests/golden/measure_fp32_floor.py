@@ -10,9 +10,11 @@ against the FP64 result.  Calls only the oracle and the seeded input generators:
   * the F and J dot tests of the 2-shot small 2D survey with the GPU test's seeded vectors:
     float32 operators, FP64 inner products, |a - b| / max(|a|, |b|);
   * the probed gradient of c2_grad shots 0 and 8 with 8 Rademacher probes (float32 oracle vs
-    the FP64 samples of tests/golden/c9_probed_full.npz).
+    the FP64 samples of tests/golden/c9_probed_full.npz);
+  * the probed gradient of the 3D crop's shot with the same probes (vs
+    tests/golden/c9_probed_crop_full.npz; asked for by name only, about half an hour).
 
-Run from the repository root:  python tests/golden/measure_fp32_floor.py [c2_grad] [dots] [c9_probed]
+Run from the repository root:  python tests/golden/measure_fp32_floor.py [c2_grad] [dots] [c9_probed] [c9_probed_crop]
 (no argument: all; a subset updates only its entries of the record).
 """
 from __future__ import annotations
@@ -125,6 +127,24 @@ def probed_floor():
             "gradient_rel_l2": _rel(g.ravel()[gold["grad_index_0"]], gold["grad_value_0"])}
 
 
+def probed_crop_floor():
+    import oracle as O
+    import workloads as W
+    spec = __import__("importlib.util").util.spec_from_file_location("mfs", os.path.join(GOLD, "make_full_size.py"))
+    G = __import__("importlib.util").util.module_from_spec(spec)
+    spec.loader.exec_module(G)
+    gold = np.load(os.path.join(GOLD, "c9_probed_crop_full.npz"))
+    wl = W.make_config("c5_crop")
+    sh = wl.shots[0]
+    C, sw = G.probe_table(sh.nt)
+    t0 = time.perf_counter()
+    g = O.gradient_probed(wl.m(0, background=True), wl.q(0), G.residual(wl, 0), C=C.astype(np.float64), s=sw,
+                          src=sh.src, rec=sh.rec, h=wl.h, dt=wl.dt, nbl=wl.nbl, vref=wl.vmax, dtype=np.float32)
+    print(f"  probed crop: {time.perf_counter() - t0:.1f} s", flush=True)
+    return {"probes": int(gold["probes"]),
+            "gradient_rel_l2": _rel(g.astype(np.float64).ravel()[gold["grad_index_0"]], gold["grad_value_0"])}
+
+
 def main():
     parts = sys.argv[1:] or ["c2_grad", "dots", "c9_probed"]
     path = os.path.join(GOLD, "fp32_floor.json")
@@ -137,6 +157,8 @@ def main():
         rec["small_2d_dot_tests"] = dot_floor()
     if "c9_probed" in parts:
         rec["c9_probed"] = probed_floor()
+    if "c9_probed_crop" in parts:
+        rec["c9_probed_crop"] = probed_crop_floor()
     rec["seconds_last_run"] = round(time.perf_counter() - t0, 1)
     rec.pop("seconds", None)
     with open(path, "w") as f:
