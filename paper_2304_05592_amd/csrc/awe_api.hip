@@ -651,6 +651,8 @@ awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s)
   awe_status st;
   const bool fuse = fused_ok(P, AWE_FUSE_FORWARD) &&
                     (store == awe::kStoreNone || store == awe::kStoreF32 || store == awe::kStoreProbe);
+  // a 2D FP32 sweep of one-level steps reads its previous levels back from the store
+  if (!fuse && P->ndim == 2 && store == awe::kStoreF32) store = awe::kStoreF32R;
   int n = 1;
   if (fuse && (P->nsteps & 1)) {
     if ((st = step_fwd(P, a, 1, store, s)) != AWE_OK) return st;
@@ -1364,8 +1366,9 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
       // first levels of uneven batches cover only the longest shots)
       if (dir == 0) {
         const bool f2 = fused_ok(P, AWE_FUSE_FORWARD);
+        const int k1 = P->ndim == 2 && fkind == awe::kStoreF32 ? awe::kStoreF32R : fkind;  // as forward_loop
         for (int n = std::max(1, P->nsteps - probe + 1); n + (f2 ? 1 : 0) <= P->nsteps; n += f2 ? 2 : 1)
-          if ((st = f2 ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, fkind, s)) != AWE_OK)
+          if ((st = f2 ? step_fwd2(P, fa, n, fkind, s) : step_fwd(P, fa, n, k1, s)) != AWE_OK)
             return fail_out(st);
       } else {
         const bool a2 = fused_ok(P, AWE_FUSE_ADJOINT);

@@ -38,10 +38,15 @@ enum ImageSrc : int { kImgNone = 0, kImgFull32 = 1, kImgBuffers = 2, kImgFullBF1
 // quantised one step later, once its max |u| is complete).
 // kStoreProbe: B_j += C[j][level] (u^k - 2u^{k-1} + u^{k-2}) instead of a stored level (probed
 // gradient; the second difference is the step's increment).
-enum StoreKind : int { kStoreNone = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreFP16 = 3, kStoreProbe = 4 };
+// kStoreF32R (2D one-level steps of a sweep without two-level launches): FP32 copy as kStoreF32,
+// but the step reads its two previous levels back from the store instead of the rotating
+// buffers, which then receive only the last level.
+enum StoreKind : int { kStoreNone = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreFP16 = 3, kStoreProbe = 4,
+                       kStoreF32R = 5 };
 
-// Probed gradient: at most this many probes; a shot's accumulators are FP64 fields [2][r][npts] at
-// ShotDev::store, B (forward second differences) first, then A (adjoint levels).
+// Probed gradient: at most this many probes; a shot's sums are 2 r FP64 values per point at
+// ShotDev::store, B (forward second differences) first, then A (adjoint levels), each in the
+// blocked layout of probe_sums.
 constexpr int kMaxProbes = 64;
 
 // Per-shot description as the kernels read it.

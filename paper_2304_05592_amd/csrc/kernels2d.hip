@@ -177,23 +177,22 @@ __device__ __forceinline__ float* fbuf(unsigned char* ws, const ShotDev& S, int 
   return reinterpret_cast<float*>(ws + S.fld) + (long long)b * S.npts;
 }
 
-// Where a forward step reads level k of shot S.  With the FULL FP32 store every level is kept
-// bit for bit in the store, so the steps read their two previous levels from it (written by
-// the launch before, with ordinary stores that leave them in the caches) and the rotating
-// buffers are not needed; otherwise the rotating buffers, or a checkpoint slot restored by
-// reference.
+// Where a one-level forward step reads level k of shot S.  kStoreF32R: the FULL FP32 store keeps
+// every level bit for bit, so the step reads its two previous levels from it (written by the
+// launch before, with ordinary stores that leave them in the caches) and the rotating buffers
+// are not needed; otherwise the rotating buffers, or a checkpoint slot restored by reference.
 template <int SK>
 __device__ __forceinline__ const float* fwd_src(const StepArgs& a, const ShotDev& S, int k) {
-  if (SK == kStoreF32) return reinterpret_cast<const float*>(a.ws + S.store) + (long long)k * S.npts;
+  if (SK == kStoreF32R) return reinterpret_cast<const float*>(a.ws + S.store) + (long long)k * S.npts;
   return fwd_level(a, S, k);
 }
 
-// Bytes of the rotating buffer a forward step writes level k into: with the FULL FP32 store only
+// Bytes of the rotating buffer a one-level forward step writes level k into: with kStoreF32R only
 // the last level goes there too (the receivers' last sample is taken from it), so the other
 // levels' buffer stores are dropped by the range check.
 template <int SK>
 __device__ __forceinline__ int fwd_ring_bytes(const ShotDev& S, int k, int bytes) {
-  return SK != kStoreF32 || k == S.nt - 1 ? bytes : 0;
+  return SK != kStoreF32R || k == S.nt - 1 ? bytes : 0;
 }
 
 // ------------------------------------------------------------------------------ forward
@@ -248,7 +247,8 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
   const float sw0 = S.src_w[0], sw1 = S.src_w[1], sw2 = S.src_w[2], sw3 = S.src_w[3];
   const long long npts = S.npts;
   // FULL store: level k (FP32) or level k-1 (16 bits, quantised with its finished scale)
-  const brsrc rst = SK == kStoreF32
+  constexpr bool F32 = SK == kStoreF32 || SK == kStoreF32R;
+  const brsrc rst = F32
       ? make_rsrc(reinterpret_cast<float*>(a.ws + S.store) + (long long)k * npts, nz * row4)
       : make_rsrc(reinterpret_cast<unsigned short*>(a.ws + S.store) + (long long)(k - 1) * npts,
                   SK == kStoreBF16 || SK == kStoreFP16 ? nz * row4 / 2 : 0);
@@ -288,7 +288,10 @@ __global__ __launch_bounds__(T2<TZ>::NT) void fwd2d_kernel(StepArgs a) {
       stb(rsl0, un, cx, zo);
       stb(rsl1, u, cx, zo);
     }
-    if (SK == kStoreF32) stb(rst, un, cx, zo);
+    // a stored level the next launch reads back stays in the caches; otherwise it is written once
+    // and read thousands of launches later
+    if (SK == kStoreF32) stb_nt(rst, un, cx, zo);
+    if (SK == kStoreF32R) stb(rst, un, cx, zo);
     if (S16) {
       lmax = fmaxf(lmax, fabsf(un));
       if (k >= 2) stb16_nt(rst, enc16(u * inv_prev, SK == kStoreBF16), cx2, zo / 2);
@@ -584,13 +587,15 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
   const int nx = S.nx, nz = S.nz, px = S.px;
   const int row4 = 4 * px;
   // levels below 1 are zero (see fwd2d_kernel)
-  const Planes u1 = planes(fwd_src<SK>(a, S, k - 1), nz, k >= 2 ? nz : 0, row4);
-  const Planes u2 = planes(fwd_src<SK>(a, S, k - 2), nz, k >= 3 ? nz : 0, row4);
+  // (two-level launches never follow a restore by reference: the rotating buffers hold the
+  // previous levels)
+  const Planes u1 = planes(fbuf(a.ws, S, fwd_buf(k - 1)), nz, k >= 2 ? nz : 0, row4);
+  const Planes u2 = planes(fbuf(a.ws, S, fwd_buf(k - 2)), nz, k >= 3 ? nz : 0, row4);
   const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
   const long long npts = S.npts;
   // new levels k and k+1 (a level outside 1..nt-1 belongs to an inactive step: no records)
-  const brsrc ro1 = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), act1 ? fwd_ring_bytes<SK>(S, k, nz * row4) : 0);
-  const brsrc ro2 = make_rsrc(fbuf(a.ws, S, fwd_buf(k + 1)), act2 ? fwd_ring_bytes<SK>(S, k + 1, nz * row4) : 0);
+  const brsrc ro1 = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), act1 ? nz * row4 : 0);
+  const brsrc ro2 = make_rsrc(fbuf(a.ws, S, fwd_buf(k + 1)), act2 ? nz * row4 : 0);
   float* st = reinterpret_cast<float*>(a.ws + S.store);
   const brsrc rs1 = make_rsrc(st + (long long)(SK == kStoreF32 ? k : 0) * npts,
                               SK == kStoreF32 && act1 ? nz * row4 : 0);
@@ -653,7 +658,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     // body slots on tile rows store level k (wave-uniform condition; columns outside drop)
     if (i < G::NB && r >= kHalo && r < kHalo + TZ) {
       stb(ro1, v, cx, z * row4);
-      if (SK == kStoreF32) stb(rs1, v, cx, z * row4);
+      if (SK == kStoreF32) stb_nt(rs1, v, cx, z * row4);
       if (PRB) INC1[r - kHalo][c - kHalo] = incr;
     }
     LE[r][c] = v;
@@ -691,7 +696,7 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
     const float incr = step_incr(u, um2, tcf[i], lap, eta);
     const float un = (u + u - um2) + incr;
     stb(ro2, un, cx, z * row4);
-    if (SK == kStoreF32) stb(rs2, un, cx, z * row4);
+    if (SK == kStoreF32) stb_nt(rs2, un, cx, z * row4);
     if (PRB && x < nx && z < nz) {
       // the same two FP64 additions, in the same order, as two one-level launches
       const long long p = (long long)z * px + x;
@@ -848,25 +853,30 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
     const int z = T.z0 + lr;
     double ac = IACC ? pacc[i] : 0.0;
     if (IACC && act1) ac = ac + (double)pu1[i] * (double)INC1[lr][lane];
-    const float w = LE[lr + kHalo][lane + kHalo];  // level j on the tile
-    float wn = 0.f;
+    float wj = 0.f, wn = 0.f;  // probe: levels j and j-1 on the tile
     if (act2) {
       const float* pc = &LE[lr + kHalo][lane + kHalo];
+      const float w = pc[0];
       const float wm2 = L1[lr + 2 * kHalo][lane + 2 * kHalo];
       float lap = lap_ptr(pc, G::WE, a.c);
       if (inj2) lap += INJ2[lr][lane];
       const int dz = border_dist(z, nz, a.nbl);
       const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
       const float incr = step_incr(w, wm2, tcf[i], lap, eta);
-      wn = (w + w - wm2) + incr;
-      stb(ro2, wn, cx, z * row4);
+      stb(ro2, (w + w - wm2) + incr, cx, z * row4);
       if (IACC) ac = ac + (double)pu2[i] * (double)incr;
+      if (IMG == kImgProbe) {
+        wj = w;
+        wn = (w + w - wm2) + incr;
+      }
+    } else if (IMG == kImgProbe) {
+      wj = LE[lr + kHalo][lane + kHalo];
     }
     if (IACC) stb64(racc, ac, cx8, 2 * z * row4);
     if (IMG == kImgProbe && x < nx && z < nz) {
       // the same two FP64 additions, in the same order, as two one-level launches
       const long long p = (long long)z * px + x;
-      probe_add(probe_sums(pa, p, a.probe_r), a.probe_r, pc1, (double)w, act1, pc2, (double)wn, act2, a.probe_pitch);
+      probe_add(probe_sums(pa, p, a.probe_r), a.probe_r, pc1, (double)wj, act1, pc2, (double)wn, act2, a.probe_pitch);
     }
   }
 }
@@ -876,6 +886,7 @@ hipError_t fwd2d_tz(const StepArgs& a, int store, hipStream_t s) {
   switch (store) {
     case kStoreNone: fwd2d_kernel<TZ, kStoreNone><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kStoreF32: fwd2d_kernel<TZ, kStoreF32><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
+    case kStoreF32R: fwd2d_kernel<TZ, kStoreF32R><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kStoreBF16: fwd2d_kernel<TZ, kStoreBF16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kStoreFP16: fwd2d_kernel<TZ, kStoreFP16><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
     case kStoreProbe: fwd2d_kernel<TZ, kStoreProbe><<<a.ntiles, T2<TZ>::NT, 0, s>>>(a); break;
