@@ -51,8 +51,7 @@ BYTES = {
 # written): reported beside the algorithmic figure, not used for the roofline fraction.
 FUSED_BYTES = {
     ("forward", "none"): 20,   # read u^{k-1}, u^{k-2}, coef; write u^k, u^{k+1}
-    ("forward", "fp32"): 20,   # read stored u^{k-1}, u^{k-2}, coef; write stored u^k, u^{k+1} (the
-                               # FULL FP32 store serves as the forward's previous levels)
+    ("forward", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
     ("adjoint", "none"): 20,   # read w^{j+1}, w^{j+2}, coef; write w^j, w^{j-1}
     ("adjoint", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
 }
