@@ -63,14 +63,15 @@ def test_born_fixture_trace_prefix(shot, n):
 
 def test_fp32_floor_record_supports_the_gpu_gates():
     """The float32-emulated oracle's rounding floor (written by measure_fp32_floor.py, oracle
-    only) is what the GPU gates lean on: the Born trace bar of 2e-5 and the probed-gradient bar of
-    1.5e-4 sit below the operators' float32 floors, and the dot-test bar of 1e-5 above the float32
+    only) is what the GPU gates lean on: the Born trace bar of 2e-5 and the probed-gradient bars of
+    1.5e-4 (2D) and 3e-5 (the 3D crop) sit below the operators' float32 floors, and the dot-test bar of 1e-5 above the float32
     dot-test floors; FP64 dot tests are exact to 1e-12."""
     import json
     rec = json.load(open(os.path.join(GOLD, "fp32_floor.json")))
     assert rec["c2_grad"]["born_traces_rel_l2"] > 2e-5
     assert rec["c2_grad"]["forward_traces_rel_l2"] > 1e-5
     assert rec["c9_probed"]["gradient_rel_l2"] > 1.5e-4      # the full-size probed gradient's bar
+    assert rec["c9_probed_crop"]["gradient_rel_l2"] > 3e-5   # the 3D crop's probed gradient's bar
     dots = rec["small_2d_dot_tests"]
     assert dots["F_dot_rel_fp32"] < 1e-5 and dots["J_dot_rel_fp32"] < 1e-5
     assert dots["F_dot_rel_fp64"] < 1e-12 and dots["J_dot_rel_fp64"] < 1e-12
