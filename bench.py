@@ -542,25 +542,34 @@ def bench_c3(args):
     for _ in range(args.warmup):
         step()
     sync()
-    plan.profile_enable(wl.shots[0].nt * args.steps + 64, 8)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         loss, g = step()
     sync()
     sec = (time.perf_counter() - t0) / args.steps
+    # kernel timing in one more step: every checkpoint advance is one timed interval (its forward
+    # steps back to back, no event between them), every adjoint step another; sampled evenly
+    sched = A.checkpoint_schedule(wl.shots[0].nt - 1, 16)
+    fwd_steps = int(sum(b - a for op, a, b in sched if op == 0))   # forward steps per gradient
+    intervals = groups * (sum(1 for op, _, _ in sched if op == 0) + wl.shots[0].nt)
+    plan.profile_enable(min(intervals, MAX_TIMED_LAUNCHES), -(-intervals // MAX_TIMED_LAUNCHES))
+    step()
+    sync()
     prof = plan.profile_read()
+    plan.profile_disable()
     kernels = kernel_table(prof, launch_points, {"forward": "none", "adjoint": "buffers"})
     names = {"forward": "fwd2d step (forward / recompute, 16 B/point)",
              "adjoint": "adj2d step (adjoint + imaging from recomputed buffers, 36 B/point)"}
-    sched = A.checkpoint_schedule(wl.shots[0].nt - 1, 16)
-    fwd_steps = int(sum(b - a for op, a, b in sched if op == 0))   # forward steps per gradient
     return base_line(args, wl, points / sec / 1e9, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "CHECKPOINT 16 FP32 slots",
                    "batched": True, "graph": False, "tiles": tiles, "shot_groups": groups},
         "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
         "forward_steps_per_gradient": fwd_steps,
-        "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item())})
+        "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item()),
+        "kernel_timing": "value from eager steps without events; kernels from one more eager step, "
+                         "HIP events around each checkpoint advance (its forward launches back to back) "
+                         "and around each adjoint launch, sampled evenly"})
 
 
 def counter_step(args):

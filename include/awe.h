@@ -358,12 +358,15 @@ awe_status awe_plan_set_fusion(awe_plan* plan, int32_t mode);
 
 /* Kernel timing (measurement aid).  After awe_profile_enable, every stride-th time-step
  * launch of the compute calls on this plan is bracketed by a pair of HIP events recorded on
- * the call's stream, for up to max_launches timed launches; further launches are not timed.
+ * the call's stream, for up to max_launches timed intervals; further launches are not timed.
+ * The forward steps of one checkpoint advance (a run of consecutive steps of the recomputing
+ * sweeps) form one interval, which counts every launch it holds, so that no event is recorded
+ * between them.
  * The records are stream work, so they are also captured into a HIP graph and then time
  * the graph's replays.  Classes: 0 forward step, 1 adjoint step (with imaging and, in 3D,
  * receiver injection), 2 Born step.  awe_profile_read waits for the recorded events,
- * returns per class the number of timed launches and the summed event time in ms, and
- * restarts the count.  Enabling creates HIP events (host resources, no device memory). */
+ * returns per class the number of timed launches and the summed time of their intervals in ms,
+ * and restarts the count.  Enabling creates HIP events (host resources, no device memory). */
 awe_status awe_profile_enable(awe_plan* plan, int64_t max_launches, int32_t stride);
 awe_status awe_profile_read(awe_plan* plan, int64_t counts[3], double ms[3]);
 awe_status awe_profile_disable(awe_plan* plan);

@@ -119,6 +119,9 @@ struct awe_plan {
   // kernel timing
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_cls;
+  std::vector<long long> prof_cnt;  // launches inside each timed interval
+  bool prof_in_run = false;         // inside a timed run of forward steps (see ProfRun)
+  long long prof_run_launches = 0;
   size_t prof_next = 0;
   int prof_stride = 1;
   long long prof_seen = 0;
@@ -571,16 +574,48 @@ struct ProfScope {
   hipStream_t s;
   bool on;
   ProfScope(awe_plan* P_, int cls, hipStream_t s_) : P(P_), s(s_) {
+    if (P->prof_in_run) {  // counted into the enclosing run's interval
+      ++P->prof_run_launches;
+      on = false;
+      return;
+    }
     on = P->prof_next + 2 <= P->prof_ev.size() && (P->prof_seen++ % P->prof_stride) == 0;
     if (on) {
       (void)hipEventRecord(P->prof_ev[P->prof_next], s);
       P->prof_cls.push_back(cls);
+      P->prof_cnt.push_back(1);
     }
   }
   ~ProfScope() {
     if (on) {
       (void)hipEventRecord(P->prof_ev[P->prof_next + 1], s);
       P->prof_next += 2;
+    }
+  }
+};
+
+// A run of consecutive forward steps (a checkpoint advance) timed as one interval: one event
+// pair for the whole run instead of one per launch, whose recording would add its dispatch
+// latency to every launch; the run's launches are counted into it.
+struct ProfRun {
+  awe_plan* P;
+  hipStream_t s;
+  bool on;
+  ProfRun(awe_plan* P_, hipStream_t s_) : P(P_), s(s_) {
+    on = !P->prof_in_run && P->prof_next + 2 <= P->prof_ev.size() && (P->prof_seen++ % P->prof_stride) == 0;
+    if (on) {
+      (void)hipEventRecord(P->prof_ev[P->prof_next], s);
+      P->prof_in_run = true;
+      P->prof_run_launches = 0;
+    }
+  }
+  ~ProfRun() {
+    if (on) {
+      (void)hipEventRecord(P->prof_ev[P->prof_next + 1], s);
+      P->prof_cls.push_back(0);
+      P->prof_cnt.push_back(P->prof_run_launches);
+      P->prof_next += 2;
+      P->prof_in_run = false;
     }
   }
 };
@@ -733,6 +768,7 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
             P->sched[3 * (i + 1) + 2] == y &&
             !(fa.rs_level != awe::kNoLevel && fa.rs_slot == P->sched[3 * (i + 1) + 1]))
           fuse_slot = P->sched[3 * (i + 1) + 1];
+        ProfRun run(P, s);
         for (int n = x + 1; n <= y; ++n) {
           fa.st_slot = n == y ? fuse_slot : -1;
           awe_status st = step_fwd(P, fa, n, 0, s);
@@ -1489,6 +1525,8 @@ awe_status awe_profile_enable(awe_plan* P, int64_t max_launches, int32_t stride)
   for (hipEvent_t e : P->prof_ev) (void)hipEventDestroy(e);
   P->prof_ev.clear();
   P->prof_cls.clear();
+  P->prof_cnt.clear();
+  P->prof_in_run = false;
   P->prof_next = 0;
   P->prof_ev.resize(2 * (size_t)max_launches, nullptr);
   for (auto& e : P->prof_ev) AWE_HIP(hipEventCreate(&e));
@@ -1506,12 +1544,13 @@ awe_status awe_profile_read(awe_plan* P, int64_t counts[3], double ms[3]) {
     float t = 0.f;
     AWE_HIP(hipEventElapsedTime(&t, P->prof_ev[2 * i], P->prof_ev[2 * i + 1]));
     const int c = P->prof_cls[i];
-    counts[c] += 1;
+    counts[c] += P->prof_cnt[i];
     ms[c] += t;
   }
   P->prof_next = 0;
   P->prof_seen = 0;
   P->prof_cls.clear();
+  P->prof_cnt.clear();
   return AWE_OK;
 }
 
@@ -1520,6 +1559,8 @@ awe_status awe_profile_disable(awe_plan* P) {
   for (hipEvent_t e : P->prof_ev) (void)hipEventDestroy(e);
   P->prof_ev.clear();
   P->prof_cls.clear();
+  P->prof_cnt.clear();
+  P->prof_in_run = false;
   P->prof_next = 0;
   return AWE_OK;
 }

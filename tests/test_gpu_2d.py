@@ -344,3 +344,28 @@ def test_checkpointed_gradient_with_uneven_nt_is_bitwise_the_full_storage_gradie
     for g, v in out[1:]:
         assert torch.equal(g, out[0][0])
         assert torch.equal(v, out[0][1])
+
+
+def test_kernel_timing_counts_every_step_launch_of_a_checkpointed_gradient():
+    """With kernel timing on, each checkpoint advance is one timed interval that counts its
+    forward launches and each adjoint launch another: a checkpointed gradient of two equal shots
+    (one shot group) reports exactly the schedule's forward steps and nt - 1 adjoint steps, with
+    positive times, and the same gradient bits as without timing."""
+    wl = W.small_2d(windows=[90, 90], T_per_shot=[200.0, 200.0])
+    dds = _residuals(wl)
+    plan = make_plan(wl, storage=A.Storage(A.STORE_CHECKPOINT, 4))
+    m, q = gpu_inputs(wl, plan)
+    dd = plan.pack(dds, "d")
+    ref = plan.gradient(m, q, dd)[0].clone()
+    nt = wl.shots[0].nt
+    sched = A.checkpoint_schedule(nt - 1, 4)
+    fwd_steps = int(sum(b - a for op, a, b in sched if op == 0))
+    plan.profile_enable(4 * nt, 1)
+    g = plan.gradient(m, q, dd)[0]
+    prof = plan.profile_read()
+    plan.profile_disable()
+    _sync()
+    print(f"timed launches: {prof}; schedule forward steps {fwd_steps}", flush=True)
+    assert prof["forward"][0] == fwd_steps and prof["adjoint"][0] == nt - 1
+    assert prof["forward"][1] > 0 and prof["adjoint"][1] > 0
+    assert torch.equal(g, ref)
