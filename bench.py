@@ -265,8 +265,8 @@ def roofline_of(kernels, names, fused_bytes=False):
 
 def timed_gradient(run, args, kind):
     """Time the gradient step of a GradientRunner.  Region 1: one to three eager steps with HIP
-    events around every launch (per-launch durations; each event pair adds the dispatch latency
-    of one extra command).  Region 2 (headline, unless --no-graph): the step as two HIP graphs,
+    events around each sweep's step loop (the library's kernel timing: interval / launches, no
+    event between launches).  Region 2 (headline, unless --no-graph): the step as two HIP graphs,
     forward sweep + residual and reverse sweep, replayed back to back for args.steps steps with
     HIP events between the segments; a kernel's average is its segment's time divided by its
     launches.  Returns (seconds per step, eager seconds per step, kernel table, timing note)."""
@@ -275,7 +275,7 @@ def timed_gradient(run, args, kind):
     kernels = kernel_table(prof, run.launch_points, {"forward": kind, "adjoint": kind},
                            fused=fusion_of(run.tiles))
     if args.no_graph:
-        return eager_sec, eager_sec, kernels, "HIP events around every launch of the eager timed steps"
+        return eager_sec, eager_sec, kernels, "HIP events around each sweep's step loop of the eager timed steps"
     run.capture()
     sec, seg = run.run(args.steps, args.warmup, use_graph=True, profile=True)
     nsteps = max(run.wl.shots[i].nt for i in run.shots) - 1
@@ -290,8 +290,8 @@ def timed_gradient(run, args, kind):
         k["segment_ms"] = round(sum(seg[key]) / len(seg[key]), 3)
     timing = ("HIP events on the launch stream between two graph segments (forward sweep + residual; "
               "reverse sweep) of every timed step: segment time / launches of its step kernel (the "
-              "segment's auxiliary kernels included); eager_event_us = events around every launch "
-              "of an eager step")
+              "segment's auxiliary kernels included); eager_event_us = events around each sweep's step "
+              "loop of an eager step, interval / launches")
     return sec, eager_sec, kernels, timing
 
 
@@ -363,18 +363,15 @@ class GradientRunner:
             ev[2].record()
 
     def run(self, steps, warmup, use_graph, profile):
-        """Seconds per step and, with profile: eager = per-launch event summary; graph = event
+        """Seconds per step and, with profile: eager = kernel-timing summary; graph = event
         time of the two graph segments per step ({'forward_ms': [...], 'backward_ms': [...]})."""
         torch = self.torch
         for _ in range(warmup):
             self.replay() if use_graph else self.step()
         sync()
         if profile and not use_graph:
-            nt = max(self.wl.shots[i].nt for i in self.shots)
-            launches = 2 * nt * steps * self.groups + 64
-            # at most MAX_TIMED_LAUNCHES event pairs: every stride-th launch is timed
-            stride = -(-launches // MAX_TIMED_LAUNCHES)
-            self.plan.profile_enable(-(-launches // stride), stride)
+            # one timed interval per sweep (forward, reverse) of each shot group and step
+            self.plan.profile_enable(2 * steps * self.groups + 64, 1)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)] \
             if profile and use_graph else None
         sync()
@@ -892,8 +889,7 @@ def bench_c9(args, base="c2_grad"):
     FUSED_BYTES[("forward", kind)] = FUSED_BYTES[("forward", "none")] + 16 * r
     FUSED_BYTES[("adjoint", kind)] = FUSED_BYTES[("adjoint", "none")] + 16 * r
     fused = fusion_of(tiles)
-    n_launch = 2 * groups * max_nt
-    plan.profile_enable(min(n_launch, MAX_TIMED_LAUNCHES), -(-n_launch // MAX_TIMED_LAUNCHES))
+    plan.profile_enable(2 * groups + 64, 1)   # one interval per sweep of each shot group
     call()
     prof = plan.profile_read()
     plan.profile_disable()
@@ -925,7 +921,8 @@ def bench_c9(args, base="c2_grad"):
         "workspace_bytes": plan.ws_bytes, "full_storage_workspace_bytes": full_ws,
         "full_storage_precision": "fp32" if wl.ndim == 2 else "bf16",
         "roofline": roofline_of(kernels, names, fused_bytes=True), "cpu_baseline": None, "kernels": kernels,
-        "kernel_timing": "HIP events around every launch of one eager call; value from graph replays",
+        "kernel_timing": "HIP events around each sweep's step loop of one eager call (interval / "
+                         "launches); value from graph replays",
         "g_norm": float(g.norm().item())})
 
 
@@ -963,7 +960,7 @@ def bench_c4(args):
         graph.replay()
     sync()
     sec = (time.perf_counter() - t0) / args.steps
-    # kernel durations: one eager pass with HIP events around every launch
+    # kernel durations: one eager pass with HIP events around each shot group's step loop
     plan.profile_enable(groups * nt_max + 64, 1)   # one launch per step and shot group
     plan.forward(m, q, d=d, ws=ws)
     prof = plan.profile_read()
@@ -998,7 +995,7 @@ def bench_c4(args):
                      "frac": None if ach is None else round(ach / PEAK_HBM_GBS, 4), "traffic": None,
                      "kernel": ("fwd2d2 (two levels per launch, 16 B per point-update; the launch itself "
                                 "moves 20 B per point)" if fused else "fwd2d step (16 B per point-update)")
-                               + "; summed event time of one eager pass"},
+                               + "; event time of each shot group's step loop in one eager pass"},
         "sequential_single_shot": {"value": round(points / seq / 1e9, 3), "seconds": round(seq, 4)},
         "cpu_baseline": None})
 

@@ -359,9 +359,10 @@ awe_status awe_plan_set_fusion(awe_plan* plan, int32_t mode);
 /* Kernel timing (measurement aid).  After awe_profile_enable, every stride-th time-step
  * launch of the compute calls on this plan is bracketed by a pair of HIP events recorded on
  * the call's stream, for up to max_launches timed intervals; further launches are not timed.
- * The forward steps of one checkpoint advance (a run of consecutive steps of the recomputing
- * sweeps) form one interval, which counts every launch it holds, so that no event is recorded
- * between them.
+ * The steps of one sweep (the forward or the adjoint step loop of a call, per shot group) and
+ * the forward steps of one checkpoint advance each form one interval, which counts every launch
+ * it holds, so that no event is recorded between them; other step launches are timed one by
+ * one.
  * The records are stream work, so they are also captured into a HIP graph and then time
  * the graph's replays.  Classes: 0 forward step, 1 adjoint step (with imaging and, in 3D,
  * receiver injection), 2 Born step.  awe_profile_read waits for the recorded events,

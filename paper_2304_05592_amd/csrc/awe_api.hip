@@ -594,14 +594,16 @@ struct ProfScope {
   }
 };
 
-// A run of consecutive forward steps (a checkpoint advance) timed as one interval: one event
-// pair for the whole run instead of one per launch, whose recording would add its dispatch
-// latency to every launch; the run's launches are counted into it.
+// A run of consecutive time steps of one class (a sweep's step loop, a checkpoint advance)
+// timed as one interval: one event pair for the whole run instead of one per launch, whose
+// recording would add its dispatch latency to every launch; the run's launches are counted
+// into it.
 struct ProfRun {
   awe_plan* P;
   hipStream_t s;
+  int cls;
   bool on;
-  ProfRun(awe_plan* P_, hipStream_t s_) : P(P_), s(s_) {
+  ProfRun(awe_plan* P_, hipStream_t s_, int cls_) : P(P_), s(s_), cls(cls_) {
     on = !P->prof_in_run && P->prof_next + 2 <= P->prof_ev.size() && (P->prof_seen++ % P->prof_stride) == 0;
     if (on) {
       (void)hipEventRecord(P->prof_ev[P->prof_next], s);
@@ -612,7 +614,7 @@ struct ProfRun {
   ~ProfRun() {
     if (on) {
       (void)hipEventRecord(P->prof_ev[P->prof_next + 1], s);
-      P->prof_cls.push_back(0);
+      P->prof_cls.push_back(cls);
       P->prof_cnt.push_back(P->prof_run_launches);
       P->prof_next += 2;
       P->prof_in_run = false;
@@ -688,6 +690,7 @@ awe_status forward_loop(awe_plan* P, awe::StepArgs& a, int store, hipStream_t s)
                     (store == awe::kStoreNone || store == awe::kStoreF32 || store == awe::kStoreProbe);
   // a 2D FP32 sweep of one-level steps reads its previous levels back from the store
   if (!fuse && P->ndim == 2 && store == awe::kStoreF32) store = awe::kStoreF32R;
+  ProfRun run(P, s, 0);
   int n = 1;
   if (fuse && (P->nsteps & 1)) {
     if ((st = step_fwd(P, a, 1, store, s)) != AWE_OK) return st;
@@ -705,6 +708,7 @@ awe_status adjoint_loop(awe_plan* P, awe::StepArgs& a, hipStream_t s) {
   awe_status st;
   const bool fuse = fused_ok(P, AWE_FUSE_ADJOINT) &&
                     (a.image_src == awe::kImgNone || a.image_src == awe::kImgFull32 || a.image_src == awe::kImgProbe);
+  ProfRun run(P, s, 1);
   int n = P->nsteps;
   if (fuse && (P->nsteps & 1)) {
     if ((st = step_adj(P, a, n, s)) != AWE_OK) return st;
@@ -768,7 +772,7 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
             P->sched[3 * (i + 1) + 2] == y &&
             !(fa.rs_level != awe::kNoLevel && fa.rs_slot == P->sched[3 * (i + 1) + 1]))
           fuse_slot = P->sched[3 * (i + 1) + 1];
-        ProfRun run(P, s);
+        ProfRun run(P, s, 0);
         for (int n = x + 1; n <= y; ++n) {
           fa.st_slot = n == y ? fuse_slot : -1;
           awe_status st = step_fwd(P, fa, n, 0, s);

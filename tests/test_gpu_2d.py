@@ -350,7 +350,8 @@ def test_kernel_timing_counts_every_step_launch_of_a_checkpointed_gradient():
     """With kernel timing on, each checkpoint advance is one timed interval that counts its
     forward launches and each adjoint launch another: a checkpointed gradient of two equal shots
     (one shot group) reports exactly the schedule's forward steps and nt - 1 adjoint steps, with
-    positive times, and the same gradient bits as without timing."""
+    positive times, and the same gradient bits as without timing.  With FULL storage each sweep
+    is one interval and counts its (two-level) launches."""
     wl = W.small_2d(windows=[90, 90], T_per_shot=[200.0, 200.0])
     dds = _residuals(wl)
     plan = make_plan(wl, storage=A.Storage(A.STORE_CHECKPOINT, 4))
@@ -369,3 +370,14 @@ def test_kernel_timing_counts_every_step_launch_of_a_checkpointed_gradient():
     assert prof["forward"][0] == fwd_steps and prof["adjoint"][0] == nt - 1
     assert prof["forward"][1] > 0 and prof["adjoint"][1] > 0
     assert torch.equal(g, ref)
+    # FULL storage: each sweep's step loop is one interval; two levels per launch in both
+    full = make_plan(wl, storage=A.Storage(A.STORE_FULL))
+    full.set_tiles(tz=16)
+    full.set_fusion(A.FUSE_BOTH)
+    full.profile_enable(8, 1)
+    full.gradient(m, q, dd)
+    prof = full.profile_read()
+    full.profile_disable()
+    _sync()
+    launches = (nt - 1) // 2 + (nt - 1) % 2
+    assert prof["forward"][0] == launches and prof["adjoint"][0] == launches, prof
