@@ -181,9 +181,9 @@ def choose_pass_tiles(plan, args, run, fusions=(0,)):
     if args.tiles or args.no_autotune:
         return choose_tiles(plan, args, None, None, None)
     best = None
-    for tz in (8, 16, 32, 64):
+    for tz in (8, 16, 24, 32, 64):
         for fu in fusions:
-            if fu and tz == 64:                # two-level kernels exist for 8, 16, 32 rows
+            if fu and tz == 64:                # two-level kernels exist for 8, 16, 24, 32 rows
                 continue
             plan.set_tiles(tz)
             plan.set_fusion(fu)

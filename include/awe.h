@@ -295,8 +295,8 @@ awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* acti
 
 /* Tile-shape autotuner (setup call, synchronous).  The plan has a launch shape for its forward
  * solves (and Born modelling) and one for its adjoint steps (reverse sweeps and awe_adjoint); the
- * autotuner chooses each separately.  Candidates: 2D 8, 16, 32 or 64 rows of 64 columns, and -
- * where the storage mode allows it - 8, 16 or 32 rows with two time levels per launch (see
+ * autotuner chooses each separately.  Candidates: 2D 8, 16, 24, 32 or 64 rows of 64 columns, and -
+ * where the storage mode allows it - 8, 16, 24 or 32 rows with two time levels per launch (see
  * awe_plan_set_fusion); 3D 64 x {4, 8, 16} columns with z-blocks of the full depth, of 128, 64 or
  * 32 planes, and of the depth split evenly in 2 to 8 (rounded up to an even plane count).  The forward probe times the last probe_steps forward levels of the sweep (storing
  * the wavefield when the plan keeps one in FP32), the adjoint probe the last probe_steps adjoint
@@ -351,7 +351,7 @@ awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz
  * storage, with FULL FP32 storage or into PROBED sums, and reverse sweeps from FULL FP32
  * storage, into PROBED sums or without imaging; other modes always use one level per launch.
  * Results are bitwise identical either way (a two-level launch adds both levels' terms to an
- * FP64 sum in the order two launches would).  Two levels per launch need tiles of 8, 16 or 32 rows (16 or 32 are set
+ * FP64 sum in the order two launches would).  Two levels per launch need tiles of 8, 16, 24 or 32 rows (16 or 32 are set
  * otherwise).  Errors: INVALID_ARG (mode outside 0..3), HIP. */
 enum { AWE_FUSE_NONE = 0, AWE_FUSE_FORWARD = 1, AWE_FUSE_ADJOINT = 2, AWE_FUSE_BOTH = 3 };
 awe_status awe_plan_set_fusion(awe_plan* plan, int32_t mode);

@@ -677,10 +677,12 @@ awe_status step_adj2(awe_plan* P, awe::StepArgs& a, int n, hipStream_t s) {
   return AWE_OK;
 }
 
-// Two-level kernels exist for 8, 16 and 32 rows (2D).
+// Two-level kernels exist for 8, 16, 24 and 32 rows (2D).
+bool two_level_rows(int tz) { return tz == 8 || tz == 16 || tz == 24 || tz == 32; }
+
 bool fused_ok(const awe_plan* P, int bit) {
   const int tz = bit == AWE_FUSE_FORWARD ? P->fw.tz : P->rv.tz;
-  return P->ndim == 2 && (P->fuse2 & bit) && (tz == 8 || tz == 16 || tz == 32);
+  return P->ndim == 2 && (P->fuse2 & bit) && two_level_rows(tz);
 }
 
 // Forward levels 1..nsteps: one single step first when the count is odd, then pairs.
@@ -905,8 +907,8 @@ bool apply_tune_entry(awe_plan* P, const TuneEntry& e, awe_status* st) {
   for (const int* t : {e.fw, e.rv})
     if (!valid_tz(t[0]) || (t[1] != 4 && t[1] != 8 && t[1] != 16) || t[2] < 0) return false;
   if (e.fusion < 0 || e.fusion > AWE_FUSE_BOTH) return false;
-  if ((e.fusion & AWE_FUSE_FORWARD) && e.fw[0] != 8 && e.fw[0] != 16 && e.fw[0] != 32) return false;
-  if ((e.fusion & AWE_FUSE_ADJOINT) && e.rv[0] != 8 && e.rv[0] != 16 && e.rv[0] != 32) return false;
+  if ((e.fusion & AWE_FUSE_FORWARD) && !two_level_rows(e.fw[0])) return false;
+  if ((e.fusion & AWE_FUSE_ADJOINT) && !two_level_rows(e.rv[0])) return false;
   P->fw.tz = e.fw[0];
   P->fw.ty = e.fw[1];
   P->fw.bz = e.fw[2];
@@ -1319,7 +1321,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   const bool fusable = P->store.mode == AWE_STORE_NONE || P->store.mode == AWE_STORE_PROBED ||
                        (P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32);
   if (P->ndim == 2) {
-    for (int tz : {8, 16, 32, 64}) {
+    for (int tz : {8, 16, 24, 32, 64}) {
       cands.push_back({tz, 8, 0, 0});
       if (fusable && tz != 64) cands.push_back({tz, 8, 0, 1});
     }
@@ -1512,11 +1514,11 @@ awe_status awe_plan_set_fusion(awe_plan* P, int32_t mode) {
   if (!P) return fail(AWE_ERR_INVALID_ARG, "plan is NULL");
   if (mode < 0 || mode > AWE_FUSE_BOTH) return fail(AWE_ERR_INVALID_ARG, "fusion mode must be 0..3");
   P->fuse2 = mode;
-  // two-level kernels exist for 8, 16 and 32 rows
+  // two-level kernels exist for 8, 16, 24 and 32 rows
   awe_status st = AWE_OK;
   for (int bit : {AWE_FUSE_FORWARD, AWE_FUSE_ADJOINT}) {
     Tiling& T = bit == AWE_FUSE_FORWARD ? P->fw : P->rv;
-    if ((mode & bit) && T.tz != 8 && T.tz != 16 && T.tz != 32)
+    if ((mode & bit) && !two_level_rows(T.tz))
       if ((st = awe_plan_set_tiles_dir(P, bit, T.tz < 24 ? 16 : 32, T.ty, T.bz)) != AWE_OK) return st;
   }
   return st;

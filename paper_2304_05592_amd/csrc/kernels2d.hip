@@ -938,6 +938,7 @@ hipError_t launch_fwd2d2(const StepArgs& a, int tz, int store, hipStream_t s) {
   switch (tz) {
     case 8: return fwd2d2_tz<8>(a, store, s);
     case 16: return fwd2d2_tz<16>(a, store, s);
+    case 24: return fwd2d2_tz<24>(a, store, s);
     case 32: return fwd2d2_tz<32>(a, store, s);
   }
   return hipErrorInvalidValue;
@@ -948,6 +949,7 @@ hipError_t launch_adj2d2(const StepArgs& a, int tz, hipStream_t s) {
   switch (tz) {
     case 8: return adj2d2_tz<8>(a, s);
     case 16: return adj2d2_tz<16>(a, s);
+    case 24: return adj2d2_tz<24>(a, s);
     case 32: return adj2d2_tz<32>(a, s);
   }
   return hipErrorInvalidValue;

@@ -79,6 +79,18 @@ def test_failure_paths_on_the_cpu_build(emu_lib):
     assert r.stdout.strip().splitlines()[-1] == "CASE OK"
 
 
+def test_two_level_tile_heights_on_the_cpu_build(emu_lib):
+    """Two levels per launch at 8, 16, 24 and 32 rows (2D, FULL FP32, uneven batch) under
+    AddressSanitizer with the host launch checks on: bitwise the one-level gradient, traces and
+    F^T dd, which match the oracle."""
+    import driver
+    r = driver.run([os.path.join(EMU, "case_two_level.py")], emu_lib, timeout=900)
+    assert r.returncode == 0, r.stderr[-4000:]
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    print(res)
+    assert all(res["bitwise"].values()) and res["grad_rel"] <= 1e-5
+
+
 def test_probed_gradient_on_the_cpu_build(emu_lib):
     """PROBED storage on an uneven 2D batch against the oracle's gradient_probed (Rademacher
     probes) and against the exact gradient (identity table), and on a 3D shot (Rademacher), under

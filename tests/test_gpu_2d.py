@@ -278,7 +278,7 @@ def test_autotune_without_a_residual_injects_nothing():
     assert rel_l2(plan.unpack(d, "d"), oracle_forward(wl)) <= TOL
 
 
-@pytest.mark.parametrize("tz", [8, 16, 32])
+@pytest.mark.parametrize("tz", [8, 16, 24, 32])
 def test_two_levels_per_launch_is_bitwise_the_one_level_path(tz):
     """Uneven windows, per-shot nt (odd and even step counts, end-aligned offsets): forward
     traces, F^T dd and the FULL-storage gradient are bitwise identical with two time levels

@@ -65,7 +65,7 @@ def test_probed_gradient_does_not_depend_on_shape_or_grouping():
     dd = plan.pack(dds, "d")
     Cd = torch.from_numpy(C).cuda()
     ref = plan.gradient_probed(m, q, dd, Cd, s)[0]
-    for tz, fusion, groups in ((8, 0, 3), (32, 3, 1), (64, 0, 2), (16, 1, 0)):
+    for tz, fusion, groups in ((8, 0, 3), (32, 3, 1), (64, 0, 2), (16, 1, 0), (24, 3, 2)):
         plan.set_tiles(tz)
         plan.set_fusion(fusion)
         plan.set_groups(groups)
