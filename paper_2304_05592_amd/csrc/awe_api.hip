@@ -120,7 +120,7 @@ struct awe_plan {
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_cls;
   std::vector<long long> prof_cnt;  // launches inside each timed interval
-  bool prof_in_run = false;         // inside a timed run of forward steps (see ProfRun)
+  bool prof_in_run = false;         // inside a timed run of steps (see ProfRun)
   long long prof_run_launches = 0;
   size_t prof_next = 0;
   int prof_stride = 1;
