@@ -54,6 +54,7 @@ FUSED_BYTES = {
     ("forward", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
     ("adjoint", "none"): 20,   # read w^{j+1}, w^{j+2}, coef; write w^j, w^{j-1}
     ("adjoint", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
+    ("born", "none"): 40,      # read u^{k-1}, u^{k-2}, du^{k-1}, du^{k-2}, coef, dm; write u, du at k and k+1
 }
 # Per-launch event timing records two HIP events around a launch; a profiler's counter pass over
 # tens of thousands of such records once ended in a host fault inside the runtime, so the eager
@@ -225,7 +226,8 @@ def kernel_table(prof, launch_points, kinds, fused=0):
         if cnt == 0:
             continue
         avg_ms = ms / cnt
-        two = bool(fused & (1 if name == "forward" else 2 if name == "adjoint" else 0)) and \
+        # Born runs two levels per launch with the forward solves
+        two = bool(fused & (1 if name in ("forward", "born") else 2 if name == "adjoint" else 0)) and \
             (name, kind) in FUSED_BYTES
         levels = 2 if two else 1
         b = BYTES[(name, kind)] * levels * launch_points
@@ -785,7 +787,8 @@ def bench_c8(args):
     q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
     ws = plan.workspace()
     dd = torch.empty(plan.layout.d_size, dtype=torch.float32, device="cuda")
-    tiles = choose_pass_tiles(plan, args, lambda: plan.born(m0, q, dm, dd=dd, ws=ws))
+    tiles = choose_pass_tiles(plan, args, lambda: plan.born(m0, q, dm, dd=dd, ws=ws),
+                              fusions=(A.FUSE_NONE, A.FUSE_FORWARD))
     groups = plan.set_groups(args.groups)
     points, launch_points = points_of(wl, range(wl.nshot))
     launch_points //= groups
@@ -815,18 +818,21 @@ def bench_c8(args):
     plan.born(m0, q, dm, dd=dd, ws=ws)
     prof = plan.profile_read()
     plan.profile_disable()
-    kernels = kernel_table(prof, launch_points, {"born": "none"})
+    fused = fusion_of(tiles) & 1
+    kernels = kernel_table(prof, launch_points, {"born": "none"}, fused=fused)
     k = kernels["born"]
     k["eager_event_us"] = k["avg_us"]
-    timing = "HIP events around every launch of one eager pass"
+    timing = "HIP events around each shot group's step loop of one eager pass"
     if graph is not None:
         # graph replay: the pass's time over its step launches (fills and the last gather included)
         avg_s = sec / (k["launches_timed"] // groups * groups)
         k["avg_us"] = round(avg_s * 1e6, 3)
         refresh_rates(k)
         timing = ("graph replay time per pass / step launches of the pass (auxiliary kernels included); "
-                  "eager_event_us = HIP events around every launch of one eager pass")
-    names = {"born": "born2d step (background + scattered field, 32 B/point)"}
+                  "eager_event_us = HIP events around each shot group's step loop of one eager pass")
+    names = {"born": ("born2d2 (two levels of background + scattered field per launch; 32 B per point-update, "
+                      "the launch itself moves 40 B per point)") if fused else
+             "born2d step (background + scattered field, 32 B/point)"}
     return base_line(args, wl, points / sec / 1e9, sec, {
         "metric": "Gpts/s Born modelling J dm (batched, 16 shots)",
         "config": {"workload": "c8_born: Born modelling of the c2_grad survey (650x341 @ 6.25 m + 40-cell "

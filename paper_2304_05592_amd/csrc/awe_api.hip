@@ -1772,13 +1772,23 @@ awe_status awe_born(awe_plan* P, const float* m, const float* q, const float* dm
   a.q = q;
   a.dm = dm;
   a.d = dd;
+  // 2D with the forward's two-level mode: levels in pairs (a single first step when the count
+  // is odd), as the forward solves
+  const bool fuse = fused_ok(P, AWE_FUSE_FORWARD);
   for (P->cur = 0; P->cur < (int)P->g_nshot.size(); ++P->cur) {
-    for (int n = 1; n <= P->nsteps; ++n) {
-      set_group(P, P->fw, a, n);
-      if (a.ntiles <= 0) continue;
-      ProfScope ps(P, 2, s);
-      if (P->ndim == 2) AWE_HIP(awe::launch_born2d(a, P->fw.tz, s));
-      else AWE_HIP(awe::launch_born3d(a, P->fw.ty, P->fw.bz, s));
+    ProfRun run(P, s, 2);
+    for (int n = 1; n <= P->nsteps;) {
+      const bool two = fuse && (n > 1 || !(P->nsteps & 1));
+      set_group(P, P->fw, a, two ? n + 1 : n);
+      a.step = n;
+      if (a.ntiles > 0) {
+        if ((st = check_step(P, P->fw, a, n, two ? n + 1 : n, "Born step")) != AWE_OK) return st;
+        ProfScope ps(P, 2, s);
+        if (P->ndim == 3) AWE_HIP(awe::launch_born3d(a, P->fw.ty, P->fw.bz, s));
+        else if (two) AWE_HIP(awe::launch_born2d2(a, P->fw.tz, s));
+        else AWE_HIP(awe::launch_born2d(a, P->fw.tz, s));
+      }
+      n += two ? 2 : 1;
     }
   }
   AWE_HIP(awe::launch_gather_last(a, P->nshot, P->total_recs, 1, s));

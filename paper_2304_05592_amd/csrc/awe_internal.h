@@ -212,6 +212,8 @@ hipError_t launch_adj2d(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_fwd2d2(const StepArgs& a, int tz, int store, hipStream_t stream);
 hipError_t launch_adj2d2(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t stream);
+// Two Born steps per launch (levels step, step+1); tz 8, 16, 24 or 32.
+hipError_t launch_born2d2(const StepArgs& a, int tz, hipStream_t stream);
 hipError_t launch_fwd3d(const StepArgs& a, int ty, int bz, int store, hipStream_t stream);
 hipError_t launch_adj3d(const StepArgs& a, int ty, int bz, hipStream_t stream);
 hipError_t launch_born3d(const StepArgs& a, int ty, int bz, hipStream_t stream);

@@ -881,6 +881,150 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   }
 }
 
+// Born, two levels per launch: u and du at levels k and k+1 (k = step - off), each point with
+// the arithmetic of born2d_kernel in the same order (so the results are bitwise those of two
+// one-level launches); samples (J dm)^{k-1} and (J dm)^k.  Per two levels the launch reads
+// u^{k-1}, u^{k-2}, du^{k-1}, du^{k-2}, coef and dm once and writes four levels: 40 B per point
+// instead of 2 x 32.
+template <int TZ>
+__global__ __launch_bounds__(F2<TZ>::NT) void born2d2_kernel(StepArgs a) {
+  using G = F2<TZ>;
+  __shared__ float L1U[G::H1][G::W1];
+  __shared__ float L1D[G::H1][G::W1];
+  __shared__ float LEU[G::HE][G::WE];
+  __shared__ float LED[G::HE][G::WE];
+  const int tid = xcd_tile(blockIdx.x, a.ntiles);
+  const TileDev T = a.t.tiles[a.tile_base + tid];
+  const ShotDev& S = a.t.shots[T.shot];
+  const int k = a.step - S.off;
+  const bool act1 = k >= 1 && k <= S.nt - 1;
+  const bool act2 = k + 1 >= 1 && k + 1 <= S.nt - 1;
+  if (!act1 && !act2) return;
+  const int nx = S.nx, nz = S.nz, px = S.px;
+  const int row4 = 4 * px;
+  // levels below 1 are zero
+  const Planes u1 = planes(fbuf(a.ws, S, fwd_buf(k - 1)), nz, k >= 2 ? nz : 0, row4);
+  const Planes u2 = planes(fbuf(a.ws, S, fwd_buf(k - 2)), nz, k >= 3 ? nz : 0, row4);
+  const Planes d1 = planes(fbuf(a.ws, S, adj_buf(k - 1)), nz, k >= 2 ? nz : 0, row4);
+  const Planes d2 = planes(fbuf(a.ws, S, adj_buf(k - 2)), nz, k >= 3 ? nz : 0, row4);
+  const Planes cf = planes(a.ws + S.coef, nz, nz, row4);
+  const Planes dmp = planes(a.dm + S.m, nz, nz, 4LL * nx);   // caller's layout: rows of nx
+  // new levels k and k+1 (a level outside 1..nt-1 belongs to an inactive step: no records)
+  const brsrc uo1 = make_rsrc(fbuf(a.ws, S, fwd_buf(k)), act1 ? nz * row4 : 0);
+  const brsrc uo2 = make_rsrc(fbuf(a.ws, S, fwd_buf(k + 1)), act2 ? nz * row4 : 0);
+  const brsrc do1 = make_rsrc(fbuf(a.ws, S, adj_buf(k)), act1 ? nz * row4 : 0);
+  const brsrc do2 = make_rsrc(fbuf(a.ws, S, adj_buf(k + 1)), act2 ? nz * row4 : 0);
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int x = T.x0 + lane;
+  const int cx = x < nx ? 4 * x : kOOB;
+
+  // the two level k-1 tiles first, then the first step's other inputs on its extended points
+  // (dm in the caller's rows of nx) and coef and dm of the tile points
+  int ho[Side8<TZ>::NH];
+  side_offsets<G::NT, G::H1, 2 * kHalo>(ho, nx, nz, px, T.x0, T.z0);
+  Tile8<TZ> tu, td;
+  tile8_issue<TZ>(tu, u1, cx, ho, T.z0);
+  tile8_issue<TZ>(td, d1, cx, ho, T.z0);
+  int eo[G::NH], eom[G::NH];
+  ext_offsets<TZ>(eo, nx, nz, px, T.x0, T.z0);
+  ext_offsets<TZ>(eom, nx, nz, nx, T.x0, T.z0);
+  float pu2[G::NS], pd2[G::NS], pcf[G::NS], pdm[G::NS], tcf[G::RPT], tdm[G::RPT];
+#pragma unroll
+  for (int i = 0; i < G::NS; ++i) {
+    pu2[i] = ld_ext<TZ>(u2, i, cx, eo, T.z0);
+    pd2[i] = ld_ext<TZ>(d2, i, cx, eo, T.z0);
+    pcf[i] = ld_ext<TZ>(cf, i, cx, eo, T.z0);
+    pdm[i] = ld_ext<TZ>(dmp, i, cx, eom, T.z0);
+  }
+#pragma unroll
+  for (int i = 0; i < G::RPT; ++i) {
+    tcf[i] = ldp(cf, cx, T.z0 + wv * G::RPT + i);
+    tdm[i] = ldp(dmp, cx, T.z0 + wv * G::RPT + i);
+  }
+  tile8_commit<TZ>(L1U, tu);
+  tile8_commit<TZ>(L1D, td);
+  __syncthreads();
+
+  if (act1 && a.d != nullptr) {
+    for (int t = threadIdx.x; t < T.gat_count; t += G::NT) {
+      const RecDev R = a.t.recs[T.gat_begin + t];
+      const int C = R.i - T.x0 + 2 * kHalo, Rw = R.k - T.z0 + 2 * kHalo;
+      a.d[S.d + (long long)(k - 1) * S.nrec + R.r] =
+          R.w[0] * L1D[Rw][C] + R.w[1] * L1D[Rw][C + 1] + R.w[2] * L1D[Rw + 1][C] + R.w[3] * L1D[Rw + 1][C + 1];
+    }
+  }
+  const int src_i = S.src_i, src_k = S.src_k;   // in registers (see the forward kernel)
+  const float sw0 = S.src_w[0], sw1 = S.src_w[1], sw2 = S.src_w[2], sw3 = S.src_w[3];
+  auto src_weight = [&](int w) { return w == 0 ? sw0 : w == 1 ? sw1 : w == 2 ? sw2 : sw3; };
+  // first step: levels k of u and du on the tile + 4-cell halo (zero outside the grid)
+  const float q1 = act1 ? a.q[S.q + k - 1] : 0.f;
+#pragma unroll
+  for (int i = 0; i < G::NS; ++i) {
+    int r, c;
+    if (!ext_slot<TZ>(i, &r, &c)) continue;
+    const int z = T.z0 - kHalo + r, xx = T.x0 - kHalo + c;
+    float v = 0.f, vd = 0.f;
+    if ((unsigned)z < (unsigned)nz && (unsigned)xx < (unsigned)nx) {
+      const int dx = border_dist(xx, nx, a.nbl), dz = border_dist(z, nz, a.nbl);
+      const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
+      const float* pc = &L1U[r + kHalo][c + kHalo];
+      const float u = pc[0];
+      float lap = lap_ptr(pc, G::W1, a.c);
+      const int bx = xx - src_i, bz = z - src_k;
+      if (act1 && (unsigned)bx < 2u && (unsigned)bz < 2u) lap += src_weight(bx + 2 * bz) * q1;
+      const float incr = pcf[i] * (lap - eta * (u - pu2[i]));
+      v = (u + u - pu2[i]) + incr;
+      const float* pd = &L1D[r + kHalo][c + kHalo];
+      const float du = pd[0];
+      const float lapd = lap_ptr(pd, G::W1, a.c) - pdm[i] * incr * a.inv_dt2;
+      const float incd = pcf[i] * (lapd - eta * (du - pd2[i]));
+      vd = (du + du - pd2[i]) + incd;
+    }
+    // body slots on tile rows store levels k (wave-uniform condition; columns outside drop)
+    if (i < G::NB && r >= kHalo && r < kHalo + TZ) {
+      stb(uo1, v, cx, z * row4);
+      stb(do1, vd, cx, z * row4);
+    }
+    LEU[r][c] = v;
+    LED[r][c] = vd;
+  }
+  __syncthreads();
+
+  if (act2 && a.d != nullptr) {
+    for (int t = threadIdx.x; t < T.gat_count; t += G::NT) {
+      const RecDev R = a.t.recs[T.gat_begin + t];
+      const int C = R.i - T.x0 + kHalo, Rw = R.k - T.z0 + kHalo;
+      a.d[S.d + (long long)k * S.nrec + R.r] =
+          R.w[0] * LED[Rw][C] + R.w[1] * LED[Rw][C + 1] + R.w[2] * LED[Rw + 1][C] + R.w[3] * LED[Rw + 1][C + 1];
+    }
+  }
+  if (!act2) return;
+  // second step: levels k+1 on the tile (every lane computes; stores outside the grid drop)
+  const float q2 = a.q[S.q + k];
+  const int dx = border_dist(x, nx, a.nbl);
+#pragma unroll
+  for (int i = 0; i < G::RPT; ++i) {
+    const int lr = wv * G::RPT + i;
+    const int z = T.z0 + lr;
+    const int dz = border_dist(z, nz, a.nbl);
+    const float eta = a.eta_dt * (float)(dx * dx + dz * dz);
+    const float* pc = &LEU[lr + kHalo][lane + kHalo];
+    const float u = pc[0];
+    const float um2 = L1U[lr + 2 * kHalo][lane + 2 * kHalo];
+    float lap = lap_ptr(pc, G::WE, a.c);
+    const int bx = x - src_i, bz = z - src_k;
+    if ((unsigned)bx < 2u && (unsigned)bz < 2u) lap += src_weight(bx + 2 * bz) * q2;
+    const float incr = tcf[i] * (lap - eta * (u - um2));
+    stb(uo2, (u + u - um2) + incr, cx, z * row4);
+    const float* pd = &LED[lr + kHalo][lane + kHalo];
+    const float du = pd[0];
+    const float dm2 = L1D[lr + 2 * kHalo][lane + 2 * kHalo];
+    const float lapd = lap_ptr(pd, G::WE, a.c) - tdm[i] * incr * a.inv_dt2;
+    const float incd = tcf[i] * (lapd - eta * (du - dm2));
+    stb(do2, (du + du - dm2) + incd, cx, z * row4);
+  }
+}
+
 template <int TZ>
 hipError_t fwd2d_tz(const StepArgs& a, int store, hipStream_t s) {
   switch (store) {
@@ -981,6 +1125,18 @@ hipError_t launch_adj2d(const StepArgs& a, int tz, hipStream_t s) {
     case 64: return adj2d_tz<64>(a, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_born2d2(const StepArgs& a, int tz, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  switch (tz) {
+    case 8: born2d2_kernel<8><<<a.ntiles, F2<8>::NT, 0, s>>>(a); break;
+    case 16: born2d2_kernel<16><<<a.ntiles, F2<16>::NT, 0, s>>>(a); break;
+    case 24: born2d2_kernel<24><<<a.ntiles, F2<24>::NT, 0, s>>>(a); break;
+    case 32: born2d2_kernel<32><<<a.ntiles, F2<32>::NT, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_born2d(const StepArgs& a, int tz, hipStream_t s) {

@@ -30,6 +30,19 @@ def main():
         res[(tz, fusion)] = plan.gradient(m, q, plan.pack(dds), v=True, d=True)
         assert plan.get_tiles()[0][0] == tz and plan.get_tiles()[2] == fusion
         del plan
+    # Born modelling with two levels per launch at every height: bitwise the one-level traces
+    dms = [W.random_field(wl.comp_shape(w), 17 + w, 2.0) * np.float32(0.01) for w in range(wl.nwindow)]
+    born = {}
+    for tz, fusion in ((16, 0), (8, 1), (16, 1), (24, 1), (32, 1)):
+        plan = D.EmuPlan(lib, wl, storage=B.Storage(B.STORE_NONE))
+        plan.set_checks(4)
+        plan.set_tiles(tz, 8, 0)
+        plan.set_fusion(fusion)
+        m = plan.pack([wl.m(w) for w in range(wl.nwindow)])
+        q = plan.pack([wl.q(i) for i in range(wl.nshot)])
+        born[(tz, fusion)] = plan.born(m, q, plan.pack(dms))
+        del plan
+    out["born_bitwise"] = {f"{tz}_{fu}": bool(np.array_equal(r, born[(16, 0)])) for (tz, fu), r in born.items()}
     base = res[(16, 0)]
     out["bitwise"] = {f"{tz}_{fu}": all(np.array_equal(a, b) for a, b in zip(r, base)) for (tz, fu), r in res.items()}
     gs = [np.zeros(wl.comp_shape(w)) for w in range(wl.nwindow)]

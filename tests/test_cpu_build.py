@@ -80,15 +80,16 @@ def test_failure_paths_on_the_cpu_build(emu_lib):
 
 
 def test_two_level_tile_heights_on_the_cpu_build(emu_lib):
-    """Two levels per launch at 8, 16, 24 and 32 rows (2D, FULL FP32, uneven batch) under
-    AddressSanitizer with the host launch checks on: bitwise the one-level gradient, traces and
-    F^T dd, which match the oracle."""
+    """Two levels per launch at 8, 16, 24 and 32 rows (2D, uneven batch) under AddressSanitizer
+    with the host launch checks on: bitwise the one-level gradient, traces and F^T dd (FULL FP32
+    storage), which match the oracle, and bitwise the one-level Born traces."""
     import driver
     r = driver.run([os.path.join(EMU, "case_two_level.py")], emu_lib, timeout=900)
     assert r.returncode == 0, r.stderr[-4000:]
     res = json.loads(r.stdout.strip().splitlines()[-1])
     print(res)
     assert all(res["bitwise"].values()) and res["grad_rel"] <= 1e-5
+    assert all(res["born_bitwise"].values())
 
 
 def test_probed_gradient_on_the_cpu_build(emu_lib):

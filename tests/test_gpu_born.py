@@ -62,3 +62,26 @@ def test_born_needs_storage_for_its_pullback():
     dd = A.born_forward(dm, m, q, plan)
     with pytest.raises(RuntimeError):
         dd.sum().backward()
+
+
+@pytest.mark.parametrize("tz", [8, 16, 24, 32])
+def test_two_level_born_is_bitwise_the_one_level_born(tz):
+    """Born modelling with two levels per launch (the forward's two-level mode) on an uneven
+    batch (per-shot nt, odd and even level counts): bitwise the one-level traces, which match
+    the oracle."""
+    wl = W.small_2d(windows=[90, 70, 113], T_per_shot=[300.0, 200.0, 251.0])
+    dms = [W.random_field(wl.comp_shape(w), 17 + w, 2.0) * np.float32(0.01) for w in range(wl.nwindow)]
+    outs = []
+    for fuse in (A.FUSE_NONE, A.FUSE_FORWARD):
+        plan = make_plan(wl)
+        plan.set_tiles(tz=tz)
+        plan.set_fusion(fuse)
+        m, q = gpu_inputs(wl, plan)
+        dd = plan.born(m, q, plan.pack(dms, "m"))
+        torch.cuda.synchronize()
+        outs.append(dd.cpu())
+    assert torch.equal(outs[0], outs[1])
+    plan = make_plan(wl)
+    err = rel_l2(plan.unpack(outs[1].cuda(), "d"), oracle_born(wl, dms))
+    print(f"two-level Born (tz {tz}): rel-L2 {err:.3e}", flush=True)
+    assert err <= TOL
