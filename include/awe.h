@@ -346,7 +346,7 @@ awe_status awe_plan_set_tiles_dir(awe_plan* plan, int32_t dirs, int32_t tz, int3
 awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz);
 
 /* 2D only: advance two time levels per launch, chosen per direction by the bits of mode:
- * AWE_FUSE_FORWARD for forward solves, AWE_FUSE_ADJOINT for reverse sweeps (0, the default:
+ * AWE_FUSE_FORWARD for forward solves and Born modelling, AWE_FUSE_ADJOINT for reverse sweeps (0, the default:
  * one level per launch everywhere).  The two-level kernels serve forward solves without
  * storage, with FULL FP32 storage or into PROBED sums, and reverse sweeps from FULL FP32
  * storage, into PROBED sums or without imaging; other modes always use one level per launch.
