@@ -61,6 +61,39 @@ def test_born_fixture_trace_prefix(shot, n):
     assert np.abs(d).max() > 0 and np.abs(gold[f"trace_value_{shot}"]).max() > 0
 
 
+@pytest.mark.parametrize("name,shot,n", [("c6_timelapse", 0, 1600), ("c7_timelapse_rock", 0, 1400)])
+def test_timelapse_fixture_trace_prefix(name, shot, n):
+    """The time-lapse fixtures' traces at each vintage's starting wavespeed (m = 1/v^2 of the
+    float32 wavespeed, in FP64); for the rock workload that wavespeed is R at zero saturation,
+    which is the brine rock's own vp.  Sources and receivers sit in two wells 2.5 km apart, so
+    the prefix runs past the first arrivals (the stored samples it covers are not all zero)."""
+    path = os.path.join(GOLD, f"{name}_full.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    gold = np.load(path)
+    wl = W.make_config(name)
+    par, v, rock = G.timelapse_models(wl)
+    if rock is not None:
+        np.testing.assert_allclose(v[0], rock[0], rtol=1e-12, atol=0)
+        assert all(np.all(p == 0) for p in par)
+    sh = wl.shots[shot]
+    d = O.forward(O.slowness2(v[sh.window]), wl.q(shot)[:n], sh.src, sh.rec, h=wl.h, dt=wl.dt,
+                  nbl=wl.nbl, vref=wl.vmax)
+    ti, ri = gold[f"trace_t_{shot}"], gold[f"trace_r_{shot}"]
+    keep = ti < n
+    assert keep.sum() >= n // G.TIME_STRIDE
+    np.testing.assert_allclose(d[np.ix_(ti[keep], ri)], gold[f"trace_value_{shot}"][keep], rtol=0,
+                               atol=1e-12 * np.abs(d).max())
+    stored = gold[f"trace_value_{shot}"]
+    assert np.abs(stored[keep]).max() > 0.05 * np.abs(stored).max()
+    assert sorted(int(k[len("grad_index_"):]) for k in gold.files if k.startswith("grad_index_")) == \
+        list(range(wl.nwindow))
+    for w in range(wl.nwindow):
+        idx, val = gold[f"grad_index_{w}"], gold[f"grad_value_{w}"]
+        assert idx.shape == val.shape and idx.max() < int(np.prod(wl.comp_shape(w)))
+        assert np.isfinite(val).all() and np.abs(val).max() > 0
+
+
 def test_fp32_floor_record_supports_the_gpu_gates():
     """The float32-emulated oracle's rounding floor (written by measure_fp32_floor.py, oracle
     only) is what the GPU gates lean on: the Born trace bar of 2e-5 and the probed-gradient bars of

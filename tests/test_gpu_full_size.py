@@ -8,7 +8,9 @@ tests/golden/make_full_size.py stored (FP64, same seeded inputs):
 receiver traces of every shot at the background model (every 32nd time sample
 of every k-th receiver) and the adjoint-state gradient J^T dd for a seeded
 synthetic residual per shot, at 4096 seeded grid points (split over windows);
-and the Born traces J(m0) dm of the c2_grad shots for dm = m - m0.
+the Born traces J(m0) dm of the c2_grad shots for dm = m - m0; and the two
+time-lapse iterations, whose gradients are taken with respect to each vintage's
+wavespeed or CO2 saturation through the parameter maps.
 
 Bar: rel-L2 over the samples <= 1e-5 with FP32 storage; with BF16 / FP16
 storage of the wavefield the gradient carries the storage rounding (unit
@@ -242,3 +244,59 @@ def test_c9_probed_crop_full_size():
     err = _rel(got, gold["grad_value_0"])
     print(f"c9_probed_crop: gradient rel-L2 {err:.2e} ({got.size} samples, {r} probes)", flush=True)
     assert np.isfinite(got).all() and err <= 3e-5
+
+
+def _timelapse(name):
+    """One time-lapse iteration at full size in the launch configuration the time-lapse
+    benchmark times (all 60 shots of the 15 vintages in one plan, FULL FP32 storage, the
+    autotuned shape, automatic shot groups): the pullback of the stored synthetic residual dd
+    through wave_forward and the parameter map gives the gradient with respect to each
+    vintage's parameter, compared with the oracle at the sampled points, and the traces at the
+    starting model are compared too."""
+    import torch
+    torch.cuda.empty_cache()
+    gold = _fixture(name)
+    wl = W.make_config(name)
+    par, _, rock = G.timelapse_models(wl)
+    plan = make_plan(wl, A.Storage(A.STORE_FULL))
+    x = plan.pack(par, "m").requires_grad_(True)
+    q = plan.pack([wl.q(s) for s in range(wl.nshot)], "q")
+    dd = plan.pack([G.residual(wl, s) for s in range(wl.nshot)], "d")
+    if rock is None:
+        v = x
+    else:
+        tvp, trho, tphi = (plan.pack([a] * wl.nwindow, "m") for a in rock)
+        v, _ = A.patchy_rock_physics(x, tvp, trho, tphi)
+    tiles, _ = plan.autotune(A.slowness2(v.detach()), q, dd, probe_steps=32)
+    groups = plan.set_groups(0)
+    print(f"{name}: autotuned {tiles}, {groups} shot groups", flush=True)
+    torch.cuda.empty_cache()
+    d = A.wave_forward(A.slowness2_from_velocity(v), q, plan)
+    (d * dd).sum().backward()
+    torch.cuda.synchronize()
+    gs = plan.unpack(x.grad.double(), "m")
+    ds = plan.unpack(d.detach(), "d")
+    got_g = np.concatenate([gs[w].ravel()[gold[f"grad_index_{w}"]] for w in range(wl.nwindow)])
+    ref_g = np.concatenate([gold[f"grad_value_{w}"] for w in range(wl.nwindow)])
+    got_d = np.concatenate([ds[s][np.ix_(gold[f"trace_t_{s}"], gold[f"trace_r_{s}"])].ravel()
+                            for s in range(wl.nshot)])
+    ref_d = np.concatenate([gold[f"trace_value_{s}"].ravel() for s in range(wl.nshot)])
+    e_g, e_d = _rel(got_g, ref_g), _rel(got_d, ref_d)
+    print(f"{name}: gradient rel-L2 {e_g:.2e} ({ref_g.size} samples over {wl.nwindow} vintages), "
+          f"traces {e_d:.2e} ({ref_d.size} samples of {wl.nshot} shots)", flush=True)
+    assert np.isfinite(got_g).all() and np.isfinite(got_d).all()
+    assert e_g <= TOL and e_d <= TOL
+
+
+@pytest.mark.gpu
+def test_c6_timelapse_full_size():
+    """The 15-vintage crosswell iteration (336 x 592 grid, nt 2505, 4 shots per vintage): the
+    gradient with respect to each vintage's wavespeed at the starting model."""
+    _timelapse("c6_timelapse")
+
+
+@pytest.mark.gpu
+def test_c7_timelapse_rock_full_size():
+    """The reservoir-rock iteration: the gradient with respect to each vintage's CO2 saturation
+    at zero saturation, through the patchy rock physics R and m = 1/v^2."""
+    _timelapse("c7_timelapse_rock")
