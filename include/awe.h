@@ -287,7 +287,10 @@ awe_status awe_patchy_vjp(const float* s, const float* vp, const float* rho, con
  *   op 0 ADVANCE  a -> b : run forward steps from state a to state b (b > a)
  *   op 1 STORE    slot a <- current state b
  *   op 2 RESTORE  current state <- slot a (which holds state b)
- *   op 3 REVERSE  adjoint step of state a (needs the current state to be a)
+ *   op 3 REVERSE  adjoint step of level a (needs u^a: the current state is a or a + 1)
+ * A state S_j = (u^j, u^{j-1}) holds two levels, so the reversals run in pairs: the state
+ * reached for level j also serves level j - 1, and the binomial law places the checkpoints on
+ * the pairs (for an even nsteps the fewest forward steps, for an odd one at most one more).
  * The first ADVANCE starts from the zero state S_0.  Returns INVALID_ARG if cap is too
  * small (*count then holds the needed size). */
 awe_status awe_checkpoint_schedule(int32_t nsteps, int32_t nslots, int32_t* actions,

@@ -1,13 +1,17 @@
 // Binomial checkpointing schedule for the reverse (adjoint) sweep.
 //
-// The adjoint-state gradient needs the forward states S_j = (u^j, u^{j-1}) in reverse
-// order j = n, n-1, ..., 1 while the forward recursion only runs forward.  With s restart
-// slots (S_0 = 0 needs none) the schedule below stores some states during a forward sweep
-// and recomputes the others from the nearest stored state.  It minimises the number of
-// forward steps: the l-th reversal of a segment, counted from its stored start, costs r
-// steps for C(s + r, s) consecutive values of l (the binomial law of optimal
-// checkpointing), so the cost T(l, s) is convex in l and the optimal place of the next
-// checkpoint is found by bisection on the discrete derivative.
+// The adjoint-state gradient needs the forward levels u^j in reverse order j = n, n-1, ..., 1
+// while the forward recursion only runs forward.  With s restart slots (S_0 = 0 needs none)
+// the schedule below stores some states S_j = (u^j, u^{j-1}) during a forward sweep and
+// recomputes the others from the nearest stored state.  Every state, reached or restored,
+// holds two consecutive levels and an adjoint step reads only its own one, so the reversals
+// run in pairs from the top of a segment, (b, b-1), (b-2, b-3), ..., each pair served by one
+// state.  The binomial law of optimal checkpointing then applies to the pairs: the l-th
+// reversal of a segment, counted from its stored start, costs r steps for C(s + r, s)
+// consecutive values of l, so the cost T(l, s) is convex in l and the optimal place of the
+// next checkpoint is found by bisection on the discrete derivative; each pair counts two
+// steps.  For an even length this is the fewest forward steps of the paired problem; for an
+// odd one the lowest pair is the single level a+1, which can cost one step more.
 #include "schedule.h"
 
 #include <algorithm>
@@ -81,24 +85,38 @@ struct Builder {
     if (to > cur) emit(kAdvance, cur, to);
     cur = to;
   }
+  // Reverse j, and j - 1 as well when it lies in the segment: the state S_j in the working
+  // buffers (reached, or restored) holds both u^j and u^{j-1}, and a reversal reads only its own
+  // level.  Returns the next level still to reverse.
+  int reverse_pair(int j, int a) {
+    emit(kReverse, j, 0);
+    if (j - 1 > a) {
+      emit(kReverse, j - 1, 0);
+      return j - 2;
+    }
+    return j - 1;
+  }
   // Reversals b, b-1, ..., a+1 with S_a restorable and s free slots.
   void ops(int a, int b, int s) {
     while (b > a) {
       const long long l = b - a;
       if (s == 0) {
-        for (int j = b; j > a; --j) {
+        for (int j = b; j > a;) {
           restore(a);
           advance(j);
-          emit(kReverse, j, 0);
+          j = reverse_pair(j, a);
         }
         return;
       }
-      const int c = (int)best_split(l, s);
+      // the reversals run in pairs from the top (b, b-1), (b-2, b-3), ...: the binomial law
+      // applies to the pairs, the lowest of which is the single level a+1 when l is odd, so
+      // the next checkpoint goes after k pairs, at a + 2k - (l odd)
+      const long long k = best_split((l + 1) / 2, s);
+      const int c = (int)(2 * k - (l & 1));
       restore(a);
       advance(a + c);
       if (c == l) {
-        emit(kReverse, b, 0);
-        b -= 1;
+        b = reverse_pair(b, a);
         continue;
       }
       slots.push_back(a + c);
@@ -106,9 +124,8 @@ struct Builder {
       emit(kStore, (int)slots.size() - 1, a + c);
       ops(a + c, b, s - 1);
       restore(a + c);
-      emit(kReverse, a + c, 0);
       slots.pop_back();
-      b = a + c - 1;
+      b = reverse_pair(a + c, a);
     }
   }
 };
