@@ -54,6 +54,7 @@ FUSED_BYTES = {
     ("forward", "fp32"): 28,   # + stored copies of u^k and u^{k+1}
     ("adjoint", "none"): 20,   # read w^{j+1}, w^{j+2}, coef; write w^j, w^{j-1}
     ("adjoint", "fp32"): 44,   # read w^{j+1}, w^{j+2}, coef, stored u^j, u^{j-1}, acc; write w^j, w^{j-1}, acc
+    ("adjoint", "buffers"): 44,  # the same with u^j, u^{j-1} from the recomputed forward levels
     ("born", "none"): 40,      # read u^{k-1}, u^{k-2}, du^{k-1}, du^{k-2}, coef, dm; write u, du at k and k+1
 }
 # Per-launch event timing records two HIP events around a launch; a profiler's counter pass over
@@ -216,7 +217,7 @@ def points_of(wl, shots):
     return per_step, per_launch
 
 
-def kernel_table(prof, launch_points, kinds, fused=0):
+def kernel_table(prof, launch_points, kinds, fused=0, mixed=None):
     """Per kernel class: launches, average event time and achieved algorithmic GB/s.  A class
     that runs two levels per launch (fused: bit 0 forward, bit 1 adjoint) performs two
     point-updates per grid point and launch; its own (fused) bytes are reported beside."""
@@ -226,6 +227,20 @@ def kernel_table(prof, launch_points, kinds, fused=0):
         if cnt == 0:
             continue
         avg_ms = ms / cnt
+        if mixed and name in mixed:
+            # launches of one or two levels: (two-level launches, one-level launches) per run,
+            # from the schedule; priced by the levels they advance
+            pairs, singles = mixed[name]
+            lv = (2 * pairs + singles) / (pairs + singles)
+            b = round(BYTES[(name, kind)] * lv * launch_points)
+            fb = round((FUSED_BYTES[(name, kind)] * pairs + BYTES[(name, kind)] * singles) / (pairs + singles)
+                       * launch_points)
+            out[name] = {"launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 3),
+                         "bytes_per_point_update": BYTES[(name, kind)], "levels_per_launch": round(lv, 4),
+                         "bytes_per_launch": b, "achieved_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1),
+                         "fused_bytes_per_point": FUSED_BYTES[(name, kind)], "fused_bytes_per_launch": fb,
+                         "fused_GBs": round(fb / (avg_ms * 1e-3) / 1e9, 1)}
+            continue
         # Born runs two levels per launch with the forward solves
         two = bool(fused & (1 if name in ("forward", "born") else 2 if name == "adjoint" else 0)) and \
             (name, kind) in FUSED_BYTES
@@ -560,15 +575,32 @@ def bench_c3(args):
     sync()
     prof = plan.profile_read()
     plan.profile_disable()
-    kernels = kernel_table(prof, launch_points, {"forward": "none", "adjoint": "buffers"})
+    # paired reversals (x, x-1) run as one two-level launch when the adjoint fusion is on
+    two = bool(plan.get_tiles()["fusion"] & A.FUSE_ADJOINT)
+    pairs = singles = 0
+    i = 0
+    while i < len(sched):
+        if sched[i][0] == 3:
+            if two and i + 1 < len(sched) and sched[i + 1][0] == 3 and sched[i + 1][1] == sched[i][1] - 1 \
+                    and sched[i][1] >= 2:
+                pairs += 1
+                i += 2
+                continue
+            singles += 1
+        i += 1
+    kernels = kernel_table(prof, launch_points, {"forward": "none", "adjoint": "buffers"},
+                           mixed={"adjoint": (pairs, singles)} if two else None)
     names = {"forward": "fwd2d step (forward / recompute, 16 B/point)",
-             "adjoint": "adj2d step (adjoint + imaging from recomputed buffers, 36 B/point)"}
+             "adjoint": ("adj2d2 / adj2d steps (paired reversals two levels per launch, imaging from the "
+                         "recomputed forward levels, 36 B/point-update)" if two else
+                         "adj2d step (adjoint + imaging from recomputed buffers, 36 B/point)")}
     return base_line(args, wl, points / sec / 1e9, sec, {
         "config": {"workload": f"{wl.name}: {wl.description}", "grid": list(wl.comp_shape(0)),
                    "shots": wl.nshot, "nt": int(wl.shots[0].nt), "storage": "CHECKPOINT 16 FP32 slots",
                    "batched": True, "graph": False, "tiles": tiles, "shot_groups": groups},
         "roofline": roofline_of(kernels, names), "cpu_baseline": None, "kernels": kernels,
         "forward_steps_per_gradient": fwd_steps,
+        "adjoint_launches_per_gradient": pairs + singles, "adjoint_two_level_launches": pairs,
         "recompute_factor": round(fwd_steps / (wl.shots[0].nt - 1), 3), "loss": float(loss.item()),
         "kernel_timing": "value from eager steps without events; kernels from one more eager step, "
                          "HIP events around each checkpoint advance (its forward launches back to back) "

@@ -351,8 +351,10 @@ awe_status awe_plan_set_tiles(awe_plan* plan, int32_t tz, int32_t ty, int32_t bz
 /* 2D only: advance two time levels per launch, chosen per direction by the bits of mode:
  * AWE_FUSE_FORWARD for forward solves and Born modelling, AWE_FUSE_ADJOINT for reverse sweeps (0, the default:
  * one level per launch everywhere).  The two-level kernels serve forward solves without
- * storage, with FULL FP32 storage or into PROBED sums, and reverse sweeps from FULL FP32
- * storage, into PROBED sums or without imaging; other modes always use one level per launch.
+ * storage, with FULL FP32 storage or into PROBED sums, reverse sweeps from FULL FP32
+ * storage, into PROBED sums or without imaging, and the paired reversals of a CHECKPOINT
+ * gradient (imaging from the recomputed forward levels); other modes always use one level per
+ * launch.
  * Results are bitwise identical either way (a two-level launch adds both levels' terms to an
  * FP64 sum in the order two launches would).  Two levels per launch need tiles of 8, 16, 24 or 32 rows (16 or 32 are set
  * otherwise).  Errors: INVALID_ARG (mode outside 0..3), HIP. */

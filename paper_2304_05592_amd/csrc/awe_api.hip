@@ -814,8 +814,13 @@ awe_status run_actions(awe_plan* P, awe::StepArgs& fa, awe::StepArgs& aa, size_t
         }
         break;
       case awe::kReverse: {
-        awe_status st = step_adj(P, aa, x, s);
+        // a pair of reversals x, x-1 from one state runs as one two-level launch when the
+        // adjoint fusion is on (both levels are read from the current state)
+        const bool two = fused_ok(P, AWE_FUSE_ADJOINT) && i + 1 < end && x >= 2 &&
+                         P->sched[3 * (i + 1)] == awe::kReverse && P->sched[3 * (i + 1) + 1] == x - 1;
+        awe_status st = two ? step_adj2(P, aa, x, s) : step_adj(P, aa, x, s);
         if (st != AWE_OK) return st;
+        if (two) ++i;
         break;
       }
     }
@@ -1319,6 +1324,7 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
   struct Cand { int tz, ty, bz, fuse; };
   std::vector<Cand> cands;
   const bool fusable = P->store.mode == AWE_STORE_NONE || P->store.mode == AWE_STORE_PROBED ||
+                       P->store.mode == AWE_STORE_CHECKPOINT ||
                        (P->store.mode == AWE_STORE_FULL && P->store.prec == AWE_PREC_FP32);
   if (P->ndim == 2) {
     for (int tz : {8, 16, 24, 32, 64}) {
@@ -1374,7 +1380,8 @@ awe_status awe_plan_autotune(awe_plan* P, const float* m, const float* q, const 
     Tiling& T = dir == 0 ? P->fw : P->rv;
     const int bit = dir == 0 ? AWE_FUSE_FORWARD : AWE_FUSE_ADJOINT;
     for (const Cand& c : cands) {
-      if (c.fuse && dir == 1 && img == awe::kImgBuffers) continue;  // no two-level recompute sweep
+      // a checkpointed gradient recomputes one level per launch; its reversals run in pairs
+      if (c.fuse && dir == 0 && P->store.mode == AWE_STORE_CHECKPOINT) continue;
       T.tz = c.tz;
       T.ty = c.ty;
       T.bz = c.bz;

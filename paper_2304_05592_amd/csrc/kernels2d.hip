@@ -713,7 +713,10 @@ __global__ __launch_bounds__(F2<TZ>::NT) void fwd2d2_kernel(StepArgs a) {
 template <int TZ, int IMG>
 __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   using G = F2<TZ>;
-  constexpr bool IACC = IMG == kImgFull32;
+  // kImgBuffers: the two levels come from the recomputed forward buffers (or the slot restored
+  // by reference) instead of the FULL store, as in a checkpointed gradient's paired reversals
+  constexpr bool IBUF = IMG == kImgBuffers;
+  constexpr bool IACC = IMG == kImgFull32 || IBUF;
   __shared__ float L1[G::H1][G::W1];
   __shared__ float LE[G::HE][G::WE];
   __shared__ float INJ1[G::HE][G::WE];
@@ -736,8 +739,10 @@ __global__ __launch_bounds__(F2<TZ>::NT) void adj2d2_kernel(StepArgs a) {
   const brsrc ro2 = make_rsrc(fbuf(a.ws, S, adj_buf(j - 1)), act2 ? nz * row4 : 0);
   // imaging: stored u^j and u^{j-1} (levels of inactive steps read 0) and the FP64 accumulator
   const float* ust = reinterpret_cast<const float*>(a.ws + S.store);
-  const Planes us1 = planes(ust + (long long)(IACC && act1 ? j : 0) * S.npts, nz, IACC && act1 ? nz : 0, row4);
-  const Planes us2 = planes(ust + (long long)(IACC && act2 ? j - 1 : 0) * S.npts, nz, IACC && act2 ? nz : 0, row4);
+  const Planes us1 = planes(IBUF ? fwd_level(a, S, j) : ust + (long long)(IACC && act1 ? j : 0) * S.npts, nz,
+                            IACC && act1 ? nz : 0, row4);
+  const Planes us2 = planes(IBUF ? fwd_level(a, S, j - 1) : ust + (long long)(IACC && act2 ? j - 1 : 0) * S.npts, nz,
+                            IACC && act2 ? nz : 0, row4);
   const Planes acc = planes(a.ws + S.acc, nz, IACC ? nz : 0, 2 * row4);
   const brsrc racc = make_rsrc(a.ws + S.acc, IACC ? 2 * nz * row4 : 0);
   const int lane = threadIdx.x & 63, wv = wave_id();
@@ -1069,6 +1074,7 @@ hipError_t adj2d2_tz(const StepArgs& a, hipStream_t s) {
   switch (a.image_src) {
     case kImgNone: adj2d2_kernel<TZ, kImgNone><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     case kImgFull32: adj2d2_kernel<TZ, kImgFull32><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
+    case kImgBuffers: adj2d2_kernel<TZ, kImgBuffers><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     case kImgProbe: adj2d2_kernel<TZ, kImgProbe><<<a.ntiles, F2<TZ>::NT, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }

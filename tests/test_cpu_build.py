@@ -92,6 +92,18 @@ def test_two_level_tile_heights_on_the_cpu_build(emu_lib):
     assert all(res["born_bitwise"].values())
 
 
+def test_checkpointed_gradient_with_paired_two_level_reversals_on_the_cpu_build(emu_lib):
+    """Checkpointed 2D gradients (uneven batch, 3 slots) whose paired reversals run two levels
+    per launch, imaging from the recomputed forward levels, under AddressSanitizer with the host
+    launch checks on: bitwise the FULL-storage one-level result with FP32 slots and the
+    one-level result with BF16 slots, at 8, 16 and 24 rows and with one and two shot groups."""
+    import driver
+    r = driver.run([os.path.join(EMU, "case_ckpt_pairs.py")], emu_lib, timeout=600)
+    assert r.returncode == 0, r.stderr[-4000:]
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    print(res)
+    assert res["nonzero"] and all(res["bitwise"].values())
+
 def test_probed_gradient_on_the_cpu_build(emu_lib):
     """PROBED storage on an uneven 2D batch against the oracle's gradient_probed (Rademacher
     probes) and against the exact gradient (identity table), and on a 3D shot (Rademacher), under

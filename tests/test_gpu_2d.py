@@ -346,6 +346,33 @@ def test_checkpointed_gradient_with_uneven_nt_is_bitwise_the_full_storage_gradie
         assert torch.equal(v, out[0][1])
 
 
+@pytest.mark.parametrize("tz,groups", [(8, 1), (16, 2), (24, 1), (32, 2)])
+def test_checkpointed_gradient_with_two_level_reversals_is_bitwise(tz, groups):
+    """The paired reversals of a checkpointed gradient run as two-level adjoint launches that
+    image from the recomputed forward levels (or a slot read by reference): on an uneven batch
+    with per-shot nt the gradient, F^T dd and traces are bitwise the FULL one-level ones with
+    FP32 slots and the one-level ones with BF16 slots."""
+    wl = W.small_2d(windows=[90, 70, 113, 64], T_per_shot=[600.0, 180.0, 400.0, 290.0])
+    dds = _residuals(wl)
+
+    def run(storage, fusion):
+        plan = make_plan(wl, storage=storage)
+        plan.set_groups(groups)
+        plan.set_tiles(tz=tz)
+        plan.set_fusion(fusion)
+        m, q = gpu_inputs(wl, plan, background=True)
+        out = plan.gradient(m, q, plan.pack(dds, "d"), v=True, d=True)
+        _sync()
+        return [t.cpu() for t in out]
+
+    ref32 = run(A.Storage(A.STORE_FULL), A.FUSE_NONE)
+    for slots in (3, 16):
+        got = run(A.Storage(A.STORE_CHECKPOINT, slots), A.FUSE_ADJOINT)
+        assert all(torch.equal(a, b) for a, b in zip(got, ref32)), f"FP32 slots {slots}"
+    ref16 = run(A.Storage(A.STORE_CHECKPOINT, 3, A.PREC_BF16), A.FUSE_NONE)
+    got = run(A.Storage(A.STORE_CHECKPOINT, 3, A.PREC_BF16), A.FUSE_ADJOINT)
+    assert all(torch.equal(a, b) for a, b in zip(got, ref16))
+
 def test_kernel_timing_counts_every_step_launch_of_a_checkpointed_gradient():
     """With kernel timing on, each checkpoint advance is one timed interval that counts its
     forward launches and each adjoint launch another: a checkpointed gradient of two equal shots
